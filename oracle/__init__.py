@@ -1,0 +1,229 @@
+"""CPU oracle of the PVG rasterizer (ctypes wrapper over ``pvg_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the smoke check and the CPU
+baseline leg of the benchmark may import this package; the product path never
+does.  It shares no code with the GPU library.
+
+Layouts follow the boundary's: parameters SoA ``[rows, N]``; images
+``[3, H, W]``; per-Gaussian FP32 stage outputs ``xy [N,2]``, ``conic_op [N,4]``
+(A, B, C, opacity at t), ``rgb [N,3]``, ``radius [N]``, ``rect [N,4]``,
+``tiles [N]``, ``flags [N]``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pvg_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+FIELDS = ("mu", "scale", "rot", "sh", "opacity", "vel", "period", "tau", "beta")
+TILE = 16
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (FP32 stays FP32: no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+               "-o", _LIB + ".tmp", _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        vp = C.c_void_p
+        i64, i32 = C.c_int64, C.c_int
+        L.orc_preprocess_f32.argtypes = [i64, i32, vp, vp, i32, i32, vp] + [vp] * 8
+        L.orc_preprocess_f32.restype = None
+        L.orc_bin_sort.argtypes = [i64, vp, vp, vp, i32, i32, i64, vp, vp, vp]
+        L.orc_bin_sort.restype = i64
+        L.orc_render_f32.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, i64, i64, vp, vp, vp]
+        L.orc_render_f32.restype = None
+        L.orc_render_bruteforce_f32.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
+        L.orc_render_bruteforce_f32.restype = None
+        L.orc_render_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_render_f64.restype = C.c_double
+        L.orc_backward_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_backward_f64.restype = None
+        L.orc_temporal_f64.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                       C.c_double, C.c_double, i32, vp, vp]
+        L.orc_temporal_f64.restype = None
+        L.orc_sh_basis_f64.argtypes = [i32, vp, vp, vp]
+        L.orc_sh_basis_f64.restype = None
+        L.orc_project_f64.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
+        L.orc_project_f64.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def cam_array(cam) -> np.ndarray:
+    return np.concatenate([np.asarray(cam["R"], np.float32).reshape(9), np.asarray(cam["T"], np.float32),
+                           np.array([cam["fx"], cam["fy"], cam["cx"], cam["cy"], cam["znear"]],
+                                    np.float32)]).astype(np.float32)
+
+
+def frame_array(t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0)) -> np.ndarray:
+    return np.array([t, dt, mode, bg[0], bg[1], bg[2]], np.float32)
+
+
+def grid(cam):
+    return (cam["width"] + TILE - 1) // TILE, (cam["height"] + TILE - 1) // TILE
+
+
+def _param_ptrs(scene, dtype):
+    arrs = [_c(scene[f], dtype) for f in FIELDS]
+    ptrs = (C.c_void_p * 9)(*[a.ctypes.data for a in arrs])
+    return arrs, ptrs
+
+
+def preprocess_f32(scene, cam, t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0)) -> dict:
+    n = int(scene["n"])
+    arrs, ptrs = _param_ptrs(scene, np.float32)
+    out = {
+        "xy": np.zeros((n, 2), np.float32), "depth": np.zeros(n, np.float32),
+        "conic_op": np.zeros((n, 4), np.float32), "rgb": np.zeros((n, 3), np.float32),
+        "radius": np.zeros(n, np.int32), "rect": np.zeros((n, 4), np.int32),
+        "tiles": np.zeros(n, np.uint32), "flags": np.zeros(n, np.uint32),
+    }
+    cv, fv = cam_array(cam), frame_array(t, dt, mode, bg)
+    lib().orc_preprocess_f32(n, int(scene["sh_degree"]), ptrs, _p(cv), cam["width"], cam["height"], _p(fv),
+                             *[_p(out[k]) for k in ("xy", "depth", "conic_op", "rgb", "radius", "rect",
+                                                    "tiles", "flags")])
+    return out
+
+
+def bin_sort(pre, cam) -> dict:
+    n = pre["depth"].shape[0]
+    GX, GY = grid(cam)
+    M = int(pre["tiles"].astype(np.int64).sum())
+    it = np.zeros(max(M, 1), np.uint32)
+    ig = np.zeros(max(M, 1), np.uint32)
+    ranges = np.zeros((GX * GY, 2), np.uint32)
+    got = lib().orc_bin_sort(n, _p(pre["depth"]), _p(pre["rect"]), _p(pre["radius"]), GX, GY, M,
+                             _p(it), _p(ig), _p(ranges))
+    assert got == M, (got, M)
+    return {"M": M, "inst_tile": it[:M], "inst_gauss": ig[:M], "ranges": ranges}
+
+
+def render_f32(pre, bins, cam, t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0), tiles=None):
+    n = pre["depth"].shape[0]
+    W, H = cam["width"], cam["height"]
+    GX, GY = grid(cam)
+    lo, hi = (0, GX * GY) if tiles is None else tiles
+    img = np.zeros((3, H, W), np.float32)
+    T = np.zeros((H, W), np.float32)
+    nc = np.zeros((H, W), np.int32)
+    cv, fv = cam_array(cam), frame_array(t, dt, mode, bg)
+    ig = bins["inst_gauss"] if bins["M"] > 0 else np.zeros(1, np.uint32)
+    lib().orc_render_f32(n, _p(pre["xy"]), _p(pre["conic_op"]), _p(pre["rgb"]), _p(pre["radius"]), _p(cv),
+                         W, H, _p(fv), _p(bins["ranges"]), _p(ig), lo, hi, _p(img), _p(T), _p(nc))
+    return img, T, nc
+
+
+def render_bruteforce_f32(pre, cam, t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0)):
+    n = pre["depth"].shape[0]
+    W, H = cam["width"], cam["height"]
+    img = np.zeros((3, H, W), np.float32)
+    T = np.zeros((H, W), np.float32)
+    nc = np.zeros((H, W), np.int32)
+    fv = frame_array(t, dt, mode, bg)
+    lib().orc_render_bruteforce_f32(n, _p(pre["xy"]), _p(pre["depth"]), _p(pre["conic_op"]), _p(pre["rgb"]),
+                                    _p(pre["radius"]), _p(pre["rect"]), W, H, _p(fv), _p(img), _p(T), _p(nc))
+    return img, T, nc
+
+
+def render(scene, cam, t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0)) -> dict:
+    """The whole FP32 forward: preprocess, instances, per-pixel compositing."""
+    pre = preprocess_f32(scene, cam, t, dt, mode, bg)
+    bins = bin_sort(pre, cam)
+    img, T, nc = render_f32(pre, bins, cam, t, dt, mode, bg)
+    return {"pre": pre, "bins": bins, "img": img, "final_T": T, "n_contrib": nc}
+
+
+def scene64(scene) -> dict:
+    out = {"n": scene["n"], "sh_degree": scene["sh_degree"]}
+    for f in FIELDS:
+        out[f] = np.ascontiguousarray(scene[f], dtype=np.float64)
+    return out
+
+
+def render_f64(sc64, cam, t, dt, mode, bg, pre, bins, tile_mask=None, w=None, want_img=True):
+    """FP64 image on the FP32 stage's discrete structure; returns (sum(w*img), img, final_T)."""
+    n = int(sc64["n"])
+    W, H = cam["width"], cam["height"]
+    arrs, ptrs = _param_ptrs(sc64, np.float64)
+    img = np.zeros((3, H, W), np.float64) if want_img else None
+    T = np.zeros((H, W), np.float64) if want_img else None
+    cv, fv = cam_array(cam), frame_array(t, dt, mode, bg)
+    ig = bins["inst_gauss"] if bins["M"] > 0 else np.zeros(1, np.uint32)
+    wv = None if w is None else _c(w, np.float64)
+    tm = None if tile_mask is None else _c(tile_mask, np.uint8)
+    L = lib().orc_render_f64(n, int(sc64["sh_degree"]), ptrs, _p(cv), W, H, _p(fv), _p(pre["xy"]),
+                             _p(pre["conic_op"]), _p(pre["radius"]), _p(pre["flags"]), _p(bins["ranges"]),
+                             _p(ig), _p(tm), _p(wv), _p(img), _p(T))
+    return L, img, T
+
+
+def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg) -> tuple[dict, np.ndarray]:
+    """FP64 gradients of sum(dimg * image) for every parameter array, and g2d [N,9]."""
+    n = int(sc64["n"])
+    W, H = cam["width"], cam["height"]
+    arrs, ptrs = _param_ptrs(sc64, np.float64)
+    grads = {f: np.zeros_like(sc64[f], dtype=np.float64) for f in FIELDS}
+    gptrs = (C.c_void_p * 9)(*[grads[f].ctypes.data for f in FIELDS])
+    g2d = np.zeros((n, 9), np.float64)
+    cv, fv = cam_array(cam), frame_array(t, dt, mode, bg)
+    ig = bins["inst_gauss"] if bins["M"] > 0 else np.zeros(1, np.uint32)
+    d = _c(dimg, np.float64)
+    lib().orc_backward_f64(n, int(sc64["sh_degree"]), ptrs, _p(cv), W, H, _p(fv), _p(pre["xy"]),
+                           _p(pre["conic_op"]), _p(pre["radius"]), _p(pre["flags"]), _p(bins["ranges"]),
+                           _p(ig), _p(d), gptrs, _p(g2d))
+    return grads, g2d
+
+
+def temporal_f64(mu, v, l, tau, beta, o, t, dt=0.0, mode=0):
+    mu = _c(mu, np.float64)
+    v = _c(v, np.float64)
+    mu_r = np.zeros(3, np.float64)
+    op = np.zeros(1, np.float64)
+    lib().orc_temporal_f64(_p(mu), _p(v), l, tau, beta, o, t, dt, mode, _p(mu_r), _p(op))
+    return mu_r, float(op[0])
+
+
+def sh_basis_f64(direction, degree=3):
+    d = _c(direction, np.float64)
+    K = (degree + 1) ** 2
+    Y = np.zeros(K, np.float64)
+    dY = np.zeros((K, 3), np.float64)
+    lib().orc_sh_basis_f64(degree, _p(d), _p(Y), _p(dY))
+    return Y, dY
+
+
+def project_f64(mu, s, q, cam):
+    m = np.zeros(2, np.float64)
+    J = np.zeros(4, np.float64)
+    cov = np.zeros(3, np.float64)
+    cv = cam_array(cam)
+    lib().orc_project_f64(_p(_c(mu, np.float64)), _p(_c(s, np.float64)), _p(_c(q, np.float64)), _p(cv),
+                          cam["width"], cam["height"], _p(m), _p(J), _p(cov))
+    return m, J, cov
