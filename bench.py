@@ -1,0 +1,237 @@
+"""Benchmark of the PVG rasterizer on one MI355X.
+
+A step is one training-shaped iteration of the 1M-Gaussian, 1920x1280,
+degree-3 workload: three cameras (yaw -45, 0, +45 degrees) at one time t, each
+rendered as H(t) and as the flow-translated H^(t + dt) with dt = 0.05
+(Eq. (12)), an L1 loss against a uniform target for each of the six images,
+and the backward of all six into one set of parameter gradients.  Inputs are
+synthetic (seeded) and resident in HBM before the timed region.
+
+Prints one JSON line: value = training-shaped iterations per second; the
+forward-only rate (Mpix/s over the three H(t) renders), per-stage times from
+HIP events recorded on the launch stream, the dominant kernel's roofline and
+the single-threaded CPU oracle timed on a bounded sample are extra fields.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s fwd and fwd+bwd iters/s @1M Gaussians 1920x1280; serving p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+# FP32 operations per evaluated (pixel, Gaussian) pair, counted from the
+# kernels' arithmetic: forward 25 (incl. one exp), adjoint 70 (recomputed
+# alpha, transmittance recovery, nine partial derivatives).
+FLOPS_PER_PAIR = {"render_fwd": 25.0, "render_bwd": 70.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=None, help="override the Gaussian count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
+    return ap.parse_args()
+
+
+def stage_bytes(stage, n, n_vis, M, K, tiles, tile_passes):
+    """Algorithmic HBM bytes of one invocation of a stage."""
+    if stage == "preprocess":
+        return n * (68 + 12) + n_vis * (12 * K + 36)
+    if stage == "compact":
+        return n * 8 + n_vis * 8
+    if stage == "depth_sort":
+        return 4 * 16 * n_vis
+    if stage == "scan_emit":
+        return n_vis * 16 + M * 8
+    if stage == "tile_sort":
+        return tile_passes * 16 * M
+    if stage == "ranges":
+        return M * 4 + tiles * 8
+    if stage == "preprocess_bwd":
+        return n * (4 + (17 + 3 * K) * 4) + n_vis * (36 + 68 + 12 * K)
+    return 0
+
+
+def cpu_baseline(cfg, budget_s=20.0):
+    """The oracle (single thread) on one camera's H(t) render of the same
+    scene: FP32 preprocess of all Gaussians, instance sort, and per-pixel
+    compositing of as many tile rows as fit the time budget."""
+    import numpy as np
+
+    import oracle
+    oracle.build(force=False)
+    scene, cam, t = cfg["scene"], cfg["cameras"][1], cfg["t"]
+    t0 = time.perf_counter()
+    pre = oracle.preprocess_f32(scene, cam, t)
+    bins = oracle.bin_sort(pre, cam)
+    t_setup = time.perf_counter() - t0
+    GX, GY = oracle.grid(cam)
+    rows, spent = 0, 0.0
+    t1 = time.perf_counter()
+    while rows < GY and (time.perf_counter() - t0) < budget_s:
+        oracle.render_f32(pre, bins, cam, t, tiles=(rows * GX, (rows + 1) * GX))
+        rows += 1
+    spent = time.perf_counter() - t1
+    px_rows = rows * 16 * cam["width"]
+    full_composite = spent * (GY / max(rows, 1))
+    per_render = t_setup + full_composite
+    return {
+        "value": (cam["width"] * cam["height"]) / per_render / 1e6,
+        "unit": "Mpix/s fwd",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one 1920x1280 H(t) render of the 1M-Gaussian scene: preprocess + sort of all "
+                   f"{scene['n']} Gaussians ({t_setup:.1f} s) and compositing of {rows}/{GY} tile rows "
+                   f"({px_rows} px, {spent:.1f} s), scaled to the full frame"),
+        "host_cores_available": os.cpu_count(),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2311_18561_amd as pvg
+    from paper_2311_18561_amd import _lib as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = gen.make_config(2, n=args.n)
+    scene = cfg["scene"]
+    N, K = scene["n"], (scene["sh_degree"] + 1) ** 2
+    params = [torch.from_numpy(scene[f]).cuda().requires_grad_(True) for f in pvg.FIELDS]
+    targets = [torch.from_numpy(x).cuda() for x in cfg["targets"]]
+    cams, t, dt = cfg["cameras"], cfg["t"], cfg["dt"]
+    W, H = cfg["width"], cfg["height"]
+    lib = L.load()
+    print(f"# workload: N={N} {W}x{H} views={len(cams)} t={t:.4f} dt={dt}", file=sys.stderr, flush=True)
+
+    def train_step():
+        for p in params:
+            p.grad = None
+        loss = None
+        for cam, tgt in zip(cams, targets):
+            for d in (0.0, dt):
+                img = pvg.pvg_render(params, cam, t, d)
+                l1 = (img - tgt).abs().mean()
+                loss = l1 if loss is None else loss + l1
+        loss.backward()
+        return loss
+
+    def fwd_step():
+        with torch.no_grad():
+            for cam in cams:
+                pvg.render(params, cam, t)
+
+    for _ in range(args.warmup):
+        train_step()
+        fwd_step()
+    torch.cuda.synchronize()
+
+    # timed region: K training-shaped steps, stage events on the launch stream
+    lib.pvg_profile_reset()
+    lib.pvg_profile_enable(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        train_step()
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    lib.pvg_profile_collect()
+    lib.pvg_profile_enable(0)
+    stages = {}
+    import ctypes as C
+    for s, name in enumerate(L.STAGES):
+        ms, calls, work = C.c_double(), C.c_int64(), C.c_int64()
+        lib.pvg_profile_read(s, C.byref(ms), C.byref(calls), C.byref(work))
+        stages[name] = {"ms": ms.value, "calls": calls.value, "work": work.value}
+    lib.pvg_profile_reset()
+
+    # forward-only rate over the three H(t) renders
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd_step()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    mpix_fwd = args.steps * len(cams) * W * H / t_fwd / 1e6
+
+    # per-render counts for the byte model
+    img, T, nc, geom, bins = pvg.render(params, cams[1], t)
+    M, n_vis = bins.num_instances, bins.num_visible
+    tiles = ((W + 15) // 16) * ((H + 15) // 16)
+    tile_passes = (max(1, (tiles - 1).bit_length()) + 7) // 8
+    per_step_calls = {}
+    table = {}
+    for name, st in stages.items():
+        if st["calls"] == 0:
+            continue
+        per_launch_ms = st["ms"] / st["calls"]
+        row = {"ms_per_step": st["ms"] / args.steps, "ms_per_call": per_launch_ms, "calls_per_step":
+               st["calls"] / args.steps}
+        if name in FLOPS_PER_PAIR:
+            pairs = st["work"] / st["calls"]
+            row.update(bound="alu", pairs_per_call=pairs,
+                       tflops=pairs * FLOPS_PER_PAIR[name] / (per_launch_ms * 1e-3) / 1e12)
+        else:
+            b = stage_bytes(name, N, n_vis, M, K, tiles, tile_passes)
+            row.update(bound="hbm", bytes_per_call=b, gbs=b / (per_launch_ms * 1e-3) / 1e9)
+        table[name] = row
+        per_step_calls[name] = row["calls_per_step"]
+    dom = max(table, key=lambda k: table[k]["ms_per_step"])
+    d = table[dom]
+    if d["bound"] == "alu":
+        roof = {"bound": "alu", "kernel": dom, "achieved": d["tflops"], "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": d["tflops"] / FP32_PEAK_TFLOPS, "traffic": None,
+                "per_launch": {"pairs": d["pairs_per_call"], "flops_per_pair": FLOPS_PER_PAIR[dom],
+                               "avg_ms": d["ms_per_call"]}}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                "per_launch": {"bytes": d["bytes_per_call"], "avg_ms": d["ms_per_call"]}}
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / t_train,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_train / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "pvg-train-step 1M Gaussians SH3 1920x1280, 3 cameras x {H(t), H^(t+0.05)}",
+                   "gaussians": N, "width": W, "height": H, "views_per_step": 2 * len(cams)},
+        "mpix_per_s_fwd": mpix_fwd,
+        "instances_per_render": M,
+        "visible_per_render": n_vis,
+        "roofline": roof,
+        "stages": table,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * pvg.h - C ABI of the MI355X (gfx950) PVG splatting rasterizer.
+ *
+ * The library renders the image of a set of Periodic Vibration Gaussians
+ * (PVG, arXiv 2311.18561) at a time t seen by a camera (E, I), and
+ * differentiates it: I^ = Render({H_i(t)}; E, I) (Sec. 3.2, Eq. (8)), where
+ * H(t) = {mu~(t), q, s, o~(t), c} (Eq. (5)),
+ *   mu~(t) = mu + (l / 2pi) sin(2pi (t - tau) / l) v      (Eq. (6)),
+ *   o~(t)  = o exp(-(t - tau)^2 / (2 beta^2))              (Eq. (7)),
+ * projected with Sigma' = J W Sigma W^T J^T (Sec. 3.1, Eq. (2)) and
+ * alpha-blended front to back in depth order, C = sum_i T_i alpha_i c_i
+ * (Sec. 3.1, Eq. (3)), over 16x16 pixel tiles.  The temporal-smoothing render
+ * of Sec. 3.4 (Eq. (12)) is the same call with frame.dt != 0: the Gaussians are
+ * evaluated at t and moved by the flow translation v_bar * dt, with
+ * v_bar = v exp(-rho / 2), rho = beta / l (Eq. (10)).
+ *
+ * Conventions.
+ *   - Every array is FP32 (or the stated integer type), contiguous, on the
+ *     device unless stated otherwise.  Parameter arrays are structure-of-arrays:
+ *     "[3][n]" means element (c, i) is at c * n + i.
+ *   - The caller owns every input, output and workspace buffer.  The library
+ *     never frees caller memory and allocates none in the rendering calls.
+ *   - Every call is asynchronous on the caller's HIP stream (a hipStream_t
+ *     passed as void*, NULL = the null stream) and returns an int status:
+ *     0 = PVG_OK, negative = error.  Arguments are validated on the host
+ *     (null pointers, n < 0, degree outside 0..3, non-positive image size or
+ *     focal length, capacity < 0); a failed validation launches nothing.
+ *     No C++ exception crosses the ABI and the library never aborts.
+ *     pvg_last_error() returns the thread's last error message.
+ *   - NaN parameters propagate: a Gaussian whose camera depth, covariance or
+ *     tile rectangle is NaN is treated as invisible; NaN colours propagate.
+ *   - Camera: x_cam = R x_world + T (R row-major), pinhole (fx, fy, cx, cy),
+ *     looking down +z, x right, y down.  Pixel (i, j) is sampled at the point
+ *     whose projected coordinates minus (0.5, 0.5) equal (i, j).
+ *   - The fixed constants of the rasterizer (the paper leaves them open):
+ *     16x16 tiles, near plane at camera.znear, Jacobian evaluated at the point
+ *     clamped to 1.3x the half field of view, +0.3 px^2 on the 2D covariance,
+ *     radius ceil(3 sqrt(lambda_max)) with a 0.1 floor under the eigenvalue
+ *     discriminant, alpha = min(0.99, o~ G), pairs with alpha < 1/255 or a
+ *     positive exponent skipped, a pixel stops before the Gaussian that would
+ *     take its transmittance below 1e-4.  Colour: real spherical harmonics of
+ *     degree <= 3 (index l*l + l + m, no Condon-Shortley phase) of the unit
+ *     direction from the camera centre to the (translated) mean, plus 0.5,
+ *     clamped at 0.  Order within a tile: camera depth, then Gaussian index.
+ */
+#ifndef PVG_H
+#define PVG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum pvg_status {
+  PVG_OK = 0,
+  PVG_ERR_INVALID = -1,   /* bad argument */
+  PVG_ERR_CAPACITY = -2,  /* instance buffers too small; bins->num_instances holds the need */
+  PVG_ERR_NOMEM = -3,     /* a workspace or memory budget is too small */
+  PVG_ERR_BUSY = -4,      /* the resource is in use (e.g. a scene with pending requests) */
+  PVG_ERR_HIP = -5,       /* a HIP runtime call failed; pvg_last_error() has its message */
+  PVG_ERR_NOT_FOUND = -6, /* unknown scene id or ticket */
+  PVG_ERR_TIMEOUT = -7    /* a wait timed out */
+};
+
+/* The per-point parameter set {mu, q, s, o, c, tau, beta, v} of Sec. 3.2,
+ * plus the cycle length l per point (a constant array reproduces the paper's
+ * scene-wide l).  All device pointers, read only. */
+typedef struct pvg_gaussians {
+  int64_t n;           /* number of Gaussians, >= 0 */
+  int32_t sh_degree;   /* 0..3; K = (sh_degree + 1)^2 coefficients per channel */
+  int32_t reserved;
+  const float* mu;      /* [3][n] mean position (world) */
+  const float* scale;   /* [3][n] scale s > 0 (linear, not log) */
+  const float* rot;     /* [4][n] quaternion (w, x, y, z), any nonzero norm */
+  const float* sh;      /* [K][3][n] colour coefficients, element (k, ch, i) */
+  const float* opacity; /* [n] peak opacity o in (0, 1] (already activated) */
+  const float* vel;     /* [3][n] velocity v = d mu~ / dt at t = tau */
+  const float* period;  /* [n] cycle length l > 0 */
+  const float* tau;     /* [n] life peak tau */
+  const float* beta;    /* [n] lifespan beta > 0 */
+} pvg_gaussians;
+
+/* Gradients in the layout of pvg_gaussians (device, written or accumulated). */
+typedef struct pvg_gaussians_grad {
+  float* mu; float* scale; float* rot; float* sh; float* opacity;
+  float* vel; float* period; float* tau; float* beta;
+} pvg_gaussians_grad;
+
+typedef struct pvg_camera { /* host struct, passed by pointer */
+  float R[9];               /* world -> camera rotation, row-major */
+  float T[3];               /* world -> camera translation */
+  float fx, fy, cx, cy;     /* pinhole intrinsics in pixels, fx, fy > 0 */
+  int32_t width, height;    /* image size in pixels, > 0 (any size; partial tiles allowed) */
+  float znear;              /* Gaussians with camera z <= znear are culled */
+} pvg_camera;
+
+typedef struct pvg_frame {  /* host struct */
+  float t;                  /* render time */
+  float dt;                 /* flow-translation interval of Eq. (12); 0 = plain render */
+  int32_t advect_mode;      /* 0: translate by v_bar = v exp(-beta / (2 l)) (Eq. (10)); 1: by v */
+  float bg[3];              /* constant background added as T_final * bg */
+} pvg_frame;
+
+/* Per-Gaussian projected record (pvg_preprocess output; caller-allocated, length n). */
+typedef struct pvg_geom {
+  int64_t n;
+  float* xy;          /* [n][2] pixel-space 2D mean */
+  float* depth;       /* [n] camera-space z (the sort key) */
+  float* conic_op;    /* [n][4] inverse 2D covariance (A, B, C) and opacity o~(t) */
+  float* rgb;         /* [n][3] colour */
+  int32_t* radius;    /* [n] screen radius in pixels; 0 = invisible */
+  uint32_t* tiles;    /* [n] number of tiles the Gaussian's rectangle touches */
+} pvg_geom;
+
+/* Tile instances: one (tile, Gaussian) pair per tile a visible Gaussian's
+ * rectangle touches, sorted by (tile, depth, index). */
+typedef struct pvg_bins {
+  int64_t capacity;     /* instance capacity of each half of keys / vals, >= 0 */
+  uint32_t* keys;       /* [2][capacity] tile id per instance (double buffer) */
+  uint32_t* vals;       /* [2][capacity] Gaussian index; sorted result in vals[0 .. M) */
+  uint32_t* ranges;     /* [tiles][2] [first, last + 1) of each tile in vals */
+  uint32_t* counters;   /* [4] device: M, visible count, overflow flag, reserved */
+  int64_t num_instances;/* host output of a synchronous count (sync_count = 1) */
+  int64_t num_visible;  /* host output of a synchronous count */
+} pvg_bins;
+
+typedef struct pvg_ws_sizes {
+  size_t bin_tmp_bytes;    /* scratch of pvg_bin_sort */
+  size_t bwd_tmp_bytes;    /* scratch of pvg_render_bwd */
+  int64_t num_tiles;       /* ceil(width / 16) * ceil(height / 16) */
+} pvg_ws_sizes;
+
+/* Scratch sizes for n Gaussians, one width x height image and an instance
+ * capacity.  Host only; does not touch the device. */
+int pvg_workspace_query(int64_t n, int32_t width, int32_t height, int64_t capacity, pvg_ws_sizes* out);
+
+/* Per-Gaussian stage (Eqs. (6), (7), (10), (12), Eq. (2), colour): temporal
+ * state at frame->t (translated by frame->dt), view transform and near cull,
+ * 3D covariance R(q) S S^T R(q)^T, EWA 2D covariance and its inverse, screen
+ * radius, tile rectangle and count, colour.  Writes every field of `out`
+ * (out->n must equal g->n). */
+int pvg_preprocess(const pvg_gaussians* g, const pvg_camera* cam, const pvg_frame* frame,
+                   pvg_geom* out, void* stream);
+
+/* Depth ordering per tile (Sec. 3.1): emits one instance per (visible
+ * Gaussian, touched tile) and sorts them by (tile, camera depth, index)
+ * with an LDS-histogram LSD radix sort; writes the per-tile ranges.
+ * tmp: bin_tmp_bytes of scratch from pvg_workspace_query (same n, image and
+ * capacity).  sync_count = 1: the instance count is read back to the host
+ * (bins->num_instances, num_visible); if it exceeds bins->capacity the call
+ * returns PVG_ERR_CAPACITY and sorts nothing.  sync_count = 0: nothing is
+ * read back; on overflow counters[2] is set, every tile range is empty and
+ * the render shows only the background. */
+int pvg_bin_sort(const pvg_geom* geom, const pvg_camera* cam, pvg_bins* bins, void* tmp,
+                 size_t tmp_bytes, int32_t sync_count, void* stream);
+
+/* Front-to-back alpha blending of each pixel's tile list (Eq. (3)).
+ * img [3][height][width] = C + T_final * bg; final_T [height][width];
+ * n_contrib [height][width] = list position of the last contributor + 1. */
+int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera* cam,
+                   const pvg_frame* frame, float* img, float* final_T, int32_t* n_contrib,
+                   void* stream);
+
+/* Adjoint of pvg_render_fwd and pvg_preprocess: given dL/dimg [3][H][W] and
+ * the forward's final_T and n_contrib, writes (accumulate = 0) or adds
+ * (accumulate = 1) dL/d(every array of g) into grad.  geom and bins must be
+ * the forward's, or a deterministic recomputation of them (same inputs give
+ * bit-identical geom and bins).  tmp: bwd_tmp_bytes of scratch. */
+int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_frame* frame,
+                   const pvg_geom* geom, const pvg_bins* bins, const float* final_T,
+                   const int32_t* n_contrib, const float* dL_dimg, pvg_gaussians_grad* grad,
+                   int32_t accumulate, void* tmp, size_t tmp_bytes, void* stream);
+
+/* ---- stage timing (HIP events recorded on the launch stream) ------------ */
+enum pvg_stage {
+  PVG_STAGE_PREPROCESS = 0, PVG_STAGE_COMPACT, PVG_STAGE_DEPTH_SORT, PVG_STAGE_SCAN_EMIT,
+  PVG_STAGE_TILE_SORT, PVG_STAGE_RANGES, PVG_STAGE_RENDER_FWD, PVG_STAGE_RENDER_BWD,
+  PVG_STAGE_PREPROCESS_BWD, PVG_STAGE_COUNT
+};
+/* on = 1: every later launch is bracketed by a pair of hipEvents on its
+ * stream and, for the render stages, counts evaluated (pixel, Gaussian) pairs. */
+int pvg_profile_enable(int32_t on);
+/* Waits for the recorded events and adds their durations to the totals. */
+int pvg_profile_collect(void);
+/* Totals since the last reset: milliseconds, number of stage invocations and
+ * work units (evaluated pairs for the render stages, 0 otherwise). */
+int pvg_profile_read(int32_t stage, double* total_ms, int64_t* invocations, int64_t* work);
+int pvg_profile_reset(void);
+const char* pvg_stage_name(int32_t stage);
+
+const char* pvg_status_str(int status);
+/* Copies the calling thread's last error message (NUL-terminated); returns its length. */
+int pvg_last_error(char* buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PVG_H */

@@ -1,0 +1,23 @@
+"""MI355X-native (gfx950) PVG splatting rasterizer.
+
+The differentiable tile-based renderer of Periodic Vibration Gaussian
+(arXiv 2311.18561): time-dependent means and opacities (Sec. 3.2), EWA
+projection and alpha blending (Sec. 3.1), flow-translated second render
+(Sec. 3.4), a hand-written adjoint, and a continuous-batching render server.
+All computation runs in ``libpvg.so`` (HIP kernels behind a C ABI declared in
+``include/pvg.h``); this package only marshals arguments and borrows PyTorch's
+device memory and streams.
+"""
+from ._lib import PVGError, load  # noqa: F401
+from .render import (  # noqa: F401
+    FIELDS,
+    PVGRender,
+    bin_sort,
+    camera_struct,
+    frame_struct,
+    preprocess,
+    pvg_render,
+    render,
+    render_bwd,
+    render_fwd,
+)

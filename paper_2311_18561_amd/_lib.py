@@ -1,0 +1,163 @@
+"""ctypes binding of libpvg (declarations mirror include/pvg.h).
+
+Argument marshalling only: every step of the rendering path runs in the HIP
+library.  Loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpvg.so")
+
+PVG_OK = 0
+PVG_ERR_INVALID = -1
+PVG_ERR_CAPACITY = -2
+PVG_ERR_NOMEM = -3
+PVG_ERR_BUSY = -4
+PVG_ERR_HIP = -5
+PVG_ERR_NOT_FOUND = -6
+PVG_ERR_TIMEOUT = -7
+
+STAGES = ("preprocess", "compact", "depth_sort", "scan_emit", "tile_sort", "ranges", "render_fwd", "render_bwd",
+          "preprocess_bwd")
+
+vp = C.c_void_p
+
+
+class Gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("reserved", C.c_int32),
+                ("mu", vp), ("scale", vp), ("rot", vp), ("sh", vp), ("opacity", vp), ("vel", vp),
+                ("period", vp), ("tau", vp), ("beta", vp)]
+
+
+class GaussiansGrad(C.Structure):
+    _fields_ = [("mu", vp), ("scale", vp), ("rot", vp), ("sh", vp), ("opacity", vp), ("vel", vp),
+                ("period", vp), ("tau", vp), ("beta", vp)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("T", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32),
+                ("znear", C.c_float)]
+
+
+class Frame(C.Structure):
+    _fields_ = [("t", C.c_float), ("dt", C.c_float), ("advect_mode", C.c_int32), ("bg", C.c_float * 3)]
+
+
+class Geom(C.Structure):
+    _fields_ = [("n", C.c_int64), ("xy", vp), ("depth", vp), ("conic_op", vp), ("rgb", vp), ("radius", vp),
+                ("tiles", vp)]
+
+
+class Bins(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("keys", vp), ("vals", vp), ("ranges", vp), ("counters", vp),
+                ("num_instances", C.c_int64), ("num_visible", C.c_int64)]
+
+
+class WsSizes(C.Structure):
+    _fields_ = [("bin_tmp_bytes", C.c_size_t), ("bwd_tmp_bytes", C.c_size_t), ("num_tiles", C.c_int64)]
+
+
+class ServeConfig(C.Structure):
+    _fields_ = [("device", C.c_int32), ("max_batch", C.c_int32), ("max_inflight", C.c_int32),
+                ("reserved", C.c_int32), ("mem_budget_bytes", C.c_int64), ("instance_capacity", C.c_int64),
+                ("max_width", C.c_int32), ("max_height", C.c_int32), ("use_graphs", C.c_int32),
+                ("batching", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("scene_id", C.c_int32), ("reserved", C.c_int32), ("camera", Camera), ("t", C.c_float),
+                ("bg", C.c_float * 3), ("dst", vp), ("user_tag", C.c_int64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("batch_size", C.c_int32), ("img", vp), ("width", C.c_int32),
+                ("height", C.c_int32), ("t_submit_ns", C.c_int64), ("t_launch_ns", C.c_int64),
+                ("t_done_ns", C.c_int64), ("num_instances", C.c_int64), ("user_tag", C.c_int64)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("failed", C.c_int64), ("batches", C.c_int64),
+                ("mean_batch", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("mpix", C.c_double), ("busy_s", C.c_double), ("graph_launches", C.c_int64),
+                ("graph_builds", C.c_int64), ("retries", C.c_int64)]
+
+
+_lib = None
+
+
+class PVGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{status_str(status)} ({status}): {msg}")
+        self.status = status
+
+
+def load():
+    """The loaded library; raises if libpvg.so is missing (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_18561_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    i32, i64 = C.c_int32, C.c_int64
+    sig = {
+        "pvg_workspace_query": ([i64, i32, i32, i64, P(WsSizes)], i32),
+        "pvg_preprocess": ([P(Gaussians), P(Camera), P(Frame), P(Geom), vp], i32),
+        "pvg_bin_sort": ([P(Geom), P(Camera), P(Bins), vp, C.c_size_t, i32, vp], i32),
+        "pvg_render_fwd": ([P(Geom), P(Bins), P(Camera), P(Frame), vp, vp, vp, vp], i32),
+        "pvg_render_bwd": ([P(Gaussians), P(Camera), P(Frame), P(Geom), P(Bins), vp, vp, vp, P(GaussiansGrad),
+                            i32, vp, C.c_size_t, vp], i32),
+        "pvg_profile_enable": ([i32], i32),
+        "pvg_profile_collect": ([], i32),
+        "pvg_profile_read": ([i32, P(C.c_double), P(i64), P(i64)], i32),
+        "pvg_profile_reset": ([], i32),
+        "pvg_stage_name": ([i32], C.c_char_p),
+        "pvg_status_str": ([i32], C.c_char_p),
+        "pvg_last_error": ([C.c_char_p, C.c_size_t], i32),
+        "pvg_serve_create": ([P(ServeConfig), P(vp)], i32),
+        "pvg_serve_load_scene": ([vp, P(Gaussians), P(i32)], i32),
+        "pvg_serve_unload_scene": ([vp, i32], i32),
+        "pvg_serve_submit": ([vp, P(Request), P(C.c_uint64)], i32),
+        "pvg_serve_wait": ([vp, C.c_uint64, i64, P(Result)], i32),
+        "pvg_serve_poll": ([vp, C.c_uint64, P(i32)], i32),
+        "pvg_serve_release": ([vp, C.c_uint64], i32),
+        "pvg_serve_stats": ([vp, P(ServeStats)], i32),
+        "pvg_serve_reset_stats": ([vp], i32),
+        "pvg_serve_destroy": ([vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        if not hasattr(L, name):
+            continue
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def status_str(status: int) -> str:
+    return load().pvg_status_str(status).decode()
+
+
+def last_error() -> str:
+    buf = C.create_string_buffer(1024)
+    load().pvg_last_error(buf, 1024)
+    return buf.value.decode()
+
+
+def check(status: int) -> int:
+    if status != PVG_OK:
+        raise PVGError(status, last_error())
+    return status
+
+
+def exported_symbols() -> list[str]:
+    """Names declared in include/pvg.h (and pvg_serve.h) that the library must export."""
+    return ["pvg_workspace_query", "pvg_preprocess", "pvg_bin_sort", "pvg_render_fwd", "pvg_render_bwd",
+            "pvg_profile_enable", "pvg_profile_collect", "pvg_profile_read", "pvg_profile_reset",
+            "pvg_stage_name", "pvg_status_str", "pvg_last_error"]

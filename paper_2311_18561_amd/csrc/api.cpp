@@ -1,0 +1,338 @@
+// C ABI of libpvg: argument validation, view construction and the stage
+// profiler.  Kernels live in preprocess.hip, binsort.hip and render.hip.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pvg_internal.hpp"
+
+namespace pvg {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error("%s failed: %s", what, hipGetErrorString(e));
+  return PVG_ERR_HIP;
+}
+
+// ------------------------------------------------------------------ profiler
+namespace {
+struct EventPair { int stage; hipEvent_t a, b; };
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<EventPair> g_pending;
+std::vector<hipEvent_t> g_pool;
+double g_ms[PVG_STAGE_COUNT];
+int64_t g_calls[PVG_STAGE_COUNT];
+int64_t g_work[PVG_STAGE_COUNT];
+unsigned long long* g_work_dev = nullptr;
+
+hipEvent_t take_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+bool profiling() { return g_prof_on; }
+
+unsigned long long* profile_work_counter(int stage) {
+  if (!g_prof_on || !g_work_dev) return nullptr;
+  return g_work_dev + stage;
+}
+
+StageScope::StageScope(int stage, hipStream_t s) : stage_(stage), s_(s), on_(false) {
+  if (!g_prof_on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  EventPair p{stage, take_event(), take_event()};
+  if (!p.a || !p.b) return;
+  if (hipEventRecord(p.a, s) != hipSuccess) return;
+  g_pending.push_back(p);
+  on_ = true;
+}
+
+StageScope::~StageScope() {
+  if (!on_) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto it = g_pending.rbegin(); it != g_pending.rend(); ++it) {
+    if (it->stage == stage_) {
+      (void)hipEventRecord(it->b, s_);
+      break;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ validation
+static bool check_gaussians(const pvg_gaussians* g) {
+  if (!g) { set_error("gaussians is null"); return false; }
+  if (g->n < 0) { set_error("n = %lld < 0", static_cast<long long>(g->n)); return false; }
+  if (g->n > 0xffffffffll) { set_error("n = %lld exceeds 2^32 - 1", static_cast<long long>(g->n)); return false; }
+  if (g->sh_degree < 0 || g->sh_degree > 3) { set_error("sh_degree %d outside 0..3", g->sh_degree); return false; }
+  if (g->n > 0 && (!g->mu || !g->scale || !g->rot || !g->sh || !g->opacity || !g->vel || !g->period || !g->tau ||
+                   !g->beta)) {
+    set_error("a parameter array is null");
+    return false;
+  }
+  return true;
+}
+
+static bool check_camera(const pvg_camera* c) {
+  if (!c) { set_error("camera is null"); return false; }
+  if (c->width <= 0 || c->height <= 0) { set_error("image size %d x %d is not positive", c->width, c->height); return false; }
+  if (c->width > 65535 * kTile || c->height > 65535 * kTile) { set_error("image size too large"); return false; }
+  if (!(c->fx > 0.0f) || !(c->fy > 0.0f)) { set_error("focal length must be positive"); return false; }
+  return true;
+}
+
+static bool check_frame(const pvg_frame* f) {
+  if (!f) { set_error("frame is null"); return false; }
+  if (f->advect_mode != 0 && f->advect_mode != 1) { set_error("advect_mode must be 0 or 1"); return false; }
+  return true;
+}
+
+static bool check_geom(const pvg_geom* g, int64_t n) {
+  if (!g) { set_error("geom is null"); return false; }
+  if (g->n != n) { set_error("geom.n = %lld differs from n = %lld", static_cast<long long>(g->n), static_cast<long long>(n)); return false; }
+  if (n > 0 && (!g->xy || !g->depth || !g->conic_op || !g->rgb || !g->radius || !g->tiles)) {
+    set_error("a geom array is null");
+    return false;
+  }
+  return true;
+}
+
+static bool check_bins(const pvg_bins* b) {
+  if (!b) { set_error("bins is null"); return false; }
+  if (b->capacity < 0 || b->capacity > 0xffffffffll) { set_error("capacity outside 0..2^32-1"); return false; }
+  if (!b->ranges || !b->counters || (b->capacity > 0 && (!b->keys || !b->vals))) {
+    set_error("a bins array is null");
+    return false;
+  }
+  return true;
+}
+
+static int64_t tiles_of(const pvg_camera* c) {
+  return static_cast<int64_t>((c->width + kTile - 1) / kTile) * ((c->height + kTile - 1) / kTile);
+}
+
+static View make_view(const pvg_gaussians* g, const pvg_camera* c, const pvg_frame* f) {
+  View v;
+  std::memset(&v, 0, sizeof(v));
+  if (g) v.s = Scene{g->mu, g->scale, g->rot, g->sh, g->opacity, g->vel, g->period, g->tau, g->beta, g->n, g->sh_degree};
+  std::memcpy(v.R, c->R, sizeof(v.R));
+  std::memcpy(v.T, c->T, sizeof(v.T));
+  v.fx = c->fx; v.fy = c->fy; v.cx = c->cx; v.cy = c->cy; v.znear = c->znear;
+  v.W = c->width; v.H = c->height;
+  v.GX = (c->width + kTile - 1) / kTile;
+  v.GY = (c->height + kTile - 1) / kTile;
+  if (f) {
+    v.t = f->t; v.dt = f->dt; v.mode = f->advect_mode;
+    v.bg[0] = f->bg[0]; v.bg[1] = f->bg[1]; v.bg[2] = f->bg[2];
+  }
+  return v;
+}
+
+static ViewSet single(const View& v, int64_t n) {
+  ViewSet vs;
+  std::memset(&vs, 0, sizeof(vs));
+  vs.table = nullptr;
+  vs.one = v;
+  vs.nviews = 1;
+  vs.total_gauss = n;
+  vs.total_tiles = static_cast<int64_t>(v.GX) * v.GY;
+  return vs;
+}
+
+static Geom to_geom(const pvg_geom* g) {
+  return Geom{g->xy, g->depth, g->conic_op, g->rgb, g->radius, g->tiles};
+}
+
+}  // namespace pvg
+
+using namespace pvg;
+
+extern "C" {
+
+int pvg_workspace_query(int64_t n, int32_t width, int32_t height, int64_t capacity, pvg_ws_sizes* out) {
+  if (!out || n < 0 || width <= 0 || height <= 0 || capacity < 0 || capacity > 0xffffffffll) {
+    set_error("invalid workspace query");
+    return PVG_ERR_INVALID;
+  }
+  const int64_t tiles = static_cast<int64_t>((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+  out->bin_tmp_bytes = plan_bins(n, tiles, capacity).total;
+  out->bwd_tmp_bytes = sizeof(float) * kG2DStride * static_cast<size_t>(std::max<int64_t>(n, 1));
+  out->num_tiles = tiles;
+  return PVG_OK;
+}
+
+int pvg_preprocess(const pvg_gaussians* g, const pvg_camera* cam, const pvg_frame* frame, pvg_geom* out,
+                   void* stream) {
+  if (!check_gaussians(g) || !check_camera(cam) || !check_frame(frame) || !check_geom(out, g ? g->n : 0))
+    return PVG_ERR_INVALID;
+  const View v = make_view(g, cam, frame);
+  PVG_HIP(launch_preprocess(single(v, g->n), to_geom(out), static_cast<hipStream_t>(stream)));
+  return PVG_OK;
+}
+
+int pvg_bin_sort(const pvg_geom* geom, const pvg_camera* cam, pvg_bins* bins, void* tmp, size_t tmp_bytes,
+                 int32_t sync_count, void* stream) {
+  if (!geom || !check_geom(geom, geom->n) || !check_camera(cam) || !check_bins(bins)) return PVG_ERR_INVALID;
+  if (geom->n > 0xffffffffll) { set_error("n too large"); return PVG_ERR_INVALID; }
+  const BinPlan plan = plan_bins(geom->n, tiles_of(cam), bins->capacity);
+  if (!tmp || tmp_bytes < plan.total) {
+    set_error("bin_sort scratch of %zu bytes is smaller than the %zu required", tmp_bytes, plan.total);
+    return PVG_ERR_NOMEM;
+  }
+  const View v = make_view(nullptr, cam, nullptr);
+  bins->num_instances = -1;
+  bins->num_visible = -1;
+  return run_bin_sort(single(v, geom->n), to_geom(geom), bins, tmp, plan, sync_count,
+                      static_cast<hipStream_t>(stream));
+}
+
+int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera* cam, const pvg_frame* frame,
+                   float* img, float* final_T, int32_t* n_contrib, void* stream) {
+  if (!geom || !check_geom(geom, geom->n) || !check_bins(bins) || !check_camera(cam) || !check_frame(frame))
+    return PVG_ERR_INVALID;
+  if (!img || !final_T || !n_contrib) { set_error("an output array is null"); return PVG_ERR_INVALID; }
+  View v = make_view(nullptr, cam, frame);
+  v.img = img;
+  v.final_T = final_T;
+  v.n_contrib = n_contrib;
+  PVG_HIP(launch_render_fwd(single(v, geom->n), to_geom(geom), bins->vals, bins->ranges,
+                            static_cast<hipStream_t>(stream)));
+  return PVG_OK;
+}
+
+int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_frame* frame, const pvg_geom* geom,
+                   const pvg_bins* bins, const float* final_T, const int32_t* n_contrib, const float* dL_dimg,
+                   pvg_gaussians_grad* grad, int32_t accumulate, void* tmp, size_t tmp_bytes, void* stream) {
+  if (!check_gaussians(g) || !check_camera(cam) || !check_frame(frame) || !check_geom(geom, g ? g->n : 0) ||
+      !check_bins(bins))
+    return PVG_ERR_INVALID;
+  if (!final_T || !n_contrib || !dL_dimg || !grad) { set_error("an input array is null"); return PVG_ERR_INVALID; }
+  if (g->n > 0 && (!grad->mu || !grad->scale || !grad->rot || !grad->sh || !grad->opacity || !grad->vel ||
+                   !grad->period || !grad->tau || !grad->beta)) {
+    set_error("a gradient array is null");
+    return PVG_ERR_INVALID;
+  }
+  const size_t need = sizeof(float) * kG2DStride * static_cast<size_t>(std::max<int64_t>(g->n, 1));
+  if (!tmp || tmp_bytes < need) {
+    set_error("render_bwd scratch of %zu bytes is smaller than the %zu required", tmp_bytes, need);
+    return PVG_ERR_NOMEM;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  View v = make_view(g, cam, frame);
+  v.final_T = const_cast<float*>(final_T);
+  v.n_contrib = const_cast<int32_t*>(n_contrib);
+  v.dL_dimg = dL_dimg;
+  const ViewSet vs = single(v, g->n);
+  float* g2d = static_cast<float*>(tmp);
+  PVG_HIP(launch_fill_f32(g2d, 0.0f, kG2DStride * g->n, s));
+  PVG_HIP(launch_render_bwd(vs, to_geom(geom), bins->vals, bins->ranges, dL_dimg, g2d, s));
+  PVG_HIP(launch_preprocess_bwd(vs, to_geom(geom), g2d, *grad, accumulate, s));
+  return PVG_OK;
+}
+
+int pvg_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (on && !g_work_dev) {
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&g_work_dev), sizeof(unsigned long long) * PVG_STAGE_COUNT);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(profile counters)");
+    e = hipMemset(g_work_dev, 0, sizeof(unsigned long long) * PVG_STAGE_COUNT);
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(profile counters)");
+  }
+  g_prof_on = on != 0;
+  return PVG_OK;
+}
+
+int pvg_profile_collect(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& p : g_pending) {
+    hipError_t e = hipEventSynchronize(p.b);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.0f;
+    e = hipEventElapsedTime(&ms, p.a, p.b);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    g_ms[p.stage] += ms;
+    g_calls[p.stage] += 1;
+    g_pool.push_back(p.a);
+    g_pool.push_back(p.b);
+  }
+  g_pending.clear();
+  if (g_work_dev) {
+    unsigned long long w[PVG_STAGE_COUNT];
+    hipError_t e = hipMemcpy(w, g_work_dev, sizeof(w), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(profile counters)");
+    for (int i = 0; i < PVG_STAGE_COUNT; ++i) g_work[i] += static_cast<int64_t>(w[i]);
+    e = hipMemset(g_work_dev, 0, sizeof(w));
+    if (e != hipSuccess) return hip_fail(e, "hipMemset(profile counters)");
+  }
+  return PVG_OK;
+}
+
+int pvg_profile_read(int32_t stage, double* total_ms, int64_t* invocations, int64_t* work) {
+  if (stage < 0 || stage >= PVG_STAGE_COUNT) { set_error("unknown stage %d", stage); return PVG_ERR_INVALID; }
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (total_ms) *total_ms = g_ms[stage];
+  if (invocations) *invocations = g_calls[stage];
+  if (work) *work = g_work[stage];
+  return PVG_OK;
+}
+
+int pvg_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (int i = 0; i < PVG_STAGE_COUNT; ++i) { g_ms[i] = 0.0; g_calls[i] = 0; g_work[i] = 0; }
+  return PVG_OK;
+}
+
+const char* pvg_stage_name(int32_t stage) {
+  static const char* names[PVG_STAGE_COUNT] = {"preprocess", "compact", "depth_sort", "scan_emit", "tile_sort",
+                                                "ranges", "render_fwd", "render_bwd", "preprocess_bwd"};
+  if (stage < 0 || stage >= PVG_STAGE_COUNT) return "unknown";
+  return names[stage];
+}
+
+const char* pvg_status_str(int status) {
+  switch (status) {
+    case PVG_OK: return "ok";
+    case PVG_ERR_INVALID: return "invalid argument";
+    case PVG_ERR_CAPACITY: return "instance capacity exceeded";
+    case PVG_ERR_NOMEM: return "insufficient memory or workspace";
+    case PVG_ERR_BUSY: return "busy";
+    case PVG_ERR_HIP: return "HIP runtime error";
+    case PVG_ERR_NOT_FOUND: return "not found";
+    case PVG_ERR_TIMEOUT: return "timeout";
+    default: return "unknown status";
+  }
+}
+
+int pvg_last_error(char* buf, size_t len) {
+  const std::string& s = g_last_error;
+  if (buf && len > 0) {
+    const size_t k = std::min(len - 1, s.size());
+    std::memcpy(buf, s.data(), k);
+    buf[k] = '\0';
+  }
+  return static_cast<int>(s.size());
+}
+
+}  // extern "C"

@@ -1,0 +1,516 @@
+// Tile binning and depth ordering (Sec. 3.1: Gaussians sorted by camera depth,
+// rendered per 16x16 tile) on gfx950.
+//
+// The instance order is the lexicographic order of (tile, depth bits, index).
+// It is built as a least-significant-digit radix sort whose depth digits are
+// hoisted in front of the duplication:
+//   1. compact the visible Gaussians (index order) with their depth bits;
+//   2. stable LSD radix sort of (depth bits, index) over the visible ones only;
+//   3. scan the tile counts in that order and emit, for each Gaussian, one
+//      instance per tile of its rectangle (row-major) - instances now appear
+//      in (depth, index) order;
+//   4. stable LSD radix sort of the instances by tile id (ceil(bits/8) passes);
+//   5. per-tile [first, last+1) ranges.
+// Step 4's stability keeps (depth, index) order inside a tile, so the result
+// equals a full sort of (tile, depth, index) keys, while the passes over the
+// instance array move 8 bytes per instance instead of 12.
+//
+// Every radix pass is the classic three-kernel form: per-block digit
+// histograms in LDS (atomics on LDS counters), an exclusive scan of each
+// digit's row of block counts, and a scatter whose in-block ranks come from
+// wave ballots (lanes with equal digits) and per-wave LDS counters, which keeps
+// the sort stable.  Counts live on the device; kernels sized for a capacity
+// exit early past the live count, so no host synchronisation is needed.
+#include "pvg_internal.hpp"
+
+namespace pvg {
+
+constexpr int kThreads = 256;
+constexpr int kScanItems = 4;                       // items per thread in the scans / compaction
+constexpr int kScanBlock = kThreads * kScanItems;   // 1024
+constexpr int kRsItems = 16;                        // items per thread in a radix pass
+constexpr int kRsBlock = kThreads * kRsItems;       // 4096
+
+// ------------------------------------------------------------------ helpers
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T x, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+template <class T>
+__device__ __forceinline__ T block_excl_scan(T v, T* lds5, T& total) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const T x = wave_incl_scan<T>(v, lane);
+  if (lane == 63) lds5[wid] = x;
+  __syncthreads();
+  if (tid == 0) {
+    T s = 0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+      const T t = lds5[w];
+      lds5[w] = s;
+      s += t;
+    }
+    lds5[4] = s;
+  }
+  __syncthreads();
+  const T r = lds5[wid] + x - v;
+  total = lds5[4];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int64_t live_count(const uint32_t* n_dev, int64_t n_host) {
+  return n_dev ? static_cast<int64_t>(*n_dev) : n_host;
+}
+
+// ------------------------------------------------------------------ step 1: compaction
+__global__ void __launch_bounds__(kThreads) k_vis_count(const uint32_t* __restrict__ tiles, int64_t n,
+                                                        unsigned long long* partials) {
+  __shared__ unsigned long long lds[5];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x * kScanItems;
+  unsigned long long c = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n && tiles[base + k] > 0u) ++c;
+  unsigned long long tot;
+  block_excl_scan<unsigned long long>(c, lds, tot);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// Exclusive scan of `count` block partials in place (one block).  The total
+// is written to *total_out (a u32 counter); with cap >= 0 it is also checked
+// against the instance capacity: counters[0] = total (or 0 on overflow),
+// counters[2] = overflow flag, counters[3] = total saturated to 32 bits.
+__global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* partials, const uint32_t* count_dev,
+                                                        int64_t count_host, int per_block, uint32_t* counters,
+                                                        int which, int64_t cap) {
+  __shared__ unsigned long long wsum[17];
+  const int64_t items = live_count(count_dev, count_host);
+  const int64_t count = (items + per_block - 1) / per_block;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  unsigned long long carry = 0;
+  for (int64_t base = 0; base < count; base += 1024) {
+    const int64_t i = base + tid;
+    const unsigned long long v = i < count ? partials[i] : 0ull;
+    const unsigned long long x = wave_incl_scan<unsigned long long>(v, lane);
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long s = 0;
+      for (int w = 0; w < 16; ++w) {
+        const unsigned long long t = wsum[w];
+        wsum[w] = s;
+        s += t;
+      }
+      wsum[16] = s;
+    }
+    __syncthreads();
+    if (i < count) partials[i] = carry + wsum[wid] + x - v;
+    carry += wsum[16];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (cap < 0) {
+      counters[which] = static_cast<uint32_t>(carry);
+    } else {
+      const bool over = carry > static_cast<unsigned long long>(cap);
+      counters[0] = over ? 0u : static_cast<uint32_t>(carry);
+      counters[2] = over ? 1u : 0u;
+      counters[3] = carry > 0xffffffffull ? 0xffffffffu : static_cast<uint32_t>(carry);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_vis_compact(const uint32_t* __restrict__ tiles,
+                                                          const float* __restrict__ depth, int64_t n,
+                                                          const unsigned long long* __restrict__ partials,
+                                                          uint32_t* keys, uint32_t* vals) {
+  __shared__ unsigned long long lds[5];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x * kScanItems;
+  bool f[kScanItems];
+  unsigned long long c = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    f[k] = base + k < n && tiles[base + k] > 0u;
+    c += f[k] ? 1 : 0;
+  }
+  unsigned long long tot;
+  unsigned long long pos = block_excl_scan<unsigned long long>(c, lds, tot) + partials[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (f[k]) {
+      keys[pos] = __float_as_uint(depth[base + k]);
+      vals[pos] = static_cast<uint32_t>(base + k);
+      ++pos;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ radix passes
+__global__ void __launch_bounds__(kThreads) k_rs_hist(const uint32_t* __restrict__ keys, const uint32_t* n_dev,
+                                                      int64_t n_host, int shift, int bits, uint32_t* hist,
+                                                      int64_t cols) {
+  __shared__ uint32_t h[256];
+  const int64_t n = live_count(n_dev, n_host);
+  const int64_t nb = (n + kRsBlock - 1) / kRsBlock;
+  if (static_cast<int64_t>(blockIdx.x) >= nb) return;
+  const int radix = 1 << bits;
+  const uint32_t mask = static_cast<uint32_t>(radix - 1);
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRsBlock + threadIdx.x;
+#pragma unroll 4
+  for (int k = 0; k < kRsItems; ++k) {
+    const int64_t i = base + k * kThreads;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < radix) hist[threadIdx.x * cols + blockIdx.x] = h[threadIdx.x];
+}
+
+// One block per digit: exclusive scan of that digit's block counts.
+__global__ void __launch_bounds__(kThreads) k_rs_rowscan(uint32_t* hist, int64_t cols, const uint32_t* n_dev,
+                                                         int64_t n_host, uint32_t* rowtot) {
+  __shared__ uint32_t lds[5];
+  const int64_t n = live_count(n_dev, n_host);
+  const int64_t nb = (n + kRsBlock - 1) / kRsBlock;
+  uint32_t* row = hist + blockIdx.x * cols;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += kThreads * 4) {
+    const int64_t i0 = base + threadIdx.x * 4;
+    uint32_t v[4], s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = i0 + k < nb ? row[i0 + k] : 0u;
+      s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan<uint32_t>(s, lds, tot) + carry;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i0 + k < nb) row[i0 + k] = run;
+      run += v[k];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) rowtot[blockIdx.x] = carry;
+}
+
+__global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                         const uint32_t* __restrict__ vin, uint32_t* kout,
+                                                         uint32_t* vout, const uint32_t* n_dev, int64_t n_host,
+                                                         int shift, int bits, const uint32_t* __restrict__ hist,
+                                                         int64_t cols, const uint32_t* __restrict__ rowtot) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t cnt[kThreads / 64][256];
+  __shared__ uint32_t lds[5];
+  const int64_t n = live_count(n_dev, n_host);
+  const int64_t nb = (n + kRsBlock - 1) / kRsBlock;
+  if (static_cast<int64_t>(blockIdx.x) >= nb) return;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int radix = 1 << bits;
+  const uint32_t mask = static_cast<uint32_t>(radix - 1);
+  {
+    const uint32_t t = tid < radix ? rowtot[tid] : 0u;
+    uint32_t tot;
+    const uint32_t digit_base = block_excl_scan<uint32_t>(t, lds, tot);
+    if (tid < radix) run[tid] = digit_base + hist[tid * cols + blockIdx.x];
+    for (int w = 0; w < kThreads / 64; ++w) cnt[w][tid] = 0;
+  }
+  __syncthreads();
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRsBlock + tid;
+  for (int k = 0; k < kRsItems; ++k) {
+    const int64_t i = base + k * kThreads;
+    const bool valid = i < n;
+    const uint32_t key = valid ? kin[i] : 0u;
+    const uint32_t val = valid ? vin[i] : 0u;
+    const uint32_t dig = (key >> shift) & mask;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+      const bool bit = (dig >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    if (!valid) peers = 0;
+    const uint32_t rank = static_cast<uint32_t>(__popcll(peers & lt));
+    if (valid && (peers & lt) == 0) cnt[wid][dig] = static_cast<uint32_t>(__popcll(peers));
+    __syncthreads();
+    if (valid) {
+      uint32_t off = run[dig] + rank;
+      for (int w = 0; w < wid; ++w) off += cnt[w][dig];
+      kout[off] = key;
+      vout[off] = val;
+    }
+    __syncthreads();
+    if (tid < radix) {
+      uint32_t s = 0;
+      for (int w = 0; w < kThreads / 64; ++w) {
+        s += cnt[w][tid];
+        cnt[w][tid] = 0;
+      }
+      run[tid] += s;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ step 3: tile counts and emission
+__global__ void __launch_bounds__(kThreads) k_tile_count(const uint32_t* __restrict__ order,
+                                                         const uint32_t* __restrict__ tiles, const uint32_t* n_dev,
+                                                         int64_t n_host, unsigned long long* partials) {
+  __shared__ unsigned long long lds[5];
+  const int64_t n = live_count(n_dev, n_host);
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x * kScanItems;
+  if (static_cast<int64_t>(blockIdx.x) * kScanBlock >= n) return;
+  unsigned long long c = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) c += tiles[order[base + k]];
+  unsigned long long tot;
+  block_excl_scan<unsigned long long>(c, lds, tot);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__device__ __forceinline__ int32_t clamp_tile_e(float v, int32_t hi) {
+  const float f = floorf(v);
+  if (f < 0.0f) return 0;
+  if (f > static_cast<float>(hi)) return hi;
+  return static_cast<int32_t>(f);
+}
+
+__device__ __forceinline__ const View& view_at(const ViewSet& vs, int32_t v) { return vs.table ? vs.table[v] : vs.one; }
+
+__device__ __forceinline__ int32_t view_of_gauss(const ViewSet& vs, int64_t g) {
+  if (!vs.table) return 0;
+  int32_t lo = 0, hi = vs.nviews - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (vs.table[mid].geom_off <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// A block takes kScanBlock consecutive Gaussians of the depth order and
+// writes all their instances cooperatively (coalesced runs, balanced across
+// the block whatever the rectangle sizes).
+__global__ void __launch_bounds__(kThreads) k_emit(ViewSet vs, const uint32_t* __restrict__ order,
+                                                   const float* __restrict__ xy, const int32_t* __restrict__ radius,
+                                                   const uint32_t* __restrict__ tiles, const uint32_t* n_dev,
+                                                   int64_t n_host, const unsigned long long* __restrict__ partials,
+                                                   const uint32_t* __restrict__ counters, uint32_t* keys,
+                                                   uint32_t* vals) {
+  __shared__ uint32_t s_off[kScanBlock + 1];
+  __shared__ uint32_t s_g[kScanBlock];
+  __shared__ uint32_t s_base[kScanBlock];
+  __shared__ uint32_t s_wg[kScanBlock];  // rectangle width (low 16) | tile grid width (high 16)
+  __shared__ unsigned long long lds[5];
+  if (counters[2]) return;  // over capacity: nothing is emitted
+  const int64_t n = live_count(n_dev, n_host);
+  const int64_t blk0 = static_cast<int64_t>(blockIdx.x) * kScanBlock;
+  if (blk0 >= n) return;
+  const int tid = threadIdx.x;
+  uint32_t cnt[kScanItems];
+  unsigned long long c = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = blk0 + tid * kScanItems + k;
+    const int li = tid * kScanItems + k;
+    if (idx < n) {
+      const uint32_t g = order[idx];
+      const View& v = view_at(vs, view_of_gauss(vs, g));
+      const float2 m = reinterpret_cast<const float2*>(xy)[g];
+      const float rr = static_cast<float>(radius[g]);
+      const int32_t x0 = clamp_tile_e((m.x - rr) / 16.0f, v.GX);
+      const int32_t y0 = clamp_tile_e((m.y - rr) / 16.0f, v.GY);
+      const int32_t x1 = clamp_tile_e(((m.x + rr) + 15.0f) / 16.0f, v.GX);
+      cnt[k] = tiles[g];
+      s_g[li] = g;
+      s_base[li] = static_cast<uint32_t>(v.tile_off + static_cast<int64_t>(y0) * v.GX + x0);
+      s_wg[li] = static_cast<uint32_t>(x1 - x0) | (static_cast<uint32_t>(v.GX) << 16);
+    } else {
+      cnt[k] = 0;
+      s_g[li] = 0;
+      s_base[li] = 0;
+      s_wg[li] = 1;
+    }
+    c += cnt[k];
+  }
+  unsigned long long tot;
+  const unsigned long long ex = block_excl_scan<unsigned long long>(c, lds, tot);
+  const unsigned long long start = partials[blockIdx.x];
+  {
+    unsigned long long r = start + ex;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      s_off[tid * kScanItems + k] = static_cast<uint32_t>(r);
+      r += cnt[k];
+    }
+  }
+  if (tid == 0) s_off[kScanBlock] = static_cast<uint32_t>(start + tot);
+  __syncthreads();
+  const uint32_t S = s_off[0], E = s_off[kScanBlock];
+  for (uint32_t j = S + tid; j < E; j += kThreads) {
+    int lo = 0, hi = kScanBlock - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t q = j - s_off[lo];
+    const uint32_t wg = s_wg[lo];
+    const uint32_t w = wg & 0xffffu, gx = wg >> 16;
+    const uint32_t dy = q / w, dx = q - dy * w;
+    keys[j] = s_base[lo] + dy * gx + dx;
+    vals[j] = s_g[lo];
+  }
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ counters,
+                         uint32_t* ranges) {
+  const int64_t n = counters[0];
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t t = keys[j];
+  if (j == 0 || keys[j - 1] != t) ranges[2 * static_cast<int64_t>(t)] = static_cast<uint32_t>(j);
+  if (j == n - 1 || keys[j + 1] != t) ranges[2 * static_cast<int64_t>(t) + 1] = static_cast<uint32_t>(j + 1);
+}
+
+// ------------------------------------------------------------------ host pipeline
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity) {
+  BinPlan p{};
+  p.n = n;
+  p.tiles = tiles;
+  p.capacity = capacity;
+  int bits = 0;
+  while ((int64_t{1} << bits) < tiles) ++bits;
+  p.tile_bits = bits;
+  p.tile_passes = static_cast<int>(cdiv(bits, 8));
+  p.hist_cols = std::max<int64_t>(1, std::max(cdiv(n, kRsBlock), cdiv(capacity, kRsBlock)));
+  size_t off = 0;
+  p.off_vis_keys = off; off = align256(off + sizeof(uint32_t) * 2 * std::max<int64_t>(n, 1));
+  p.off_vis_vals = off; off = align256(off + sizeof(uint32_t) * 2 * std::max<int64_t>(n, 1));
+  p.off_offsets = off;  off = align256(off + sizeof(uint32_t) * 4);
+  const int64_t nparts = std::max<int64_t>(1, cdiv(n, kScanBlock));
+  p.off_partials = off; off = align256(off + sizeof(unsigned long long) * (nparts + 1));
+  p.off_hist = off;     off = align256(off + sizeof(uint32_t) * 256 * p.hist_cols);
+  p.off_rowtot = off;   off = align256(off + sizeof(uint32_t) * 256);
+  p.total = off;
+  return p;
+}
+
+// One stable LSD pass of `bits` bits at `shift` from (kin, vin) to (kout, vout).
+static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                             const uint32_t* n_dev, int64_t n_grid, int shift, int bits, uint32_t* hist,
+                             int64_t cols, uint32_t* rowtot, hipStream_t s) {
+  const unsigned nb = static_cast<unsigned>(std::max<int64_t>(1, cdiv(n_grid, kRsBlock)));
+  hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, kin, n_dev, n_grid, shift, bits, hist, cols);
+  hipLaunchKernelGGL(k_rs_rowscan, dim3(1u << bits), dim3(kThreads), 0, s, hist, cols, n_dev, n_grid, rowtot);
+  hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_grid, shift,
+                     bits, hist, cols, rowtot);
+  return hipGetLastError();
+}
+
+int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp, const BinPlan& plan,
+                 int sync_count, hipStream_t s) {
+  char* base = static_cast<char*>(tmp);
+  uint32_t* vkeys = reinterpret_cast<uint32_t*>(base + plan.off_vis_keys);
+  uint32_t* vvals = reinterpret_cast<uint32_t*>(base + plan.off_vis_vals);
+  unsigned long long* partials = reinterpret_cast<unsigned long long*>(base + plan.off_partials);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(base + plan.off_hist);
+  uint32_t* rowtot = reinterpret_cast<uint32_t*>(base + plan.off_rowtot);
+  uint32_t* counters = bins->counters;
+  const int64_t n = plan.n;
+  const int64_t cap = plan.capacity;
+  const int64_t nvis_stride = std::max<int64_t>(n, 1);
+
+  PVG_HIP(launch_fill_u32(counters, 0u, 4, s));
+  if (n > 0) {
+    StageScope sc(PVG_STAGE_COMPACT, s);
+    const unsigned nb = static_cast<unsigned>(cdiv(n, kScanBlock));
+    hipLaunchKernelGGL(k_vis_count, dim3(nb), dim3(kThreads), 0, s, geom.tiles, n, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nullptr, n, kScanBlock, counters, 1,
+                       int64_t{-1});
+    hipLaunchKernelGGL(k_vis_compact, dim3(nb), dim3(kThreads), 0, s, geom.tiles, geom.depth, n, partials, vkeys,
+                       vvals);
+    PVG_HIP(hipGetLastError());
+  }
+  // depth sort of the visible Gaussians: 4 passes of 8 bits, ends in buffer 0
+  if (n > 0) {
+    StageScope sc(PVG_STAGE_DEPTH_SORT, s);
+    for (int pass = 0; pass < 4; ++pass) {
+      const int src = pass & 1, dst = src ^ 1;
+      PVG_HIP(radix_pass(vkeys + src * nvis_stride, vvals + src * nvis_stride, vkeys + dst * nvis_stride,
+                         vvals + dst * nvis_stride, counters + 1, n, 8 * pass, 8, hist, plan.hist_cols, rowtot, s));
+    }
+  }
+  const uint32_t* order = vvals;  // buffer 0 after an even number of passes
+  // instance offsets in depth order and the capacity check
+  {
+    StageScope sc(PVG_STAGE_SCAN_EMIT, s);
+    if (n > 0) {
+      const unsigned nb = static_cast<unsigned>(cdiv(n, kScanBlock));
+      hipLaunchKernelGGL(k_tile_count, dim3(nb), dim3(kThreads), 0, s, order, geom.tiles, counters + 1, n,
+                         partials);
+      hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, counters + 1, n, kScanBlock,
+                         counters, 0, cap);
+      PVG_HIP(hipGetLastError());
+    }
+  }
+  int64_t m_grid = cap;
+  int64_t vis_grid = n;
+  if (sync_count) {
+    uint32_t host_counts[4];
+    PVG_HIP(hipMemcpyAsync(host_counts, counters, sizeof(host_counts), hipMemcpyDeviceToHost, s));
+    PVG_HIP(hipStreamSynchronize(s));
+    bins->num_instances = host_counts[3] == 0xffffffffu ? int64_t{0xffffffff} : int64_t{host_counts[3]};
+    bins->num_visible = host_counts[1];
+    if (host_counts[2]) {
+      set_error("instance capacity %lld is smaller than the %lld instances of this render",
+                static_cast<long long>(cap), static_cast<long long>(bins->num_instances));
+      return PVG_ERR_CAPACITY;
+    }
+    m_grid = host_counts[0];
+    vis_grid = host_counts[1];
+  }
+  const int passes = plan.tile_passes;
+  const int start = passes & 1;  // so that the last pass lands in buffer 0
+  if (n > 0 && vis_grid > 0) {
+    StageScope sc(PVG_STAGE_SCAN_EMIT, s);
+    const unsigned nb = static_cast<unsigned>(cdiv(vis_grid, kScanBlock));
+    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kThreads), 0, s, vs, order, geom.xy, geom.radius, geom.tiles,
+                       counters + 1, n, partials, counters, bins->keys + start * cap, bins->vals + start * cap);
+    PVG_HIP(hipGetLastError());
+  }
+  if (passes > 0 && m_grid > 0) {
+    StageScope sc(PVG_STAGE_TILE_SORT, s);
+    const int per = (plan.tile_bits + passes - 1) / passes;
+    for (int pass = 0; pass < passes; ++pass) {
+      const int src = (start + pass) & 1, dst = src ^ 1;
+      const int shift = per * pass;
+      const int bits = std::min(per, plan.tile_bits - shift);
+      PVG_HIP(radix_pass(bins->keys + src * cap, bins->vals + src * cap, bins->keys + dst * cap,
+                         bins->vals + dst * cap, counters, m_grid, shift, bits, hist, plan.hist_cols, rowtot, s));
+    }
+  }
+  {
+    StageScope sc(PVG_STAGE_RANGES, s);
+    PVG_HIP(launch_fill_u32(bins->ranges, 0u, 2 * plan.tiles, s));
+    if (m_grid > 0) {
+      hipLaunchKernelGGL(k_ranges, dim3(static_cast<unsigned>(cdiv(m_grid, 256))), dim3(256), 0, s, bins->keys,
+                         counters, bins->ranges);
+      PVG_HIP(hipGetLastError());
+    }
+  }
+  return PVG_OK;
+}
+
+}  // namespace pvg

@@ -1,0 +1,268 @@
+// Per-Gaussian stage (forward and adjoint) of the PVG rasterizer on gfx950.
+//
+// Forward: one thread per (view, Gaussian): temporal state (Sec. 3.2,
+// Eqs. (6)-(7)), flow translation (Sec. 3.4, Eqs. (10), (12)), EWA projection
+// (Sec. 3.1, Eq. (2)), radius, tile rectangle and SH colour.  Parameter reads
+// are structure-of-arrays, so a wave reads 256 contiguous bytes per field; the
+// SH coefficients (up to 192 B per Gaussian) are only read for visible ones.
+//
+// Adjoint: one thread per Gaussian recomputes the forward state (bit-identical,
+// so every branch decision is the forward's) and applies the chain rule from
+// the screen-space gradient (2D mean, conic, opacity, colour) back to
+// {mu, q, s, o, c, tau, beta, v} and l.
+#include "pvg_math.hpp"
+
+namespace pvg {
+
+__device__ __forceinline__ const View& view_of(const ViewSet& vs, int32_t v) {
+  return vs.table ? vs.table[v] : vs.one;
+}
+
+// Block -> (view, first Gaussian).  Views of a batched launch are laid out
+// back to back in geom; geom_off is the running sum of the views' n.
+__device__ __forceinline__ int32_t find_view_by_gauss(const ViewSet& vs, int64_t g) {
+  if (!vs.table) return 0;
+  int32_t lo = 0, hi = vs.nviews - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (vs.table[mid].geom_off <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256) k_preprocess(ViewSet vs, Geom geom, unsigned long long* dummy) {
+  const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (gi >= vs.total_gauss) return;
+  const int32_t vid = find_view_by_gauss(vs, gi);
+  const View& v = view_of(vs, vid);
+  const int64_t i = gi - v.geom_off;
+  Proj P;
+  const bool vis = project(v, i, P, true);
+  geom.depth[gi] = P.p[2];
+  if (vis) {
+    reinterpret_cast<float2*>(geom.xy)[gi] = make_float2(P.x, P.y);
+    reinterpret_cast<float4*>(geom.conic_op)[gi] = make_float4(P.A, P.B, P.C, P.op);
+    geom.rgb[3 * gi] = P.rgb[0];
+    geom.rgb[3 * gi + 1] = P.rgb[1];
+    geom.rgb[3 * gi + 2] = P.rgb[2];
+    geom.radius[gi] = P.radius;
+    geom.tiles[gi] = static_cast<uint32_t>((P.rect[2] - P.rect[0]) * (P.rect[3] - P.rect[1]));
+  } else {
+    reinterpret_cast<float2*>(geom.xy)[gi] = make_float2(0.0f, 0.0f);
+    reinterpret_cast<float4*>(geom.conic_op)[gi] = make_float4(0.0f, 0.0f, 0.0f, P.op);
+    geom.rgb[3 * gi] = 0.0f;
+    geom.rgb[3 * gi + 1] = 0.0f;
+    geom.rgb[3 * gi + 2] = 0.0f;
+    geom.radius[gi] = 0;
+    geom.tiles[gi] = 0u;
+  }
+  (void)dummy;
+}
+
+__device__ __forceinline__ void put(float* a, int64_t idx, float val, int accumulate) {
+  if (accumulate) a[idx] += val; else a[idx] = val;
+}
+
+__global__ void __launch_bounds__(256) k_preprocess_bwd(ViewSet vs, Geom geom, const float* __restrict__ g2d,
+                                                         pvg_gaussians_grad grad, int accumulate) {
+  const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (gi >= vs.total_gauss) return;
+  const int32_t vid = find_view_by_gauss(vs, gi);
+  const View& v = view_of(vs, vid);
+  const int64_t i = gi - v.geom_off;
+  const Scene& s = v.s;
+  const int64_t n = s.n;
+  const int K = (s.degree + 1) * (s.degree + 1);
+  if (geom.radius[gi] <= 0) {
+    if (!accumulate) {
+      for (int c = 0; c < 3; ++c) {
+        grad.mu[c * n + i] = 0.0f; grad.scale[c * n + i] = 0.0f; grad.vel[c * n + i] = 0.0f;
+      }
+      for (int c = 0; c < 4; ++c) grad.rot[c * n + i] = 0.0f;
+      for (int c = 0; c < 3 * K; ++c) grad.sh[c * n + i] = 0.0f;
+      grad.opacity[i] = 0.0f; grad.period[i] = 0.0f; grad.tau[i] = 0.0f; grad.beta[i] = 0.0f;
+    }
+    return;
+  }
+  Proj P;
+  project(v, i, P, true);
+  const float* g = g2d + kG2DStride * gi;
+  const float dmx = g[0], dmy = g[1], dA = g[2], dB = g[3], dC = g[4], dop = g[5];
+  float dmr[3] = {0.0f, 0.0f, 0.0f};
+
+  // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2), dir = u / |u|
+  {
+    float draw[3];
+    for (int ch = 0; ch < 3; ++ch) draw[ch] = (P.flags & (kClampR << ch)) ? 0.0f : g[6 + ch];
+    float Y[16], wk[16];
+    sh_eval_basis(s.degree, P.dir[0], P.dir[1], P.dir[2], Y);
+    for (int k = 0; k < K; ++k) {
+      float acc = 0.0f;
+      for (int ch = 0; ch < 3; ++ch) {
+        put(grad.sh, (3 * k + ch) * n + i, Y[k] * draw[ch], accumulate);
+        acc += s.sh[(3 * k + ch) * n + i] * draw[ch];
+      }
+      wk[k] = acc;
+    }
+    for (int k = K; k < 16; ++k) wk[k] = 0.0f;
+    float dd[3];
+    sh_grad_basis(s.degree, P.dir[0], P.dir[1], P.dir[2], wk, dd);
+    const float proj = P.dir[0] * dd[0] + P.dir[1] * dd[1] + P.dir[2] * dd[2];
+    for (int c = 0; c < 3; ++c) dmr[c] += (dd[c] - P.dir[c] * proj) / P.ulen;
+  }
+
+  // conic (A, B, C) = inverse of the dilated covariance [[a, b], [b, c]]
+  const float a = P.ca, b = P.cb, c = P.cc;
+  const float id2 = 1.0f / (P.det * P.det);
+  const float da = (-(c * c) * dA + (b * c) * dB - (b * b) * dC) * id2;
+  const float db = ((2.0f * b * c) * dA - (a * c + b * b) * dB + (2.0f * a * b) * dC) * id2;
+  const float dc = (-(b * b) * dA + (a * b) * dB - (a * a) * dC) * id2;
+  // Sigma' = T2 Sigma T2^T (the +0.3 dilation is constant)
+  const float hb = 0.5f * db;
+  const float* T0 = P.T2;
+  const float* T1 = P.T2 + 3;
+  float dSig[9];
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q)
+      dSig[3 * r + q] = da * T0[r] * T0[q] + hb * (T0[r] * T1[q] + T1[r] * T0[q]) + dc * T1[r] * T1[q];
+  float V0[3], V1[3], dT0[3], dT1[3];
+  for (int q = 0; q < 3; ++q) {
+    V0[q] = da * T0[q] + hb * T1[q];
+    V1[q] = hb * T0[q] + dc * T1[q];
+  }
+  for (int q = 0; q < 3; ++q) {
+    dT0[q] = 2.0f * (V0[0] * P.Sig[q] + V0[1] * P.Sig[3 + q] + V0[2] * P.Sig[6 + q]);
+    dT1[q] = 2.0f * (V1[0] * P.Sig[q] + V1[1] * P.Sig[3 + q] + V1[2] * P.Sig[6 + q]);
+  }
+  const float* W = v.R;
+  float dJ00 = 0.0f, dJ02 = 0.0f, dJ11 = 0.0f, dJ12 = 0.0f;
+  for (int q = 0; q < 3; ++q) {
+    dJ00 += dT0[q] * W[q];
+    dJ02 += dT0[q] * W[6 + q];
+    dJ11 += dT1[q] * W[3 + q];
+    dJ12 += dT1[q] * W[6 + q];
+  }
+  // J(p) at the guarded point, 2D mean m(p)
+  const float px = P.p[0], py = P.p[1], pz = P.p[2];
+  const float iz = 1.0f / pz, iz2 = iz * iz;
+  float dp[3] = {0.0f, 0.0f, 0.0f};
+  dp[2] += -v.fx * iz2 * dJ00 - v.fy * iz2 * dJ11;
+  if (P.flags & (kGuardXLo | kGuardXHi)) {
+    dp[2] += v.fx * (P.tx * iz) * iz2 * dJ02;
+  } else {
+    dp[0] += -v.fx * iz2 * dJ02;
+    dp[2] += 2.0f * v.fx * px * iz2 * iz * dJ02;
+  }
+  if (P.flags & (kGuardYLo | kGuardYHi)) {
+    dp[2] += v.fy * (P.ty * iz) * iz2 * dJ12;
+  } else {
+    dp[1] += -v.fy * iz2 * dJ12;
+    dp[2] += 2.0f * v.fy * py * iz2 * iz * dJ12;
+  }
+  dp[0] += v.fx * iz * dmx;
+  dp[1] += v.fy * iz * dmy;
+  dp[2] += -v.fx * px * iz2 * dmx - v.fy * py * iz2 * dmy;
+  for (int q = 0; q < 3; ++q) dmr[q] += W[q] * dp[0] + W[3 + q] * dp[1] + W[6 + q] * dp[2];
+
+  // Sigma = M M^T, M = R(q^) diag(s)
+  float dR[9];
+  for (int q = 0; q < 3; ++q) {
+    float ds = 0.0f;
+    for (int r = 0; r < 3; ++r) {
+      const float dM = 2.0f * (dSig[3 * r] * P.M[q] + dSig[3 * r + 1] * P.M[3 + q] + dSig[3 * r + 2] * P.M[6 + q]);
+      ds += dM * P.Rq[3 * r + q];
+      dR[3 * r + q] = dM * P.sc[q];
+    }
+    put(grad.scale, q * n + i, ds, accumulate);
+  }
+  {
+    const float w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+    float dq[4];
+    dq[0] = 2.0f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dq[1] = 2.0f * (y * dR[1] + z * dR[2] + y * dR[3] - w * dR[5] + z * dR[6] + w * dR[7]) -
+            4.0f * x * (dR[4] + dR[8]);
+    dq[2] = 2.0f * (x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7]) -
+            4.0f * y * (dR[0] + dR[8]);
+    dq[3] = 2.0f * (-w * dR[1] + x * dR[2] + w * dR[3] + y * dR[5] + x * dR[6] + y * dR[7]) -
+            4.0f * z * (dR[0] + dR[4]);
+    const float qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+    for (int q = 0; q < 4; ++q) put(grad.rot, q * n + i, (dq[q] - P.qn[q] * qd) / P.qnorm, accumulate);
+  }
+
+  // temporal model
+  const float l = s.period[i], tau = s.tau[i], beta = s.beta[i];
+  float vel[3];
+  for (int q = 0; q < 3; ++q) vel[q] = s.vel[q * n + i];
+  const float vg = vel[0] * dmr[0] + vel[1] * dmr[1] + vel[2] * dmr[2];
+  float dv[3] = {0.0f, 0.0f, 0.0f};
+  float dl = 0.0f, dtau = 0.0f, dbeta = 0.0f;
+  if (v.dt != 0.0f) {
+    if (v.mode == 0) {
+      const float e = expf(-0.5f * (beta / l));
+      for (int q = 0; q < 3; ++q) dv[q] += e * v.dt * dmr[q];
+      dbeta += vg * v.dt * e * (-0.5f / l);
+      dl += vg * v.dt * e * (0.5f * beta / (l * l));
+    } else {
+      for (int q = 0; q < 3; ++q) dv[q] += v.dt * dmr[q];
+    }
+  }
+  const float d = v.t - tau;
+  const float phi = (kTwoPi * d) / l;
+  float sphi, cphi;
+  sincosf(phi, &sphi, &cphi);
+  const float k = (l / kTwoPi) * sphi;
+  for (int q = 0; q < 3; ++q) {
+    put(grad.mu, q * n + i, dmr[q], accumulate);
+    put(grad.vel, q * n + i, dv[q] + k * dmr[q], accumulate);
+  }
+  dtau += -cphi * vg;
+  dl += (sphi / kTwoPi - (d / l) * cphi) * vg;
+  const float qb = d / beta;
+  const float eo = expf(-0.5f * (qb * qb));
+  put(grad.opacity, i, eo * dop, accumulate);
+  dtau += dop * P.op * d / (beta * beta);
+  dbeta += dop * P.op * d * d / (beta * beta * beta);
+  put(grad.period, i, dl, accumulate);
+  put(grad.tau, i, dtau, accumulate);
+  put(grad.beta, i, dbeta, accumulate);
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f32(float* p, float v, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+static unsigned grid_for(int64_t n, int block) { return static_cast<unsigned>((n + block - 1) / block); }
+
+hipError_t launch_preprocess(const ViewSet& vs, const Geom& geom, hipStream_t s) {
+  if (vs.total_gauss == 0) return hipSuccess;
+  StageScope scope(PVG_STAGE_PREPROCESS, s);
+  hipLaunchKernelGGL(k_preprocess, dim3(grid_for(vs.total_gauss, 256)), dim3(256), 0, s, vs, geom, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const ViewSet& vs, const Geom& geom, const float* g2d,
+                                 const pvg_gaussians_grad& grad, int accumulate, hipStream_t s) {
+  if (vs.total_gauss == 0) return hipSuccess;
+  StageScope scope(PVG_STAGE_PREPROCESS_BWD, s);
+  hipLaunchKernelGGL(k_preprocess_bwd, dim3(grid_for(vs.total_gauss, 256)), dim3(256), 0, s, vs, geom, g2d, grad,
+                     accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace pvg

@@ -1,0 +1,110 @@
+// Internal declarations shared by the HIP kernels and the host code of libpvg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "pvg.h"
+
+namespace pvg {
+
+constexpr int kTile = 16;
+constexpr int kTilePixels = kTile * kTile;
+constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr float kDilation = 0.3f;        // low-pass added to the 2D covariance (px^2)
+constexpr float kLambdaFloor = 0.1f;     // floor under the eigenvalue discriminant
+constexpr float kGuard = 1.3f;           // Jacobian guard band, in half fields of view
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 0.0001f;
+constexpr int kG2DStride = 12;           // floats per Gaussian in the screen-space gradient buffer
+
+// Parameters of one scene (device pointers).
+struct Scene {
+  const float* mu; const float* scale; const float* rot; const float* sh; const float* opacity;
+  const float* vel; const float* period; const float* tau; const float* beta;
+  int64_t n;
+  int32_t degree;
+};
+
+// One rendered view: scene, camera, frame, its tile grid and its place in a batch.
+struct View {
+  Scene s;
+  float R[9], T[3];
+  float fx, fy, cx, cy, znear;
+  int32_t W, H, GX, GY;
+  float t, dt;
+  int32_t mode;
+  float bg[3];
+  int64_t geom_off;  // first slot of this view's Gaussians in the batch's geom arrays
+  int64_t tile_off;  // first global tile id of this view
+  float* img;        // [3][H][W]
+  float* final_T;    // [H][W]
+  int32_t* n_contrib;// [H][W]
+  const float* dL_dimg;  // [3][H][W] upstream gradient (adjoint only)
+};
+
+struct Geom {
+  float* xy; float* depth; float* conic_op; float* rgb; int32_t* radius; uint32_t* tiles;
+};
+
+// Views of a launch: either one view passed by value or a device table.
+struct ViewSet {
+  const View* table;  // device table of nviews views (batched launches), or null
+  View one;           // the view when table is null
+  int32_t nviews;
+  int64_t total_gauss;  // sum of the views' n
+  int64_t total_tiles;  // sum of the views' GX * GY
+};
+
+// ---------------------------------------------------------------- host side
+// error handling (thread-local message)
+void set_error(const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+#define PVG_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return ::pvg::hip_fail(e_, #call); \
+  } while (0)
+
+// stage profiler
+struct StageScope {
+  StageScope(int stage, hipStream_t s);
+  ~StageScope();
+  int stage_;
+  hipStream_t s_;
+  bool on_;
+};
+bool profiling();
+unsigned long long* profile_work_counter(int stage);  // device counter, or null when off
+
+// kernel launchers (stream-ordered, no host sync)
+hipError_t launch_preprocess(const ViewSet& vs, const Geom& geom, hipStream_t s);
+hipError_t launch_preprocess_bwd(const ViewSet& vs, const Geom& geom, const float* g2d,
+                                 const pvg_gaussians_grad& grad, int accumulate, hipStream_t s);
+hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals,
+                             const uint32_t* ranges, hipStream_t s);
+hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals,
+                             const uint32_t* ranges, const float* dL_dimg_base, float* g2d,
+                             hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
+
+// binning: scratch layout and the sort pipeline
+struct BinPlan {
+  int64_t n;             // Gaussians in the batch
+  int64_t tiles;         // total tiles
+  int64_t capacity;      // instance capacity
+  int tile_bits;         // bits of the global tile id
+  int tile_passes;       // radix passes over the tile key
+  // scratch carve-up (bytes offsets into tmp)
+  size_t off_vis_keys, off_vis_vals, off_offsets, off_partials, off_hist, off_rowtot, total;
+  int64_t hist_cols;     // blocks per radix row (max over the passes)
+};
+BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity);
+int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp, const BinPlan& plan,
+                 int sync_count, hipStream_t s);
+
+}  // namespace pvg

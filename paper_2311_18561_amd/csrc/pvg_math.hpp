@@ -1,0 +1,266 @@
+// Device-side per-Gaussian mathematics of the PVG rasterizer (gfx950).
+//
+// The evaluation order of every floating-point expression of the
+// per-Gaussian stage is fixed (left to right, as written) and the file is
+// compiled without FMA contraction, so that the discrete structure (screen
+// radius, tile rectangle, depth key) is reproducible bit for bit by any other
+// IEEE FP32 implementation that follows the same order.  The sine and
+// exponential of the temporal model are correctly rounded FP32 values:
+// evaluated in FP64 and rounded once.
+#pragma once
+
+#include "pvg_internal.hpp"
+
+namespace pvg {
+
+__device__ __forceinline__ float sin_cr(float x) { return static_cast<float>(sin(static_cast<double>(x))); }
+__device__ __forceinline__ float exp_cr(float x) { return static_cast<float>(exp(static_cast<double>(x))); }
+
+enum : uint32_t {
+  kGuardXLo = 1u << 0, kGuardXHi = 1u << 1, kGuardYLo = 1u << 2, kGuardYHi = 1u << 3,
+  kClampR = 1u << 4, kClampG = 1u << 5, kClampB = 1u << 6,
+};
+
+// Real spherical harmonics of degree <= 3 (no Condon-Shortley phase) at the
+// unit vector (x, y, z), index l*l + l + m, as Cartesian polynomials.
+namespace shc {
+constexpr float c0 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
+constexpr float c1 = 0.48860251190291992f;   // sqrt(3 / (4 pi))
+constexpr float c2a = 1.09254843059207907f;  // sqrt(15 / pi) / 2
+constexpr float c2b = 0.31539156525252001f;  // sqrt(5 / pi) / 4
+constexpr float c2c = 0.54627421529603954f;  // sqrt(15 / pi) / 4
+constexpr float c3a = 0.59004358992664352f;  // sqrt(35 / (2 pi)) / 4
+constexpr float c3b = 2.89061144264055405f;  // sqrt(105 / pi) / 2
+constexpr float c3c = 0.45704579946446573f;  // sqrt(21 / (2 pi)) / 4
+constexpr float c3d = 0.37317633259011540f;  // sqrt(7 / pi) / 4
+constexpr float c3e = 1.44530572132027702f;  // sqrt(105 / pi) / 4
+}  // namespace shc
+
+__device__ __forceinline__ void sh_eval_basis(int degree, float x, float y, float z, float Y[16]) {
+  Y[0] = shc::c0;
+  if (degree < 1) return;
+  Y[1] = shc::c1 * y;
+  Y[2] = shc::c1 * z;
+  Y[3] = shc::c1 * x;
+  if (degree < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = shc::c2a * (x * y);
+  Y[5] = shc::c2a * (y * z);
+  Y[6] = shc::c2b * ((2.0f * zz - xx) - yy);
+  Y[7] = shc::c2a * (x * z);
+  Y[8] = shc::c2c * (xx - yy);
+  if (degree < 3) return;
+  Y[9] = shc::c3a * (y * (3.0f * xx - yy));
+  Y[10] = shc::c3b * (x * y * z);
+  Y[11] = shc::c3c * (y * ((4.0f * zz - xx) - yy));
+  Y[12] = shc::c3d * (z * ((2.0f * zz - 3.0f * xx) - 3.0f * yy));
+  Y[13] = shc::c3c * (x * ((4.0f * zz - xx) - yy));
+  Y[14] = shc::c3e * (z * (xx - yy));
+  Y[15] = shc::c3a * (x * (xx - 3.0f * yy));
+}
+
+// Gradient of sum_k w[k] Y_k(x, y, z) with respect to (x, y, z) of the
+// polynomials above (only its component tangent to the sphere is used).
+__device__ __forceinline__ void sh_grad_basis(int degree, float x, float y, float z, const float w[16],
+                                              float g[3]) {
+  g[0] = 0.0f; g[1] = 0.0f; g[2] = 0.0f;
+  if (degree < 1) return;
+  g[1] += shc::c1 * w[1];
+  g[2] += shc::c1 * w[2];
+  g[0] += shc::c1 * w[3];
+  if (degree < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  g[0] += shc::c2a * (y * w[4] + z * w[7]) + shc::c2b * (-2.0f * x) * w[6] + shc::c2c * (2.0f * x) * w[8];
+  g[1] += shc::c2a * (x * w[4] + z * w[5]) + shc::c2b * (-2.0f * y) * w[6] + shc::c2c * (-2.0f * y) * w[8];
+  g[2] += shc::c2a * (y * w[5] + x * w[7]) + shc::c2b * (4.0f * z) * w[6];
+  if (degree < 3) return;
+  // Y9 = a y (3xx - yy)
+  g[0] += shc::c3a * (6.0f * x * y) * w[9];
+  g[1] += shc::c3a * (3.0f * xx - 3.0f * yy) * w[9];
+  // Y10 = b x y z
+  g[0] += shc::c3b * (y * z) * w[10];
+  g[1] += shc::c3b * (x * z) * w[10];
+  g[2] += shc::c3b * (x * y) * w[10];
+  // Y11 = c y (4zz - xx - yy)
+  g[0] += shc::c3c * (-2.0f * x * y) * w[11];
+  g[1] += shc::c3c * ((4.0f * zz - xx) - 3.0f * yy) * w[11];
+  g[2] += shc::c3c * (8.0f * y * z) * w[11];
+  // Y12 = d z (2zz - 3xx - 3yy)
+  g[0] += shc::c3d * (-6.0f * x * z) * w[12];
+  g[1] += shc::c3d * (-6.0f * y * z) * w[12];
+  g[2] += shc::c3d * ((6.0f * zz - 3.0f * xx) - 3.0f * yy) * w[12];
+  // Y13 = c x (4zz - xx - yy)
+  g[0] += shc::c3c * ((4.0f * zz - 3.0f * xx) - yy) * w[13];
+  g[1] += shc::c3c * (-2.0f * x * y) * w[13];
+  g[2] += shc::c3c * (8.0f * x * z) * w[13];
+  // Y14 = e z (xx - yy)
+  g[0] += shc::c3e * (2.0f * x * z) * w[14];
+  g[1] += shc::c3e * (-2.0f * y * z) * w[14];
+  g[2] += shc::c3e * (xx - yy) * w[14];
+  // Y15 = a x (xx - 3yy)
+  g[0] += shc::c3a * (3.0f * xx - 3.0f * yy) * w[15];
+  g[1] += shc::c3a * (-6.0f * x * y) * w[15];
+}
+
+// Forward state of one Gaussian in one view.
+struct Proj {
+  float mr[3];      // translated mean (Eq. (12)) or mu~(t) (Eq. (6))
+  float op;         // o~(t) (Eq. (7))
+  float p[3];       // camera-space point
+  float qn[4], qnorm, Rq[9], sc[3], M[9];
+  float Sig[9];     // 3D covariance (row-major, symmetric)
+  float tx, ty, J00, J02, J11, J12, T2[6];
+  float ca, cb, cc, det;  // dilated 2D covariance
+  float A, B, C, x, y;
+  int32_t radius;
+  int32_t rect[4];
+  uint32_t flags;
+  float dir[3], ulen;
+  float rgb[3];
+};
+
+__device__ __forceinline__ int32_t clamp_tile(float v, int32_t hi) {
+  const float f = floorf(v);
+  if (f < 0.0f) return 0;
+  if (f > static_cast<float>(hi)) return hi;
+  return static_cast<int32_t>(f);
+}
+
+// Tile rectangle [x0, x1) x [y0, y1) of a splat at (x, y) with radius r.
+__device__ __forceinline__ void tile_rect(float x, float y, int32_t r, int32_t GX, int32_t GY, int32_t rect[4]) {
+  const float rr = static_cast<float>(r);
+  rect[0] = clamp_tile((x - rr) / 16.0f, GX);
+  rect[1] = clamp_tile((y - rr) / 16.0f, GY);
+  rect[2] = clamp_tile(((x + rr) + 15.0f) / 16.0f, GX);
+  rect[3] = clamp_tile(((y + rr) + 15.0f) / 16.0f, GY);
+}
+
+// Temporal state (Eqs. (6), (7)) and flow translation (Eqs. (10), (12)).
+__device__ __forceinline__ void temporal_state(const View& v, int64_t i, float mr[3], float& op) {
+  const Scene& s = v.s;
+  const int64_t n = s.n;
+  const float l = s.period[i], tau = s.tau[i], beta = s.beta[i], o = s.opacity[i];
+  const float d = v.t - tau;
+  const float phi = (kTwoPi * d) / l;
+  const float k = (l / kTwoPi) * sin_cr(phi);
+  const float q = d / beta;
+  op = o * exp_cr(-0.5f * (q * q));
+  float vel[3];
+  for (int c = 0; c < 3; ++c) {
+    vel[c] = s.vel[c * n + i];
+    mr[c] = s.mu[c * n + i] + k * vel[c];
+  }
+  if (v.dt != 0.0f) {
+    const float ev = v.mode == 0 ? exp_cr(-0.5f * (beta / l)) : 1.0f;
+    for (int c = 0; c < 3; ++c) mr[c] = mr[c] + (vel[c] * ev) * v.dt;
+  }
+}
+
+// The per-Gaussian stage up to the tile rectangle; returns false for an
+// invisible Gaussian.  With `color` it also evaluates the clamped SH colour.
+__device__ __forceinline__ bool project(const View& v, int64_t i, Proj& P, bool color) {
+  const Scene& s = v.s;
+  const int64_t n = s.n;
+  temporal_state(v, i, P.mr, P.op);
+  const float* W = v.R;
+  for (int r = 0; r < 3; ++r)
+    P.p[r] = ((W[3 * r] * P.mr[0] + W[3 * r + 1] * P.mr[1]) + W[3 * r + 2] * P.mr[2]) + v.T[r];
+  P.radius = 0;
+  P.flags = 0;
+  if (!(P.p[2] > v.znear)) return false;
+
+  // Sigma = R(q) S S^T R(q)^T
+  float q[4];
+  for (int c = 0; c < 4; ++c) q[c] = s.rot[c * n + i];
+  const float n2 = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
+  P.qnorm = sqrtf(n2);
+  for (int c = 0; c < 4; ++c) P.qn[c] = q[c] / P.qnorm;
+  {
+    const float w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+    P.Rq[0] = 1.0f - 2.0f * (y * y + z * z);
+    P.Rq[1] = 2.0f * (x * y - w * z);
+    P.Rq[2] = 2.0f * (x * z + w * y);
+    P.Rq[3] = 2.0f * (x * y + w * z);
+    P.Rq[4] = 1.0f - 2.0f * (x * x + z * z);
+    P.Rq[5] = 2.0f * (y * z - w * x);
+    P.Rq[6] = 2.0f * (x * z - w * y);
+    P.Rq[7] = 2.0f * (y * z + w * x);
+    P.Rq[8] = 1.0f - 2.0f * (x * x + y * y);
+  }
+  for (int c = 0; c < 3; ++c) P.sc[c] = s.scale[c * n + i];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) P.M[3 * r + c] = P.Rq[3 * r + c] * P.sc[c];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      P.Sig[3 * r + c] = (P.M[3 * r] * P.M[3 * c] + P.M[3 * r + 1] * P.M[3 * c + 1]) + P.M[3 * r + 2] * P.M[3 * c + 2];
+
+  // EWA (Eq. (2)) with the Jacobian at the guarded point
+  const float px = P.p[0], py = P.p[1], pz = P.p[2];
+  const float limx = kGuard * ((0.5f * static_cast<float>(v.W)) / v.fx);
+  const float limy = kGuard * ((0.5f * static_cast<float>(v.H)) / v.fy);
+  const float txz = px / pz, tyz = py / pz;
+  uint32_t fl = 0;
+  if (txz < -limx) fl |= kGuardXLo;
+  if (txz > limx) fl |= kGuardXHi;
+  if (tyz < -limy) fl |= kGuardYLo;
+  if (tyz > limy) fl |= kGuardYHi;
+  P.tx = (fl & kGuardXLo) ? (-limx) * pz : (fl & kGuardXHi) ? limx * pz : px;
+  P.ty = (fl & kGuardYLo) ? (-limy) * pz : (fl & kGuardYHi) ? limy * pz : py;
+  P.J00 = v.fx / pz;
+  P.J02 = -(v.fx * P.tx) / (pz * pz);
+  P.J11 = v.fy / pz;
+  P.J12 = -(v.fy * P.ty) / (pz * pz);
+  for (int c = 0; c < 3; ++c) {
+    P.T2[c] = P.J00 * W[c] + P.J02 * W[6 + c];
+    P.T2[3 + c] = P.J11 * W[3 + c] + P.J12 * W[6 + c];
+  }
+  float U[6];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 3; ++c)
+      U[3 * r + c] = (P.T2[3 * r] * P.Sig[c] + P.T2[3 * r + 1] * P.Sig[3 + c]) + P.T2[3 * r + 2] * P.Sig[6 + c];
+  const float s00 = (U[0] * P.T2[0] + U[1] * P.T2[1]) + U[2] * P.T2[2];
+  const float s01 = (U[0] * P.T2[3] + U[1] * P.T2[4]) + U[2] * P.T2[5];
+  const float s11 = (U[3] * P.T2[3] + U[4] * P.T2[4]) + U[5] * P.T2[5];
+  P.ca = s00 + kDilation;
+  P.cb = s01;
+  P.cc = s11 + kDilation;
+  P.det = P.ca * P.cc - P.cb * P.cb;
+  P.flags = fl;
+  if (!(P.det > 0.0f)) return false;
+  P.A = P.cc / P.det;
+  P.B = -P.cb / P.det;
+  P.C = P.ca / P.det;
+  P.x = (v.fx * txz + v.cx) - 0.5f;
+  P.y = (v.fy * tyz + v.cy) - 0.5f;
+  const float mid = 0.5f * (P.ca + P.cc);
+  const float lam = mid + sqrtf(fmaxf(kLambdaFloor, mid * mid - P.det));
+  const int32_t rad = static_cast<int32_t>(ceilf(3.0f * sqrtf(lam)));
+  tile_rect(P.x, P.y, rad, v.GX, v.GY, P.rect);
+  if ((P.rect[2] - P.rect[0]) * (P.rect[3] - P.rect[1]) == 0) return false;
+  P.radius = rad;
+
+  if (color) {
+    float cp[3], u[3];
+    for (int c = 0; c < 3; ++c) cp[c] = -((W[c] * v.T[0] + W[3 + c] * v.T[1]) + W[6 + c] * v.T[2]);
+    for (int c = 0; c < 3; ++c) u[c] = P.mr[c] - cp[c];
+    P.ulen = sqrtf((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+    for (int c = 0; c < 3; ++c) P.dir[c] = u[c] / P.ulen;
+    float Y[16];
+    sh_eval_basis(s.degree, P.dir[0], P.dir[1], P.dir[2], Y);
+    const int K = (s.degree + 1) * (s.degree + 1);
+    for (int ch = 0; ch < 3; ++ch) {
+      float acc = 0.0f;
+      for (int k = 0; k < K; ++k) acc += s.sh[(3 * k + ch) * n + i] * Y[k];
+      const float raw = acc + 0.5f;
+      if (raw < 0.0f) {
+        P.flags |= (kClampR << ch);
+        P.rgb[ch] = 0.0f;
+      } else {
+        P.rgb[ch] = raw;
+      }
+    }
+  }
+  return true;
+}
+
+}  // namespace pvg
