@@ -63,9 +63,8 @@ class WsSizes(C.Structure):
 
 class ServeConfig(C.Structure):
     _fields_ = [("device", C.c_int32), ("max_batch", C.c_int32), ("max_inflight", C.c_int32),
-                ("reserved", C.c_int32), ("mem_budget_bytes", C.c_int64), ("instance_capacity", C.c_int64),
-                ("max_width", C.c_int32), ("max_height", C.c_int32), ("use_graphs", C.c_int32),
-                ("batching", C.c_int32)]
+                ("use_graphs", C.c_int32), ("mem_budget_bytes", C.c_int64), ("max_batch_gaussians", C.c_int64),
+                ("max_batch_pixels", C.c_int64), ("instance_capacity", C.c_int64), ("stub_launch_us", C.c_int64)]
 
 
 class Request(C.Structure):
@@ -74,16 +73,16 @@ class Request(C.Structure):
 
 
 class Result(C.Structure):
-    _fields_ = [("status", C.c_int32), ("batch_size", C.c_int32), ("img", vp), ("width", C.c_int32),
-                ("height", C.c_int32), ("t_submit_ns", C.c_int64), ("t_launch_ns", C.c_int64),
-                ("t_done_ns", C.c_int64), ("num_instances", C.c_int64), ("user_tag", C.c_int64)]
+    _fields_ = [("status", C.c_int32), ("batch_size", C.c_int32), ("t_submit_ns", C.c_int64),
+                ("t_launch_ns", C.c_int64), ("t_done_ns", C.c_int64), ("num_instances", C.c_int64),
+                ("user_tag", C.c_int64)]
 
 
-class ServeStats(C.Structure):
-    _fields_ = [("completed", C.c_int64), ("failed", C.c_int64), ("batches", C.c_int64),
-                ("mean_batch", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
-                ("mpix", C.c_double), ("busy_s", C.c_double), ("graph_launches", C.c_int64),
-                ("graph_builds", C.c_int64), ("retries", C.c_int64)]
+class ServeReport(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("failed", C.c_int64), ("batches", C.c_int64), ("retries", C.c_int64),
+                ("graph_launches", C.c_int64), ("graph_builds", C.c_int64), ("mean_batch", C.c_double),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mpix_per_s", C.c_double),
+                ("span_s", C.c_double)]
 
 
 _lib = None
@@ -126,13 +125,13 @@ def load():
         "pvg_serve_wait": ([vp, C.c_uint64, i64, P(Result)], i32),
         "pvg_serve_poll": ([vp, C.c_uint64, P(i32)], i32),
         "pvg_serve_release": ([vp, C.c_uint64], i32),
-        "pvg_serve_stats": ([vp, P(ServeStats)], i32),
+        "pvg_serve_stats": ([vp, P(ServeReport)], i32),
         "pvg_serve_reset_stats": ([vp], i32),
         "pvg_serve_destroy": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         if not hasattr(L, name):
-            continue
+            raise RuntimeError(f"{LIB_PATH} does not export {name}: rebuild it")
         f = getattr(L, name)
         f.argtypes = args
         f.restype = res
@@ -156,8 +155,3 @@ def check(status: int) -> int:
     return status
 
 
-def exported_symbols() -> list[str]:
-    """Names declared in include/pvg.h (and pvg_serve.h) that the library must export."""
-    return ["pvg_workspace_query", "pvg_preprocess", "pvg_bin_sort", "pvg_render_fwd", "pvg_render_bwd",
-            "pvg_profile_enable", "pvg_profile_collect", "pvg_profile_read", "pvg_profile_reset",
-            "pvg_stage_name", "pvg_status_str", "pvg_last_error"]

@@ -62,6 +62,8 @@ unsigned long long* profile_work_counter(int stage) {
 
 StageScope::StageScope(int stage, hipStream_t s) : stage_(stage), s_(s), on_(false) {
   if (!g_prof_on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   EventPair p{stage, take_event(), take_event()};
   if (!p.a || !p.b) return;
@@ -82,7 +84,7 @@ StageScope::~StageScope() {
 }
 
 // ------------------------------------------------------------------ validation
-static bool check_gaussians(const pvg_gaussians* g) {
+bool check_gaussians(const pvg_gaussians* g) {
   if (!g) { set_error("gaussians is null"); return false; }
   if (g->n < 0) { set_error("n = %lld < 0", static_cast<long long>(g->n)); return false; }
   if (g->n > 0xffffffffll) { set_error("n = %lld exceeds 2^32 - 1", static_cast<long long>(g->n)); return false; }
@@ -95,7 +97,7 @@ static bool check_gaussians(const pvg_gaussians* g) {
   return true;
 }
 
-static bool check_camera(const pvg_camera* c) {
+bool check_camera(const pvg_camera* c) {
   if (!c) { set_error("camera is null"); return false; }
   if (c->width <= 0 || c->height <= 0) { set_error("image size %d x %d is not positive", c->width, c->height); return false; }
   if (c->width > 65535 * kTile || c->height > 65535 * kTile) { set_error("image size too large"); return false; }
@@ -133,7 +135,7 @@ static int64_t tiles_of(const pvg_camera* c) {
   return static_cast<int64_t>((c->width + kTile - 1) / kTile) * ((c->height + kTile - 1) / kTile);
 }
 
-static View make_view(const pvg_gaussians* g, const pvg_camera* c, const pvg_frame* f) {
+View make_view(const pvg_gaussians* g, const pvg_camera* c, const pvg_frame* f) {
   View v;
   std::memset(&v, 0, sizeof(v));
   if (g) v.s = Scene{g->mu, g->scale, g->rot, g->sh, g->opacity, g->vel, g->period, g->tau, g->beta, g->n, g->sh_degree};

@@ -68,11 +68,16 @@ __device__ __forceinline__ T block_excl_scan(T v, T* lds5, T& total) {
 __device__ __forceinline__ int64_t live_count(const uint32_t* n_dev, int64_t n_host) {
   return n_dev ? static_cast<int64_t>(*n_dev) : n_host;
 }
+__device__ __forceinline__ int64_t live_count64(const int64_t* n_dev, int64_t n_host) {
+  return n_dev ? *n_dev : n_host;
+}
 
 // ------------------------------------------------------------------ step 1: compaction
-__global__ void __launch_bounds__(kThreads) k_vis_count(const uint32_t* __restrict__ tiles, int64_t n,
-                                                        unsigned long long* partials) {
+__global__ void __launch_bounds__(kThreads) k_vis_count(const uint32_t* __restrict__ tiles, const int64_t* n_live,
+                                                        int64_t n_host, unsigned long long* partials) {
   __shared__ unsigned long long lds[5];
+  const int64_t n = live_count64(n_live, n_host);
+  if (static_cast<int64_t>(blockIdx.x) * kScanBlock >= n) return;
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x * kScanItems;
   unsigned long long c = 0;
 #pragma unroll
@@ -88,10 +93,10 @@ __global__ void __launch_bounds__(kThreads) k_vis_count(const uint32_t* __restri
 // against the instance capacity: counters[0] = total (or 0 on overflow),
 // counters[2] = overflow flag, counters[3] = total saturated to 32 bits.
 __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* partials, const uint32_t* count_dev,
-                                                        int64_t count_host, int per_block, uint32_t* counters,
-                                                        int which, int64_t cap) {
+                                                        const int64_t* count_dev64, int64_t count_host,
+                                                        int per_block, uint32_t* counters, int which, int64_t cap) {
   __shared__ unsigned long long wsum[17];
-  const int64_t items = live_count(count_dev, count_host);
+  const int64_t items = count_dev64 ? *count_dev64 : live_count(count_dev, count_host);
   const int64_t count = (items + per_block - 1) / per_block;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   unsigned long long carry = 0;
@@ -128,10 +133,13 @@ __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* part
 }
 
 __global__ void __launch_bounds__(kThreads) k_vis_compact(const uint32_t* __restrict__ tiles,
-                                                          const float* __restrict__ depth, int64_t n,
+                                                          const float* __restrict__ depth, const int64_t* n_live,
+                                                          int64_t n_host,
                                                           const unsigned long long* __restrict__ partials,
                                                           uint32_t* keys, uint32_t* vals) {
   __shared__ unsigned long long lds[5];
+  const int64_t n = live_count64(n_live, n_host);
+  if (static_cast<int64_t>(blockIdx.x) * kScanBlock >= n) return;
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x * kScanItems;
   bool f[kScanItems];
   unsigned long long c = 0;
@@ -159,19 +167,21 @@ __global__ void __launch_bounds__(kThreads) k_rs_hist(const uint32_t* __restrict
   __shared__ uint32_t h[256];
   const int64_t n = live_count(n_dev, n_host);
   const int64_t nb = (n + kRsBlock - 1) / kRsBlock;
-  if (static_cast<int64_t>(blockIdx.x) >= nb) return;
   const int radix = 1 << bits;
   const uint32_t mask = static_cast<uint32_t>(radix - 1);
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRsBlock + threadIdx.x;
+  for (int64_t lb = blockIdx.x; lb < nb; lb += gridDim.x) {
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = lb * kRsBlock + threadIdx.x;
 #pragma unroll 4
-  for (int k = 0; k < kRsItems; ++k) {
-    const int64_t i = base + k * kThreads;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    for (int k = 0; k < kRsItems; ++k) {
+      const int64_t i = base + k * kThreads;
+      if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < radix) hist[threadIdx.x * cols + lb] = h[threadIdx.x];
+    __syncthreads();
   }
-  __syncthreads();
-  if (threadIdx.x < radix) hist[threadIdx.x * cols + blockIdx.x] = h[threadIdx.x];
 }
 
 // One block per digit: exclusive scan of that digit's block counts.
@@ -216,16 +226,18 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint32_t* __restr
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int radix = 1 << bits;
   const uint32_t mask = static_cast<uint32_t>(radix - 1);
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint32_t digit_base;
   {
     const uint32_t t = tid < radix ? rowtot[tid] : 0u;
     uint32_t tot;
-    const uint32_t digit_base = block_excl_scan<uint32_t>(t, lds, tot);
-    if (tid < radix) run[tid] = digit_base + hist[tid * cols + blockIdx.x];
-    for (int w = 0; w < kThreads / 64; ++w) cnt[w][tid] = 0;
+    digit_base = block_excl_scan<uint32_t>(t, lds, tot);
   }
+  for (int64_t lb = blockIdx.x; lb < nb; lb += gridDim.x) {
+  if (tid < radix) run[tid] = digit_base + hist[tid * cols + lb];
+  for (int w = 0; w < kThreads / 64; ++w) cnt[w][tid] = 0;
   __syncthreads();
-  const uint64_t lt = (1ull << lane) - 1ull;
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * kRsBlock + tid;
+  const int64_t base = lb * kRsBlock + tid;
   for (int k = 0; k < kRsItems; ++k) {
     const int64_t i = base + k * kThreads;
     const bool valid = i < n;
@@ -259,6 +271,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint32_t* __restr
     }
     __syncthreads();
   }
+  }
 }
 
 // ------------------------------------------------------------------ step 3: tile counts and emission
@@ -285,100 +298,124 @@ __device__ __forceinline__ int32_t clamp_tile_e(float v, int32_t hi) {
   return static_cast<int32_t>(f);
 }
 
-__device__ __forceinline__ const View& view_at(const ViewSet& vs, int32_t v) { return vs.table ? vs.table[v] : vs.one; }
+// First instance of each visible Gaussian in depth order: the exclusive scan
+// of the tile counts (block partials already scanned).
+__global__ void __launch_bounds__(kThreads) k_tile_offsets(const uint32_t* __restrict__ order,
+                                                           const uint32_t* __restrict__ tiles,
+                                                           const uint32_t* n_dev, int64_t n_host,
+                                                           const unsigned long long* __restrict__ partials,
+                                                           const uint32_t* __restrict__ counters,
+                                                           uint32_t* offsets) {
+  __shared__ unsigned long long lds[5];
+  if (counters[2]) return;  // over capacity: offsets would not fit 32 bits, nothing is emitted
+  const int64_t n = live_count(n_dev, n_host);
+  if (static_cast<int64_t>(blockIdx.x) * kScanBlock >= n) return;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x * kScanItems;
+  uint32_t c[kScanItems];
+  unsigned long long sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    c[k] = base + k < n ? tiles[order[base + k]] : 0u;
+    sum += c[k];
+  }
+  unsigned long long tot;
+  unsigned long long r = block_excl_scan<unsigned long long>(sum, lds, tot) + partials[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) offsets[base + k] = static_cast<uint32_t>(r);
+    r += c[k];
+  }
+}
 
-__device__ __forceinline__ int32_t view_of_gauss(const ViewSet& vs, int64_t g) {
-  if (!vs.table) return 0;
-  int32_t lo = 0, hi = vs.nviews - 1;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi + 1) >> 1;
-    if (vs.table[mid].geom_off <= g) lo = mid; else hi = mid - 1;
+// Last k in [0, n) with a[k] <= x, for non-decreasing a with a[0] <= x, by a
+// 64-way search of the whole wave (each round shrinks the interval 64x).
+__device__ __forceinline__ int64_t wave_last_le(const uint32_t* __restrict__ a, int64_t n, uint32_t x, int lane) {
+  int64_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int64_t p = lo + (((hi - lo) * (lane + 1)) >> 6);
+    const bool ok = p <= lo || (p < hi && a[p] <= x);
+    const int L = __popcll(__ballot(ok));  // ok holds for a prefix of the lanes
+    const int64_t nlo = L > 0 ? __shfl(p, L - 1, 64) : lo;
+    const int64_t nhi = __shfl(p, L, 64);
+    lo = nlo > lo ? nlo : lo;
+    hi = nhi;
   }
   return lo;
 }
 
-// A block takes kScanBlock consecutive Gaussians of the depth order and
-// writes all their instances cooperatively (coalesced runs, balanced across
-// the block whatever the rectangle sizes).
+constexpr int kEmitChunk = 2048;  // instances per block iteration
+
+// Instance emission balanced by instances: a block writes a fixed chunk of
+// the instance array, finds the Gaussians that own it with a wave search over
+// the offsets, stages their rectangles in LDS and fills the chunk (coalesced),
+// so a few huge near-camera splats cannot serialise one block.
 __global__ void __launch_bounds__(kThreads) k_emit(ViewSet vs, const uint32_t* __restrict__ order,
                                                    const float* __restrict__ xy, const int32_t* __restrict__ radius,
-                                                   const uint32_t* __restrict__ tiles, const uint32_t* n_dev,
-                                                   int64_t n_host, const unsigned long long* __restrict__ partials,
+                                                   const uint32_t* __restrict__ offsets,
                                                    const uint32_t* __restrict__ counters, uint32_t* keys,
                                                    uint32_t* vals) {
-  __shared__ uint32_t s_off[kScanBlock + 1];
-  __shared__ uint32_t s_g[kScanBlock];
-  __shared__ uint32_t s_base[kScanBlock];
-  __shared__ uint32_t s_wg[kScanBlock];  // rectangle width (low 16) | tile grid width (high 16)
-  __shared__ unsigned long long lds[5];
-  if (counters[2]) return;  // over capacity: nothing is emitted
-  const int64_t n = live_count(n_dev, n_host);
-  const int64_t blk0 = static_cast<int64_t>(blockIdx.x) * kScanBlock;
-  if (blk0 >= n) return;
-  const int tid = threadIdx.x;
-  uint32_t cnt[kScanItems];
-  unsigned long long c = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t idx = blk0 + tid * kScanItems + k;
-    const int li = tid * kScanItems + k;
-    if (idx < n) {
-      const uint32_t g = order[idx];
+  __shared__ uint32_t s_off[kEmitChunk];
+  __shared__ uint32_t s_g[kEmitChunk];
+  __shared__ uint32_t s_base[kEmitChunk];
+  __shared__ uint32_t s_wg[kEmitChunk];  // rectangle width (low 16) | tile grid width (high 16)
+  __shared__ int64_t s_k[2];
+  if (counters[2]) return;
+  const int64_t M = counters[0];
+  const int64_t nvis = counters[1];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int64_t nchunks = (M + kEmitChunk - 1) / kEmitChunk;
+  for (int64_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    const int64_t j0 = chunk * kEmitChunk;
+    const int64_t j1 = min(M, j0 + kEmitChunk);
+    if (wid < 2) {
+      const int64_t k = wave_last_le(offsets, nvis, static_cast<uint32_t>(wid == 0 ? j0 : j1 - 1), lane);
+      if (lane == 0) s_k[wid] = k;
+    }
+    __syncthreads();
+    const int64_t k0 = s_k[0];
+    const int cnt = static_cast<int>(s_k[1] - k0 + 1);  // <= kEmitChunk: each owner starts in the chunk
+    for (int q = tid; q < cnt; q += kThreads) {
+      const int64_t k = k0 + q;
+      const uint32_t g = order[k];
       const View& v = view_at(vs, view_of_gauss(vs, g));
       const float2 m = reinterpret_cast<const float2*>(xy)[g];
       const float rr = static_cast<float>(radius[g]);
       const int32_t x0 = clamp_tile_e((m.x - rr) / 16.0f, v.GX);
       const int32_t y0 = clamp_tile_e((m.y - rr) / 16.0f, v.GY);
       const int32_t x1 = clamp_tile_e(((m.x + rr) + 15.0f) / 16.0f, v.GX);
-      cnt[k] = tiles[g];
-      s_g[li] = g;
-      s_base[li] = static_cast<uint32_t>(v.tile_off + static_cast<int64_t>(y0) * v.GX + x0);
-      s_wg[li] = static_cast<uint32_t>(x1 - x0) | (static_cast<uint32_t>(v.GX) << 16);
-    } else {
-      cnt[k] = 0;
-      s_g[li] = 0;
-      s_base[li] = 0;
-      s_wg[li] = 1;
+      s_off[q] = offsets[k];
+      s_g[q] = g;
+      s_base[q] = static_cast<uint32_t>(v.tile_off + static_cast<int64_t>(y0) * v.GX + x0);
+      s_wg[q] = static_cast<uint32_t>(x1 - x0) | (static_cast<uint32_t>(v.GX) << 16);
     }
-    c += cnt[k];
-  }
-  unsigned long long tot;
-  const unsigned long long ex = block_excl_scan<unsigned long long>(c, lds, tot);
-  const unsigned long long start = partials[blockIdx.x];
-  {
-    unsigned long long r = start + ex;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      s_off[tid * kScanItems + k] = static_cast<uint32_t>(r);
-      r += cnt[k];
+    __syncthreads();
+    for (int64_t j = j0 + tid; j < j1; j += kThreads) {
+      int lo = 0, hi = cnt - 1;
+      const uint32_t uj = static_cast<uint32_t>(j);
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= uj) lo = mid; else hi = mid - 1;
+      }
+      const uint32_t q = uj - s_off[lo];
+      const uint32_t wg = s_wg[lo];
+      const uint32_t w = wg & 0xffffu, gx = wg >> 16;
+      const uint32_t dy = q / w, dx = q - dy * w;
+      keys[j] = s_base[lo] + dy * gx + dx;
+      vals[j] = s_g[lo];
     }
-  }
-  if (tid == 0) s_off[kScanBlock] = static_cast<uint32_t>(start + tot);
-  __syncthreads();
-  const uint32_t S = s_off[0], E = s_off[kScanBlock];
-  for (uint32_t j = S + tid; j < E; j += kThreads) {
-    int lo = 0, hi = kScanBlock - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= j) lo = mid; else hi = mid - 1;
-    }
-    const uint32_t q = j - s_off[lo];
-    const uint32_t wg = s_wg[lo];
-    const uint32_t w = wg & 0xffffu, gx = wg >> 16;
-    const uint32_t dy = q / w, dx = q - dy * w;
-    keys[j] = s_base[lo] + dy * gx + dx;
-    vals[j] = s_g[lo];
+    __syncthreads();
   }
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ counters,
                          uint32_t* ranges) {
   const int64_t n = counters[0];
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const uint32_t t = keys[j];
-  if (j == 0 || keys[j - 1] != t) ranges[2 * static_cast<int64_t>(t)] = static_cast<uint32_t>(j);
-  if (j == n - 1 || keys[j + 1] != t) ranges[2 * static_cast<int64_t>(t) + 1] = static_cast<uint32_t>(j + 1);
+  for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
+       j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t t = keys[j];
+    if (j == 0 || keys[j - 1] != t) ranges[2 * static_cast<int64_t>(t)] = static_cast<uint32_t>(j);
+    if (j == n - 1 || keys[j + 1] != t) ranges[2 * static_cast<int64_t>(t) + 1] = static_cast<uint32_t>(j + 1);
+  }
 }
 
 // ------------------------------------------------------------------ host pipeline
@@ -398,7 +435,7 @@ BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity) {
   size_t off = 0;
   p.off_vis_keys = off; off = align256(off + sizeof(uint32_t) * 2 * std::max<int64_t>(n, 1));
   p.off_vis_vals = off; off = align256(off + sizeof(uint32_t) * 2 * std::max<int64_t>(n, 1));
-  p.off_offsets = off;  off = align256(off + sizeof(uint32_t) * 4);
+  p.off_offsets = off;  off = align256(off + sizeof(uint32_t) * std::max<int64_t>(n, 1));
   const int64_t nparts = std::max<int64_t>(1, cdiv(n, kScanBlock));
   p.off_partials = off; off = align256(off + sizeof(unsigned long long) * (nparts + 1));
   p.off_hist = off;     off = align256(off + sizeof(uint32_t) * 256 * p.hist_cols);
@@ -408,10 +445,12 @@ BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity) {
 }
 
 // One stable LSD pass of `bits` bits at `shift` from (kin, vin) to (kout, vout).
+constexpr int64_t kMaxGrid = 8192;  // physical blocks of a grid-stride pass
+
 static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, int64_t n_grid, int shift, int bits, uint32_t* hist,
                              int64_t cols, uint32_t* rowtot, hipStream_t s) {
-  const unsigned nb = static_cast<unsigned>(std::max<int64_t>(1, cdiv(n_grid, kRsBlock)));
+  const unsigned nb = static_cast<unsigned>(std::min(kMaxGrid, std::max<int64_t>(1, cdiv(n_grid, kRsBlock))));
   hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, kin, n_dev, n_grid, shift, bits, hist, cols);
   hipLaunchKernelGGL(k_rs_rowscan, dim3(1u << bits), dim3(kThreads), 0, s, hist, cols, n_dev, n_grid, rowtot);
   hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_grid, shift,
@@ -427,6 +466,7 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
   unsigned long long* partials = reinterpret_cast<unsigned long long*>(base + plan.off_partials);
   uint32_t* hist = reinterpret_cast<uint32_t*>(base + plan.off_hist);
   uint32_t* rowtot = reinterpret_cast<uint32_t*>(base + plan.off_rowtot);
+  uint32_t* offsets = reinterpret_cast<uint32_t*>(base + plan.off_offsets);
   uint32_t* counters = bins->counters;
   const int64_t n = plan.n;
   const int64_t cap = plan.capacity;
@@ -436,11 +476,11 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
   if (n > 0) {
     StageScope sc(PVG_STAGE_COMPACT, s);
     const unsigned nb = static_cast<unsigned>(cdiv(n, kScanBlock));
-    hipLaunchKernelGGL(k_vis_count, dim3(nb), dim3(kThreads), 0, s, geom.tiles, n, partials);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nullptr, n, kScanBlock, counters, 1,
-                       int64_t{-1});
-    hipLaunchKernelGGL(k_vis_compact, dim3(nb), dim3(kThreads), 0, s, geom.tiles, geom.depth, n, partials, vkeys,
-                       vvals);
+    hipLaunchKernelGGL(k_vis_count, dim3(nb), dim3(kThreads), 0, s, geom.tiles, vs.live, n, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nullptr, vs.live, n, kScanBlock,
+                       counters, 1, int64_t{-1});
+    hipLaunchKernelGGL(k_vis_compact, dim3(nb), dim3(kThreads), 0, s, geom.tiles, geom.depth, vs.live, n, partials,
+                       vkeys, vvals);
     PVG_HIP(hipGetLastError());
   }
   // depth sort of the visible Gaussians: 4 passes of 8 bits, ends in buffer 0
@@ -460,8 +500,8 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
       const unsigned nb = static_cast<unsigned>(cdiv(n, kScanBlock));
       hipLaunchKernelGGL(k_tile_count, dim3(nb), dim3(kThreads), 0, s, order, geom.tiles, counters + 1, n,
                          partials);
-      hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, counters + 1, n, kScanBlock,
-                         counters, 0, cap);
+      hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, counters + 1,
+                         static_cast<const int64_t*>(nullptr), n, kScanBlock, counters, 0, cap);
       PVG_HIP(hipGetLastError());
     }
   }
@@ -483,11 +523,14 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
   }
   const int passes = plan.tile_passes;
   const int start = passes & 1;  // so that the last pass lands in buffer 0
-  if (n > 0 && vis_grid > 0) {
+  if (n > 0 && vis_grid > 0 && m_grid > 0) {
     StageScope sc(PVG_STAGE_SCAN_EMIT, s);
-    const unsigned nb = static_cast<unsigned>(cdiv(vis_grid, kScanBlock));
-    hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kThreads), 0, s, vs, order, geom.xy, geom.radius, geom.tiles,
-                       counters + 1, n, partials, counters, bins->keys + start * cap, bins->vals + start * cap);
+    const unsigned nbv = static_cast<unsigned>(cdiv(vis_grid, kScanBlock));
+    hipLaunchKernelGGL(k_tile_offsets, dim3(nbv), dim3(kThreads), 0, s, order, geom.tiles, counters + 1, n,
+                       partials, counters, offsets);
+    const unsigned nbe = static_cast<unsigned>(std::min(kMaxGrid, cdiv(m_grid, kEmitChunk)));
+    hipLaunchKernelGGL(k_emit, dim3(nbe), dim3(kThreads), 0, s, vs, order, geom.xy, geom.radius, offsets, counters,
+                       bins->keys + start * cap, bins->vals + start * cap);
     PVG_HIP(hipGetLastError());
   }
   if (passes > 0 && m_grid > 0) {
@@ -505,8 +548,8 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
     StageScope sc(PVG_STAGE_RANGES, s);
     PVG_HIP(launch_fill_u32(bins->ranges, 0u, 2 * plan.tiles, s));
     if (m_grid > 0) {
-      hipLaunchKernelGGL(k_ranges, dim3(static_cast<unsigned>(cdiv(m_grid, 256))), dim3(256), 0, s, bins->keys,
-                         counters, bins->ranges);
+      hipLaunchKernelGGL(k_ranges, dim3(static_cast<unsigned>(std::min(kMaxGrid * 4, cdiv(m_grid, 256)))),
+                         dim3(256), 0, s, bins->keys, counters, bins->ranges);
       PVG_HIP(hipGetLastError());
     }
   }

@@ -14,27 +14,10 @@
 
 namespace pvg {
 
-__device__ __forceinline__ const View& view_of(const ViewSet& vs, int32_t v) {
-  return vs.table ? vs.table[v] : vs.one;
-}
-
-// Block -> (view, first Gaussian).  Views of a batched launch are laid out
-// back to back in geom; geom_off is the running sum of the views' n.
-__device__ __forceinline__ int32_t find_view_by_gauss(const ViewSet& vs, int64_t g) {
-  if (!vs.table) return 0;
-  int32_t lo = 0, hi = vs.nviews - 1;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi + 1) >> 1;
-    if (vs.table[mid].geom_off <= g) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 __global__ void __launch_bounds__(256) k_preprocess(ViewSet vs, Geom geom, unsigned long long* dummy) {
   const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (gi >= vs.total_gauss) return;
-  const int32_t vid = find_view_by_gauss(vs, gi);
-  const View& v = view_of(vs, vid);
+  if (gi >= live_gauss(vs)) return;
+  const View& v = view_at(vs, view_of_gauss(vs, gi));
   const int64_t i = gi - v.geom_off;
   Proj P;
   const bool vis = project(v, i, P, true);
@@ -66,9 +49,8 @@ __device__ __forceinline__ void put(float* a, int64_t idx, float val, int accumu
 __global__ void __launch_bounds__(256) k_preprocess_bwd(ViewSet vs, Geom geom, const float* __restrict__ g2d,
                                                          pvg_gaussians_grad grad, int accumulate) {
   const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (gi >= vs.total_gauss) return;
-  const int32_t vid = find_view_by_gauss(vs, gi);
-  const View& v = view_of(vs, vid);
+  if (gi >= live_gauss(vs)) return;
+  const View& v = view_at(vs, view_of_gauss(vs, gi));
   const int64_t i = gi - v.geom_off;
   const Scene& s = v.s;
   const int64_t n = s.n;

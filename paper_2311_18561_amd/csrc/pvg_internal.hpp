@@ -51,13 +51,45 @@ struct Geom {
 };
 
 // Views of a launch: either one view passed by value or a device table.
+// Batched launches read their live totals from device memory (`live`:
+// Gaussians, tiles, views), so one captured graph serves any batch that fits
+// its grid bounds total_gauss / total_tiles.
 struct ViewSet {
-  const View* table;  // device table of nviews views (batched launches), or null
-  View one;           // the view when table is null
-  int32_t nviews;
-  int64_t total_gauss;  // sum of the views' n
-  int64_t total_tiles;  // sum of the views' GX * GY
+  const View* table;    // device table of views (batched launches), or null
+  const int64_t* live;  // device [3]: live Gaussians, tiles, views (batched), or null
+  View one;             // the view when table is null
+  int32_t nviews;       // views (single: 1; batched: table capacity)
+  int64_t total_gauss;  // sum of the views' n (batched: grid bound)
+  int64_t total_tiles;  // sum of the views' GX * GY (batched: grid bound)
 };
+
+#ifdef __HIPCC__
+__device__ __forceinline__ int64_t live_gauss(const ViewSet& vs) { return vs.live ? vs.live[0] : vs.total_gauss; }
+__device__ __forceinline__ int64_t live_tiles(const ViewSet& vs) { return vs.live ? vs.live[1] : vs.total_tiles; }
+__device__ __forceinline__ int32_t live_views(const ViewSet& vs) {
+  return vs.live ? static_cast<int32_t>(vs.live[2]) : vs.nviews;
+}
+__device__ __forceinline__ const View& view_at(const ViewSet& vs, int32_t v) { return vs.table ? vs.table[v] : vs.one; }
+// the view holding global Gaussian slot g (views are laid out back to back)
+__device__ __forceinline__ int32_t view_of_gauss(const ViewSet& vs, int64_t g) {
+  if (!vs.table) return 0;
+  int32_t lo = 0, hi = live_views(vs) - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (vs.table[mid].geom_off <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ __forceinline__ int32_t view_of_tile(const ViewSet& vs, int64_t tile) {
+  if (!vs.table) return 0;
+  int32_t lo = 0, hi = live_views(vs) - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (vs.table[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+#endif
 
 // ---------------------------------------------------------------- host side
 // error handling (thread-local message)
@@ -68,6 +100,11 @@ int hip_fail(hipError_t e, const char* what);
     hipError_t e_ = (call);                             \
     if (e_ != hipSuccess) return ::pvg::hip_fail(e_, #call); \
   } while (0)
+
+// validation and view construction (api.cpp)
+bool check_gaussians(const pvg_gaussians* g);
+bool check_camera(const pvg_camera* c);
+View make_view(const pvg_gaussians* g, const pvg_camera* c, const pvg_frame* f);
 
 // stage profiler
 struct StageScope {
@@ -106,5 +143,8 @@ struct BinPlan {
 BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity);
 int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp, const BinPlan& plan,
                  int sync_count, hipStream_t s);
+// batched forward of a device view table (no host synchronisation, capturable)
+int run_batch_forward(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp, const BinPlan& plan,
+                      hipStream_t s);
 
 }  // namespace pvg

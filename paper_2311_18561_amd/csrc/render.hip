@@ -20,18 +20,6 @@
 
 namespace pvg {
 
-__device__ __forceinline__ const View& rview(const ViewSet& vs, int32_t v) { return vs.table ? vs.table[v] : vs.one; }
-
-__device__ __forceinline__ int32_t view_of_tile(const ViewSet& vs, int64_t tile) {
-  if (!vs.table) return 0;
-  int32_t lo = 0, hi = vs.nviews - 1;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi + 1) >> 1;
-    if (vs.table[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
   const int64_t per = (total + 7) / 8;
   return (b % 8) * per + b / 8;
@@ -74,9 +62,10 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
   __shared__ float2 s_xy[64];
   __shared__ float4 s_co[64];
   __shared__ float4 s_rgb[64];
-  const int64_t tile = xcd_tile(blockIdx.x, vs.total_tiles);
-  if (tile >= vs.total_tiles) return;
-  const View& v = rview(vs, view_of_tile(vs, tile));
+  const int64_t ntiles = live_tiles(vs);
+  const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+  if (tile >= ntiles) return;
+  const View& v = view_at(vs, view_of_tile(vs, tile));
   const int64_t local = tile - v.tile_off;
   const int tx = static_cast<int>(local % v.GX), ty = static_cast<int>(local / v.GX);
   const int lane = threadIdx.x;
@@ -163,9 +152,10 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const 
   __shared__ uint32_t s_g[64];
   __shared__ float s_acc[64][9];
   __shared__ int s_any[64];
-  const int64_t tile = xcd_tile(blockIdx.x, vs.total_tiles);
-  if (tile >= vs.total_tiles) return;
-  const View& v = rview(vs, view_of_tile(vs, tile));
+  const int64_t ntiles = live_tiles(vs);
+  const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+  if (tile >= ntiles) return;
+  const View& v = view_at(vs, view_of_tile(vs, tile));
   const int64_t local = tile - v.tile_off;
   const int tx = static_cast<int>(local % v.GX), ty = static_cast<int>(local / v.GX);
   const int lane = threadIdx.x;

@@ -1,0 +1,109 @@
+"""The render server on the GPU: each request's image is the same alone and in
+a mixed batch (scenes, resolutions, times), through graph replays, and when a
+batch overflows its instance capacity and is rerun request by request."""
+import numpy as np
+import pytest
+
+import gen
+from helpers import to_device
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _scenes():
+    out = []
+    for k, (n, layout) in enumerate([(20_000, "box"), (50_000, "path"), (8_000, "box")]):
+        out.append(gen.make_scene(n, 40 + k, sh_degree=3 if k != 2 else 1, layout=layout))
+    return out
+
+
+def _requests(rng, n_req):
+    res = [(160, 96), (200, 136), (320, 240)]
+    reqs = []
+    for i in range(n_req):
+        w, h = res[i % 3]
+        sc = int(rng.integers(0, 3))
+        yaw = float(rng.uniform(-40, 40))
+        center = (0.0, 0.0, float(rng.uniform(0, 20))) if sc == 1 else (0.0, 0.0, 0.0)
+        cam = gen.yaw_camera(w, h, yaw if sc == 1 else 0.0, center)
+        reqs.append((sc, cam, float(np.float32(rng.uniform(0, 1))), (0.1 * (i % 3), 0.0, 0.2)))
+    return reqs
+
+
+def _direct(params, cam, t, bg):
+    import paper_2311_18561_amd as pvg
+    img, _, _, _, _ = pvg.render(params, cam, t, 0.0, 0, bg)
+    return img
+
+
+@pytest.mark.parametrize("use_graphs", [False, True])
+def test_batched_results_equal_individual_renders(use_graphs):
+    from paper_2311_18561_amd.serve import Server
+    scenes = _scenes()
+    params = [to_device(s) for s in scenes]
+    rng = np.random.default_rng(7)
+    reqs = _requests(rng, 24)
+    expect = [_direct(params[sc], cam, t, bg) for sc, cam, t, bg in reqs]
+    torch.cuda.synchronize()
+    with Server(max_batch=6, max_inflight=2, use_graphs=use_graphs, max_batch_gaussians=400_000,
+                max_batch_pixels=6 * 320 * 240, instance_capacity=1 << 24) as srv:
+        sids = [srv.load_scene(p) for p in params]
+        for rep in range(3):  # replays, with eager work between them
+            outs = [torch.full((3, cam["height"], cam["width"]), -1.0, device="cuda") for _, cam, _, _ in reqs]
+            tks = [srv.submit(sids[sc], cam, t, out, bg) for (sc, cam, t, bg), out in zip(reqs, outs)]
+            res = [srv.wait(tk) for tk in tks]
+            assert all(r.status == 0 for r in res)
+            sizes = [r.batch_size for r in res]
+            print(f"replay {rep}: batch sizes {sizes}")
+            assert max(sizes) > 1
+            for i, (o, e) in enumerate(zip(outs, expect)):
+                assert torch.equal(o, e), (rep, i, float((o - e).abs().max()))
+            _ = _direct(params[0], reqs[0][1], 0.3, (0, 0, 0))  # unrelated eager work
+            torch.cuda.synchronize()
+        st = srv.stats()
+        print(st)
+        assert st["completed"] == 72
+        if use_graphs:
+            assert st["graph_launches"] == st["batches"] and st["graph_builds"] >= 1
+
+
+def test_overflow_reruns_requests_alone():
+    from paper_2311_18561_amd.serve import Server
+    import paper_2311_18561_amd as pvg
+    scenes = _scenes()
+    params = [to_device(s) for s in scenes[:1]]
+    cams = [gen.make_camera(160 + 16 * k, 96) for k in range(4)]
+    Ms = []
+    expect = []
+    for cam in cams:
+        img, _, _, _, bins = pvg.render(params[0], cam, 0.5)
+        Ms.append(bins.num_instances)
+        expect.append(img)
+    cap = int(max(Ms) * 1.5)  # each fits alone, four together do not
+    assert cap < sum(Ms)
+    with Server(max_batch=4, max_inflight=1, use_graphs=True, max_batch_gaussians=100_000,
+                max_batch_pixels=4 * 208 * 96, instance_capacity=cap) as srv:
+        sid = srv.load_scene(params[0])
+        blocker = srv.submit(sid, cams[0], 0.5, torch.empty_like(expect[0]))
+        outs = [torch.empty_like(e) for e in expect]
+        tks = [srv.submit(sid, cam, 0.5, o) for cam, o in zip(cams, outs)]
+        res = [srv.wait(tk) for tk in tks]
+        srv.wait(blocker)
+        assert all(r.status == 0 for r in res)
+        for o, e in zip(outs, expect):
+            assert torch.equal(o, e)
+        st = srv.stats()
+        assert st["retries"] >= 2
+    # a request that alone exceeds the capacity fails cleanly
+    with Server(max_batch=2, max_inflight=1, max_batch_gaussians=100_000, max_batch_pixels=208 * 96,
+                instance_capacity=max(16, min(Ms) // 4)) as srv:
+        sid = srv.load_scene(params[0])
+        r = srv.wait(srv.submit(sid, cams[1], 0.5, torch.empty_like(expect[1])))
+        assert r.status == -2  # PVG_ERR_CAPACITY
