@@ -146,6 +146,16 @@ def main():
     torch.cuda.synchronize()
 
     # timed region: K training-shaped steps, stage events on the launch stream
+    import ctypes as C
+
+    def read_stages():
+        out = {}
+        for s, name in enumerate(L.STAGES):
+            ms, calls, work = C.c_double(), C.c_int64(), C.c_int64()
+            lib.pvg_profile_read(s, C.byref(ms), C.byref(calls), C.byref(work))
+            out[name] = {"ms": ms.value, "calls": calls.value, "work": work.value}
+        return out
+
     lib.pvg_profile_reset()
     lib.pvg_profile_enable(1)
     torch.cuda.synchronize()
@@ -156,13 +166,20 @@ def main():
     t_train = time.perf_counter() - t0
     lib.pvg_profile_collect()
     lib.pvg_profile_enable(0)
-    stages = {}
-    import ctypes as C
-    for s, name in enumerate(L.STAGES):
-        ms, calls, work = C.c_double(), C.c_int64(), C.c_int64()
-        lib.pvg_profile_read(s, C.byref(ms), C.byref(calls), C.byref(work))
-        stages[name] = {"ms": ms.value, "calls": calls.value, "work": work.value}
+    stages = read_stages()
     lib.pvg_profile_reset()
+    # one more step, untimed, with the render kernels counting evaluated pairs
+    # (the counts are deterministic: same inputs, same pairs)
+    lib.pvg_profile_enable(2)
+    train_step()
+    torch.cuda.synchronize()
+    lib.pvg_profile_collect()
+    lib.pvg_profile_enable(0)
+    counted = read_stages()
+    lib.pvg_profile_reset()
+    for name in ("render_fwd", "render_bwd"):
+        if counted[name]["calls"]:
+            stages[name]["work"] = counted[name]["work"] / counted[name]["calls"] * stages[name]["calls"]
 
     # forward-only rate over the three H(t) renders
     torch.cuda.synchronize()

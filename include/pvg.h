@@ -180,7 +180,8 @@ enum pvg_stage {
   PVG_STAGE_PREPROCESS_BWD, PVG_STAGE_COUNT
 };
 /* on = 1: every later launch is bracketed by a pair of hipEvents on its
- * stream and, for the render stages, counts evaluated (pixel, Gaussian) pairs. */
+ * stream.  on = 2: in addition the render stages count the (pixel, Gaussian)
+ * pairs they evaluate (a slower variant of their kernels).  on = 0: off. */
 int pvg_profile_enable(int32_t on);
 /* Waits for the recorded events and adds their durations to the totals. */
 int pvg_profile_collect(void);

@@ -34,6 +34,7 @@ namespace {
 struct EventPair { int stage; hipEvent_t a, b; };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+bool g_count_work = false;
 std::vector<EventPair> g_pending;
 std::vector<hipEvent_t> g_pool;
 double g_ms[PVG_STAGE_COUNT];
@@ -56,7 +57,7 @@ hipEvent_t take_event() {
 bool profiling() { return g_prof_on; }
 
 unsigned long long* profile_work_counter(int stage) {
-  if (!g_prof_on || !g_work_dev) return nullptr;
+  if (!g_prof_on || !g_count_work || !g_work_dev) return nullptr;
   return g_work_dev + stage;
 }
 
@@ -263,6 +264,7 @@ int pvg_profile_enable(int32_t on) {
     if (e != hipSuccess) return hip_fail(e, "hipMemset(profile counters)");
   }
   g_prof_on = on != 0;
+  g_count_work = on >= 2;
   return PVG_OK;
 }
 

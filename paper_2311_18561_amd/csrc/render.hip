@@ -37,31 +37,46 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
-// alpha of a (pixel, Gaussian) pair; the exact arithmetic is shared by the
-// forward and the adjoint so that both take the same branch decisions.
-struct Pair {
-  float dx, dy, power, G, raw, alpha;
-};
-__device__ __forceinline__ bool eval_pair(float gx, float gy, float A, float B, float C, float op, float px, float py,
-                                          Pair& p) {
-  p.dx = gx - px;
-  p.dy = gy - py;
-  p.power = -0.5f * (A * (p.dx * p.dx) + C * (p.dy * p.dy)) - B * (p.dx * p.dy);
-  if (p.power > 0.0f) return false;
-  p.G = expf(p.power);
-  p.raw = op * p.G;
-  p.alpha = fminf(kAlphaMax, p.raw);
-  return !(p.alpha < kAlphaMin);
+// G-exponent of a (pixel, Gaussian) pair; the exact arithmetic (and with it
+// every branch decision) is shared by the forward and the adjoint.
+__device__ __forceinline__ float pair_power(float dx, float dy, float A, float B, float C) {
+  return -0.5f * (A * (dx * dx) + C * (dy * dy)) - B * (dx * dy);
+}
+
+// Can a Gaussian reach alpha >= 1/255 at any pixel of the tile?  alpha =
+// min(0.99, o~ G) >= 1/255 needs power >= ln(1 / (255 o~)); power = -q/2 with
+// q the conic's quadratic form, whose minimum over the tile's sample
+// rectangle is exact (interior: 0; else the best of the four edges).  The test
+// keeps a wide margin, and never drops a Gaussian with non-finite values, so a
+// dropped Gaussian is one every pixel of the tile would skip.
+__device__ __forceinline__ bool tile_reachable(float gx, float gy, float A, float B, float C, float op, float X0,
+                                               float X1, float Y0, float Y1) {
+  if (!(isfinite(gx) && isfinite(gy) && isfinite(A) && isfinite(B) && isfinite(C) && isfinite(op))) return true;
+  if (op < kAlphaMin) return false;
+  if (!(A > 0.0f && C > 0.0f)) return true;
+  const float dxl = gx - X1, dxh = gx - X0, dyl = gy - Y1, dyh = gy - Y0;
+  float qmin;
+  if (dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f) {
+    qmin = 0.0f;
+  } else {
+    auto q = [&](float dx, float dy) { return A * dx * dx + 2.0f * B * dx * dy + C * dy * dy; };
+    auto best_dy = [&](float dx) { return fminf(fmaxf(-B * dx / C, dyl), dyh); };
+    auto best_dx = [&](float dy) { return fminf(fmaxf(-B * dy / A, dxl), dxh); };
+    qmin = fminf(fminf(q(dxl, best_dy(dxl)), q(dxh, best_dy(dxh))), fminf(q(best_dx(dyl), dyl), q(best_dx(dyh), dyh)));
+  }
+  const float need = -logf(kAlphaMin / op);  // -power must stay below this
+  return !(0.5f * qmin * 0.999f > need + 0.01f);
 }
 
 constexpr int kPix = 4;  // pixels per lane
 
+template <bool kCount>
 __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const uint32_t* __restrict__ vals,
                                                    const uint32_t* __restrict__ ranges,
                                                    unsigned long long* pair_counter) {
   __shared__ float2 s_xy[64];
   __shared__ float4 s_co[64];
-  __shared__ float4 s_rgb[64];
+  __shared__ float4 s_rgb[64];  // rgb and the list position (as int bits)
   const int64_t ntiles = live_tiles(vs);
   const int64_t tile = xcd_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
@@ -72,52 +87,66 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
   const int px = tx * kTile + (lane & 15);
   const int py0 = ty * kTile + (lane >> 4);
   const float fpx = static_cast<float>(px);
+  const float X0 = static_cast<float>(tx * kTile), Y0 = static_cast<float>(ty * kTile);
+  const float X1 = static_cast<float>(min(v.W, (tx + 1) * kTile) - 1);
+  const float Y1 = static_cast<float>(min(v.H, (ty + 1) * kTile) - 1);
+  const uint64_t lt = (1ull << lane) - 1ull;
   float T[kPix], Cr[kPix], Cg[kPix], Cb[kPix];
   int last[kPix];
-  bool done[kPix];
+  bool act[kPix];
 #pragma unroll
   for (int k = 0; k < kPix; ++k) {
     T[k] = 1.0f; Cr[k] = 0.0f; Cg[k] = 0.0f; Cb[k] = 0.0f; last[k] = 0;
-    done[k] = !(px < v.W && py0 + 4 * k < v.H);
+    act[k] = px < v.W && py0 + 4 * k < v.H;
   }
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
   long long evaluated = 0;
   for (uint32_t b0 = start; b0 < end; b0 += 64) {
-    const bool active = !(done[0] && done[1] && done[2] && done[3]);
-    if (!__any(active)) break;
+    if (!__any(act[0] || act[1] || act[2] || act[3])) break;
     const uint32_t idx = b0 + lane;
+    bool keep = false;
+    float2 m;
+    float4 co, c;
     if (idx < end) {
       const uint32_t g = vals[idx];
-      s_xy[lane] = reinterpret_cast<const float2*>(geom.xy)[g];
-      s_co[lane] = reinterpret_cast<const float4*>(geom.conic_op)[g];
-      s_rgb[lane] = make_float4(geom.rgb[3 * g], geom.rgb[3 * g + 1], geom.rgb[3 * g + 2], 0.0f);
+      m = reinterpret_cast<const float2*>(geom.xy)[g];
+      co = reinterpret_cast<const float4*>(geom.conic_op)[g];
+      c = make_float4(geom.rgb[3 * g], geom.rgb[3 * g + 1], geom.rgb[3 * g + 2],
+                      __int_as_float(static_cast<int>(idx - start) + 1));
+      keep = tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1);
+    }
+    const uint64_t km = __ballot(keep);
+    if (keep) {
+      const int slot = __popcll(km & lt);
+      s_xy[slot] = m;
+      s_co[slot] = co;
+      s_rgb[slot] = c;
     }
     __syncthreads();
-    const int cnt = static_cast<int>(min(64u, end - b0));
+    const int cnt = __popcll(km);
     for (int j = 0; j < cnt; ++j) {
-      const bool act = !(done[0] && done[1] && done[2] && done[3]);
-      if (!__any(act)) break;
-      const float2 m = s_xy[j];
-      const float4 co = s_co[j];
-      const float4 c = s_rgb[j];
-      const int pos = static_cast<int>(b0 - start) + j + 1;
+      if (!__any(act[0] || act[1] || act[2] || act[3])) break;
+      const float2 gm = s_xy[j];
+      const float4 gc = s_co[j];
+      const float4 cc = s_rgb[j];
+      const int pos = __float_as_int(cc.w);
 #pragma unroll
       for (int k = 0; k < kPix; ++k) {
-        if (done[k]) continue;
-        ++evaluated;
-        Pair p;
-        if (!eval_pair(m.x, m.y, co.x, co.y, co.z, co.w, fpx, static_cast<float>(py0 + 4 * k), p)) continue;
-        const float Tn = T[k] * (1.0f - p.alpha);
-        if (Tn < kTMin) {
-          done[k] = true;
-          continue;
-        }
-        const float w = p.alpha * T[k];
-        Cr[k] = Cr[k] + c.x * w;
-        Cg[k] = Cg[k] + c.y * w;
-        Cb[k] = Cb[k] + c.z * w;
-        T[k] = Tn;
-        last[k] = pos;
+        if (kCount) evaluated += act[k] ? 1 : 0;
+        const float dx = gm.x - fpx, dy = gm.y - static_cast<float>(py0 + 4 * k);
+        const float power = pair_power(dx, dy, gc.x, gc.y, gc.z);
+        const float alpha = fminf(kAlphaMax, gc.w * expf(power));
+        const bool ok = act[k] && !(power > 0.0f) && !(alpha < kAlphaMin);
+        const float Tn = T[k] * (1.0f - alpha);
+        const bool stop = ok && Tn < kTMin;
+        const bool use = ok && !stop;
+        const float w = use ? alpha * T[k] : 0.0f;
+        Cr[k] = fmaf(cc.x, w, Cr[k]);
+        Cg[k] = fmaf(cc.y, w, Cg[k]);
+        Cb[k] = fmaf(cc.z, w, Cb[k]);
+        T[k] = use ? Tn : T[k];
+        last[k] = use ? pos : last[k];
+        act[k] = act[k] && !stop;
       }
     }
     __syncthreads();
@@ -135,7 +164,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
       v.n_contrib[o] = last[k];
     }
   }
-  if (pair_counter) {
+  if (kCount && pair_counter) {
     long long e = evaluated;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
@@ -143,12 +172,13 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
   }
 }
 
+template <bool kCount>
 __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const uint32_t* __restrict__ vals,
                                                    const uint32_t* __restrict__ ranges, float* g2d,
                                                    unsigned long long* pair_counter) {
   __shared__ float2 s_xy[64];
   __shared__ float4 s_co[64];
-  __shared__ float4 s_rgb[64];
+  __shared__ float4 s_rgb[64];  // rgb and the 0-based list position (as int bits)
   __shared__ uint32_t s_g[64];
   __shared__ float s_acc[64][9];
   __shared__ int s_any[64];
@@ -162,6 +192,10 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const 
   const int px = tx * kTile + (lane & 15);
   const int py0 = ty * kTile + (lane >> 4);
   const float fpx = static_cast<float>(px);
+  const float X0 = static_cast<float>(tx * kTile), Y0 = static_cast<float>(ty * kTile);
+  const float X1 = static_cast<float>(min(v.W, (tx + 1) * kTile) - 1);
+  const float Y1 = static_cast<float>(min(v.H, (ty + 1) * kTile) - 1);
+  const uint64_t lt = (1ull << lane) - 1ull;
   const int64_t HW = static_cast<int64_t>(v.W) * v.H;
   float T[kPix], rr[kPix], gr[kPix], gg[kPix], gb[kPix];
   int last[kPix];
@@ -188,48 +222,64 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const 
   long long evaluated = 0;
   for (int hi = lmax; hi > 0; hi -= 64) {
     const int lo = max(0, hi - 64);
-    const int cnt = hi - lo;
-    if (lane < cnt) {
-      const uint32_t g = vals[start + lo + lane];
-      s_g[lane] = g;
-      s_xy[lane] = reinterpret_cast<const float2*>(geom.xy)[g];
-      s_co[lane] = reinterpret_cast<const float4*>(geom.conic_op)[g];
-      s_rgb[lane] = make_float4(geom.rgb[3 * g], geom.rgb[3 * g + 1], geom.rgb[3 * g + 2], 0.0f);
+    bool keep = false;
+    uint32_t g = 0;
+    float2 m;
+    float4 co, c;
+    if (lane < hi - lo) {
+      g = vals[start + lo + lane];
+      m = reinterpret_cast<const float2*>(geom.xy)[g];
+      co = reinterpret_cast<const float4*>(geom.conic_op)[g];
+      c = make_float4(geom.rgb[3 * g], geom.rgb[3 * g + 1], geom.rgb[3 * g + 2], __int_as_float(lo + lane));
+      keep = tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1);
+    }
+    const uint64_t km = __ballot(keep);
+    if (keep) {
+      const int slot = __popcll(km & lt);
+      s_g[slot] = g;
+      s_xy[slot] = m;
+      s_co[slot] = co;
+      s_rgb[slot] = c;
     }
     __syncthreads();
+    const int cnt = __popcll(km);
     for (int j = cnt - 1; j >= 0; --j) {
-      const int pos = lo + j;  // 0-based list position
-      const float2 m = s_xy[j];
-      const float4 co = s_co[j];
-      const float4 c = s_rgb[j];
+      const float2 gm = s_xy[j];
+      const float4 gc = s_co[j];
+      const float4 cc = s_rgb[j];
+      const int pos = __float_as_int(cc.w);
       float a[9];
 #pragma unroll
       for (int q = 0; q < 9; ++q) a[q] = 0.0f;
       bool any = false;
 #pragma unroll
       for (int k = 0; k < kPix; ++k) {
-        if (pos >= last[k]) continue;
-        ++evaluated;
-        Pair p;
-        if (!eval_pair(m.x, m.y, co.x, co.y, co.z, co.w, fpx, static_cast<float>(py0 + 4 * k), p)) continue;
-        any = true;
-        T[k] = T[k] / (1.0f - p.alpha);
-        const float cg = c.x * gr[k] + c.y * gg[k] + c.z * gb[k];
-        const float dalpha = T[k] * (cg - rr[k]);
-        const float w = p.alpha * T[k];
-        a[6] += w * gr[k];
-        a[7] += w * gg[k];
-        a[8] += w * gb[k];
-        rr[k] = p.alpha * cg + (1.0f - p.alpha) * rr[k];
-        if (!(p.raw > kAlphaMax)) {
-          a[5] += p.G * dalpha;
-          const float gp = p.alpha * dalpha;
-          a[2] += -0.5f * p.dx * p.dx * gp;
-          a[3] += -p.dx * p.dy * gp;
-          a[4] += -0.5f * p.dy * p.dy * gp;
-          a[0] += -(co.x * p.dx + co.y * p.dy) * gp;
-          a[1] += -(co.y * p.dx + co.z * p.dy) * gp;
-        }
+        const bool inr = pos < last[k];
+        if (kCount) evaluated += inr ? 1 : 0;
+        const float dx = gm.x - fpx, dy = gm.y - static_cast<float>(py0 + 4 * k);
+        const float power = pair_power(dx, dy, gc.x, gc.y, gc.z);
+        const float G = expf(power);
+        const float raw = gc.w * G;
+        const float alpha = fminf(kAlphaMax, raw);
+        const bool ok = inr && !(power > 0.0f) && !(alpha < kAlphaMin);
+        any = any || ok;
+        const float om = 1.0f - alpha;
+        T[k] = ok ? T[k] * __builtin_amdgcn_rcpf(om) : T[k];
+        const float cg = cc.x * gr[k] + cc.y * gg[k] + cc.z * gb[k];
+        const float dal = T[k] * (cg - rr[k]);
+        const float w = ok ? alpha * T[k] : 0.0f;
+        a[6] = fmaf(w, gr[k], a[6]);
+        a[7] = fmaf(w, gg[k], a[7]);
+        a[8] = fmaf(w, gb[k], a[8]);
+        rr[k] = ok ? fmaf(alpha, cg, om * rr[k]) : rr[k];
+        const bool nc = ok && !(raw > kAlphaMax);
+        const float gp = nc ? alpha * dal : 0.0f;
+        a[5] += nc ? G * dal : 0.0f;
+        a[2] = fmaf(-0.5f * dx * dx, gp, a[2]);
+        a[3] = fmaf(-dx * dy, gp, a[3]);
+        a[4] = fmaf(-0.5f * dy * dy, gp, a[4]);
+        a[0] = fmaf(-(gc.x * dx + gc.y * dy), gp, a[0]);
+        a[1] = fmaf(-(gc.y * dx + gc.z * dy), gp, a[1]);
       }
       const bool wany = __any(any);
       if (wany) {
@@ -250,7 +300,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const 
     }
     __syncthreads();
   }
-  if (pair_counter) {
+  if (kCount && pair_counter) {
     long long e = evaluated;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
@@ -263,8 +313,13 @@ hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t
   if (vs.total_tiles == 0) return hipSuccess;
   StageScope scope(PVG_STAGE_RENDER_FWD, s);
   const int64_t grid = ((vs.total_tiles + 7) / 8) * 8;
-  hipLaunchKernelGGL(k_render_fwd, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals, ranges,
-                     profile_work_counter(PVG_STAGE_RENDER_FWD));
+  unsigned long long* cnt = profile_work_counter(PVG_STAGE_RENDER_FWD);
+  if (cnt)
+    hipLaunchKernelGGL(k_render_fwd<true>, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals, ranges,
+                       cnt);
+  else
+    hipLaunchKernelGGL(k_render_fwd<false>, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals, ranges,
+                       cnt);
   return hipGetLastError();
 }
 
@@ -274,8 +329,13 @@ hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const uint32_t
   if (vs.total_tiles == 0) return hipSuccess;
   StageScope scope(PVG_STAGE_RENDER_BWD, s);
   const int64_t grid = ((vs.total_tiles + 7) / 8) * 8;
-  hipLaunchKernelGGL(k_render_bwd, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals, ranges, g2d,
-                     profile_work_counter(PVG_STAGE_RENDER_BWD));
+  unsigned long long* cnt = profile_work_counter(PVG_STAGE_RENDER_BWD);
+  if (cnt)
+    hipLaunchKernelGGL(k_render_bwd<true>, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals, ranges,
+                       g2d, cnt);
+  else
+    hipLaunchKernelGGL(k_render_bwd<false>, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals, ranges,
+                       g2d, cnt);
   return hipGetLastError();
 }
 

@@ -14,15 +14,18 @@ CAM = gen.make_camera(640, 480)
 
 
 def test_continuous_batching_admits_requests_as_lanes_free():
-    with Server(max_batch=4, max_inflight=2, stub_launch_us=30_000, max_batch_gaussians=100_000_000) as s:
+    with Server(max_batch=4, max_inflight=2, stub_launch_us=150_000, max_batch_gaussians=100_000_000) as s:
         sid = s.load_scene(n=1000)
-        tks = [s.submit(sid, CAM, 0.1 * i) for i in range(10)]
+        tks = [s.submit(sid, CAM, 0.0)]
+        time.sleep(0.03)            # launched alone on the first lane
+        tks.append(s.submit(sid, CAM, 0.1))
+        time.sleep(0.03)            # launched alone on the second lane, overlapping the first
+        tks += [s.submit(sid, CAM, 0.1 * i) for i in range(2, 10)]  # both lanes busy: these queue
         res = [s.wait(t) for t in tks]
         assert all(r.status == 0 for r in res)
-        sizes = [r.batch_size for r in res]
-        # both lanes were free: the first two requests launch alone at once, the
-        # eight that queued meanwhile fill the next launches four at a time
-        assert sizes == [1, 1, 4, 4, 4, 4, 4, 4, 4, 4]
+        assert [r.batch_size for r in res] == [1, 1, 4, 4, 4, 4, 4, 4, 4, 4]
+        # the second request ran while the first was still on the "device"
+        assert res[1].t_launch_ns < res[0].t_done_ns
         launches = [r.t_launch_ns for r in res]
         assert launches == sorted(launches)  # FIFO
         st = s.stats()
