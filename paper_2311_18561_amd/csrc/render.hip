@@ -31,6 +31,45 @@ __device__ __forceinline__ float wave_sum(float x) {
   return x;
 }
 
+// Sums nine per-lane values over the wave by halving: a half-wave swap adds
+// two values at once (lanes 0-31 keep the sums of the even-indexed values,
+// 32-63 of the odd ones), a row swap does the same between the two 16-lane
+// rows of each half, and DPP folds the last three values within each row.
+// Afterwards every lane of row r (lanes 16r .. 16r+15) holds, in out[k], the
+// wave total of value 4k + 2(r & 1) + (r >> 1) (indices >= 9 are padding).
+__device__ __forceinline__ float swap_sum32(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap_sum16(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float dpp_add(float x, int ctrl) {
+  switch (ctrl) {  // the control word must be a compile-time constant
+    case 0x128: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, false));
+    case 0x124: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xf, 0xf, false));
+    case 0x4e: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4e, 0xf, 0xf, false));
+    default: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xb1, 0xf, 0xf, false));
+  }
+}
+__device__ __forceinline__ void wave_sum9(const float a[9], float out[3]) {
+  float h[5];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) h[m] = swap_sum32(a[2 * m], a[2 * m + 1]);
+  h[4] = swap_sum32(a[8], 0.0f);
+  out[0] = swap_sum16(h[0], h[1]);
+  out[1] = swap_sum16(h[2], h[3]);
+  out[2] = swap_sum16(h[4], 0.0f);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    out[k] = dpp_add(out[k], 0x128);  // row_ror:8
+    out[k] = dpp_add(out[k], 0x124);  // row_ror:4
+    out[k] = dpp_add(out[k], 0x4e);   // quad_perm [2,3,0,1]
+    out[k] = dpp_add(out[k], 0xb1);   // quad_perm [1,0,3,2]
+  }
+}
+
 __device__ __forceinline__ int wave_max(int x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
@@ -283,11 +322,15 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const 
       }
       const bool wany = __any(any);
       if (wany) {
+        float red[3];
+        wave_sum9(a, red);
+        if ((lane & 15) == 0) {
+          const int r = lane >> 4;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) a[q] = wave_sum(a[q]);
-        if (lane == 0) {
-#pragma unroll
-          for (int q = 0; q < 9; ++q) s_acc[j][q] = a[q];
+          for (int k = 0; k < 3; ++k) {
+            const int q = 4 * k + 2 * (r & 1) + (r >> 1);
+            if (q < 9) s_acc[j][q] = red[k];
+          }
         }
       }
       if (lane == 0) s_any[j] = wany ? 1 : 0;

@@ -14,12 +14,12 @@ CAM = gen.make_camera(640, 480)
 
 
 def test_continuous_batching_admits_requests_as_lanes_free():
-    with Server(max_batch=4, max_inflight=2, stub_launch_us=150_000, max_batch_gaussians=100_000_000) as s:
+    with Server(max_batch=4, max_inflight=2, stub_launch_us=400_000, max_batch_gaussians=100_000_000) as s:
         sid = s.load_scene(n=1000)
         tks = [s.submit(sid, CAM, 0.0)]
-        time.sleep(0.03)            # launched alone on the first lane
+        time.sleep(0.08)            # launched alone on the first lane
         tks.append(s.submit(sid, CAM, 0.1))
-        time.sleep(0.03)            # launched alone on the second lane, overlapping the first
+        time.sleep(0.08)            # launched alone on the second lane, overlapping the first
         tks += [s.submit(sid, CAM, 0.1 * i) for i in range(2, 10)]  # both lanes busy: these queue
         res = [s.wait(t) for t in tks]
         assert all(r.status == 0 for r in res)
@@ -33,10 +33,10 @@ def test_continuous_batching_admits_requests_as_lanes_free():
 
 
 def test_late_arrivals_join_the_next_batch_while_one_runs():
-    with Server(max_batch=8, max_inflight=1, stub_launch_us=50_000) as s:
+    with Server(max_batch=8, max_inflight=1, stub_launch_us=300_000) as s:
         sid = s.load_scene(n=1000)
         first = s.submit(sid, CAM, 0.0)
-        time.sleep(0.01)
+        time.sleep(0.08)
         late = [s.submit(sid, CAM, 0.0) for _ in range(3)]
         r0 = s.wait(first)
         rl = [s.wait(t) for t in late]
@@ -46,12 +46,13 @@ def test_late_arrivals_join_the_next_batch_while_one_runs():
 
 
 def test_admission_by_batch_budget():
-    with Server(max_batch=8, max_inflight=1, stub_launch_us=20_000, max_batch_gaussians=5_000_000,
+    with Server(max_batch=8, max_inflight=1, stub_launch_us=300_000, max_batch_gaussians=5_000_000,
                 max_batch_pixels=3 * 640 * 480) as s:
         big = s.load_scene(n=3_000_000)
         small = s.load_scene(n=1_000_000)
         huge = s.load_scene(n=6_000_000)
         blocker = s.submit(small, CAM, 0.0)
+        time.sleep(0.08)  # the blocker holds the only lane while the rest queue
         tks = [s.submit(big, CAM, 0.0), s.submit(small, CAM, 0.0), s.submit(big, CAM, 0.0),
                s.submit(small, CAM, 0.0), s.submit(small, CAM, 0.0), s.submit(small, CAM, 0.0)]
         bad = s.submit(huge, CAM, 0.0)
@@ -86,7 +87,7 @@ def test_unload_is_deferred_until_pending_requests_finish():
 
 
 def test_wait_timeout_poll_and_cancel():
-    with Server(max_batch=1, max_inflight=1, stub_launch_us=100_000) as s:
+    with Server(max_batch=1, max_inflight=1, stub_launch_us=400_000) as s:
         sid = s.load_scene(n=1000)
         a = s.submit(sid, CAM, 0.0)
         b = s.submit(sid, CAM, 0.0)
@@ -99,7 +100,7 @@ def test_wait_timeout_poll_and_cancel():
         with pytest.raises(L.PVGError) as e:
             s.poll(c)
         assert e.value.status == L.PVG_ERR_NOT_FOUND
-        time.sleep(0.02)
+        time.sleep(0.08)
         with pytest.raises(L.PVGError) as e:
             s.release(a)  # launched, not finished
         assert e.value.status == L.PVG_ERR_BUSY
