@@ -100,6 +100,114 @@ def cpu_baseline(cfg, budget_s=20.0):
     }
 
 
+SERVE_SCENES = ((500_000, 30), (1_000_000, 31), (2_000_000, 32), (3_000_000, 33))
+
+
+def serve_bench(seconds: float, warm: float = 1.0):
+    """The serving workload: four resident scenes (0.5M, 1M, 2M, 3M Gaussians,
+    degree 3, driving-path layout), a Poisson stream of 200 requests/s, each a
+    random scene, a camera on the 100 m path (yaw in [-45, 45] degrees), t in
+    [0, 1] and a resolution from {640x480, 960x640, 1920x1280}.  Replayed open
+    loop (arrival times honoured) against the batched server and against the
+    same server restricted to one request per launch and no overlap; then as a
+    burst (all requests queued at once) for the saturation throughput."""
+    import threading
+
+    import torch
+
+    import gen
+    import paper_2311_18561_amd as pvg
+    from paper_2311_18561_amd.serve import Server
+
+    scenes = []
+    for n, seed in SERVE_SCENES:
+        sc = gen.make_scene(n, seed, sh_degree=3, layout="path")
+        scenes.append([torch.from_numpy(sc[f]).cuda() for f in pvg.FIELDS])
+    trace = gen.make_trace(seed=3, rate=200.0, duration=seconds)
+    pool = {}
+    for r in trace:
+        cam = r["camera"]
+        key = (cam["width"], cam["height"])
+        pool.setdefault(key, [])
+    bufs = {k: [torch.empty((3, k[1], k[0]), dtype=torch.float32, device="cuda") for _ in range(96)]
+            for k in pool}
+
+    def replay(srv, sids, open_loop):
+        tickets = [None] * len(trace)
+        owner = {k: [None] * len(v) for k, v in bufs.items()}
+        nxt = {k: 0 for k in bufs}
+        done = threading.Event()
+        results = [None] * len(trace)
+
+        def waiter():
+            for i in range(len(trace)):
+                while tickets[i] is None:
+                    time.sleep(0.0002)
+                results[i] = srv.wait(tickets[i])
+            done.set()
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for i, r in enumerate(trace):
+            cam = r["camera"]
+            key = (cam["width"], cam["height"])
+            slot = nxt[key]
+            nxt[key] = (slot + 1) % len(bufs[key])
+            prev = owner[key][slot]
+            if prev is not None:
+                while results[prev] is None:
+                    time.sleep(0.0002)
+            owner[key][slot] = i
+            if open_loop:
+                delay = r["arrival"] - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+            tickets[i] = srv.submit(sids[r["scene"]], cam, r["t"], bufs[key][slot])
+        done.wait()
+        th.join()
+        return results
+
+    def summarize(results, skip_s):
+        lat = []
+        px = 0
+        t_first = min(r.t_submit_ns for r in results)
+        kept = [(r, tr) for r, tr in zip(results, trace) if (r.t_submit_ns - t_first) * 1e-9 >= skip_s]
+        for r, tr in kept:
+            assert r.status == 0, r.status
+            lat.append((r.t_done_ns - r.t_submit_ns) * 1e-6)
+            px += tr["camera"]["width"] * tr["camera"]["height"]
+        span = (max(r.t_done_ns for r, _ in kept) - min(r.t_submit_ns for r, _ in kept)) * 1e-9
+        lat.sort()
+        pct = lambda q: lat[min(len(lat) - 1, int(q * (len(lat) - 1) + 0.5))]
+        return {"requests": len(kept), "p50_ms": pct(0.5), "p99_ms": pct(0.99), "mpix_per_s": px / span / 1e6,
+                "req_per_s": len(kept) / span,
+                "mean_batch": sum(r.batch_size for r, _ in kept) / max(1, len(kept))}
+
+    out = {"trace": {"requests": len(trace), "rate_per_s": 200.0, "seconds": seconds, "warmup_s": warm,
+                     "scenes": [n for n, _ in SERVE_SCENES],
+                     "resolutions": ["640x480", "960x640", "1920x1280"]}}
+    modes = {"batched": dict(max_batch=8, max_inflight=2),
+             "one_at_a_time": dict(max_batch=1, max_inflight=1)}
+    for name, kw in modes.items():
+        with Server(use_graphs=True, max_batch_gaussians=24_000_000, max_batch_pixels=8 * 1920 * 1280,
+                    instance_capacity=(1 << 30) - 1, **kw) as srv:
+            sids = [srv.load_scene(p) for p in scenes]
+            torch.cuda.synchronize()
+            replay(srv, sids, open_loop=False)  # warm-up: builds the graphs
+            print(f"# serving {name}: warm", file=sys.stderr, flush=True)
+            res = replay(srv, sids, open_loop=True)
+            out[name] = summarize(res, warm)
+            st = srv.stats()
+            out[name]["retries"] = st["retries"]
+            burst = replay(srv, sids, open_loop=False)
+            sat = summarize(burst, 0.0)
+            out[name]["saturation_mpix_per_s"] = sat["mpix_per_s"]
+            out[name]["saturation_req_per_s"] = sat["req_per_s"]
+            print(f"# serving {name}: {out[name]}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -255,6 +363,10 @@ def main():
         "roofline": roof,
         "stages": table,
     }
+    if not args.no_serve:
+        del params, targets
+        torch.cuda.empty_cache()
+        out["serving"] = serve_bench(args.serve_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out))

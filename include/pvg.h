@@ -122,13 +122,15 @@ typedef struct pvg_bins {
   uint32_t* vals;       /* [2][capacity] Gaussian index; sorted result in vals[0 .. M) */
   uint32_t* ranges;     /* [tiles][2] [first, last + 1) of each tile in vals */
   uint32_t* counters;   /* [4] device: M, visible count, overflow flag, reserved */
+  uint32_t* first;      /* [n] optional (may be NULL): index, in emission order, of each visible
+                           Gaussian's first instance; pvg_render_bwd needs it */
   int64_t num_instances;/* host output of a synchronous count (sync_count = 1) */
   int64_t num_visible;  /* host output of a synchronous count */
 } pvg_bins;
 
 typedef struct pvg_ws_sizes {
   size_t bin_tmp_bytes;    /* scratch of pvg_bin_sort */
-  size_t bwd_tmp_bytes;    /* scratch of pvg_render_bwd */
+  size_t bwd_tmp_bytes;    /* scratch of pvg_render_bwd (grows with n, the tiles and the capacity) */
   int64_t num_tiles;       /* ceil(width / 16) * ceil(height / 16) */
 } pvg_ws_sizes;
 
@@ -167,7 +169,10 @@ int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera*
  * the forward's final_T and n_contrib, writes (accumulate = 0) or adds
  * (accumulate = 1) dL/d(every array of g) into grad.  geom and bins must be
  * the forward's, or a deterministic recomputation of them (same inputs give
- * bit-identical geom and bins).  tmp: bwd_tmp_bytes of scratch. */
+ * bit-identical geom and bins), and bins->first must have been filled.
+ * tmp: bwd_tmp_bytes of scratch for the same n, image and capacity.  The
+ * per-Gaussian sums are formed without atomics, so the result is bitwise
+ * reproducible. */
 int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_frame* frame,
                    const pvg_geom* geom, const pvg_bins* bins, const float* final_T,
                    const int32_t* n_contrib, const float* dL_dimg, pvg_gaussians_grad* grad,
@@ -177,7 +182,7 @@ int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_fram
 enum pvg_stage {
   PVG_STAGE_PREPROCESS = 0, PVG_STAGE_COMPACT, PVG_STAGE_DEPTH_SORT, PVG_STAGE_SCAN_EMIT,
   PVG_STAGE_TILE_SORT, PVG_STAGE_RANGES, PVG_STAGE_RENDER_FWD, PVG_STAGE_RENDER_BWD,
-  PVG_STAGE_PREPROCESS_BWD, PVG_STAGE_COUNT
+  PVG_STAGE_PREPROCESS_BWD, PVG_STAGE_GRAD_GATHER, PVG_STAGE_COUNT
 };
 /* on = 1: every later launch is bracketed by a pair of hipEvents on its
  * stream.  on = 2: in addition the render stages count the (pixel, Gaussian)

@@ -21,7 +21,7 @@ PVG_ERR_NOT_FOUND = -6
 PVG_ERR_TIMEOUT = -7
 
 STAGES = ("preprocess", "compact", "depth_sort", "scan_emit", "tile_sort", "ranges", "render_fwd", "render_bwd",
-          "preprocess_bwd")
+          "preprocess_bwd", "grad_gather")
 
 vp = C.c_void_p
 
@@ -54,7 +54,7 @@ class Geom(C.Structure):
 
 class Bins(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("keys", vp), ("vals", vp), ("ranges", vp), ("counters", vp),
-                ("num_instances", C.c_int64), ("num_visible", C.c_int64)]
+                ("first", vp), ("num_instances", C.c_int64), ("num_visible", C.c_int64)]
 
 
 class WsSizes(C.Structure):

@@ -164,6 +164,16 @@ static ViewSet single(const View& v, int64_t n) {
   return vs;
 }
 
+size_t bwd_scratch_bytes(int64_t n, int64_t tiles, int64_t capacity, size_t* off_rec, size_t* off_cut) {
+  auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
+  const size_t g2d = al(sizeof(float) * kG2DStride * static_cast<size_t>(std::max<int64_t>(n, 1)));
+  const size_t rec = al(sizeof(float) * 9 * static_cast<size_t>(std::max<int64_t>(capacity, 1)));
+  const size_t cut = al(sizeof(unsigned long long) * static_cast<size_t>(std::max<int64_t>(tiles, 1)));
+  if (off_rec) *off_rec = g2d;
+  if (off_cut) *off_cut = g2d + rec;
+  return g2d + rec + cut;
+}
+
 static Geom to_geom(const pvg_geom* g) {
   return Geom{g->xy, g->depth, g->conic_op, g->rgb, g->radius, g->tiles};
 }
@@ -181,7 +191,7 @@ int pvg_workspace_query(int64_t n, int32_t width, int32_t height, int64_t capaci
   }
   const int64_t tiles = static_cast<int64_t>((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
   out->bin_tmp_bytes = plan_bins(n, tiles, capacity).total;
-  out->bwd_tmp_bytes = sizeof(float) * kG2DStride * static_cast<size_t>(std::max<int64_t>(n, 1));
+  out->bwd_tmp_bytes = bwd_scratch_bytes(n, tiles, capacity, nullptr, nullptr);
   out->num_tiles = tiles;
   return PVG_OK;
 }
@@ -237,7 +247,12 @@ int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_fram
     set_error("a gradient array is null");
     return PVG_ERR_INVALID;
   }
-  const size_t need = sizeof(float) * kG2DStride * static_cast<size_t>(std::max<int64_t>(g->n, 1));
+  if (g->n > 0 && !bins->first) {
+    set_error("bins.first is null: the adjoint needs each Gaussian's first instance index");
+    return PVG_ERR_INVALID;
+  }
+  size_t off_rec = 0, off_cut = 0;
+  const size_t need = bwd_scratch_bytes(g->n, tiles_of(cam), bins->capacity, &off_rec, &off_cut);
   if (!tmp || tmp_bytes < need) {
     set_error("render_bwd scratch of %zu bytes is smaller than the %zu required", tmp_bytes, need);
     return PVG_ERR_NOMEM;
@@ -248,9 +263,11 @@ int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_fram
   v.n_contrib = const_cast<int32_t*>(n_contrib);
   v.dL_dimg = dL_dimg;
   const ViewSet vs = single(v, g->n);
-  float* g2d = static_cast<float*>(tmp);
-  PVG_HIP(launch_fill_f32(g2d, 0.0f, kG2DStride * g->n, s));
-  PVG_HIP(launch_render_bwd(vs, to_geom(geom), bins->vals, bins->ranges, dL_dimg, g2d, s));
+  char* base = static_cast<char*>(tmp);
+  float* g2d = reinterpret_cast<float*>(base);
+  float* rec = reinterpret_cast<float*>(base + off_rec);
+  unsigned long long* cut = reinterpret_cast<unsigned long long*>(base + off_cut);
+  PVG_HIP(launch_render_bwd(vs, to_geom(geom), bins->vals, bins->ranges, bins->first, rec, cut, g2d, s));
   PVG_HIP(launch_preprocess_bwd(vs, to_geom(geom), g2d, *grad, accumulate, s));
   return PVG_OK;
 }
@@ -310,7 +327,7 @@ int pvg_profile_reset(void) {
 
 const char* pvg_stage_name(int32_t stage) {
   static const char* names[PVG_STAGE_COUNT] = {"preprocess", "compact", "depth_sort", "scan_emit", "tile_sort",
-                                                "ranges", "render_fwd", "render_bwd", "preprocess_bwd"};
+                                                "ranges", "render_fwd", "render_bwd", "preprocess_bwd", "grad_gather"};
   if (stage < 0 || stage >= PVG_STAGE_COUNT) return "unknown";
   return names[stage];
 }

@@ -212,13 +212,23 @@ __global__ void __launch_bounds__(kThreads) k_rs_rowscan(uint32_t* hist, int64_t
   if (threadIdx.x == 0) rowtot[blockIdx.x] = carry;
 }
 
+// Scatter of one stable LSD pass.  Each wave ranks its own contiguous 1024
+// keys (wave ballots find lanes with equal digits; a wave-private LDS counter
+// per digit carries ranks across its 16 sub-tiles), the block combines the
+// four waves per digit, stages the block's 4096 pairs locally sorted in LDS and
+// writes each digit's run contiguously.
 __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint32_t* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin, uint32_t* kout,
                                                          uint32_t* vout, const uint32_t* n_dev, int64_t n_host,
                                                          int shift, int bits, const uint32_t* __restrict__ hist,
                                                          int64_t cols, const uint32_t* __restrict__ rowtot) {
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t cnt[kThreads / 64][256];
+  constexpr int kPer = kRsItems;                 // items per lane
+  constexpr int kWaveItems = 64 * kPer;          // contiguous items per wave
+  __shared__ uint32_t s_cnt[kThreads / 64][256];  // per-wave digit counts, then per-wave digit bases
+  __shared__ uint32_t s_off[256];                // block-local first slot of each digit
+  __shared__ uint32_t s_gbase[256];              // global first slot of each digit for this block
+  __shared__ uint32_t s_k[kRsBlock];
+  __shared__ uint32_t s_v[kRsBlock];
   __shared__ uint32_t lds[5];
   const int64_t n = live_count(n_dev, n_host);
   const int64_t nb = (n + kRsBlock - 1) / kRsBlock;
@@ -234,43 +244,74 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint32_t* __restr
     digit_base = block_excl_scan<uint32_t>(t, lds, tot);
   }
   for (int64_t lb = blockIdx.x; lb < nb; lb += gridDim.x) {
-  if (tid < radix) run[tid] = digit_base + hist[tid * cols + lb];
-  for (int w = 0; w < kThreads / 64; ++w) cnt[w][tid] = 0;
-  __syncthreads();
-  const int64_t base = lb * kRsBlock + tid;
-  for (int k = 0; k < kRsItems; ++k) {
-    const int64_t i = base + k * kThreads;
-    const bool valid = i < n;
-    const uint32_t key = valid ? kin[i] : 0u;
-    const uint32_t val = valid ? vin[i] : 0u;
-    const uint32_t dig = (key >> shift) & mask;
-    uint64_t peers = __ballot(valid);
-    for (int b = 0; b < bits; ++b) {
-      const bool bit = (dig >> b) & 1u;
-      const uint64_t bal = __ballot(bit);
-      peers &= bit ? bal : ~bal;
-    }
-    if (!valid) peers = 0;
-    const uint32_t rank = static_cast<uint32_t>(__popcll(peers & lt));
-    if (valid && (peers & lt) == 0) cnt[wid][dig] = static_cast<uint32_t>(__popcll(peers));
+    for (int w = 0; w < kThreads / 64; ++w) s_cnt[w][tid] = 0;
+    if (tid < radix) s_gbase[tid] = digit_base + hist[tid * cols + lb];
     __syncthreads();
-    if (valid) {
-      uint32_t off = run[dig] + rank;
-      for (int w = 0; w < wid; ++w) off += cnt[w][dig];
-      kout[off] = key;
-      vout[off] = val;
-    }
-    __syncthreads();
-    if (tid < radix) {
-      uint32_t s = 0;
-      for (int w = 0; w < kThreads / 64; ++w) {
-        s += cnt[w][tid];
-        cnt[w][tid] = 0;
+    // phase 1: wave-local stable ranks
+    const int64_t wbase = lb * kRsBlock + static_cast<int64_t>(wid) * kWaveItems;
+    uint32_t key[kPer], val[kPer], rank[kPer];
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) {
+      const int64_t i = wbase + it * 64 + lane;
+      const bool valid = i < n;
+      key[it] = valid ? kin[i] : 0u;
+      val[it] = valid ? vin[i] : 0u;
+      const uint32_t dig = (key[it] >> shift) & mask;
+      uint64_t peers = __ballot(valid);
+      for (int b = 0; b < bits; ++b) {
+        const bool bit = (dig >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
       }
-      run[tid] += s;
+      uint32_t old = 0;
+      if (valid) old = s_cnt[wid][dig];
+      rank[it] = old + static_cast<uint32_t>(__popcll(peers & lt));
+      __builtin_amdgcn_wave_barrier();
+      if (valid && (peers & lt) == 0) s_cnt[wid][dig] = old + static_cast<uint32_t>(__popcll(peers));
+      __builtin_amdgcn_wave_barrier();
+      if (!valid) rank[it] = 0xffffffffu;
     }
     __syncthreads();
-  }
+    // phase 2: per digit, combine the waves and scan over digits
+    {
+      uint32_t c[kThreads / 64], tot = 0;
+      for (int w = 0; w < kThreads / 64; ++w) {
+        c[w] = tid < radix ? s_cnt[w][tid] : 0u;
+        tot += c[w];
+      }
+      uint32_t all;
+      const uint32_t off = block_excl_scan<uint32_t>(tot, lds, all);
+      if (tid < radix) {
+        s_off[tid] = off;
+        uint32_t run = off;
+        for (int w = 0; w < kThreads / 64; ++w) {
+          s_cnt[w][tid] = run;
+          run += c[w];
+        }
+      }
+    }
+    __syncthreads();
+    // phase 3: stage locally sorted
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) {
+      if (rank[it] != 0xffffffffu) {
+        const uint32_t dig = (key[it] >> shift) & mask;
+        const uint32_t p = s_cnt[wid][dig] + rank[it];
+        s_k[p] = key[it];
+        s_v[p] = val[it];
+      }
+    }
+    __syncthreads();
+    // phase 4: coalesced runs out
+    const int64_t live = min(static_cast<int64_t>(kRsBlock), n - lb * kRsBlock);
+    for (int p = tid; p < live; p += kThreads) {
+      const uint32_t k = s_k[p];
+      const uint32_t dig = (k >> shift) & mask;
+      const uint32_t o = s_gbase[dig] + (static_cast<uint32_t>(p) - s_off[dig]);
+      kout[o] = k;
+      vout[o] = s_v[p];
+    }
+    __syncthreads();
   }
 }
 
@@ -305,7 +346,7 @@ __global__ void __launch_bounds__(kThreads) k_tile_offsets(const uint32_t* __res
                                                            const uint32_t* n_dev, int64_t n_host,
                                                            const unsigned long long* __restrict__ partials,
                                                            const uint32_t* __restrict__ counters,
-                                                           uint32_t* offsets) {
+                                                           uint32_t* offsets, uint32_t* first) {
   __shared__ unsigned long long lds[5];
   if (counters[2]) return;  // over capacity: offsets would not fit 32 bits, nothing is emitted
   const int64_t n = live_count(n_dev, n_host);
@@ -322,7 +363,10 @@ __global__ void __launch_bounds__(kThreads) k_tile_offsets(const uint32_t* __res
   unsigned long long r = block_excl_scan<unsigned long long>(sum, lds, tot) + partials[blockIdx.x];
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) offsets[base + k] = static_cast<uint32_t>(r);
+    if (base + k < n) {
+      offsets[base + k] = static_cast<uint32_t>(r);
+      if (first) first[order[base + k]] = static_cast<uint32_t>(r);
+    }
     r += c[k];
   }
 }
@@ -527,7 +571,7 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
     StageScope sc(PVG_STAGE_SCAN_EMIT, s);
     const unsigned nbv = static_cast<unsigned>(cdiv(vis_grid, kScanBlock));
     hipLaunchKernelGGL(k_tile_offsets, dim3(nbv), dim3(kThreads), 0, s, order, geom.tiles, counters + 1, n,
-                       partials, counters, offsets);
+                       partials, counters, offsets, bins->first);
     const unsigned nbe = static_cast<unsigned>(std::min(kMaxGrid, cdiv(m_grid, kEmitChunk)));
     hipLaunchKernelGGL(k_emit, dim3(nbe), dim3(kThreads), 0, s, vs, order, geom.xy, geom.radius, offsets, counters,
                        bins->keys + start * cap, bins->vals + start * cap);

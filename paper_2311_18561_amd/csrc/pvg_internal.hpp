@@ -123,9 +123,12 @@ hipError_t launch_preprocess_bwd(const ViewSet& vs, const Geom& geom, const floa
                                  const pvg_gaussians_grad& grad, int accumulate, hipStream_t s);
 hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals,
                              const uint32_t* ranges, hipStream_t s);
+// adjoint of compositing: per-(Gaussian, tile) records, then their per-Gaussian sums into g2d
 hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals,
-                             const uint32_t* ranges, const float* dL_dimg_base, float* g2d,
-                             hipStream_t s);
+                             const uint32_t* ranges, const uint32_t* first, float* rec,
+                             unsigned long long* cut, float* g2d, hipStream_t s);
+// scratch of pvg_render_bwd: g2d [n][12] | rec [capacity][9] | cut [tiles] (u64)
+size_t bwd_scratch_bytes(int64_t n, int64_t tiles, int64_t capacity, size_t* off_rec, size_t* off_cut);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 

@@ -10,13 +10,17 @@
 //
 // The adjoint walks the list backwards from the wave's last contributor,
 // recovering each pixel's transmittance by division, sums the four pixels'
-// screen-space gradients per lane, reduces them across the wave and issues one
-// set of 9 global atomics per (Gaussian, tile).
+// screen-space gradients per lane and reduces them across the wave.  Each
+// (Gaussian, tile) pair's nine sums are stored, without atomics, at the pair's
+// index in emission order (a Gaussian's pairs are contiguous there); a gather
+// kernel then adds each Gaussian's pairs.  Device-scope float atomics resolve
+// at the memory side on this chip and cost three times the rest of the
+// kernel, and the atomic-free sums are bitwise reproducible.
 //
 // Tiles are assigned so that each of the eight XCDs (which receive workgroups
 // round-robin) works on one contiguous band of tiles, keeping the Gaussians
 // shared by neighbouring tiles in that XCD's L2.
-#include "pvg_internal.hpp"
+#include "pvg_math.hpp"
 
 namespace pvg {
 
@@ -213,8 +217,9 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
 
 template <bool kCount>
 __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const uint32_t* __restrict__ vals,
-                                                   const uint32_t* __restrict__ ranges, float* g2d,
-                                                   unsigned long long* pair_counter) {
+                                                   const uint32_t* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ first, float* rec,
+                                                   unsigned long long* cut, unsigned long long* pair_counter) {
   __shared__ float2 s_xy[64];
   __shared__ float4 s_co[64];
   __shared__ float4 s_rgb[64];  // rgb and the 0-based list position (as int bits)
@@ -258,6 +263,16 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const 
   lmax = wave_max(lmax);
   const uint32_t start = ranges[2 * tile];
   lmax = min(lmax, static_cast<int>(ranges[2 * tile + 1] - start));  // never read past the tile's list
+  if (lane == 0) {
+    // (depth, index) key of the last list entry this tile visits: the gather
+    // kernel reads a pair's record only if its key is not above it
+    unsigned long long key = 0ull;
+    if (lmax > 0) {
+      const uint32_t gl = vals[start + lmax - 1];
+      key = (static_cast<unsigned long long>(__float_as_uint(geom.depth[gl])) << 32) | gl;
+    }
+    cut[tile] = key;
+  }
   long long evaluated = 0;
   for (int hi = lmax; hi > 0; hi -= 64) {
     const int lo = max(0, hi - 64);
@@ -336,10 +351,16 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const 
       if (lane == 0) s_any[j] = wany ? 1 : 0;
     }
     __syncthreads();
-    if (lane < cnt && s_any[lane]) {
-      float* dst = g2d + static_cast<int64_t>(kG2DStride) * s_g[lane];
+    if (keep) {
+      // record of this (Gaussian, tile) pair at its emission-order index
+      const int slot = __popcll(km & lt);
+      int32_t rect[4];
+      tile_rect(m.x, m.y, geom.radius[g], v.GX, v.GY, rect);
+      const uint32_t e = first[g] + static_cast<uint32_t>((ty - rect[1]) * (rect[2] - rect[0]) + (tx - rect[0]));
+      float* dst = rec + 9 * static_cast<int64_t>(e);
+      const bool has = s_any[slot] != 0;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) atomicAdd(dst + q, s_acc[lane][q]);
+      for (int q = 0; q < 9; ++q) dst[q] = has ? s_acc[slot][q] : 0.0f;
     }
     __syncthreads();
   }
@@ -348,6 +369,80 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const 
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
     if (lane == 0) atomicAdd(pair_counter, static_cast<unsigned long long>(e));
+  }
+}
+
+// Sum of one Gaussian's stored (Gaussian, tile) records over the tiles
+// q0, q0 + step, ... of its rectangle, skipping tiles the adjoint did not
+// reach (key above the tile's cut) and tiles it culled (same test).
+__device__ __forceinline__ void gather_pairs(const ViewSet& vs, const Geom& geom, uint32_t g, uint32_t q0,
+                                             uint32_t step, const uint32_t* __restrict__ first,
+                                             const float* __restrict__ rec,
+                                             const unsigned long long* __restrict__ cut, float acc[9]) {
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
+  const View& v = view_at(vs, view_of_gauss(vs, g));
+  const float2 m = reinterpret_cast<const float2*>(geom.xy)[g];
+  const float4 co = reinterpret_cast<const float4*>(geom.conic_op)[g];
+  int32_t rect[4];
+  tile_rect(m.x, m.y, geom.radius[g], v.GX, v.GY, rect);
+  const uint32_t w = static_cast<uint32_t>(rect[2] - rect[0]);
+  const uint32_t n = w * static_cast<uint32_t>(rect[3] - rect[1]);
+  const unsigned long long key = (static_cast<unsigned long long>(__float_as_uint(geom.depth[g])) << 32) | g;
+  const uint32_t e0 = first[g];
+  for (uint32_t q = q0; q < n; q += step) {
+    const uint32_t dy = q / w, dx = q - dy * w;
+    const int tx = rect[0] + static_cast<int>(dx), ty = rect[1] + static_cast<int>(dy);
+    const int64_t t = v.tile_off + static_cast<int64_t>(ty) * v.GX + tx;
+    if (key > cut[t]) continue;
+    const float X0 = static_cast<float>(tx * kTile), Y0 = static_cast<float>(ty * kTile);
+    const float X1 = static_cast<float>(min(v.W, (tx + 1) * kTile) - 1);
+    const float Y1 = static_cast<float>(min(v.H, (ty + 1) * kTile) - 1);
+    if (!tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1)) continue;
+    const float* r = rec + 9 * static_cast<int64_t>(e0 + q);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] += r[c];
+  }
+}
+
+constexpr uint32_t kShortRect = 16;  // Gaussians with more tiles are gathered by a whole wave
+
+__global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, const uint32_t* __restrict__ first,
+                                                     const float* __restrict__ rec,
+                                                     const unsigned long long* __restrict__ cut, float* g2d) {
+  __shared__ uint32_t s_queue[256];
+  __shared__ int s_qn;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) s_qn = 0;
+  __syncthreads();
+  const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + tid;
+  const bool vis = gi < live_gauss(vs) && geom.radius[gi] > 0;
+  const uint32_t nt = vis ? geom.tiles[gi] : 0u;
+  if (vis && nt <= kShortRect) {
+    float acc[9];
+    gather_pairs(vs, geom, static_cast<uint32_t>(gi), 0u, 1u, first, rec, cut, acc);
+    float* dst = g2d + kG2DStride * gi;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dst[c] = acc[c];
+  } else if (vis) {
+    s_queue[atomicAdd(&s_qn, 1)] = static_cast<uint32_t>(gi);
+  }
+  __syncthreads();
+  const int qn = s_qn;
+  for (int qi = wid; qi < qn; qi += 4) {
+    const uint32_t g = s_queue[qi];
+    float acc[9], red[3];
+    gather_pairs(vs, geom, g, static_cast<uint32_t>(lane), 64u, first, rec, cut, acc);
+    wave_sum9(acc, red);
+    if ((lane & 15) == 0) {
+      const int r = lane >> 4;
+      float* dst = g2d + kG2DStride * static_cast<int64_t>(g);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int q = 4 * k + 2 * (r & 1) + (r >> 1);
+        if (q < 9) dst[q] = red[k];
+      }
+    }
   }
 }
 
@@ -367,18 +462,26 @@ hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t
 }
 
 hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals, const uint32_t* ranges,
-                             const float* dL_dimg_base, float* g2d, hipStream_t s) {
-  (void)dL_dimg_base;
+                             const uint32_t* first, float* rec, unsigned long long* cut, float* g2d,
+                             hipStream_t s) {
   if (vs.total_tiles == 0) return hipSuccess;
-  StageScope scope(PVG_STAGE_RENDER_BWD, s);
-  const int64_t grid = ((vs.total_tiles + 7) / 8) * 8;
-  unsigned long long* cnt = profile_work_counter(PVG_STAGE_RENDER_BWD);
-  if (cnt)
-    hipLaunchKernelGGL(k_render_bwd<true>, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals, ranges,
-                       g2d, cnt);
-  else
-    hipLaunchKernelGGL(k_render_bwd<false>, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals, ranges,
-                       g2d, cnt);
+  {
+    StageScope scope(PVG_STAGE_RENDER_BWD, s);
+    const int64_t grid = ((vs.total_tiles + 7) / 8) * 8;
+    unsigned long long* cnt = profile_work_counter(PVG_STAGE_RENDER_BWD);
+    if (cnt)
+      hipLaunchKernelGGL(k_render_bwd<true>, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals,
+                         ranges, first, rec, cut, cnt);
+    else
+      hipLaunchKernelGGL(k_render_bwd<false>, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals,
+                         ranges, first, rec, cut, cnt);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (vs.total_gauss == 0) return hipSuccess;
+  StageScope scope(PVG_STAGE_GRAD_GATHER, s);
+  hipLaunchKernelGGL(k_grad_gather, dim3(static_cast<unsigned>((vs.total_gauss + 255) / 256)), dim3(256), 0, s, vs,
+                     geom, first, rec, cut, g2d);
   return hipGetLastError();
 }
 

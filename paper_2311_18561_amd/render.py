@@ -109,12 +109,13 @@ class Geom:
 class Bins:
     """Sorted tile instances (device tensors) and their ctypes view."""
 
-    def __init__(self, capacity, num_tiles, device):
+    def __init__(self, capacity, num_tiles, device, n=0):
         self.capacity = capacity
         self.keys = torch.empty(2 * max(capacity, 1), dtype=torch.int32, device=device)
         self.vals = torch.empty(2 * max(capacity, 1), dtype=torch.int32, device=device)
         self.ranges = torch.empty((num_tiles, 2), dtype=torch.int32, device=device)
         self.counters = torch.empty(4, dtype=torch.int32, device=device)
+        self.first = torch.empty(max(n, 1), dtype=torch.int32, device=device)
         self.num_instances = -1
         self.num_visible = -1
 
@@ -123,6 +124,7 @@ class Bins:
         b.capacity = self.capacity
         b.keys, b.vals = self.keys.data_ptr(), self.vals.data_ptr()
         b.ranges, b.counters = self.ranges.data_ptr(), self.counters.data_ptr()
+        b.first = self.first.data_ptr()
         return b
 
 
@@ -150,7 +152,7 @@ def bin_sort(geom: Geom, cam: L.Camera, capacity: int | None = None) -> Bins:
     gs = geom.struct()
     for _ in range(3):
         ws = workspace(geom.n, cam.width, cam.height, cap)
-        bins = Bins(cap, int(ws.num_tiles), dev)
+        bins = Bins(cap, int(ws.num_tiles), dev, geom.n)
         tmp = torch.empty(max(int(ws.bin_tmp_bytes), 1), dtype=torch.uint8, device=dev)
         bs = bins.struct()
         st = lib.pvg_bin_sort(C.byref(gs), C.byref(cam), C.byref(bs), _p(tmp), int(ws.bin_tmp_bytes), 1,
@@ -186,7 +188,7 @@ def render_bwd(params, n, degree, cam, frame, geom, bins, final_T, n_contrib, dL
     gg = L.GaussiansGrad()
     for name, t in zip(FIELDS, grads):
         setattr(gg, name, t.data_ptr())
-    ws = workspace(n, cam.width, cam.height, 0)
+    ws = workspace(n, cam.width, cam.height, bins.capacity)
     tmp = torch.empty(max(int(ws.bwd_tmp_bytes), 1), dtype=torch.uint8, device=dev)
     gs, bs = geom.struct(), bins.struct()
     dL = dL_dimg.contiguous()

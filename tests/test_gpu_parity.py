@@ -197,7 +197,7 @@ def test_capacity_handling():
     M = bins.num_instances
     c = pvg.camera_struct(cam)
     from paper_2311_18561_amd.render import Bins, _p, _stream_handle, workspace
-    small = Bins(16, bins.ranges.shape[0], params[0].device)
+    small = Bins(16, bins.ranges.shape[0], params[0].device, geom.n)
     ws = workspace(geom.n, cam["width"], cam["height"], 16)
     tmp = torch.empty(int(ws.bin_tmp_bytes), dtype=torch.uint8, device="cuda")
     bs = small.struct()
