@@ -46,8 +46,10 @@ def parse():
     return ap.parse_args()
 
 
-def stage_bytes(stage, n, n_vis, M, K, tiles, tile_passes):
-    """Algorithmic HBM bytes of one invocation of a stage."""
+def stage_bytes(stage, n, n_vis, M, Lst, visited, K, tiles, tile_passes):
+    """Algorithmic HBM bytes of one invocation of a stage.  M: rectangle
+    instances, Lst: listed (culled) instances, visited: (Gaussian, tile)
+    records the adjoint writes and the gather reads."""
     if stage == "preprocess":
         return n * (68 + 12) + n_vis * (12 * K + 36)
     if stage == "compact":
@@ -55,14 +57,49 @@ def stage_bytes(stage, n, n_vis, M, K, tiles, tile_passes):
     if stage == "depth_sort":
         return 4 * 16 * n_vis
     if stage == "scan_emit":
-        return n_vis * 16 + M * 8
+        # tile counts and offsets, each owner's record read by the count and
+        # the write pass, and the listed instances written
+        return n_vis * 16 + 2 * n_vis * 36 + Lst * 8
     if stage == "tile_sort":
-        return tile_passes * 16 * M
+        return tile_passes * 16 * Lst
     if stage == "ranges":
-        return M * 4 + tiles * 8
+        return Lst * 4 + tiles * 8
+    if stage == "grad_gather":
+        # per visible Gaussian its record (40 B) in and nine sums out, the cut keys, the visited records
+        return n * 4 + n_vis * (40 + 36) + tiles * 8 + visited * 36
     if stage == "preprocess_bwd":
         return n * (4 + (17 + 3 * K) * 4) + n_vis * (36 + 68 + 12 * K)
     return 0
+
+
+# stages that are one kernel each (the roofline is reported for the dominant one)
+SINGLE_KERNEL = {"preprocess": "k_preprocess", "render_fwd": "k_render_fwd", "render_bwd": "k_render_bwd",
+                 "grad_gather": "k_grad_gather", "preprocess_bwd": "k_preprocess_bwd"}
+KERNEL_SOURCES = ("render.hip", "preprocess.hip", "pvg_math.hpp", "pvg_internal.hpp")
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_18561_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, scaled by the plain-copy calibration; None when there is none or
+    when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_1M_1920x1280_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != kernel_source_digest():
+        return None
+    return (rec["fetch_kib_per_dispatch"] * 1024 * rec["fetch_scale"]
+            + rec["write_kib_per_dispatch"] * 1024 * rec["write_scale"])
 
 
 def cpu_baseline(cfg, budget_s=20.0):
@@ -101,16 +138,19 @@ def cpu_baseline(cfg, budget_s=20.0):
 
 
 SERVE_SCENES = ((500_000, 30), (1_000_000, 31), (2_000_000, 32), (3_000_000, 33))
+SERVE_RATES = ((200.0, 3), (1200.0, 4))  # (requests per second, trace seed)
 
 
-def serve_bench(seconds: float, warm: float = 1.0):
+def serve_bench(seconds: float, warm: float = 1.0, high_seconds: float = 3.0):
     """The serving workload: four resident scenes (0.5M, 1M, 2M, 3M Gaussians,
-    degree 3, driving-path layout), a Poisson stream of 200 requests/s, each a
+    degree 3, driving-path layout), Poisson request streams, each request a
     random scene, a camera on the 100 m path (yaw in [-45, 45] degrees), t in
-    [0, 1] and a resolution from {640x480, 960x640, 1920x1280}.  Replayed open
-    loop (arrival times honoured) against the batched server and against the
-    same server restricted to one request per launch and no overlap; then as a
-    burst (all requests queued at once) for the saturation throughput."""
+    [0, 1] and a resolution from {640x480, 960x640, 1920x1280}.  Each stream is
+    replayed open loop (arrival times honoured; latency = result on the host -
+    scheduled arrival) against the batched server and against the same server
+    restricted to one request per launch and no overlap: at 200 requests/s
+    and at a rate above what one-at-a-time service sustains.  Then the 200/s
+    stream as a burst (all queued at once) gives the saturation throughput."""
     import threading
 
     import torch
@@ -123,17 +163,15 @@ def serve_bench(seconds: float, warm: float = 1.0):
     for n, seed in SERVE_SCENES:
         sc = gen.make_scene(n, seed, sh_degree=3, layout="path")
         scenes.append([torch.from_numpy(sc[f]).cuda() for f in pvg.FIELDS])
-    trace = gen.make_trace(seed=3, rate=200.0, duration=seconds)
-    pool = {}
-    for r in trace:
-        cam = r["camera"]
-        key = (cam["width"], cam["height"])
-        pool.setdefault(key, [])
-    bufs = {k: [torch.empty((3, k[1], k[0]), dtype=torch.float32, device="cuda") for _ in range(96)]
-            for k in pool}
+    traces = {rate: gen.make_trace(seed=seed, rate=rate, duration=seconds if rate <= 200.0 else high_seconds)
+              for rate, seed in SERVE_RATES}
+    keys = sorted({(r["camera"]["width"], r["camera"]["height"]) for tr in traces.values() for r in tr})
+    bufs = {k: [torch.empty((3, k[1], k[0]), dtype=torch.float32, device="cuda") for _ in range(192)]
+            for k in keys}
 
-    def replay(srv, sids, open_loop):
+    def replay(srv, sids, trace, open_loop):
         tickets = [None] * len(trace)
+        arrival_ns = [0] * len(trace)
         owner = {k: [None] * len(v) for k, v in bufs.items()}
         nxt = {k: 0 for k in bufs}
         done = threading.Event()
@@ -148,7 +186,7 @@ def serve_bench(seconds: float, warm: float = 1.0):
 
         th = threading.Thread(target=waiter)
         th.start()
-        t0 = time.perf_counter()
+        t0 = time.monotonic_ns()
         for i, r in enumerate(trace):
             cam = r["camera"]
             key = (cam["width"], cam["height"])
@@ -160,51 +198,60 @@ def serve_bench(seconds: float, warm: float = 1.0):
                     time.sleep(0.0002)
             owner[key][slot] = i
             if open_loop:
-                delay = r["arrival"] - (time.perf_counter() - t0)
+                arrival_ns[i] = t0 + int(r["arrival"] * 1e9)
+                delay = (arrival_ns[i] - time.monotonic_ns()) * 1e-9
                 if delay > 0:
                     time.sleep(delay)
             tickets[i] = srv.submit(sids[r["scene"]], cam, r["t"], bufs[key][slot])
+            if not open_loop:
+                arrival_ns[i] = time.monotonic_ns()
         done.wait()
         th.join()
-        return results
+        return results, arrival_ns
 
-    def summarize(results, skip_s):
+    def summarize(trace, results, arrival_ns, skip_s):
         lat = []
         px = 0
-        t_first = min(r.t_submit_ns for r in results)
-        kept = [(r, tr) for r, tr in zip(results, trace) if (r.t_submit_ns - t_first) * 1e-9 >= skip_s]
-        for r, tr in kept:
+        t_first = min(arrival_ns)
+        kept = [(r, tr, a) for r, tr, a in zip(results, trace, arrival_ns) if (a - t_first) * 1e-9 >= skip_s]
+        for r, tr, a in kept:
             assert r.status == 0, r.status
-            lat.append((r.t_done_ns - r.t_submit_ns) * 1e-6)
+            lat.append((r.t_done_ns - a) * 1e-6)
             px += tr["camera"]["width"] * tr["camera"]["height"]
-        span = (max(r.t_done_ns for r, _ in kept) - min(r.t_submit_ns for r, _ in kept)) * 1e-9
+        span = (max(r.t_done_ns for r, _, _ in kept) - min(a for _, _, a in kept)) * 1e-9
         lat.sort()
         pct = lambda q: lat[min(len(lat) - 1, int(q * (len(lat) - 1) + 0.5))]
         return {"requests": len(kept), "p50_ms": pct(0.5), "p99_ms": pct(0.99), "mpix_per_s": px / span / 1e6,
                 "req_per_s": len(kept) / span,
-                "mean_batch": sum(r.batch_size for r, _ in kept) / max(1, len(kept))}
+                "mean_batch": sum(r.batch_size for r, _, _ in kept) / max(1, len(kept))}
 
-    out = {"trace": {"requests": len(trace), "rate_per_s": 200.0, "seconds": seconds, "warmup_s": warm,
-                     "scenes": [n for n, _ in SERVE_SCENES],
+    out = {"trace": {"rates_per_s": [r for r, _ in SERVE_RATES],
+                     "requests": {str(int(r)): len(tr) for r, tr in traces.items()},
+                     "seconds": {str(int(r)): seconds if r <= 200.0 else high_seconds for r, _ in SERVE_RATES},
+                     "warmup_s": warm, "scenes": [n for n, _ in SERVE_SCENES],
                      "resolutions": ["640x480", "960x640", "1920x1280"]}}
     modes = {"batched": dict(max_batch=8, max_inflight=2),
              "one_at_a_time": dict(max_batch=1, max_inflight=1)}
+    base = traces[SERVE_RATES[0][0]]
     for name, kw in modes.items():
         with Server(use_graphs=True, max_batch_gaussians=24_000_000, max_batch_pixels=8 * 1920 * 1280,
                     instance_capacity=(1 << 30) - 1, **kw) as srv:
             sids = [srv.load_scene(p) for p in scenes]
             torch.cuda.synchronize()
-            replay(srv, sids, open_loop=False)  # warm-up: builds the graphs
+            replay(srv, sids, base, open_loop=False)  # warm-up: builds the graphs
             print(f"# serving {name}: warm", file=sys.stderr, flush=True)
-            res = replay(srv, sids, open_loop=True)
-            out[name] = summarize(res, warm)
-            st = srv.stats()
-            out[name]["retries"] = st["retries"]
-            burst = replay(srv, sids, open_loop=False)
-            sat = summarize(burst, 0.0)
+            out[name] = {}
+            for rate, _ in SERVE_RATES:
+                tr = traces[rate]
+                res, arr = replay(srv, sids, tr, open_loop=True)
+                out[name][f"rate_{int(rate)}"] = summarize(tr, res, arr, warm if rate <= 200.0 else 0.5)
+                print(f"# serving {name} @ {rate:.0f}/s: {out[name][f'rate_{int(rate)}']}", file=sys.stderr,
+                      flush=True)
+            res, arr = replay(srv, sids, base, open_loop=False)
+            sat = summarize(base, res, arr, 0.0)
             out[name]["saturation_mpix_per_s"] = sat["mpix_per_s"]
             out[name]["saturation_req_per_s"] = sat["req_per_s"]
-            print(f"# serving {name}: {out[name]}", file=sys.stderr, flush=True)
+            out[name]["retries"] = srv.stats()["retries"]
     return out
 
 
@@ -233,15 +280,14 @@ def main():
     lib = L.load()
     print(f"# workload: N={N} {W}x{H} views={len(cams)} t={t:.4f} dt={dt}", file=sys.stderr, flush=True)
 
+    views = [(cam, t, d) for cam in cams for d in (0.0, dt)]
+    view_targets = [tgt for tgt in targets for _ in (0.0, dt)]
+
     def train_step():
         for p in params:
             p.grad = None
-        loss = None
-        for cam, tgt in zip(cams, targets):
-            for d in (0.0, dt):
-                img = pvg.pvg_render(params, cam, t, d)
-                l1 = (img - tgt).abs().mean()
-                loss = l1 if loss is None else loss + l1
+        imgs = pvg.pvg_render_views(params, views)
+        loss = sum((img - tgt).abs().mean() for img, tgt in zip(imgs, view_targets))
         loss.backward()
         return loss
 
@@ -308,12 +354,18 @@ def main():
     t_fwd = time.perf_counter() - t0
     mpix_fwd = args.steps * len(cams) * W * H / t_fwd / 1e6
 
-    # per-render counts for the byte model
+    # per-render counts for the byte model (the middle camera)
     img, T, nc, geom, bins = pvg.render(params, cams[1], t)
-    M, n_vis = bins.num_instances, bins.num_visible
-    tiles = ((W + 15) // 16) * ((H + 15) // 16)
+    n_vis = bins.num_visible
+    Lst = bins.num_listed()
+    M = int(geom.tiles.long().clamp(min=0).sum().item())  # rectangle instances
+    GXt, GYt = (W + 15) // 16, (H + 15) // 16
+    tiles = GXt * GYt
+    rng = bins.ranges.long()
+    lmax = torch.nn.functional.pad(nc, (0, GXt * 16 - W, 0, GYt * 16 - H)).reshape(GYt, 16, GXt, 16)
+    lmax = lmax.amax(dim=(1, 3)).reshape(-1).long()
+    visited = int(torch.minimum(lmax, rng[:, 1] - rng[:, 0]).sum().item())
     tile_passes = (max(1, (tiles - 1).bit_length()) + 7) // 8
-    per_step_calls = {}
     table = {}
     for name, st in stages.items():
         if st["calls"] == 0:
@@ -326,20 +378,21 @@ def main():
             row.update(bound="alu", pairs_per_call=pairs,
                        tflops=pairs * FLOPS_PER_PAIR[name] / (per_launch_ms * 1e-3) / 1e12)
         else:
-            b = stage_bytes(name, N, n_vis, M, K, tiles, tile_passes)
+            b = stage_bytes(name, N, n_vis, M, Lst, visited, K, tiles, tile_passes)
             row.update(bound="hbm", bytes_per_call=b, gbs=b / (per_launch_ms * 1e-3) / 1e9)
         table[name] = row
-        per_step_calls[name] = row["calls_per_step"]
-    dom = max(table, key=lambda k: table[k]["ms_per_step"])
+    dom = max((k for k in table if k in SINGLE_KERNEL), key=lambda k: table[k]["ms_per_step"])
     d = table[dom]
+    kernel = SINGLE_KERNEL[dom]
+    traffic = measured_traffic(kernel)
     if d["bound"] == "alu":
-        roof = {"bound": "alu", "kernel": dom, "achieved": d["tflops"], "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": d["tflops"] / FP32_PEAK_TFLOPS, "traffic": None,
+        roof = {"bound": "alu", "kernel": kernel, "achieved": d["tflops"], "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": d["tflops"] / FP32_PEAK_TFLOPS, "traffic": traffic,
                 "per_launch": {"pairs": d["pairs_per_call"], "flops_per_pair": FLOPS_PER_PAIR[dom],
                                "avg_ms": d["ms_per_call"]}}
     else:
-        roof = {"bound": "hbm", "kernel": dom, "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": None,
+        roof = {"bound": "hbm", "kernel": kernel, "achieved": d["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": d["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                 "per_launch": {"bytes": d["bytes_per_call"], "avg_ms": d["ms_per_call"]}}
 
     out = {
@@ -358,7 +411,7 @@ def main():
         "config": {"workload": "pvg-train-step 1M Gaussians SH3 1920x1280, 3 cameras x {H(t), H^(t+0.05)}",
                    "gaussians": N, "width": W, "height": H, "views_per_step": 2 * len(cams)},
         "mpix_per_s_fwd": mpix_fwd,
-        "instances_per_render": M,
+        "instances_per_render": {"rectangle": M, "listed": Lst, "adjoint_records": visited},
         "visible_per_render": n_vis,
         "roofline": roof,
         "stages": table,

@@ -92,7 +92,7 @@ typedef struct pvg_camera { /* host struct, passed by pointer */
   float R[9];               /* world -> camera rotation, row-major */
   float T[3];               /* world -> camera translation */
   float fx, fy, cx, cy;     /* pinhole intrinsics in pixels, fx, fy > 0 */
-  int32_t width, height;    /* image size in pixels, > 0 (any size; partial tiles allowed) */
+  int32_t width, height;    /* image size in pixels, 1 .. 65535 (partial tiles allowed) */
   float znear;              /* Gaussians with camera z <= znear are culled */
 } pvg_camera;
 
@@ -121,11 +121,26 @@ typedef struct pvg_bins {
   uint32_t* keys;       /* [2][capacity] tile id per instance (double buffer) */
   uint32_t* vals;       /* [2][capacity] Gaussian index; sorted result in vals[0 .. M) */
   uint32_t* ranges;     /* [tiles][2] [first, last + 1) of each tile in vals */
-  uint32_t* counters;   /* [4] device: M, visible count, overflow flag, reserved */
+  uint32_t* counters;   /* [4] device: listed instances, visible count, overflow flag,
+                           the count checked against the capacity (saturated to 2^32 - 1) */
   uint32_t* first;      /* [n] optional (may be NULL): index, in emission order, of each visible
                            Gaussian's first instance; pvg_render_bwd needs it */
-  int64_t num_instances;/* host output of a synchronous count (sync_count = 1) */
+  int64_t num_instances;/* host output of a synchronous count (sync_count = 1): listed instances */
   int64_t num_visible;  /* host output of a synchronous count */
+  int32_t tile_cull;    /* 0: one instance per tile of each rectangle (Sec. 3.1 as in 3D Gaussian
+                           splatting); 1: only the tiles where the Gaussian can reach alpha >= 1/255
+                           at some pixel (per tile row, the columns meeting the x-extent of the
+                           alpha = 1/255 ellipse, widened for rounding), which leaves every image
+                           and gradient unchanged and shortens the lists; n_contrib then counts
+                           positions in the shorter lists and `first` indexes listed instances.
+                           The capacity bounds the listed instances and, with culling, also the
+                           rectangle rows (16 bytes of bin_sort scratch each). */
+  int32_t reserved;
+  uint32_t* rows;       /* [capacity][2] optional (tile_cull = 1): per rectangle row of each
+                           visible Gaussian, (its reached tiles in earlier rows, first reached
+                           column | count << 16); pvg_render_bwd needs it with tile_cull = 1 */
+  uint32_t* row_base;   /* [n] optional (tile_cull = 1): index into rows of grid row 0 of each
+                           visible Gaussian, modulo 2^32; pvg_render_bwd needs it with tile_cull = 1 */
 } pvg_bins;
 
 typedef struct pvg_ws_sizes {

@@ -12,11 +12,14 @@ from ._lib import PVGError, load  # noqa: F401
 from .render import (  # noqa: F401
     FIELDS,
     PVGRender,
+    PVGRenderViews,
     bin_sort,
+    bin_sort_nosync,
     camera_struct,
     frame_struct,
     preprocess,
     pvg_render,
+    pvg_render_views,
     render,
     render_bwd,
     render_fwd,

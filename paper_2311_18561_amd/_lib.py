@@ -54,7 +54,8 @@ class Geom(C.Structure):
 
 class Bins(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("keys", vp), ("vals", vp), ("ranges", vp), ("counters", vp),
-                ("first", vp), ("num_instances", C.c_int64), ("num_visible", C.c_int64)]
+                ("first", vp), ("num_instances", C.c_int64), ("num_visible", C.c_int64), ("tile_cull", C.c_int32),
+                ("reserved", C.c_int32), ("rows", vp), ("row_base", vp)]
 
 
 class WsSizes(C.Structure):

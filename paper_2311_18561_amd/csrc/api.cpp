@@ -101,7 +101,7 @@ bool check_gaussians(const pvg_gaussians* g) {
 bool check_camera(const pvg_camera* c) {
   if (!c) { set_error("camera is null"); return false; }
   if (c->width <= 0 || c->height <= 0) { set_error("image size %d x %d is not positive", c->width, c->height); return false; }
-  if (c->width > 65535 * kTile || c->height > 65535 * kTile) { set_error("image size too large"); return false; }
+  if (c->width > 65535 || c->height > 65535) { set_error("image size above 65535 pixels"); return false; }
   if (!(c->fx > 0.0f) || !(c->fy > 0.0f)) { set_error("focal length must be positive"); return false; }
   return true;
 }
@@ -129,6 +129,7 @@ static bool check_bins(const pvg_bins* b) {
     set_error("a bins array is null");
     return false;
   }
+  if (b->tile_cull != 0 && b->tile_cull != 1) { set_error("tile_cull must be 0 or 1"); return false; }
   return true;
 }
 
@@ -230,7 +231,7 @@ int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera*
   v.img = img;
   v.final_T = final_T;
   v.n_contrib = n_contrib;
-  PVG_HIP(launch_render_fwd(single(v, geom->n), to_geom(geom), bins->vals, bins->ranges,
+  PVG_HIP(launch_render_fwd(single(v, geom->n), to_geom(geom), bins->vals, bins->ranges, bins->tile_cull != 0,
                             static_cast<hipStream_t>(stream)));
   return PVG_OK;
 }
@@ -251,6 +252,10 @@ int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_fram
     set_error("bins.first is null: the adjoint needs each Gaussian's first instance index");
     return PVG_ERR_INVALID;
   }
+  if (g->n > 0 && bins->tile_cull && (!bins->rows || !bins->row_base)) {
+    set_error("bins.rows / bins.row_base are null: the adjoint of culled lists needs the row records");
+    return PVG_ERR_INVALID;
+  }
   size_t off_rec = 0, off_cut = 0;
   const size_t need = bwd_scratch_bytes(g->n, tiles_of(cam), bins->capacity, &off_rec, &off_cut);
   if (!tmp || tmp_bytes < need) {
@@ -267,7 +272,9 @@ int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_fram
   float* g2d = reinterpret_cast<float*>(base);
   float* rec = reinterpret_cast<float*>(base + off_rec);
   unsigned long long* cut = reinterpret_cast<unsigned long long*>(base + off_cut);
-  PVG_HIP(launch_render_bwd(vs, to_geom(geom), bins->vals, bins->ranges, bins->first, rec, cut, g2d, s));
+  const Lists lists{bins->vals, bins->ranges, bins->first, bins->tile_cull != 0,
+                    reinterpret_cast<const uint2*>(bins->rows), bins->row_base};
+  PVG_HIP(launch_render_bwd(vs, to_geom(geom), lists, rec, cut, g2d, s));
   PVG_HIP(launch_preprocess_bwd(vs, to_geom(geom), g2d, *grad, accumulate, s));
   return PVG_OK;
 }

@@ -15,13 +15,21 @@
 // equals a full sort of (tile, depth, index) keys, while the passes over the
 // instance array move 8 bytes per instance instead of 12.
 //
+// With tile culling on, step 3 lists a Gaussian only in the tiles it can
+// reach (alpha >= 1/255 at some pixel).  Those form one column interval per
+// tile row of its rectangle, so the culled emission works on rows: count the
+// rectangle rows, compute every row's interval once (a thread per Gaussian,
+// at most one loop over its rows), scan the interval lengths into instance
+// offsets and write each row's interval (a thread per row).  Fewer instances
+// then reach the tile sort, the ranges and the compositing loops.
+//
 // Every radix pass is the classic three-kernel form: per-block digit
 // histograms in LDS (atomics on LDS counters), an exclusive scan of each
 // digit's row of block counts, and a scatter whose in-block ranks come from
 // wave ballots (lanes with equal digits) and per-wave LDS counters, which keeps
 // the sort stable.  Counts live on the device; kernels sized for a capacity
 // exit early past the live count, so no host synchronisation is needed.
-#include "pvg_internal.hpp"
+#include "pvg_math.hpp"
 
 namespace pvg {
 
@@ -88,14 +96,17 @@ __global__ void __launch_bounds__(kThreads) k_vis_count(const uint32_t* __restri
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-// Exclusive scan of `count` block partials in place (one block).  The total
-// is written to *total_out (a u32 counter); with cap >= 0 it is also checked
-// against the instance capacity: counters[0] = total (or 0 on overflow),
-// counters[2] = overflow flag, counters[3] = total saturated to 32 bits.
+// Exclusive scan of `count` block partials in place (one block), unless
+// *skip is set.  The total goes to *total_out; with cap >= 0 it is checked
+// against the capacity: over it, *total_out = 0 and *over_flag = 1.
+// sat_out (optional) receives the total saturated to 32 bits.
 __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* partials, const uint32_t* count_dev,
                                                         const int64_t* count_dev64, int64_t count_host,
-                                                        int per_block, uint32_t* counters, int which, int64_t cap) {
+                                                        int per_block, uint32_t* total_out, int64_t cap,
+                                                        uint32_t* over_flag, uint32_t* sat_out,
+                                                        const uint32_t* skip) {
   __shared__ unsigned long long wsum[17];
+  if (skip && *skip) return;
   const int64_t items = count_dev64 ? *count_dev64 : live_count(count_dev, count_host);
   const int64_t count = (items + per_block - 1) / per_block;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -121,14 +132,10 @@ __global__ void __launch_bounds__(1024) k_scan_partials(unsigned long long* part
     __syncthreads();
   }
   if (tid == 0) {
-    if (cap < 0) {
-      counters[which] = static_cast<uint32_t>(carry);
-    } else {
-      const bool over = carry > static_cast<unsigned long long>(cap);
-      counters[0] = over ? 0u : static_cast<uint32_t>(carry);
-      counters[2] = over ? 1u : 0u;
-      counters[3] = carry > 0xffffffffull ? 0xffffffffu : static_cast<uint32_t>(carry);
-    }
+    const bool over = cap >= 0 && carry > static_cast<unsigned long long>(cap);
+    *total_out = over ? 0u : static_cast<uint32_t>(carry);
+    if (over) *over_flag = 1u;
+    if (sat_out) *sat_out = carry > 0xffffffffull ? 0xffffffffu : static_cast<uint32_t>(carry);
   }
 }
 
@@ -451,6 +458,169 @@ __global__ void __launch_bounds__(kThreads) k_emit(ViewSet vs, const uint32_t* _
   }
 }
 
+// ------------------------------------------------------------------ step 3 with tile culling
+// Rectangle of Gaussian g (in its view) and the view.
+__device__ __forceinline__ const View& rect_of(const ViewSet& vs, const float* __restrict__ xy,
+                                               const int32_t* __restrict__ radius, uint32_t g, float2& m,
+                                               int32_t rect[4]) {
+  const View& v = view_at(vs, view_of_gauss(vs, g));
+  m = reinterpret_cast<const float2*>(xy)[g];
+  tile_rect(m.x, m.y, radius[g], v.GX, v.GY, rect);
+  return v;
+}
+
+// The row kernels take one visible Gaussian per thread (a row loop is at
+// most one image height of tiles long, and near splats sort first).
+constexpr int kRowBlock = kThreads;
+
+// Block sums of the rectangle row counts in depth order.
+__global__ void __launch_bounds__(kThreads) k_row_count(ViewSet vs, const uint32_t* __restrict__ order,
+                                                        const float* __restrict__ xy,
+                                                        const int32_t* __restrict__ radius, const uint32_t* n_dev,
+                                                        int64_t n_host, unsigned long long* partials) {
+  __shared__ unsigned long long lds[5];
+  const int64_t n = live_count(n_dev, n_host);
+  if (static_cast<int64_t>(blockIdx.x) * kRowBlock >= n) return;
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kRowBlock + threadIdx.x;
+  unsigned long long c = 0;
+  if (k < n) {
+    float2 m;
+    int32_t rect[4];
+    rect_of(vs, xy, radius, order[k], m, rect);
+    c = static_cast<unsigned long long>(rect[3] - rect[1]);
+  }
+  unsigned long long tot;
+  block_excl_scan<unsigned long long>(c, lds, tot);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// Row records: for each visible Gaussian k (depth order) and each row of its
+// rectangle, rows[i] = (k, first reached column | count << 16, tile row,
+// reached tiles of the Gaussian's earlier rows); lsum[k] = its reached tiles;
+// block sums of lsum.  Optionally the adjoint's copy of each row,
+// brows[i] = (earlier reached tiles, first column | count << 16), and
+// row_base[g] = index of row 0 of the grid (mod 2^32) for Gaussian g.
+__global__ void __launch_bounds__(kThreads) k_row_intervals(ViewSet vs, const uint32_t* __restrict__ order,
+                                                            const float* __restrict__ xy,
+                                                            const float* __restrict__ conic_op,
+                                                            const int32_t* __restrict__ radius,
+                                                            const uint32_t* n_dev, int64_t n_host,
+                                                            const unsigned long long* __restrict__ row_partials,
+                                                            const uint32_t* __restrict__ counters, uint4* rows,
+                                                            uint32_t* lsum, uint2* brows, uint32_t* row_base,
+                                                            unsigned long long* tile_partials) {
+  __shared__ unsigned long long lds[5];
+  if (counters[2]) return;
+  const int64_t n = live_count(n_dev, n_host);
+  if (static_cast<int64_t>(blockIdx.x) * kRowBlock >= n) return;
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kRowBlock + threadIdx.x;
+  uint32_t g = 0;
+  float2 m = make_float2(0.0f, 0.0f);
+  int32_t rect[4] = {0, 0, 0, 0};
+  const View* v = nullptr;
+  if (k < n) {
+    g = order[k];
+    v = &rect_of(vs, xy, radius, g, m, rect);
+  }
+  unsigned long long tot;
+  const unsigned long long r0 =
+      block_excl_scan<unsigned long long>(static_cast<unsigned long long>(rect[3] - rect[1]), lds, tot) +
+      row_partials[blockIdx.x];
+  uint32_t pre = 0;
+  if (k < n) {
+    const float4 co = reinterpret_cast<const float4*>(conic_op)[g];
+    const ReachRows rr = reach_rows_init(m.x, m.y, co.x, co.y, co.z, co.w);
+    if (row_base) row_base[g] = static_cast<uint32_t>(r0) - static_cast<uint32_t>(rect[1]);
+    for (int ty = rect[1]; ty < rect[3]; ++ty) {
+      int lo, hi;
+      reach_row(rr, ty, v->H, rect[0], rect[2], lo, hi);
+      const uint32_t len = hi >= lo ? static_cast<uint32_t>(hi - lo + 1) : 0u;
+      const uint32_t packed = static_cast<uint32_t>(lo) | (len << 16);
+      const unsigned long long i = r0 + static_cast<uint32_t>(ty - rect[1]);
+      rows[i] = make_uint4(static_cast<uint32_t>(k), packed, static_cast<uint32_t>(ty), pre);
+      if (brows) brows[i] = make_uint2(pre, packed);
+      pre += len;
+    }
+    lsum[k] = pre;
+  }
+  block_excl_scan<unsigned long long>(pre, lds, tot);
+  if (threadIdx.x == 0) tile_partials[blockIdx.x] = tot;
+}
+
+// Instance offset of each visible Gaussian: offsets[k], first[g].
+__global__ void __launch_bounds__(kThreads) k_row_offsets(const uint32_t* __restrict__ order, const uint32_t* n_dev,
+                                                          int64_t n_host, const uint32_t* __restrict__ lsum,
+                                                          const unsigned long long* __restrict__ tile_partials,
+                                                          const uint32_t* __restrict__ counters, uint32_t* offsets,
+                                                          uint32_t* first) {
+  __shared__ unsigned long long lds[5];
+  if (counters[2]) return;
+  const int64_t n = live_count(n_dev, n_host);
+  if (static_cast<int64_t>(blockIdx.x) * kRowBlock >= n) return;
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * kRowBlock + threadIdx.x;
+  const uint32_t c = k < n ? lsum[k] : 0u;
+  unsigned long long tot;
+  const unsigned long long e = block_excl_scan<unsigned long long>(c, lds, tot) + tile_partials[blockIdx.x];
+  if (k < n) {
+    offsets[k] = static_cast<uint32_t>(e);
+    if (first) first[order[k]] = static_cast<uint32_t>(e);
+  }
+}
+
+// Each wave takes 64 consecutive rows: their instances are consecutive in
+// the output, so the wave stages the rows in LDS, scans their lengths and
+// then writes the instances 64 at a time (lane j writes instance t + j,
+// locating its row by a binary search of the staged starts).
+__global__ void __launch_bounds__(kThreads) k_emit_rows(ViewSet vs, const uint32_t* __restrict__ order,
+                                                        const uint4* __restrict__ rows,
+                                                        const uint32_t* __restrict__ num_rows,
+                                                        const uint32_t* __restrict__ offsets,
+                                                        const uint32_t* __restrict__ counters, uint32_t* keys,
+                                                        uint32_t* vals) {
+  __shared__ uint32_t s_start[4][64];  // offset of the row's first instance, relative to the wave's first
+  __shared__ uint32_t s_tile[4][64];   // global tile id of the row's first reached tile
+  __shared__ uint32_t s_g[4][64];
+  if (counters[2]) return;
+  const int64_t R = *num_rows;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (kThreads / 64);
+  for (int64_t w0 = (static_cast<int64_t>(blockIdx.x) * (kThreads / 64) + wid) * 64; w0 < R; w0 += waves * 64) {
+    const int64_t i = w0 + lane;
+    uint32_t len = 0, e = 0, tile = 0, g = 0;
+    if (i < R) {
+      const uint4 rec = rows[i];
+      len = rec.y >> 16;
+      g = order[rec.x];
+      e = offsets[rec.x] + rec.w;
+      const View& v = view_at(vs, view_of_gauss(vs, g));
+      tile = static_cast<uint32_t>(v.tile_off + static_cast<int64_t>(rec.z) * v.GX + (rec.y & 0xffffu));
+    }
+    // rows in order are contiguous in the output: base = first row's start
+    const uint32_t base = __shfl(e, 0, 64);
+    uint32_t x = len;  // inclusive scan of the lengths
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    const uint32_t total = __shfl(x, 63, 64);
+    s_start[wid][lane] = x - len;
+    s_tile[wid][lane] = tile;
+    s_g[wid][lane] = g;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t t = lane; t < total; t += 64) {
+      int lo = 0, hi = 63;  // last row whose start <= t (empty rows share the next row's start)
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_start[wid][mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      keys[base + t] = s_tile[wid][lo] + (t - s_start[wid][lo]);
+      vals[base + t] = s_g[wid][lo];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ counters,
                          uint32_t* ranges) {
   const int64_t n = counters[0];
@@ -480,10 +650,14 @@ BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity) {
   p.off_vis_keys = off; off = align256(off + sizeof(uint32_t) * 2 * std::max<int64_t>(n, 1));
   p.off_vis_vals = off; off = align256(off + sizeof(uint32_t) * 2 * std::max<int64_t>(n, 1));
   p.off_offsets = off;  off = align256(off + sizeof(uint32_t) * std::max<int64_t>(n, 1));
-  const int64_t nparts = std::max<int64_t>(1, cdiv(n, kScanBlock));
+  const int64_t nparts = std::max<int64_t>(1, cdiv(n, kThreads));  // blocks of the row kernels (the most)
   p.off_partials = off; off = align256(off + sizeof(unsigned long long) * (nparts + 1));
   p.off_hist = off;     off = align256(off + sizeof(uint32_t) * 256 * p.hist_cols);
   p.off_rowtot = off;   off = align256(off + sizeof(uint32_t) * 256);
+  p.off_partials2 = off; off = align256(off + sizeof(unsigned long long) * (nparts + 1));
+  p.off_rows = off;     off = align256(off + sizeof(uint4) * std::max<int64_t>(capacity, 1));
+  p.off_num_rows = off; off = align256(off + sizeof(uint32_t) * 4);
+  p.off_lsum = off;     off = align256(off + sizeof(uint32_t) * std::max<int64_t>(n, 1));
   p.total = off;
   return p;
 }
@@ -521,8 +695,9 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
     StageScope sc(PVG_STAGE_COMPACT, s);
     const unsigned nb = static_cast<unsigned>(cdiv(n, kScanBlock));
     hipLaunchKernelGGL(k_vis_count, dim3(nb), dim3(kThreads), 0, s, geom.tiles, vs.live, n, partials);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nullptr, vs.live, n, kScanBlock,
-                       counters, 1, int64_t{-1});
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, static_cast<const uint32_t*>(nullptr),
+                       vs.live, n, kScanBlock, counters + 1, int64_t{-1}, static_cast<uint32_t*>(nullptr),
+                       static_cast<uint32_t*>(nullptr), static_cast<const uint32_t*>(nullptr));
     hipLaunchKernelGGL(k_vis_compact, dim3(nb), dim3(kThreads), 0, s, geom.tiles, geom.depth, vs.live, n, partials,
                        vkeys, vvals);
     PVG_HIP(hipGetLastError());
@@ -537,44 +712,78 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
     }
   }
   const uint32_t* order = vvals;  // buffer 0 after an even number of passes
-  // instance offsets in depth order and the capacity check
-  {
+  const bool cull = bins->tile_cull != 0;
+  unsigned long long* partials2 = reinterpret_cast<unsigned long long*>(base + plan.off_partials2);
+  uint4* rows = reinterpret_cast<uint4*>(base + plan.off_rows);
+  uint32_t* num_rows = reinterpret_cast<uint32_t*>(base + plan.off_num_rows);
+  uint32_t* lsum = reinterpret_cast<uint32_t*>(base + plan.off_lsum);
+  const unsigned nbv_max = static_cast<unsigned>(std::max<int64_t>(1, cdiv(n, kScanBlock)));
+  // instance counts in depth order and the capacity check: rectangle tiles, or
+  // (culled) rectangle rows, their reached intervals and the reached tiles
+  if (n > 0) {
     StageScope sc(PVG_STAGE_SCAN_EMIT, s);
-    if (n > 0) {
-      const unsigned nb = static_cast<unsigned>(cdiv(n, kScanBlock));
-      hipLaunchKernelGGL(k_tile_count, dim3(nb), dim3(kThreads), 0, s, order, geom.tiles, counters + 1, n,
+    if (!cull) {
+      hipLaunchKernelGGL(k_tile_count, dim3(nbv_max), dim3(kThreads), 0, s, order, geom.tiles, counters + 1, n,
                          partials);
       hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, counters + 1,
-                         static_cast<const int64_t*>(nullptr), n, kScanBlock, counters, 0, cap);
-      PVG_HIP(hipGetLastError());
+                         static_cast<const int64_t*>(nullptr), n, kScanBlock, counters, cap, counters + 2,
+                         counters + 3, static_cast<const uint32_t*>(nullptr));
+    } else {
+      PVG_HIP(launch_fill_u32(num_rows, 0u, 1, s));
+      const unsigned nbr = static_cast<unsigned>(cdiv(n, kRowBlock));
+      hipLaunchKernelGGL(k_row_count, dim3(nbr), dim3(kThreads), 0, s, vs, order, geom.xy, geom.radius,
+                         counters + 1, n, partials);
+      hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, counters + 1,
+                         static_cast<const int64_t*>(nullptr), n, kRowBlock, num_rows, cap, counters + 2,
+                         counters + 3, static_cast<const uint32_t*>(nullptr));
+      hipLaunchKernelGGL(k_row_intervals, dim3(nbr), dim3(kThreads), 0, s, vs, order, geom.xy, geom.conic_op,
+                         geom.radius, counters + 1, n, partials, counters, rows, lsum,
+                         reinterpret_cast<uint2*>(bins->rows), bins->row_base, partials2);
+      hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials2, counters + 1,
+                         static_cast<const int64_t*>(nullptr), n, kRowBlock, counters, cap, counters + 2,
+                         counters + 3, counters + 2);
     }
+    PVG_HIP(hipGetLastError());
   }
   int64_t m_grid = cap;
   int64_t vis_grid = n;
+  int64_t row_grid = cap;
   if (sync_count) {
-    uint32_t host_counts[4];
+    uint32_t host_counts[4], host_rows = 0;
     PVG_HIP(hipMemcpyAsync(host_counts, counters, sizeof(host_counts), hipMemcpyDeviceToHost, s));
+    if (cull && n > 0) PVG_HIP(hipMemcpyAsync(&host_rows, num_rows, sizeof(host_rows), hipMemcpyDeviceToHost, s));
     PVG_HIP(hipStreamSynchronize(s));
     bins->num_instances = host_counts[3] == 0xffffffffu ? int64_t{0xffffffff} : int64_t{host_counts[3]};
     bins->num_visible = host_counts[1];
     if (host_counts[2]) {
-      set_error("instance capacity %lld is smaller than the %lld instances of this render",
-                static_cast<long long>(cap), static_cast<long long>(bins->num_instances));
+      set_error("instance capacity %lld is smaller than the %lld %s of this render", static_cast<long long>(cap),
+                static_cast<long long>(bins->num_instances),
+                cull && host_rows == 0 ? "rectangle rows" : "instances");
       return PVG_ERR_CAPACITY;
     }
     m_grid = host_counts[0];
     vis_grid = host_counts[1];
+    row_grid = host_rows;
   }
   const int passes = plan.tile_passes;
   const int start = passes & 1;  // so that the last pass lands in buffer 0
   if (n > 0 && vis_grid > 0 && m_grid > 0) {
     StageScope sc(PVG_STAGE_SCAN_EMIT, s);
     const unsigned nbv = static_cast<unsigned>(cdiv(vis_grid, kScanBlock));
-    hipLaunchKernelGGL(k_tile_offsets, dim3(nbv), dim3(kThreads), 0, s, order, geom.tiles, counters + 1, n,
-                       partials, counters, offsets, bins->first);
-    const unsigned nbe = static_cast<unsigned>(std::min(kMaxGrid, cdiv(m_grid, kEmitChunk)));
-    hipLaunchKernelGGL(k_emit, dim3(nbe), dim3(kThreads), 0, s, vs, order, geom.xy, geom.radius, offsets, counters,
-                       bins->keys + start * cap, bins->vals + start * cap);
+    if (!cull) {
+      hipLaunchKernelGGL(k_tile_offsets, dim3(nbv), dim3(kThreads), 0, s, order, geom.tiles, counters + 1, n,
+                         partials, counters, offsets, bins->first);
+      const unsigned nbe = static_cast<unsigned>(std::min(kMaxGrid, cdiv(m_grid, kEmitChunk)));
+      hipLaunchKernelGGL(k_emit, dim3(nbe), dim3(kThreads), 0, s, vs, order, geom.xy, geom.radius, offsets,
+                         counters, bins->keys + start * cap, bins->vals + start * cap);
+    } else {
+      const unsigned nbo = static_cast<unsigned>(cdiv(vis_grid, kRowBlock));
+      hipLaunchKernelGGL(k_row_offsets, dim3(nbo), dim3(kThreads), 0, s, order, counters + 1, n, lsum, partials2,
+                         counters, offsets, bins->first);
+      const unsigned nbe = static_cast<unsigned>(std::min(kMaxGrid, std::max<int64_t>(1, cdiv(row_grid, kThreads))));
+      hipLaunchKernelGGL(k_emit_rows, dim3(nbe), dim3(kThreads), 0, s, vs, order, rows, num_rows, offsets, counters,
+                         bins->keys + start * cap, bins->vals + start * cap);
+    }
     PVG_HIP(hipGetLastError());
   }
   if (passes > 0 && m_grid > 0) {

@@ -121,11 +121,22 @@ unsigned long long* profile_work_counter(int stage);  // device counter, or null
 hipError_t launch_preprocess(const ViewSet& vs, const Geom& geom, hipStream_t s);
 hipError_t launch_preprocess_bwd(const ViewSet& vs, const Geom& geom, const float* g2d,
                                  const pvg_gaussians_grad& grad, int accumulate, hipStream_t s);
+// culled: the lists hold only tiles that pass tile_reachable (the render skips the test)
 hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals,
-                             const uint32_t* ranges, hipStream_t s);
+                             const uint32_t* ranges, bool culled, hipStream_t s);
+// The sorted lists as the adjoint reads them.  Rectangle lists: a pair's
+// record is first[g] + its tile's row-major index in the rectangle.  Culled
+// lists: first[g] + rows[row_base[g] + ty].x + (tx - first reached column).
+struct Lists {
+  const uint32_t* vals;
+  const uint32_t* ranges;
+  const uint32_t* first;
+  bool culled;
+  const uint2* rows;
+  const uint32_t* row_base;
+};
 // adjoint of compositing: per-(Gaussian, tile) records, then their per-Gaussian sums into g2d
-hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals,
-                             const uint32_t* ranges, const uint32_t* first, float* rec,
+hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const Lists& lists, float* rec,
                              unsigned long long* cut, float* g2d, hipStream_t s);
 // scratch of pvg_render_bwd: g2d [n][12] | rec [capacity][9] | cut [tiles] (u64)
 size_t bwd_scratch_bytes(int64_t n, int64_t tiles, int64_t capacity, size_t* off_rec, size_t* off_cut);
@@ -140,7 +151,8 @@ struct BinPlan {
   int tile_bits;         // bits of the global tile id
   int tile_passes;       // radix passes over the tile key
   // scratch carve-up (bytes offsets into tmp)
-  size_t off_vis_keys, off_vis_vals, off_offsets, off_partials, off_hist, off_rowtot, total;
+  size_t off_vis_keys, off_vis_vals, off_offsets, off_partials, off_hist, off_rowtot, off_partials2, off_rows,
+      off_num_rows, off_lsum, total;
   int64_t hist_cols;     // blocks per radix row (max over the passes)
 };
 BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity);

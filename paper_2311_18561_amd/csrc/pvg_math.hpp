@@ -135,6 +135,119 @@ __device__ __forceinline__ void tile_rect(float x, float y, int32_t r, int32_t G
   rect[3] = clamp_tile(((y + rr) + 15.0f) / 16.0f, GY);
 }
 
+// Can a Gaussian reach alpha >= 1/255 at any pixel of the tile?  alpha =
+// min(0.99, o~ G) >= 1/255 needs power >= ln(1 / (255 o~)); power = -q/2 with
+// q the conic's quadratic form, whose minimum over the tile's sample
+// rectangle is exact (interior: 0; else the best of the four edges).  The test
+// keeps a wide margin, and never drops a Gaussian with non-finite values, so a
+// dropped Gaussian is one every pixel of the tile would skip.
+__device__ __forceinline__ bool tile_reachable(float gx, float gy, float A, float B, float C, float op, float X0,
+                                               float X1, float Y0, float Y1) {
+  if (!(isfinite(gx) && isfinite(gy) && isfinite(A) && isfinite(B) && isfinite(C) && isfinite(op))) return true;
+  if (op < kAlphaMin) return false;
+  if (!(A > 0.0f && C > 0.0f)) return true;
+  const float dxl = gx - X1, dxh = gx - X0, dyl = gy - Y1, dyh = gy - Y0;
+  float qmin;
+  if (dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f) {
+    qmin = 0.0f;
+  } else {
+    auto q = [&](float dx, float dy) { return A * dx * dx + 2.0f * B * dx * dy + C * dy * dy; };
+    auto best_dy = [&](float dx) { return fminf(fmaxf(-B * dx / C, dyl), dyh); };
+    auto best_dx = [&](float dy) { return fminf(fmaxf(-B * dy / A, dxl), dxh); };
+    qmin = fminf(fminf(q(dxl, best_dy(dxl)), q(dxh, best_dy(dxh))), fminf(q(best_dx(dyl), dyl), q(best_dx(dyh), dyh)));
+  }
+  const float need = -logf(kAlphaMin / op);  // -power must stay below this
+  return !(0.5f * qmin * 0.999f > need + 0.01f);
+}
+
+// Reachable tiles as one column interval per tile row.  A pixel can take
+// alpha >= 1/255 only where o~ exp(-q/2) >= 1/255, q = d^T Q d the conic's
+// quadratic form at d = mean - pixel, i.e. inside the ellipse q <= 2 ln(255 o~).
+// The ellipse is widened for rounding: the bound gets a 0.1% and an additive
+// margin, and Q is shrunk by k I with k far above the FP32 error of
+// evaluating q (a few ulp of |A| dx^2 + 2 |B dx dy| + |C| dy^2); a conic too
+// close to singular for that keeps its whole rectangle.  Within tile row ty
+// the ellipse's x-extent over the row's sample band is exact: each horizontal
+// slice is an interval, whose right end is a concave function of dy
+// (maximal at the ellipse's rightmost point) and whose left end is convex.
+struct ReachRows {
+  float gx, gy;
+  float ex, ey;    // largest |dx|, |dy| on the ellipse
+  float dyr;       // dy of the rightmost point (the leftmost is at -dyr)
+  float bA;        // B / A: a horizontal slice at dy is centred at -bA dy
+  float c1, c2;    // its half-width is sqrt(c1 - c2 dy^2)
+  float slack;     // pixels added on both sides for rounding
+  int mode;        // 0: ellipse, 1: every tile of the rectangle, 2: no tile
+};
+
+__device__ __forceinline__ ReachRows reach_rows_init(float gx, float gy, float A, float B, float C, float op) {
+  ReachRows r;
+  r.gx = gx; r.gy = gy;
+  r.ex = r.ey = r.dyr = r.bA = r.c1 = r.c2 = r.slack = 0.0f;
+  r.mode = 0;
+  if (!(isfinite(gx) && isfinite(gy) && isfinite(A) && isfinite(B) && isfinite(C) && isfinite(op))) {
+    r.mode = 1;
+    return r;
+  }
+  if (op < kAlphaMin) {  // alpha <= o~ < 1/255 everywhere
+    r.mode = 2;
+    return r;
+  }
+  const float k = 1e-5f * (fabsf(A) + fabsf(C) + 2.0f * fabsf(B));
+  const float a = A - k, c = C - k;
+  const float det = a * c - B * B;
+  if (!(a > 0.0f && c > 0.0f && det > 0.0f)) {
+    r.mode = 1;
+    return r;
+  }
+  const float need = -logf(kAlphaMin / op);  // alpha >= 1/255 needs q / 2 <= need
+  const float lim = 2.0f * (need + 0.01f) * 1.001f;
+  r.ex = sqrtf(lim * c / det);
+  r.ey = sqrtf(lim * a / det);
+  r.dyr = -B * r.ex / c;
+  r.bA = B / a;
+  r.c1 = lim / a;
+  r.c2 = det / (a * a);
+  r.slack = 0.05f + 2e-5f * (r.ex + fabsf(gx));
+  if (!(isfinite(r.ex) && isfinite(r.ey) && isfinite(r.c1) && isfinite(r.c2))) r.mode = 1;
+  return r;
+}
+
+// Columns [lo, hi] of tile row ty, within the rectangle columns [x0, x1), that
+// the ellipse reaches (lo > hi: none).  H is the image height.
+__device__ __forceinline__ void reach_row(const ReachRows& r, int ty, int H, int x0, int x1, int& lo, int& hi) {
+  lo = x0;
+  hi = x1 - 1;
+  if (r.mode == 1) return;
+  hi = x0 - 1;
+  if (r.mode == 2) return;
+  const float Y0 = static_cast<float>(ty * kTile);
+  const float Y1 = static_cast<float>(min(H, (ty + 1) * kTile) - 1);
+  const float a = fmaxf(r.gy - Y1, -r.ey), b = fminf(r.gy - Y0, r.ey);  // dy band on the ellipse
+  if (!(a <= b)) return;
+  const float ha = __builtin_amdgcn_sqrtf(fmaxf(0.0f, r.c1 - r.c2 * (a * a)));
+  const float hb = __builtin_amdgcn_sqrtf(fmaxf(0.0f, r.c1 - r.c2 * (b * b)));
+  const float ca = -r.bA * a, cb = -r.bA * b;  // slice centres
+  const float dmax = (r.dyr >= a && r.dyr <= b) ? r.ex : fmaxf(ca + ha, cb + hb);
+  const float dmin = (-r.dyr >= a && -r.dyr <= b) ? -r.ex : fminf(ca - ha, cb - hb);
+  const float xl = (r.gx - dmax) - r.slack, xh = (r.gx - dmin) + r.slack;  // sample columns reached
+  // tiles whose sample columns [16 tx, 16 tx + 15] meet [xl, xh]
+  float tl = ceilf((xl - 15.0f) * 0.0625f), th = floorf(xh * 0.0625f);
+  if (!(tl >= static_cast<float>(x0))) tl = static_cast<float>(x0);
+  if (!(th <= static_cast<float>(x1 - 1))) th = static_cast<float>(x1 - 1);
+  if (tl > th) return;
+  lo = static_cast<int>(tl);
+  hi = static_cast<int>(th);
+}
+
+// Sample rectangle [X0, X1] x [Y0, Y1] of tile (tx, ty) in a W x H image.
+__device__ __forceinline__ void tile_bounds(int tx, int ty, int W, int H, float& X0, float& X1, float& Y0, float& Y1) {
+  X0 = static_cast<float>(tx * kTile);
+  Y0 = static_cast<float>(ty * kTile);
+  X1 = static_cast<float>(min(W, (tx + 1) * kTile) - 1);
+  Y1 = static_cast<float>(min(H, (ty + 1) * kTile) - 1);
+}
+
 // Temporal state (Eqs. (6), (7)) and flow translation (Eqs. (10), (12)).
 __device__ __forceinline__ void temporal_state(const View& v, int64_t i, float mr[3], float& op) {
   const Scene& s = v.s;

@@ -86,34 +86,9 @@ __device__ __forceinline__ float pair_power(float dx, float dy, float A, float B
   return -0.5f * (A * (dx * dx) + C * (dy * dy)) - B * (dx * dy);
 }
 
-// Can a Gaussian reach alpha >= 1/255 at any pixel of the tile?  alpha =
-// min(0.99, o~ G) >= 1/255 needs power >= ln(1 / (255 o~)); power = -q/2 with
-// q the conic's quadratic form, whose minimum over the tile's sample
-// rectangle is exact (interior: 0; else the best of the four edges).  The test
-// keeps a wide margin, and never drops a Gaussian with non-finite values, so a
-// dropped Gaussian is one every pixel of the tile would skip.
-__device__ __forceinline__ bool tile_reachable(float gx, float gy, float A, float B, float C, float op, float X0,
-                                               float X1, float Y0, float Y1) {
-  if (!(isfinite(gx) && isfinite(gy) && isfinite(A) && isfinite(B) && isfinite(C) && isfinite(op))) return true;
-  if (op < kAlphaMin) return false;
-  if (!(A > 0.0f && C > 0.0f)) return true;
-  const float dxl = gx - X1, dxh = gx - X0, dyl = gy - Y1, dyh = gy - Y0;
-  float qmin;
-  if (dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f) {
-    qmin = 0.0f;
-  } else {
-    auto q = [&](float dx, float dy) { return A * dx * dx + 2.0f * B * dx * dy + C * dy * dy; };
-    auto best_dy = [&](float dx) { return fminf(fmaxf(-B * dx / C, dyl), dyh); };
-    auto best_dx = [&](float dy) { return fminf(fmaxf(-B * dy / A, dxl), dxh); };
-    qmin = fminf(fminf(q(dxl, best_dy(dxl)), q(dxh, best_dy(dxh))), fminf(q(best_dx(dyl), dyl), q(best_dx(dyh), dyh)));
-  }
-  const float need = -logf(kAlphaMin / op);  // -power must stay below this
-  return !(0.5f * qmin * 0.999f > need + 0.01f);
-}
-
 constexpr int kPix = 4;  // pixels per lane
 
-template <bool kCount>
+template <bool kCount, bool kCulled>
 __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const uint32_t* __restrict__ vals,
                                                    const uint32_t* __restrict__ ranges,
                                                    unsigned long long* pair_counter) {
@@ -130,9 +105,8 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
   const int px = tx * kTile + (lane & 15);
   const int py0 = ty * kTile + (lane >> 4);
   const float fpx = static_cast<float>(px);
-  const float X0 = static_cast<float>(tx * kTile), Y0 = static_cast<float>(ty * kTile);
-  const float X1 = static_cast<float>(min(v.W, (tx + 1) * kTile) - 1);
-  const float Y1 = static_cast<float>(min(v.H, (ty + 1) * kTile) - 1);
+  float X0, X1, Y0, Y1;
+  tile_bounds(tx, ty, v.W, v.H, X0, X1, Y0, Y1);
   const uint64_t lt = (1ull << lane) - 1ull;
   float T[kPix], Cr[kPix], Cg[kPix], Cb[kPix];
   int last[kPix];
@@ -156,7 +130,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
       co = reinterpret_cast<const float4*>(geom.conic_op)[g];
       c = make_float4(geom.rgb[3 * g], geom.rgb[3 * g + 1], geom.rgb[3 * g + 2],
                       __int_as_float(static_cast<int>(idx - start) + 1));
-      keep = tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1);
+      keep = kCulled || tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1);
     }
     const uint64_t km = __ballot(keep);
     if (keep) {
@@ -215,11 +189,12 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
   }
 }
 
-template <bool kCount>
-__global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const uint32_t* __restrict__ vals,
-                                                   const uint32_t* __restrict__ ranges,
-                                                   const uint32_t* __restrict__ first, float* rec,
+template <bool kCount, bool kCulled>
+__global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists lists, float* rec,
                                                    unsigned long long* cut, unsigned long long* pair_counter) {
+  const uint32_t* __restrict__ vals = lists.vals;
+  const uint32_t* __restrict__ ranges = lists.ranges;
+  const uint32_t* __restrict__ first = lists.first;
   __shared__ float2 s_xy[64];
   __shared__ float4 s_co[64];
   __shared__ float4 s_rgb[64];  // rgb and the 0-based list position (as int bits)
@@ -236,9 +211,8 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const 
   const int px = tx * kTile + (lane & 15);
   const int py0 = ty * kTile + (lane >> 4);
   const float fpx = static_cast<float>(px);
-  const float X0 = static_cast<float>(tx * kTile), Y0 = static_cast<float>(ty * kTile);
-  const float X1 = static_cast<float>(min(v.W, (tx + 1) * kTile) - 1);
-  const float Y1 = static_cast<float>(min(v.H, (ty + 1) * kTile) - 1);
+  float X0, X1, Y0, Y1;
+  tile_bounds(tx, ty, v.W, v.H, X0, X1, Y0, Y1);
   const uint64_t lt = (1ull << lane) - 1ull;
   const int64_t HW = static_cast<int64_t>(v.W) * v.H;
   float T[kPix], rr[kPix], gr[kPix], gg[kPix], gb[kPix];
@@ -285,7 +259,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const 
       m = reinterpret_cast<const float2*>(geom.xy)[g];
       co = reinterpret_cast<const float4*>(geom.conic_op)[g];
       c = make_float4(geom.rgb[3 * g], geom.rgb[3 * g + 1], geom.rgb[3 * g + 2], __int_as_float(lo + lane));
-      keep = tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1);
+      keep = kCulled || tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1);
     }
     const uint64_t km = __ballot(keep);
     if (keep) {
@@ -354,9 +328,15 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const 
     if (keep) {
       // record of this (Gaussian, tile) pair at its emission-order index
       const int slot = __popcll(km & lt);
-      int32_t rect[4];
-      tile_rect(m.x, m.y, geom.radius[g], v.GX, v.GY, rect);
-      const uint32_t e = first[g] + static_cast<uint32_t>((ty - rect[1]) * (rect[2] - rect[0]) + (tx - rect[0]));
+      uint32_t e;
+      if (kCulled) {  // the tile's rank among the Gaussian's reached tiles
+        const uint2 rw = lists.rows[lists.row_base[g] + static_cast<uint32_t>(ty)];
+        e = first[g] + rw.x + static_cast<uint32_t>(tx - static_cast<int>(rw.y & 0xffffu));
+      } else {
+        int32_t rect[4];
+        tile_rect(m.x, m.y, geom.radius[g], v.GX, v.GY, rect);
+        e = first[g] + static_cast<uint32_t>((ty - rect[1]) * (rect[2] - rect[0]) + (tx - rect[0]));
+      }
       float* dst = rec + 9 * static_cast<int64_t>(e);
       const bool has = s_any[slot] != 0;
 #pragma unroll
@@ -372,9 +352,9 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, const 
   }
 }
 
-// Sum of one Gaussian's stored (Gaussian, tile) records over the tiles
-// q0, q0 + step, ... of its rectangle, skipping tiles the adjoint did not
-// reach (key above the tile's cut) and tiles it culled (same test).
+// Rectangle lists: sum of one Gaussian's stored (Gaussian, tile) records over
+// the tiles q0, q0 + step, ... of its rectangle, skipping tiles the adjoint
+// did not reach (key above the tile's cut) and tiles it culled (same test).
 __device__ __forceinline__ void gather_pairs(const ViewSet& vs, const Geom& geom, uint32_t g, uint32_t q0,
                                              uint32_t step, const uint32_t* __restrict__ first,
                                              const float* __restrict__ rec,
@@ -395,9 +375,8 @@ __device__ __forceinline__ void gather_pairs(const ViewSet& vs, const Geom& geom
     const int tx = rect[0] + static_cast<int>(dx), ty = rect[1] + static_cast<int>(dy);
     const int64_t t = v.tile_off + static_cast<int64_t>(ty) * v.GX + tx;
     if (key > cut[t]) continue;
-    const float X0 = static_cast<float>(tx * kTile), Y0 = static_cast<float>(ty * kTile);
-    const float X1 = static_cast<float>(min(v.W, (tx + 1) * kTile) - 1);
-    const float Y1 = static_cast<float>(min(v.H, (ty + 1) * kTile) - 1);
+    float X0, X1, Y0, Y1;
+    tile_bounds(tx, ty, v.W, v.H, X0, X1, Y0, Y1);
     if (!tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1)) continue;
     const float* r = rec + 9 * static_cast<int64_t>(e0 + q);
 #pragma unroll
@@ -405,9 +384,38 @@ __device__ __forceinline__ void gather_pairs(const ViewSet& vs, const Geom& geom
   }
 }
 
+// Culled lists: a Gaussian's records are its reached tiles in row-major
+// order; the row records give each row's reached columns and the count of
+// reached tiles before it.  One thread walks all rows, or, with the whole
+// wave, lane l takes rows l, l + 64, ...
+__device__ __forceinline__ void gather_rows(const ViewSet& vs, const Geom& geom, uint32_t g, bool wave, int lane,
+                                            const Lists& lists, const float* __restrict__ rec,
+                                            const unsigned long long* __restrict__ cut, float acc[9]) {
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
+  const View& v = view_at(vs, view_of_gauss(vs, g));
+  const float2 m = reinterpret_cast<const float2*>(geom.xy)[g];
+  int32_t rect[4];
+  tile_rect(m.x, m.y, geom.radius[g], v.GX, v.GY, rect);
+  const unsigned long long key = (static_cast<unsigned long long>(__float_as_uint(geom.depth[g])) << 32) | g;
+  const uint32_t e0 = lists.first[g], rb = lists.row_base[g];
+  for (int ty = rect[1] + (wave ? lane : 0); ty < rect[3]; ty += wave ? 64 : 1) {
+    const uint2 rw = lists.rows[rb + static_cast<uint32_t>(ty)];
+    const uint32_t lo = rw.y & 0xffffu, len = rw.y >> 16;
+    const int64_t trow = v.tile_off + static_cast<int64_t>(ty) * v.GX + lo;
+    for (uint32_t c = 0; c < len; ++c) {
+      if (key > cut[trow + c]) continue;
+      const float* r = rec + 9 * static_cast<int64_t>(e0 + rw.x + c);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) acc[q] += r[q];
+    }
+  }
+}
+
 constexpr uint32_t kShortRect = 16;  // Gaussians with more tiles are gathered by a whole wave
 
-__global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, const uint32_t* __restrict__ first,
+template <bool kCulled>
+__global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, Lists lists,
                                                      const float* __restrict__ rec,
                                                      const unsigned long long* __restrict__ cut, float* g2d) {
   __shared__ uint32_t s_queue[256];
@@ -420,7 +428,10 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, cons
   const uint32_t nt = vis ? geom.tiles[gi] : 0u;
   if (vis && nt <= kShortRect) {
     float acc[9];
-    gather_pairs(vs, geom, static_cast<uint32_t>(gi), 0u, 1u, first, rec, cut, acc);
+    if (kCulled)
+      gather_rows(vs, geom, static_cast<uint32_t>(gi), false, 0, lists, rec, cut, acc);
+    else
+      gather_pairs(vs, geom, static_cast<uint32_t>(gi), 0u, 1u, lists.first, rec, cut, acc);
     float* dst = g2d + kG2DStride * gi;
 #pragma unroll
     for (int c = 0; c < 9; ++c) dst[c] = acc[c];
@@ -432,7 +443,10 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, cons
   for (int qi = wid; qi < qn; qi += 4) {
     const uint32_t g = s_queue[qi];
     float acc[9], red[3];
-    gather_pairs(vs, geom, g, static_cast<uint32_t>(lane), 64u, first, rec, cut, acc);
+    if (kCulled)
+      gather_rows(vs, geom, g, true, lane, lists, rec, cut, acc);
+    else
+      gather_pairs(vs, geom, g, static_cast<uint32_t>(lane), 64u, lists.first, rec, cut, acc);
     wave_sum9(acc, red);
     if ((lane & 15) == 0) {
       const int r = lane >> 4;
@@ -447,41 +461,36 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, cons
 }
 
 hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals, const uint32_t* ranges,
-                             hipStream_t s) {
+                             bool culled, hipStream_t s) {
   if (vs.total_tiles == 0) return hipSuccess;
   StageScope scope(PVG_STAGE_RENDER_FWD, s);
-  const int64_t grid = ((vs.total_tiles + 7) / 8) * 8;
+  const dim3 grid(static_cast<unsigned>(((vs.total_tiles + 7) / 8) * 8));
   unsigned long long* cnt = profile_work_counter(PVG_STAGE_RENDER_FWD);
-  if (cnt)
-    hipLaunchKernelGGL(k_render_fwd<true>, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals, ranges,
-                       cnt);
-  else
-    hipLaunchKernelGGL(k_render_fwd<false>, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals, ranges,
-                       cnt);
+  auto k = cnt ? (culled ? k_render_fwd<true, true> : k_render_fwd<true, false>)
+               : (culled ? k_render_fwd<false, true> : k_render_fwd<false, false>);
+  hipLaunchKernelGGL(k, grid, dim3(64), 0, s, vs, geom, vals, ranges, cnt);
   return hipGetLastError();
 }
 
-hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals, const uint32_t* ranges,
-                             const uint32_t* first, float* rec, unsigned long long* cut, float* g2d,
-                             hipStream_t s) {
+hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const Lists& lists, float* rec,
+                             unsigned long long* cut, float* g2d, hipStream_t s) {
   if (vs.total_tiles == 0) return hipSuccess;
+  const bool culled = lists.culled;
   {
     StageScope scope(PVG_STAGE_RENDER_BWD, s);
-    const int64_t grid = ((vs.total_tiles + 7) / 8) * 8;
+    const dim3 grid(static_cast<unsigned>(((vs.total_tiles + 7) / 8) * 8));
     unsigned long long* cnt = profile_work_counter(PVG_STAGE_RENDER_BWD);
-    if (cnt)
-      hipLaunchKernelGGL(k_render_bwd<true>, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals,
-                         ranges, first, rec, cut, cnt);
-    else
-      hipLaunchKernelGGL(k_render_bwd<false>, dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, vs, geom, vals,
-                         ranges, first, rec, cut, cnt);
+    auto k = cnt ? (culled ? k_render_bwd<true, true> : k_render_bwd<true, false>)
+                 : (culled ? k_render_bwd<false, true> : k_render_bwd<false, false>);
+    hipLaunchKernelGGL(k, grid, dim3(64), 0, s, vs, geom, lists, rec, cut, cnt);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (vs.total_gauss == 0) return hipSuccess;
   StageScope scope(PVG_STAGE_GRAD_GATHER, s);
-  hipLaunchKernelGGL(k_grad_gather, dim3(static_cast<unsigned>((vs.total_gauss + 255) / 256)), dim3(256), 0, s, vs,
-                     geom, first, rec, cut, g2d);
+  hipLaunchKernelGGL(culled ? k_grad_gather<true> : k_grad_gather<false>,
+                     dim3(static_cast<unsigned>((vs.total_gauss + 255) / 256)), dim3(256), 0, s, vs, geom, lists, rec,
+                     cut, g2d);
   return hipGetLastError();
 }
 

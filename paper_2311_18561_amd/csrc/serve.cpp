@@ -145,6 +145,7 @@ int lane_init(pvg_server* s, Lane& L) {
   L.bins.vals = reinterpret_cast<uint32_t*>(b + o_vals);
   L.bins.ranges = reinterpret_cast<uint32_t*>(b + o_ranges);
   L.bins.counters = reinterpret_cast<uint32_t*>(b + o_counters);
+  L.bins.tile_cull = 1;
   L.tmp = b + o_tmp;
   L.final_T = reinterpret_cast<float*>(b + o_T);
   L.n_contrib = reinterpret_cast<int32_t*>(b + o_nc);
@@ -430,7 +431,7 @@ int run_batch_forward(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void*
   PVG_HIP(launch_preprocess(vs, geom, s));
   const int st = run_bin_sort(vs, geom, bins, tmp, plan, 0, s);
   if (st != PVG_OK) return st;
-  PVG_HIP(launch_render_fwd(vs, geom, bins->vals, bins->ranges, s));
+  PVG_HIP(launch_render_fwd(vs, geom, bins->vals, bins->ranges, bins->tile_cull != 0, s));
   return PVG_OK;
 }
 

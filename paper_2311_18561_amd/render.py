@@ -6,7 +6,7 @@ GPU): mu [3,N], scale [3,N], rot [4,N] (w,x,y,z), sh [K,3,N] with
 K = (D+1)^2, opacity [N], vel [3,N], period [N], tau [N], beta [N].
 
 ``PVGRender.apply(mu, scale, rot, sh, opacity, vel, period, tau, beta, cam, t,
-dt=0, advect_mode=0, bg=(0,0,0), recompute=True)`` renders Eq. (8) of the
+dt=0, advect_mode=0, bg=(0,0,0), recompute=True, tile_cull=True)`` renders Eq. (8) of the
 paper (the flow-translated Eq. (12) render when dt != 0) and returns the image
 [3,H,W]; its backward returns gradients for the nine parameter tensors.  With
 ``recompute=True`` only the parameters, final transmittance and contributor
@@ -107,15 +107,22 @@ class Geom:
 
 
 class Bins:
-    """Sorted tile instances (device tensors) and their ctypes view."""
+    """Sorted tile instances (device tensors) and their ctypes view.
 
-    def __init__(self, capacity, num_tiles, device, n=0):
+    tile_cull=True lists a Gaussian only in the tiles where it can reach
+    alpha >= 1/255 (images and gradients are unchanged, the lists shorter);
+    False lists every tile of its screen rectangle."""
+
+    def __init__(self, capacity, num_tiles, device, n=0, tile_cull=True):
         self.capacity = capacity
+        self.tile_cull = bool(tile_cull)
         self.keys = torch.empty(2 * max(capacity, 1), dtype=torch.int32, device=device)
         self.vals = torch.empty(2 * max(capacity, 1), dtype=torch.int32, device=device)
         self.ranges = torch.empty((num_tiles, 2), dtype=torch.int32, device=device)
         self.counters = torch.empty(4, dtype=torch.int32, device=device)
         self.first = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        self.rows = torch.empty(2 * max(capacity, 1) if tile_cull else 1, dtype=torch.int32, device=device)
+        self.row_base = torch.empty(max(n, 1) if tile_cull else 1, dtype=torch.int32, device=device)
         self.num_instances = -1
         self.num_visible = -1
 
@@ -125,7 +132,14 @@ class Bins:
         b.keys, b.vals = self.keys.data_ptr(), self.vals.data_ptr()
         b.ranges, b.counters = self.ranges.data_ptr(), self.counters.data_ptr()
         b.first = self.first.data_ptr()
+        b.tile_cull = 1 if self.tile_cull else 0
+        if self.tile_cull:
+            b.rows, b.row_base = self.rows.data_ptr(), self.row_base.data_ptr()
         return b
+
+    def num_listed(self) -> int:
+        """Instances in the sorted lists (reads the device counter: synchronises)."""
+        return int(self.counters[0].item()) & 0xFFFFFFFF
 
 
 def workspace(n, width, height, capacity) -> L.WsSizes:
@@ -142,17 +156,17 @@ def preprocess(params, n, degree, cam: L.Camera, frame: L.Frame) -> Geom:
     return geom
 
 
-def bin_sort(geom: Geom, cam: L.Camera, capacity: int | None = None) -> Bins:
+def bin_sort(geom: Geom, cam: L.Camera, capacity: int | None = None, tile_cull: bool = True) -> Bins:
     """Instances sorted by (tile, depth, index); grows the capacity on demand."""
     dev = geom.xy.device
-    key = (dev.index, int(cam.width), int(cam.height))
+    key = (dev.index, int(cam.width), int(cam.height), bool(tile_cull))
     cap = int(capacity if capacity is not None else _capacity_hint.get(key, max(1 << 16, 4 * geom.n)))
     cap = min(cap, 0xFFFFFFFF)
     lib = L.load()
     gs = geom.struct()
     for _ in range(3):
         ws = workspace(geom.n, cam.width, cam.height, cap)
-        bins = Bins(cap, int(ws.num_tiles), dev, geom.n)
+        bins = Bins(cap, int(ws.num_tiles), dev, geom.n, tile_cull)
         tmp = torch.empty(max(int(ws.bin_tmp_bytes), 1), dtype=torch.uint8, device=dev)
         bs = bins.struct()
         st = lib.pvg_bin_sort(C.byref(gs), C.byref(cam), C.byref(bs), _p(tmp), int(ws.bin_tmp_bytes), 1,
@@ -166,6 +180,19 @@ def bin_sort(geom: Geom, cam: L.Camera, capacity: int | None = None) -> Bins:
             _capacity_hint[key] = max(cap, int(bins.num_instances * 1.2) + 4096)
         return bins
     raise RuntimeError("bin_sort did not converge on an instance capacity")
+
+
+def bin_sort_nosync(geom: Geom, cam: L.Camera, capacity: int, tile_cull: bool = True) -> Bins:
+    """bin_sort without reading the count back: on overflow the device flag
+    bins.counters[2] is set and the lists are empty (see overflowed())."""
+    dev = geom.xy.device
+    ws = workspace(geom.n, cam.width, cam.height, capacity)
+    bins = Bins(capacity, int(ws.num_tiles), dev, geom.n, tile_cull)
+    tmp = torch.empty(max(int(ws.bin_tmp_bytes), 1), dtype=torch.uint8, device=dev)
+    gs, bs = geom.struct(), bins.struct()
+    L.check(L.load().pvg_bin_sort(C.byref(gs), C.byref(cam), C.byref(bs), _p(tmp), int(ws.bin_tmp_bytes), 0,
+                                  _stream_handle()))
+    return bins
 
 
 def render_fwd(geom: Geom, bins: Bins, cam: L.Camera, frame: L.Frame):
@@ -198,12 +225,12 @@ def render_bwd(params, n, degree, cam, frame, geom, bins, final_T, n_contrib, dL
     return grads
 
 
-def render(params, cam: dict, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0)):
+def render(params, cam: dict, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), tile_cull=True):
     """Forward only: returns (img [3,H,W], final_T [H,W], n_contrib [H,W], geom, bins)."""
     params, n, degree = _check_params(params)
     c, f = camera_struct(cam), frame_struct(t, dt, advect_mode, bg)
     geom = preprocess(params, n, degree, c, f)
-    bins = bin_sort(geom, c)
+    bins = bin_sort(geom, c, tile_cull=tile_cull)
     img, T, nc = render_fwd(geom, bins, c, f)
     return img, T, nc, geom, bins
 
@@ -211,31 +238,99 @@ def render(params, cam: dict, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0)):
 class PVGRender(torch.autograd.Function):
     @staticmethod
     def forward(ctx, mu, scale, rot, sh, opacity, vel, period, tau, beta, cam, t, dt=0.0, advect_mode=0,
-                bg=(0.0, 0.0, 0.0), recompute=True):
+                bg=(0.0, 0.0, 0.0), recompute=True, tile_cull=True):
         params, n, degree = _check_params([mu, scale, rot, sh, opacity, vel, period, tau, beta])
         c, f = camera_struct(cam), frame_struct(t, dt, advect_mode, bg)
         geom = preprocess(params, n, degree, c, f)
-        bins = bin_sort(geom, c)
+        bins = bin_sort(geom, c, tile_cull=tile_cull)
         img, final_T, n_contrib = render_fwd(geom, bins, c, f)
-        ctx.meta = (n, degree, c, f, recompute)
+        ctx.meta = (n, degree, c, f, recompute, tile_cull)
         ctx.kept = None if recompute else (geom, bins)
         ctx.save_for_backward(*params, final_T, n_contrib)
         return img
 
     @staticmethod
     def backward(ctx, dL_dimg):
-        n, degree, c, f, recompute = ctx.meta
+        n, degree, c, f, recompute, tile_cull = ctx.meta
         saved = ctx.saved_tensors
         params, final_T, n_contrib = list(saved[:9]), saved[9], saved[10]
         if recompute:
             geom = preprocess(params, n, degree, c, f)
-            bins = bin_sort(geom, c)
+            bins = bin_sort(geom, c, tile_cull=tile_cull)
         else:
             geom, bins = ctx.kept
         grads = render_bwd(params, n, degree, c, f, geom, bins, final_T, n_contrib, dL_dimg)
-        return (*grads, None, None, None, None, None, None)
+        return (*grads, None, None, None, None, None, None, None)
 
 
-def pvg_render(params, cam, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), recompute=True):
+class PVGRenderViews(torch.autograd.Function):
+    """Several renders (cameras x times) of one set of Gaussians as one node:
+    the forward launches every view without a host round trip per view (one
+    overflow check at the end), the backward rebuilds each view's lists and
+    adds all views' gradients in the kernels into one zeroed set."""
+
+    @staticmethod
+    def forward(ctx, views, recompute, tile_cull, *tensors):
+        params, n, degree = _check_params(list(tensors))
+        dev = params[0].device
+        plans, outs = [], []
+        for cam, t, dt, mode, bg in views:
+            c, f = camera_struct(cam), frame_struct(t, dt, mode, bg)
+            geom = preprocess(params, n, degree, c, f)
+            cap = _capacity_hint.get((dev.index, int(c.width), int(c.height), bool(tile_cull)))
+            bins = bin_sort(geom, c, tile_cull=tile_cull) if cap is None else bin_sort_nosync(geom, c, cap, tile_cull)
+            plans.append([c, f, geom, bins])
+        for k, (c, f, geom, bins) in enumerate(plans):
+            outs.append(render_fwd(geom, bins, c, f))
+        over = torch.stack([b.counters[2] for _, _, _, b in plans]).cpu().tolist()
+        for k, flag in enumerate(over):
+            if flag:  # this view outgrew the cached capacity: redo it with the counting path
+                c, f, geom, _ = plans[k]
+                bins = bin_sort(geom, c, tile_cull=tile_cull)
+                plans[k][3] = bins
+                outs[k] = render_fwd(geom, bins, c, f)
+        ctx.meta = (n, degree, recompute, tile_cull, [(c, f, b.capacity) for c, f, _, b in plans])
+        ctx.kept = None if recompute else [(g, b) for _, _, g, b in plans]
+        saved = list(params)
+        for _, T, nc in outs:
+            saved += [T, nc]
+        ctx.save_for_backward(*saved)
+        return tuple(img for img, _, _ in outs)
+
+    @staticmethod
+    def backward(ctx, *dimgs):
+        n, degree, recompute, tile_cull, plan = ctx.meta
+        saved = ctx.saved_tensors
+        params = list(saved[:9])
+        grads = [torch.zeros_like(p) for p in params]
+        for k, (c, f, cap) in enumerate(plan):
+            if dimgs[k] is None:
+                continue
+            T, nc = saved[9 + 2 * k], saved[10 + 2 * k]
+            if recompute:  # same inputs give the forward's lists bit for bit, within the same capacity
+                geom = preprocess(params, n, degree, c, f)
+                bins = bin_sort_nosync(geom, c, cap, tile_cull)
+            else:
+                geom, bins = ctx.kept[k]
+            render_bwd(params, n, degree, c, f, geom, bins, T, nc, dimgs[k], grads=grads, accumulate=True)
+        return (None, None, None, *grads)
+
+
+def pvg_render_views(params, views, recompute=True, tile_cull=True):
+    """Differentiable renders of the nine parameter tensors for several views:
+    views = [(cam, t), (cam, t, dt), ... or (cam, t, dt, advect_mode, bg)];
+    returns one image [3,H,W] per view."""
+    full = []
+    for v in views:
+        v = tuple(v)
+        cam, t = v[0], v[1]
+        dt = v[2] if len(v) > 2 else 0.0
+        mode = v[3] if len(v) > 3 else 0
+        bg = v[4] if len(v) > 4 else (0.0, 0.0, 0.0)
+        full.append((cam, float(t), float(dt), int(mode), tuple(float(b) for b in bg)))
+    return PVGRenderViews.apply(full, recompute, tile_cull, *params)
+
+
+def pvg_render(params, cam, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), recompute=True, tile_cull=True):
     """Differentiable render of the nine parameter tensors (see module doc)."""
-    return PVGRender.apply(*params, cam, t, dt, advect_mode, bg, recompute)
+    return PVGRender.apply(*params, cam, t, dt, advect_mode, bg, recompute, tile_cull)

@@ -4,12 +4,17 @@ Bars: bit-exact per-Gaussian discrete structure (radius, tile counts, depth
 keys, 2D mean and conic), bit-exact sorted instances and ranges; images within
 1e-4 absolute of the FP32 oracle; gradients within 1e-3 relative of the FP64
 oracle (per element, relative to max(|g*|, 1e-2 rms(g*)) of that tensor).
+
+The product path lists a Gaussian only in tiles it can reach (tile culling);
+its lists are checked to be the rectangle lists minus entries that every pixel
+skips, and its images against the rectangle-list path bit for bit.
 """
 import numpy as np
 import pytest
 
 import gen
-from helpers import FIELDS, geom_as_oracle_pre, gpu_forward, grad_tolerance_report, to_device
+from helpers import (FIELDS, check_culled_lists, geom_as_oracle_pre, gpu_forward, grad_tolerance_report,
+                     last_contributor_ids, to_device)
 
 pytestmark = pytest.mark.gpu
 
@@ -39,12 +44,13 @@ CASES = _cases()
 def case(request, orc):
     scene, cam, t, dt, mode, bg = CASES[request.param]()
     g = gpu_forward(scene, cam, t, dt, mode, bg)
+    gr = gpu_forward(scene, cam, t, dt, mode, bg, params=g["_params"], tile_cull=False)
     o = orc.render(scene, cam, t, dt, mode, bg)
-    return request.param, scene, cam, (t, dt, mode, bg), g, o
+    return request.param, scene, cam, (t, dt, mode, bg), g, o, gr
 
 
 def test_preprocess_bit_exact(case):
-    name, scene, cam, fr, g, o = case
+    name, scene, cam, fr, g, o, gr = case
     pre = o["pre"]
     print(f"[{name}] visible gpu={int((g['radius'] > 0).sum())} oracle={int((pre['radius'] > 0).sum())}")
     assert np.array_equal(g["radius"], pre["radius"])
@@ -59,45 +65,60 @@ def test_preprocess_bit_exact(case):
 
 
 def test_bin_sort_exact(case, orc):
-    name, scene, cam, fr, g, o = case
+    name, scene, cam, fr, g, o, gr = case
     b = o["bins"]
-    assert g["M"] == b["M"]
-    assert np.array_equal(g["vals"], b["inst_gauss"])
-    assert np.array_equal(g["keys"], b["inst_tile"])
-    assert np.array_equal(g["ranges"], b["ranges"])
+    assert gr["M"] == b["M"] and gr["L"] == b["M"]
+    assert np.array_equal(gr["vals"], b["inst_gauss"])
+    assert np.array_equal(gr["keys"], b["inst_tile"])
+    assert np.array_equal(gr["ranges"], b["ranges"])
     # same check with the GPU's own record fed to the oracle's sort (structure injection)
-    bins2 = orc.bin_sort(geom_as_oracle_pre(g, cam), cam)
-    assert np.array_equal(g["vals"], bins2["inst_gauss"])
+    bins2 = orc.bin_sort(geom_as_oracle_pre(gr, cam), cam)
+    assert np.array_equal(gr["vals"], bins2["inst_gauss"])
+
+
+def test_culled_lists_valid(case):
+    name, scene, cam, fr, g, o, gr = case
+    b = o["bins"]
+    assert g["M"] == g["L"] and g["L"] <= b["M"]
+    dropped = check_culled_lists(g["keys"], g["vals"], g["ranges"], b["inst_tile"], b["inst_gauss"], o["pre"], cam,
+                                 scene["n"])
+    print(f"[{name}] rectangle instances {b['M']}, listed {g['L']}, removed {dropped}")
+    assert dropped == b["M"] - g["L"]
 
 
 def test_render_forward_parity(case):
-    name, scene, cam, fr, g, o = case
-    err = np.abs(g["img"] - o["img"]).max()
-    terr = np.abs(g["final_T"] - o["final_T"]).max()
-    flips = int((g["n_contrib"] != o["n_contrib"]).sum())
-    print(f"[{name}] max |img - oracle| = {err:.3g}, max |T - oracle| = {terr:.3g}, n_contrib flips = {flips}")
-    assert err <= 1e-4
-    assert terr <= 1e-4
-    assert flips == 0
+    name, scene, cam, fr, g, o, gr = case
+    ids_orc = last_contributor_ids(o["n_contrib"], o["bins"]["inst_gauss"], o["bins"]["ranges"], cam["width"])
+    for label, x in (("culled", g), ("rect", gr)):
+        err = np.abs(x["img"] - o["img"]).max()
+        terr = np.abs(x["final_T"] - o["final_T"]).max()
+        ids = last_contributor_ids(x["n_contrib"], x["vals"], x["ranges"], cam["width"])
+        flips = int((ids != ids_orc).sum())
+        print(f"[{name}/{label}] max |img - oracle| = {err:.3g}, max |T - oracle| = {terr:.3g}, "
+              f"last-contributor flips = {flips}")
+        assert err <= 1e-4
+        assert terr <= 1e-4
+        assert flips == 0
+    assert np.array_equal(gr["n_contrib"], o["n_contrib"])
+    # culling removes only entries every pixel skips: identical compositing
+    assert np.array_equal(g["img"], gr["img"]) and np.array_equal(g["final_T"], gr["final_T"])
 
 
 def test_forward_deterministic(case):
-    name, scene, cam, fr, g, o = case
-    g2 = gpu_forward(scene, cam, *fr, params=g["_params"])
-    for k in ("img", "final_T", "n_contrib", "vals", "keys", "ranges", "xy", "conic_op", "rgb"):
-        assert np.array_equal(g[k], g2[k]), k
+    name, scene, cam, fr, g, o, gr = case
+    for tc, ref in ((True, g), (False, gr)):
+        g2 = gpu_forward(scene, cam, *fr, params=g["_params"], tile_cull=tc)
+        for k in ("img", "final_T", "n_contrib", "vals", "keys", "ranges", "xy", "conic_op", "rgb"):
+            assert np.array_equal(ref[k], g2[k]), (tc, k)
 
 
-def _backward_compare(orc, scene, cam, t, dt, mode, bg, seed=0, rel=1e-3):
+def _backward_compare(orc, scene, cam, t, dt, mode, bg, seed=0, rel=1e-3, tile_cull=True):
     import paper_2311_18561_amd as pvg
-    params = to_device(scene)
-    img = pvg.pvg_render(params, cam, t, dt, mode, bg)
     H, W = cam["height"], cam["width"]
     rng = np.random.default_rng(seed)
     w = rng.standard_normal((3, H, W)).astype(np.float32)
-    for p in params:
-        p.requires_grad_(True)
-    img = pvg.pvg_render(params, cam, t, dt, mode, bg)
+    params = [p.requires_grad_(True) for p in to_device(scene)]
+    img = pvg.pvg_render(params, cam, t, dt, mode, bg, tile_cull=tile_cull)
     (img * torch.from_numpy(w).cuda()).sum().backward()
     pre = orc.preprocess_f32(scene, cam, t, dt, mode, bg)
     bins = orc.bin_sort(pre, cam)
@@ -119,11 +140,24 @@ def test_backward_tiny_vs_fp64(orc, name, dt, mode):
         assert worst <= 1.0, f
 
 
-def test_backward_cfg0_vs_fp64(orc):
+@pytest.mark.parametrize("tile_cull", [True, False])
+def test_backward_cfg0_vs_fp64(orc, tile_cull):
     cfg = gen.make_config(0)
-    rep = _backward_compare(orc, cfg["scene"], cfg["cameras"][0], cfg["t"], 0.05, 0, (0, 0, 0))
+    rep = _backward_compare(orc, cfg["scene"], cfg["cameras"][0], cfg["t"], 0.05, 0, (0, 0, 0), tile_cull=tile_cull)
     for f, (worst, l2) in rep.items():
-        print(f"[cfg0] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+        print(f"[cfg0 cull={tile_cull}] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+        assert worst <= 1.0, f
+
+
+@pytest.mark.parametrize("tile_cull", [True, False])
+def test_backward_cfg1_20k_vs_fp64(orc, tile_cull):
+    """Both list forms on 20k Gaussians at 960x640 (many tiles per splat, so
+    the gather's whole-wave path runs) against the FP64 adjoint."""
+    cfg = gen.make_config(1, n=20_000)
+    rep = _backward_compare(orc, cfg["scene"], cfg["cameras"][0], cfg["t"], 0.05, 0, (0, 0, 0), seed=5,
+                            tile_cull=tile_cull)
+    for f, (worst, l2) in rep.items():
+        print(f"[cfg1-20k cull={tile_cull}] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
         assert worst <= 1.0, f
 
 
@@ -155,6 +189,39 @@ def test_recompute_and_kept_lists_agree(orc):
         np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * (1 + np.abs(b).max()))
 
 
+def test_multi_view_render_matches_single_views():
+    """pvg_render_views: each image equals the single-view render bit for bit;
+    the gradients (added in the kernels) equal the sum of the single-view
+    gradients up to FP32 addition order; a view that outgrows the cached
+    capacity is redone."""
+    import importlib
+    import paper_2311_18561_amd as pvg
+    R = importlib.import_module("paper_2311_18561_amd.render")
+    cfg = gen.make_config(1, n=20_000)
+    cams = [gen.yaw_camera(320, 208, yaw, (0.0, 0.0, 0.0)) for yaw in (-20.0, 0.0, 20.0)]
+    views = [(cam, 0.4, d) for cam in cams for d in (0.0, 0.05)]
+    w = [torch.linspace(-1, 1, 3 * 208 * 320, device="cuda").reshape(3, 208, 320) * (k + 1) for k in range(6)]
+    ref_imgs, ref_grads = [], None
+    params = [p.requires_grad_(True) for p in to_device(cfg["scene"])]
+    for k, (cam, t, d) in enumerate(views):
+        img = pvg.pvg_render(params, cam, t, d)
+        ref_imgs.append(img.detach().clone())
+        (img * w[k]).sum().backward()
+    ref_grads = [p.grad.detach().clone() for p in params]
+    for shrink in (False, True):
+        if shrink:  # force an overflow of the cached capacity on every view
+            for key in list(R._capacity_hint):
+                R._capacity_hint[key] = 64
+        params = [p.requires_grad_(True) for p in to_device(cfg["scene"])]
+        imgs = pvg.pvg_render_views(params, views)
+        sum((img * w[k]).sum() for k, img in enumerate(imgs)).backward()
+        for a, b in zip(imgs, ref_imgs):
+            assert torch.equal(a.detach(), b)
+        for f, p, g in zip(FIELDS, params, ref_grads):
+            worst, l2 = grad_tolerance_report(p.grad.cpu().numpy(), g.cpu().numpy(), rel=1e-4)
+            assert worst <= 1.0, (shrink, f, worst)
+
+
 def test_edge_cases(orc):
     import paper_2311_18561_amd as pvg
     cam = gen.make_camera(72, 40)  # ragged 4.5 x 2.5 tiles
@@ -178,42 +245,54 @@ def test_edge_cases(orc):
            "vel": np.zeros((3, n), np.float32), "period": np.ones(n, np.float32),
            "tau": np.full(n, 0.5, np.float32), "beta": np.full(n, 1e8, np.float32)}
     big["scale"][:, 0] = 3.0
-    g = gpu_forward(big, cam, 0.5)
     o = orc.render(big, cam, 0.5)
-    assert g["M"] == o["bins"]["M"]
-    assert np.array_equal(g["vals"], o["bins"]["inst_gauss"])
-    assert np.abs(g["img"] - o["img"]).max() <= 1e-4
-    assert np.array_equal(g["n_contrib"], o["n_contrib"])
+    gr = gpu_forward(big, cam, 0.5, tile_cull=False)
+    assert gr["M"] == o["bins"]["M"]
+    assert np.array_equal(gr["vals"], o["bins"]["inst_gauss"])
+    assert np.abs(gr["img"] - o["img"]).max() <= 1e-4
+    assert np.array_equal(gr["n_contrib"], o["n_contrib"])
+    g = gpu_forward(big, cam, 0.5, params=gr["_params"])
+    check_culled_lists(g["keys"], g["vals"], g["ranges"], o["bins"]["inst_tile"], o["bins"]["inst_gauss"], o["pre"],
+                       cam, n)
+    assert np.array_equal(g["img"], gr["img"])
 
 
-def test_capacity_handling():
+@pytest.mark.parametrize("tile_cull", [False, True])
+def test_capacity_handling(tile_cull):
     import ctypes as C
     import paper_2311_18561_amd as pvg
     from paper_2311_18561_amd import _lib as L
     cfg = gen.make_config(0)
     cam = cfg["cameras"][0]
     params = to_device(cfg["scene"])
-    img, T, nc, geom, bins = pvg.render(params, cam, 0.5)
+    img, T, nc, geom, bins = pvg.render(params, cam, 0.5, tile_cull=tile_cull)
     M = bins.num_instances
     c = pvg.camera_struct(cam)
     from paper_2311_18561_amd.render import Bins, _p, _stream_handle, workspace
-    small = Bins(16, bins.ranges.shape[0], params[0].device, geom.n)
+    small = Bins(16, bins.ranges.shape[0], params[0].device, geom.n, tile_cull)
     ws = workspace(geom.n, cam["width"], cam["height"], 16)
     tmp = torch.empty(int(ws.bin_tmp_bytes), dtype=torch.uint8, device="cuda")
     bs = small.struct()
     st = L.load().pvg_bin_sort(C.byref(geom.struct()), C.byref(c), C.byref(bs), _p(tmp), int(ws.bin_tmp_bytes), 1,
                                _stream_handle())
-    assert st == L.PVG_ERR_CAPACITY and bs.num_instances == M
+    assert st == L.PVG_ERR_CAPACITY
+    # the count that did not fit: the instances, or (culled) first the rectangle rows
+    assert bs.num_instances == M if not tile_cull else bs.num_instances > 16
     # without the host count: overflow flag on the device, empty ranges, background image
     st = L.load().pvg_bin_sort(C.byref(geom.struct()), C.byref(c), C.byref(bs), _p(tmp), int(ws.bin_tmp_bytes), 0,
                                _stream_handle())
     assert st == 0
     torch.cuda.synchronize()
     cnt = small.counters.cpu().numpy().view(np.uint32)
-    assert cnt[2] == 1 and cnt[3] == M and cnt[0] == 0
+    assert cnt[2] == 1 and cnt[0] == 0
+    if not tile_cull:
+        assert cnt[3] == M
     assert torch.all(small.ranges == 0)
     img2, _, _ = pvg.render_fwd(geom, small, c, pvg.frame_struct(0.5, bg=(0.5, 0.5, 0.5)))
     assert torch.all(img2 == 0.5)
+    # the Python layer grows the capacity until it fits and reproduces the image
+    img3, _, _, _, bins3 = pvg.render(params, cam, 0.5, tile_cull=tile_cull)
+    assert bins3.num_instances == M and torch.equal(img3, img)
 
 
 def test_config1_full_size(orc):
@@ -224,13 +303,21 @@ def test_config1_full_size(orc):
     cam, t = cfg["cameras"][0], cfg["t"]
     scene = cfg["scene"]
     g = gpu_forward(scene, cam, t)
+    gr = gpu_forward(scene, cam, t, params=g["_params"], tile_cull=False)
     o = orc.render(scene, cam, t)
-    assert g["M"] == o["bins"]["M"]
+    assert gr["M"] == o["bins"]["M"] and g["M"] == g["L"] < gr["M"]
     assert np.array_equal(g["radius"], o["pre"]["radius"])
-    assert np.array_equal(g["vals"], o["bins"]["inst_gauss"])
+    assert np.array_equal(gr["vals"], o["bins"]["inst_gauss"])
+    assert np.array_equal(gr["keys"], o["bins"]["inst_tile"])
+    dropped = check_culled_lists(g["keys"], g["vals"], g["ranges"], o["bins"]["inst_tile"], o["bins"]["inst_gauss"],
+                                 o["pre"], cam, scene["n"], sample=200_000)
+    assert np.array_equal(g["img"], gr["img"])
     err = np.abs(g["img"] - o["img"]).max()
-    flips = int((g["n_contrib"] != o["n_contrib"]).sum())
-    print(f"[cfg1] M={g['M']} max |img - oracle| = {err:.3g}, n_contrib flips = {flips}")
+    ids = last_contributor_ids(g["n_contrib"], g["vals"], g["ranges"], cam["width"])
+    ids_orc = last_contributor_ids(o["n_contrib"], o["bins"]["inst_gauss"], o["bins"]["ranges"], cam["width"])
+    flips = int((ids != ids_orc).sum())
+    print(f"[cfg1] M={g['M']} listed={g['L']} (removed {dropped}) max |img - oracle| = {err:.3g}, "
+          f"last-contributor flips = {flips}")
     # The per-pair exponential is each side's FP32 library expf (<= 1 ulp apart);
     # a contributor count can only differ where alpha or the transmittance sits
     # within an ulp of its threshold.  Bound how often, and hold the image bar
