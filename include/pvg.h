@@ -137,8 +137,9 @@ typedef struct pvg_bins {
                            rectangle rows (16 bytes of bin_sort scratch each). */
   int32_t reserved;
   uint32_t* rows;       /* [capacity][2] optional (tile_cull = 1): per rectangle row of each
-                           visible Gaussian, (its reached tiles in earlier rows, first reached
-                           column | count << 16); pvg_render_bwd needs it with tile_cull = 1 */
+                           visible Gaussian, (emission index of the row's first listed instance,
+                           first reached column | count << 16); pvg_render_bwd needs it with
+                           tile_cull = 1 */
   uint32_t* row_base;   /* [n] optional (tile_cull = 1): index into rows of grid row 0 of each
                            visible Gaussian, modulo 2^32; pvg_render_bwd needs it with tile_cull = 1 */
 } pvg_bins;

@@ -494,130 +494,158 @@ __global__ void __launch_bounds__(kThreads) k_row_count(ViewSet vs, const uint32
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-// Row records: for each visible Gaussian k (depth order) and each row of its
-// rectangle, rows[i] = (k, first reached column | count << 16, tile row,
-// reached tiles of the Gaussian's earlier rows); lsum[k] = its reached tiles;
-// block sums of lsum.  Optionally the adjoint's copy of each row,
-// brows[i] = (earlier reached tiles, first column | count << 16), and
-// row_base[g] = index of row 0 of the grid (mod 2^32) for Gaussian g.
-__global__ void __launch_bounds__(kThreads) k_row_intervals(ViewSet vs, const uint32_t* __restrict__ order,
-                                                            const float* __restrict__ xy,
-                                                            const float* __restrict__ conic_op,
-                                                            const int32_t* __restrict__ radius,
-                                                            const uint32_t* n_dev, int64_t n_host,
-                                                            const unsigned long long* __restrict__ row_partials,
-                                                            const uint32_t* __restrict__ counters, uint4* rows,
-                                                            uint32_t* lsum, uint2* brows, uint32_t* row_base,
-                                                            unsigned long long* tile_partials) {
+// Index of each visible Gaussian's first rectangle row (row_off[k]) and, for
+// the adjoint, row_base[g] = row_off[k] - y0 (mod 2^32).
+__global__ void __launch_bounds__(kThreads) k_row_base(ViewSet vs, const uint32_t* __restrict__ order,
+                                                       const float* __restrict__ xy,
+                                                       const int32_t* __restrict__ radius, const uint32_t* n_dev,
+                                                       int64_t n_host,
+                                                       const unsigned long long* __restrict__ row_partials,
+                                                       const uint32_t* __restrict__ counters, uint32_t* row_off,
+                                                       uint32_t* row_base) {
   __shared__ unsigned long long lds[5];
   if (counters[2]) return;
   const int64_t n = live_count(n_dev, n_host);
   if (static_cast<int64_t>(blockIdx.x) * kRowBlock >= n) return;
   const int64_t k = static_cast<int64_t>(blockIdx.x) * kRowBlock + threadIdx.x;
   uint32_t g = 0;
-  float2 m = make_float2(0.0f, 0.0f);
   int32_t rect[4] = {0, 0, 0, 0};
-  const View* v = nullptr;
   if (k < n) {
+    float2 m;
     g = order[k];
-    v = &rect_of(vs, xy, radius, g, m, rect);
+    rect_of(vs, xy, radius, g, m, rect);
   }
   unsigned long long tot;
   const unsigned long long r0 =
       block_excl_scan<unsigned long long>(static_cast<unsigned long long>(rect[3] - rect[1]), lds, tot) +
       row_partials[blockIdx.x];
-  uint32_t pre = 0;
   if (k < n) {
-    const float4 co = reinterpret_cast<const float4*>(conic_op)[g];
-    const ReachRows rr = reach_rows_init(m.x, m.y, co.x, co.y, co.z, co.w);
+    row_off[k] = static_cast<uint32_t>(r0);
     if (row_base) row_base[g] = static_cast<uint32_t>(r0) - static_cast<uint32_t>(rect[1]);
-    for (int ty = rect[1]; ty < rect[3]; ++ty) {
-      int lo, hi;
-      reach_row(rr, ty, v->H, rect[0], rect[2], lo, hi);
-      const uint32_t len = hi >= lo ? static_cast<uint32_t>(hi - lo + 1) : 0u;
-      const uint32_t packed = static_cast<uint32_t>(lo) | (len << 16);
-      const unsigned long long i = r0 + static_cast<uint32_t>(ty - rect[1]);
-      rows[i] = make_uint4(static_cast<uint32_t>(k), packed, static_cast<uint32_t>(ty), pre);
-      if (brows) brows[i] = make_uint2(pre, packed);
-      pre += len;
-    }
-    lsum[k] = pre;
   }
-  block_excl_scan<unsigned long long>(pre, lds, tot);
-  if (threadIdx.x == 0) tile_partials[blockIdx.x] = tot;
 }
 
-// Instance offset of each visible Gaussian: offsets[k], first[g].
-__global__ void __launch_bounds__(kThreads) k_row_offsets(const uint32_t* __restrict__ order, const uint32_t* n_dev,
-                                                          int64_t n_host, const uint32_t* __restrict__ lsum,
-                                                          const unsigned long long* __restrict__ tile_partials,
-                                                          const uint32_t* __restrict__ counters, uint32_t* offsets,
-                                                          uint32_t* first) {
+// One thread per rectangle row, 256 consecutive rows per block iteration.
+// The rows' owners (at most 256, consecutive in depth order) are found by a
+// wave search over row_off and staged in LDS with their ellipse.  Writes
+// rows[i] = (g, first reached column | count << 16, global tile id of that
+// column, row index within the Gaussian) and the block's reached-tile sums.
+__global__ void __launch_bounds__(kThreads) k_row_intervals(ViewSet vs, const uint32_t* __restrict__ order,
+                                                            const float* __restrict__ xy,
+                                                            const float* __restrict__ conic_op,
+                                                            const int32_t* __restrict__ radius,
+                                                            const uint32_t* __restrict__ row_off,
+                                                            const uint32_t* __restrict__ num_rows,
+                                                            const uint32_t* __restrict__ counters, uint4* rows,
+                                                            unsigned long long* tile_partials) {
+  __shared__ uint32_t s_off[kRowBlock];
+  __shared__ uint32_t s_g[kRowBlock];
+  __shared__ int32_t s_rect[kRowBlock][3];  // x0, x1, y0
+  __shared__ int32_t s_view[kRowBlock][3];  // H, GX, tile_off (32 bits)
+  __shared__ ReachRows s_rr[kRowBlock];
+  __shared__ int64_t s_k[2];
   __shared__ unsigned long long lds[5];
   if (counters[2]) return;
-  const int64_t n = live_count(n_dev, n_host);
-  if (static_cast<int64_t>(blockIdx.x) * kRowBlock >= n) return;
-  const int64_t k = static_cast<int64_t>(blockIdx.x) * kRowBlock + threadIdx.x;
-  const uint32_t c = k < n ? lsum[k] : 0u;
-  unsigned long long tot;
-  const unsigned long long e = block_excl_scan<unsigned long long>(c, lds, tot) + tile_partials[blockIdx.x];
-  if (k < n) {
-    offsets[k] = static_cast<uint32_t>(e);
-    if (first) first[order[k]] = static_cast<uint32_t>(e);
+  const int64_t R = *num_rows;
+  const int64_t nvis = counters[1];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int64_t nblocks = (R + kRowBlock - 1) / kRowBlock;
+  for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const int64_t i0 = blk * kRowBlock;
+    const int64_t i1 = min(R, i0 + kRowBlock);
+    if (wid < 2) {
+      const int64_t k = wave_last_le(row_off, nvis, static_cast<uint32_t>(wid == 0 ? i0 : i1 - 1), lane);
+      if (lane == 0) s_k[wid] = k;
+    }
+    __syncthreads();
+    const int64_t k0 = s_k[0];
+    const int cnt = static_cast<int>(s_k[1] - k0 + 1);  // <= kRowBlock: every Gaussian has a row
+    if (tid < cnt) {
+      const uint32_t g = order[k0 + tid];
+      float2 m;
+      int32_t rect[4];
+      const View& v = rect_of(vs, xy, radius, g, m, rect);
+      const float4 co = reinterpret_cast<const float4*>(conic_op)[g];
+      s_off[tid] = row_off[k0 + tid];
+      s_g[tid] = g;
+      s_rect[tid][0] = rect[0];
+      s_rect[tid][1] = rect[2];
+      s_rect[tid][2] = rect[1];
+      s_view[tid][0] = v.H;
+      s_view[tid][1] = v.GX;
+      s_view[tid][2] = static_cast<int32_t>(v.tile_off);
+      s_rr[tid] = reach_rows_init(m.x, m.y, co.x, co.y, co.z, co.w);
+    }
+    __syncthreads();
+    const int64_t i = i0 + tid;
+    uint32_t len = 0;
+    if (i < i1) {
+      int lo = 0, hi = cnt - 1;
+      const uint32_t ui = static_cast<uint32_t>(i);
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= ui) lo = mid; else hi = mid - 1;
+      }
+      const uint32_t r = ui - s_off[lo];
+      const int ty = s_rect[lo][2] + static_cast<int>(r);
+      int c0, c1;
+      reach_row(s_rr[lo], ty, s_view[lo][0], s_rect[lo][0], s_rect[lo][1], c0, c1);
+      len = c1 >= c0 ? static_cast<uint32_t>(c1 - c0 + 1) : 0u;
+      const uint32_t tile = static_cast<uint32_t>(s_view[lo][2]) +
+                            static_cast<uint32_t>(ty) * static_cast<uint32_t>(s_view[lo][1]) +
+                            static_cast<uint32_t>(c0);
+      rows[i] = make_uint4(s_g[lo], static_cast<uint32_t>(c0) | (len << 16), tile, r);
+    }
+    unsigned long long tot;
+    block_excl_scan<unsigned long long>(len, lds, tot);
+    if (tid == 0) tile_partials[blk] = tot;
   }
 }
 
-// Each wave takes 64 consecutive rows: their instances are consecutive in
-// the output, so the wave stages the rows in LDS, scans their lengths and
-// then writes the instances 64 at a time (lane j writes instance t + j,
-// locating its row by a binary search of the staged starts).
-__global__ void __launch_bounds__(kThreads) k_emit_rows(ViewSet vs, const uint32_t* __restrict__ order,
-                                                        const uint4* __restrict__ rows,
-                                                        const uint32_t* __restrict__ num_rows,
-                                                        const uint32_t* __restrict__ offsets,
-                                                        const uint32_t* __restrict__ counters, uint32_t* keys,
-                                                        uint32_t* vals) {
-  __shared__ uint32_t s_start[4][64];  // offset of the row's first instance, relative to the wave's first
-  __shared__ uint32_t s_tile[4][64];   // global tile id of the row's first reached tile
-  __shared__ uint32_t s_g[4][64];
+// One thread per row again (same blocks): instance offset of each row from
+// the scanned block sums and a block scan, the adjoint's row records
+// brows[i] = (offset, first column | count << 16), first[g], and the block's
+// instances, which are consecutive in the output, written 256 at a time.
+__global__ void __launch_bounds__(kThreads) k_row_emit(const uint4* __restrict__ rows,
+                                                       const uint32_t* __restrict__ num_rows,
+                                                       const unsigned long long* __restrict__ tile_partials,
+                                                       const uint32_t* __restrict__ counters, uint2* brows,
+                                                       uint32_t* first, uint32_t* keys, uint32_t* vals) {
+  __shared__ uint32_t s_start[kRowBlock];
+  __shared__ uint32_t s_tile[kRowBlock];
+  __shared__ uint32_t s_g[kRowBlock];
+  __shared__ unsigned long long lds[5];
   if (counters[2]) return;
   const int64_t R = *num_rows;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int64_t waves = static_cast<int64_t>(gridDim.x) * (kThreads / 64);
-  for (int64_t w0 = (static_cast<int64_t>(blockIdx.x) * (kThreads / 64) + wid) * 64; w0 < R; w0 += waves * 64) {
-    const int64_t i = w0 + lane;
-    uint32_t len = 0, e = 0, tile = 0, g = 0;
+  const int tid = threadIdx.x;
+  const int64_t nblocks = (R + kRowBlock - 1) / kRowBlock;
+  for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const int64_t i = blk * kRowBlock + tid;
+    uint4 rec = make_uint4(0u, 0u, 0u, 1u);
+    if (i < R) rec = rows[i];
+    const uint32_t len = rec.y >> 16;
+    unsigned long long tot;
+    const uint32_t pre = static_cast<uint32_t>(block_excl_scan<unsigned long long>(len, lds, tot));
+    const uint32_t base = static_cast<uint32_t>(tile_partials[blk]);
     if (i < R) {
-      const uint4 rec = rows[i];
-      len = rec.y >> 16;
-      g = order[rec.x];
-      e = offsets[rec.x] + rec.w;
-      const View& v = view_at(vs, view_of_gauss(vs, g));
-      tile = static_cast<uint32_t>(v.tile_off + static_cast<int64_t>(rec.z) * v.GX + (rec.y & 0xffffu));
+      if (brows) brows[i] = make_uint2(base + pre, rec.y);
+      if (first && rec.w == 0u) first[rec.x] = base + pre;
     }
-    // rows in order are contiguous in the output: base = first row's start
-    const uint32_t base = __shfl(e, 0, 64);
-    uint32_t x = len;  // inclusive scan of the lengths
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(x, off, 64);
-      if (lane >= off) x += y;
-    }
-    const uint32_t total = __shfl(x, 63, 64);
-    s_start[wid][lane] = x - len;
-    s_tile[wid][lane] = tile;
-    s_g[wid][lane] = g;
-    __builtin_amdgcn_wave_barrier();
-    for (uint32_t t = lane; t < total; t += 64) {
-      int lo = 0, hi = 63;  // last row whose start <= t (empty rows share the next row's start)
+    s_start[tid] = i < R ? pre : static_cast<uint32_t>(tot);
+    s_tile[tid] = rec.z;
+    s_g[tid] = rec.x;
+    __syncthreads();
+    const uint32_t total = static_cast<uint32_t>(tot);
+    for (uint32_t t = tid; t < total; t += kRowBlock) {
+      int lo = 0, hi = kRowBlock - 1;  // last row whose start <= t (empty rows share the next start)
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (s_start[wid][mid] <= t) lo = mid; else hi = mid - 1;
+        if (s_start[mid] <= t) lo = mid; else hi = mid - 1;
       }
-      keys[base + t] = s_tile[wid][lo] + (t - s_start[wid][lo]);
-      vals[base + t] = s_g[wid][lo];
+      keys[base + t] = s_tile[lo] + (t - s_start[lo]);
+      vals[base + t] = s_g[lo];
     }
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
   }
 }
 
@@ -654,10 +682,10 @@ BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity) {
   p.off_partials = off; off = align256(off + sizeof(unsigned long long) * (nparts + 1));
   p.off_hist = off;     off = align256(off + sizeof(uint32_t) * 256 * p.hist_cols);
   p.off_rowtot = off;   off = align256(off + sizeof(uint32_t) * 256);
-  p.off_partials2 = off; off = align256(off + sizeof(unsigned long long) * (nparts + 1));
+  p.off_partials2 = off;
+  off = align256(off + sizeof(unsigned long long) * (std::max<int64_t>(1, cdiv(capacity, kThreads)) + 1));
   p.off_rows = off;     off = align256(off + sizeof(uint4) * std::max<int64_t>(capacity, 1));
   p.off_num_rows = off; off = align256(off + sizeof(uint32_t) * 4);
-  p.off_lsum = off;     off = align256(off + sizeof(uint32_t) * std::max<int64_t>(n, 1));
   p.total = off;
   return p;
 }
@@ -716,7 +744,6 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
   unsigned long long* partials2 = reinterpret_cast<unsigned long long*>(base + plan.off_partials2);
   uint4* rows = reinterpret_cast<uint4*>(base + plan.off_rows);
   uint32_t* num_rows = reinterpret_cast<uint32_t*>(base + plan.off_num_rows);
-  uint32_t* lsum = reinterpret_cast<uint32_t*>(base + plan.off_lsum);
   const unsigned nbv_max = static_cast<unsigned>(std::max<int64_t>(1, cdiv(n, kScanBlock)));
   // instance counts in depth order and the capacity check: rectangle tiles, or
   // (culled) rectangle rows, their reached intervals and the reached tiles
@@ -731,16 +758,18 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
     } else {
       PVG_HIP(launch_fill_u32(num_rows, 0u, 1, s));
       const unsigned nbr = static_cast<unsigned>(cdiv(n, kRowBlock));
+      const unsigned nrb = static_cast<unsigned>(std::min(kMaxGrid, std::max<int64_t>(1, cdiv(cap, kRowBlock))));
       hipLaunchKernelGGL(k_row_count, dim3(nbr), dim3(kThreads), 0, s, vs, order, geom.xy, geom.radius,
                          counters + 1, n, partials);
       hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, counters + 1,
                          static_cast<const int64_t*>(nullptr), n, kRowBlock, num_rows, cap, counters + 2,
                          counters + 3, static_cast<const uint32_t*>(nullptr));
-      hipLaunchKernelGGL(k_row_intervals, dim3(nbr), dim3(kThreads), 0, s, vs, order, geom.xy, geom.conic_op,
-                         geom.radius, counters + 1, n, partials, counters, rows, lsum,
-                         reinterpret_cast<uint2*>(bins->rows), bins->row_base, partials2);
-      hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials2, counters + 1,
-                         static_cast<const int64_t*>(nullptr), n, kRowBlock, counters, cap, counters + 2,
+      hipLaunchKernelGGL(k_row_base, dim3(nbr), dim3(kThreads), 0, s, vs, order, geom.xy, geom.radius, counters + 1,
+                         n, partials, counters, offsets, bins->row_base);
+      hipLaunchKernelGGL(k_row_intervals, dim3(nrb), dim3(kThreads), 0, s, vs, order, geom.xy, geom.conic_op,
+                         geom.radius, offsets, num_rows, counters, rows, partials2);
+      hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials2, num_rows,
+                         static_cast<const int64_t*>(nullptr), int64_t{0}, kRowBlock, counters, cap, counters + 2,
                          counters + 3, counters + 2);
     }
     PVG_HIP(hipGetLastError());
@@ -777,12 +806,10 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
       hipLaunchKernelGGL(k_emit, dim3(nbe), dim3(kThreads), 0, s, vs, order, geom.xy, geom.radius, offsets,
                          counters, bins->keys + start * cap, bins->vals + start * cap);
     } else {
-      const unsigned nbo = static_cast<unsigned>(cdiv(vis_grid, kRowBlock));
-      hipLaunchKernelGGL(k_row_offsets, dim3(nbo), dim3(kThreads), 0, s, order, counters + 1, n, lsum, partials2,
-                         counters, offsets, bins->first);
-      const unsigned nbe = static_cast<unsigned>(std::min(kMaxGrid, std::max<int64_t>(1, cdiv(row_grid, kThreads))));
-      hipLaunchKernelGGL(k_emit_rows, dim3(nbe), dim3(kThreads), 0, s, vs, order, rows, num_rows, offsets, counters,
-                         bins->keys + start * cap, bins->vals + start * cap);
+      const unsigned nre = static_cast<unsigned>(std::min(kMaxGrid, std::max<int64_t>(1, cdiv(row_grid, kRowBlock))));
+      hipLaunchKernelGGL(k_row_emit, dim3(nre), dim3(kThreads), 0, s, rows, num_rows, partials2, counters,
+                         reinterpret_cast<uint2*>(bins->rows), bins->first, bins->keys + start * cap,
+                         bins->vals + start * cap);
     }
     PVG_HIP(hipGetLastError());
   }

@@ -126,7 +126,7 @@ hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t
                              const uint32_t* ranges, bool culled, hipStream_t s);
 // The sorted lists as the adjoint reads them.  Rectangle lists: a pair's
 // record is first[g] + its tile's row-major index in the rectangle.  Culled
-// lists: first[g] + rows[row_base[g] + ty].x + (tx - first reached column).
+// lists: rows[row_base[g] + ty].x + (tx - first reached column).
 struct Lists {
   const uint32_t* vals;
   const uint32_t* ranges;
@@ -152,7 +152,7 @@ struct BinPlan {
   int tile_passes;       // radix passes over the tile key
   // scratch carve-up (bytes offsets into tmp)
   size_t off_vis_keys, off_vis_vals, off_offsets, off_partials, off_hist, off_rowtot, off_partials2, off_rows,
-      off_num_rows, off_lsum, total;
+      off_num_rows, total;
   int64_t hist_cols;     // blocks per radix row (max over the passes)
 };
 BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity);

@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       uint32_t e;
       if (kCulled) {  // the tile's rank among the Gaussian's reached tiles
         const uint2 rw = lists.rows[lists.row_base[g] + static_cast<uint32_t>(ty)];
-        e = first[g] + rw.x + static_cast<uint32_t>(tx - static_cast<int>(rw.y & 0xffffu));
+        e = rw.x + static_cast<uint32_t>(tx - static_cast<int>(rw.y & 0xffffu));
       } else {
         int32_t rect[4];
         tile_rect(m.x, m.y, geom.radius[g], v.GX, v.GY, rect);
@@ -385,8 +385,8 @@ __device__ __forceinline__ void gather_pairs(const ViewSet& vs, const Geom& geom
 }
 
 // Culled lists: a Gaussian's records are its reached tiles in row-major
-// order; the row records give each row's reached columns and the count of
-// reached tiles before it.  One thread walks all rows, or, with the whole
+// order; the row records give each row's reached columns and the index of
+// its first record.  One thread walks all rows, or, with the whole
 // wave, lane l takes rows l, l + 64, ...
 __device__ __forceinline__ void gather_rows(const ViewSet& vs, const Geom& geom, uint32_t g, bool wave, int lane,
                                             const Lists& lists, const float* __restrict__ rec,
@@ -398,14 +398,14 @@ __device__ __forceinline__ void gather_rows(const ViewSet& vs, const Geom& geom,
   int32_t rect[4];
   tile_rect(m.x, m.y, geom.radius[g], v.GX, v.GY, rect);
   const unsigned long long key = (static_cast<unsigned long long>(__float_as_uint(geom.depth[g])) << 32) | g;
-  const uint32_t e0 = lists.first[g], rb = lists.row_base[g];
+  const uint32_t rb = lists.row_base[g];
   for (int ty = rect[1] + (wave ? lane : 0); ty < rect[3]; ty += wave ? 64 : 1) {
     const uint2 rw = lists.rows[rb + static_cast<uint32_t>(ty)];
     const uint32_t lo = rw.y & 0xffffu, len = rw.y >> 16;
     const int64_t trow = v.tile_off + static_cast<int64_t>(ty) * v.GX + lo;
     for (uint32_t c = 0; c < len; ++c) {
       if (key > cut[trow + c]) continue;
-      const float* r = rec + 9 * static_cast<int64_t>(e0 + rw.x + c);
+      const float* r = rec + 9 * static_cast<int64_t>(rw.x + c);
 #pragma unroll
       for (int q = 0; q < 9; ++q) acc[q] += r[q];
     }
