@@ -283,10 +283,10 @@ def main():
     views = [(cam, t, d) for cam in cams for d in (0.0, dt)]
     view_targets = [tgt for tgt in targets for _ in (0.0, dt)]
 
-    def train_step():
+    def train_step(recompute="auto"):
         for p in params:
             p.grad = None
-        imgs = pvg.pvg_render_views(params, views)
+        imgs = pvg.pvg_render_views(params, views, recompute=recompute)
         loss = sum((img - tgt).abs().mean() for img, tgt in zip(imgs, view_targets))
         loss.backward()
         return loss
@@ -344,6 +344,15 @@ def main():
     for name in ("render_fwd", "render_bwd"):
         if counted[name]["calls"]:
             stages[name]["work"] = counted[name]["work"] / counted[name]["calls"] * stages[name]["calls"]
+
+    # the same step with the lists rebuilt in the backward (memory O(N + pixels + one view's instances))
+    train_step(recompute=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        train_step(recompute=True)
+    torch.cuda.synchronize()
+    t_recompute = time.perf_counter() - t0
 
     # forward-only rate over the three H(t) renders
     torch.cuda.synchronize()
@@ -411,6 +420,8 @@ def main():
         "config": {"workload": "pvg-train-step 1M Gaussians SH3 1920x1280, 3 cameras x {H(t), H^(t+0.05)}",
                    "gaussians": N, "width": W, "height": H, "views_per_step": 2 * len(cams)},
         "mpix_per_s_fwd": mpix_fwd,
+        "iters_per_s_recompute": args.steps / t_recompute,
+        "lists": "kept from the forward (recompute='auto': they fit in a tenth of HBM)",
         "instances_per_render": {"rectangle": M, "listed": Lst, "adjoint_records": visited},
         "visible_per_render": n_vis,
         "roofline": roof,

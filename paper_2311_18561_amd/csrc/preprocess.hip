@@ -42,9 +42,6 @@ __global__ void __launch_bounds__(256) k_preprocess(ViewSet vs, Geom geom, unsig
   (void)dummy;
 }
 
-__device__ __forceinline__ void put(float* a, int64_t idx, float val, int accumulate) {
-  if (accumulate) a[idx] += val; else a[idx] = val;
-}
 
 __global__ void __launch_bounds__(256) k_preprocess_bwd(ViewSet vs, Geom geom, const float* __restrict__ g2d,
                                                          pvg_gaussians_grad grad, int accumulate) {
@@ -66,6 +63,23 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(ViewSet vs, Geom geom, c
     }
     return;
   }
+  // With accumulate, the previous values of the non-SH gradient entries are
+  // read up front (the gradient arrays may alias as far as the compiler
+  // knows, so a read after a store could not be moved ahead of it).
+  float o_mu[3] = {0.0f, 0.0f, 0.0f}, o_vel[3] = {0.0f, 0.0f, 0.0f}, o_sc[3] = {0.0f, 0.0f, 0.0f};
+  float o_rot[4] = {0.0f, 0.0f, 0.0f, 0.0f}, o_op = 0.0f, o_l = 0.0f, o_tau = 0.0f, o_beta = 0.0f;
+  if (accumulate) {
+    for (int q = 0; q < 3; ++q) {
+      o_mu[q] = grad.mu[q * n + i];
+      o_vel[q] = grad.vel[q * n + i];
+      o_sc[q] = grad.scale[q * n + i];
+    }
+    for (int q = 0; q < 4; ++q) o_rot[q] = grad.rot[q * n + i];
+    o_op = grad.opacity[i];
+    o_l = grad.period[i];
+    o_tau = grad.tau[i];
+    o_beta = grad.beta[i];
+  }
   Proj P;
   project(v, i, P, true);
   const float* g = g2d + kG2DStride * gi;
@@ -78,15 +92,34 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(ViewSet vs, Geom geom, c
     for (int ch = 0; ch < 3; ++ch) draw[ch] = (P.flags & (kClampR << ch)) ? 0.0f : g[6 + ch];
     float Y[16], wk[16];
     sh_eval_basis(s.degree, P.dir[0], P.dir[1], P.dir[2], Y);
-    for (int k = 0; k < K; ++k) {
-      float acc = 0.0f;
-      for (int ch = 0; ch < 3; ++ch) {
-        put(grad.sh, (3 * k + ch) * n + i, Y[k] * draw[ch], accumulate);
-        acc += s.sh[(3 * k + ch) * n + i] * draw[ch];
+    // four coefficients (12 values) at a time: all reads of a group before its stores
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 4) {
+      if (k0 < K) {
+        float c[12], og[12];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+          const int k = k0 + j / 3;
+          const int64_t o = (3 * k + j % 3) * n + i;
+          c[j] = k < K ? s.sh[o] : 0.0f;
+          og[j] = (k < K && accumulate) ? grad.sh[o] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+          const int k = k0 + j / 3;
+          if (k < K) grad.sh[(3 * k + j % 3) * n + i] = og[j] + Y[k] * draw[j % 3];
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          float acc = 0.0f;
+          for (int ch = 0; ch < 3; ++ch) acc += c[3 * kk + ch] * draw[ch];
+          wk[k0 + kk] = acc;
+        }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) wk[k0 + kk] = 0.0f;
       }
-      wk[k] = acc;
     }
-    for (int k = K; k < 16; ++k) wk[k] = 0.0f;
     float dd[3];
     sh_grad_basis(s.degree, P.dir[0], P.dir[1], P.dir[2], wk, dd);
     const float proj = P.dir[0] * dd[0] + P.dir[1] * dd[1] + P.dir[2] * dd[2];
@@ -155,7 +188,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(ViewSet vs, Geom geom, c
       ds += dM * P.Rq[3 * r + q];
       dR[3 * r + q] = dM * P.sc[q];
     }
-    put(grad.scale, q * n + i, ds, accumulate);
+    grad.scale[q * n + i] = o_sc[q] + ds;
   }
   {
     const float w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
@@ -168,7 +201,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(ViewSet vs, Geom geom, c
     dq[3] = 2.0f * (-w * dR[1] + x * dR[2] + w * dR[3] + y * dR[5] + x * dR[6] + y * dR[7]) -
             4.0f * z * (dR[0] + dR[4]);
     const float qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-    for (int q = 0; q < 4; ++q) put(grad.rot, q * n + i, (dq[q] - P.qn[q] * qd) / P.qnorm, accumulate);
+    for (int q = 0; q < 4; ++q) grad.rot[q * n + i] = o_rot[q] + (dq[q] - P.qn[q] * qd) / P.qnorm;
   }
 
   // temporal model
@@ -194,19 +227,19 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(ViewSet vs, Geom geom, c
   sincosf(phi, &sphi, &cphi);
   const float k = (l / kTwoPi) * sphi;
   for (int q = 0; q < 3; ++q) {
-    put(grad.mu, q * n + i, dmr[q], accumulate);
-    put(grad.vel, q * n + i, dv[q] + k * dmr[q], accumulate);
+    grad.mu[q * n + i] = o_mu[q] + dmr[q];
+    grad.vel[q * n + i] = o_vel[q] + (dv[q] + k * dmr[q]);
   }
   dtau += -cphi * vg;
   dl += (sphi / kTwoPi - (d / l) * cphi) * vg;
   const float qb = d / beta;
   const float eo = expf(-0.5f * (qb * qb));
-  put(grad.opacity, i, eo * dop, accumulate);
+  grad.opacity[i] = o_op + eo * dop;
   dtau += dop * P.op * d / (beta * beta);
   dbeta += dop * P.op * d * d / (beta * beta * beta);
-  put(grad.period, i, dl, accumulate);
-  put(grad.tau, i, dtau, accumulate);
-  put(grad.beta, i, dbeta, accumulate);
+  grad.period[i] = o_l + dl;
+  grad.tau[i] = o_tau + dtau;
+  grad.beta[i] = o_beta + dbeta;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {

@@ -263,11 +263,21 @@ class PVGRender(torch.autograd.Function):
         return (*grads, None, None, None, None, None, None, None)
 
 
+KEEP_FRACTION = 0.1  # recompute="auto" keeps the views' lists while they fit this share of device memory
+
+
+def _bins_bytes(b: Bins) -> int:
+    return sum(t.numel() * t.element_size() for t in (b.keys, b.vals, b.ranges, b.first, b.rows, b.row_base))
+
+
 class PVGRenderViews(torch.autograd.Function):
     """Several renders (cameras x times) of one set of Gaussians as one node:
     the forward launches every view without a host round trip per view (one
-    overflow check at the end), the backward rebuilds each view's lists and
-    adds all views' gradients in the kernels into one zeroed set."""
+    overflow check at the end); the backward uses each view's lists (kept
+    from the forward, or rebuilt bit for bit when recompute is set: memory
+    then stays O(N + pixels + one view's instances)) and adds all views'
+    gradients in the kernels into one zeroed set.  recompute="auto" keeps
+    the lists when they fit KEEP_FRACTION of the device memory."""
 
     @staticmethod
     def forward(ctx, views, recompute, tile_cull, *tensors):
@@ -289,7 +299,10 @@ class PVGRenderViews(torch.autograd.Function):
                 bins = bin_sort(geom, c, tile_cull=tile_cull)
                 plans[k][3] = bins
                 outs[k] = render_fwd(geom, bins, c, f)
-        ctx.meta = (n, degree, recompute, tile_cull, [(c, f, b.capacity) for c, f, _, b in plans])
+        if recompute == "auto":
+            kept_bytes = sum(_bins_bytes(b) for _, _, _, b in plans)
+            recompute = kept_bytes > KEEP_FRACTION * torch.cuda.get_device_properties(dev).total_memory
+        ctx.meta = (n, degree, bool(recompute), tile_cull, [(c, f, b.capacity) for c, f, _, b in plans])
         ctx.kept = None if recompute else [(g, b) for _, _, g, b in plans]
         saved = list(params)
         for _, T, nc in outs:
@@ -316,10 +329,11 @@ class PVGRenderViews(torch.autograd.Function):
         return (None, None, None, *grads)
 
 
-def pvg_render_views(params, views, recompute=True, tile_cull=True):
+def pvg_render_views(params, views, recompute="auto", tile_cull=True):
     """Differentiable renders of the nine parameter tensors for several views:
     views = [(cam, t), (cam, t, dt), ... or (cam, t, dt, advect_mode, bg)];
-    returns one image [3,H,W] per view."""
+    returns one image [3,H,W] per view.  recompute: True, False or "auto"
+    (see PVGRenderViews)."""
     full = []
     for v in views:
         v = tuple(v)

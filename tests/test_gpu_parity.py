@@ -189,7 +189,8 @@ def test_recompute_and_kept_lists_agree(orc):
         np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * (1 + np.abs(b).max()))
 
 
-def test_multi_view_render_matches_single_views():
+@pytest.mark.parametrize("recompute", [True, False])
+def test_multi_view_render_matches_single_views(recompute):
     """pvg_render_views: each image equals the single-view render bit for bit;
     the gradients (added in the kernels) equal the sum of the single-view
     gradients up to FP32 addition order; a view that outgrows the cached
@@ -213,7 +214,7 @@ def test_multi_view_render_matches_single_views():
             for key in list(R._capacity_hint):
                 R._capacity_hint[key] = 64
         params = [p.requires_grad_(True) for p in to_device(cfg["scene"])]
-        imgs = pvg.pvg_render_views(params, views)
+        imgs = pvg.pvg_render_views(params, views, recompute=recompute)
         sum((img * w[k]).sum() for k, img in enumerate(imgs)).backward()
         for a, b in zip(imgs, ref_imgs):
             assert torch.equal(a.detach(), b)
