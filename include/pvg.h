@@ -194,6 +194,26 @@ int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_fram
                    const int32_t* n_contrib, const float* dL_dimg, pvg_gaussians_grad* grad,
                    int32_t accumulate, void* tmp, size_t tmp_bytes, void* stream);
 
+/* Adjoint of several renders of one set of Gaussians (several cameras, and
+ * H(t) with the flow-translated H(t + dt) of Sec. 3.4), summed into one
+ * gradient: for each view the compositing adjoint as in pvg_render_bwd, then
+ * one pass over the Gaussians that applies every view's per-Gaussian chain
+ * rule and writes (accumulate = 0) or adds (accumulate = 1) the sum once, so
+ * the parameters are read and the gradient written once rather than per view.
+ * Host arrays of n_views entries: cams, frames, geoms, bins (as for
+ * pvg_render_bwd, all for the same g), and device pointers final_T[v],
+ * n_contrib[v], dL_dimg[v]; dL_dimg[v] = NULL skips view v.  tmp: at least
+ * pvg_bwd_views_tmp_bytes(n, n_views, largest width and height, largest
+ * bins capacity) bytes.  Bitwise reproducible (no atomics). */
+int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_camera* cams,
+                         const pvg_frame* frames, const pvg_geom* geoms, const pvg_bins* bins,
+                         const float* const* final_T, const int32_t* const* n_contrib,
+                         const float* const* dL_dimg, pvg_gaussians_grad* grad, int32_t accumulate,
+                         void* tmp, size_t tmp_bytes, void* stream);
+/* Scratch bytes of pvg_render_bwd_views.  Host only. */
+int pvg_bwd_views_tmp_bytes(int64_t n, int32_t n_views, int32_t max_width, int32_t max_height,
+                            int64_t max_capacity, size_t* bytes);
+
 /* ---- stage timing (HIP events recorded on the launch stream) ------------ */
 enum pvg_stage {
   PVG_STAGE_PREPROCESS = 0, PVG_STAGE_COMPACT, PVG_STAGE_DEPTH_SORT, PVG_STAGE_SCAN_EMIT,

@@ -165,13 +165,16 @@ static ViewSet single(const View& v, int64_t n) {
   return vs;
 }
 
-size_t bwd_scratch_bytes(int64_t n, int64_t tiles, int64_t capacity, size_t* off_rec, size_t* off_cut) {
+size_t bwd_scratch_bytes(int64_t n, int32_t views, int64_t tiles, int64_t capacity, size_t* off_rec, size_t* off_cut,
+                         size_t* slot_bytes) {
   auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
-  const size_t g2d = al(sizeof(float) * kG2DStride * static_cast<size_t>(std::max<int64_t>(n, 1)));
+  const size_t slot = al(sizeof(float) * kG2DStride * static_cast<size_t>(std::max<int64_t>(n, 1)));
+  const size_t g2d = slot * static_cast<size_t>(std::max(views, 1));
   const size_t rec = al(sizeof(float) * 9 * static_cast<size_t>(std::max<int64_t>(capacity, 1)));
   const size_t cut = al(sizeof(unsigned long long) * static_cast<size_t>(std::max<int64_t>(tiles, 1)));
   if (off_rec) *off_rec = g2d;
   if (off_cut) *off_cut = g2d + rec;
+  if (slot_bytes) *slot_bytes = slot;
   return g2d + rec + cut;
 }
 
@@ -192,7 +195,7 @@ int pvg_workspace_query(int64_t n, int32_t width, int32_t height, int64_t capaci
   }
   const int64_t tiles = static_cast<int64_t>((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
   out->bin_tmp_bytes = plan_bins(n, tiles, capacity).total;
-  out->bwd_tmp_bytes = bwd_scratch_bytes(n, tiles, capacity, nullptr, nullptr);
+  out->bwd_tmp_bytes = bwd_scratch_bytes(n, 1, tiles, capacity, nullptr, nullptr, nullptr);
   out->num_tiles = tiles;
   return PVG_OK;
 }
@@ -239,43 +242,112 @@ int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera*
 int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_frame* frame, const pvg_geom* geom,
                    const pvg_bins* bins, const float* final_T, const int32_t* n_contrib, const float* dL_dimg,
                    pvg_gaussians_grad* grad, int32_t accumulate, void* tmp, size_t tmp_bytes, void* stream) {
-  if (!check_gaussians(g) || !check_camera(cam) || !check_frame(frame) || !check_geom(geom, g ? g->n : 0) ||
-      !check_bins(bins))
+  if (!final_T || !n_contrib || !dL_dimg) { set_error("an input array is null"); return PVG_ERR_INVALID; }
+  return pvg_render_bwd_views(g, 1, cam, frame, geom, bins, &final_T, &n_contrib, &dL_dimg, grad, accumulate, tmp,
+                              tmp_bytes, stream);
+}
+
+int pvg_bwd_views_tmp_bytes(int64_t n, int32_t n_views, int32_t max_width, int32_t max_height, int64_t max_capacity,
+                            size_t* bytes) {
+  if (!bytes || n < 0 || n_views < 1 || max_width <= 0 || max_height <= 0 || max_capacity < 0 ||
+      max_capacity > 0xffffffffll) {
+    set_error("invalid scratch query");
     return PVG_ERR_INVALID;
-  if (!final_T || !n_contrib || !dL_dimg || !grad) { set_error("an input array is null"); return PVG_ERR_INVALID; }
-  if (g->n > 0 && (!grad->mu || !grad->scale || !grad->rot || !grad->sh || !grad->opacity || !grad->vel ||
-                   !grad->period || !grad->tau || !grad->beta)) {
+  }
+  const int64_t tiles = static_cast<int64_t>((max_width + kTile - 1) / kTile) * ((max_height + kTile - 1) / kTile);
+  *bytes = bwd_scratch_bytes(n, std::min(n_views, kMaxBwdViews), tiles, max_capacity, nullptr, nullptr, nullptr);
+  return PVG_OK;
+}
+
+int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_camera* cams, const pvg_frame* frames,
+                         const pvg_geom* geoms, const pvg_bins* bins, const float* const* final_T,
+                         const int32_t* const* n_contrib, const float* const* dL_dimg, pvg_gaussians_grad* grad,
+                         int32_t accumulate, void* tmp, size_t tmp_bytes, void* stream) {
+  if (!check_gaussians(g)) return PVG_ERR_INVALID;
+  if (n_views < 1 || !cams || !frames || !geoms || !bins || !final_T || !n_contrib || !dL_dimg) {
+    set_error("n_views < 1 or a per-view array is null");
+    return PVG_ERR_INVALID;
+  }
+  if (!grad || (g->n > 0 && (!grad->mu || !grad->scale || !grad->rot || !grad->sh || !grad->opacity ||
+                             !grad->vel || !grad->period || !grad->tau || !grad->beta))) {
     set_error("a gradient array is null");
     return PVG_ERR_INVALID;
   }
-  if (g->n > 0 && !bins->first) {
-    set_error("bins.first is null: the adjoint needs each Gaussian's first instance index");
-    return PVG_ERR_INVALID;
+  int64_t max_tiles = 1, max_cap = 0;
+  for (int32_t k = 0; k < n_views; ++k) {
+    if (!check_camera(&cams[k]) || !check_frame(&frames[k]) || !check_geom(&geoms[k], g->n) ||
+        !check_bins(&bins[k]))
+      return PVG_ERR_INVALID;
+    if (!dL_dimg[k]) continue;  // no gradient flows into this view
+    if (!final_T[k] || !n_contrib[k]) { set_error("view %d: final_T or n_contrib is null", k); return PVG_ERR_INVALID; }
+    if (g->n > 0 && !bins[k].first) {
+      set_error("view %d: bins.first is null: the adjoint needs each Gaussian's first instance index", k);
+      return PVG_ERR_INVALID;
+    }
+    if (g->n > 0 && bins[k].tile_cull && (!bins[k].rows || !bins[k].row_base)) {
+      set_error("view %d: bins.rows / bins.row_base are null: the adjoint of culled lists needs them", k);
+      return PVG_ERR_INVALID;
+    }
+    max_tiles = std::max(max_tiles, tiles_of(&cams[k]));
+    max_cap = std::max(max_cap, bins[k].capacity);
   }
-  if (g->n > 0 && bins->tile_cull && (!bins->rows || !bins->row_base)) {
-    set_error("bins.rows / bins.row_base are null: the adjoint of culled lists needs the row records");
-    return PVG_ERR_INVALID;
-  }
+  const int32_t slots = std::min(n_views, kMaxBwdViews);
   size_t off_rec = 0, off_cut = 0;
-  const size_t need = bwd_scratch_bytes(g->n, tiles_of(cam), bins->capacity, &off_rec, &off_cut);
+  const size_t need = bwd_scratch_bytes(g->n, slots, max_tiles, max_cap, &off_rec, &off_cut, nullptr);
   if (!tmp || tmp_bytes < need) {
     set_error("render_bwd scratch of %zu bytes is smaller than the %zu required", tmp_bytes, need);
     return PVG_ERR_NOMEM;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  View v = make_view(g, cam, frame);
-  v.final_T = const_cast<float*>(final_T);
-  v.n_contrib = const_cast<int32_t*>(n_contrib);
-  v.dL_dimg = dL_dimg;
-  const ViewSet vs = single(v, g->n);
   char* base = static_cast<char*>(tmp);
-  float* g2d = reinterpret_cast<float*>(base);
+  size_t slot_bytes = 0;
+  bwd_scratch_bytes(g->n, slots, max_tiles, max_cap, &off_rec, &off_cut, &slot_bytes);
   float* rec = reinterpret_cast<float*>(base + off_rec);
   unsigned long long* cut = reinterpret_cast<unsigned long long*>(base + off_cut);
-  const Lists lists{bins->vals, bins->ranges, bins->first, bins->tile_cull != 0,
-                    reinterpret_cast<const uint2*>(bins->rows), bins->row_base};
-  PVG_HIP(launch_render_bwd(vs, to_geom(geom), lists, rec, cut, g2d, s));
-  PVG_HIP(launch_preprocess_bwd(vs, to_geom(geom), g2d, *grad, accumulate, s));
+  BwdViews pk;
+  std::memset(&pk, 0, sizeof(pk));
+  bool first_group = true;
+  auto flush = [&]() -> int {
+    if (pk.nv == 0) return PVG_OK;
+    PVG_HIP(launch_preprocess_bwd(pk, *grad, first_group ? accumulate : 1, s));
+    first_group = false;
+    pk.nv = 0;
+    return PVG_OK;
+  };
+  for (int32_t k = 0; k < n_views; ++k) {
+    if (!dL_dimg[k]) continue;
+    View v = make_view(g, &cams[k], &frames[k]);
+    v.final_T = const_cast<float*>(final_T[k]);
+    v.n_contrib = const_cast<int32_t*>(n_contrib[k]);
+    v.dL_dimg = dL_dimg[k];
+    float* g2d = reinterpret_cast<float*>(base + slot_bytes * static_cast<size_t>(pk.nv));
+    const Lists lists{bins[k].vals, bins[k].ranges, bins[k].first, bins[k].tile_cull != 0,
+                      reinterpret_cast<const uint2*>(bins[k].rows), bins[k].row_base};
+    PVG_HIP(launch_render_bwd(single(v, g->n), to_geom(&geoms[k]), lists, rec, cut, g2d, s));
+    pk.views[pk.nv] = v;
+    pk.radius[pk.nv] = geoms[k].radius;
+    pk.g2d[pk.nv] = g2d;
+    ++pk.nv;
+    if (pk.nv == kMaxBwdViews) {
+      const int st = flush();
+      if (st != PVG_OK) return st;
+    }
+  }
+  const int st = flush();
+  if (st != PVG_OK) return st;
+  if (first_group && !accumulate && g->n > 0) {
+    // no view carries a gradient: overwriting still means writing zeros
+    const int64_t n = g->n, K = (g->sh_degree + 1) * (g->sh_degree + 1);
+    PVG_HIP(launch_fill_f32(grad->mu, 0.0f, 3 * n, s));
+    PVG_HIP(launch_fill_f32(grad->scale, 0.0f, 3 * n, s));
+    PVG_HIP(launch_fill_f32(grad->rot, 0.0f, 4 * n, s));
+    PVG_HIP(launch_fill_f32(grad->sh, 0.0f, 3 * K * n, s));
+    PVG_HIP(launch_fill_f32(grad->opacity, 0.0f, n, s));
+    PVG_HIP(launch_fill_f32(grad->vel, 0.0f, 3 * n, s));
+    PVG_HIP(launch_fill_f32(grad->period, 0.0f, n, s));
+    PVG_HIP(launch_fill_f32(grad->tau, 0.0f, n, s));
+    PVG_HIP(launch_fill_f32(grad->beta, 0.0f, n, s));
+  }
   return PVG_OK;
 }
 

@@ -6,10 +6,11 @@
 // are structure-of-arrays, so a wave reads 256 contiguous bytes per field; the
 // SH coefficients (up to 192 B per Gaussian) are only read for visible ones.
 //
-// Adjoint: one thread per Gaussian recomputes the forward state (bit-identical,
-// so every branch decision is the forward's) and applies the chain rule from
-// the screen-space gradient (2D mean, conic, opacity, colour) back to
-// {mu, q, s, o, c, tau, beta, v} and l.
+// Adjoint: one thread per Gaussian recomputes the forward state of each view
+// (bit-identical, so every branch decision is the forward's), applies the
+// chain rule from that view's screen-space gradient (2D mean, conic,
+// opacity, colour) back to {mu, q, s, o, c, tau, beta, v} and l, sums over
+// the views in registers and writes each gradient entry once.
 #include "pvg_math.hpp"
 
 namespace pvg {
@@ -43,87 +44,46 @@ __global__ void __launch_bounds__(256) k_preprocess(ViewSet vs, Geom geom, unsig
 }
 
 
-__global__ void __launch_bounds__(256) k_preprocess_bwd(ViewSet vs, Geom geom, const float* __restrict__ g2d,
-                                                         pvg_gaussians_grad grad, int accumulate) {
-  const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (gi >= live_gauss(vs)) return;
-  const View& v = view_at(vs, view_of_gauss(vs, gi));
-  const int64_t i = gi - v.geom_off;
+// Gradient entries of one Gaussian other than its SH coefficients.
+struct GeoGrad {
+  float mu[3], scale[3], rot[4], vel[3], op, l, tau, beta;
+};
+
+// One view's chain rule for everything but dL/dsh, added into acc.  g is the
+// view's screen-space gradient of the Gaussian: d(mean x, y), d(conic A, B, C),
+// d(opacity), d(rgb); on return g[6..8] holds d(rgb) with clamped channels
+// zeroed and g[9..11] the view direction, which is all dL/dsh needs.
+__device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const Proj& P, float* g,
+                                                 GeoGrad& acc) {
   const Scene& s = v.s;
   const int64_t n = s.n;
   const int K = (s.degree + 1) * (s.degree + 1);
-  if (geom.radius[gi] <= 0) {
-    if (!accumulate) {
-      for (int c = 0; c < 3; ++c) {
-        grad.mu[c * n + i] = 0.0f; grad.scale[c * n + i] = 0.0f; grad.vel[c * n + i] = 0.0f;
-      }
-      for (int c = 0; c < 4; ++c) grad.rot[c * n + i] = 0.0f;
-      for (int c = 0; c < 3 * K; ++c) grad.sh[c * n + i] = 0.0f;
-      grad.opacity[i] = 0.0f; grad.period[i] = 0.0f; grad.tau[i] = 0.0f; grad.beta[i] = 0.0f;
-    }
-    return;
-  }
-  // With accumulate, the previous values of the non-SH gradient entries are
-  // read up front (the gradient arrays may alias as far as the compiler
-  // knows, so a read after a store could not be moved ahead of it).
-  float o_mu[3] = {0.0f, 0.0f, 0.0f}, o_vel[3] = {0.0f, 0.0f, 0.0f}, o_sc[3] = {0.0f, 0.0f, 0.0f};
-  float o_rot[4] = {0.0f, 0.0f, 0.0f, 0.0f}, o_op = 0.0f, o_l = 0.0f, o_tau = 0.0f, o_beta = 0.0f;
-  if (accumulate) {
-    for (int q = 0; q < 3; ++q) {
-      o_mu[q] = grad.mu[q * n + i];
-      o_vel[q] = grad.vel[q * n + i];
-      o_sc[q] = grad.scale[q * n + i];
-    }
-    for (int q = 0; q < 4; ++q) o_rot[q] = grad.rot[q * n + i];
-    o_op = grad.opacity[i];
-    o_l = grad.period[i];
-    o_tau = grad.tau[i];
-    o_beta = grad.beta[i];
-  }
-  Proj P;
-  project(v, i, P, true);
-  const float* g = g2d + kG2DStride * gi;
   const float dmx = g[0], dmy = g[1], dA = g[2], dB = g[3], dC = g[4], dop = g[5];
   float dmr[3] = {0.0f, 0.0f, 0.0f};
 
-  // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2), dir = u / |u|
+  // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2), dir = u / |u|; its
+  // dependence on the direction moves the mean
   {
     float draw[3];
     for (int ch = 0; ch < 3; ++ch) draw[ch] = (P.flags & (kClampR << ch)) ? 0.0f : g[6 + ch];
-    float Y[16], wk[16];
-    sh_eval_basis(s.degree, P.dir[0], P.dir[1], P.dir[2], Y);
-    // four coefficients (12 values) at a time: all reads of a group before its stores
+    float wk[16];
 #pragma unroll
-    for (int k0 = 0; k0 < 16; k0 += 4) {
-      if (k0 < K) {
-        float c[12], og[12];
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-          const int k = k0 + j / 3;
-          const int64_t o = (3 * k + j % 3) * n + i;
-          c[j] = k < K ? s.sh[o] : 0.0f;
-          og[j] = (k < K && accumulate) ? grad.sh[o] : 0.0f;
-        }
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-          const int k = k0 + j / 3;
-          if (k < K) grad.sh[(3 * k + j % 3) * n + i] = og[j] + Y[k] * draw[j % 3];
-        }
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          float acc = 0.0f;
-          for (int ch = 0; ch < 3; ++ch) acc += c[3 * kk + ch] * draw[ch];
-          wk[k0 + kk] = acc;
-        }
-      } else {
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) wk[k0 + kk] = 0.0f;
-      }
+    for (int k = 0; k < 16; ++k) {
+      float w = 0.0f;
+      if (k < K)
+        for (int ch = 0; ch < 3; ++ch) w += s.sh[(3 * k + ch) * n + i] * draw[ch];
+      wk[k] = w;
+      // read the coefficients four at a time rather than all 48 at once
+      if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
     float dd[3];
     sh_grad_basis(s.degree, P.dir[0], P.dir[1], P.dir[2], wk, dd);
     const float proj = P.dir[0] * dd[0] + P.dir[1] * dd[1] + P.dir[2] * dd[2];
     for (int c = 0; c < 3; ++c) dmr[c] += (dd[c] - P.dir[c] * proj) / P.ulen;
+    for (int c = 0; c < 3; ++c) {
+      g[6 + c] = draw[c];
+      g[9 + c] = P.dir[c];
+    }
   }
 
   // conic (A, B, C) = inverse of the dilated covariance [[a, b], [b, c]]
@@ -188,7 +148,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(ViewSet vs, Geom geom, c
       ds += dM * P.Rq[3 * r + q];
       dR[3 * r + q] = dM * P.sc[q];
     }
-    grad.scale[q * n + i] = o_sc[q] + ds;
+    acc.scale[q] += ds;
   }
   {
     const float w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
@@ -201,7 +161,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(ViewSet vs, Geom geom, c
     dq[3] = 2.0f * (-w * dR[1] + x * dR[2] + w * dR[3] + y * dR[5] + x * dR[6] + y * dR[7]) -
             4.0f * z * (dR[0] + dR[4]);
     const float qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-    for (int q = 0; q < 4; ++q) grad.rot[q * n + i] = o_rot[q] + (dq[q] - P.qn[q] * qd) / P.qnorm;
+    for (int q = 0; q < 4; ++q) acc.rot[q] += (dq[q] - P.qn[q] * qd) / P.qnorm;
   }
 
   // temporal model
@@ -227,19 +187,94 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(ViewSet vs, Geom geom, c
   sincosf(phi, &sphi, &cphi);
   const float k = (l / kTwoPi) * sphi;
   for (int q = 0; q < 3; ++q) {
-    grad.mu[q * n + i] = o_mu[q] + dmr[q];
-    grad.vel[q * n + i] = o_vel[q] + (dv[q] + k * dmr[q]);
+    acc.mu[q] += dmr[q];
+    acc.vel[q] += dv[q] + k * dmr[q];
   }
   dtau += -cphi * vg;
   dl += (sphi / kTwoPi - (d / l) * cphi) * vg;
   const float qb = d / beta;
   const float eo = expf(-0.5f * (qb * qb));
-  grad.opacity[i] = o_op + eo * dop;
+  acc.op += eo * dop;
   dtau += dop * P.op * d / (beta * beta);
   dbeta += dop * P.op * d * d / (beta * beta * beta);
-  grad.period[i] = o_l + dl;
-  grad.tau[i] = o_tau + dtau;
-  grad.beta[i] = o_beta + dbeta;
+  acc.l += dl;
+  acc.tau += dtau;
+  acc.beta += dbeta;
+}
+
+// Adjoint of the per-Gaussian stage for up to kMaxBwdViews views of one set
+// of Gaussians: each Gaussian's gradient is summed over the views in
+// registers (the SH part in a second loop over the views, to bound register
+// use) and written, or added, once.  A Gaussian no view sees gets zeros
+// (accumulate = 0) or is left alone.
+// 3 waves per SIMD: the compiler fits the view loop in 168 registers without spilling
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_preprocess_bwd(BwdViews pk, pvg_gaussians_grad grad, int accumulate) {
+  const Scene& s = pk.views[0].s;
+  const int64_t n = s.n;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int K = (s.degree + 1) * (s.degree + 1);
+  bool any = false;
+  for (int v = 0; v < pk.nv; ++v) any = any || pk.radius[v][i] > 0;
+  if (!any) {
+    if (!accumulate) {
+      for (int c = 0; c < 3; ++c) {
+        grad.mu[c * n + i] = 0.0f; grad.scale[c * n + i] = 0.0f; grad.vel[c * n + i] = 0.0f;
+      }
+      for (int c = 0; c < 4; ++c) grad.rot[c * n + i] = 0.0f;
+      for (int c = 0; c < 3 * K; ++c) grad.sh[c * n + i] = 0.0f;
+      grad.opacity[i] = 0.0f; grad.period[i] = 0.0f; grad.tau[i] = 0.0f; grad.beta[i] = 0.0f;
+    }
+    return;
+  }
+  GeoGrad acc = {};
+  if (accumulate) {  // start from the previous values
+    for (int q = 0; q < 3; ++q) {
+      acc.mu[q] = grad.mu[q * n + i];
+      acc.vel[q] = grad.vel[q * n + i];
+      acc.scale[q] = grad.scale[q * n + i];
+    }
+    for (int q = 0; q < 4; ++q) acc.rot[q] = grad.rot[q * n + i];
+    acc.op = grad.opacity[i];
+    acc.l = grad.period[i];
+    acc.tau = grad.tau[i];
+    acc.beta = grad.beta[i];
+  }
+  for (int v = 0; v < pk.nv; ++v) {
+    if (pk.radius[v][i] <= 0) continue;
+    Proj P;
+    project(pk.views[v], i, P, true);
+    adjoint_geometry(pk.views[v], i, P, pk.g2d[v] + kG2DStride * i, acc);
+  }
+  for (int q = 0; q < 3; ++q) {
+    grad.mu[q * n + i] = acc.mu[q];
+    grad.vel[q * n + i] = acc.vel[q];
+    grad.scale[q * n + i] = acc.scale[q];
+  }
+  for (int q = 0; q < 4; ++q) grad.rot[q * n + i] = acc.rot[q];
+  grad.opacity[i] = acc.op;
+  grad.period[i] = acc.l;
+  grad.tau[i] = acc.tau;
+  grad.beta[i] = acc.beta;
+
+  // dL/dsh_k = Y_k(dir) d(rgb), where the colour is not clamped
+  float gsh[48];
+#pragma unroll
+  for (int j = 0; j < 48; ++j) gsh[j] = (j < 3 * K && accumulate) ? grad.sh[j * n + i] : 0.0f;
+  for (int v = 0; v < pk.nv; ++v) {
+    if (pk.radius[v][i] <= 0) continue;
+    const float* g = pk.g2d[v] + kG2DStride * i;  // d(rgb) unclamped part and direction, from the first loop
+    const float draw[3] = {g[6], g[7], g[8]};
+    float Y[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) Y[k] = 0.0f;
+    sh_eval_basis(s.degree, g[9], g[10], g[11], Y);
+#pragma unroll
+    for (int j = 0; j < 48; ++j) gsh[j] += Y[j / 3] * draw[j % 3];
+  }
+#pragma unroll
+  for (int j = 0; j < 48; ++j)
+    if (j < 3 * K) grad.sh[j * n + i] = gsh[j];
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
@@ -260,12 +295,12 @@ hipError_t launch_preprocess(const ViewSet& vs, const Geom& geom, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_preprocess_bwd(const ViewSet& vs, const Geom& geom, const float* g2d,
-                                 const pvg_gaussians_grad& grad, int accumulate, hipStream_t s) {
-  if (vs.total_gauss == 0) return hipSuccess;
+hipError_t launch_preprocess_bwd(const BwdViews& pk, const pvg_gaussians_grad& grad, int accumulate,
+                                 hipStream_t s) {
+  const int64_t n = pk.views[0].s.n;
+  if (n == 0 || pk.nv <= 0) return hipSuccess;
   StageScope scope(PVG_STAGE_PREPROCESS_BWD, s);
-  hipLaunchKernelGGL(k_preprocess_bwd, dim3(grid_for(vs.total_gauss, 256)), dim3(256), 0, s, vs, geom, g2d, grad,
-                     accumulate);
+  hipLaunchKernelGGL(k_preprocess_bwd, dim3(grid_for(n, 256)), dim3(256), 0, s, pk, grad, accumulate);
   return hipGetLastError();
 }
 

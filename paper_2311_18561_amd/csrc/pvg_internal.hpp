@@ -119,8 +119,18 @@ unsigned long long* profile_work_counter(int stage);  // device counter, or null
 
 // kernel launchers (stream-ordered, no host sync)
 hipError_t launch_preprocess(const ViewSet& vs, const Geom& geom, hipStream_t s);
-hipError_t launch_preprocess_bwd(const ViewSet& vs, const Geom& geom, const float* g2d,
-                                 const pvg_gaussians_grad& grad, int accumulate, hipStream_t s);
+// Views of one set of Gaussians for the per-Gaussian adjoint (same scene in
+// every view): each view's camera and frame, its radii (visibility) and its
+// screen-space gradient g2d [n][kG2DStride].
+constexpr int kMaxBwdViews = 8;
+struct BwdViews {
+  int32_t nv;
+  View views[kMaxBwdViews];
+  const int32_t* radius[kMaxBwdViews];
+  float* g2d[kMaxBwdViews];  // the adjoint also leaves per-view scratch values in slots 6..11
+};
+hipError_t launch_preprocess_bwd(const BwdViews& pk, const pvg_gaussians_grad& grad, int accumulate,
+                                 hipStream_t s);
 // culled: the lists hold only tiles that pass tile_reachable (the render skips the test)
 hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals,
                              const uint32_t* ranges, bool culled, hipStream_t s);
@@ -138,8 +148,9 @@ struct Lists {
 // adjoint of compositing: per-(Gaussian, tile) records, then their per-Gaussian sums into g2d
 hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const Lists& lists, float* rec,
                              unsigned long long* cut, float* g2d, hipStream_t s);
-// scratch of pvg_render_bwd: g2d [n][12] | rec [capacity][9] | cut [tiles] (u64)
-size_t bwd_scratch_bytes(int64_t n, int64_t tiles, int64_t capacity, size_t* off_rec, size_t* off_cut);
+// scratch of the adjoint: g2d [views][n][12] | rec [capacity][9] | cut [tiles] (u64)
+size_t bwd_scratch_bytes(int64_t n, int32_t views, int64_t tiles, int64_t capacity, size_t* off_rec,
+                         size_t* off_cut, size_t* slot_bytes);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 

@@ -192,6 +192,10 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
 template <bool kCount, bool kCulled>
 __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists lists, float* rec,
                                                    unsigned long long* cut, unsigned long long* pair_counter) {
+  // The gradient arithmetic may fuse multiply-adds.  Every branch decision
+  // (exponent sign, alpha thresholds) comes from pair_power and single
+  // products, which stay unfused, so the adjoint takes the forward's.
+#pragma clang fp contract(fast)
   const uint32_t* __restrict__ vals = lists.vals;
   const uint32_t* __restrict__ ranges = lists.ranges;
   const uint32_t* __restrict__ first = lists.first;
@@ -276,6 +280,9 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       const float4 gc = s_co[j];
       const float4 cc = s_rgb[j];
       const int pos = __float_as_int(cc.w);
+      // a[0..4] first hold the lane's moments sum(gp dx), sum(gp dy),
+      // sum(gp dx^2), sum(gp dx dy), sum(gp dy^2) of the power gradient gp;
+      // the conic turns them into the mean and conic gradients once per lane
       float a[9];
 #pragma unroll
       for (int q = 0; q < 9; ++q) a[q] = 0.0f;
@@ -303,11 +310,19 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
         const bool nc = ok && !(raw > kAlphaMax);
         const float gp = nc ? alpha * dal : 0.0f;
         a[5] += nc ? G * dal : 0.0f;
-        a[2] = fmaf(-0.5f * dx * dx, gp, a[2]);
-        a[3] = fmaf(-dx * dy, gp, a[3]);
-        a[4] = fmaf(-0.5f * dy * dy, gp, a[4]);
-        a[0] = fmaf(-(gc.x * dx + gc.y * dy), gp, a[0]);
-        a[1] = fmaf(-(gc.y * dx + gc.z * dy), gp, a[1]);
+        a[0] = fmaf(dx, gp, a[0]);
+        a[1] = fmaf(dy, gp, a[1]);
+        a[2] = fmaf(dx * dx, gp, a[2]);
+        a[3] = fmaf(dx * dy, gp, a[3]);
+        a[4] = fmaf(dy * dy, gp, a[4]);
+      }
+      {  // power = -(A dx^2 + C dy^2)/2 - B dx dy, d(mean) = d(dx, dy)
+        const float sx = a[0], sy = a[1];
+        a[0] = -(gc.x * sx + gc.y * sy);
+        a[1] = -(gc.y * sx + gc.z * sy);
+        a[2] *= -0.5f;
+        a[3] = -a[3];
+        a[4] *= -0.5f;
       }
       const bool wany = __any(any);
       if (wany) {

@@ -225,6 +225,38 @@ def render_bwd(params, n, degree, cam, frame, geom, bins, final_T, n_contrib, dL
     return grads
 
 
+def render_bwd_views(params, n, degree, views, grads=None, accumulate=False):
+    """One adjoint call for several views of the same Gaussians:
+    views = [(cam, frame, geom, bins, final_T, n_contrib, dL_dimg or None)];
+    the per-Gaussian chain rule of all views is summed in registers and the
+    gradient written (or added) once."""
+    dev = params[0].device
+    if grads is None:
+        grads = [torch.empty_like(p) for p in params]
+    nv = len(views)
+    g = gaussians_struct(params, n, degree)
+    gg = L.GaussiansGrad()
+    for name, t in zip(FIELDS, grads):
+        setattr(gg, name, t.data_ptr())
+    cams = (L.Camera * nv)(*[v[0] for v in views])
+    frames = (L.Frame * nv)(*[v[1] for v in views])
+    geoms = (L.Geom * nv)(*[v[2].struct() for v in views])
+    bins = (L.Bins * nv)(*[v[3].struct() for v in views])
+    dls = [None if v[6] is None else v[6].contiguous() for v in views]
+    f_t = (C.c_void_p * nv)(*[v[4].data_ptr() for v in views])
+    n_c = (C.c_void_p * nv)(*[v[5].data_ptr() for v in views])
+    d_l = (C.c_void_p * nv)(*[None if d is None else d.data_ptr() for d in dls])
+    size = C.c_size_t()
+    lib = L.load()
+    L.check(lib.pvg_bwd_views_tmp_bytes(n, nv, max(int(v[0].width) for v in views),
+                                        max(int(v[0].height) for v in views),
+                                        max(v[3].capacity for v in views), C.byref(size)))
+    tmp = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=dev)
+    L.check(lib.pvg_render_bwd_views(C.byref(g), nv, cams, frames, geoms, bins, f_t, n_c, d_l, C.byref(gg),
+                                     1 if accumulate else 0, _p(tmp), int(size.value), _stream_handle()))
+    return grads
+
+
 def render(params, cam: dict, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), tile_cull=True):
     """Forward only: returns (img [3,H,W], final_T [H,W], n_contrib [H,W], geom, bins)."""
     params, n, degree = _check_params(params)
@@ -315,17 +347,26 @@ class PVGRenderViews(torch.autograd.Function):
         n, degree, recompute, tile_cull, plan = ctx.meta
         saved = ctx.saved_tensors
         params = list(saved[:9])
-        grads = [torch.zeros_like(p) for p in params]
-        for k, (c, f, cap) in enumerate(plan):
-            if dimgs[k] is None:
-                continue
-            T, nc = saved[9 + 2 * k], saved[10 + 2 * k]
-            if recompute:  # same inputs give the forward's lists bit for bit, within the same capacity
+        grads = [torch.empty_like(p) for p in params]
+        if recompute:
+            # one view at a time, so only one view's lists exist at once; the
+            # same inputs give the forward's lists bit for bit, within its capacity
+            first = True
+            for k, (c, f, cap) in enumerate(plan):
+                if dimgs[k] is None:
+                    continue
                 geom = preprocess(params, n, degree, c, f)
                 bins = bin_sort_nosync(geom, c, cap, tile_cull)
-            else:
-                geom, bins = ctx.kept[k]
-            render_bwd(params, n, degree, c, f, geom, bins, T, nc, dimgs[k], grads=grads, accumulate=True)
+                render_bwd_views(params, n, degree, [(c, f, geom, bins, saved[9 + 2 * k], saved[10 + 2 * k],
+                                                      dimgs[k])], grads=grads, accumulate=not first)
+                first = False
+            if first:
+                for gr in grads:
+                    gr.zero_()
+        else:
+            views = [(c, f, geom, bins, saved[9 + 2 * k], saved[10 + 2 * k], dimgs[k])
+                     for k, ((c, f, _), (geom, bins)) in enumerate(zip(plan, ctx.kept))]
+            render_bwd_views(params, n, degree, views, grads=grads, accumulate=False)
         return (None, None, None, *grads)
 
 
