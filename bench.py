@@ -46,7 +46,7 @@ def parse():
     return ap.parse_args()
 
 
-def stage_bytes(stage, n, n_vis, M, Lst, visited, K, tiles, tile_passes):
+def stage_bytes(stage, n, n_vis, M, Lst, visited, K, tiles, tile_passes, views=1):
     """Algorithmic HBM bytes of one invocation of a stage.  M: rectangle
     instances, Lst: listed (culled) instances, visited: (Gaussian, tile)
     records the adjoint writes and the gather reads."""
@@ -68,7 +68,9 @@ def stage_bytes(stage, n, n_vis, M, Lst, visited, K, tiles, tile_passes):
         # per visible Gaussian its record (40 B) in and nine sums out, the cut keys, the visited records
         return n * 4 + n_vis * (40 + 36) + tiles * 8 + visited * 36
     if stage == "preprocess_bwd":
-        return n * (4 + (17 + 3 * K) * 4) + n_vis * (36 + 68 + 12 * K)
+        # per view: radii and the visible Gaussians' screen-space gradients; once:
+        # the visible Gaussians' parameters in, every gradient entry out
+        return views * (n * 4 + n_vis * 36) + n * (17 + 3 * K) * 4 + n_vis * (68 + 12 * K)
     return 0
 
 
@@ -387,7 +389,8 @@ def main():
             row.update(bound="alu", pairs_per_call=pairs,
                        tflops=pairs * FLOPS_PER_PAIR[name] / (per_launch_ms * 1e-3) / 1e12)
         else:
-            b = stage_bytes(name, N, n_vis, M, Lst, visited, K, tiles, tile_passes)
+            per_call_views = 2 * len(cams) / row["calls_per_step"] if name == "preprocess_bwd" else 1
+            b = stage_bytes(name, N, n_vis, M, Lst, visited, K, tiles, tile_passes, views=per_call_views)
             row.update(bound="hbm", bytes_per_call=b, gbs=b / (per_launch_ms * 1e-3) / 1e9)
         table[name] = row
     dom = max((k for k in table if k in SINGLE_KERNEL), key=lambda k: table[k]["ms_per_step"])
