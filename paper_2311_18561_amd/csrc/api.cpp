@@ -165,17 +165,19 @@ static ViewSet single(const View& v, int64_t n) {
   return vs;
 }
 
-size_t bwd_scratch_bytes(int64_t n, int32_t views, int64_t tiles, int64_t capacity, size_t* off_rec, size_t* off_cut,
-                         size_t* slot_bytes) {
+size_t bwd_scratch_bytes(int64_t n, int32_t views, int64_t capacity, size_t* off_rec, size_t* off_vis,
+                         size_t* vis_bytes, size_t* slot_bytes) {
   auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
   const size_t slot = al(sizeof(float) * kG2DStride * static_cast<size_t>(std::max<int64_t>(n, 1)));
   const size_t g2d = slot * static_cast<size_t>(std::max(views, 1));
   const size_t rec = al(sizeof(float) * 9 * static_cast<size_t>(std::max<int64_t>(capacity, 1)));
-  const size_t cut = al(sizeof(unsigned long long) * static_cast<size_t>(std::max<int64_t>(tiles, 1)));
+  // one flag byte per instance, padded so 16-byte reads past the last one stay inside
+  const size_t vis = al((static_cast<size_t>(std::max<int64_t>(capacity, 1)) + 31) & ~static_cast<size_t>(15));
   if (off_rec) *off_rec = g2d;
-  if (off_cut) *off_cut = g2d + rec;
+  if (off_vis) *off_vis = g2d + rec;
+  if (vis_bytes) *vis_bytes = vis;
   if (slot_bytes) *slot_bytes = slot;
-  return g2d + rec + cut;
+  return g2d + rec + vis;
 }
 
 static Geom to_geom(const pvg_geom* g) {
@@ -195,7 +197,7 @@ int pvg_workspace_query(int64_t n, int32_t width, int32_t height, int64_t capaci
   }
   const int64_t tiles = static_cast<int64_t>((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
   out->bin_tmp_bytes = plan_bins(n, tiles, capacity).total;
-  out->bwd_tmp_bytes = bwd_scratch_bytes(n, 1, tiles, capacity, nullptr, nullptr, nullptr);
+  out->bwd_tmp_bytes = bwd_scratch_bytes(n, 1, capacity, nullptr, nullptr, nullptr, nullptr);
   out->num_tiles = tiles;
   return PVG_OK;
 }
@@ -255,7 +257,8 @@ int pvg_bwd_views_tmp_bytes(int64_t n, int32_t n_views, int32_t max_width, int32
     return PVG_ERR_INVALID;
   }
   const int64_t tiles = static_cast<int64_t>((max_width + kTile - 1) / kTile) * ((max_height + kTile - 1) / kTile);
-  *bytes = bwd_scratch_bytes(n, std::min(n_views, kMaxBwdViews), tiles, max_capacity, nullptr, nullptr, nullptr);
+  (void)tiles;
+  *bytes = bwd_scratch_bytes(n, std::min(n_views, kMaxBwdViews), max_capacity, nullptr, nullptr, nullptr, nullptr);
   return PVG_OK;
 }
 
@@ -292,18 +295,17 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
     max_cap = std::max(max_cap, bins[k].capacity);
   }
   const int32_t slots = std::min(n_views, kMaxBwdViews);
-  size_t off_rec = 0, off_cut = 0;
-  const size_t need = bwd_scratch_bytes(g->n, slots, max_tiles, max_cap, &off_rec, &off_cut, nullptr);
+  (void)max_tiles;
+  size_t off_rec = 0, off_vis = 0, vis_bytes = 0, slot_bytes = 0;
+  const size_t need = bwd_scratch_bytes(g->n, slots, max_cap, &off_rec, &off_vis, &vis_bytes, &slot_bytes);
   if (!tmp || tmp_bytes < need) {
     set_error("render_bwd scratch of %zu bytes is smaller than the %zu required", tmp_bytes, need);
     return PVG_ERR_NOMEM;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(tmp);
-  size_t slot_bytes = 0;
-  bwd_scratch_bytes(g->n, slots, max_tiles, max_cap, &off_rec, &off_cut, &slot_bytes);
   float* rec = reinterpret_cast<float*>(base + off_rec);
-  unsigned long long* cut = reinterpret_cast<unsigned long long*>(base + off_cut);
+  uint8_t* vis = reinterpret_cast<uint8_t*>(base + off_vis);
   BwdViews pk;
   std::memset(&pk, 0, sizeof(pk));
   bool first_group = true;
@@ -322,8 +324,9 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
     v.dL_dimg = dL_dimg[k];
     float* g2d = reinterpret_cast<float*>(base + slot_bytes * static_cast<size_t>(pk.nv));
     const Lists lists{bins[k].vals, bins[k].ranges, bins[k].first, bins[k].tile_cull != 0,
-                      reinterpret_cast<const uint2*>(bins[k].rows), bins[k].row_base};
-    PVG_HIP(launch_render_bwd(single(v, g->n), to_geom(&geoms[k]), lists, rec, cut, g2d, s));
+                      reinterpret_cast<const uint2*>(bins[k].rows), bins[k].row_base, bins[k].capacity};
+    PVG_HIP(launch_render_bwd(single(v, g->n), to_geom(&geoms[k]), lists, rec, vis,
+                              static_cast<int64_t>(vis_bytes), g2d, s));
     pk.views[pk.nv] = v;
     pk.radius[pk.nv] = geoms[k].radius;
     pk.g2d[pk.nv] = g2d;

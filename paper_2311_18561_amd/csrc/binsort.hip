@@ -796,7 +796,9 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
   }
   const int passes = plan.tile_passes;
   const int start = passes & 1;  // so that the last pass lands in buffer 0
-  if (n > 0 && vis_grid > 0 && m_grid > 0) {
+  // culled lists: the row pass also writes the adjoint's row records and
+  // first[], so it runs whenever there are rows, even with nothing listed
+  if (n > 0 && vis_grid > 0 && (cull ? row_grid > 0 : m_grid > 0)) {
     StageScope sc(PVG_STAGE_SCAN_EMIT, s);
     const unsigned nbv = static_cast<unsigned>(cdiv(vis_grid, kScanBlock));
     if (!cull) {

@@ -12,8 +12,9 @@
 // recovering each pixel's transmittance by division, sums the four pixels'
 // screen-space gradients per lane and reduces them across the wave.  Each
 // (Gaussian, tile) pair's nine sums are stored, without atomics, at the pair's
-// index in emission order (a Gaussian's pairs are contiguous there); a gather
-// kernel then adds each Gaussian's pairs.  Device-scope float atomics resolve
+// index in emission order (a Gaussian's pairs are contiguous there) and
+// flagged in a byte array; a gather kernel then adds each Gaussian's flagged
+// pairs.  Device-scope float atomics resolve
 // at the memory side on this chip and cost three times the rest of the
 // kernel, and the atomic-free sums are bitwise reproducible.
 //
@@ -191,7 +192,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
 
 template <bool kCount, bool kCulled>
 __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists lists, float* rec,
-                                                   unsigned long long* cut, unsigned long long* pair_counter) {
+                                                   uint8_t* vis, unsigned long long* pair_counter) {
   // The gradient arithmetic may fuse multiply-adds.  Every branch decision
   // (exponent sign, alpha thresholds) comes from pair_power and single
   // products, which stay unfused, so the adjoint takes the forward's.
@@ -241,16 +242,6 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
   lmax = wave_max(lmax);
   const uint32_t start = ranges[2 * tile];
   lmax = min(lmax, static_cast<int>(ranges[2 * tile + 1] - start));  // never read past the tile's list
-  if (lane == 0) {
-    // (depth, index) key of the last list entry this tile visits: the gather
-    // kernel reads a pair's record only if its key is not above it
-    unsigned long long key = 0ull;
-    if (lmax > 0) {
-      const uint32_t gl = vals[start + lmax - 1];
-      key = (static_cast<unsigned long long>(__float_as_uint(geom.depth[gl])) << 32) | gl;
-    }
-    cut[tile] = key;
-  }
   long long evaluated = 0;
   for (int hi = lmax; hi > 0; hi -= 64) {
     const int lo = max(0, hi - 64);
@@ -340,8 +331,9 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       if (lane == 0) s_any[j] = wany ? 1 : 0;
     }
     __syncthreads();
-    if (keep) {
-      // record of this (Gaussian, tile) pair at its emission-order index
+    if (keep && s_any[__popcll(km & lt)] != 0) {
+      // record of this (Gaussian, tile) pair at its emission-order index,
+      // flagged for the gather (pairs no pixel used keep flag 0, no record)
       const int slot = __popcll(km & lt);
       uint32_t e;
       if (kCulled) {  // the tile's rank among the Gaussian's reached tiles
@@ -352,10 +344,12 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
         tile_rect(m.x, m.y, geom.radius[g], v.GX, v.GY, rect);
         e = first[g] + static_cast<uint32_t>((ty - rect[1]) * (rect[2] - rect[0]) + (tx - rect[0]));
       }
-      float* dst = rec + 9 * static_cast<int64_t>(e);
-      const bool has = s_any[slot] != 0;
+      if (static_cast<int64_t>(e) < lists.capacity) {
+        float* dst = rec + 9 * static_cast<int64_t>(e);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) dst[q] = has ? s_acc[slot][q] : 0.0f;
+        for (int q = 0; q < 9; ++q) dst[q] = s_acc[slot][q];
+        vis[e] = 1;
+      }
     }
     __syncthreads();
   }
@@ -367,109 +361,97 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
   }
 }
 
-// Rectangle lists: sum of one Gaussian's stored (Gaussian, tile) records over
-// the tiles q0, q0 + step, ... of its rectangle, skipping tiles the adjoint
-// did not reach (key above the tile's cut) and tiles it culled (same test).
-__device__ __forceinline__ void gather_pairs(const ViewSet& vs, const Geom& geom, uint32_t g, uint32_t q0,
-                                             uint32_t step, const uint32_t* __restrict__ first,
-                                             const float* __restrict__ rec,
-                                             const unsigned long long* __restrict__ cut, float acc[9]) {
+// Sum of one Gaussian's flagged records in [e0, e0 + cnt): one thread reads
+// the flags 16 at a time, or, with the whole wave, lane l takes e0 + l,
+// e0 + l + 64, ...  The emission order keeps a Gaussian's pairs contiguous.
+__device__ __forceinline__ void gather_range(uint32_t e0, uint32_t cnt, bool wave, int lane,
+                                             const float* __restrict__ rec, const uint8_t* __restrict__ vis,
+                                             float acc[9]) {
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
-  const View& v = view_at(vs, view_of_gauss(vs, g));
-  const float2 m = reinterpret_cast<const float2*>(geom.xy)[g];
-  const float4 co = reinterpret_cast<const float4*>(geom.conic_op)[g];
-  int32_t rect[4];
-  tile_rect(m.x, m.y, geom.radius[g], v.GX, v.GY, rect);
-  const uint32_t w = static_cast<uint32_t>(rect[2] - rect[0]);
-  const uint32_t n = w * static_cast<uint32_t>(rect[3] - rect[1]);
-  const unsigned long long key = (static_cast<unsigned long long>(__float_as_uint(geom.depth[g])) << 32) | g;
-  const uint32_t e0 = first[g];
-  for (uint32_t q = q0; q < n; q += step) {
-    const uint32_t dy = q / w, dx = q - dy * w;
-    const int tx = rect[0] + static_cast<int>(dx), ty = rect[1] + static_cast<int>(dy);
-    const int64_t t = v.tile_off + static_cast<int64_t>(ty) * v.GX + tx;
-    if (key > cut[t]) continue;
-    float X0, X1, Y0, Y1;
-    tile_bounds(tx, ty, v.W, v.H, X0, X1, Y0, Y1);
-    if (!tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1)) continue;
-    const float* r = rec + 9 * static_cast<int64_t>(e0 + q);
-#pragma unroll
-    for (int c = 0; c < 9; ++c) acc[c] += r[c];
-  }
-}
-
-// Culled lists: a Gaussian's records are its reached tiles in row-major
-// order; the row records give each row's reached columns and the index of
-// its first record.  One thread walks all rows, or, with the whole
-// wave, lane l takes rows l, l + 64, ...
-__device__ __forceinline__ void gather_rows(const ViewSet& vs, const Geom& geom, uint32_t g, bool wave, int lane,
-                                            const Lists& lists, const float* __restrict__ rec,
-                                            const unsigned long long* __restrict__ cut, float acc[9]) {
-#pragma unroll
-  for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
-  const View& v = view_at(vs, view_of_gauss(vs, g));
-  const float2 m = reinterpret_cast<const float2*>(geom.xy)[g];
-  int32_t rect[4];
-  tile_rect(m.x, m.y, geom.radius[g], v.GX, v.GY, rect);
-  const unsigned long long key = (static_cast<unsigned long long>(__float_as_uint(geom.depth[g])) << 32) | g;
-  const uint32_t rb = lists.row_base[g];
-  for (int ty = rect[1] + (wave ? lane : 0); ty < rect[3]; ty += wave ? 64 : 1) {
-    const uint2 rw = lists.rows[rb + static_cast<uint32_t>(ty)];
-    const uint32_t lo = rw.y & 0xffffu, len = rw.y >> 16;
-    const int64_t trow = v.tile_off + static_cast<int64_t>(ty) * v.GX + lo;
-    for (uint32_t c = 0; c < len; ++c) {
-      if (key > cut[trow + c]) continue;
-      const float* r = rec + 9 * static_cast<int64_t>(rw.x + c);
+  const uint32_t e1 = e0 + cnt;
+  if (wave) {
+    for (uint32_t e = e0 + static_cast<uint32_t>(lane); e < e1; e += 64) {
+      if (!vis[e]) continue;
+      const float* r = rec + 9 * static_cast<int64_t>(e);
 #pragma unroll
       for (int q = 0; q < 9; ++q) acc[q] += r[q];
+    }
+    return;
+  }
+  for (uint32_t b = e0 & ~15u; b < e1; b += 16) {
+    const uint4 w = *reinterpret_cast<const uint4*>(vis + b);
+    const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const uint32_t e = b + static_cast<uint32_t>(j);
+      if (((words[j >> 2] >> (8 * (j & 3))) & 0xffu) && e >= e0 && e < e1) {
+        const float* r = rec + 9 * static_cast<int64_t>(e);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[q] += r[q];
+      }
     }
   }
 }
 
-constexpr uint32_t kShortRect = 16;  // Gaussians with more tiles are gathered by a whole wave
+constexpr uint32_t kShortRange = 48;  // Gaussians with more listed pairs are gathered by a whole wave
 
+// Per visible Gaussian: the index range of its pairs (first[g] and the
+// listed count: its rectangle's tiles, or, for culled lists, up to the end
+// of its last row) and the sum of the flagged records.
 template <bool kCulled>
 __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, Lists lists,
                                                      const float* __restrict__ rec,
-                                                     const unsigned long long* __restrict__ cut, float* g2d) {
-  __shared__ uint32_t s_queue[256];
+                                                     const uint8_t* __restrict__ vis, float* g2d) {
+  __shared__ uint32_t s_queue[256][3];
   __shared__ int s_qn;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (tid == 0) s_qn = 0;
   __syncthreads();
   const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + tid;
-  const bool vis = gi < live_gauss(vs) && geom.radius[gi] > 0;
-  const uint32_t nt = vis ? geom.tiles[gi] : 0u;
-  if (vis && nt <= kShortRect) {
+  const bool visible = gi < live_gauss(vs) && geom.radius[gi] > 0;
+  uint32_t e0 = 0, cnt = 0;
+  if (visible) {
+    e0 = lists.first[gi];
+    if (kCulled) {  // (lists of an overflowed sort hold nothing; the bound below keeps reads inside)
+      const View& v = view_at(vs, view_of_gauss(vs, gi));
+      const float2 m = reinterpret_cast<const float2*>(geom.xy)[gi];
+      int32_t rect[4];
+      tile_rect(m.x, m.y, geom.radius[gi], v.GX, v.GY, rect);
+      const uint2 rw = lists.rows[lists.row_base[gi] + static_cast<uint32_t>(rect[3] - 1)];
+      cnt = rw.x + (rw.y >> 16) - e0;
+    } else {
+      cnt = geom.tiles[gi];
+    }
+    const uint64_t cap = static_cast<uint64_t>(lists.capacity);
+    if (static_cast<uint64_t>(e0) > cap || static_cast<uint64_t>(cnt) > cap - e0) cnt = 0;
+  }
+  if (visible && cnt <= kShortRange) {
     float acc[9];
-    if (kCulled)
-      gather_rows(vs, geom, static_cast<uint32_t>(gi), false, 0, lists, rec, cut, acc);
-    else
-      gather_pairs(vs, geom, static_cast<uint32_t>(gi), 0u, 1u, lists.first, rec, cut, acc);
+    gather_range(e0, cnt, false, 0, rec, vis, acc);
     float* dst = g2d + kG2DStride * gi;
 #pragma unroll
     for (int c = 0; c < 9; ++c) dst[c] = acc[c];
-  } else if (vis) {
-    s_queue[atomicAdd(&s_qn, 1)] = static_cast<uint32_t>(gi);
+  } else if (visible) {
+    const int q = atomicAdd(&s_qn, 1);
+    s_queue[q][0] = static_cast<uint32_t>(gi);
+    s_queue[q][1] = e0;
+    s_queue[q][2] = cnt;
   }
   __syncthreads();
   const int qn = s_qn;
   for (int qi = wid; qi < qn; qi += 4) {
-    const uint32_t g = s_queue[qi];
+    const uint32_t g = s_queue[qi][0];
     float acc[9], red[3];
-    if (kCulled)
-      gather_rows(vs, geom, g, true, lane, lists, rec, cut, acc);
-    else
-      gather_pairs(vs, geom, g, static_cast<uint32_t>(lane), 64u, lists.first, rec, cut, acc);
+    gather_range(s_queue[qi][1], s_queue[qi][2], true, lane, rec, vis, acc);
     wave_sum9(acc, red);
     if ((lane & 15) == 0) {
       const int r = lane >> 4;
       float* dst = g2d + kG2DStride * static_cast<int64_t>(g);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const int q = 4 * k + 2 * (r & 1) + (r >> 1);
-        if (q < 9) dst[q] = red[k];
+        const int qq = 4 * k + 2 * (r & 1) + (r >> 1);
+        if (qq < 9) dst[qq] = red[k];
       }
     }
   }
@@ -487,25 +469,28 @@ hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t
   return hipGetLastError();
 }
 
-hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const Lists& lists, float* rec,
-                             unsigned long long* cut, float* g2d, hipStream_t s) {
+hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const Lists& lists, float* rec, uint8_t* vis,
+                             int64_t vis_bytes, float* g2d, hipStream_t s) {
   if (vs.total_tiles == 0) return hipSuccess;
   const bool culled = lists.culled;
   {
     StageScope scope(PVG_STAGE_RENDER_BWD, s);
+    // clear the flags (a fill kernel: no memset node in a captured graph)
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(vis), 0u, vis_bytes / 4, s);
+    if (e != hipSuccess) return e;
     const dim3 grid(static_cast<unsigned>(((vs.total_tiles + 7) / 8) * 8));
     unsigned long long* cnt = profile_work_counter(PVG_STAGE_RENDER_BWD);
     auto k = cnt ? (culled ? k_render_bwd<true, true> : k_render_bwd<true, false>)
                  : (culled ? k_render_bwd<false, true> : k_render_bwd<false, false>);
-    hipLaunchKernelGGL(k, grid, dim3(64), 0, s, vs, geom, lists, rec, cut, cnt);
-    const hipError_t e = hipGetLastError();
+    hipLaunchKernelGGL(k, grid, dim3(64), 0, s, vs, geom, lists, rec, vis, cnt);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (vs.total_gauss == 0) return hipSuccess;
   StageScope scope(PVG_STAGE_GRAD_GATHER, s);
   hipLaunchKernelGGL(culled ? k_grad_gather<true> : k_grad_gather<false>,
                      dim3(static_cast<unsigned>((vs.total_gauss + 255) / 256)), dim3(256), 0, s, vs, geom, lists, rec,
-                     cut, g2d);
+                     vis, g2d);
   return hipGetLastError();
 }
 

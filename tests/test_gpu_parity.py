@@ -258,6 +258,26 @@ def test_edge_cases(orc):
     assert np.array_equal(g["img"], gr["img"])
 
 
+@pytest.mark.parametrize("tile_cull", [True, False])
+def test_faint_scene_lists_nothing(tile_cull):
+    """Visible Gaussians whose opacity is below 1/255: the culled lists are
+    empty while the rectangle lists are not; both render the background and
+    give zero gradients."""
+    import paper_2311_18561_amd as pvg
+    sc = gen.make_scene(400, 9)
+    sc["opacity"][:] = np.float32(1e-3)
+    cam = gen.make_camera(96, 64)
+    params = [p.requires_grad_(True) for p in to_device(sc)]
+    img, T, nc, geom, bins = pvg.render(params, cam, 0.5, bg=(0.2, 0.3, 0.4), tile_cull=tile_cull)
+    assert bins.num_visible > 0
+    assert (bins.num_instances == 0) == tile_cull
+    assert torch.all(T == 1) and torch.all(nc == 0)
+    img = pvg.pvg_render(params, cam, 0.5, bg=(0.2, 0.3, 0.4), tile_cull=tile_cull)
+    img.sum().backward()
+    for f, p in zip(FIELDS, params):
+        assert torch.count_nonzero(p.grad) == 0, f
+
+
 @pytest.mark.parametrize("tile_cull", [False, True])
 def test_capacity_handling(tile_cull):
     import ctypes as C
