@@ -93,7 +93,7 @@ typedef struct pvg_camera { /* host struct, passed by pointer */
   float T[3];               /* world -> camera translation */
   float fx, fy, cx, cy;     /* pinhole intrinsics in pixels, fx, fy > 0 */
   int32_t width, height;    /* image size in pixels, 1 .. 65535 (partial tiles allowed) */
-  float znear;              /* Gaussians with camera z <= znear are culled */
+  float znear;              /* > 0: Gaussians with camera z <= znear are culled */
 } pvg_camera;
 
 typedef struct pvg_frame {  /* host struct */
@@ -109,7 +109,7 @@ typedef struct pvg_geom {
   float* xy;          /* [n][2] pixel-space 2D mean */
   float* depth;       /* [n] camera-space z (the sort key) */
   float* conic_op;    /* [n][4] inverse 2D covariance (A, B, C) and opacity o~(t) */
-  float* rgb;         /* [n][3] colour */
+  float* rgb;         /* [n][3] colour; a channel clamped at zero is stored as -0 (the adjoint reads the clamp from the sign) */
   int32_t* radius;    /* [n] screen radius in pixels; 0 = invisible */
   uint32_t* tiles;    /* [n] number of tiles the Gaussian's rectangle touches */
 } pvg_geom;

@@ -112,6 +112,9 @@ def load():
         "pvg_render_fwd": ([P(Geom), P(Bins), P(Camera), P(Frame), vp, vp, vp, vp], i32),
         "pvg_render_bwd": ([P(Gaussians), P(Camera), P(Frame), P(Geom), P(Bins), vp, vp, vp, P(GaussiansGrad),
                             i32, vp, C.c_size_t, vp], i32),
+        "pvg_render_bwd_views": ([P(Gaussians), i32, P(Camera), P(Frame), P(Geom), P(Bins), P(vp), P(vp), P(vp),
+                                  P(GaussiansGrad), i32, vp, C.c_size_t, vp], i32),
+        "pvg_bwd_views_tmp_bytes": ([i64, i32, i32, i32, i64, P(C.c_size_t)], i32),
         "pvg_profile_enable": ([i32], i32),
         "pvg_profile_collect": ([], i32),
         "pvg_profile_read": ([i32, P(C.c_double), P(i64), P(i64)], i32),

@@ -103,6 +103,10 @@ bool check_camera(const pvg_camera* c) {
   if (c->width <= 0 || c->height <= 0) { set_error("image size %d x %d is not positive", c->width, c->height); return false; }
   if (c->width > 65535 || c->height > 65535) { set_error("image size above 65535 pixels"); return false; }
   if (!(c->fx > 0.0f) || !(c->fy > 0.0f)) { set_error("focal length must be positive"); return false; }
+  if (!(c->znear > 0.0f) || !std::isfinite(c->znear)) {
+    set_error("znear must be positive and finite (depth keys are the bits of a positive float)");
+    return false;
+  }
   return true;
 }
 
@@ -329,6 +333,7 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
                               static_cast<int64_t>(vis_bytes), g2d, s));
     pk.views[pk.nv] = v;
     pk.radius[pk.nv] = geoms[k].radius;
+    pk.rgb[pk.nv] = geoms[k].rgb;
     pk.g2d[pk.nv] = g2d;
     ++pk.nv;
     if (pk.nv == kMaxBwdViews) {

@@ -52,8 +52,9 @@ struct GeoGrad {
 // One view's chain rule for everything but dL/dsh, added into acc.  g is the
 // view's screen-space gradient of the Gaussian: d(mean x, y), d(conic A, B, C),
 // d(opacity), d(rgb); on return g[6..8] holds d(rgb) with clamped channels
-// zeroed and g[9..11] the view direction, which is all dL/dsh needs.
-__device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const Proj& P, float* g,
+// zeroed and g[9..11] the view direction, which is all dL/dsh needs.  rgb is
+// the forward's colour of the Gaussian, where a clamped channel is -0.
+__device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const Proj& P, const float* rgb, float* g,
                                                  GeoGrad& acc) {
   const Scene& s = v.s;
   const int64_t n = s.n;
@@ -65,7 +66,7 @@ __device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const
   // dependence on the direction moves the mean
   {
     float draw[3];
-    for (int ch = 0; ch < 3; ++ch) draw[ch] = (P.flags & (kClampR << ch)) ? 0.0f : g[6 + ch];
+    for (int ch = 0; ch < 3; ++ch) draw[ch] = signbit(rgb[ch]) ? 0.0f : g[6 + ch];
     float wk[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -243,8 +244,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   for (int v = 0; v < pk.nv; ++v) {
     if (pk.radius[v][i] <= 0) continue;
     Proj P;
-    project(pk.views[v], i, P, true);
-    adjoint_geometry(pk.views[v], i, P, pk.g2d[v] + kG2DStride * i, acc);
+    project(pk.views[v], i, P, false);
+    view_direction(pk.views[v], P);
+    adjoint_geometry(pk.views[v], i, P, pk.rgb[v] + 3 * i, pk.g2d[v] + kG2DStride * i, acc);
   }
   for (int q = 0; q < 3; ++q) {
     grad.mu[q * n + i] = acc.mu[q];

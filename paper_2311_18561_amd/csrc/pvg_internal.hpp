@@ -127,6 +127,7 @@ struct BwdViews {
   int32_t nv;
   View views[kMaxBwdViews];
   const int32_t* radius[kMaxBwdViews];
+  const float* rgb[kMaxBwdViews];  // the forward's colours (clamped channels are -0)
   float* g2d[kMaxBwdViews];  // the adjoint also leaves per-view scratch values in slots 6..11
 };
 hipError_t launch_preprocess_bwd(const BwdViews& pk, const pvg_gaussians_grad& grad, int accumulate,

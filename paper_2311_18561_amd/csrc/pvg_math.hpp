@@ -269,6 +269,16 @@ __device__ __forceinline__ void temporal_state(const View& v, int64_t i, float m
   }
 }
 
+// Unit direction from the camera centre -R^T T to the (translated) mean.
+__device__ __forceinline__ void view_direction(const View& v, Proj& P) {
+  const float* W = v.R;
+  float cp[3], u[3];
+  for (int c = 0; c < 3; ++c) cp[c] = -((W[c] * v.T[0] + W[3 + c] * v.T[1]) + W[6 + c] * v.T[2]);
+  for (int c = 0; c < 3; ++c) u[c] = P.mr[c] - cp[c];
+  P.ulen = sqrtf((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+  for (int c = 0; c < 3; ++c) P.dir[c] = u[c] / P.ulen;
+}
+
 // The per-Gaussian stage up to the tile rectangle; returns false for an
 // invisible Gaussian.  With `color` it also evaluates the clamped SH colour.
 __device__ __forceinline__ bool project(const View& v, int64_t i, Proj& P, bool color) {
@@ -353,11 +363,7 @@ __device__ __forceinline__ bool project(const View& v, int64_t i, Proj& P, bool 
   P.radius = rad;
 
   if (color) {
-    float cp[3], u[3];
-    for (int c = 0; c < 3; ++c) cp[c] = -((W[c] * v.T[0] + W[3 + c] * v.T[1]) + W[6 + c] * v.T[2]);
-    for (int c = 0; c < 3; ++c) u[c] = P.mr[c] - cp[c];
-    P.ulen = sqrtf((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
-    for (int c = 0; c < 3; ++c) P.dir[c] = u[c] / P.ulen;
+    view_direction(v, P);
     float Y[16];
     sh_eval_basis(s.degree, P.dir[0], P.dir[1], P.dir[2], Y);
     const int K = (s.degree + 1) * (s.degree + 1);
@@ -365,9 +371,9 @@ __device__ __forceinline__ bool project(const View& v, int64_t i, Proj& P, bool 
       float acc = 0.0f;
       for (int k = 0; k < K; ++k) acc += s.sh[(3 * k + ch) * n + i] * Y[k];
       const float raw = acc + 0.5f;
-      if (raw < 0.0f) {
+      if (raw < 0.0f) {  // clamped: stored as -0, which composites like +0 and marks the clamp
         P.flags |= (kClampR << ch);
-        P.rgb[ch] = 0.0f;
+        P.rgb[ch] = -0.0f;
       } else {
         P.rgb[ch] = raw;
       }

@@ -44,7 +44,7 @@ def test_invalid_arguments_rejected_on_host(lib):
     g = L.Gaussians()
     g.n = -1
     cam = L.Camera()
-    cam.width, cam.height, cam.fx, cam.fy = 64, 48, 50.0, 50.0
+    cam.width, cam.height, cam.fx, cam.fy, cam.znear = 64, 48, 50.0, 50.0, 0.2
     fr = L.Frame()
     geom = L.Geom()
     assert lib.pvg_preprocess(C.byref(g), C.byref(cam), C.byref(fr), C.byref(geom), None) == L.PVG_ERR_INVALID
@@ -65,6 +65,25 @@ def test_invalid_arguments_rejected_on_host(lib):
     fr.advect_mode = 3
     assert lib.pvg_render_fwd(C.byref(geom), C.byref(bins), C.byref(cam), C.byref(fr), None, None, None,
                               None) == L.PVG_ERR_INVALID
+    # a near plane at or behind the camera is rejected (depth keys need z > 0)
+    fr.advect_mode = 0
+    for z in (0.0, -1.0, float("nan")):
+        cam.znear = z
+        assert lib.pvg_preprocess(C.byref(g), C.byref(cam), C.byref(fr), C.byref(geom), None) == L.PVG_ERR_INVALID
+        assert "znear" in L.last_error()
+    cam.znear = 0.2
+    # list form flag and the multi-view adjoint's arguments
+    bins.capacity = 0
+    bins.ranges = bins.counters = 1
+    bins.tile_cull = 2
+    assert lib.pvg_bin_sort(C.byref(geom), C.byref(cam), C.byref(bins), None, 0, 1, None) == L.PVG_ERR_INVALID
+    assert "tile_cull" in L.last_error()
+    gg = L.GaussiansGrad()
+    assert lib.pvg_render_bwd_views(C.byref(g), 0, C.byref(cam), C.byref(fr), C.byref(geom), C.byref(bins), None,
+                                    None, None, C.byref(gg), 0, None, 0, None) == L.PVG_ERR_INVALID
+    size = C.c_size_t()
+    assert lib.pvg_bwd_views_tmp_bytes(100, 6, 64, 48, 1000, C.byref(size)) == 0 and size.value > 0
+    assert lib.pvg_bwd_views_tmp_bytes(100, 0, 64, 48, 1000, C.byref(size)) == L.PVG_ERR_INVALID
 
 
 def test_workspace_query(lib):
