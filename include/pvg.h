@@ -204,7 +204,10 @@ int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_fram
  * pvg_render_bwd, all for the same g), and device pointers final_T[v],
  * n_contrib[v], dL_dimg[v]; dL_dimg[v] = NULL skips view v.  tmp: at least
  * pvg_bwd_views_tmp_bytes(n, n_views, largest width and height, largest
- * bins capacity) bytes.  Bitwise reproducible (no atomics). */
+ * bins capacity) bytes.  The views' compositing adjoints run concurrently on
+ * library-owned side streams (default priority) forked from and joined back
+ * into `stream`; under stream capture they run on `stream` alone.  Bitwise
+ * reproducible (no atomics). */
 int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_camera* cams,
                          const pvg_frame* frames, const pvg_geom* geoms, const pvg_bins* bins,
                          const float* const* final_T, const int32_t* const* n_contrib,

@@ -23,4 +23,5 @@ from .render import (  # noqa: F401
     render,
     render_bwd,
     render_fwd,
+    render_views,
 )

@@ -169,8 +169,8 @@ static ViewSet single(const View& v, int64_t n) {
   return vs;
 }
 
-size_t bwd_scratch_bytes(int64_t n, int32_t views, int64_t capacity, size_t* off_rec, size_t* off_vis,
-                         size_t* vis_bytes, size_t* slot_bytes) {
+size_t bwd_scratch_bytes(int64_t n, int32_t views, int32_t regions, int64_t capacity, size_t* off_rec,
+                         size_t* off_vis, size_t* vis_bytes, size_t* slot_bytes, size_t* region_bytes) {
   auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
   const size_t slot = al(sizeof(float) * kG2DStride * static_cast<size_t>(std::max<int64_t>(n, 1)));
   const size_t g2d = slot * static_cast<size_t>(std::max(views, 1));
@@ -181,8 +181,44 @@ size_t bwd_scratch_bytes(int64_t n, int32_t views, int64_t capacity, size_t* off
   if (off_vis) *off_vis = g2d + rec;
   if (vis_bytes) *vis_bytes = vis;
   if (slot_bytes) *slot_bytes = slot;
-  return g2d + rec + vis;
+  if (region_bytes) *region_bytes = rec + vis;
+  return g2d + (rec + vis) * static_cast<size_t>(std::max(regions, 1));
 }
+
+// Side streams (default priority, non-blocking) on which the multi-view
+// adjoint runs views concurrently; created once per device.
+namespace {
+std::mutex g_side_mu;
+std::vector<std::vector<hipStream_t>> g_side;
+thread_local std::vector<hipEvent_t> t_events;
+
+int side_streams(std::vector<hipStream_t>& out) {
+  int dev = 0;
+  PVG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  if (static_cast<int>(g_side.size()) <= dev) g_side.resize(dev + 1);
+  if (g_side[dev].empty()) {
+    for (int k = 0; k < kBwdStreams; ++k) {
+      hipStream_t st = nullptr;
+      PVG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      g_side[dev].push_back(st);
+    }
+  }
+  out = g_side[dev];
+  return PVG_OK;
+}
+
+// The i-th event of this thread's pool (events are only recorded and waited
+// on within one call, so reuse across calls is safe).
+hipEvent_t pool_event(size_t i) {
+  while (t_events.size() <= i) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    t_events.push_back(e);
+  }
+  return t_events[i];
+}
+}  // namespace
 
 static Geom to_geom(const pvg_geom* g) {
   return Geom{g->xy, g->depth, g->conic_op, g->rgb, g->radius, g->tiles};
@@ -201,7 +237,7 @@ int pvg_workspace_query(int64_t n, int32_t width, int32_t height, int64_t capaci
   }
   const int64_t tiles = static_cast<int64_t>((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
   out->bin_tmp_bytes = plan_bins(n, tiles, capacity).total;
-  out->bwd_tmp_bytes = bwd_scratch_bytes(n, 1, capacity, nullptr, nullptr, nullptr, nullptr);
+  out->bwd_tmp_bytes = bwd_scratch_bytes(n, 1, 1, capacity, nullptr, nullptr, nullptr, nullptr, nullptr);
   out->num_tiles = tiles;
   return PVG_OK;
 }
@@ -262,7 +298,8 @@ int pvg_bwd_views_tmp_bytes(int64_t n, int32_t n_views, int32_t max_width, int32
   }
   const int64_t tiles = static_cast<int64_t>((max_width + kTile - 1) / kTile) * ((max_height + kTile - 1) / kTile);
   (void)tiles;
-  *bytes = bwd_scratch_bytes(n, std::min(n_views, kMaxBwdViews), max_capacity, nullptr, nullptr, nullptr, nullptr);
+  *bytes = bwd_scratch_bytes(n, std::min(n_views, kMaxBwdViews), std::min(n_views, kBwdStreams), max_capacity,
+                             nullptr, nullptr, nullptr, nullptr, nullptr);
   return PVG_OK;
 }
 
@@ -300,26 +337,64 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
   }
   const int32_t slots = std::min(n_views, kMaxBwdViews);
   (void)max_tiles;
-  size_t off_rec = 0, off_vis = 0, vis_bytes = 0, slot_bytes = 0;
-  const size_t need = bwd_scratch_bytes(g->n, slots, max_cap, &off_rec, &off_vis, &vis_bytes, &slot_bytes);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // views run concurrently on side streams, each with its own record region;
+  // under stream capture everything stays on the caller's stream
+  hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+  PVG_HIP(hipStreamIsCapturing(s, &cap_status));
+  int32_t with_grad = 0;
+  for (int32_t k = 0; k < n_views; ++k) with_grad += dL_dimg[k] ? 1 : 0;
+  const bool serial = cap_status != hipStreamCaptureStatusNone || with_grad <= 1;
+  const int32_t regions = serial ? 1 : std::min(with_grad, kBwdStreams);
+  size_t off_rec = 0, off_vis = 0, vis_bytes = 0, slot_bytes = 0, region_bytes = 0;
+  const size_t need = bwd_scratch_bytes(g->n, slots, regions, max_cap, &off_rec, &off_vis, &vis_bytes, &slot_bytes,
+                                        &region_bytes);
   if (!tmp || tmp_bytes < need) {
     set_error("render_bwd scratch of %zu bytes is smaller than the %zu required", tmp_bytes, need);
     return PVG_ERR_NOMEM;
   }
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<hipStream_t> side;
+  if (!serial) {
+    const int st = side_streams(side);
+    if (st != PVG_OK) return st;
+  }
+  size_t nev = 0;
+  auto fork = [&]() -> int {  // side streams wait for the caller's stream
+    if (serial) return PVG_OK;
+    hipEvent_t e = pool_event(nev++);
+    if (!e) { set_error("hipEventCreate failed"); return PVG_ERR_HIP; }
+    PVG_HIP(hipEventRecord(e, s));
+    for (int32_t r = 0; r < regions; ++r) PVG_HIP(hipStreamWaitEvent(side[r], e, 0));
+    return PVG_OK;
+  };
+  auto join = [&]() -> int {  // the caller's stream waits for the side streams
+    if (serial) return PVG_OK;
+    for (int32_t r = 0; r < regions; ++r) {
+      hipEvent_t e = pool_event(nev++);
+      if (!e) { set_error("hipEventCreate failed"); return PVG_ERR_HIP; }
+      PVG_HIP(hipEventRecord(e, side[r]));
+      PVG_HIP(hipStreamWaitEvent(s, e, 0));
+    }
+    return PVG_OK;
+  };
   char* base = static_cast<char*>(tmp);
-  float* rec = reinterpret_cast<float*>(base + off_rec);
-  uint8_t* vis = reinterpret_cast<uint8_t*>(base + off_vis);
   BwdViews pk;
   std::memset(&pk, 0, sizeof(pk));
   bool first_group = true;
   auto flush = [&]() -> int {
     if (pk.nv == 0) return PVG_OK;
+    int st = join();
+    if (st != PVG_OK) return st;
     PVG_HIP(launch_preprocess_bwd(pk, *grad, first_group ? accumulate : 1, s));
     first_group = false;
     pk.nv = 0;
-    return PVG_OK;
+    return fork();  // the next group reuses the g2d slots
   };
+  {
+    const int st = fork();
+    if (st != PVG_OK) return st;
+  }
+  int32_t launched = 0;
   for (int32_t k = 0; k < n_views; ++k) {
     if (!dL_dimg[k]) continue;
     View v = make_view(g, &cams[k], &frames[k]);
@@ -327,10 +402,15 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
     v.n_contrib = const_cast<int32_t*>(n_contrib[k]);
     v.dL_dimg = dL_dimg[k];
     float* g2d = reinterpret_cast<float*>(base + slot_bytes * static_cast<size_t>(pk.nv));
+    const int32_t r = launched % regions;
+    char* region = base + off_rec + region_bytes * static_cast<size_t>(r);
+    float* rec = reinterpret_cast<float*>(region);
+    uint8_t* vis = reinterpret_cast<uint8_t*>(region + (off_vis - off_rec));
     const Lists lists{bins[k].vals, bins[k].ranges, bins[k].first, bins[k].tile_cull != 0,
                       reinterpret_cast<const uint2*>(bins[k].rows), bins[k].row_base, bins[k].capacity};
     PVG_HIP(launch_render_bwd(single(v, g->n), to_geom(&geoms[k]), lists, rec, vis,
-                              static_cast<int64_t>(vis_bytes), g2d, s));
+                              static_cast<int64_t>(vis_bytes), g2d, serial ? s : side[r]));
+    ++launched;
     pk.views[pk.nv] = v;
     pk.radius[pk.nv] = geoms[k].radius;
     pk.rgb[pk.nv] = geoms[k].rgb;

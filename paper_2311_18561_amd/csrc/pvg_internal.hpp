@@ -150,9 +150,11 @@ struct Lists {
 // adjoint of compositing: per-(Gaussian, tile) records, then their per-Gaussian sums into g2d
 hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const Lists& lists, float* rec, uint8_t* vis,
                              int64_t vis_bytes, float* g2d, hipStream_t s);
-// scratch of the adjoint: g2d [views][n][12] | rec [capacity][9] | vis [capacity] bytes (+16, multiple of 16)
-size_t bwd_scratch_bytes(int64_t n, int32_t views, int64_t capacity, size_t* off_rec, size_t* off_vis,
-                         size_t* vis_bytes, size_t* slot_bytes);
+// scratch of the adjoint: g2d [views][n][12] | regions x (rec [capacity][9] | vis [capacity] bytes, padded);
+// one region per view adjoint that runs concurrently (at most kBwdStreams)
+constexpr int kBwdStreams = 3;
+size_t bwd_scratch_bytes(int64_t n, int32_t views, int32_t regions, int64_t capacity, size_t* off_rec,
+                         size_t* off_vis, size_t* vis_bytes, size_t* slot_bytes, size_t* region_bytes);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 

@@ -98,6 +98,9 @@ class Geom:
         self.radius = torch.empty(n, dtype=torch.int32, device=device)
         self.tiles = torch.empty(n, dtype=torch.int32, device=device)  # uint32 counts
 
+    def tensors(self):
+        return (self.xy, self.depth, self.conic_op, self.rgb, self.radius, self.tiles)
+
     def struct(self) -> L.Geom:
         g = L.Geom()
         g.n = self.n
@@ -136,6 +139,9 @@ class Bins:
         if self.tile_cull:
             b.rows, b.row_base = self.rows.data_ptr(), self.row_base.data_ptr()
         return b
+
+    def tensors(self):
+        return (self.keys, self.vals, self.ranges, self.counters, self.first, self.rows, self.row_base)
 
     def num_listed(self) -> int:
         """Instances in the sorted lists (reads the device counter: synchronises)."""
@@ -296,6 +302,75 @@ class PVGRender(torch.autograd.Function):
 
 
 KEEP_FRACTION = 0.1  # recompute="auto" keeps the views' lists while they fit this share of device memory
+VIEW_STREAMS = 3     # views of one call run concurrently on this many side streams (default priority)
+_side_streams: dict = {}
+
+
+def _streams(dev):
+    key = dev.index
+    if key not in _side_streams:
+        _side_streams[key] = [torch.cuda.Stream(device=dev) for _ in range(VIEW_STREAMS)]
+    return _side_streams[key]
+
+
+def _forward_views(params, n, degree, views, tile_cull):
+    """Preprocess, bin and composite every view; view k runs on side stream
+    k mod VIEW_STREAMS (their latency-bound sort and scan kernels overlap),
+    joined back into the caller's stream.  One overflow check for all views
+    at the end; a view that outgrew its cached capacity is redone."""
+    dev = params[0].device
+    main = torch.cuda.current_stream(dev)
+    side = _streams(dev)
+    start = torch.cuda.Event()
+    start.record(main)
+    plans, outs, done = [], [], []
+    for k, (cam, t, dt, mode, bg) in enumerate(views):
+        st = side[k % len(side)]
+        st.wait_event(start)
+        with torch.cuda.stream(st):
+            c, f = camera_struct(cam), frame_struct(t, dt, mode, bg)
+            geom = preprocess(params, n, degree, c, f)
+            cap = _capacity_hint.get((dev.index, int(c.width), int(c.height), bool(tile_cull)))
+            bins = bin_sort(geom, c, tile_cull=tile_cull) if cap is None else bin_sort_nosync(geom, c, cap, tile_cull)
+            out = render_fwd(geom, bins, c, f)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        plans.append([c, f, geom, bins])
+        outs.append(out)
+        done.append(ev)
+    for ev in done:
+        main.wait_event(ev)
+    for (_, _, geom, bins), out in zip(plans, outs):
+        for tns in (*geom.tensors(), *bins.tensors(), *out):
+            tns.record_stream(main)
+    over = torch.stack([b.counters[2] for _, _, _, b in plans]).cpu().tolist()
+    for k, flag in enumerate(over):
+        if flag:  # this view outgrew the cached capacity: redo it with the counting path
+            c, f, geom, _ = plans[k]
+            bins = bin_sort(geom, c, tile_cull=tile_cull)
+            plans[k][3] = bins
+            outs[k] = render_fwd(geom, bins, c, f)
+    return plans, outs
+
+
+def render_views(params, views, tile_cull=True):
+    """Forward only, several views: returns [(img, final_T, n_contrib, geom, bins)] per view;
+    views = [(cam, t) | (cam, t, dt) | (cam, t, dt, advect_mode, bg)]."""
+    params, n, degree = _check_params(params)
+    plans, outs = _forward_views(params, n, degree, _full_views(views), tile_cull)
+    return [(img, T, nc, geom, bins) for (_, _, geom, bins), (img, T, nc) in zip(plans, outs)]
+
+
+def _full_views(views):
+    full = []
+    for v in views:
+        v = tuple(v)
+        cam, t = v[0], v[1]
+        dt = v[2] if len(v) > 2 else 0.0
+        mode = v[3] if len(v) > 3 else 0
+        bg = v[4] if len(v) > 4 else (0.0, 0.0, 0.0)
+        full.append((cam, float(t), float(dt), int(mode), tuple(float(b) for b in bg)))
+    return full
 
 
 def _bins_bytes(b: Bins) -> int:
@@ -315,22 +390,7 @@ class PVGRenderViews(torch.autograd.Function):
     def forward(ctx, views, recompute, tile_cull, *tensors):
         params, n, degree = _check_params(list(tensors))
         dev = params[0].device
-        plans, outs = [], []
-        for cam, t, dt, mode, bg in views:
-            c, f = camera_struct(cam), frame_struct(t, dt, mode, bg)
-            geom = preprocess(params, n, degree, c, f)
-            cap = _capacity_hint.get((dev.index, int(c.width), int(c.height), bool(tile_cull)))
-            bins = bin_sort(geom, c, tile_cull=tile_cull) if cap is None else bin_sort_nosync(geom, c, cap, tile_cull)
-            plans.append([c, f, geom, bins])
-        for k, (c, f, geom, bins) in enumerate(plans):
-            outs.append(render_fwd(geom, bins, c, f))
-        over = torch.stack([b.counters[2] for _, _, _, b in plans]).cpu().tolist()
-        for k, flag in enumerate(over):
-            if flag:  # this view outgrew the cached capacity: redo it with the counting path
-                c, f, geom, _ = plans[k]
-                bins = bin_sort(geom, c, tile_cull=tile_cull)
-                plans[k][3] = bins
-                outs[k] = render_fwd(geom, bins, c, f)
+        plans, outs = _forward_views(params, n, degree, views, tile_cull)
         if recompute == "auto":
             kept_bytes = sum(_bins_bytes(b) for _, _, _, b in plans)
             recompute = kept_bytes > KEEP_FRACTION * torch.cuda.get_device_properties(dev).total_memory
@@ -375,15 +435,7 @@ def pvg_render_views(params, views, recompute="auto", tile_cull=True):
     views = [(cam, t), (cam, t, dt), ... or (cam, t, dt, advect_mode, bg)];
     returns one image [3,H,W] per view.  recompute: True, False or "auto"
     (see PVGRenderViews)."""
-    full = []
-    for v in views:
-        v = tuple(v)
-        cam, t = v[0], v[1]
-        dt = v[2] if len(v) > 2 else 0.0
-        mode = v[3] if len(v) > 3 else 0
-        bg = v[4] if len(v) > 4 else (0.0, 0.0, 0.0)
-        full.append((cam, float(t), float(dt), int(mode), tuple(float(b) for b in bg)))
-    return PVGRenderViews.apply(full, recompute, tile_cull, *params)
+    return PVGRenderViews.apply(_full_views(views), recompute, tile_cull, *params)
 
 
 def pvg_render(params, cam, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), recompute=True, tile_cull=True):
