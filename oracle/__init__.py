@@ -55,7 +55,7 @@ def lib():
         L.orc_render_bruteforce_f32.restype = None
         L.orc_render_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_render_f64.restype = C.c_double
-        L.orc_backward_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_backward_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_backward_f64.restype = None
         L.orc_temporal_f64.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_double, i32, vp, vp]
@@ -184,8 +184,10 @@ def render_f64(sc64, cam, t, dt, mode, bg, pre, bins, tile_mask=None, w=None, wa
     return L, img, T
 
 
-def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg) -> tuple[dict, np.ndarray]:
-    """FP64 gradients of sum(dimg * image) for every parameter array, and g2d [N,9]."""
+def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, tile_mask=None) -> tuple[dict, np.ndarray]:
+    """FP64 gradients of sum(dimg * image) for every parameter array, and g2d [N,9].
+    tile_mask (optional, one byte per tile): only these tiles are visited; dimg
+    must be zero on every other tile."""
     n = int(sc64["n"])
     W, H = cam["width"], cam["height"]
     arrs, ptrs = _param_ptrs(sc64, np.float64)
@@ -195,9 +197,15 @@ def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg) -> tuple[dict, np.
     cv, fv = cam_array(cam), frame_array(t, dt, mode, bg)
     ig = bins["inst_gauss"] if bins["M"] > 0 else np.zeros(1, np.uint32)
     d = _c(dimg, np.float64)
+    tm = None if tile_mask is None else _c(tile_mask, np.uint8)
+    if tm is not None:
+        GX, GY = grid(cam)
+        assert tm.size == GX * GY
+        keep = np.repeat(np.repeat(tm.reshape(GY, GX), 16, 0), 16, 1)[:H, :W].astype(bool)
+        assert not np.any(d[:, ~keep]), "dimg must be zero outside the tile mask"
     lib().orc_backward_f64(n, int(sc64["sh_degree"]), ptrs, _p(cv), W, H, _p(fv), _p(pre["xy"]),
                            _p(pre["conic_op"]), _p(pre["radius"]), _p(pre["flags"]), _p(bins["ranges"]),
-                           _p(ig), _p(d), gptrs, _p(g2d))
+                           _p(ig), _p(d), gptrs, _p(g2d), _p(tm))
     return grads, g2d
 
 

@@ -645,7 +645,8 @@ double orc_render_f64(int64_t n, int degree, const void* const* arr, const float
 void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float* camv, int W, int H,
                       const float* framev, const float* xy32, const float* conic_op32,
                       const int32_t* radius32, const uint32_t* flags32, const uint32_t* ranges,
-                      const uint32_t* inst_gauss, const double* dimg, void* const* garr, double* g2d_out) {
+                      const uint32_t* inst_gauss, const double* dimg, void* const* garr, double* g2d_out,
+                      const uint8_t* tile_mask) {
   const Params prm = make_params(n, degree, arr);
   const Camera cam = make_cam(camv, W, H);
   const Frame fr = make_frame(framev);
@@ -665,6 +666,8 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
   // O6: per pixel, the derivative of Eq. (3) with respect to each
   // contributor's alpha, colour, and through alpha its opacity, conic and mean.
   for (int64_t t = 0; t < static_cast<int64_t>(GX) * GY; ++t) {
+    // tile_mask (optional): tiles left out must carry a zero dimg, so they add nothing
+    if (tile_mask && !tile_mask[t]) continue;
     const int tx = static_cast<int>(t % GX), ty = static_cast<int>(t / GX);
     const uint32_t* list = inst_gauss + ranges[2 * t];
     const int64_t len = static_cast<int64_t>(ranges[2 * t + 1]) - ranges[2 * t];

@@ -231,6 +231,19 @@ def render_bwd(params, n, degree, cam, frame, geom, bins, final_T, n_contrib, dL
     return grads
 
 
+_scratch_cache: dict = {}
+
+
+def _scratch(dev, nbytes):
+    """Grow-only scratch of the adjoint per (device, stream): reused by every
+    call in stream order, so steady-state steps allocate nothing."""
+    key = (dev.index, torch.cuda.current_stream(dev).cuda_stream)
+    buf = _scratch_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        _scratch_cache[key] = buf = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    return buf
+
+
 def render_bwd_views(params, n, degree, views, grads=None, accumulate=False):
     """One adjoint call for several views of the same Gaussians:
     views = [(cam, frame, geom, bins, final_T, n_contrib, dL_dimg or None)];
@@ -257,9 +270,9 @@ def render_bwd_views(params, n, degree, views, grads=None, accumulate=False):
     L.check(lib.pvg_bwd_views_tmp_bytes(n, nv, max(int(v[0].width) for v in views),
                                         max(int(v[0].height) for v in views),
                                         max(v[3].capacity for v in views), C.byref(size)))
-    tmp = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=dev)
+    tmp = _scratch(dev, int(size.value))
     L.check(lib.pvg_render_bwd_views(C.byref(g), nv, cams, frames, geoms, bins, f_t, n_c, d_l, C.byref(gg),
-                                     1 if accumulate else 0, _p(tmp), int(size.value), _stream_handle()))
+                                     1 if accumulate else 0, _p(tmp), int(tmp.numel()), _stream_handle()))
     return grads
 
 

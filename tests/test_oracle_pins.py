@@ -492,3 +492,26 @@ def test_fp64_image_close_to_fp32(orc):
                                    r["bins"])
     assert np.abs(img64 - r["img"]).max() < 2e-6
     assert np.abs(T64 - r["final_T"]).max() < 2e-6
+
+
+def test_tile_masked_adjoint_equals_full(orc):
+    """The adjoint restricted to a tile mask equals the full adjoint when the
+    image gradient vanishes outside the mask (the mask only skips work)."""
+    import gen
+    scene = gen.make_scene(300, 17, sh_degree=2)
+    cam = gen.make_camera(96, 64)
+    t = 0.4
+    pre = orc.preprocess_f32(scene, cam, t)
+    bins = orc.bin_sort(pre, cam)
+    GX, GY = orc.grid(cam)
+    mask = np.zeros(GX * GY, np.uint8)
+    mask[[3, 9, 14]] = 1
+    keep = np.repeat(np.repeat(mask.reshape(GY, GX), 16, 0), 16, 1)[:64, :96].astype(bool)
+    dimg = np.random.default_rng(3).standard_normal((3, 64, 96)) * keep
+    sc64 = orc.scene64(scene)
+    full, g_full = orc.backward_f64(sc64, cam, t, 0.0, 0, (0, 0, 0), pre, bins, dimg)
+    part, g_part = orc.backward_f64(sc64, cam, t, 0.0, 0, (0, 0, 0), pre, bins, dimg, tile_mask=mask)
+    assert np.array_equal(g_full, g_part)
+    for f in full:
+        assert np.array_equal(full[f], part[f]), f
+    assert np.abs(g_full).max() > 0
