@@ -288,12 +288,14 @@ def main():
 
     views = [(cam, t, d) for cam in cams for d in (0.0, dt)]
     view_targets = [tgt for tgt in targets for _ in (0.0, dt)]
+    stacked_targets = torch.stack(view_targets)
 
     def train_step(recompute="auto"):
+        # the six L1 losses (each the mean over its image), on the stacked images
         for p in params:
             p.grad = None
-        imgs = pvg.pvg_render_views(params, views, recompute=recompute)
-        loss = sum((img - tgt).abs().mean() for img, tgt in zip(imgs, view_targets))
+        imgs = pvg.pvg_render_views(params, views, recompute=recompute, stack=True)
+        loss = (imgs - stacked_targets).abs().mean() * len(views)  # = the sum of the six per-image means
         loss.backward()
         return loss
 

@@ -201,10 +201,11 @@ def bin_sort_nosync(geom: Geom, cam: L.Camera, capacity: int, tile_cull: bool = 
     return bins
 
 
-def render_fwd(geom: Geom, bins: Bins, cam: L.Camera, frame: L.Frame):
+def render_fwd(geom: Geom, bins: Bins, cam: L.Camera, frame: L.Frame, out=None):
+    """Composite one view; `out` (optional, contiguous [3,H,W] float32) receives the image."""
     dev = geom.xy.device
     H, W = int(cam.height), int(cam.width)
-    img = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    img = torch.empty((3, H, W), dtype=torch.float32, device=dev) if out is None else out
     final_T = torch.empty((H, W), dtype=torch.float32, device=dev)
     n_contrib = torch.empty((H, W), dtype=torch.int32, device=dev)
     gs, bs = geom.struct(), bins.struct()
@@ -326,11 +327,13 @@ def _streams(dev):
     return _side_streams[key]
 
 
-def _forward_views(params, n, degree, views, tile_cull):
+def _forward_views(params, n, degree, views, tile_cull, stacked=None):
     """Preprocess, bin and composite every view; view k runs on side stream
     k mod VIEW_STREAMS (their latency-bound sort and scan kernels overlap),
     joined back into the caller's stream.  One overflow check for all views
-    at the end; a view that outgrew its cached capacity is redone."""
+    at the end; a view that outgrew its cached capacity is redone.  With
+    `stacked` ([V,3,H,W], allocated on the caller's stream) view k's image is
+    written into stacked[k]."""
     dev = params[0].device
     main = torch.cuda.current_stream(dev)
     side = _streams(dev)
@@ -345,7 +348,7 @@ def _forward_views(params, n, degree, views, tile_cull):
             geom = preprocess(params, n, degree, c, f)
             cap = _capacity_hint.get((dev.index, int(c.width), int(c.height), bool(tile_cull)))
             bins = bin_sort(geom, c, tile_cull=tile_cull) if cap is None else bin_sort_nosync(geom, c, cap, tile_cull)
-            out = render_fwd(geom, bins, c, f)
+            out = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k])
             ev = torch.cuda.Event()
             ev.record(st)
         plans.append([c, f, geom, bins])
@@ -354,7 +357,7 @@ def _forward_views(params, n, degree, views, tile_cull):
     for ev in done:
         main.wait_event(ev)
     for (_, _, geom, bins), out in zip(plans, outs):
-        for tns in (*geom.tensors(), *bins.tensors(), *out):
+        for tns in (*geom.tensors(), *bins.tensors(), *(out if stacked is None else out[1:])):
             tns.record_stream(main)
     over = torch.stack([b.counters[2] for _, _, _, b in plans]).cpu().tolist()
     for k, flag in enumerate(over):
@@ -362,7 +365,7 @@ def _forward_views(params, n, degree, views, tile_cull):
             c, f, geom, _ = plans[k]
             bins = bin_sort(geom, c, tile_cull=tile_cull)
             plans[k][3] = bins
-            outs[k] = render_fwd(geom, bins, c, f)
+            outs[k] = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k])
     return plans, outs
 
 
@@ -400,10 +403,14 @@ class PVGRenderViews(torch.autograd.Function):
     the lists when they fit KEEP_FRACTION of the device memory."""
 
     @staticmethod
-    def forward(ctx, views, recompute, tile_cull, *tensors):
+    def forward(ctx, views, recompute, tile_cull, stack, *tensors):
         params, n, degree = _check_params(list(tensors))
         dev = params[0].device
-        plans, outs = _forward_views(params, n, degree, views, tile_cull)
+        stacked = None
+        if stack:
+            H, W = int(views[0][0]["height"]), int(views[0][0]["width"])
+            stacked = torch.empty((len(views), 3, H, W), dtype=torch.float32, device=dev)
+        plans, outs = _forward_views(params, n, degree, views, tile_cull, stacked)
         if recompute == "auto":
             kept_bytes = sum(_bins_bytes(b) for _, _, _, b in plans)
             recompute = kept_bytes > KEEP_FRACTION * torch.cuda.get_device_properties(dev).total_memory
@@ -413,11 +420,17 @@ class PVGRenderViews(torch.autograd.Function):
         for _, T, nc in outs:
             saved += [T, nc]
         ctx.save_for_backward(*saved)
+        ctx.stack = stack
+        if stack:
+            return stacked
         return tuple(img for img, _, _ in outs)
 
     @staticmethod
     def backward(ctx, *dimgs):
         n, degree, recompute, tile_cull, plan = ctx.meta
+        if ctx.stack:
+            d = dimgs[0]
+            dimgs = tuple(None if d is None else d[k] for k in range(len(plan)))
         saved = ctx.saved_tensors
         params = list(saved[:9])
         grads = [torch.empty_like(p) for p in params]
@@ -440,15 +453,19 @@ class PVGRenderViews(torch.autograd.Function):
             views = [(c, f, geom, bins, saved[9 + 2 * k], saved[10 + 2 * k], dimgs[k])
                      for k, ((c, f, _), (geom, bins)) in enumerate(zip(plan, ctx.kept))]
             render_bwd_views(params, n, degree, views, grads=grads, accumulate=False)
-        return (None, None, None, *grads)
+        return (None, None, None, None, *grads)
 
 
-def pvg_render_views(params, views, recompute="auto", tile_cull=True):
+def pvg_render_views(params, views, recompute="auto", tile_cull=True, stack=False):
     """Differentiable renders of the nine parameter tensors for several views:
     views = [(cam, t), (cam, t, dt), ... or (cam, t, dt, advect_mode, bg)];
-    returns one image [3,H,W] per view.  recompute: True, False or "auto"
+    returns one image [3,H,W] per view, or with stack=True (views of one
+    resolution) a single [V,3,H,W] tensor.  recompute: True, False or "auto"
     (see PVGRenderViews)."""
-    return PVGRenderViews.apply(_full_views(views), recompute, tile_cull, *params)
+    full = _full_views(views)
+    if stack and len({(int(v[0]["width"]), int(v[0]["height"])) for v in full}) != 1:
+        raise ValueError("stack=True needs views of one resolution")
+    return PVGRenderViews.apply(full, recompute, tile_cull, bool(stack), *params)
 
 
 def pvg_render(params, cam, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), recompute=True, tile_cull=True):

@@ -221,6 +221,17 @@ def test_multi_view_render_matches_single_views(recompute):
         for f, p, g in zip(FIELDS, params, ref_grads):
             worst, l2 = grad_tolerance_report(p.grad.cpu().numpy(), g.cpu().numpy(), rel=1e-4)
             assert worst <= 1.0, (shrink, f, worst)
+        # the same views as one stacked [V,3,H,W] output
+        for p in params:
+            p.grad = None
+        stacked = pvg.pvg_render_views(params, views, recompute=recompute, stack=True)
+        assert stacked.shape == (6, 3, 208, 320)
+        (stacked * torch.stack(w)).sum().backward()
+        for k, b in enumerate(ref_imgs):
+            assert torch.equal(stacked[k].detach(), b)
+        for f, p, g in zip(FIELDS, params, ref_grads):
+            worst, l2 = grad_tolerance_report(p.grad.cpu().numpy(), g.cpu().numpy(), rel=1e-4)
+            assert worst <= 1.0, ("stacked", shrink, f, worst)
 
 
 def test_edge_cases(orc):
