@@ -381,6 +381,12 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
   BwdViews pk;
   std::memset(&pk, 0, sizeof(pk));
   bool first_group = true;
+  // Views go to g2d slots in turn.  The per-Gaussian pass runs per group of
+  // `group` views: concurrently, one view per side stream, so the pass over
+  // a finished group overlaps the next group's compositing adjoints; the
+  // side streams wait for the caller's stream only when slots are reused.
+  const int32_t group = serial ? kMaxBwdViews : regions;
+  int32_t used_slots = 0;
   auto flush = [&]() -> int {
     if (pk.nv == 0) return PVG_OK;
     int st = join();
@@ -388,7 +394,11 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
     PVG_HIP(launch_preprocess_bwd(pk, *grad, first_group ? accumulate : 1, s));
     first_group = false;
     pk.nv = 0;
-    return fork();  // the next group reuses the g2d slots
+    if (used_slots == kMaxBwdViews) {  // the next views reuse the slots this pass read
+      used_slots = 0;
+      return fork();
+    }
+    return PVG_OK;
   };
   {
     const int st = fork();
@@ -401,7 +411,8 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
     v.final_T = const_cast<float*>(final_T[k]);
     v.n_contrib = const_cast<int32_t*>(n_contrib[k]);
     v.dL_dimg = dL_dimg[k];
-    float* g2d = reinterpret_cast<float*>(base + slot_bytes * static_cast<size_t>(pk.nv));
+    float* g2d = reinterpret_cast<float*>(base + slot_bytes * static_cast<size_t>(used_slots));
+    ++used_slots;
     const int32_t r = launched % regions;
     char* region = base + off_rec + region_bytes * static_cast<size_t>(r);
     float* rec = reinterpret_cast<float*>(region);
@@ -416,7 +427,7 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
     pk.rgb[pk.nv] = geoms[k].rgb;
     pk.g2d[pk.nv] = g2d;
     ++pk.nv;
-    if (pk.nv == kMaxBwdViews) {
+    if (pk.nv == group || used_slots == kMaxBwdViews) {
       const int st = flush();
       if (st != PVG_OK) return st;
     }
