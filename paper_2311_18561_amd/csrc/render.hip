@@ -81,6 +81,26 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
+// e^x for the compositing loops: Cody and Waite's reduction x log2(e) = n + f
+// with n = rint(x log2(e)), where the product's rounding error is recovered
+// by an FMA and a second, low-order part of log2(e) (the constant split in
+// two floats), 2^f from the hardware base-2 exponential on |f| <= 1/2 + eps,
+// and the exponent n applied exactly by ldexp.  These are the operations of
+// the device library's expf, which adds range checks for overflow and
+// underflow; here the results are equal bit for bit on (-103, 0] and callers
+// discard every pair with x > 0, while below -103 the value is 0 or a
+// subnormal far under any alpha threshold.  |x| stays below 2^31 / log2(e)
+// for any finite pair exponent of a listed Gaussian (a conic entry is at most
+// 1 / 0.3 after the dilation, and offsets are bounded by the image).
+__device__ __forceinline__ float exp_blend(float x) {
+  constexpr float kL2eHi = 1.44269502162933349609375f;  // log2(e) rounded to float
+  constexpr float kL2eLo = 1.92596285e-08f;             // log2(e) - kL2eHi, rounded toward zero
+  const float ph = x * kL2eHi;
+  const float pl = fmaf(x, kL2eLo, fmaf(x, kL2eHi, -ph));
+  const float n = __builtin_rintf(ph);
+  return __builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f((ph - n) + pl), static_cast<int>(n));
+}
+
 // G-exponent of a (pixel, Gaussian) pair; the exact arithmetic (and with it
 // every branch decision) is shared by the forward and the adjoint.
 __device__ __forceinline__ float pair_power(float dx, float dy, float A, float B, float C) {
@@ -153,7 +173,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
         if (kCount) evaluated += act[k] ? 1 : 0;
         const float dx = gm.x - fpx, dy = gm.y - static_cast<float>(py0 + 4 * k);
         const float power = pair_power(dx, dy, gc.x, gc.y, gc.z);
-        const float alpha = fminf(kAlphaMax, gc.w * expf(power));
+        const float alpha = fminf(kAlphaMax, gc.w * exp_blend(power));
         const bool ok = act[k] && !(power > 0.0f) && !(alpha < kAlphaMin);
         const float Tn = T[k] * (1.0f - alpha);
         const bool stop = ok && Tn < kTMin;
@@ -271,49 +291,55 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       const float4 gc = s_co[j];
       const float4 cc = s_rgb[j];
       const int pos = __float_as_int(cc.w);
-      // a[0..4] first hold the lane's moments sum(gp dx), sum(gp dy),
-      // sum(gp dx^2), sum(gp dx dy), sum(gp dy^2) of the power gradient gp;
-      // the conic turns them into the mean and conic gradients once per lane
-      float a[9];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) a[q] = 0.0f;
+      // The lane's four pixels share the column offset dx.  Per pixel the
+      // power gradient is gp = alpha dL/dalpha (zero where the pair is unused
+      // or alpha is clamped); the lane sums s0 = sum gp, s1 = sum gp dy and
+      // s2 = sum gp dy^2, from which the moments of gp in (dx, dy) follow.
+      // An unused pair takes alpha = 0, which leaves T (rcp(1) is exact)
+      // and the colour behind it unchanged, so no selects are needed.
+      const float dx = gm.x - fpx;
+      float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, cr = 0.0f, cgr = 0.0f, cb = 0.0f;
       bool any = false;
 #pragma unroll
       for (int k = 0; k < kPix; ++k) {
         const bool inr = pos < last[k];
         if (kCount) evaluated += inr ? 1 : 0;
-        const float dx = gm.x - fpx, dy = gm.y - static_cast<float>(py0 + 4 * k);
+        const float dy = gm.y - static_cast<float>(py0 + 4 * k);
         const float power = pair_power(dx, dy, gc.x, gc.y, gc.z);
-        const float G = expf(power);
-        const float raw = gc.w * G;
+        const float raw = gc.w * exp_blend(power);
         const float alpha = fminf(kAlphaMax, raw);
         const bool ok = inr && !(power > 0.0f) && !(alpha < kAlphaMin);
         any = any || ok;
-        const float om = 1.0f - alpha;
-        T[k] = ok ? T[k] * __builtin_amdgcn_rcpf(om) : T[k];
+        const float au = ok ? alpha : 0.0f;
+        const float om = 1.0f - au;
+        T[k] *= __builtin_amdgcn_rcpf(om);
         const float cg = cc.x * gr[k] + cc.y * gg[k] + cc.z * gb[k];
         const float dal = T[k] * (cg - rr[k]);
-        const float w = ok ? alpha * T[k] : 0.0f;
-        a[6] = fmaf(w, gr[k], a[6]);
-        a[7] = fmaf(w, gg[k], a[7]);
-        a[8] = fmaf(w, gb[k], a[8]);
-        rr[k] = ok ? fmaf(alpha, cg, om * rr[k]) : rr[k];
-        const bool nc = ok && !(raw > kAlphaMax);
-        const float gp = nc ? alpha * dal : 0.0f;
-        a[5] += nc ? G * dal : 0.0f;
-        a[0] = fmaf(dx, gp, a[0]);
-        a[1] = fmaf(dy, gp, a[1]);
-        a[2] = fmaf(dx * dx, gp, a[2]);
-        a[3] = fmaf(dx * dy, gp, a[3]);
-        a[4] = fmaf(dy * dy, gp, a[4]);
+        const float w = au * T[k];
+        cr = fmaf(w, gr[k], cr);
+        cgr = fmaf(w, gg[k], cgr);
+        cb = fmaf(w, gb[k], cb);
+        rr[k] = fmaf(au, cg, om * rr[k]);
+        const float gp = (raw > kAlphaMax ? 0.0f : au) * dal;
+        s0 += gp;
+        s1 = fmaf(dy, gp, s1);
+        s2 = fmaf(dy * dy, gp, s2);
       }
-      {  // power = -(A dx^2 + C dy^2)/2 - B dx dy, d(mean) = d(dx, dy)
-        const float sx = a[0], sy = a[1];
-        a[0] = -(gc.x * sx + gc.y * sy);
-        a[1] = -(gc.y * sx + gc.z * sy);
-        a[2] *= -0.5f;
-        a[3] = -a[3];
-        a[4] *= -0.5f;
+      // power = -(A dx^2 + C dy^2)/2 - B dx dy and d(mean) = d(dx, dy); the
+      // exponential's own gradient, sum G dL/dalpha over unclamped pairs, is
+      // s0 / o (there alpha = o G)
+      float a[9];
+      {
+        const float sx = dx * s0;
+        a[0] = -(gc.x * sx + gc.y * s1);
+        a[1] = -(gc.y * sx + gc.z * s1);
+        a[2] = -0.5f * (dx * sx);
+        a[3] = -(dx * s1);
+        a[4] = -0.5f * s2;
+        a[5] = gc.w > 0.0f ? s0 * __builtin_amdgcn_rcpf(gc.w) : 0.0f;
+        a[6] = cr;
+        a[7] = cgr;
+        a[8] = cb;
       }
       const bool wany = __any(any);
       if (wany) {
