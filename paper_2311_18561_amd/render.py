@@ -316,51 +316,69 @@ class PVGRender(torch.autograd.Function):
 
 
 KEEP_FRACTION = 0.1  # recompute="auto" keeps the views' lists while they fit this share of device memory
-VIEW_STREAMS = 3     # views of one call run concurrently on this many side streams (default priority)
+VIEW_STREAMS = 3     # views of one call run concurrently on this many lanes: the caller's stream and side streams (default priority)
 _side_streams: dict = {}
 
 
 def _streams(dev):
     key = dev.index
     if key not in _side_streams:
-        _side_streams[key] = [torch.cuda.Stream(device=dev) for _ in range(VIEW_STREAMS)]
+        _side_streams[key] = [torch.cuda.Stream(device=dev) for _ in range(max(VIEW_STREAMS - 1, 0))]
     return _side_streams[key]
 
 
 def _forward_views(params, n, degree, views, tile_cull, stacked=None):
-    """Preprocess, bin and composite every view; view k runs on side stream
-    k mod VIEW_STREAMS (their latency-bound sort and scan kernels overlap),
-    joined back into the caller's stream.  One overflow check for all views
-    at the end; a view that outgrew its cached capacity is redone.  With
-    `stacked` ([V,3,H,W], allocated on the caller's stream) view k's image is
-    written into stacked[k]."""
+    """Preprocess, bin and composite every view.  View k runs on lane
+    k mod VIEW_STREAMS, where lane 0 is the caller's stream and the others
+    are side streams forked from it and joined back into it (the views'
+    latency-bound sort and scan kernels overlap; the first view starts with
+    no cross-stream wait).  Each view copies its overflow flag to pinned
+    host memory right after binning, so the host waits only for the last
+    binning, not for the compositing, before it checks the flags and returns
+    (the images are ordered before any later work on the caller's stream).
+    A view that outgrew its cached capacity is redone.  With `stacked`
+    ([V,3,H,W], allocated on the caller's stream) view k's image is written
+    into stacked[k]."""
     dev = params[0].device
     main = torch.cuda.current_stream(dev)
-    side = _streams(dev)
-    start = torch.cuda.Event()
-    start.record(main)
-    plans, outs, done = [], [], []
+    lanes = [main, *_streams(dev)]
+    start = None
+    if len(views) > 1 and len(lanes) > 1:
+        start = torch.cuda.Event()
+        start.record(main)
+    flags = torch.empty(len(views), dtype=torch.int32, pin_memory=True)
+    plans, outs, done, flagged = [], [], [], []
     for k, (cam, t, dt, mode, bg) in enumerate(views):
-        st = side[k % len(side)]
-        st.wait_event(start)
+        st = lanes[k % len(lanes)]
+        if st is not main and k < len(lanes):
+            st.wait_event(start)
         with torch.cuda.stream(st):
             c, f = camera_struct(cam), frame_struct(t, dt, mode, bg)
             geom = preprocess(params, n, degree, c, f)
             cap = _capacity_hint.get((dev.index, int(c.width), int(c.height), bool(tile_cull)))
             bins = bin_sort(geom, c, tile_cull=tile_cull) if cap is None else bin_sort_nosync(geom, c, cap, tile_cull)
+            flags[k].copy_(bins.counters[2], non_blocking=True)
+            fe = torch.cuda.Event()
+            fe.record(st)
             out = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k])
-            ev = torch.cuda.Event()
-            ev.record(st)
+            ev = None
+            if st is not main:
+                ev = torch.cuda.Event()
+                ev.record(st)
         plans.append([c, f, geom, bins])
         outs.append(out)
-        done.append(ev)
-    for ev in done:
-        main.wait_event(ev)
-    for (_, _, geom, bins), out in zip(plans, outs):
-        for tns in (*geom.tensors(), *bins.tensors(), *(out if stacked is None else out[1:])):
-            tns.record_stream(main)
-    over = torch.stack([b.counters[2] for _, _, _, b in plans]).cpu().tolist()
-    for k, flag in enumerate(over):
+        done.append((st, ev))
+        flagged.append(fe)
+    for st, ev in done:
+        if ev is not None:
+            main.wait_event(ev)
+    for (st, _), (_, _, geom, bins), out in zip(done, plans, outs):
+        if st is not main:
+            for tns in (*geom.tensors(), *bins.tensors(), *(out if stacked is None else out[1:])):
+                tns.record_stream(main)
+    for fe in flagged:
+        fe.synchronize()
+    for k, flag in enumerate(flags.tolist()):
         if flag:  # this view outgrew the cached capacity: redo it with the counting path
             c, f, geom, _ = plans[k]
             bins = bin_sort(geom, c, tile_cull=tile_cull)
