@@ -245,36 +245,50 @@ def _scratch(dev, nbytes):
     return buf
 
 
+class _BwdViewsArgs:
+    """The ctypes arguments of pvg_render_bwd_views for a fixed set of views,
+    views = [(cam, frame, geom, bins, final_T, n_contrib)], built once (the
+    multi-view autograd node builds them in its forward, so its backward only
+    adds the image gradients)."""
+
+    def __init__(self, params, n, degree, views):
+        nv = len(views)
+        self.nv = nv
+        self.g = gaussians_struct(params, n, degree)
+        self.cams = (L.Camera * nv)(*[v[0] for v in views])
+        self.frames = (L.Frame * nv)(*[v[1] for v in views])
+        self.geoms = (L.Geom * nv)(*[v[2].struct() for v in views])
+        self.bins = (L.Bins * nv)(*[v[3].struct() for v in views])
+        self.f_t = (C.c_void_p * nv)(*[v[4].data_ptr() for v in views])
+        self.n_c = (C.c_void_p * nv)(*[v[5].data_ptr() for v in views])
+        size = C.c_size_t()
+        L.check(L.load().pvg_bwd_views_tmp_bytes(n, nv, max(int(v[0].width) for v in views),
+                                                 max(int(v[0].height) for v in views),
+                                                 max(v[3].capacity for v in views), C.byref(size)))
+        self.tmp_bytes = int(size.value)
+
+    def call(self, dev, dimgs, grads, accumulate):
+        gg = L.GaussiansGrad()
+        for name, t in zip(FIELDS, grads):
+            setattr(gg, name, t.data_ptr())
+        dls = [None if d is None else d.contiguous() for d in dimgs]
+        d_l = (C.c_void_p * self.nv)(*[None if d is None else d.data_ptr() for d in dls])
+        tmp = _scratch(dev, self.tmp_bytes)
+        L.check(L.load().pvg_render_bwd_views(C.byref(self.g), self.nv, self.cams, self.frames, self.geoms,
+                                              self.bins, self.f_t, self.n_c, d_l, C.byref(gg),
+                                              1 if accumulate else 0, _p(tmp), int(tmp.numel()), _stream_handle()))
+        return grads
+
+
 def render_bwd_views(params, n, degree, views, grads=None, accumulate=False):
     """One adjoint call for several views of the same Gaussians:
     views = [(cam, frame, geom, bins, final_T, n_contrib, dL_dimg or None)];
     the per-Gaussian chain rule of all views is summed in registers and the
     gradient written (or added) once."""
-    dev = params[0].device
     if grads is None:
         grads = [torch.empty_like(p) for p in params]
-    nv = len(views)
-    g = gaussians_struct(params, n, degree)
-    gg = L.GaussiansGrad()
-    for name, t in zip(FIELDS, grads):
-        setattr(gg, name, t.data_ptr())
-    cams = (L.Camera * nv)(*[v[0] for v in views])
-    frames = (L.Frame * nv)(*[v[1] for v in views])
-    geoms = (L.Geom * nv)(*[v[2].struct() for v in views])
-    bins = (L.Bins * nv)(*[v[3].struct() for v in views])
-    dls = [None if v[6] is None else v[6].contiguous() for v in views]
-    f_t = (C.c_void_p * nv)(*[v[4].data_ptr() for v in views])
-    n_c = (C.c_void_p * nv)(*[v[5].data_ptr() for v in views])
-    d_l = (C.c_void_p * nv)(*[None if d is None else d.data_ptr() for d in dls])
-    size = C.c_size_t()
-    lib = L.load()
-    L.check(lib.pvg_bwd_views_tmp_bytes(n, nv, max(int(v[0].width) for v in views),
-                                        max(int(v[0].height) for v in views),
-                                        max(v[3].capacity for v in views), C.byref(size)))
-    tmp = _scratch(dev, int(size.value))
-    L.check(lib.pvg_render_bwd_views(C.byref(g), nv, cams, frames, geoms, bins, f_t, n_c, d_l, C.byref(gg),
-                                     1 if accumulate else 0, _p(tmp), int(tmp.numel()), _stream_handle()))
-    return grads
+    args = _BwdViewsArgs(params, n, degree, [v[:6] for v in views])
+    return args.call(params[0].device, [v[6] for v in views], grads, accumulate)
 
 
 def render(params, cam: dict, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), tile_cull=True):
@@ -434,6 +448,8 @@ class PVGRenderViews(torch.autograd.Function):
             recompute = kept_bytes > KEEP_FRACTION * torch.cuda.get_device_properties(dev).total_memory
         ctx.meta = (n, degree, bool(recompute), tile_cull, [(c, f, b.capacity) for c, f, _, b in plans])
         ctx.kept = None if recompute else [(g, b) for _, _, g, b in plans]
+        ctx.bwd = None if recompute else _BwdViewsArgs(
+            params, n, degree, [(c, f, g, b, T, nc) for (c, f, g, b), (_, T, nc) in zip(plans, outs)])
         saved = list(params)
         for _, T, nc in outs:
             saved += [T, nc]
@@ -467,10 +483,8 @@ class PVGRenderViews(torch.autograd.Function):
             if first:
                 for gr in grads:
                     gr.zero_()
-        else:
-            views = [(c, f, geom, bins, saved[9 + 2 * k], saved[10 + 2 * k], dimgs[k])
-                     for k, ((c, f, _), (geom, bins)) in enumerate(zip(plan, ctx.kept))]
-            render_bwd_views(params, n, degree, views, grads=grads, accumulate=False)
+        else:  # the kept lists, final_T and n_contrib, with the arguments built in the forward
+            ctx.bwd.call(params[0].device, dimgs, grads, accumulate=False)
         return (None, None, None, None, *grads)
 
 
