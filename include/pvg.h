@@ -162,6 +162,18 @@ int pvg_workspace_query(int64_t n, int32_t width, int32_t height, int64_t capaci
 int pvg_preprocess(const pvg_gaussians* g, const pvg_camera* cam, const pvg_frame* frame,
                    pvg_geom* out, void* stream);
 
+/* pvg_preprocess for n_views views of the same Gaussians (a training step's
+ * cameras and times, Sec. 3.4: H(t) and the translated H^(t + dt)): outs[k]
+ * receives exactly what pvg_preprocess(g, &cams[k], &frames[k], &outs[k])
+ * would write.  The views are processed eight at a time in one pass over the
+ * parameters, so each Gaussian's parameters are read from HBM once per pass.
+ * cams, frames and outs are host arrays of n_views entries (the geom arrays
+ * in them are device memory, outs[k].n must equal g->n, and no two outs may
+ * share memory).  PVG_ERR_INVALID on null arrays, n_views < 1 or an invalid
+ * camera, frame or geom; asynchronous on `stream`. */
+int pvg_preprocess_views(const pvg_gaussians* g, int32_t n_views, const pvg_camera* cams,
+                         const pvg_frame* frames, pvg_geom* outs, void* stream);
+
 /* Depth ordering per tile (Sec. 3.1): emits one instance per (visible
  * Gaussian, touched tile) and sorts them by (tile, camera depth, index)
  * with an LDS-histogram LSD radix sort; writes the per-tile ranges.

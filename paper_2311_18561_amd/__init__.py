@@ -18,6 +18,7 @@ from .render import (  # noqa: F401
     camera_struct,
     frame_struct,
     preprocess,
+    preprocess_views,
     pvg_render,
     pvg_render_views,
     render,

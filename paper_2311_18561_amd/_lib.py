@@ -108,6 +108,7 @@ def load():
     sig = {
         "pvg_workspace_query": ([i64, i32, i32, i64, P(WsSizes)], i32),
         "pvg_preprocess": ([P(Gaussians), P(Camera), P(Frame), P(Geom), vp], i32),
+        "pvg_preprocess_views": ([P(Gaussians), i32, P(Camera), P(Frame), P(Geom), vp], i32),
         "pvg_bin_sort": ([P(Geom), P(Camera), P(Bins), vp, C.c_size_t, i32, vp], i32),
         "pvg_render_fwd": ([P(Geom), P(Bins), P(Camera), P(Frame), vp, vp, vp, vp], i32),
         "pvg_render_bwd": ([P(Gaussians), P(Camera), P(Frame), P(Geom), P(Bins), vp, vp, vp, P(GaussiansGrad),

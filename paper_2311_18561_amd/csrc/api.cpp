@@ -251,6 +251,29 @@ int pvg_preprocess(const pvg_gaussians* g, const pvg_camera* cam, const pvg_fram
   return PVG_OK;
 }
 
+int pvg_preprocess_views(const pvg_gaussians* g, int32_t n_views, const pvg_camera* cams, const pvg_frame* frames,
+                         pvg_geom* outs, void* stream) {
+  if (!check_gaussians(g)) return PVG_ERR_INVALID;
+  if (n_views < 1 || !cams || !frames || !outs) {
+    set_error("n_views < 1 or a per-view array is null");
+    return PVG_ERR_INVALID;
+  }
+  for (int32_t k = 0; k < n_views; ++k)
+    if (!check_camera(&cams[k]) || !check_frame(&frames[k]) || !check_geom(&outs[k], g->n)) return PVG_ERR_INVALID;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  PreViews pk;
+  std::memset(&pk, 0, sizeof(pk));
+  for (int32_t k0 = 0; k0 < n_views; k0 += kMaxBwdViews) {  // up to eight views per pass over the parameters
+    pk.nv = std::min(n_views - k0, kMaxBwdViews);
+    for (int32_t k = 0; k < pk.nv; ++k) {
+      pk.views[k] = make_view(g, &cams[k0 + k], &frames[k0 + k]);
+      pk.geoms[k] = to_geom(&outs[k0 + k]);
+    }
+    PVG_HIP(launch_preprocess_views(pk, s));
+  }
+  return PVG_OK;
+}
+
 int pvg_bin_sort(const pvg_geom* geom, const pvg_camera* cam, pvg_bins* bins, void* tmp, size_t tmp_bytes,
                  int32_t sync_count, void* stream) {
   if (!geom || !check_geom(geom, geom->n) || !check_camera(cam) || !check_bins(bins)) return PVG_ERR_INVALID;

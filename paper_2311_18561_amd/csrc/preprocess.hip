@@ -15,11 +15,8 @@
 
 namespace pvg {
 
-__global__ void __launch_bounds__(256) k_preprocess(ViewSet vs, Geom geom, unsigned long long* dummy) {
-  const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (gi >= live_gauss(vs)) return;
-  const View& v = view_at(vs, view_of_gauss(vs, gi));
-  const int64_t i = gi - v.geom_off;
+// The projected record of Gaussian i of view v at slot gi of geom.
+__device__ __forceinline__ void preprocess_one(const View& v, int64_t i, const Geom& geom, int64_t gi) {
   Proj P;
   const bool vis = project(v, i, P, true);
   geom.depth[gi] = P.p[2];
@@ -40,9 +37,24 @@ __global__ void __launch_bounds__(256) k_preprocess(ViewSet vs, Geom geom, unsig
     geom.radius[gi] = 0;
     geom.tiles[gi] = 0u;
   }
+}
+
+__global__ void __launch_bounds__(256) k_preprocess(ViewSet vs, Geom geom, unsigned long long* dummy) {
+  const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (gi >= live_gauss(vs)) return;
+  const View& v = view_at(vs, view_of_gauss(vs, gi));
+  preprocess_one(v, gi - v.geom_off, geom, gi);
   (void)dummy;
 }
 
+// Several views of one set of Gaussians: one thread per Gaussian projects it
+// into every view in turn, so its parameters come from HBM once (the later
+// views hit the caches) and each view's record is the single-view one.
+__global__ void __launch_bounds__(256) k_preprocess_views(PreViews pk) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= pk.views[0].s.n) return;
+  for (int32_t k = 0; k < pk.nv; ++k) preprocess_one(pk.views[k], i, pk.geoms[k], i);
+}
 
 // Gradient entries of one Gaussian other than its SH coefficients.
 struct GeoGrad {
@@ -294,6 +306,14 @@ hipError_t launch_preprocess(const ViewSet& vs, const Geom& geom, hipStream_t s)
   if (vs.total_gauss == 0) return hipSuccess;
   StageScope scope(PVG_STAGE_PREPROCESS, s);
   hipLaunchKernelGGL(k_preprocess, dim3(grid_for(vs.total_gauss, 256)), dim3(256), 0, s, vs, geom, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_views(const PreViews& pk, hipStream_t s) {
+  const int64_t n = pk.views[0].s.n;
+  if (n == 0 || pk.nv <= 0) return hipSuccess;
+  StageScope scope(PVG_STAGE_PREPROCESS, s);
+  hipLaunchKernelGGL(k_preprocess_views, dim3(grid_for(n, 256)), dim3(256), 0, s, pk);
   return hipGetLastError();
 }
 

@@ -132,6 +132,14 @@ struct BwdViews {
 };
 hipError_t launch_preprocess_bwd(const BwdViews& pk, const pvg_gaussians_grad& grad, int accumulate,
                                  hipStream_t s);
+// Forward records of up to kMaxBwdViews views of one set of Gaussians (each
+// view's geom holds slots 0..n-1).
+struct PreViews {
+  int32_t nv;
+  View views[kMaxBwdViews];
+  Geom geoms[kMaxBwdViews];
+};
+hipError_t launch_preprocess_views(const PreViews& pk, hipStream_t s);
 // culled: the lists hold only tiles that pass tile_reachable (the render skips the test)
 hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals,
                              const uint32_t* ranges, bool culled, hipStream_t s);

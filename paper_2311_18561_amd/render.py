@@ -162,6 +162,18 @@ def preprocess(params, n, degree, cam: L.Camera, frame: L.Frame) -> Geom:
     return geom
 
 
+def preprocess_views(params, n, degree, cams, frames) -> list:
+    """preprocess for several views in one pass over the parameters: one Geom per view."""
+    dev = params[0].device
+    geoms = [Geom(n, dev) for _ in cams]
+    g = gaussians_struct(params, n, degree)
+    nv = len(cams)
+    outs = (L.Geom * nv)(*[gm.struct() for gm in geoms])
+    L.check(L.load().pvg_preprocess_views(C.byref(g), nv, (L.Camera * nv)(*cams), (L.Frame * nv)(*frames), outs,
+                                          _stream_handle()))
+    return geoms
+
+
 def bin_sort(geom: Geom, cam: L.Camera, capacity: int | None = None, tile_cull: bool = True) -> Bins:
     """Instances sorted by (tile, depth, index); grows the capacity on demand."""
     dev = geom.xy.device
@@ -342,33 +354,34 @@ def _streams(dev):
 
 
 def _forward_views(params, n, degree, views, tile_cull, stacked=None):
-    """Preprocess, bin and composite every view.  View k runs on lane
-    k mod VIEW_STREAMS, where lane 0 is the caller's stream and the others
-    are side streams forked from it and joined back into it (the views'
-    latency-bound sort and scan kernels overlap; the first view starts with
-    no cross-stream wait).  Each view copies its overflow flag to pinned
-    host memory right after binning, so the host waits only for the last
-    binning, not for the compositing, before it checks the flags and returns
-    (the images are ordered before any later work on the caller's stream).
-    A view that outgrew its cached capacity is redone.  With `stacked`
+    """Preprocess all views in one pass over the parameters on the caller's
+    stream, then bin and composite view k on lane k mod VIEW_STREAMS, where
+    lane 0 is the caller's stream and the others are side streams forked from
+    it and joined back into it (the views' latency-bound sort and scan
+    kernels overlap).  Each view copies its overflow flag to pinned host
+    memory right after binning, so the host waits only for the last binning,
+    not for the compositing, before it checks the flags and returns (the
+    images are ordered before any later work on the caller's stream).  A
+    view that outgrew its cached capacity is redone.  With `stacked`
     ([V,3,H,W], allocated on the caller's stream) view k's image is written
     into stacked[k]."""
     dev = params[0].device
     main = torch.cuda.current_stream(dev)
     lanes = [main, *_streams(dev)]
+    cams = [camera_struct(cam) for cam, *_ in views]
+    frames = [frame_struct(t, dt, mode, bg) for _, t, dt, mode, bg in views]
+    geoms = preprocess_views(params, n, degree, cams, frames)
     start = None
     if len(views) > 1 and len(lanes) > 1:
         start = torch.cuda.Event()
         start.record(main)
     flags = torch.empty(len(views), dtype=torch.int32, pin_memory=True)
     plans, outs, done, flagged = [], [], [], []
-    for k, (cam, t, dt, mode, bg) in enumerate(views):
+    for k, (c, f, geom) in enumerate(zip(cams, frames, geoms)):
         st = lanes[k % len(lanes)]
         if st is not main and k < len(lanes):
             st.wait_event(start)
         with torch.cuda.stream(st):
-            c, f = camera_struct(cam), frame_struct(t, dt, mode, bg)
-            geom = preprocess(params, n, degree, c, f)
             cap = _capacity_hint.get((dev.index, int(c.width), int(c.height), bool(tile_cull)))
             bins = bin_sort(geom, c, tile_cull=tile_cull) if cap is None else bin_sort_nosync(geom, c, cap, tile_cull)
             flags[k].copy_(bins.counters[2], non_blocking=True)
@@ -386,9 +399,9 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None):
     for st, ev in done:
         if ev is not None:
             main.wait_event(ev)
-    for (st, _), (_, _, geom, bins), out in zip(done, plans, outs):
-        if st is not main:
-            for tns in (*geom.tensors(), *bins.tensors(), *(out if stacked is None else out[1:])):
+    for (st, _), (_, _, _, bins), out in zip(done, plans, outs):
+        if st is not main:  # allocated on the side stream, used later on the caller's
+            for tns in (*bins.tensors(), *(out if stacked is None else out[1:])):
                 tns.record_stream(main)
     for fe in flagged:
         fe.synchronize()

@@ -189,6 +189,28 @@ def test_recompute_and_kept_lists_agree(orc):
         np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * (1 + np.abs(b).max()))
 
 
+def test_preprocess_views_equals_single_view_preprocess():
+    """pvg_preprocess_views writes, for each view, exactly the record
+    pvg_preprocess writes (ten views: two passes of up to eight; several
+    cameras, times, flow offsets and both advection modes)."""
+    import importlib
+    R = importlib.import_module("paper_2311_18561_amd.render")
+    cfg = gen.make_config(1, n=20_000)
+    params = to_device(cfg["scene"])
+    n, degree = cfg["scene"]["n"], cfg["scene"]["sh_degree"]
+    cams, frames = [], []
+    for k in range(10):
+        cam = gen.yaw_camera(320 - 16 * (k % 3), 208, -30.0 + 6.0 * k, (0.0, 0.0, 0.5 * k))
+        cams.append(R.camera_struct(cam))
+        frames.append(R.frame_struct(0.1 * k, 0.05 * (k % 2), k % 2, (0.0, 0.0, 0.0)))
+    multi = R.preprocess_views(params, n, degree, cams, frames)
+    for k, (c, f) in enumerate(zip(cams, frames)):
+        ref = R.preprocess(params, n, degree, c, f)
+        for a, b in zip(multi[k].tensors(), ref.tensors()):
+            assert torch.equal(a, b), k
+        assert int((ref.radius > 0).sum()) > 100, k
+
+
 @pytest.mark.parametrize("recompute", [True, False])
 def test_multi_view_render_matches_single_views(recompute):
     """pvg_render_views: each image equals the single-view render bit for bit;

@@ -84,6 +84,16 @@ def test_invalid_arguments_rejected_on_host(lib):
     size = C.c_size_t()
     assert lib.pvg_bwd_views_tmp_bytes(100, 6, 64, 48, 1000, C.byref(size)) == 0 and size.value > 0
     assert lib.pvg_bwd_views_tmp_bytes(100, 0, 64, 48, 1000, C.byref(size)) == L.PVG_ERR_INVALID
+    # the multi-view preprocess: view count, null arrays, a bad camera among the views
+    g.n, g.sh_degree = 0, 0
+    cams2 = (L.Camera * 2)(cam, cam)
+    frs2 = (L.Frame * 2)(fr, fr)
+    geoms2 = (L.Geom * 2)(geom, geom)
+    assert lib.pvg_preprocess_views(C.byref(g), 0, cams2, frs2, geoms2, None) == L.PVG_ERR_INVALID
+    assert lib.pvg_preprocess_views(C.byref(g), 2, cams2, None, geoms2, None) == L.PVG_ERR_INVALID
+    cams2[1].znear = 0.0
+    assert lib.pvg_preprocess_views(C.byref(g), 2, cams2, frs2, geoms2, None) == L.PVG_ERR_INVALID
+    assert "znear" in L.last_error()
 
 
 def test_workspace_query(lib):
