@@ -47,13 +47,15 @@ __global__ void __launch_bounds__(256) k_preprocess(ViewSet vs, Geom geom, unsig
   (void)dummy;
 }
 
-// Several views of one set of Gaussians: one thread per Gaussian projects it
-// into every view in turn, so its parameters come from HBM once (the later
-// views hit the caches) and each view's record is the single-view one.
+// Several views of one set of Gaussians: block b projects the 256 Gaussians
+// of chunk b / nv into view b % nv, so the views of a chunk are dispatched
+// back to back and its parameters come from HBM once (the other views' reads
+// hit the caches); each view's record is the single-view one.
 __global__ void __launch_bounds__(256) k_preprocess_views(PreViews pk) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int32_t k = static_cast<int32_t>(blockIdx.x % static_cast<uint32_t>(pk.nv));
+  const int64_t i = static_cast<int64_t>(blockIdx.x / static_cast<uint32_t>(pk.nv)) * 256 + threadIdx.x;
   if (i >= pk.views[0].s.n) return;
-  for (int32_t k = 0; k < pk.nv; ++k) preprocess_one(pk.views[k], i, pk.geoms[k], i);
+  preprocess_one(pk.views[k], i, pk.geoms[k], i);
 }
 
 // Gradient entries of one Gaussian other than its SH coefficients.
@@ -313,7 +315,7 @@ hipError_t launch_preprocess_views(const PreViews& pk, hipStream_t s) {
   const int64_t n = pk.views[0].s.n;
   if (n == 0 || pk.nv <= 0) return hipSuccess;
   StageScope scope(PVG_STAGE_PREPROCESS, s);
-  hipLaunchKernelGGL(k_preprocess_views, dim3(grid_for(n, 256)), dim3(256), 0, s, pk);
+  hipLaunchKernelGGL(k_preprocess_views, dim3(grid_for(n, 256) * static_cast<unsigned>(pk.nv)), dim3(256), 0, s, pk);
   return hipGetLastError();
 }
 
