@@ -162,10 +162,12 @@ def preprocess(params, n, degree, cam: L.Camera, frame: L.Frame) -> Geom:
     return geom
 
 
-def preprocess_views(params, n, degree, cams, frames) -> list:
-    """preprocess for several views in one pass over the parameters: one Geom per view."""
+def preprocess_views(params, n, degree, cams, frames, geoms=None) -> list:
+    """preprocess for several views in one pass over the parameters: one Geom
+    per view (written into `geoms` when given)."""
     dev = params[0].device
-    geoms = [Geom(n, dev) for _ in cams]
+    if geoms is None:
+        geoms = [Geom(n, dev) for _ in cams]
     g = gaussians_struct(params, n, degree)
     nv = len(cams)
     outs = (L.Geom * nv)(*[gm.struct() for gm in geoms])
@@ -349,38 +351,59 @@ _side_streams: dict = {}
 def _streams(dev):
     key = dev.index
     if key not in _side_streams:
-        _side_streams[key] = [torch.cuda.Stream(device=dev) for _ in range(max(VIEW_STREAMS - 1, 0))]
+        # VIEW_STREAMS - 1 binning lanes besides the caller's stream, and one stream for later preprocess chunks
+        _side_streams[key] = [torch.cuda.Stream(device=dev) for _ in range(max(VIEW_STREAMS, 1))]
     return _side_streams[key]
 
 
+def _record(stream):
+    ev = torch.cuda.Event()
+    ev.record(stream)
+    return ev
+
+
 def _forward_views(params, n, degree, views, tile_cull, stacked=None):
-    """Preprocess all views in one pass over the parameters on the caller's
-    stream, then bin and composite view k on lane k mod VIEW_STREAMS, where
-    lane 0 is the caller's stream and the others are side streams forked from
-    it and joined back into it (the views' latency-bound sort and scan
-    kernels overlap).  Each view copies its overflow flag to pinned host
-    memory right after binning, so the host waits only for the last binning,
-    not for the compositing, before it checks the flags and returns (the
-    images are ordered before any later work on the caller's stream).  A
-    view that outgrew its cached capacity is redone.  With `stacked`
-    ([V,3,H,W], allocated on the caller's stream) view k's image is written
-    into stacked[k]."""
+    """Bin and composite view k on lane k mod VIEW_STREAMS, where lane 0 is
+    the caller's stream and the others are side streams forked from it and
+    joined back into it (the views' latency-bound sort and scan kernels
+    overlap).  The views are preprocessed in chunks of VIEW_STREAMS, each in
+    one pass over the parameters: the first on the caller's stream, the
+    others on a further side stream while the lanes bin the first chunk.
+    Each view copies its overflow flag to pinned host memory right after
+    binning, so the host waits only for the last binning, not for the
+    compositing, before it checks the flags and returns (the images are
+    ordered before any later work on the caller's stream).  A view that
+    outgrew its cached capacity is redone.  With `stacked` ([V,3,H,W],
+    allocated on the caller's stream) view k's image is written into
+    stacked[k]."""
     dev = params[0].device
     main = torch.cuda.current_stream(dev)
-    lanes = [main, *_streams(dev)]
+    side = _streams(dev)
+    lanes = [main, *side[:-1]]
     cams = [camera_struct(cam) for cam, *_ in views]
     frames = [frame_struct(t, dt, mode, bg) for _, t, dt, mode, bg in views]
-    geoms = preprocess_views(params, n, degree, cams, frames)
-    start = None
-    if len(views) > 1 and len(lanes) > 1:
+    geoms = [Geom(n, dev) for _ in views]  # on the caller's stream; every user is joined back into it
+    nl = len(lanes)
+    preprocess_views(params, n, degree, cams[:nl], frames[:nl], geoms[:nl])
+    start, ready = None, {}
+    if len(views) > 1 and nl > 1:
         start = torch.cuda.Event()
         start.record(main)
+    if len(views) > nl:
+        pre = side[-1]
+        pre.wait_event(start if start is not None else _record(main))
+        with torch.cuda.stream(pre):
+            for c0 in range(nl, len(views), nl):
+                preprocess_views(params, n, degree, cams[c0:c0 + nl], frames[c0:c0 + nl], geoms[c0:c0 + nl])
+                ready[c0 // nl] = _record(pre)
     flags = torch.empty(len(views), dtype=torch.int32, pin_memory=True)
     plans, outs, done, flagged = [], [], [], []
     for k, (c, f, geom) in enumerate(zip(cams, frames, geoms)):
-        st = lanes[k % len(lanes)]
-        if st is not main and k < len(lanes):
+        st = lanes[k % nl]
+        if st is not main and k < nl:
             st.wait_event(start)
+        if k >= nl:
+            st.wait_event(ready[k // nl])
         with torch.cuda.stream(st):
             cap = _capacity_hint.get((dev.index, int(c.width), int(c.height), bool(tile_cull)))
             bins = bin_sort(geom, c, tile_cull=tile_cull) if cap is None else bin_sort_nosync(geom, c, cap, tile_cull)
