@@ -387,24 +387,14 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
   }
 }
 
-// Sum of one Gaussian's flagged records in [e0, e0 + cnt): one thread reads
-// the flags 16 at a time, or, with the whole wave, lane l takes e0 + l,
-// e0 + l + 64, ...  The emission order keeps a Gaussian's pairs contiguous.
-__device__ __forceinline__ void gather_range(uint32_t e0, uint32_t cnt, bool wave, int lane,
-                                             const float* __restrict__ rec, const uint8_t* __restrict__ vis,
-                                             float acc[9]) {
+// Sum of one Gaussian's flagged records in [e0, e0 + cnt) by one thread,
+// reading the flags 16 at a time.  The emission order keeps a Gaussian's
+// pairs contiguous.
+__device__ __forceinline__ void gather_range(uint32_t e0, uint32_t cnt, const float* __restrict__ rec,
+                                             const uint8_t* __restrict__ vis, float acc[9]) {
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
   const uint32_t e1 = e0 + cnt;
-  if (wave) {
-    for (uint32_t e = e0 + static_cast<uint32_t>(lane); e < e1; e += 64) {
-      if (!vis[e]) continue;
-      const float* r = rec + 9 * static_cast<int64_t>(e);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) acc[q] += r[q];
-    }
-    return;
-  }
   for (uint32_t b = e0 & ~15u; b < e1; b += 16) {
     const uint4 w = *reinterpret_cast<const uint4*>(vis + b);
     const uint32_t words[4] = {w.x, w.y, w.z, w.w};
@@ -422,6 +412,61 @@ __device__ __forceinline__ void gather_range(uint32_t e0, uint32_t cnt, bool wav
 
 constexpr uint32_t kShortRange = 48;  // Gaussians with more listed pairs are gathered by a whole wave
 
+// Sum of one Gaussian's flagged records in [e0, e0 + cnt) by a whole wave:
+// each round, lane l reads the 16 flags at b + 16 l (1024 pairs per round),
+// the wave compacts the flagged indices into its LDS list `idx` (a wave
+// prefix sum of the lanes' counts gives each lane its slots), and the lanes
+// then take the listed records 64 at a time.  A near-camera splat with
+// thousands of listed tiles thus needs a few rounds instead of one round per
+// 64 flags.  Every lane returns its partial sums; the caller reduces them.
+__device__ __forceinline__ void gather_range_wave(uint32_t e0, uint32_t cnt, int lane,
+                                                  const float* __restrict__ rec,
+                                                  const uint8_t* __restrict__ vis, uint32_t* idx,
+                                                  float acc[9]) {
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
+  const uint32_t e1 = e0 + cnt;
+  for (uint32_t b = e0 & ~15u; b < e1; b += 1024) {
+    const uint32_t mb = b + 16u * static_cast<uint32_t>(lane);
+    uint32_t words[4] = {0u, 0u, 0u, 0u};
+    if (mb < e1) {
+      const uint4 w = *reinterpret_cast<const uint4*>(vis + mb);
+      words[0] = w.x; words[1] = w.y; words[2] = w.z; words[3] = w.w;
+    }
+    uint32_t bits = 0;  // bit j: pair mb + j is flagged and inside the range
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const uint32_t e = mb + static_cast<uint32_t>(j);
+      if (((words[j >> 2] >> (8 * (j & 3))) & 0xffu) && e >= e0 && e < e1) bits |= 1u << j;
+    }
+    const int c = __popc(bits);
+    int incl = c;  // inclusive prefix over the lanes
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += y;
+    }
+    const int total = __shfl(incl, 63, 64);
+    int slot = incl - c;
+    while (bits) {
+      const int j = __ffs(bits) - 1;
+      bits &= bits - 1u;
+      idx[slot++] = mb + static_cast<uint32_t>(j);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int k = lane; k < total; k += 64) {
+      const float* r = rec + 9 * static_cast<int64_t>(idx[k]);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) acc[q] += r[q];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 // Per visible Gaussian: the index range of its pairs (first[g] and the
 // listed count: its rectangle's tiles, or, for culled lists, up to the end
 // of its last row) and the sum of the flagged records.
@@ -430,6 +475,7 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, List
                                                      const float* __restrict__ rec,
                                                      const uint8_t* __restrict__ vis, float* g2d) {
   __shared__ uint32_t s_queue[256][3];
+  __shared__ uint32_t s_idx[4][1024];  // per wave: flagged pair indices of one round
   __shared__ int s_qn;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (tid == 0) s_qn = 0;
@@ -454,7 +500,7 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, List
   }
   if (visible && cnt <= kShortRange) {
     float acc[9];
-    gather_range(e0, cnt, false, 0, rec, vis, acc);
+    gather_range(e0, cnt, rec, vis, acc);
     float* dst = g2d + kG2DStride * gi;
 #pragma unroll
     for (int c = 0; c < 9; ++c) dst[c] = acc[c];
@@ -469,7 +515,7 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, List
   for (int qi = wid; qi < qn; qi += 4) {
     const uint32_t g = s_queue[qi][0];
     float acc[9], red[3];
-    gather_range(s_queue[qi][1], s_queue[qi][2], true, lane, rec, vis, acc);
+    gather_range_wave(s_queue[qi][1], s_queue[qi][2], lane, rec, vis, s_idx[wid], acc);
     wave_sum9(acc, red);
     if ((lane & 15) == 0) {
       const int r = lane >> 4;
