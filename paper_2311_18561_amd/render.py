@@ -366,9 +366,11 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None):
     """Bin and composite view k on lane k mod VIEW_STREAMS, where lane 0 is
     the caller's stream and the others are side streams forked from it and
     joined back into it (the views' latency-bound sort and scan kernels
-    overlap).  The views are preprocessed in chunks of VIEW_STREAMS, each in
-    one pass over the parameters: the first on the caller's stream, the
-    others on a further side stream while the lanes bin the first chunk.
+    overlap).  Views are preprocessed in chunks, each in one pass over the
+    parameters: with at most VIEW_STREAMS views all at once on the caller's
+    stream; with more, the first view on the caller's stream and the others
+    (views 1 .. VIEW_STREAMS - 1, then VIEW_STREAMS at a time) on a further
+    side stream while the lanes bin the earlier views.
     Each view copies its overflow flag to pinned host memory right after
     binning, so the host waits only for the last binning, not for the
     compositing, before it checks the flags and returns (the images are
@@ -384,26 +386,29 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None):
     frames = [frame_struct(t, dt, mode, bg) for _, t, dt, mode, bg in views]
     geoms = [Geom(n, dev) for _ in views]  # on the caller's stream; every user is joined back into it
     nl = len(lanes)
-    preprocess_views(params, n, degree, cams[:nl], frames[:nl], geoms[:nl])
-    start, ready = None, {}
-    if len(views) > 1 and nl > 1:
-        start = torch.cuda.Event()
-        start.record(main)
+    # chunks [0], [1, nl), [nl, 2 nl), ... when there are more views than lanes (the first
+    # view's binning then starts after one view's preprocess), else one chunk
     if len(views) > nl:
+        bounds = sorted(set([0, 1, *range(nl, len(views), nl), len(views)]))
+    else:
+        bounds = [0, len(views)]
+    preprocess_views(params, n, degree, cams[:bounds[1]], frames[:bounds[1]], geoms[:bounds[1]])
+    start, ready = _record(main), {}
+    if len(bounds) > 2:
         pre = side[-1]
-        pre.wait_event(start if start is not None else _record(main))
+        pre.wait_event(start)
         with torch.cuda.stream(pre):
-            for c0 in range(nl, len(views), nl):
-                preprocess_views(params, n, degree, cams[c0:c0 + nl], frames[c0:c0 + nl], geoms[c0:c0 + nl])
-                ready[c0 // nl] = _record(pre)
+            for a, b in zip(bounds[1:-1], bounds[2:]):
+                preprocess_views(params, n, degree, cams[a:b], frames[a:b], geoms[a:b])
+                ev = _record(pre)
+                for k in range(a, b):
+                    ready[k] = ev
     flags = torch.empty(len(views), dtype=torch.int32, pin_memory=True)
     plans, outs, done, flagged = [], [], [], []
     for k, (c, f, geom) in enumerate(zip(cams, frames, geoms)):
         st = lanes[k % nl]
-        if st is not main and k < nl:
-            st.wait_event(start)
-        if k >= nl:
-            st.wait_event(ready[k // nl])
+        if k in ready:
+            st.wait_event(ready[k])
         with torch.cuda.stream(st):
             cap = _capacity_hint.get((dev.index, int(c.width), int(c.height), bool(tile_cull)))
             bins = bin_sort(geom, c, tile_cull=tile_cull) if cap is None else bin_sort_nosync(geom, c, cap, tile_cull)
