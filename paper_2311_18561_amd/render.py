@@ -356,6 +356,31 @@ def _streams(dev):
     return _side_streams[key]
 
 
+def _view_plan(n_views: int, n_lanes: int):
+    """Preprocess chunks and stream waits of the multi-view forward.
+
+    Returns (bounds, waits): chunk c preprocesses views bounds[c] ..
+    bounds[c + 1] - 1, chunk 0 on the caller's stream (lane 0) and the
+    others in order on a further stream after it; view k is binned on lane
+    k mod n_lanes after waits[k]: None (lane 0, chunk 0: already ordered),
+    "start" (the caller's stream after chunk 0) or the chunk index c >= 1.
+    With more views than lanes the chunks are [0], [1, n_lanes), then
+    n_lanes views at a time, so the first view's binning starts after one
+    view's preprocess; otherwise one chunk holds every view."""
+    if n_views > n_lanes:
+        bounds = sorted(set([0, 1, *range(n_lanes, n_views, n_lanes), n_views]))
+    else:
+        bounds = [0, n_views]
+    waits = []
+    for k in range(n_views):
+        c = next(i for i in range(len(bounds) - 1) if bounds[i] <= k < bounds[i + 1])
+        if c > 0:
+            waits.append(c)
+        else:
+            waits.append(None if k % n_lanes == 0 else "start")
+    return bounds, waits
+
+
 def _record(stream):
     ev = torch.cuda.Event()
     ev.record(stream)
@@ -386,29 +411,24 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None):
     frames = [frame_struct(t, dt, mode, bg) for _, t, dt, mode, bg in views]
     geoms = [Geom(n, dev) for _ in views]  # on the caller's stream; every user is joined back into it
     nl = len(lanes)
-    # chunks [0], [1, nl), [nl, 2 nl), ... when there are more views than lanes (the first
-    # view's binning then starts after one view's preprocess), else one chunk
-    if len(views) > nl:
-        bounds = sorted(set([0, 1, *range(nl, len(views), nl), len(views)]))
-    else:
-        bounds = [0, len(views)]
+    bounds, waits = _view_plan(len(views), nl)
     preprocess_views(params, n, degree, cams[:bounds[1]], frames[:bounds[1]], geoms[:bounds[1]])
     start, ready = _record(main), {}
     if len(bounds) > 2:
         pre = side[-1]
         pre.wait_event(start)
         with torch.cuda.stream(pre):
-            for a, b in zip(bounds[1:-1], bounds[2:]):
+            for c, (a, b) in enumerate(zip(bounds[1:-1], bounds[2:]), start=1):
                 preprocess_views(params, n, degree, cams[a:b], frames[a:b], geoms[a:b])
-                ev = _record(pre)
-                for k in range(a, b):
-                    ready[k] = ev
+                ready[c] = _record(pre)
     flags = torch.empty(len(views), dtype=torch.int32, pin_memory=True)
     plans, outs, done, flagged = [], [], [], []
     for k, (c, f, geom) in enumerate(zip(cams, frames, geoms)):
         st = lanes[k % nl]
-        if k in ready:
-            st.wait_event(ready[k])
+        if waits[k] == "start":
+            st.wait_event(start)
+        elif waits[k] is not None:
+            st.wait_event(ready[waits[k]])
         with torch.cuda.stream(st):
             cap = _capacity_hint.get((dev.index, int(c.width), int(c.height), bool(tile_cull)))
             bins = bin_sort(geom, c, tile_cull=tile_cull) if cap is None else bin_sort_nosync(geom, c, cap, tile_cull)
