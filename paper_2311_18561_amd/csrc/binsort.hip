@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(kThreads) k_row_intervals(ViewSet vs, const ui
                                                             unsigned long long* tile_partials) {
   __shared__ uint32_t s_off[kRowBlock];
   __shared__ uint32_t s_g[kRowBlock];
-  __shared__ int32_t s_rect[kRowBlock][3];  // x0, x1, y0
+  __shared__ int32_t s_rect[kRowBlock][4];  // x0, x1, y0, y1
   __shared__ int32_t s_view[kRowBlock][3];  // H, GX, tile_off (32 bits)
   __shared__ ReachRows s_rr[kRowBlock];
   __shared__ int64_t s_k[2];
@@ -559,7 +559,10 @@ __global__ void __launch_bounds__(kThreads) k_row_intervals(ViewSet vs, const ui
     }
     __syncthreads();
     const int64_t k0 = s_k[0];
-    const int cnt = static_cast<int>(s_k[1] - k0 + 1);  // <= kRowBlock: every Gaussian has a row
+    // <= kRowBlock as every Gaussian has a row; the bound only matters for
+    // records that changed since k_row_count (a caller's race), as does the
+    // row check below: such input yields wrong lists, never a write out of bounds
+    const int cnt = static_cast<int>(min<int64_t>(kRowBlock, s_k[1] - k0 + 1));
     if (tid < cnt) {
       const uint32_t g = order[k0 + tid];
       float2 m;
@@ -571,6 +574,7 @@ __global__ void __launch_bounds__(kThreads) k_row_intervals(ViewSet vs, const ui
       s_rect[tid][0] = rect[0];
       s_rect[tid][1] = rect[2];
       s_rect[tid][2] = rect[1];
+      s_rect[tid][3] = rect[3];
       s_view[tid][0] = v.H;
       s_view[tid][1] = v.GX;
       s_view[tid][2] = static_cast<int32_t>(v.tile_off);
@@ -588,8 +592,8 @@ __global__ void __launch_bounds__(kThreads) k_row_intervals(ViewSet vs, const ui
       }
       const uint32_t r = ui - s_off[lo];
       const int ty = s_rect[lo][2] + static_cast<int>(r);
-      int c0, c1;
-      reach_row(s_rr[lo], ty, s_view[lo][0], s_rect[lo][0], s_rect[lo][1], c0, c1);
+      int c0 = 0, c1 = -1;
+      if (ty < s_rect[lo][3]) reach_row(s_rr[lo], ty, s_view[lo][0], s_rect[lo][0], s_rect[lo][1], c0, c1);
       len = c1 >= c0 ? static_cast<uint32_t>(c1 - c0 + 1) : 0u;
       const uint32_t tile = static_cast<uint32_t>(s_view[lo][2]) +
                             static_cast<uint32_t>(ty) * static_cast<uint32_t>(s_view[lo][1]) +
@@ -650,11 +654,12 @@ __global__ void __launch_bounds__(kThreads) k_row_emit(const uint4* __restrict__
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ counters,
-                         uint32_t* ranges) {
+                         uint32_t* ranges, int64_t ntiles) {
   const int64_t n = counters[0];
   for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
        j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const uint32_t t = keys[j];
+    if (static_cast<int64_t>(t) >= ntiles) continue;  // only records changed under a running sort get here
     if (j == 0 || keys[j - 1] != t) ranges[2 * static_cast<int64_t>(t)] = static_cast<uint32_t>(j);
     if (j == n - 1 || keys[j + 1] != t) ranges[2 * static_cast<int64_t>(t) + 1] = static_cast<uint32_t>(j + 1);
   }
@@ -831,7 +836,7 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
     PVG_HIP(launch_fill_u32(bins->ranges, 0u, 2 * plan.tiles, s));
     if (m_grid > 0) {
       hipLaunchKernelGGL(k_ranges, dim3(static_cast<unsigned>(std::min(kMaxGrid * 4, cdiv(m_grid, 256)))),
-                         dim3(256), 0, s, bins->keys, counters, bins->ranges);
+                         dim3(256), 0, s, bins->keys, counters, bins->ranges, static_cast<int64_t>(plan.tiles));
       PVG_HIP(hipGetLastError());
     }
   }

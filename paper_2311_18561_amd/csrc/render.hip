@@ -363,8 +363,12 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       const int slot = __popcll(km & lt);
       uint32_t e;
       if (kCulled) {  // the tile's rank among the Gaussian's reached tiles
-        const uint2 rw = lists.rows[lists.row_base[g] + static_cast<uint32_t>(ty)];
-        e = rw.x + static_cast<uint32_t>(tx - static_cast<int>(rw.y & 0xffffu));
+        const uint32_t ri = lists.row_base[g] + static_cast<uint32_t>(ty);
+        e = static_cast<uint32_t>(min<int64_t>(lists.capacity, 0xffffffffll));  // skipped below
+        if (static_cast<int64_t>(ri) < lists.capacity) {  // false only for lists not from these records
+          const uint2 rw = lists.rows[ri];
+          e = rw.x + static_cast<uint32_t>(tx - static_cast<int>(rw.y & 0xffffu));
+        }
       } else {
         int32_t rect[4];
         tile_rect(m.x, m.y, geom.radius[g], v.GX, v.GY, rect);
@@ -490,8 +494,11 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, List
       const float2 m = reinterpret_cast<const float2*>(geom.xy)[gi];
       int32_t rect[4];
       tile_rect(m.x, m.y, geom.radius[gi], v.GX, v.GY, rect);
-      const uint2 rw = lists.rows[lists.row_base[gi] + static_cast<uint32_t>(rect[3] - 1)];
-      cnt = rw.x + (rw.y >> 16) - e0;
+      const uint32_t ri = lists.row_base[gi] + static_cast<uint32_t>(rect[3] - 1);
+      if (static_cast<int64_t>(ri) < lists.capacity) {
+        const uint2 rw = lists.rows[ri];
+        cnt = rw.x + (rw.y >> 16) - e0;
+      }
     } else {
       cnt = geom.tiles[gi];
     }
