@@ -362,11 +362,12 @@ template <class R> struct Contrib {
 
 template <class R>
 void composite_pixel(int px, int py, const uint32_t* list, int64_t len, const Splat<float>* dec,
-                     const Splat<R>* val, const float bg[3], R out[3], R& Tfin, int& ncontrib,
+                     const Splat<R>* val, const float bg[3], R out[3], R& Tfin, R& Dout, int& ncontrib,
                      std::vector<Contrib<R>>* rec) {
   float T32 = 1.0f;
   R T = R(1);
   R C[3] = {R(0), R(0), R(0)};
+  R D = R(0);  // "flexible rendering" (Sec. 3.1): the Gaussians' camera depths blended like colour
   ncontrib = 0;
   const float fpx = static_cast<float>(px), fpy = static_cast<float>(py);
   for (int64_t k = 0; k < len; ++k) {
@@ -388,19 +389,22 @@ void composite_pixel(int px, int py, const uint32_t* list, int64_t len, const Sp
     const R alpha = clamped ? R(0.99f) : v.op * G;
     if (rec) rec->push_back({g, alpha, T, G, vdx, vdy, clamped});
     for (int c = 0; c < 3; ++c) C[c] = C[c] + v.rgb[c] * (alpha * T);
+    D = D + v.depth * (alpha * T);
     T = T * (R(1) - alpha);
     T32 = Tn;
     ncontrib = static_cast<int>(k + 1);
   }
   for (int c = 0; c < 3; ++c) out[c] = C[c] + T * R(bg[c]);
   Tfin = T;
+  Dout = D;
 }
 
 // FP32 image path specialisation: values and decisions are one array.
 void composite_pixel_f32(int px, int py, const uint32_t* list, int64_t len, const Splat<float>* sp,
-                         const float bg[3], float out[3], float& Tfin, int& ncontrib) {
+                         const float bg[3], float out[3], float& Tfin, float& Dout, int& ncontrib) {
   float T = 1.0f;
   float C[3] = {0.0f, 0.0f, 0.0f};
+  float D = 0.0f;
   ncontrib = 0;
   const float fpx = static_cast<float>(px), fpy = static_cast<float>(py);
   for (int64_t k = 0; k < len; ++k) {
@@ -413,11 +417,13 @@ void composite_pixel_f32(int px, int py, const uint32_t* list, int64_t len, cons
     const float Tn = T * (1.0f - alpha);
     if (Tn < 0.0001f) break;
     for (int c = 0; c < 3; ++c) C[c] = C[c] + d.rgb[c] * (alpha * T);
+    D = D + d.depth * (alpha * T);
     T = Tn;
     ncontrib = static_cast<int>(k + 1);
   }
   for (int c = 0; c < 3; ++c) out[c] = C[c] + T * bg[c];
   Tfin = T;
+  Dout = D;
 }
 
 Camera make_cam(const float* c, int W, int H) {
@@ -442,7 +448,8 @@ Params make_params(int64_t n, int degree, const void* const* arr) {
 
 // Rebuild FP32 splats (the decision side) from the arrays the FP32 stage wrote.
 std::vector<Splat<float>> load_splats(int64_t n, const float* xy, const float* conic_op,
-                                      const float* rgb, const int32_t* radius, const uint32_t* flags) {
+                                      const float* rgb, const int32_t* radius, const uint32_t* flags,
+                                      const float* depth = nullptr) {
   std::vector<Splat<float>> sp(n);
   for (int64_t i = 0; i < n; ++i) {
     Splat<float>& s = sp[i];
@@ -451,6 +458,7 @@ std::vector<Splat<float>> load_splats(int64_t n, const float* xy, const float* c
     s.A = conic_op[4 * i]; s.B = conic_op[4 * i + 1]; s.C = conic_op[4 * i + 2];
     s.op = conic_op[4 * i + 3];
     for (int c = 0; c < 3; ++c) s.rgb[c] = rgb ? rgb[3 * i + c] : 0.0f;
+    s.depth = depth ? depth[i] : 0.0f;
     s.flags = flags ? flags[i] : 0;
     s.radius = radius[i];
   }
@@ -458,6 +466,8 @@ std::vector<Splat<float>> load_splats(int64_t n, const float* xy, const float* c
 }
 
 struct Inst { uint32_t tile, dbits, g; };
+
+constexpr int kG2D = 10;  // per-Gaussian screen-space gradient entries of the adjoint
 
 }  // namespace
 
@@ -530,13 +540,16 @@ int64_t orc_bin_sort(int64_t n, const float* depth, const int32_t* rect, const i
 
 // O4 in FP32 over the tiles [tile_lo, tile_hi) (all tiles: 0, GX*GY).
 // img[3][H][W], final_T[H][W], n_contrib[H][W]; untouched outside those tiles.
+// depth (optional, per Gaussian) and depth_img (optional output): the blended
+// depth channel sum T alpha z of each pixel.
 void orc_render_f32(int64_t n, const float* xy, const float* conic_op, const float* rgb,
                     const int32_t* radius, const float* camv, int W, int H, const float* framev,
                     const uint32_t* ranges, const uint32_t* inst_gauss, int64_t tile_lo,
-                    int64_t tile_hi, float* img, float* final_T, int32_t* n_contrib) {
+                    int64_t tile_hi, float* img, float* final_T, int32_t* n_contrib, const float* depth,
+                    float* depth_img) {
   const Frame fr = make_frame(framev);
   (void)camv;
-  const std::vector<Splat<float>> sp = load_splats(n, xy, conic_op, rgb, radius, nullptr);
+  const std::vector<Splat<float>> sp = load_splats(n, xy, conic_op, rgb, radius, nullptr, depth);
   const int GX = (W + kTile - 1) / kTile;
   const int64_t HW = static_cast<int64_t>(H) * W;
   for (int64_t t = tile_lo; t < tile_hi; ++t) {
@@ -545,13 +558,14 @@ void orc_render_f32(int64_t n, const float* xy, const float* conic_op, const flo
     const int64_t len = static_cast<int64_t>(ranges[2 * t + 1]) - ranges[2 * t];
     for (int py = ty * kTile; py < std::min(H, (ty + 1) * kTile); ++py)
       for (int px = tx * kTile; px < std::min(W, (tx + 1) * kTile); ++px) {
-        float out[3], Tf;
+        float out[3], Tf, Df;
         int nc;
-        composite_pixel_f32(px, py, list, len, sp.data(), fr.bg, out, Tf, nc);
+        composite_pixel_f32(px, py, list, len, sp.data(), fr.bg, out, Tf, Df, nc);
         const int64_t o = static_cast<int64_t>(py) * W + px;
         for (int c = 0; c < 3; ++c) img[c * HW + o] = out[c];
         final_T[o] = Tf;
         n_contrib[o] = nc;
+        if (depth_img) depth_img[o] = Df;
       }
   }
 }
@@ -582,10 +596,10 @@ void orc_render_bruteforce_f32(int64_t n, const float* xy, const float* depth, c
       std::sort(cand.begin(), cand.end());
       list.clear();
       for (auto& c : cand) list.push_back(c.second);
-      float out[3], Tf;
+      float out[3], Tf, Df;
       int nc;
       composite_pixel_f32(px, py, list.data(), static_cast<int64_t>(list.size()), sp.data(), fr.bg, out,
-                          Tf, nc);
+                          Tf, Df, nc);
       const int64_t o = static_cast<int64_t>(py) * W + px;
       for (int c = 0; c < 3; ++c) img[c * HW + o] = out[c];
       final_T[o] = Tf;
@@ -597,12 +611,14 @@ void orc_render_bruteforce_f32(int64_t n, const float* xy, const float* depth, c
 // sorted lists, per-pair skip/clamp/stop decisions from the FP32 splats).
 // `arr` holds double* parameter arrays.  Returns sum over the rendered pixels
 // of w[c][y][x] * img[c][y][x] (w may be null: returns 0); writes img/final_T
-// if non-null.  tile_mask (GX*GY bytes) selects tiles; null = all.
+// if non-null.  tile_mask (GX*GY bytes) selects tiles; null = all.  wD and wT
+// (optional, [H][W]) add sum wD * depth + sum wT * final_T to the returned
+// value; depth_img (optional) receives the blended depth channel.
 double orc_render_f64(int64_t n, int degree, const void* const* arr, const float* camv, int W, int H,
                       const float* framev, const float* xy32, const float* conic_op32,
                       const int32_t* radius32, const uint32_t* flags32, const uint32_t* ranges,
                       const uint32_t* inst_gauss, const uint8_t* tile_mask, const double* w,
-                      double* img, double* final_T) {
+                      double* img, double* final_T, const double* wD, const double* wT, double* depth_img) {
   const Params prm = make_params(n, degree, arr);
   const Camera cam = make_cam(camv, W, H);
   const Frame fr = make_frame(framev);
@@ -623,30 +639,34 @@ double orc_render_f64(int64_t n, int degree, const void* const* arr, const float
     const int64_t len = static_cast<int64_t>(ranges[2 * t + 1]) - ranges[2 * t];
     for (int py = ty * kTile; py < std::min(H, (ty + 1) * kTile); ++py)
       for (int px = tx * kTile; px < std::min(W, (tx + 1) * kTile); ++px) {
-        double out[3], Tf;
+        double out[3], Tf, Df;
         int nc;
-        composite_pixel<double>(px, py, list, len, dec.data(), val.data(), fr.bg, out, Tf, nc, nullptr);
+        composite_pixel<double>(px, py, list, len, dec.data(), val.data(), fr.bg, out, Tf, Df, nc, nullptr);
         const int64_t o = static_cast<int64_t>(py) * W + px;
         for (int c = 0; c < 3; ++c) {
           if (img) img[c * HW + o] = out[c];
           if (w) L += w[c * HW + o] * out[c];
         }
         if (final_T) final_T[o] = Tf;
+        if (depth_img) depth_img[o] = Df;
+        if (wD) L += wD[o] * Df;
+        if (wT) L += wT[o] * Tf;
       }
   }
   return L;
 }
 
 // FP64 adjoint (O6, O7) of the image of orc_render_f64 for the upstream
-// gradient dimg[3][H][W].  Writes the gradient of every parameter array into
-// `garr` (9 double* in parameter layout, overwritten) and, if non-null, the
-// per-Gaussian screen-space gradient g2d[n][9] = (d x, d y, d A, d B, d C,
-// d o~, d r, d g, d b).
+// gradient dimg[3][H][W], plus (optional, [H][W]) dD for the blended depth
+// channel and dT for final_T (the rendered opacity is 1 - final_T).  Writes
+// the gradient of every parameter array into `garr` (9 double* in parameter
+// layout, overwritten) and, if non-null, the per-Gaussian screen-space
+// gradient g2d[n][10] = (d x, d y, d A, d B, d C, d o~, d r, d g, d b, d z).
 void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float* camv, int W, int H,
                       const float* framev, const float* xy32, const float* conic_op32,
                       const int32_t* radius32, const uint32_t* flags32, const uint32_t* ranges,
                       const uint32_t* inst_gauss, const double* dimg, void* const* garr, double* g2d_out,
-                      const uint8_t* tile_mask) {
+                      const uint8_t* tile_mask, const double* dD, const double* dT) {
   const Params prm = make_params(n, degree, arr);
   const Camera cam = make_cam(camv, W, H);
   const Frame fr = make_frame(framev);
@@ -660,7 +680,7 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
   }
   const int GX = (W + kTile - 1) / kTile, GY = (H + kTile - 1) / kTile;
   const int64_t HW = static_cast<int64_t>(H) * W;
-  std::vector<double> g2d(static_cast<size_t>(n) * 9, 0.0);
+  std::vector<double> g2d(static_cast<size_t>(n) * kG2D, 0.0);
   std::vector<Contrib<double>> rec;
 
   // O6: per pixel, the derivative of Eq. (3) with respect to each
@@ -674,23 +694,30 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
     for (int py = ty * kTile; py < std::min(H, (ty + 1) * kTile); ++py)
       for (int px = tx * kTile; px < std::min(W, (tx + 1) * kTile); ++px) {
         rec.clear();
-        double out[3], Tf;
+        double out[3], Tf, Df;
         int nc;
-        composite_pixel<double>(px, py, list, len, dec.data(), val.data(), fr.bg, out, Tf, nc, &rec);
+        composite_pixel<double>(px, py, list, len, dec.data(), val.data(), fr.bg, out, Tf, Df, nc, &rec);
         const int64_t o = static_cast<int64_t>(py) * W + px;
         const double g[3] = {dimg[o], dimg[HW + o], dimg[2 * HW + o]};
-        // S = colour accumulated behind the current contributor, incl. background
+        const double gD = dD ? dD[o] : 0.0, gT = dT ? dT[o] : 0.0;
+        // S = colour accumulated behind the current contributor, incl. background;
+        // SD the same for depth (no background term); final_T = prod (1 - alpha)
         double S[3] = {Tf * fr.bg[0], Tf * fr.bg[1], Tf * fr.bg[2]};
+        double SD = 0.0;
         for (int64_t k = static_cast<int64_t>(rec.size()) - 1; k >= 0; --k) {
           const Contrib<double>& c = rec[k];
           const Splat<double>& v = val[c.g];
-          double* gg = &g2d[9 * static_cast<size_t>(c.g)];
+          double* gg = &g2d[kG2D * static_cast<size_t>(c.g)];
           double dalpha = 0.0;
           for (int ch = 0; ch < 3; ++ch) {
             gg[6 + ch] += c.T * c.alpha * g[ch];
             dalpha += g[ch] * (c.T * v.rgb[ch] - S[ch] / (1.0 - c.alpha));
           }
+          gg[9] += c.T * c.alpha * gD;
+          dalpha += gD * (c.T * v.depth - SD / (1.0 - c.alpha));
+          dalpha += gT * (-Tf / (1.0 - c.alpha));
           for (int ch = 0; ch < 3; ++ch) S[ch] += c.T * c.alpha * v.rgb[ch];
+          SD += c.T * c.alpha * v.depth;
           if (c.clamped) continue;
           gg[5] += c.G * dalpha;
           const double gp = c.alpha * dalpha;  // d alpha / d power = alpha
@@ -728,7 +755,7 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
     if (!val[i].visible) continue;
     const Inter<double>& it = inter[i];
     const Splat<double>& v = val[i];
-    const double* gg = &g2d[9 * static_cast<size_t>(i)];
+    const double* gg = &g2d[kG2D * static_cast<size_t>(i)];
     double dmur[3] = {0, 0, 0};
 
     // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2)
@@ -792,6 +819,8 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
       dp[1] += -fy / (pz * pz) * dJ12;
       dp[2] += 2.0 * fy * py / (pz * pz * pz) * dJ12;
     }
+    // the depth channel's z is the camera-space pz
+    dp[2] += gg[9];
     // 2D mean m = (fx px/pz + cx - 1/2, fy py/pz + cy - 1/2)
     dp[0] += fx / pz * gg[0];
     dp[1] += fy / pz * gg[1];

@@ -404,14 +404,16 @@ def test_instances_sorted_by_tile_depth_index(orc):
 
 
 # ---------------------------------------------------------------- P8 gradients
-def _fd_check(orc, sc, cam, t, dt, mode, bg, fields=None, sample=None, seed=0, tol=1e-6):
+def _fd_check(orc, sc, cam, t, dt, mode, bg, fields=None, sample=None, seed=0, tol=1e-6, channels=False):
     pre = orc.preprocess_f32(sc, cam, t, dt, mode, bg)
     bins = orc.bin_sort(pre, cam)
     s64 = orc.scene64(sc)
     W, H = cam["width"], cam["height"]
     rng = np.random.default_rng(seed)
     w = rng.standard_normal((3, H, W))
-    grads, _ = orc.backward_f64(s64, cam, t, dt, mode, bg, pre, bins, w)
+    wD = rng.standard_normal((H, W)) * 0.1 if channels else None  # depths are O(10): keep the terms comparable
+    wT = rng.standard_normal((H, W)) if channels else None
+    grads, _ = orc.backward_f64(s64, cam, t, dt, mode, bg, pre, bins, w, dD=wD, dT=wT)
     GX, GY = orc.grid(cam)
     vis = np.nonzero(pre["radius"] > 0)[0]
     assert vis.size > 0
@@ -433,7 +435,7 @@ def _fd_check(orc, sc, cam, t, dt, mode, bg, fields=None, sample=None, seed=0, t
             for k in (-2, -1, 1, 2):
                 arr[r, i] = old + k * h
                 L[k] = orc.render_f64(s64, cam, t, dt, mode, bg, pre, bins, tile_mask=tm.reshape(-1), w=w,
-                                      want_img=False)[0]
+                                      want_img=False, wD=wD, wT=wT)[0]
             arr[r, i] = old
             fd = (8 * (L[1] - L[-1]) - (L[2] - L[-2])) / (12 * h)
             err = abs(fd - g[r, i]) / max(abs(g[r, i]), 1e-2 * rms)
@@ -452,6 +454,65 @@ def test_adjoint_matches_finite_differences_tiny(orc, dt, mode):
     cam = gen.yaw_camera(64, 48, 10.0, (0.2, 0.1, -0.5))
     n = _fd_check(orc, sc, cam, 0.45, dt, mode, (0.1, 0.2, 0.3))
     assert n > 500
+
+
+@pytest.mark.parametrize("dt,mode", [(0.0, 0), (0.05, 0)])
+def test_channel_adjoint_matches_finite_differences_tiny(orc, dt, mode):
+    """Flexible rendering (Sec. 3.1): the blended depth channel sum T alpha z
+    and the final transmittance (the rendered opacity O is 1 - final_T) enter
+    the loss with their own upstream gradients; finite differences of that
+    loss against the FP64 adjoint for every parameter of every visible
+    Gaussian (z moves with the mean, the flow offset and the time terms)."""
+    sc = gen.make_scene(30, 7, sh_degree=3)
+    cam = gen.yaw_camera(64, 48, 10.0, (0.2, 0.1, -0.5))
+    n = _fd_check(orc, sc, cam, 0.45, dt, mode, (0.1, 0.2, 0.3), channels=True)
+    assert n > 500
+
+
+def test_depth_channel_closed_form(orc):
+    """With every Gaussian at one camera depth z0 the blended depth is
+    z0 * sum T alpha = z0 * (1 - final_T) at every pixel (FP64 to rounding,
+    the FP32 image path to a few ulps), and a pixel no Gaussian reaches has
+    depth 0 and final_T 1."""
+    cfg = gen.make_config(0)
+    sc = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in cfg["scene"].items()}
+    cam = cfg["cameras"][0]
+    assert np.allclose(np.asarray(cam["R"], np.float64).reshape(3, 3), np.eye(3)) and not np.any(cam["T"])
+    z0 = 6.5
+    sc["mu"][2] = z0
+    sc["vel"][2] = 0.0  # the vibration leaves z unchanged
+    pre = orc.preprocess_f32(sc, cam, cfg["t"])
+    assert np.all(pre["depth"][pre["radius"] > 0] == np.float32(z0))
+    bins = orc.bin_sort(pre, cam)
+    img, T, nc, D = orc.render_f32(pre, bins, cam, cfg["t"], want_depth=True)
+    np.testing.assert_allclose(D, z0 * (1.0 - T.astype(np.float64)), rtol=1e-5, atol=1e-5)
+    empty = nc == 0
+    assert np.all(D[empty] == 0.0) and np.all(T[empty] == 1.0)
+    _, _, T64, D64 = orc.render_f64(orc.scene64(sc), cam, cfg["t"], 0.0, 0, (0, 0, 0), pre, bins, want_depth=True)
+    np.testing.assert_allclose(D64, z0 * (1.0 - T64), rtol=1e-12, atol=1e-12)
+
+
+def test_channel_adjoint_linear(orc):
+    """The adjoint of image, depth and final_T gradients together is the sum
+    of the three adjoints taken one at a time."""
+    cfg = gen.make_config(0)
+    cam = cfg["cameras"][0]
+    sc, t = cfg["scene"], cfg["t"]
+    pre = orc.preprocess_f32(sc, cam, t, 0.05)
+    bins = orc.bin_sort(pre, cam)
+    s64 = orc.scene64(sc)
+    H, W = cam["height"], cam["width"]
+    rng = np.random.default_rng(5)
+    w, wD, wT = rng.standard_normal((3, H, W)), rng.standard_normal((H, W)), rng.standard_normal((H, W))
+    zero = np.zeros((3, H, W))
+    g_all, g2_all = orc.backward_f64(s64, cam, t, 0.05, 0, (0, 0, 0), pre, bins, w, dD=wD, dT=wT)
+    parts = [orc.backward_f64(s64, cam, t, 0.05, 0, (0, 0, 0), pre, bins, w),
+             orc.backward_f64(s64, cam, t, 0.05, 0, (0, 0, 0), pre, bins, zero, dD=wD),
+             orc.backward_f64(s64, cam, t, 0.05, 0, (0, 0, 0), pre, bins, zero, dT=wT)]
+    for f in orc.FIELDS:
+        tot = sum(p[0][f] for p in parts)
+        np.testing.assert_allclose(g_all[f], tot, rtol=1e-9, atol=1e-12 * (1 + np.abs(tot).max()))
+    assert np.any(parts[1][1][:, 9] != 0) and not np.any(parts[2][1][:, 9])  # only the depth term reaches d z
 
 
 def test_adjoint_matches_finite_differences_config1_subset(orc):
