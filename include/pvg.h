@@ -193,6 +193,29 @@ int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera*
                    const pvg_frame* frame, float* img, float* final_T, int32_t* n_contrib,
                    void* stream);
 
+/* Extra render channels of the flexible rendering in Sec. 3.1, where a
+ * Gaussian's camera depth z takes the place of its colour in Eq. (3).  Every
+ * pointer is optional (NULL: not rendered / no gradient), device memory of
+ * [height][width] floats, owned by the caller:
+ *   depth      forward output: sum over contributors of T_i alpha_i z_i (the
+ *              normalized depth of the paper is depth / (1 - final_T));
+ *   dL_ddepth  adjoint input: upstream gradient of `depth`;
+ *   dL_dT      adjoint input: upstream gradient of final_T (the rendered
+ *              opacity O = sum T_i alpha_i is 1 - final_T, so dL/dO enters as
+ *              dL_dT = -dL/dO). */
+typedef struct pvg_channels {
+  float* depth;
+  const float* dL_ddepth;
+  const float* dL_dT;
+} pvg_channels;
+
+/* pvg_render_fwd that also writes the channels requested in `channels`
+ * (NULL: exactly pvg_render_fwd).  Images, final_T and n_contrib are those
+ * of pvg_render_fwd bit for bit. */
+int pvg_render_fwd_channels(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera* cam,
+                            const pvg_frame* frame, float* img, float* final_T, int32_t* n_contrib,
+                            const pvg_channels* channels, void* stream);
+
 /* Adjoint of pvg_render_fwd and pvg_preprocess: given dL/dimg [3][H][W] and
  * the forward's final_T and n_contrib, writes (accumulate = 0) or adds
  * (accumulate = 1) dL/d(every array of g) into grad.  geom and bins must be
@@ -225,6 +248,20 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
                          const float* const* final_T, const int32_t* const* n_contrib,
                          const float* const* dL_dimg, pvg_gaussians_grad* grad, int32_t accumulate,
                          void* tmp, size_t tmp_bytes, void* stream);
+/* pvg_render_bwd_views with the channels' upstream gradients: `channels`
+ * (host array of n_views entries, or NULL: exactly pvg_render_bwd_views)
+ * gives view k's dL_ddepth and dL_dT (either may be NULL; `depth` is
+ * ignored).  The gradient of the depth channel reaches the mean, the flow
+ * offset and the temporal parameters through z; that of final_T reaches
+ * every parameter alpha depends on.  A view whose dL_dimg is NULL is skipped
+ * with its channel gradients (pass zeros to use only the channels).  Same
+ * scratch (pvg_bwd_views_tmp_bytes), streams and errors. */
+int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const pvg_camera* cams,
+                                  const pvg_frame* frames, const pvg_geom* geoms, const pvg_bins* bins,
+                                  const float* const* final_T, const int32_t* const* n_contrib,
+                                  const float* const* dL_dimg, const pvg_channels* channels,
+                                  pvg_gaussians_grad* grad, int32_t accumulate, void* tmp,
+                                  size_t tmp_bytes, void* stream);
 /* Scratch bytes of pvg_render_bwd_views.  Host only. */
 int pvg_bwd_views_tmp_bytes(int64_t n, int32_t n_views, int32_t max_width, int32_t max_height,
                             int64_t max_capacity, size_t* bytes);

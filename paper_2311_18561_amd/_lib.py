@@ -47,6 +47,10 @@ class Frame(C.Structure):
     _fields_ = [("t", C.c_float), ("dt", C.c_float), ("advect_mode", C.c_int32), ("bg", C.c_float * 3)]
 
 
+class Channels(C.Structure):
+    _fields_ = [("depth", C.c_void_p), ("dL_ddepth", C.c_void_p), ("dL_dT", C.c_void_p)]
+
+
 class Geom(C.Structure):
     _fields_ = [("n", C.c_int64), ("xy", vp), ("depth", vp), ("conic_op", vp), ("rgb", vp), ("radius", vp),
                 ("tiles", vp)]
@@ -111,6 +115,9 @@ def load():
         "pvg_preprocess_views": ([P(Gaussians), i32, P(Camera), P(Frame), P(Geom), vp], i32),
         "pvg_bin_sort": ([P(Geom), P(Camera), P(Bins), vp, C.c_size_t, i32, vp], i32),
         "pvg_render_fwd": ([P(Geom), P(Bins), P(Camera), P(Frame), vp, vp, vp, vp], i32),
+        "pvg_render_fwd_channels": ([P(Geom), P(Bins), P(Camera), P(Frame), vp, vp, vp, P(Channels), vp], i32),
+        "pvg_render_bwd_views_channels": ([P(Gaussians), i32, P(Camera), P(Frame), P(Geom), P(Bins), P(vp), P(vp),
+                                           P(vp), P(Channels), P(GaussiansGrad), i32, vp, C.c_size_t, vp], i32),
         "pvg_render_bwd": ([P(Gaussians), P(Camera), P(Frame), P(Geom), P(Bins), vp, vp, vp, P(GaussiansGrad),
                             i32, vp, C.c_size_t, vp], i32),
         "pvg_render_bwd_views": ([P(Gaussians), i32, P(Camera), P(Frame), P(Geom), P(Bins), P(vp), P(vp), P(vp),

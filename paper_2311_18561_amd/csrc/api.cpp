@@ -174,7 +174,7 @@ size_t bwd_scratch_bytes(int64_t n, int32_t views, int32_t regions, int64_t capa
   auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
   const size_t slot = al(sizeof(float) * kG2DStride * static_cast<size_t>(std::max<int64_t>(n, 1)));
   const size_t g2d = slot * static_cast<size_t>(std::max(views, 1));
-  const size_t rec = al(sizeof(float) * 9 * static_cast<size_t>(std::max<int64_t>(capacity, 1)));
+  const size_t rec = al(sizeof(float) * kRecFloats * static_cast<size_t>(std::max<int64_t>(capacity, 1)));
   // one flag byte per instance, padded so 16-byte reads past the last one stay inside
   const size_t vis = al((static_cast<size_t>(std::max<int64_t>(capacity, 1)) + 31) & ~static_cast<size_t>(15));
   if (off_rec) *off_rec = g2d;
@@ -292,6 +292,12 @@ int pvg_bin_sort(const pvg_geom* geom, const pvg_camera* cam, pvg_bins* bins, vo
 
 int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera* cam, const pvg_frame* frame,
                    float* img, float* final_T, int32_t* n_contrib, void* stream) {
+  return pvg_render_fwd_channels(geom, bins, cam, frame, img, final_T, n_contrib, nullptr, stream);
+}
+
+int pvg_render_fwd_channels(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera* cam,
+                            const pvg_frame* frame, float* img, float* final_T, int32_t* n_contrib,
+                            const pvg_channels* channels, void* stream) {
   if (!geom || !check_geom(geom, geom->n) || !check_bins(bins) || !check_camera(cam) || !check_frame(frame))
     return PVG_ERR_INVALID;
   if (!img || !final_T || !n_contrib) { set_error("an output array is null"); return PVG_ERR_INVALID; }
@@ -299,6 +305,7 @@ int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera*
   v.img = img;
   v.final_T = final_T;
   v.n_contrib = n_contrib;
+  if (channels) v.depth_img = channels->depth;
   PVG_HIP(launch_render_fwd(single(v, geom->n), to_geom(geom), bins->vals, bins->ranges, bins->tile_cull != 0,
                             static_cast<hipStream_t>(stream)));
   return PVG_OK;
@@ -330,6 +337,16 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
                          const pvg_geom* geoms, const pvg_bins* bins, const float* const* final_T,
                          const int32_t* const* n_contrib, const float* const* dL_dimg, pvg_gaussians_grad* grad,
                          int32_t accumulate, void* tmp, size_t tmp_bytes, void* stream) {
+  return pvg_render_bwd_views_channels(g, n_views, cams, frames, geoms, bins, final_T, n_contrib, dL_dimg, nullptr,
+                                       grad, accumulate, tmp, tmp_bytes, stream);
+}
+
+int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const pvg_camera* cams,
+                                  const pvg_frame* frames, const pvg_geom* geoms, const pvg_bins* bins,
+                                  const float* const* final_T, const int32_t* const* n_contrib,
+                                  const float* const* dL_dimg, const pvg_channels* channels,
+                                  pvg_gaussians_grad* grad, int32_t accumulate, void* tmp, size_t tmp_bytes,
+                                  void* stream) {
   if (!check_gaussians(g)) return PVG_ERR_INVALID;
   if (n_views < 1 || !cams || !frames || !geoms || !bins || !final_T || !n_contrib || !dL_dimg) {
     set_error("n_views < 1 or a per-view array is null");
@@ -434,6 +451,10 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
     v.final_T = const_cast<float*>(final_T[k]);
     v.n_contrib = const_cast<int32_t*>(n_contrib[k]);
     v.dL_dimg = dL_dimg[k];
+    if (channels) {
+      v.dL_ddepth = channels[k].dL_ddepth;
+      v.dL_dT = channels[k].dL_dT;
+    }
     float* g2d = reinterpret_cast<float*>(base + slot_bytes * static_cast<size_t>(used_slots));
     ++used_slots;
     const int32_t r = launched % regions;

@@ -65,7 +65,7 @@ struct GeoGrad {
 
 // One view's chain rule for everything but dL/dsh, added into acc.  g is the
 // view's screen-space gradient of the Gaussian: d(mean x, y), d(conic A, B, C),
-// d(opacity), d(rgb); on return g[6..8] holds d(rgb) with clamped channels
+// d(opacity), d(rgb), d(depth); on return g[6..8] holds d(rgb) with clamped channels
 // zeroed and g[9..11] the view direction, which is all dL/dsh needs.  rgb is
 // the forward's colour of the Gaussian, where a clamped channel is -0.
 __device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const Proj& P, const float* rgb, float* g,
@@ -74,6 +74,7 @@ __device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const
   const int64_t n = s.n;
   const int K = (s.degree + 1) * (s.degree + 1);
   const float dmx = g[0], dmy = g[1], dA = g[2], dB = g[3], dC = g[4], dop = g[5];
+  const float dz = g[9];  // the blended depth channel's gradient (0 without it), read before slot 9 is reused
   float dmr[3] = {0.0f, 0.0f, 0.0f};
 
   // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2), dir = u / |u|; its
@@ -149,6 +150,7 @@ __device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const
     dp[1] += -v.fy * iz2 * dJ12;
     dp[2] += 2.0f * v.fy * py * iz2 * iz * dJ12;
   }
+  dp[2] += dz;  // the depth channel blends the camera-space z
   dp[0] += v.fx * iz * dmx;
   dp[1] += v.fy * iz * dmy;
   dp[2] += -v.fx * px * iz2 * dmx - v.fy * py * iz2 * dmy;

@@ -19,6 +19,7 @@ constexpr float kGuard = 1.3f;           // Jacobian guard band, in half fields 
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 0.0001f;
+constexpr int kRecFloats = 10;  // floats per adjoint record slot: 9 screen-space sums + d depth
 constexpr int kG2DStride = 12;           // floats per Gaussian in the screen-space gradient buffer
 
 // Parameters of one scene (device pointers).
@@ -44,6 +45,12 @@ struct View {
   float* final_T;    // [H][W]
   int32_t* n_contrib;// [H][W]
   const float* dL_dimg;  // [3][H][W] upstream gradient (adjoint only)
+  // flexible rendering channels (Sec. 3.1), each optional: the blended camera
+  // depth sum T alpha z (forward output) and the upstream gradients of it and
+  // of final_T (adjoint inputs; the rendered opacity is 1 - final_T)
+  float* depth_img;          // [H][W]
+  const float* dL_ddepth;    // [H][W]
+  const float* dL_dT;        // [H][W]
 };
 
 struct Geom {

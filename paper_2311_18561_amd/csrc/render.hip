@@ -36,12 +36,12 @@ __device__ __forceinline__ float wave_sum(float x) {
   return x;
 }
 
-// Sums nine per-lane values over the wave by halving: a half-wave swap adds
+// Sums ten per-lane values over the wave by halving: a half-wave swap adds
 // two values at once (lanes 0-31 keep the sums of the even-indexed values,
 // 32-63 of the odd ones), a row swap does the same between the two 16-lane
 // rows of each half, and DPP folds the last three values within each row.
 // Afterwards every lane of row r (lanes 16r .. 16r+15) holds, in out[k], the
-// wave total of value 4k + 2(r & 1) + (r >> 1) (indices >= 9 are padding).
+// wave total of value 4k + 2(r & 1) + (r >> 1) (indices >= 10 are padding).
 __device__ __forceinline__ float swap_sum32(float x, float y) {
   const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
@@ -58,11 +58,10 @@ __device__ __forceinline__ float dpp_add(float x, int ctrl) {
     default: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xb1, 0xf, 0xf, false));
   }
 }
-__device__ __forceinline__ void wave_sum9(const float a[9], float out[3]) {
+__device__ __forceinline__ void wave_sum10(const float a[10], float out[3]) {
   float h[5];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) h[m] = swap_sum32(a[2 * m], a[2 * m + 1]);
-  h[4] = swap_sum32(a[8], 0.0f);
+  for (int m = 0; m < 5; ++m) h[m] = swap_sum32(a[2 * m], a[2 * m + 1]);
   out[0] = swap_sum16(h[0], h[1]);
   out[1] = swap_sum16(h[2], h[3]);
   out[2] = swap_sum16(h[4], 0.0f);
@@ -109,13 +108,16 @@ __device__ __forceinline__ float pair_power(float dx, float dy, float A, float B
 
 constexpr int kPix = 4;  // pixels per lane
 
-template <bool kCount, bool kCulled>
+// kDepth: also blend each Gaussian's camera depth into v.depth_img (the
+// flexible rendering of Sec. 3.1, with the depth in place of the colour).
+template <bool kCount, bool kCulled, bool kDepth>
 __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const uint32_t* __restrict__ vals,
                                                    const uint32_t* __restrict__ ranges,
                                                    unsigned long long* pair_counter) {
   __shared__ float2 s_xy[64];
   __shared__ float4 s_co[64];
   __shared__ float4 s_rgb[64];  // rgb and the list position (as int bits)
+  __shared__ float s_z[kDepth ? 64 : 1];
   const int64_t ntiles = live_tiles(vs);
   const int64_t tile = xcd_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
@@ -129,12 +131,12 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
   float X0, X1, Y0, Y1;
   tile_bounds(tx, ty, v.W, v.H, X0, X1, Y0, Y1);
   const uint64_t lt = (1ull << lane) - 1ull;
-  float T[kPix], Cr[kPix], Cg[kPix], Cb[kPix];
+  float T[kPix], Cr[kPix], Cg[kPix], Cb[kPix], Dz[kPix];
   int last[kPix];
   bool act[kPix];
 #pragma unroll
   for (int k = 0; k < kPix; ++k) {
-    T[k] = 1.0f; Cr[k] = 0.0f; Cg[k] = 0.0f; Cb[k] = 0.0f; last[k] = 0;
+    T[k] = 1.0f; Cr[k] = 0.0f; Cg[k] = 0.0f; Cb[k] = 0.0f; Dz[k] = 0.0f; last[k] = 0;
     act[k] = px < v.W && py0 + 4 * k < v.H;
   }
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
@@ -145,12 +147,14 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
     bool keep = false;
     float2 m;
     float4 co, c;
+    float z = 0.0f;
     if (idx < end) {
       const uint32_t g = vals[idx];
       m = reinterpret_cast<const float2*>(geom.xy)[g];
       co = reinterpret_cast<const float4*>(geom.conic_op)[g];
       c = make_float4(geom.rgb[3 * g], geom.rgb[3 * g + 1], geom.rgb[3 * g + 2],
                       __int_as_float(static_cast<int>(idx - start) + 1));
+      if (kDepth) z = geom.depth[g];
       keep = kCulled || tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1);
     }
     const uint64_t km = __ballot(keep);
@@ -159,6 +163,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
       s_xy[slot] = m;
       s_co[slot] = co;
       s_rgb[slot] = c;
+      if (kDepth) s_z[slot] = z;
     }
     __syncthreads();
     const int cnt = __popcll(km);
@@ -167,6 +172,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
       const float2 gm = s_xy[j];
       const float4 gc = s_co[j];
       const float4 cc = s_rgb[j];
+      const float gz = kDepth ? s_z[j] : 0.0f;
       const int pos = __float_as_int(cc.w);
 #pragma unroll
       for (int k = 0; k < kPix; ++k) {
@@ -182,6 +188,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
         Cr[k] = fmaf(cc.x, w, Cr[k]);
         Cg[k] = fmaf(cc.y, w, Cg[k]);
         Cb[k] = fmaf(cc.z, w, Cb[k]);
+        if (kDepth) Dz[k] = fmaf(gz, w, Dz[k]);
         T[k] = use ? Tn : T[k];
         last[k] = use ? pos : last[k];
         act[k] = act[k] && !stop;
@@ -200,6 +207,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
       v.img[2 * HW + o] = Cb[k] + T[k] * v.bg[2];
       v.final_T[o] = T[k];
       v.n_contrib[o] = last[k];
+      if (kDepth) v.depth_img[o] = Dz[k];
     }
   }
   if (kCount && pair_counter) {
@@ -210,7 +218,9 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
   }
 }
 
-template <bool kCount, bool kCulled>
+// kCh: the view also carries upstream gradients of the depth channel and/or
+// of final_T (either may be null); records then hold a tenth sum, d depth.
+template <bool kCount, bool kCulled, bool kCh>
 __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists lists, float* rec,
                                                    uint8_t* vis, unsigned long long* pair_counter) {
   // The gradient arithmetic may fuse multiply-adds.  Every branch decision
@@ -224,8 +234,10 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
   __shared__ float4 s_co[64];
   __shared__ float4 s_rgb[64];  // rgb and the 0-based list position (as int bits)
   __shared__ uint32_t s_g[64];
-  __shared__ float s_acc[64][9];
+  __shared__ float s_acc[64][kRecFloats];
+  __shared__ float s_z[kCh ? 64 : 1];
   __shared__ int s_any[64];
+  constexpr int kSums = kCh ? 10 : 9;
   const int64_t ntiles = live_tiles(vs);
   const int64_t tile = xcd_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
@@ -240,12 +252,14 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
   tile_bounds(tx, ty, v.W, v.H, X0, X1, Y0, Y1);
   const uint64_t lt = (1ull << lane) - 1ull;
   const int64_t HW = static_cast<int64_t>(v.W) * v.H;
-  float T[kPix], rr[kPix], gr[kPix], gg[kPix], gb[kPix];
+  float T[kPix], rr[kPix], gr[kPix], gg[kPix], gb[kPix], gd[kPix];
   int last[kPix];
   int lmax = 0;
 #pragma unroll
   for (int k = 0; k < kPix; ++k) {
     const int py = py0 + 4 * k;
+    float gt = 0.0f;
+    gd[k] = 0.0f;
     if (px < v.W && py < v.H) {
       const int64_t o = static_cast<int64_t>(py) * v.W + px;
       T[k] = v.final_T[o];
@@ -253,10 +267,16 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       gr[k] = v.dL_dimg[o];
       gg[k] = v.dL_dimg[HW + o];
       gb[k] = v.dL_dimg[2 * HW + o];
+      if (kCh) {
+        if (v.dL_ddepth) gd[k] = v.dL_ddepth[o];
+        if (v.dL_dT) gt = v.dL_dT[o];
+      }
     } else {
       T[k] = 1.0f; last[k] = 0; gr[k] = 0.0f; gg[k] = 0.0f; gb[k] = 0.0f;
     }
-    rr[k] = v.bg[0] * gr[k] + v.bg[1] * gg[k] + v.bg[2] * gb[k];
+    // the blend behind the last contributor: the background colour, and for
+    // final_T a channel that is 0 on every Gaussian and 1 behind them all
+    rr[k] = v.bg[0] * gr[k] + v.bg[1] * gg[k] + v.bg[2] * gb[k] + gt;
     lmax = max(lmax, last[k]);
   }
   lmax = wave_max(lmax);
@@ -269,11 +289,13 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
     uint32_t g = 0;
     float2 m;
     float4 co, c;
+    float z = 0.0f;
     if (lane < hi - lo) {
       g = vals[start + lo + lane];
       m = reinterpret_cast<const float2*>(geom.xy)[g];
       co = reinterpret_cast<const float4*>(geom.conic_op)[g];
       c = make_float4(geom.rgb[3 * g], geom.rgb[3 * g + 1], geom.rgb[3 * g + 2], __int_as_float(lo + lane));
+      if (kCh) z = geom.depth[g];
       keep = kCulled || tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1);
     }
     const uint64_t km = __ballot(keep);
@@ -283,6 +305,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       s_xy[slot] = m;
       s_co[slot] = co;
       s_rgb[slot] = c;
+      if (kCh) s_z[slot] = z;
     }
     __syncthreads();
     const int cnt = __popcll(km);
@@ -290,6 +313,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       const float2 gm = s_xy[j];
       const float4 gc = s_co[j];
       const float4 cc = s_rgb[j];
+      const float gz = kCh ? s_z[j] : 0.0f;
       const int pos = __float_as_int(cc.w);
       // The lane's four pixels share the column offset dx.  Per pixel the
       // power gradient is gp = alpha dL/dalpha (zero where the pair is unused
@@ -298,7 +322,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       // An unused pair takes alpha = 0, which leaves T (rcp(1) is exact)
       // and the colour behind it unchanged, so no selects are needed.
       const float dx = gm.x - fpx;
-      float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, cr = 0.0f, cgr = 0.0f, cb = 0.0f;
+      float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, cr = 0.0f, cgr = 0.0f, cb = 0.0f, cz = 0.0f;
       bool any = false;
 #pragma unroll
       for (int k = 0; k < kPix; ++k) {
@@ -313,12 +337,14 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
         const float au = ok ? alpha : 0.0f;
         const float om = 1.0f - au;
         T[k] *= __builtin_amdgcn_rcpf(om);
-        const float cg = cc.x * gr[k] + cc.y * gg[k] + cc.z * gb[k];
+        float cg = cc.x * gr[k] + cc.y * gg[k] + cc.z * gb[k];
+        if (kCh) cg = fmaf(gz, gd[k], cg);  // the depth channel blends like a colour
         const float dal = T[k] * (cg - rr[k]);
         const float w = au * T[k];
         cr = fmaf(w, gr[k], cr);
         cgr = fmaf(w, gg[k], cgr);
         cb = fmaf(w, gb[k], cb);
+        if (kCh) cz = fmaf(w, gd[k], cz);
         rr[k] = fmaf(au, cg, om * rr[k]);
         const float gp = (raw > kAlphaMax ? 0.0f : au) * dal;
         s0 += gp;
@@ -328,7 +354,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       // power = -(A dx^2 + C dy^2)/2 - B dx dy and d(mean) = d(dx, dy); the
       // exponential's own gradient, sum G dL/dalpha over unclamped pairs, is
       // s0 / o (there alpha = o G)
-      float a[9];
+      float a[10];
       {
         const float sx = dx * s0;
         a[0] = -(gc.x * sx + gc.y * s1);
@@ -340,17 +366,18 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
         a[6] = cr;
         a[7] = cgr;
         a[8] = cb;
+        a[9] = cz;  // 0 without the depth channel
       }
       const bool wany = __any(any);
       if (wany) {
         float red[3];
-        wave_sum9(a, red);
+        wave_sum10(a, red);
         if ((lane & 15) == 0) {
           const int r = lane >> 4;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
             const int q = 4 * k + 2 * (r & 1) + (r >> 1);
-            if (q < 9) s_acc[j][q] = red[k];
+            if (q < kSums) s_acc[j][q] = red[k];
           }
         }
       }
@@ -375,9 +402,9 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
         e = first[g] + static_cast<uint32_t>((ty - rect[1]) * (rect[2] - rect[0]) + (tx - rect[0]));
       }
       if (static_cast<int64_t>(e) < lists.capacity) {
-        float* dst = rec + 9 * static_cast<int64_t>(e);
+        float* dst = rec + kRecFloats * static_cast<int64_t>(e);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) dst[q] = s_acc[slot][q];
+        for (int q = 0; q < kSums; ++q) dst[q] = s_acc[slot][q];
         vis[e] = 1;
       }
     }
@@ -394,10 +421,11 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
 // Sum of one Gaussian's flagged records in [e0, e0 + cnt) by one thread,
 // reading the flags 16 at a time.  The emission order keeps a Gaussian's
 // pairs contiguous.
+template <int kSums>
 __device__ __forceinline__ void gather_range(uint32_t e0, uint32_t cnt, const float* __restrict__ rec,
-                                             const uint8_t* __restrict__ vis, float acc[9]) {
+                                             const uint8_t* __restrict__ vis, float acc[10]) {
 #pragma unroll
-  for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
+  for (int c = 0; c < 10; ++c) acc[c] = 0.0f;
   const uint32_t e1 = e0 + cnt;
   for (uint32_t b = e0 & ~15u; b < e1; b += 16) {
     const uint4 w = *reinterpret_cast<const uint4*>(vis + b);
@@ -406,9 +434,9 @@ __device__ __forceinline__ void gather_range(uint32_t e0, uint32_t cnt, const fl
     for (int j = 0; j < 16; ++j) {
       const uint32_t e = b + static_cast<uint32_t>(j);
       if (((words[j >> 2] >> (8 * (j & 3))) & 0xffu) && e >= e0 && e < e1) {
-        const float* r = rec + 9 * static_cast<int64_t>(e);
+        const float* r = rec + kRecFloats * static_cast<int64_t>(e);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) acc[q] += r[q];
+        for (int q = 0; q < kSums; ++q) acc[q] += r[q];
       }
     }
   }
@@ -423,12 +451,13 @@ constexpr uint32_t kShortRange = 48;  // Gaussians with more listed pairs are ga
 // then take the listed records 64 at a time.  A near-camera splat with
 // thousands of listed tiles thus needs a few rounds instead of one round per
 // 64 flags.  Every lane returns its partial sums; the caller reduces them.
+template <int kSums>
 __device__ __forceinline__ void gather_range_wave(uint32_t e0, uint32_t cnt, int lane,
                                                   const float* __restrict__ rec,
                                                   const uint8_t* __restrict__ vis, uint32_t* idx,
-                                                  float acc[9]) {
+                                                  float acc[10]) {
 #pragma unroll
-  for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
+  for (int c = 0; c < 10; ++c) acc[c] = 0.0f;
   const uint32_t e1 = e0 + cnt;
   for (uint32_t b = e0 & ~15u; b < e1; b += 1024) {
     const uint32_t mb = b + 16u * static_cast<uint32_t>(lane);
@@ -461,9 +490,9 @@ __device__ __forceinline__ void gather_range_wave(uint32_t e0, uint32_t cnt, int
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int k = lane; k < total; k += 64) {
-      const float* r = rec + 9 * static_cast<int64_t>(idx[k]);
+      const float* r = rec + kRecFloats * static_cast<int64_t>(idx[k]);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) acc[q] += r[q];
+      for (int q = 0; q < kSums; ++q) acc[q] += r[q];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -474,10 +503,12 @@ __device__ __forceinline__ void gather_range_wave(uint32_t e0, uint32_t cnt, int
 // Per visible Gaussian: the index range of its pairs (first[g] and the
 // listed count: its rectangle's tiles, or, for culled lists, up to the end
 // of its last row) and the sum of the flagged records.
-template <bool kCulled>
+// kCh: the records hold a tenth sum (d depth); g2d slot 9 receives it, or 0.
+template <bool kCulled, bool kCh>
 __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, Lists lists,
                                                      const float* __restrict__ rec,
                                                      const uint8_t* __restrict__ vis, float* g2d) {
+  constexpr int kSums = kCh ? 10 : 9;
   __shared__ uint32_t s_queue[256][3];
   __shared__ uint32_t s_idx[4][1024];  // per wave: flagged pair indices of one round
   __shared__ int s_qn;
@@ -506,11 +537,11 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, List
     if (static_cast<uint64_t>(e0) > cap || static_cast<uint64_t>(cnt) > cap - e0) cnt = 0;
   }
   if (visible && cnt <= kShortRange) {
-    float acc[9];
-    gather_range(e0, cnt, rec, vis, acc);
+    float acc[10];
+    gather_range<kSums>(e0, cnt, rec, vis, acc);
     float* dst = g2d + kG2DStride * gi;
 #pragma unroll
-    for (int c = 0; c < 9; ++c) dst[c] = acc[c];
+    for (int c = 0; c < 10; ++c) dst[c] = acc[c];
   } else if (visible) {
     const int q = atomicAdd(&s_qn, 1);
     s_queue[q][0] = static_cast<uint32_t>(gi);
@@ -521,16 +552,16 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, List
   const int qn = s_qn;
   for (int qi = wid; qi < qn; qi += 4) {
     const uint32_t g = s_queue[qi][0];
-    float acc[9], red[3];
-    gather_range_wave(s_queue[qi][1], s_queue[qi][2], lane, rec, vis, s_idx[wid], acc);
-    wave_sum9(acc, red);
+    float acc[10], red[3];
+    gather_range_wave<kSums>(s_queue[qi][1], s_queue[qi][2], lane, rec, vis, s_idx[wid], acc);
+    wave_sum10(acc, red);
     if ((lane & 15) == 0) {
       const int r = lane >> 4;
       float* dst = g2d + kG2DStride * static_cast<int64_t>(g);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const int qq = 4 * k + 2 * (r & 1) + (r >> 1);
-        if (qq < 9) dst[qq] = red[k];
+        if (qq < 10) dst[qq] = red[k];
       }
     }
   }
@@ -542,8 +573,11 @@ hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t
   StageScope scope(PVG_STAGE_RENDER_FWD, s);
   const dim3 grid(static_cast<unsigned>(((vs.total_tiles + 7) / 8) * 8));
   unsigned long long* cnt = profile_work_counter(PVG_STAGE_RENDER_FWD);
-  auto k = cnt ? (culled ? k_render_fwd<true, true> : k_render_fwd<true, false>)
-               : (culled ? k_render_fwd<false, true> : k_render_fwd<false, false>);
+  const bool depth = !vs.table && vs.one.depth_img;  // channels are single-view only
+  auto k = depth ? (cnt ? (culled ? k_render_fwd<true, true, true> : k_render_fwd<true, false, true>)
+                        : (culled ? k_render_fwd<false, true, true> : k_render_fwd<false, false, true>))
+                 : (cnt ? (culled ? k_render_fwd<true, true, false> : k_render_fwd<true, false, false>)
+                        : (culled ? k_render_fwd<false, true, false> : k_render_fwd<false, false, false>));
   hipLaunchKernelGGL(k, grid, dim3(64), 0, s, vs, geom, vals, ranges, cnt);
   return hipGetLastError();
 }
@@ -552,6 +586,8 @@ hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const Lists& l
                              int64_t vis_bytes, float* g2d, hipStream_t s) {
   if (vs.total_tiles == 0) return hipSuccess;
   const bool culled = lists.culled;
+  // channel gradients are single-view only
+  const bool ch = !vs.table && (vs.one.dL_ddepth || vs.one.dL_dT);
   {
     StageScope scope(PVG_STAGE_RENDER_BWD, s);
     // clear the flags (a fill kernel: no memset node in a captured graph)
@@ -559,15 +595,18 @@ hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const Lists& l
     if (e != hipSuccess) return e;
     const dim3 grid(static_cast<unsigned>(((vs.total_tiles + 7) / 8) * 8));
     unsigned long long* cnt = profile_work_counter(PVG_STAGE_RENDER_BWD);
-    auto k = cnt ? (culled ? k_render_bwd<true, true> : k_render_bwd<true, false>)
-                 : (culled ? k_render_bwd<false, true> : k_render_bwd<false, false>);
+    auto k = ch ? (cnt ? (culled ? k_render_bwd<true, true, true> : k_render_bwd<true, false, true>)
+                       : (culled ? k_render_bwd<false, true, true> : k_render_bwd<false, false, true>))
+                : (cnt ? (culled ? k_render_bwd<true, true, false> : k_render_bwd<true, false, false>)
+                       : (culled ? k_render_bwd<false, true, false> : k_render_bwd<false, false, false>));
     hipLaunchKernelGGL(k, grid, dim3(64), 0, s, vs, geom, lists, rec, vis, cnt);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (vs.total_gauss == 0) return hipSuccess;
   StageScope scope(PVG_STAGE_GRAD_GATHER, s);
-  hipLaunchKernelGGL(culled ? k_grad_gather<true> : k_grad_gather<false>,
+  hipLaunchKernelGGL(ch ? (culled ? k_grad_gather<true, true> : k_grad_gather<false, true>)
+                        : (culled ? k_grad_gather<true, false> : k_grad_gather<false, false>),
                      dim3(static_cast<unsigned>((vs.total_gauss + 255) / 256)), dim3(256), 0, s, vs, geom, lists, rec,
                      vis, g2d);
   return hipGetLastError();

@@ -215,16 +215,24 @@ def bin_sort_nosync(geom: Geom, cam: L.Camera, capacity: int, tile_cull: bool = 
     return bins
 
 
-def render_fwd(geom: Geom, bins: Bins, cam: L.Camera, frame: L.Frame, out=None):
-    """Composite one view; `out` (optional, contiguous [3,H,W] float32) receives the image."""
+def render_fwd(geom: Geom, bins: Bins, cam: L.Camera, frame: L.Frame, out=None, depth=None):
+    """Composite one view; `out` (optional, contiguous [3,H,W] float32)
+    receives the image and `depth` (optional, contiguous [H,W] float32) the
+    blended camera depth sum T alpha z."""
     dev = geom.xy.device
     H, W = int(cam.height), int(cam.width)
     img = torch.empty((3, H, W), dtype=torch.float32, device=dev) if out is None else out
     final_T = torch.empty((H, W), dtype=torch.float32, device=dev)
     n_contrib = torch.empty((H, W), dtype=torch.int32, device=dev)
     gs, bs = geom.struct(), bins.struct()
-    L.check(L.load().pvg_render_fwd(C.byref(gs), C.byref(bs), C.byref(cam), C.byref(frame), _p(img), _p(final_T),
-                                    _p(n_contrib), _stream_handle()))
+    if depth is None:
+        L.check(L.load().pvg_render_fwd(C.byref(gs), C.byref(bs), C.byref(cam), C.byref(frame), _p(img),
+                                        _p(final_T), _p(n_contrib), _stream_handle()))
+    else:
+        assert depth.is_contiguous() and depth.shape == (H, W) and depth.dtype == torch.float32
+        ch = L.Channels(depth.data_ptr(), None, None)
+        L.check(L.load().pvg_render_fwd_channels(C.byref(gs), C.byref(bs), C.byref(cam), C.byref(frame), _p(img),
+                                                 _p(final_T), _p(n_contrib), C.byref(ch), _stream_handle()))
     return img, final_T, n_contrib
 
 
@@ -281,28 +289,51 @@ class _BwdViewsArgs:
                                                  max(v[3].capacity for v in views), C.byref(size)))
         self.tmp_bytes = int(size.value)
 
-    def call(self, dev, dimgs, grads, accumulate):
+    def call(self, dev, dimgs, grads, accumulate, ddepths=None, dTs=None):
+        """ddepths / dTs (optional, per view [H,W] or None): upstream gradients
+        of the depth channel and of final_T."""
         gg = L.GaussiansGrad()
         for name, t in zip(FIELDS, grads):
             setattr(gg, name, t.data_ptr())
+        ddepths = list(ddepths) if ddepths is not None else [None] * self.nv
+        dTs = list(dTs) if dTs is not None else [None] * self.nv
+        chan = any(d is not None for d in ddepths + dTs)
+        dimgs = list(dimgs)
+        if chan:  # a view with only channel gradients still needs an image gradient (zeros)
+            for k in range(self.nv):
+                if dimgs[k] is None and (ddepths[k] is not None or dTs[k] is not None):
+                    dimgs[k] = torch.zeros((3, int(self.cams[k].height), int(self.cams[k].width)),
+                                           dtype=torch.float32, device=dev)
         dls = [None if d is None else d.contiguous() for d in dimgs]
         d_l = (C.c_void_p * self.nv)(*[None if d is None else d.data_ptr() for d in dls])
         tmp = _scratch(dev, self.tmp_bytes)
-        L.check(L.load().pvg_render_bwd_views(C.byref(self.g), self.nv, self.cams, self.frames, self.geoms,
-                                              self.bins, self.f_t, self.n_c, d_l, C.byref(gg),
-                                              1 if accumulate else 0, _p(tmp), int(tmp.numel()), _stream_handle()))
+        if not chan:
+            L.check(L.load().pvg_render_bwd_views(C.byref(self.g), self.nv, self.cams, self.frames, self.geoms,
+                                                  self.bins, self.f_t, self.n_c, d_l, C.byref(gg),
+                                                  1 if accumulate else 0, _p(tmp), int(tmp.numel()),
+                                                  _stream_handle()))
+            return grads
+        dd = [None if d is None else d.contiguous() for d in ddepths]
+        dt = [None if d is None else d.contiguous() for d in dTs]
+        ch = (L.Channels * self.nv)(*[L.Channels(None, None if a is None else a.data_ptr(),
+                                                 None if b is None else b.data_ptr()) for a, b in zip(dd, dt)])
+        L.check(L.load().pvg_render_bwd_views_channels(C.byref(self.g), self.nv, self.cams, self.frames, self.geoms,
+                                                       self.bins, self.f_t, self.n_c, d_l, ch, C.byref(gg),
+                                                       1 if accumulate else 0, _p(tmp), int(tmp.numel()),
+                                                       _stream_handle()))
         return grads
 
 
-def render_bwd_views(params, n, degree, views, grads=None, accumulate=False):
+def render_bwd_views(params, n, degree, views, grads=None, accumulate=False, ddepths=None, dTs=None):
     """One adjoint call for several views of the same Gaussians:
     views = [(cam, frame, geom, bins, final_T, n_contrib, dL_dimg or None)];
     the per-Gaussian chain rule of all views is summed in registers and the
-    gradient written (or added) once."""
+    gradient written (or added) once.  ddepths / dTs: optional per-view
+    upstream gradients of the depth channel and of final_T."""
     if grads is None:
         grads = [torch.empty_like(p) for p in params]
     args = _BwdViewsArgs(params, n, degree, [v[:6] for v in views])
-    return args.call(params[0].device, [v[6] for v in views], grads, accumulate)
+    return args.call(params[0].device, [v[6] for v in views], grads, accumulate, ddepths, dTs)
 
 
 def render(params, cam: dict, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), tile_cull=True):
@@ -387,7 +418,7 @@ def _record(stream):
     return ev
 
 
-def _forward_views(params, n, degree, views, tile_cull, stacked=None):
+def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=None):
     """Bin and composite view k on lane k mod VIEW_STREAMS, where lane 0 is
     the caller's stream and the others are side streams forked from it and
     joined back into it (the views' latency-bound sort and scan kernels
@@ -402,7 +433,8 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None):
     ordered before any later work on the caller's stream).  A view that
     outgrew its cached capacity is redone.  With `stacked` ([V,3,H,W],
     allocated on the caller's stream) view k's image is written into
-    stacked[k]."""
+    stacked[k]; with `depths` ([V,H,W], the same) its depth channel into
+    depths[k]."""
     dev = params[0].device
     main = torch.cuda.current_stream(dev)
     side = _streams(dev)
@@ -435,7 +467,8 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None):
             flags[k].copy_(bins.counters[2], non_blocking=True)
             fe = torch.cuda.Event()
             fe.record(st)
-            out = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k])
+            out = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k],
+                             None if depths is None else depths[k])
             ev = None
             if st is not main:
                 ev = torch.cuda.Event()
@@ -458,7 +491,8 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None):
             c, f, geom, _ = plans[k]
             bins = bin_sort(geom, c, tile_cull=tile_cull)
             plans[k][3] = bins
-            outs[k] = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k])
+            outs[k] = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k],
+                                 None if depths is None else depths[k])
     return plans, outs
 
 
@@ -496,14 +530,16 @@ class PVGRenderViews(torch.autograd.Function):
     the lists when they fit KEEP_FRACTION of the device memory."""
 
     @staticmethod
-    def forward(ctx, views, recompute, tile_cull, stack, *tensors):
+    def forward(ctx, views, recompute, tile_cull, stack, channels, *tensors):
         params, n, degree = _check_params(list(tensors))
         dev = params[0].device
-        stacked = None
+        stacked, depths = None, None
         if stack:
             H, W = int(views[0][0]["height"]), int(views[0][0]["width"])
             stacked = torch.empty((len(views), 3, H, W), dtype=torch.float32, device=dev)
-        plans, outs = _forward_views(params, n, degree, views, tile_cull, stacked)
+            if channels:
+                depths = torch.empty((len(views), H, W), dtype=torch.float32, device=dev)
+        plans, outs = _forward_views(params, n, degree, views, tile_cull, stacked, depths)
         if recompute == "auto":
             kept_bytes = sum(_bins_bytes(b) for _, _, _, b in plans)
             recompute = kept_bytes > KEEP_FRACTION * torch.cuda.get_device_properties(dev).total_memory
@@ -516,6 +552,9 @@ class PVGRenderViews(torch.autograd.Function):
             saved += [T, nc]
         ctx.save_for_backward(*saved)
         ctx.stack = stack
+        ctx.channels = channels
+        if channels:  # the images, the depth channels and final_T, each stacked over the views
+            return stacked, depths, torch.stack([T for _, T, _ in outs])
         if stack:
             return stacked
         return tuple(img for img, _, _ in outs)
@@ -523,6 +562,11 @@ class PVGRenderViews(torch.autograd.Function):
     @staticmethod
     def backward(ctx, *dimgs):
         n, degree, recompute, tile_cull, plan = ctx.meta
+        ddepths = dTs = None
+        if ctx.channels:
+            d_depth, d_T = dimgs[1], dimgs[2]
+            ddepths = [None if d_depth is None else d_depth[k] for k in range(len(plan))]
+            dTs = [None if d_T is None else d_T[k] for k in range(len(plan))]
         if ctx.stack:
             d = dimgs[0]
             dimgs = tuple(None if d is None else d[k] for k in range(len(plan)))
@@ -534,31 +578,42 @@ class PVGRenderViews(torch.autograd.Function):
             # same inputs give the forward's lists bit for bit, within its capacity
             first = True
             for k, (c, f, cap) in enumerate(plan):
-                if dimgs[k] is None:
+                dd = None if ddepths is None else ddepths[k]
+                dt = None if dTs is None else dTs[k]
+                if dimgs[k] is None and dd is None and dt is None:
                     continue
                 geom = preprocess(params, n, degree, c, f)
                 bins = bin_sort_nosync(geom, c, cap, tile_cull)
                 render_bwd_views(params, n, degree, [(c, f, geom, bins, saved[9 + 2 * k], saved[10 + 2 * k],
-                                                      dimgs[k])], grads=grads, accumulate=not first)
+                                                      dimgs[k])], grads=grads, accumulate=not first,
+                                 ddepths=[dd], dTs=[dt])
                 first = False
             if first:
                 for gr in grads:
                     gr.zero_()
         else:  # the kept lists, final_T and n_contrib, with the arguments built in the forward
-            ctx.bwd.call(params[0].device, dimgs, grads, accumulate=False)
-        return (None, None, None, None, *grads)
+            ctx.bwd.call(params[0].device, dimgs, grads, accumulate=False, ddepths=ddepths, dTs=dTs)
+        return (None, None, None, None, None, *grads)
 
 
-def pvg_render_views(params, views, recompute="auto", tile_cull=True, stack=False):
+def pvg_render_views(params, views, recompute="auto", tile_cull=True, stack=False, channels=False):
     """Differentiable renders of the nine parameter tensors for several views:
     views = [(cam, t), (cam, t, dt), ... or (cam, t, dt, advect_mode, bg)];
     returns one image [3,H,W] per view, or with stack=True (views of one
     resolution) a single [V,3,H,W] tensor.  recompute: True, False or "auto"
-    (see PVGRenderViews)."""
+    (see PVGRenderViews).  channels=True (implies stack) also renders the
+    flexible-rendering channels of Sec. 3.1 and returns (images [V,3,H,W],
+    depth [V,H,W] = sum T alpha z, opacity [V,H,W] = sum T alpha = 1 -
+    final_T), all differentiable; the normalized depth is depth / opacity."""
     full = _full_views(views)
+    stack = bool(stack or channels)
     if stack and len({(int(v[0]["width"]), int(v[0]["height"])) for v in full}) != 1:
         raise ValueError("stack=True needs views of one resolution")
-    return PVGRenderViews.apply(full, recompute, tile_cull, bool(stack), *params)
+    out = PVGRenderViews.apply(full, recompute, tile_cull, stack, bool(channels), *params)
+    if channels:
+        img, depth, final_T = out
+        return img, depth, 1.0 - final_T
+    return out
 
 
 def pvg_render(params, cam, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), recompute=True, tile_cull=True):
