@@ -45,19 +45,20 @@ def lib():
         L = C.CDLL(_LIB)
         vp = C.c_void_p
         i64, i32 = C.c_int64, C.c_int
-        L.orc_preprocess_f32.argtypes = [i64, i32, vp, vp, i32, i32, vp] + [vp] * 8
+        L.orc_preprocess_f32.argtypes = [i64, i32, vp, vp, i32, i32, vp] + [vp] * 9
         L.orc_preprocess_f32.restype = None
         L.orc_bin_sort.argtypes = [i64, vp, vp, vp, i32, i32, i64, vp, vp, vp]
         L.orc_bin_sort.restype = i64
-        L.orc_render_f32.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, i64, i64, vp, vp, vp, vp, vp]
+        L.orc_render_f32.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, i64, i64, vp, vp, vp, vp, vp,
+                                     vp, vp]
         L.orc_render_f32.restype = None
         L.orc_render_bruteforce_f32.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
         L.orc_render_bruteforce_f32.restype = None
         L.orc_render_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
-                                     vp, vp, vp]
+                                     vp, vp, vp, vp, vp]
         L.orc_render_f64.restype = C.c_double
         L.orc_backward_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
-                                       vp, vp]
+                                       vp, vp, vp]
         L.orc_backward_f64.restype = None
         L.orc_temporal_f64.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_double, i32, vp, vp]
@@ -106,11 +107,12 @@ def preprocess_f32(scene, cam, t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0)) -> dict:
         "conic_op": np.zeros((n, 4), np.float32), "rgb": np.zeros((n, 3), np.float32),
         "radius": np.zeros(n, np.int32), "rect": np.zeros((n, 4), np.int32),
         "tiles": np.zeros(n, np.uint32), "flags": np.zeros(n, np.uint32),
+        "feat": np.zeros((n, 4), np.float32),  # mean velocity v~ (3) and staticness rho
     }
     cv, fv = cam_array(cam), frame_array(t, dt, mode, bg)
     lib().orc_preprocess_f32(n, int(scene["sh_degree"]), ptrs, _p(cv), cam["width"], cam["height"], _p(fv),
                              *[_p(out[k]) for k in ("xy", "depth", "conic_op", "rgb", "radius", "rect",
-                                                    "tiles", "flags")])
+                                                    "tiles", "flags", "feat")])
     return out
 
 
@@ -127,9 +129,11 @@ def bin_sort(pre, cam) -> dict:
     return {"M": M, "inst_tile": it[:M], "inst_gauss": ig[:M], "ranges": ranges}
 
 
-def render_f32(pre, bins, cam, t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0), tiles=None, want_depth=False):
+def render_f32(pre, bins, cam, t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0), tiles=None, want_depth=False,
+               want_feat=False):
     """FP32 image, final_T and last contributor of the tiles [lo, hi); with
-    want_depth also the blended depth channel sum T alpha z (a fourth result)."""
+    want_depth also the blended depth channel sum T alpha z, and with
+    want_feat the blended velocity and staticness maps [4,H,W] (appended)."""
     n = pre["depth"].shape[0]
     W, H = cam["width"], cam["height"]
     GX, GY = grid(cam)
@@ -140,10 +144,16 @@ def render_f32(pre, bins, cam, t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0), tiles=None
     cv, fv = cam_array(cam), frame_array(t, dt, mode, bg)
     ig = bins["inst_gauss"] if bins["M"] > 0 else np.zeros(1, np.uint32)
     D = np.zeros((H, W), np.float32) if want_depth else None
+    F = np.zeros((4, H, W), np.float32) if want_feat else None
     lib().orc_render_f32(n, _p(pre["xy"]), _p(pre["conic_op"]), _p(pre["rgb"]), _p(pre["radius"]), _p(cv),
                          W, H, _p(fv), _p(bins["ranges"]), _p(ig), lo, hi, _p(img), _p(T), _p(nc),
-                         _p(pre["depth"]), _p(D))
-    return (img, T, nc, D) if want_depth else (img, T, nc)
+                         _p(pre["depth"]), _p(D), _p(pre["feat"]), _p(F))
+    out = (img, T, nc)
+    if want_depth:
+        out += (D,)
+    if want_feat:
+        out += (F,)
+    return out
 
 
 def render_bruteforce_f32(pre, cam, t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0)):
@@ -174,7 +184,7 @@ def scene64(scene) -> dict:
 
 
 def render_f64(sc64, cam, t, dt, mode, bg, pre, bins, tile_mask=None, w=None, want_img=True, wD=None, wT=None,
-               want_depth=False):
+               want_depth=False, wF=None):
     """FP64 image on the FP32 stage's discrete structure; returns (sum(w*img)
     + sum(wD*depth) + sum(wT*final_T), img, final_T), and the depth channel
     as a fourth result with want_depth."""
@@ -188,18 +198,20 @@ def render_f64(sc64, cam, t, dt, mode, bg, pre, bins, tile_mask=None, w=None, wa
     wv = None if w is None else _c(w, np.float64)
     wDv = None if wD is None else _c(wD, np.float64)
     wTv = None if wT is None else _c(wT, np.float64)
+    wFv = None if wF is None else _c(wF, np.float64)
     D = np.zeros((H, W), np.float64) if want_depth else None
     tm = None if tile_mask is None else _c(tile_mask, np.uint8)
     L = lib().orc_render_f64(n, int(sc64["sh_degree"]), ptrs, _p(cv), W, H, _p(fv), _p(pre["xy"]),
                              _p(pre["conic_op"]), _p(pre["radius"]), _p(pre["flags"]), _p(bins["ranges"]),
-                             _p(ig), _p(tm), _p(wv), _p(img), _p(T), _p(wDv), _p(wTv), _p(D))
+                             _p(ig), _p(tm), _p(wv), _p(img), _p(T), _p(wDv), _p(wTv), _p(D), _p(wFv), None)
     return (L, img, T, D) if want_depth else (L, img, T)
 
 
-def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, tile_mask=None, dD=None, dT=None
+def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, tile_mask=None, dD=None, dT=None, dF=None
                  ) -> tuple[dict, np.ndarray]:
     """FP64 gradients of sum(dimg * image) + sum(dD * depth) + sum(dT * final_T)
-    for every parameter array, and g2d [N,10] (the tenth entry: d depth).
+    + sum(dF * (velocity map, staticness map)) for every parameter array, and
+    g2d [N,14] (entries 9..13: d depth, d v~, d rho).
     tile_mask (optional, one byte per tile): only these tiles are visited; dimg,
     dD and dT must be zero on every other tile."""
     n = int(sc64["n"])
@@ -207,7 +219,7 @@ def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, tile_mask=None, dD
     arrs, ptrs = _param_ptrs(sc64, np.float64)
     grads = {f: np.zeros_like(sc64[f], dtype=np.float64) for f in FIELDS}
     gptrs = (C.c_void_p * 9)(*[grads[f].ctypes.data for f in FIELDS])
-    g2d = np.zeros((n, 10), np.float64)
+    g2d = np.zeros((n, 14), np.float64)
     cv, fv = cam_array(cam), frame_array(t, dt, mode, bg)
     ig = bins["inst_gauss"] if bins["M"] > 0 else np.zeros(1, np.uint32)
     d = _c(dimg, np.float64)
@@ -219,12 +231,15 @@ def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, tile_mask=None, dD
         assert not np.any(d[:, ~keep]), "dimg must be zero outside the tile mask"
     dDv = None if dD is None else _c(dD, np.float64)
     dTv = None if dT is None else _c(dT, np.float64)
+    dFv = None if dF is None else _c(dF, np.float64)
     if tm is not None:
+        if dFv is not None:
+            assert not np.any(dFv[:, ~keep]), "dF must be zero outside the tile mask"
         for extra in (dDv, dTv):
             assert extra is None or not np.any(extra[~keep]), "dD and dT must be zero outside the tile mask"
     lib().orc_backward_f64(n, int(sc64["sh_degree"]), ptrs, _p(cv), W, H, _p(fv), _p(pre["xy"]),
                            _p(pre["conic_op"]), _p(pre["radius"]), _p(pre["flags"]), _p(bins["ranges"]),
-                           _p(ig), _p(d), gptrs, _p(g2d), _p(tm), _p(dDv), _p(dTv))
+                           _p(ig), _p(d), gptrs, _p(g2d), _p(tm), _p(dDv), _p(dTv), _p(dFv))
     return grads, g2d
 
 

@@ -154,6 +154,7 @@ template <class R> struct Splat {
   R op;          // opacity at time t
   R rgb[3];
   R depth;       // camera-space z
+  R feat[4];     // mean velocity v~ = v exp(-beta / (2 l)) (Sec. 3.4) and staticness rho = beta / l
   int radius;
   int rect[4];   // tile rectangle x0, y0, x1, y1 (half-open)
   uint32_t flags;
@@ -242,6 +243,11 @@ void preprocess_one(const Params& prm, int64_t i, const Camera& cam, const Frame
   for (int r = 0; r < 3; ++r)
     it.p[r] = ((W[3 * r] * it.mu_r[0] + W[3 * r + 1] * it.mu_r[1]) + W[3 * r + 2] * it.mu_r[2]) + T[r];
   s.depth = it.p[2];
+  {  // the per-Gaussian quantities of the velocity and staticness maps
+    const R e = exp_cr(R(-0.5) * (it.beta / it.l));
+    for (int c = 0; c < 3; ++c) s.feat[c] = it.v[c] * e;
+    s.feat[3] = it.beta / it.l;
+  }
   if (fixed) {
     if (!fixed->visible) return;
   } else if (!(it.p[2] > R(cam.znear))) {
@@ -362,12 +368,14 @@ template <class R> struct Contrib {
 
 template <class R>
 void composite_pixel(int px, int py, const uint32_t* list, int64_t len, const Splat<float>* dec,
-                     const Splat<R>* val, const float bg[3], R out[3], R& Tfin, R& Dout, int& ncontrib,
+                     const Splat<R>* val, const float bg[3], R out[3], R& Tfin, R Fout[5], int& ncontrib,
                      std::vector<Contrib<R>>* rec) {
   float T32 = 1.0f;
   R T = R(1);
   R C[3] = {R(0), R(0), R(0)};
-  R D = R(0);  // "flexible rendering" (Sec. 3.1): the Gaussians' camera depths blended like colour
+  // "flexible rendering" (Sec. 3.1): the Gaussians' camera depths, mean
+  // velocities and staticness blended like colour (no background term)
+  R F[5] = {R(0), R(0), R(0), R(0), R(0)};
   ncontrib = 0;
   const float fpx = static_cast<float>(px), fpy = static_cast<float>(py);
   for (int64_t k = 0; k < len; ++k) {
@@ -389,22 +397,23 @@ void composite_pixel(int px, int py, const uint32_t* list, int64_t len, const Sp
     const R alpha = clamped ? R(0.99f) : v.op * G;
     if (rec) rec->push_back({g, alpha, T, G, vdx, vdy, clamped});
     for (int c = 0; c < 3; ++c) C[c] = C[c] + v.rgb[c] * (alpha * T);
-    D = D + v.depth * (alpha * T);
+    F[0] = F[0] + v.depth * (alpha * T);
+    for (int f = 0; f < 4; ++f) F[1 + f] = F[1 + f] + v.feat[f] * (alpha * T);
     T = T * (R(1) - alpha);
     T32 = Tn;
     ncontrib = static_cast<int>(k + 1);
   }
   for (int c = 0; c < 3; ++c) out[c] = C[c] + T * R(bg[c]);
   Tfin = T;
-  Dout = D;
+  for (int f = 0; f < 5; ++f) Fout[f] = F[f];
 }
 
 // FP32 image path specialisation: values and decisions are one array.
 void composite_pixel_f32(int px, int py, const uint32_t* list, int64_t len, const Splat<float>* sp,
-                         const float bg[3], float out[3], float& Tfin, float& Dout, int& ncontrib) {
+                         const float bg[3], float out[3], float& Tfin, float Fout[5], int& ncontrib) {
   float T = 1.0f;
   float C[3] = {0.0f, 0.0f, 0.0f};
-  float D = 0.0f;
+  float F[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   ncontrib = 0;
   const float fpx = static_cast<float>(px), fpy = static_cast<float>(py);
   for (int64_t k = 0; k < len; ++k) {
@@ -417,13 +426,14 @@ void composite_pixel_f32(int px, int py, const uint32_t* list, int64_t len, cons
     const float Tn = T * (1.0f - alpha);
     if (Tn < 0.0001f) break;
     for (int c = 0; c < 3; ++c) C[c] = C[c] + d.rgb[c] * (alpha * T);
-    D = D + d.depth * (alpha * T);
+    F[0] = F[0] + d.depth * (alpha * T);
+    for (int f = 0; f < 4; ++f) F[1 + f] = F[1 + f] + d.feat[f] * (alpha * T);
     T = Tn;
     ncontrib = static_cast<int>(k + 1);
   }
   for (int c = 0; c < 3; ++c) out[c] = C[c] + T * bg[c];
   Tfin = T;
-  Dout = D;
+  for (int f = 0; f < 5; ++f) Fout[f] = F[f];
 }
 
 Camera make_cam(const float* c, int W, int H) {
@@ -449,7 +459,7 @@ Params make_params(int64_t n, int degree, const void* const* arr) {
 // Rebuild FP32 splats (the decision side) from the arrays the FP32 stage wrote.
 std::vector<Splat<float>> load_splats(int64_t n, const float* xy, const float* conic_op,
                                       const float* rgb, const int32_t* radius, const uint32_t* flags,
-                                      const float* depth = nullptr) {
+                                      const float* depth = nullptr, const float* feat = nullptr) {
   std::vector<Splat<float>> sp(n);
   for (int64_t i = 0; i < n; ++i) {
     Splat<float>& s = sp[i];
@@ -459,6 +469,7 @@ std::vector<Splat<float>> load_splats(int64_t n, const float* xy, const float* c
     s.op = conic_op[4 * i + 3];
     for (int c = 0; c < 3; ++c) s.rgb[c] = rgb ? rgb[3 * i + c] : 0.0f;
     s.depth = depth ? depth[i] : 0.0f;
+    for (int f = 0; f < 4; ++f) s.feat[f] = feat ? feat[4 * i + f] : 0.0f;
     s.flags = flags ? flags[i] : 0;
     s.radius = radius[i];
   }
@@ -467,7 +478,7 @@ std::vector<Splat<float>> load_splats(int64_t n, const float* xy, const float* c
 
 struct Inst { uint32_t tile, dbits, g; };
 
-constexpr int kG2D = 10;  // per-Gaussian screen-space gradient entries of the adjoint
+constexpr int kG2D = 14;  // per-Gaussian screen-space gradient entries of the adjoint
 
 }  // namespace
 
@@ -477,10 +488,11 @@ extern "C" {
 // rot, sh, opacity, vel, period, tau, beta (SoA, [rows][n]).  cam = R[9],
 // T[3], fx, fy, cx, cy, znear; frame = t, dt, mode, bg[3].
 // Outputs: xy[n][2], depth[n], conic_op[n][4], rgb[n][3], radius[n] (0 =
-// invisible), rect[n][4], tiles[n], flags[n].
+// invisible), rect[n][4], tiles[n], flags[n], and (optional) feat[n][4] = mean
+// velocity v~ and staticness rho.
 void orc_preprocess_f32(int64_t n, int degree, const void* const* arr, const float* camv, int W, int H,
                         const float* framev, float* xy, float* depth, float* conic_op, float* rgb,
-                        int32_t* radius, int32_t* rect, uint32_t* tiles, uint32_t* flags) {
+                        int32_t* radius, int32_t* rect, uint32_t* tiles, uint32_t* flags, float* feat) {
   const Params prm = make_params(n, degree, arr);
   const Camera cam = make_cam(camv, W, H);
   const Frame fr = make_frame(framev);
@@ -490,6 +502,8 @@ void orc_preprocess_f32(int64_t n, int degree, const void* const* arr, const flo
     xy[2 * i] = s.visible ? s.x : 0.0f;
     xy[2 * i + 1] = s.visible ? s.y : 0.0f;
     depth[i] = s.depth;
+    if (feat)
+      for (int f = 0; f < 4; ++f) feat[4 * i + f] = s.feat[f];
     conic_op[4 * i] = s.visible ? s.A : 0.0f;
     conic_op[4 * i + 1] = s.visible ? s.B : 0.0f;
     conic_op[4 * i + 2] = s.visible ? s.C : 0.0f;
@@ -546,10 +560,10 @@ void orc_render_f32(int64_t n, const float* xy, const float* conic_op, const flo
                     const int32_t* radius, const float* camv, int W, int H, const float* framev,
                     const uint32_t* ranges, const uint32_t* inst_gauss, int64_t tile_lo,
                     int64_t tile_hi, float* img, float* final_T, int32_t* n_contrib, const float* depth,
-                    float* depth_img) {
+                    float* depth_img, const float* feat, float* feat_img) {
   const Frame fr = make_frame(framev);
   (void)camv;
-  const std::vector<Splat<float>> sp = load_splats(n, xy, conic_op, rgb, radius, nullptr, depth);
+  const std::vector<Splat<float>> sp = load_splats(n, xy, conic_op, rgb, radius, nullptr, depth, feat);
   const int GX = (W + kTile - 1) / kTile;
   const int64_t HW = static_cast<int64_t>(H) * W;
   for (int64_t t = tile_lo; t < tile_hi; ++t) {
@@ -558,14 +572,16 @@ void orc_render_f32(int64_t n, const float* xy, const float* conic_op, const flo
     const int64_t len = static_cast<int64_t>(ranges[2 * t + 1]) - ranges[2 * t];
     for (int py = ty * kTile; py < std::min(H, (ty + 1) * kTile); ++py)
       for (int px = tx * kTile; px < std::min(W, (tx + 1) * kTile); ++px) {
-        float out[3], Tf, Df;
+        float out[3], Tf, Fo[5];
         int nc;
-        composite_pixel_f32(px, py, list, len, sp.data(), fr.bg, out, Tf, Df, nc);
+        composite_pixel_f32(px, py, list, len, sp.data(), fr.bg, out, Tf, Fo, nc);
         const int64_t o = static_cast<int64_t>(py) * W + px;
         for (int c = 0; c < 3; ++c) img[c * HW + o] = out[c];
         final_T[o] = Tf;
         n_contrib[o] = nc;
-        if (depth_img) depth_img[o] = Df;
+        if (depth_img) depth_img[o] = Fo[0];
+        if (feat_img)
+          for (int f = 0; f < 4; ++f) feat_img[f * HW + o] = Fo[1 + f];
       }
   }
 }
@@ -596,10 +612,10 @@ void orc_render_bruteforce_f32(int64_t n, const float* xy, const float* depth, c
       std::sort(cand.begin(), cand.end());
       list.clear();
       for (auto& c : cand) list.push_back(c.second);
-      float out[3], Tf, Df;
+      float out[3], Tf, Fo[5];
       int nc;
       composite_pixel_f32(px, py, list.data(), static_cast<int64_t>(list.size()), sp.data(), fr.bg, out,
-                          Tf, Df, nc);
+                          Tf, Fo, nc);
       const int64_t o = static_cast<int64_t>(py) * W + px;
       for (int c = 0; c < 3; ++c) img[c * HW + o] = out[c];
       final_T[o] = Tf;
@@ -613,12 +629,14 @@ void orc_render_bruteforce_f32(int64_t n, const float* xy, const float* depth, c
 // of w[c][y][x] * img[c][y][x] (w may be null: returns 0); writes img/final_T
 // if non-null.  tile_mask (GX*GY bytes) selects tiles; null = all.  wD and wT
 // (optional, [H][W]) add sum wD * depth + sum wT * final_T to the returned
-// value; depth_img (optional) receives the blended depth channel.
+// value, wF (optional, [4][H][W]) sum wF * (velocity map, staticness map);
+// depth_img / feat_img (optional) receive those channels.
 double orc_render_f64(int64_t n, int degree, const void* const* arr, const float* camv, int W, int H,
                       const float* framev, const float* xy32, const float* conic_op32,
                       const int32_t* radius32, const uint32_t* flags32, const uint32_t* ranges,
                       const uint32_t* inst_gauss, const uint8_t* tile_mask, const double* w,
-                      double* img, double* final_T, const double* wD, const double* wT, double* depth_img) {
+                      double* img, double* final_T, const double* wD, const double* wT, double* depth_img,
+                      const double* wF, double* feat_img) {
   const Params prm = make_params(n, degree, arr);
   const Camera cam = make_cam(camv, W, H);
   const Frame fr = make_frame(framev);
@@ -639,9 +657,10 @@ double orc_render_f64(int64_t n, int degree, const void* const* arr, const float
     const int64_t len = static_cast<int64_t>(ranges[2 * t + 1]) - ranges[2 * t];
     for (int py = ty * kTile; py < std::min(H, (ty + 1) * kTile); ++py)
       for (int px = tx * kTile; px < std::min(W, (tx + 1) * kTile); ++px) {
-        double out[3], Tf, Df;
+        double out[3], Tf, Fo[5];
         int nc;
-        composite_pixel<double>(px, py, list, len, dec.data(), val.data(), fr.bg, out, Tf, Df, nc, nullptr);
+        composite_pixel<double>(px, py, list, len, dec.data(), val.data(), fr.bg, out, Tf, Fo, nc, nullptr);
+        const double Df = Fo[0];
         const int64_t o = static_cast<int64_t>(py) * W + px;
         for (int c = 0; c < 3; ++c) {
           if (img) img[c * HW + o] = out[c];
@@ -651,6 +670,10 @@ double orc_render_f64(int64_t n, int degree, const void* const* arr, const float
         if (depth_img) depth_img[o] = Df;
         if (wD) L += wD[o] * Df;
         if (wT) L += wT[o] * Tf;
+        for (int f = 0; f < 4; ++f) {
+          if (feat_img) feat_img[f * HW + o] = Fo[1 + f];
+          if (wF) L += wF[f * HW + o] * Fo[1 + f];
+        }
       }
   }
   return L;
@@ -661,12 +684,14 @@ double orc_render_f64(int64_t n, int degree, const void* const* arr, const float
 // channel and dT for final_T (the rendered opacity is 1 - final_T).  Writes
 // the gradient of every parameter array into `garr` (9 double* in parameter
 // layout, overwritten) and, if non-null, the per-Gaussian screen-space
-// gradient g2d[n][10] = (d x, d y, d A, d B, d C, d o~, d r, d g, d b, d z).
+// gradient g2d[n][14] = (d x, d y, d A, d B, d C, d o~, d r, d g, d b, d z,
+// d v~ (3), d rho).  dF (optional, [4][H][W]): upstream gradient of the
+// velocity and staticness maps.
 void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float* camv, int W, int H,
                       const float* framev, const float* xy32, const float* conic_op32,
                       const int32_t* radius32, const uint32_t* flags32, const uint32_t* ranges,
                       const uint32_t* inst_gauss, const double* dimg, void* const* garr, double* g2d_out,
-                      const uint8_t* tile_mask, const double* dD, const double* dT) {
+                      const uint8_t* tile_mask, const double* dD, const double* dT, const double* dF) {
   const Params prm = make_params(n, degree, arr);
   const Camera cam = make_cam(camv, W, H);
   const Frame fr = make_frame(framev);
@@ -694,9 +719,9 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
     for (int py = ty * kTile; py < std::min(H, (ty + 1) * kTile); ++py)
       for (int px = tx * kTile; px < std::min(W, (tx + 1) * kTile); ++px) {
         rec.clear();
-        double out[3], Tf, Df;
+        double out[3], Tf, Fo[5];
         int nc;
-        composite_pixel<double>(px, py, list, len, dec.data(), val.data(), fr.bg, out, Tf, Df, nc, &rec);
+        composite_pixel<double>(px, py, list, len, dec.data(), val.data(), fr.bg, out, Tf, Fo, nc, &rec);
         const int64_t o = static_cast<int64_t>(py) * W + px;
         const double g[3] = {dimg[o], dimg[HW + o], dimg[2 * HW + o]};
         const double gD = dD ? dD[o] : 0.0, gT = dT ? dT[o] : 0.0;
@@ -704,6 +729,8 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
         // SD the same for depth (no background term); final_T = prod (1 - alpha)
         double S[3] = {Tf * fr.bg[0], Tf * fr.bg[1], Tf * fr.bg[2]};
         double SD = 0.0;
+        double gF[4], SF[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int f = 0; f < 4; ++f) gF[f] = dF ? dF[f * HW + o] : 0.0;
         for (int64_t k = static_cast<int64_t>(rec.size()) - 1; k >= 0; --k) {
           const Contrib<double>& c = rec[k];
           const Splat<double>& v = val[c.g];
@@ -716,8 +743,13 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
           gg[9] += c.T * c.alpha * gD;
           dalpha += gD * (c.T * v.depth - SD / (1.0 - c.alpha));
           dalpha += gT * (-Tf / (1.0 - c.alpha));
+          for (int f = 0; f < 4; ++f) {
+            gg[10 + f] += c.T * c.alpha * gF[f];
+            dalpha += gF[f] * (c.T * v.feat[f] - SF[f] / (1.0 - c.alpha));
+          }
           for (int ch = 0; ch < 3; ++ch) S[ch] += c.T * c.alpha * v.rgb[ch];
           SD += c.T * c.alpha * v.depth;
+          for (int f = 0; f < 4; ++f) SF[f] += c.T * c.alpha * v.feat[f];
           if (c.clamped) continue;
           gg[5] += c.G * dalpha;
           const double gp = c.alpha * dalpha;  // d alpha / d power = alpha
@@ -882,6 +914,18 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
     }
     dtau += -std::cos(phi) * vg;
     dl += (std::sin(phi) / (2.0 * kPi) - del / it.l * std::cos(phi)) * vg;
+    // velocity map: v~ = v e, e = exp(-beta/(2l)); staticness rho = beta / l
+    {
+      const double e = std::exp(-0.5 * it.beta / it.l);
+      double vdot = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        dv[c] += e * gg[10 + c];
+        vdot += it.v[c] * gg[10 + c];
+      }
+      dbeta += vdot * e * (-0.5 / it.l) + gg[13] / it.l;
+      dl += vdot * e * (0.5 * it.beta / (it.l * it.l)) - gg[13] * it.beta / (it.l * it.l);
+      for (int c = 0; c < 3; ++c) gv[c * n + i] = dv[c];
+    }
     // opacity decay (Eq. (7)): o~ = o exp(-(t - tau)^2 / (2 beta^2))
     const double eo = std::exp(-0.5 * (del / it.beta) * (del / it.beta));
     const double dop = gg[5];

@@ -413,7 +413,8 @@ def _fd_check(orc, sc, cam, t, dt, mode, bg, fields=None, sample=None, seed=0, t
     w = rng.standard_normal((3, H, W))
     wD = rng.standard_normal((H, W)) * 0.1 if channels else None  # depths are O(10): keep the terms comparable
     wT = rng.standard_normal((H, W)) if channels else None
-    grads, _ = orc.backward_f64(s64, cam, t, dt, mode, bg, pre, bins, w, dD=wD, dT=wT)
+    wF = rng.standard_normal((4, H, W)) if channels else None
+    grads, _ = orc.backward_f64(s64, cam, t, dt, mode, bg, pre, bins, w, dD=wD, dT=wT, dF=wF)
     GX, GY = orc.grid(cam)
     vis = np.nonzero(pre["radius"] > 0)[0]
     assert vis.size > 0
@@ -435,7 +436,7 @@ def _fd_check(orc, sc, cam, t, dt, mode, bg, fields=None, sample=None, seed=0, t
             for k in (-2, -1, 1, 2):
                 arr[r, i] = old + k * h
                 L[k] = orc.render_f64(s64, cam, t, dt, mode, bg, pre, bins, tile_mask=tm.reshape(-1), w=w,
-                                      want_img=False, wD=wD, wT=wT)[0]
+                                      want_img=False, wD=wD, wT=wT, wF=wF)[0]
             arr[r, i] = old
             fd = (8 * (L[1] - L[-1]) - (L[2] - L[-2])) / (12 * h)
             err = abs(fd - g[r, i]) / max(abs(g[r, i]), 1e-2 * rms)
@@ -458,11 +459,12 @@ def test_adjoint_matches_finite_differences_tiny(orc, dt, mode):
 
 @pytest.mark.parametrize("dt,mode", [(0.0, 0), (0.05, 0)])
 def test_channel_adjoint_matches_finite_differences_tiny(orc, dt, mode):
-    """Flexible rendering (Sec. 3.1): the blended depth channel sum T alpha z
-    and the final transmittance (the rendered opacity O is 1 - final_T) enter
-    the loss with their own upstream gradients; finite differences of that
-    loss against the FP64 adjoint for every parameter of every visible
-    Gaussian (z moves with the mean, the flow offset and the time terms)."""
+    """Flexible rendering (Sec. 3.1): the blended depth channel sum T alpha z,
+    the velocity map sum T alpha v~ with v~ = v exp(-beta / (2 l)) and the
+    staticness map sum T alpha beta / l, and the final transmittance (the
+    rendered opacity O is 1 - final_T) enter the loss with their own upstream
+    gradients; finite differences of that loss against the FP64 adjoint for
+    every parameter of every visible Gaussian."""
     sc = gen.make_scene(30, 7, sh_degree=3)
     cam = gen.yaw_camera(64, 48, 10.0, (0.2, 0.1, -0.5))
     n = _fd_check(orc, sc, cam, 0.45, dt, mode, (0.1, 0.2, 0.3), channels=True)
@@ -490,6 +492,43 @@ def test_depth_channel_closed_form(orc):
     assert np.all(D[empty] == 0.0) and np.all(T[empty] == 1.0)
     _, _, T64, D64 = orc.render_f64(orc.scene64(sc), cam, cfg["t"], 0.0, 0, (0, 0, 0), pre, bins, want_depth=True)
     np.testing.assert_allclose(D64, z0 * (1.0 - T64), rtol=1e-12, atol=1e-12)
+
+
+def test_velocity_and_staticness_maps_closed_form(orc):
+    """With v = 0 the velocity map is exactly 0; with beta / l = rho0 for
+    every Gaussian the staticness map is rho0 * (1 - final_T) (FP64 to
+    rounding, FP32 to a few ulps); and the velocity map of one Gaussian alone
+    over a pixel is its T alpha v exp(-beta / (2 l))."""
+    cfg = gen.make_config(0)
+    cam, t = cfg["cameras"][0], cfg["t"]
+    sc = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in cfg["scene"].items()}
+    sc["vel"][:] = 0.0
+    rho0 = 0.625
+    sc["beta"][:] = np.float32(rho0) * sc["period"]
+    pre = orc.preprocess_f32(sc, cam, t)
+    vis = pre["radius"] > 0
+    assert np.all(pre["feat"][vis, :3] == 0.0)
+    bins = orc.bin_sort(pre, cam)
+    img, T, nc, F = orc.render_f32(pre, bins, cam, t, want_feat=True)
+    assert np.all(F[:3] == 0.0)
+    np.testing.assert_allclose(F[3], pre["feat"][vis, 3].max() * (1.0 - T.astype(np.float64)), rtol=1e-5,
+                               atol=1e-5)
+    assert np.allclose(pre["feat"][vis, 3], rho0, rtol=1e-6)
+    # one Gaussian: the map at its centre pixel is alpha v~ (T = 1 in front of it)
+    full = orc.preprocess_f32(cfg["scene"], cam, t)
+    inside = np.nonzero((full["radius"] > 0) & (full["xy"][:, 0] > 4) & (full["xy"][:, 0] < cam["width"] - 4)
+                        & (full["xy"][:, 1] > 4) & (full["xy"][:, 1] < cam["height"] - 4)
+                        & (full["conic_op"][:, 3] > 0.1))[0]
+    one = gen.subset_scene(cfg["scene"], inside[:1])
+    p1 = orc.preprocess_f32(one, cam, t)
+    b1 = orc.bin_sort(p1, cam)
+    _, T1, n1, F1 = orc.render_f32(p1, b1, cam, t, want_feat=True)
+    x, y = int(round(float(p1["xy"][0, 0]))), int(round(float(p1["xy"][0, 1])))
+    assert n1[y, x] == 1
+    a = 1.0 - float(T1[y, x])
+    e = np.exp(-0.5 * float(one["beta"][0]) / float(one["period"][0]))
+    np.testing.assert_allclose(F1[:3, y, x], a * e * one["vel"][:, 0].astype(np.float64), rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(F1[3, y, x], a * float(one["beta"][0]) / float(one["period"][0]), rtol=1e-5)
 
 
 def test_channel_adjoint_linear(orc):
