@@ -301,9 +301,9 @@ def main():
 
     # the step with the flexible-rendering channels (Sec. 3.1) in the loss: L1
     # on the images plus an inverse-depth L1 against a sparse synthetic depth
-    # target (5% of the pixels, standing in for projected LiDAR) and the
-    # opacity entropy term with a synthetic sky mask (the top eighth of each
-    # view), weights 0.1 and 0.01
+    # target (5% of the pixels, standing in for projected LiDAR), the opacity
+    # entropy term with a synthetic sky mask (the top eighth of each view) and
+    # the sparse velocity term on the velocity map, weights 0.1, 0.01, 0.01
     gch = torch.Generator(device="cuda").manual_seed(7)
     V = len(views)
     sparse = (torch.rand((V, H, W), device="cuda", generator=gch) < 0.05).float()
@@ -314,11 +314,11 @@ def main():
     def train_step_channels():
         for p in params:
             p.grad = None
-        imgs, depth, opac = pvg.pvg_render_views(params, views, channels=True)
+        imgs, depth, opac, vbar, _ = pvg.pvg_render_views(params, views, channels=True)
         o = opac.clamp(1e-6, 1.0 - 1e-6)
         inv = o / depth.clamp_min(1e-6)  # the inverse of the normalized depth depth / O
         loss = ((imgs - stacked_targets).abs().mean() * V + 0.1 * (sparse * (inv - inv_depth_target).abs()).mean()
-                + 0.01 * (-(o * o.log()).mean() - (sky * (1.0 - o).log()).mean()))
+                + 0.01 * (-(o * o.log()).mean() - (sky * (1.0 - o).log()).mean()) + 0.01 * vbar.abs().mean())
         loss.backward()
         return loss
 
@@ -482,9 +482,10 @@ def main():
         "mpix_per_s_fwd": mpix_fwd,
         "iters_per_s_recompute": args.steps / t_recompute,
         "iters_per_s_channels": args.steps / t_channels,
-        "channels_note": ("the same step with pvg_render_views(channels=True): depth sum T alpha z and opacity "
-                          "1 - final_T rendered and differentiated, with an inverse-depth L1 on 5% of the pixels "
-                          "and the opacity entropy term with a sky mask added to the loss (synthetic targets)"),
+        "channels_note": ("the same step with pvg_render_views(channels=True): depth sum T alpha z, opacity "
+                          "1 - final_T, velocity and staticness maps rendered; an inverse-depth L1 on 5% of the "
+                          "pixels, the opacity entropy term with a sky mask and the sparse velocity term added to "
+                          "the loss (synthetic targets)"),
         "lists": "kept from the forward (recompute='auto': they fit in a tenth of HBM)",
         "instances_per_render": {"rectangle": M, "listed": Lst, "adjoint_records": visited},
         "visible_per_render": n_vis,

@@ -112,6 +112,9 @@ typedef struct pvg_geom {
   float* rgb;         /* [n][3] colour; a channel clamped at zero is stored as -0 (the adjoint reads the clamp from the sign) */
   int32_t* radius;    /* [n] screen radius in pixels; 0 = invisible */
   uint32_t* tiles;    /* [n] number of tiles the Gaussian's rectangle touches */
+  float* feat;        /* [n][4] optional (may be NULL): mean velocity v~ = v exp(-beta / (2 l))
+                         (Sec. 3.4) and staticness rho = beta / l, written by the preprocess and
+                         read by the velocity and staticness channels */
 } pvg_geom;
 
 /* Tile instances: one (tile, Gaussian) pair per tile a visible Gaussian's
@@ -202,11 +205,20 @@ int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera*
  *   dL_ddepth  adjoint input: upstream gradient of `depth`;
  *   dL_dT      adjoint input: upstream gradient of final_T (the rendered
  *              opacity O = sum T_i alpha_i is 1 - final_T, so dL/dO enters as
- *              dL_dT = -dL/dO). */
+ *              dL_dT = -dL/dO);
+ *   vbar, rho  the velocity map and the staticness map (Sec. 3.4 and the
+ *              dynamic element analysis), blending each Gaussian's v~ and
+ *              rho from geom->feat, which must then be non-NULL (the preprocess
+ *              fills it); dL_dvbar and dL_drho their upstream gradients, which
+ *              reach v, beta and l. */
 typedef struct pvg_channels {
   float* depth;
   const float* dL_ddepth;
   const float* dL_dT;
+  float* vbar;             /* forward output [3][height][width]: sum T_i alpha_i v~_i (world frame) */
+  float* rho;              /* forward output [height][width]: sum T_i alpha_i rho_i */
+  const float* dL_dvbar;   /* adjoint input [3][height][width] */
+  const float* dL_drho;    /* adjoint input [height][width] */
 } pvg_channels;
 
 /* pvg_render_fwd that also writes the channels requested in `channels`

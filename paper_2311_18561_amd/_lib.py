@@ -48,12 +48,13 @@ class Frame(C.Structure):
 
 
 class Channels(C.Structure):
-    _fields_ = [("depth", C.c_void_p), ("dL_ddepth", C.c_void_p), ("dL_dT", C.c_void_p)]
+    _fields_ = [("depth", C.c_void_p), ("dL_ddepth", C.c_void_p), ("dL_dT", C.c_void_p), ("vbar", C.c_void_p),
+                ("rho", C.c_void_p), ("dL_dvbar", C.c_void_p), ("dL_drho", C.c_void_p)]
 
 
 class Geom(C.Structure):
     _fields_ = [("n", C.c_int64), ("xy", vp), ("depth", vp), ("conic_op", vp), ("rgb", vp), ("radius", vp),
-                ("tiles", vp)]
+                ("tiles", vp), ("feat", vp)]
 
 
 class Bins(C.Structure):

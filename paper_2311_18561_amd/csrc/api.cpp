@@ -221,7 +221,7 @@ hipEvent_t pool_event(size_t i) {
 }  // namespace
 
 static Geom to_geom(const pvg_geom* g) {
-  return Geom{g->xy, g->depth, g->conic_op, g->rgb, g->radius, g->tiles};
+  return Geom{g->xy, g->depth, g->conic_op, g->rgb, g->radius, g->tiles, g->feat};
 }
 
 }  // namespace pvg
@@ -305,7 +305,15 @@ int pvg_render_fwd_channels(const pvg_geom* geom, const pvg_bins* bins, const pv
   v.img = img;
   v.final_T = final_T;
   v.n_contrib = n_contrib;
-  if (channels) v.depth_img = channels->depth;
+  if (channels) {
+    v.depth_img = channels->depth;
+    v.vbar_img = channels->vbar;
+    v.rho_img = channels->rho;
+    if ((v.vbar_img || v.rho_img) && geom->n > 0 && !geom->feat) {
+      set_error("the velocity and staticness channels need geom.feat");
+      return PVG_ERR_INVALID;
+    }
+  }
   PVG_HIP(launch_render_fwd(single(v, geom->n), to_geom(geom), bins->vals, bins->ranges, bins->tile_cull != 0,
                             static_cast<hipStream_t>(stream)));
   return PVG_OK;
@@ -454,6 +462,12 @@ int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const
     if (channels) {
       v.dL_ddepth = channels[k].dL_ddepth;
       v.dL_dT = channels[k].dL_dT;
+      v.dL_dvbar = channels[k].dL_dvbar;
+      v.dL_drho = channels[k].dL_drho;
+      if ((v.dL_dvbar || v.dL_drho) && g->n > 0 && !geoms[k].feat) {
+        set_error("the velocity and staticness gradients need geom.feat of view %d", k);
+        return PVG_ERR_INVALID;
+      }
     }
     float* g2d = reinterpret_cast<float*>(base + slot_bytes * static_cast<size_t>(used_slots));
     ++used_slots;

@@ -37,6 +37,13 @@ __device__ __forceinline__ void preprocess_one(const View& v, int64_t i, const G
     geom.radius[gi] = 0;
     geom.tiles[gi] = 0u;
   }
+  if (geom.feat) {  // mean velocity v~ = v exp(-beta / (2 l)) and staticness rho = beta / l
+    const Scene& sc = v.s;
+    const float l = sc.period[i], beta = sc.beta[i];
+    const float e = exp_cr(-0.5f * (beta / l));
+    reinterpret_cast<float4*>(geom.feat)[gi] =
+        make_float4(sc.vel[i] * e, sc.vel[sc.n + i] * e, sc.vel[2 * sc.n + i] * e, beta / l);
+  }
 }
 
 __global__ void __launch_bounds__(256) k_preprocess(ViewSet vs, Geom geom, unsigned long long* dummy) {
@@ -74,7 +81,9 @@ __device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const
   const int64_t n = s.n;
   const int K = (s.degree + 1) * (s.degree + 1);
   const float dmx = g[0], dmy = g[1], dA = g[2], dB = g[3], dC = g[4], dop = g[5];
-  const float dz = g[9];  // the blended depth channel's gradient (0 without it), read before slot 9 is reused
+  // the blended channels' gradients (0 without them), read before slots 9.. are reused:
+  // camera depth z, mean velocity v~ and staticness rho
+  const float dz = g[9], dvb0 = g[10], dvb1 = g[11], dvb2 = g[12], drho = g[13];
   float dmr[3] = {0.0f, 0.0f, 0.0f};
 
   // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2), dir = u / |u|; its
@@ -209,6 +218,15 @@ __device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const
   }
   dtau += -cphi * vg;
   dl += (sphi / kTwoPi - (d / l) * cphi) * vg;
+  {  // v~ = v e with e = exp(-beta / (2 l)), rho = beta / l
+    const float e = expf(-0.5f * (beta / l));
+    const float vdot = vel[0] * dvb0 + vel[1] * dvb1 + vel[2] * dvb2;
+    acc.vel[0] += e * dvb0;
+    acc.vel[1] += e * dvb1;
+    acc.vel[2] += e * dvb2;
+    dbeta += vdot * e * (-0.5f / l) + drho / l;
+    dl += vdot * e * (0.5f * beta / (l * l)) - drho * beta / (l * l);
+  }
   const float qb = d / beta;
   const float eo = expf(-0.5f * (qb * qb));
   acc.op += eo * dop;

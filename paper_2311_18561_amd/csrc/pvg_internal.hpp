@@ -19,8 +19,8 @@ constexpr float kGuard = 1.3f;           // Jacobian guard band, in half fields 
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 0.0001f;
-constexpr int kRecFloats = 10;  // floats per adjoint record slot: 9 screen-space sums + d depth
-constexpr int kG2DStride = 12;           // floats per Gaussian in the screen-space gradient buffer
+constexpr int kRecFloats = 14;  // floats per adjoint record slot: 9 screen-space sums + 5 channel sums
+constexpr int kG2DStride = 16;           // floats per Gaussian in the screen-space gradient buffer
 
 // Parameters of one scene (device pointers).
 struct Scene {
@@ -51,10 +51,15 @@ struct View {
   float* depth_img;          // [H][W]
   const float* dL_ddepth;    // [H][W]
   const float* dL_dT;        // [H][W]
+  float* vbar_img;           // [3][H][W] velocity map
+  float* rho_img;            // [H][W] staticness map
+  const float* dL_dvbar;     // [3][H][W]
+  const float* dL_drho;      // [H][W]
 };
 
 struct Geom {
   float* xy; float* depth; float* conic_op; float* rgb; int32_t* radius; uint32_t* tiles;
+  float* feat;  // [n][4] optional: mean velocity v~ and staticness rho
 };
 
 // Views of a launch: either one view passed by value or a device table.

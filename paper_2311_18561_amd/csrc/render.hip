@@ -74,6 +74,23 @@ __device__ __forceinline__ void wave_sum10(const float a[10], float out[3]) {
   }
 }
 
+// The same for sixteen values: out[k] (k < 4) of the lanes of row r holds the
+// wave total of value 4k + 2(r & 1) + (r >> 1).
+__device__ __forceinline__ void wave_sum16(const float a[16], float out[4]) {
+  float h[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) h[m] = swap_sum32(a[2 * m], a[2 * m + 1]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[k] = swap_sum16(h[2 * k], h[2 * k + 1]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    out[k] = dpp_add(out[k], 0x128);  // row_ror:8
+    out[k] = dpp_add(out[k], 0x124);  // row_ror:4
+    out[k] = dpp_add(out[k], 0x4e);   // quad_perm [2,3,0,1]
+    out[k] = dpp_add(out[k], 0xb1);   // quad_perm [1,0,3,2]
+  }
+}
+
 __device__ __forceinline__ int wave_max(int x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
@@ -108,16 +125,18 @@ __device__ __forceinline__ float pair_power(float dx, float dy, float A, float B
 
 constexpr int kPix = 4;  // pixels per lane
 
-// kDepth: also blend each Gaussian's camera depth into v.depth_img (the
-// flexible rendering of Sec. 3.1, with the depth in place of the colour).
-template <bool kCount, bool kCulled, bool kDepth>
+// kCh: also blend each Gaussian's camera depth, mean velocity and
+// staticness into the channels the view asks for (the flexible rendering of
+// Sec. 3.1, with these in place of the colour).
+template <bool kCount, bool kCulled, bool kCh>
 __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const uint32_t* __restrict__ vals,
                                                    const uint32_t* __restrict__ ranges,
                                                    unsigned long long* pair_counter) {
   __shared__ float2 s_xy[64];
   __shared__ float4 s_co[64];
   __shared__ float4 s_rgb[64];  // rgb and the list position (as int bits)
-  __shared__ float s_z[kDepth ? 64 : 1];
+  __shared__ float s_z[kCh ? 64 : 1];
+  __shared__ float4 s_fv[kCh ? 64 : 1];  // v~ and rho
   const int64_t ntiles = live_tiles(vs);
   const int64_t tile = xcd_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
@@ -131,12 +150,13 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
   float X0, X1, Y0, Y1;
   tile_bounds(tx, ty, v.W, v.H, X0, X1, Y0, Y1);
   const uint64_t lt = (1ull << lane) - 1ull;
-  float T[kPix], Cr[kPix], Cg[kPix], Cb[kPix], Dz[kPix];
+  float T[kPix], Cr[kPix], Cg[kPix], Cb[kPix], Dz[kPix], V0[kPix], V1[kPix], V2[kPix], Rh[kPix];
   int last[kPix];
   bool act[kPix];
 #pragma unroll
   for (int k = 0; k < kPix; ++k) {
-    T[k] = 1.0f; Cr[k] = 0.0f; Cg[k] = 0.0f; Cb[k] = 0.0f; Dz[k] = 0.0f; last[k] = 0;
+    T[k] = 1.0f; Cr[k] = 0.0f; Cg[k] = 0.0f; Cb[k] = 0.0f; last[k] = 0;
+    Dz[k] = 0.0f; V0[k] = 0.0f; V1[k] = 0.0f; V2[k] = 0.0f; Rh[k] = 0.0f;
     act[k] = px < v.W && py0 + 4 * k < v.H;
   }
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
@@ -148,13 +168,17 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
     float2 m;
     float4 co, c;
     float z = 0.0f;
+    float4 fv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (idx < end) {
       const uint32_t g = vals[idx];
       m = reinterpret_cast<const float2*>(geom.xy)[g];
       co = reinterpret_cast<const float4*>(geom.conic_op)[g];
       c = make_float4(geom.rgb[3 * g], geom.rgb[3 * g + 1], geom.rgb[3 * g + 2],
                       __int_as_float(static_cast<int>(idx - start) + 1));
-      if (kDepth) z = geom.depth[g];
+      if (kCh) {
+        z = geom.depth[g];
+        if (geom.feat) fv = reinterpret_cast<const float4*>(geom.feat)[g];
+      }
       keep = kCulled || tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1);
     }
     const uint64_t km = __ballot(keep);
@@ -163,7 +187,10 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
       s_xy[slot] = m;
       s_co[slot] = co;
       s_rgb[slot] = c;
-      if (kDepth) s_z[slot] = z;
+      if (kCh) {
+        s_z[slot] = z;
+        s_fv[slot] = fv;
+      }
     }
     __syncthreads();
     const int cnt = __popcll(km);
@@ -172,7 +199,8 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
       const float2 gm = s_xy[j];
       const float4 gc = s_co[j];
       const float4 cc = s_rgb[j];
-      const float gz = kDepth ? s_z[j] : 0.0f;
+      const float gz = kCh ? s_z[j] : 0.0f;
+      const float4 gv = kCh ? s_fv[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       const int pos = __float_as_int(cc.w);
 #pragma unroll
       for (int k = 0; k < kPix; ++k) {
@@ -188,7 +216,13 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
         Cr[k] = fmaf(cc.x, w, Cr[k]);
         Cg[k] = fmaf(cc.y, w, Cg[k]);
         Cb[k] = fmaf(cc.z, w, Cb[k]);
-        if (kDepth) Dz[k] = fmaf(gz, w, Dz[k]);
+        if (kCh) {
+          Dz[k] = fmaf(gz, w, Dz[k]);
+          V0[k] = fmaf(gv.x, w, V0[k]);
+          V1[k] = fmaf(gv.y, w, V1[k]);
+          V2[k] = fmaf(gv.z, w, V2[k]);
+          Rh[k] = fmaf(gv.w, w, Rh[k]);
+        }
         T[k] = use ? Tn : T[k];
         last[k] = use ? pos : last[k];
         act[k] = act[k] && !stop;
@@ -207,7 +241,15 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
       v.img[2 * HW + o] = Cb[k] + T[k] * v.bg[2];
       v.final_T[o] = T[k];
       v.n_contrib[o] = last[k];
-      if (kDepth) v.depth_img[o] = Dz[k];
+      if (kCh) {
+        if (v.depth_img) v.depth_img[o] = Dz[k];
+        if (v.vbar_img) {
+          v.vbar_img[o] = V0[k];
+          v.vbar_img[HW + o] = V1[k];
+          v.vbar_img[2 * HW + o] = V2[k];
+        }
+        if (v.rho_img) v.rho_img[o] = Rh[k];
+      }
     }
   }
   if (kCount && pair_counter) {
@@ -218,8 +260,9 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
   }
 }
 
-// kCh: the view also carries upstream gradients of the depth channel and/or
-// of final_T (either may be null); records then hold a tenth sum, d depth.
+// kCh: the view also carries upstream gradients of the depth, velocity and
+// staticness channels and/or of final_T (each may be null); records then hold
+// five more sums (d z, d v~, d rho).
 template <bool kCount, bool kCulled, bool kCh>
 __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists lists, float* rec,
                                                    uint8_t* vis, unsigned long long* pair_counter) {
@@ -236,8 +279,9 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
   __shared__ uint32_t s_g[64];
   __shared__ float s_acc[64][kRecFloats];
   __shared__ float s_z[kCh ? 64 : 1];
+  __shared__ float4 s_fv[kCh ? 64 : 1];
   __shared__ int s_any[64];
-  constexpr int kSums = kCh ? 10 : 9;
+  constexpr int kSums = kCh ? 14 : 9;  // also the record stride
   const int64_t ntiles = live_tiles(vs);
   const int64_t tile = xcd_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
@@ -252,14 +296,15 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
   tile_bounds(tx, ty, v.W, v.H, X0, X1, Y0, Y1);
   const uint64_t lt = (1ull << lane) - 1ull;
   const int64_t HW = static_cast<int64_t>(v.W) * v.H;
-  float T[kPix], rr[kPix], gr[kPix], gg[kPix], gb[kPix], gd[kPix];
+  float T[kPix], rr[kPix], gr[kPix], gg[kPix], gb[kPix];
+  float gd[kPix], gv0[kPix], gv1[kPix], gv2[kPix], gh[kPix];  // channel gradients: z, v~, rho
   int last[kPix];
   int lmax = 0;
 #pragma unroll
   for (int k = 0; k < kPix; ++k) {
     const int py = py0 + 4 * k;
     float gt = 0.0f;
-    gd[k] = 0.0f;
+    gd[k] = 0.0f; gv0[k] = 0.0f; gv1[k] = 0.0f; gv2[k] = 0.0f; gh[k] = 0.0f;
     if (px < v.W && py < v.H) {
       const int64_t o = static_cast<int64_t>(py) * v.W + px;
       T[k] = v.final_T[o];
@@ -270,6 +315,12 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       if (kCh) {
         if (v.dL_ddepth) gd[k] = v.dL_ddepth[o];
         if (v.dL_dT) gt = v.dL_dT[o];
+        if (v.dL_dvbar) {
+          gv0[k] = v.dL_dvbar[o];
+          gv1[k] = v.dL_dvbar[HW + o];
+          gv2[k] = v.dL_dvbar[2 * HW + o];
+        }
+        if (v.dL_drho) gh[k] = v.dL_drho[o];
       }
     } else {
       T[k] = 1.0f; last[k] = 0; gr[k] = 0.0f; gg[k] = 0.0f; gb[k] = 0.0f;
@@ -290,12 +341,16 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
     float2 m;
     float4 co, c;
     float z = 0.0f;
+    float4 fv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (lane < hi - lo) {
       g = vals[start + lo + lane];
       m = reinterpret_cast<const float2*>(geom.xy)[g];
       co = reinterpret_cast<const float4*>(geom.conic_op)[g];
       c = make_float4(geom.rgb[3 * g], geom.rgb[3 * g + 1], geom.rgb[3 * g + 2], __int_as_float(lo + lane));
-      if (kCh) z = geom.depth[g];
+      if (kCh) {
+        z = geom.depth[g];
+        if (geom.feat) fv = reinterpret_cast<const float4*>(geom.feat)[g];
+      }
       keep = kCulled || tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1);
     }
     const uint64_t km = __ballot(keep);
@@ -305,7 +360,10 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       s_xy[slot] = m;
       s_co[slot] = co;
       s_rgb[slot] = c;
-      if (kCh) s_z[slot] = z;
+      if (kCh) {
+        s_z[slot] = z;
+        s_fv[slot] = fv;
+      }
     }
     __syncthreads();
     const int cnt = __popcll(km);
@@ -314,6 +372,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       const float4 gc = s_co[j];
       const float4 cc = s_rgb[j];
       const float gz = kCh ? s_z[j] : 0.0f;
+      const float4 gf = kCh ? s_fv[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       const int pos = __float_as_int(cc.w);
       // The lane's four pixels share the column offset dx.  Per pixel the
       // power gradient is gp = alpha dL/dalpha (zero where the pair is unused
@@ -322,7 +381,8 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       // An unused pair takes alpha = 0, which leaves T (rcp(1) is exact)
       // and the colour behind it unchanged, so no selects are needed.
       const float dx = gm.x - fpx;
-      float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, cr = 0.0f, cgr = 0.0f, cb = 0.0f, cz = 0.0f;
+      float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, cr = 0.0f, cgr = 0.0f, cb = 0.0f;
+      float cz = 0.0f, cv0 = 0.0f, cv1 = 0.0f, cv2 = 0.0f, ch = 0.0f;
       bool any = false;
 #pragma unroll
       for (int k = 0; k < kPix; ++k) {
@@ -338,13 +398,25 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
         const float om = 1.0f - au;
         T[k] *= __builtin_amdgcn_rcpf(om);
         float cg = cc.x * gr[k] + cc.y * gg[k] + cc.z * gb[k];
-        if (kCh) cg = fmaf(gz, gd[k], cg);  // the depth channel blends like a colour
+        if (kCh) {  // the channels blend like a colour
+          cg = fmaf(gz, gd[k], cg);
+          cg = fmaf(gf.x, gv0[k], cg);
+          cg = fmaf(gf.y, gv1[k], cg);
+          cg = fmaf(gf.z, gv2[k], cg);
+          cg = fmaf(gf.w, gh[k], cg);
+        }
         const float dal = T[k] * (cg - rr[k]);
         const float w = au * T[k];
         cr = fmaf(w, gr[k], cr);
         cgr = fmaf(w, gg[k], cgr);
         cb = fmaf(w, gb[k], cb);
-        if (kCh) cz = fmaf(w, gd[k], cz);
+        if (kCh) {
+          cz = fmaf(w, gd[k], cz);
+          cv0 = fmaf(w, gv0[k], cv0);
+          cv1 = fmaf(w, gv1[k], cv1);
+          cv2 = fmaf(w, gv2[k], cv2);
+          ch = fmaf(w, gh[k], ch);
+        }
         rr[k] = fmaf(au, cg, om * rr[k]);
         const float gp = (raw > kAlphaMax ? 0.0f : au) * dal;
         s0 += gp;
@@ -354,7 +426,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       // power = -(A dx^2 + C dy^2)/2 - B dx dy and d(mean) = d(dx, dy); the
       // exponential's own gradient, sum G dL/dalpha over unclamped pairs, is
       // s0 / o (there alpha = o G)
-      float a[10];
+      float a[16];
       {
         const float sx = dx * s0;
         a[0] = -(gc.x * sx + gc.y * s1);
@@ -366,18 +438,37 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
         a[6] = cr;
         a[7] = cgr;
         a[8] = cb;
-        a[9] = cz;  // 0 without the depth channel
+        a[9] = cz;  // the channel sums are 0 without channels
+        a[10] = cv0;
+        a[11] = cv1;
+        a[12] = cv2;
+        a[13] = ch;
+        a[14] = 0.0f;
+        a[15] = 0.0f;
       }
       const bool wany = __any(any);
       if (wany) {
-        float red[3];
-        wave_sum10(a, red);
-        if ((lane & 15) == 0) {
-          const int r = lane >> 4;
+        if (kCh) {
+          float red[4];
+          wave_sum16(a, red);
+          if ((lane & 15) == 0) {
+            const int r = lane >> 4;
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const int q = 4 * k + 2 * (r & 1) + (r >> 1);
-            if (q < kSums) s_acc[j][q] = red[k];
+            for (int k = 0; k < 4; ++k) {
+              const int q = 4 * k + 2 * (r & 1) + (r >> 1);
+              if (q < kSums) s_acc[j][q] = red[k];
+            }
+          }
+        } else {
+          float red[3];
+          wave_sum10(a, red);
+          if ((lane & 15) == 0) {
+            const int r = lane >> 4;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              const int q = 4 * k + 2 * (r & 1) + (r >> 1);
+              if (q < kSums) s_acc[j][q] = red[k];
+            }
           }
         }
       }
@@ -402,7 +493,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
         e = first[g] + static_cast<uint32_t>((ty - rect[1]) * (rect[2] - rect[0]) + (tx - rect[0]));
       }
       if (static_cast<int64_t>(e) < lists.capacity) {
-        float* dst = rec + kRecFloats * static_cast<int64_t>(e);
+        float* dst = rec + kSums * static_cast<int64_t>(e);
 #pragma unroll
         for (int q = 0; q < kSums; ++q) dst[q] = s_acc[slot][q];
         vis[e] = 1;
@@ -423,9 +514,9 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
 // pairs contiguous.
 template <int kSums>
 __device__ __forceinline__ void gather_range(uint32_t e0, uint32_t cnt, const float* __restrict__ rec,
-                                             const uint8_t* __restrict__ vis, float acc[10]) {
+                                             const uint8_t* __restrict__ vis, float acc[16]) {
 #pragma unroll
-  for (int c = 0; c < 10; ++c) acc[c] = 0.0f;
+  for (int c = 0; c < 16; ++c) acc[c] = 0.0f;
   const uint32_t e1 = e0 + cnt;
   for (uint32_t b = e0 & ~15u; b < e1; b += 16) {
     const uint4 w = *reinterpret_cast<const uint4*>(vis + b);
@@ -434,7 +525,7 @@ __device__ __forceinline__ void gather_range(uint32_t e0, uint32_t cnt, const fl
     for (int j = 0; j < 16; ++j) {
       const uint32_t e = b + static_cast<uint32_t>(j);
       if (((words[j >> 2] >> (8 * (j & 3))) & 0xffu) && e >= e0 && e < e1) {
-        const float* r = rec + kRecFloats * static_cast<int64_t>(e);
+        const float* r = rec + kSums * static_cast<int64_t>(e);  // records are kSums floats apart
 #pragma unroll
         for (int q = 0; q < kSums; ++q) acc[q] += r[q];
       }
@@ -455,9 +546,9 @@ template <int kSums>
 __device__ __forceinline__ void gather_range_wave(uint32_t e0, uint32_t cnt, int lane,
                                                   const float* __restrict__ rec,
                                                   const uint8_t* __restrict__ vis, uint32_t* idx,
-                                                  float acc[10]) {
+                                                  float acc[16]) {
 #pragma unroll
-  for (int c = 0; c < 10; ++c) acc[c] = 0.0f;
+  for (int c = 0; c < 16; ++c) acc[c] = 0.0f;
   const uint32_t e1 = e0 + cnt;
   for (uint32_t b = e0 & ~15u; b < e1; b += 1024) {
     const uint32_t mb = b + 16u * static_cast<uint32_t>(lane);
@@ -490,7 +581,7 @@ __device__ __forceinline__ void gather_range_wave(uint32_t e0, uint32_t cnt, int
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int k = lane; k < total; k += 64) {
-      const float* r = rec + kRecFloats * static_cast<int64_t>(idx[k]);
+      const float* r = rec + kSums * static_cast<int64_t>(idx[k]);
 #pragma unroll
       for (int q = 0; q < kSums; ++q) acc[q] += r[q];
     }
@@ -503,12 +594,13 @@ __device__ __forceinline__ void gather_range_wave(uint32_t e0, uint32_t cnt, int
 // Per visible Gaussian: the index range of its pairs (first[g] and the
 // listed count: its rectangle's tiles, or, for culled lists, up to the end
 // of its last row) and the sum of the flagged records.
-// kCh: the records hold a tenth sum (d depth); g2d slot 9 receives it, or 0.
+// kCh: the records hold the five channel sums too (d z, d v~, d rho); g2d
+// slots 9..13 receive them, or zeros.
 template <bool kCulled, bool kCh>
 __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, Lists lists,
                                                      const float* __restrict__ rec,
                                                      const uint8_t* __restrict__ vis, float* g2d) {
-  constexpr int kSums = kCh ? 10 : 9;
+  constexpr int kSums = kCh ? 14 : 9;
   __shared__ uint32_t s_queue[256][3];
   __shared__ uint32_t s_idx[4][1024];  // per wave: flagged pair indices of one round
   __shared__ int s_qn;
@@ -537,11 +629,11 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, List
     if (static_cast<uint64_t>(e0) > cap || static_cast<uint64_t>(cnt) > cap - e0) cnt = 0;
   }
   if (visible && cnt <= kShortRange) {
-    float acc[10];
+    float acc[16];
     gather_range<kSums>(e0, cnt, rec, vis, acc);
     float* dst = g2d + kG2DStride * gi;
 #pragma unroll
-    for (int c = 0; c < 10; ++c) dst[c] = acc[c];
+    for (int c = 0; c < 14; ++c) dst[c] = acc[c];
   } else if (visible) {
     const int q = atomicAdd(&s_qn, 1);
     s_queue[q][0] = static_cast<uint32_t>(gi);
@@ -552,16 +644,16 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, List
   const int qn = s_qn;
   for (int qi = wid; qi < qn; qi += 4) {
     const uint32_t g = s_queue[qi][0];
-    float acc[10], red[3];
+    float acc[16], red[4];
     gather_range_wave<kSums>(s_queue[qi][1], s_queue[qi][2], lane, rec, vis, s_idx[wid], acc);
-    wave_sum10(acc, red);
+    wave_sum16(acc, red);
     if ((lane & 15) == 0) {
       const int r = lane >> 4;
       float* dst = g2d + kG2DStride * static_cast<int64_t>(g);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < 4; ++k) {
         const int qq = 4 * k + 2 * (r & 1) + (r >> 1);
-        if (qq < 10) dst[qq] = red[k];
+        if (qq < 14) dst[qq] = red[k];
       }
     }
   }
@@ -573,7 +665,8 @@ hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t
   StageScope scope(PVG_STAGE_RENDER_FWD, s);
   const dim3 grid(static_cast<unsigned>(((vs.total_tiles + 7) / 8) * 8));
   unsigned long long* cnt = profile_work_counter(PVG_STAGE_RENDER_FWD);
-  const bool depth = !vs.table && vs.one.depth_img;  // channels are single-view only
+  // channels are single-view only
+  const bool depth = !vs.table && (vs.one.depth_img || vs.one.vbar_img || vs.one.rho_img);
   auto k = depth ? (cnt ? (culled ? k_render_fwd<true, true, true> : k_render_fwd<true, false, true>)
                         : (culled ? k_render_fwd<false, true, true> : k_render_fwd<false, false, true>))
                  : (cnt ? (culled ? k_render_fwd<true, true, false> : k_render_fwd<true, false, false>)
@@ -587,7 +680,7 @@ hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const Lists& l
   if (vs.total_tiles == 0) return hipSuccess;
   const bool culled = lists.culled;
   // channel gradients are single-view only
-  const bool ch = !vs.table && (vs.one.dL_ddepth || vs.one.dL_dT);
+  const bool ch = !vs.table && (vs.one.dL_ddepth || vs.one.dL_dT || vs.one.dL_dvbar || vs.one.dL_drho);
   {
     StageScope scope(PVG_STAGE_RENDER_BWD, s);
     // clear the flags (a fill kernel: no memset node in a captured graph)

@@ -89,8 +89,10 @@ def frame_struct(t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0)) -> L.Frame:
 class Geom:
     """Per-Gaussian projected record (device tensors) and its ctypes view."""
 
-    def __init__(self, n, device):
+    def __init__(self, n, device, feat=False):
         self.n = n
+        # [n][4] mean velocity v~ and staticness rho, for the velocity and staticness channels
+        self.feat = torch.empty((n, 4), dtype=torch.float32, device=device) if feat else None
         self.xy = torch.empty((n, 2), dtype=torch.float32, device=device)
         self.depth = torch.empty(n, dtype=torch.float32, device=device)
         self.conic_op = torch.empty((n, 4), dtype=torch.float32, device=device)
@@ -99,13 +101,15 @@ class Geom:
         self.tiles = torch.empty(n, dtype=torch.int32, device=device)  # uint32 counts
 
     def tensors(self):
-        return (self.xy, self.depth, self.conic_op, self.rgb, self.radius, self.tiles)
+        t = (self.xy, self.depth, self.conic_op, self.rgb, self.radius, self.tiles)
+        return t if self.feat is None else t + (self.feat,)
 
     def struct(self) -> L.Geom:
         g = L.Geom()
         g.n = self.n
         for f in ("xy", "depth", "conic_op", "rgb", "radius", "tiles"):
             setattr(g, f, getattr(self, f).data_ptr())
+        g.feat = None if self.feat is None else self.feat.data_ptr()
         return g
 
 
@@ -154,8 +158,8 @@ def workspace(n, width, height, capacity) -> L.WsSizes:
     return ws
 
 
-def preprocess(params, n, degree, cam: L.Camera, frame: L.Frame) -> Geom:
-    geom = Geom(n, params[0].device)
+def preprocess(params, n, degree, cam: L.Camera, frame: L.Frame, feat: bool = False) -> Geom:
+    geom = Geom(n, params[0].device, feat)
     g = gaussians_struct(params, n, degree)
     gs = geom.struct()
     L.check(L.load().pvg_preprocess(C.byref(g), C.byref(cam), C.byref(frame), C.byref(gs), _stream_handle()))
@@ -215,22 +219,25 @@ def bin_sort_nosync(geom: Geom, cam: L.Camera, capacity: int, tile_cull: bool = 
     return bins
 
 
-def render_fwd(geom: Geom, bins: Bins, cam: L.Camera, frame: L.Frame, out=None, depth=None):
+def render_fwd(geom: Geom, bins: Bins, cam: L.Camera, frame: L.Frame, out=None, depth=None, vbar=None,
+               rho=None):
     """Composite one view; `out` (optional, contiguous [3,H,W] float32)
-    receives the image and `depth` (optional, contiguous [H,W] float32) the
-    blended camera depth sum T alpha z."""
+    receives the image, `depth` (optional, contiguous [H,W] float32) the
+    blended camera depth sum T alpha z, `vbar` ([3,H,W]) and `rho` ([H,W])
+    the velocity and staticness maps (these need a Geom with feat)."""
     dev = geom.xy.device
     H, W = int(cam.height), int(cam.width)
     img = torch.empty((3, H, W), dtype=torch.float32, device=dev) if out is None else out
     final_T = torch.empty((H, W), dtype=torch.float32, device=dev)
     n_contrib = torch.empty((H, W), dtype=torch.int32, device=dev)
     gs, bs = geom.struct(), bins.struct()
-    if depth is None:
+    if depth is None and vbar is None and rho is None:
         L.check(L.load().pvg_render_fwd(C.byref(gs), C.byref(bs), C.byref(cam), C.byref(frame), _p(img),
                                         _p(final_T), _p(n_contrib), _stream_handle()))
     else:
-        assert depth.is_contiguous() and depth.shape == (H, W) and depth.dtype == torch.float32
-        ch = L.Channels(depth.data_ptr(), None, None)
+        for t, shp in ((depth, (H, W)), (vbar, (3, H, W)), (rho, (H, W))):
+            assert t is None or (t.is_contiguous() and t.shape == shp and t.dtype == torch.float32)
+        ch = L.Channels(_p(depth), None, None, _p(vbar), _p(rho), None, None)
         L.check(L.load().pvg_render_fwd_channels(C.byref(gs), C.byref(bs), C.byref(cam), C.byref(frame), _p(img),
                                                  _p(final_T), _p(n_contrib), C.byref(ch), _stream_handle()))
     return img, final_T, n_contrib
@@ -289,19 +296,21 @@ class _BwdViewsArgs:
                                                  max(v[3].capacity for v in views), C.byref(size)))
         self.tmp_bytes = int(size.value)
 
-    def call(self, dev, dimgs, grads, accumulate, ddepths=None, dTs=None):
-        """ddepths / dTs (optional, per view [H,W] or None): upstream gradients
-        of the depth channel and of final_T."""
+    def call(self, dev, dimgs, grads, accumulate, ddepths=None, dTs=None, dvbars=None, drhos=None):
+        """ddepths / dTs / dvbars / drhos (optional, per view or None):
+        upstream gradients of the depth channel, final_T, the velocity map
+        [3,H,W] and the staticness map."""
         gg = L.GaussiansGrad()
         for name, t in zip(FIELDS, grads):
             setattr(gg, name, t.data_ptr())
-        ddepths = list(ddepths) if ddepths is not None else [None] * self.nv
-        dTs = list(dTs) if dTs is not None else [None] * self.nv
-        chan = any(d is not None for d in ddepths + dTs)
+        lists = [list(x) if x is not None else [None] * self.nv for x in (ddepths, dTs, dvbars, drhos)]
+        ddepths, dTs, dvbars, drhos = lists
+        has = [any(x[k] is not None for x in lists) for k in range(self.nv)]
+        chan = any(has)
         dimgs = list(dimgs)
         if chan:  # a view with only channel gradients still needs an image gradient (zeros)
             for k in range(self.nv):
-                if dimgs[k] is None and (ddepths[k] is not None or dTs[k] is not None):
+                if dimgs[k] is None and has[k]:
                     dimgs[k] = torch.zeros((3, int(self.cams[k].height), int(self.cams[k].width)),
                                            dtype=torch.float32, device=dev)
         dls = [None if d is None else d.contiguous() for d in dimgs]
@@ -313,10 +322,9 @@ class _BwdViewsArgs:
                                                   1 if accumulate else 0, _p(tmp), int(tmp.numel()),
                                                   _stream_handle()))
             return grads
-        dd = [None if d is None else d.contiguous() for d in ddepths]
-        dt = [None if d is None else d.contiguous() for d in dTs]
-        ch = (L.Channels * self.nv)(*[L.Channels(None, None if a is None else a.data_ptr(),
-                                                 None if b is None else b.data_ptr()) for a, b in zip(dd, dt)])
+        cont = [[None if d is None else d.contiguous() for d in x] for x in lists]
+        ch = (L.Channels * self.nv)(*[L.Channels(None, _p(a), _p(b), None, None, _p(c), _p(d))
+                                      for a, b, c, d in zip(*cont)])
         L.check(L.load().pvg_render_bwd_views_channels(C.byref(self.g), self.nv, self.cams, self.frames, self.geoms,
                                                        self.bins, self.f_t, self.n_c, d_l, ch, C.byref(gg),
                                                        1 if accumulate else 0, _p(tmp), int(tmp.numel()),
@@ -324,16 +332,17 @@ class _BwdViewsArgs:
         return grads
 
 
-def render_bwd_views(params, n, degree, views, grads=None, accumulate=False, ddepths=None, dTs=None):
+def render_bwd_views(params, n, degree, views, grads=None, accumulate=False, ddepths=None, dTs=None, dvbars=None,
+                     drhos=None):
     """One adjoint call for several views of the same Gaussians:
     views = [(cam, frame, geom, bins, final_T, n_contrib, dL_dimg or None)];
     the per-Gaussian chain rule of all views is summed in registers and the
-    gradient written (or added) once.  ddepths / dTs: optional per-view
-    upstream gradients of the depth channel and of final_T."""
+    gradient written (or added) once.  ddepths / dTs / dvbars / drhos:
+    optional per-view upstream gradients of the channels and of final_T."""
     if grads is None:
         grads = [torch.empty_like(p) for p in params]
     args = _BwdViewsArgs(params, n, degree, [v[:6] for v in views])
-    return args.call(params[0].device, [v[6] for v in views], grads, accumulate, ddepths, dTs)
+    return args.call(params[0].device, [v[6] for v in views], grads, accumulate, ddepths, dTs, dvbars, drhos)
 
 
 def render(params, cam: dict, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), tile_cull=True):
@@ -418,7 +427,7 @@ def _record(stream):
     return ev
 
 
-def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=None):
+def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=None, vbars=None, rhos=None):
     """Bin and composite view k on lane k mod VIEW_STREAMS, where lane 0 is
     the caller's stream and the others are side streams forked from it and
     joined back into it (the views' latency-bound sort and scan kernels
@@ -434,14 +443,16 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
     outgrew its cached capacity is redone.  With `stacked` ([V,3,H,W],
     allocated on the caller's stream) view k's image is written into
     stacked[k]; with `depths` ([V,H,W], the same) its depth channel into
-    depths[k]."""
+    depths[k], and likewise the velocity and staticness maps into vbars
+    ([V,3,H,W]) and rhos ([V,H,W])."""
     dev = params[0].device
     main = torch.cuda.current_stream(dev)
     side = _streams(dev)
     lanes = [main, *side[:-1]]
     cams = [camera_struct(cam) for cam, *_ in views]
     frames = [frame_struct(t, dt, mode, bg) for _, t, dt, mode, bg in views]
-    geoms = [Geom(n, dev) for _ in views]  # on the caller's stream; every user is joined back into it
+    feat = vbars is not None or rhos is not None
+    geoms = [Geom(n, dev, feat) for _ in views]  # on the caller's stream; every user is joined back into it
     nl = len(lanes)
     bounds, waits = _view_plan(len(views), nl)
     preprocess_views(params, n, degree, cams[:bounds[1]], frames[:bounds[1]], geoms[:bounds[1]])
@@ -468,7 +479,8 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
             fe = torch.cuda.Event()
             fe.record(st)
             out = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k],
-                             None if depths is None else depths[k])
+                             None if depths is None else depths[k], None if vbars is None else vbars[k],
+                             None if rhos is None else rhos[k])
             ev = None
             if st is not main:
                 ev = torch.cuda.Event()
@@ -492,7 +504,8 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
             bins = bin_sort(geom, c, tile_cull=tile_cull)
             plans[k][3] = bins
             outs[k] = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k],
-                                 None if depths is None else depths[k])
+                                 None if depths is None else depths[k], None if vbars is None else vbars[k],
+                                 None if rhos is None else rhos[k])
     return plans, outs
 
 
@@ -533,13 +546,15 @@ class PVGRenderViews(torch.autograd.Function):
     def forward(ctx, views, recompute, tile_cull, stack, channels, *tensors):
         params, n, degree = _check_params(list(tensors))
         dev = params[0].device
-        stacked, depths = None, None
+        stacked = depths = vbars = rhos = None
         if stack:
-            H, W = int(views[0][0]["height"]), int(views[0][0]["width"])
-            stacked = torch.empty((len(views), 3, H, W), dtype=torch.float32, device=dev)
+            V, H, W = len(views), int(views[0][0]["height"]), int(views[0][0]["width"])
+            stacked = torch.empty((V, 3, H, W), dtype=torch.float32, device=dev)
             if channels:
-                depths = torch.empty((len(views), H, W), dtype=torch.float32, device=dev)
-        plans, outs = _forward_views(params, n, degree, views, tile_cull, stacked, depths)
+                depths = torch.empty((V, H, W), dtype=torch.float32, device=dev)
+                vbars = torch.empty((V, 3, H, W), dtype=torch.float32, device=dev)
+                rhos = torch.empty((V, H, W), dtype=torch.float32, device=dev)
+        plans, outs = _forward_views(params, n, degree, views, tile_cull, stacked, depths, vbars, rhos)
         if recompute == "auto":
             kept_bytes = sum(_bins_bytes(b) for _, _, _, b in plans)
             recompute = kept_bytes > KEEP_FRACTION * torch.cuda.get_device_properties(dev).total_memory
@@ -553,8 +568,8 @@ class PVGRenderViews(torch.autograd.Function):
         ctx.save_for_backward(*saved)
         ctx.stack = stack
         ctx.channels = channels
-        if channels:  # the images, the depth channels and final_T, each stacked over the views
-            return stacked, depths, torch.stack([T for _, T, _ in outs])
+        if channels:  # images, depth, final_T, velocity and staticness maps, each stacked over the views
+            return stacked, depths, torch.stack([T for _, T, _ in outs]), vbars, rhos
         if stack:
             return stacked
         return tuple(img for img, _, _ in outs)
@@ -562,11 +577,10 @@ class PVGRenderViews(torch.autograd.Function):
     @staticmethod
     def backward(ctx, *dimgs):
         n, degree, recompute, tile_cull, plan = ctx.meta
-        ddepths = dTs = None
+        ddepths = dTs = dvbars = drhos = None
         if ctx.channels:
-            d_depth, d_T = dimgs[1], dimgs[2]
-            ddepths = [None if d_depth is None else d_depth[k] for k in range(len(plan))]
-            dTs = [None if d_T is None else d_T[k] for k in range(len(plan))]
+            ddepths, dTs, dvbars, drhos = ([None if d is None else d[k] for k in range(len(plan))]
+                                           for d in dimgs[1:5])
         if ctx.stack:
             d = dimgs[0]
             dimgs = tuple(None if d is None else d[k] for k in range(len(plan)))
@@ -578,21 +592,21 @@ class PVGRenderViews(torch.autograd.Function):
             # same inputs give the forward's lists bit for bit, within its capacity
             first = True
             for k, (c, f, cap) in enumerate(plan):
-                dd = None if ddepths is None else ddepths[k]
-                dt = None if dTs is None else dTs[k]
-                if dimgs[k] is None and dd is None and dt is None:
+                chk = [None if x is None else x[k] for x in (ddepths, dTs, dvbars, drhos)]
+                if dimgs[k] is None and all(x is None for x in chk):
                     continue
-                geom = preprocess(params, n, degree, c, f)
+                geom = preprocess(params, n, degree, c, f, feat=ctx.channels)
                 bins = bin_sort_nosync(geom, c, cap, tile_cull)
                 render_bwd_views(params, n, degree, [(c, f, geom, bins, saved[9 + 2 * k], saved[10 + 2 * k],
                                                       dimgs[k])], grads=grads, accumulate=not first,
-                                 ddepths=[dd], dTs=[dt])
+                                 ddepths=[chk[0]], dTs=[chk[1]], dvbars=[chk[2]], drhos=[chk[3]])
                 first = False
             if first:
                 for gr in grads:
                     gr.zero_()
         else:  # the kept lists, final_T and n_contrib, with the arguments built in the forward
-            ctx.bwd.call(params[0].device, dimgs, grads, accumulate=False, ddepths=ddepths, dTs=dTs)
+            ctx.bwd.call(params[0].device, dimgs, grads, accumulate=False, ddepths=ddepths, dTs=dTs, dvbars=dvbars,
+                         drhos=drhos)
         return (None, None, None, None, None, *grads)
 
 
@@ -604,15 +618,17 @@ def pvg_render_views(params, views, recompute="auto", tile_cull=True, stack=Fals
     (see PVGRenderViews).  channels=True (implies stack) also renders the
     flexible-rendering channels of Sec. 3.1 and returns (images [V,3,H,W],
     depth [V,H,W] = sum T alpha z, opacity [V,H,W] = sum T alpha = 1 -
-    final_T), all differentiable; the normalized depth is depth / opacity."""
+    final_T, velocity map [V,3,H,W] = sum T alpha v~ with v~ = v exp(-beta /
+    (2 l)), staticness map [V,H,W] = sum T alpha beta / l), all
+    differentiable; the normalized depth is depth / opacity."""
     full = _full_views(views)
     stack = bool(stack or channels)
     if stack and len({(int(v[0]["width"]), int(v[0]["height"])) for v in full}) != 1:
         raise ValueError("stack=True needs views of one resolution")
     out = PVGRenderViews.apply(full, recompute, tile_cull, stack, bool(channels), *params)
     if channels:
-        img, depth, final_T = out
-        return img, depth, 1.0 - final_T
+        img, depth, final_T, vbar, rho = out
+        return img, depth, 1.0 - final_T, vbar, rho
     return out
 
 

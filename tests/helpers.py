@@ -119,12 +119,16 @@ def geom_as_oracle_pre(g, cam):
             "radius": g["radius"], "rect": rect, "tiles": g["tiles"], "flags": np.zeros(n, np.uint32)}
 
 
-def grad_tolerance_report(g_gpu, g_ref, rel=1e-3, floor=1e-2):
-    """Per element |g - g*| <= rel * max(|g*|, floor * rms(g*)); returns (worst ratio, l2 rel err)."""
+def grad_tolerance_report(g_gpu, g_ref, rel=1e-3, floor=1e-2, magnitude=None):
+    """Per element |g - g*| <= rel * max(|g*|, floor * rms(g*)); returns (worst ratio, l2 rel err).
+    magnitude (optional, same shape): the scale of the terms summed into g*
+    (for a sum over views, the sum of the views' |g*|), used instead of |g*|,
+    since FP32 sums are accurate relative to their terms, not to the total."""
     g_gpu = np.asarray(g_gpu, np.float64)
     g_ref = np.asarray(g_ref, np.float64)
     rms = np.sqrt(np.mean(g_ref ** 2)) if g_ref.size else 0.0
-    denom = np.maximum(np.abs(g_ref), floor * rms)
+    mag = np.abs(g_ref) if magnitude is None else np.maximum(np.abs(g_ref), np.asarray(magnitude, np.float64))
+    denom = np.maximum(mag, floor * rms)
     denom = np.where(denom > 0, denom, 1.0)
     ratio = np.abs(g_gpu - g_ref) / (rel * denom)
     l2 = np.linalg.norm(g_gpu - g_ref) / max(np.linalg.norm(g_ref), 1e-300)

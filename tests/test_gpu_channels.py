@@ -1,6 +1,8 @@
 """Flexible rendering channels (Sec. 3.1) on the GPU against the oracle: the
-blended camera depth sum T alpha z, and the rendered opacity O = sum T alpha
-= 1 - final_T, both as differentiable outputs of pvg_render_views.
+blended camera depth sum T alpha z, the rendered opacity O = sum T alpha =
+1 - final_T, the velocity map sum T alpha v~ (v~ = v exp(-beta / (2 l))) and
+the staticness map sum T alpha beta / l, all differentiable outputs of
+pvg_render_views.
 
 Forward: the depth channel against the oracle's FP32 compositor (and the
 images, final_T and last contributors unchanged by asking for it).  Adjoint:
@@ -40,28 +42,37 @@ def test_depth_channel_forward(orc, name, mk_scene, mk_cam, t, dts, tile_cull):
     params = to_device(scene)
     views = [(cam, t, d) for d in dts]
     with torch.no_grad():
-        img, depth, opac = pvg.pvg_render_views(params, views, tile_cull=tile_cull, channels=True)
+        img, depth, opac, vbar, rho = pvg.pvg_render_views(params, views, tile_cull=tile_cull, channels=True)
     for k, (_, tt, d) in enumerate(views):
         ref_img = pvg.render(params, cam, tt, d, tile_cull=tile_cull)
         assert torch.equal(img[k], ref_img[0]), k  # the channel leaves the image alone
         assert torch.equal(opac[k], 1.0 - ref_img[1]), k
         pre = orc.preprocess_f32(scene, cam, tt, d)
         bins = orc.bin_sort(pre, cam)
-        o_img, o_T, o_nc, o_D = orc.render_f32(pre, bins, cam, tt, d, want_depth=True)
+        o_img, o_T, o_nc, o_D, o_F = orc.render_f32(pre, bins, cam, tt, d, want_depth=True, want_feat=True)
         got = depth[k].cpu().numpy()
         scale = max(1.0, float(np.abs(o_D).max()))
         err = float(np.abs(got - o_D).max()) / scale
         print(f"[{name} cull={tile_cull} view {k}] max |depth - oracle| / max depth = {err:.3g}")
         assert err <= 1e-5
         np.testing.assert_allclose(ref_img[1].cpu().numpy(), o_T, atol=1e-5)
+        got_f = np.concatenate([vbar[k].cpu().numpy(), rho[k].cpu().numpy()[None]])
+        fscale = max(1.0, float(np.abs(o_F).max()))
+        ferr = float(np.abs(got_f - o_F).max()) / fscale
+        print(f"[{name} cull={tile_cull} view {k}] max |velocity, staticness - oracle| / max = {ferr:.3g}")
+        assert ferr <= 1e-5
 
 
 @pytest.mark.parametrize("name,mk_scene,mk_cam,t,dts", CASES)
 @pytest.mark.parametrize("recompute", [False, True])
 def test_channel_gradients_vs_fp64(orc, name, mk_scene, mk_cam, t, dts, recompute):
-    """L = sum w img + sum wD depth + sum wO opacity over two views (H(t)
-    and the flow-translated render), against the oracle's FP64 adjoint with
-    dimg = w, dD = wD and dT = -wO, summed over the views."""
+    """L = sum w img + sum wD depth + sum wO opacity + sum wV velocity map +
+    sum wR staticness map over two views (H(t) and the flow-translated
+    render), against the oracle's FP64 adjoint with dimg = w, dD = wD,
+    dT = -wO and dF = (wV, wR), summed over the views.  Each element is held
+    to 1e-3 of the sum of the two views' |g*| (a view's FP32 adjoint is
+    accurate relative to its own gradient; where the views cancel the total
+    is smaller than either term)."""
     import paper_2311_18561_amd as pvg
     scene, cam = mk_scene(), mk_cam()
     H, W = cam["height"], cam["width"]
@@ -70,23 +81,29 @@ def test_channel_gradients_vs_fp64(orc, name, mk_scene, mk_cam, t, dts, recomput
     w = rng.standard_normal((V, 3, H, W)).astype(np.float32)
     wD = (0.05 * rng.standard_normal((V, H, W))).astype(np.float32)
     wO = rng.standard_normal((V, H, W)).astype(np.float32)
+    wV = rng.standard_normal((V, 3, H, W)).astype(np.float32)
+    wR = rng.standard_normal((V, H, W)).astype(np.float32)
     params = [p.requires_grad_(True) for p in to_device(scene)]
     views = [(cam, t, d) for d in dts]
-    img, depth, opac = pvg.pvg_render_views(params, views, recompute=recompute, channels=True)
-    loss = ((img * torch.from_numpy(w).cuda()).sum() + (depth * torch.from_numpy(wD).cuda()).sum()
-            + (opac * torch.from_numpy(wO).cuda()).sum())
+    img, depth, opac, vbar, rho = pvg.pvg_render_views(params, views, recompute=recompute, channels=True)
+    cu = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    loss = ((img * cu(w)).sum() + (depth * cu(wD)).sum() + (opac * cu(wO)).sum() + (vbar * cu(wV)).sum()
+            + (rho * cu(wR)).sum())
     loss.backward()
     sc64 = orc.scene64(scene)
     ref = {f: np.zeros_like(sc64[f]) for f in FIELDS}
+    mag = {f: np.zeros_like(sc64[f]) for f in FIELDS}  # sum over the views of |g*|
     for k, d in enumerate(dts):
         pre = orc.preprocess_f32(scene, cam, t, d)
         bins = orc.bin_sort(pre, cam)
+        dF = np.concatenate([wV[k], wR[k][None]]).astype(np.float64)
         part, _ = orc.backward_f64(sc64, cam, t, d, 0, (0.0, 0.0, 0.0), pre, bins, w[k].astype(np.float64),
-                                   dD=wD[k].astype(np.float64), dT=-wO[k].astype(np.float64))
+                                   dD=wD[k].astype(np.float64), dT=-wO[k].astype(np.float64), dF=dF)
         for f in FIELDS:
             ref[f] += part[f]
+            mag[f] += np.abs(part[f])
     for f, p in zip(FIELDS, params):
-        worst, l2 = grad_tolerance_report(p.grad.detach().cpu().numpy(), ref[f], rel=1e-3)
+        worst, l2 = grad_tolerance_report(p.grad.detach().cpu().numpy(), ref[f], rel=1e-3, magnitude=mag[f])
         print(f"[{name} recompute={recompute}] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
         assert worst <= 1.0, f
 
@@ -102,7 +119,7 @@ def test_channels_without_image_gradient(orc):
     wD = (0.05 * rng.standard_normal((1, H, W))).astype(np.float32)
     wO = rng.standard_normal((1, H, W)).astype(np.float32)
     params = [p.requires_grad_(True) for p in to_device(scene)]
-    _, depth, opac = pvg.pvg_render_views(params, [(cam, t)], channels=True)
+    _, depth, opac, _, _ = pvg.pvg_render_views(params, [(cam, t)], channels=True)
     ((depth * torch.from_numpy(wD).cuda()).sum() + (opac * torch.from_numpy(wO).cuda()).sum()).backward()
     pre = orc.preprocess_f32(scene, cam, t)
     bins = orc.bin_sort(pre, cam)
@@ -111,4 +128,29 @@ def test_channels_without_image_gradient(orc):
     for f, p in zip(FIELDS, params):
         worst, l2 = grad_tolerance_report(p.grad.detach().cpu().numpy(), ref[f], rel=1e-3)
         print(f"[cfg0 channels only] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+        assert worst <= 1.0, f
+
+
+def test_velocity_staticness_only(orc):
+    """Only the velocity and staticness maps carry a loss (the sparse velocity
+    term of the objective, and a staticness term): the result equals the
+    oracle adjoint with only dF set, and the gradient reaches v, beta and l
+    through v~ and rho as well as every parameter alpha depends on."""
+    import paper_2311_18561_amd as pvg
+    cfg = gen.make_config(0)
+    scene, cam, t = cfg["scene"], cfg["cameras"][0], cfg["t"]
+    H, W = cam["height"], cam["width"]
+    rng = np.random.default_rng(4)
+    wV = rng.standard_normal((1, 3, H, W)).astype(np.float32)
+    wR = rng.standard_normal((1, H, W)).astype(np.float32)
+    params = [p.requires_grad_(True) for p in to_device(scene)]
+    _, _, _, vbar, rho = pvg.pvg_render_views(params, [(cam, t, 0.05)], channels=True)
+    ((vbar * torch.from_numpy(wV).cuda()).sum() + (rho * torch.from_numpy(wR).cuda()).sum()).backward()
+    pre = orc.preprocess_f32(scene, cam, t, 0.05)
+    bins = orc.bin_sort(pre, cam)
+    ref, _ = orc.backward_f64(orc.scene64(scene), cam, t, 0.05, 0, (0.0, 0.0, 0.0), pre, bins, np.zeros((3, H, W)),
+                              dF=np.concatenate([wV[0], wR[0][None]]).astype(np.float64))
+    for f, p in zip(FIELDS, params):
+        worst, l2 = grad_tolerance_report(p.grad.detach().cpu().numpy(), ref[f], rel=1e-3)
+        print(f"[cfg0 velocity/staticness only] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
         assert worst <= 1.0, f
