@@ -67,6 +67,12 @@ def lib():
         L.orc_sh_basis_f64.restype = None
         L.orc_project_f64.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
         L.orc_project_f64.restype = C.c_int
+        L.orc_sky_f64.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp]
+        L.orc_sky_f64.restype = None
+        L.orc_sky_bwd_f64.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp, vp]
+        L.orc_sky_bwd_f64.restype = None
+        L.orc_sky_face_uv.argtypes = [vp, vp, vp]
+        L.orc_sky_face_uv.restype = None
         _lib = L
     return _lib
 
@@ -269,3 +275,36 @@ def project_f64(mu, s, q, cam):
     lib().orc_project_f64(_p(_c(mu, np.float64)), _p(_c(s, np.float64)), _p(_c(q, np.float64)), _p(cv),
                           cam["width"], cam["height"], _p(m), _p(J), _p(cov))
     return m, J, cov
+
+
+def sky_f64(img, opac, cube, cam, jitter=None):
+    """Sky composite img + (1 - opac) f_sky(d) in FP64 (img [3,H,W], opac [H,W],
+    cube [6,3,R,R], jitter optional [2,H,W] pixel offsets)."""
+    W, H = cam["width"], cam["height"]
+    R = int(cube.shape[-1])
+    out = np.zeros((3, H, W), np.float64)
+    cv = cam_array(cam)
+    jv = None if jitter is None else _c(jitter, np.float32)
+    lib().orc_sky_f64(_p(_c(img, np.float64)), _p(_c(opac, np.float64)), _p(_c(cube, np.float64)), R, _p(cv), W, H,
+                      _p(jv), _p(out))
+    return out
+
+
+def sky_bwd_f64(g, opac, cube, cam, jitter=None):
+    """Adjoint of sky_f64 for dL/dout = g: (dL/dopac [H,W], dL/dcube [6,3,R,R])."""
+    W, H = cam["width"], cam["height"]
+    R = int(cube.shape[-1])
+    dO = np.zeros((H, W), np.float64)
+    dC = np.zeros((6, 3, R, R), np.float64)
+    cv = cam_array(cam)
+    jv = None if jitter is None else _c(jitter, np.float32)
+    lib().orc_sky_bwd_f64(_p(_c(g, np.float64)), _p(_c(opac, np.float64)), _p(_c(cube, np.float64)), R, _p(cv), W, H,
+                          _p(jv), _p(dO), _p(dC))
+    return dO, dC
+
+
+def sky_face_uv(d):
+    face = np.zeros(1, np.int32)
+    uv = np.zeros(2, np.float64)
+    lib().orc_sky_face_uv(_p(_c(d, np.float64)), _p(face), _p(uv))
+    return int(face[0]), uv

@@ -978,3 +978,122 @@ int orc_project_f64(const double* mu, const double* s, const double* q, const fl
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Sky (Sec. 3.4, sky refinement): C_f = C + (1 - O) f_sky(d), with f_sky a
+// learnable cube map looked up in the pixel's viewing direction d, here taken
+// through the pixel centre moved by an optional jitter (the paper perturbs d
+// within the unit pixel while training); the lookup geometry in FP32, the
+// blend in FP64.  Conventions of this build (the
+// paper fixes none): d_cam = ((px + 0.5 + jx - cx) / fx, (py + 0.5 + jy - cy)
+// / fy, 1), d = R^T d_cam in the world frame; faces +X, -X, +Y, -Y, +Z, -Z
+// (0..5) chosen by the largest |d_i| (ties to the lower axis); face
+// coordinates as in OpenGL cube maps; texel (x, y) = (u R - 1/2, v R - 1/2)
+// sampled bilinearly with the coordinates clamped to [0, R - 1] inside the
+// face; cube layout [6][3][R][R] (face, channel, row v, column u).
+namespace sky {
+// The lookup geometry (direction, face, face coordinates, texel taps) is
+// evaluated in FP32, the precision in which the renderer takes the face and
+// texel decisions; only the blend is accumulated in FP64.
+template <class R>
+void face_uv(const R d[3], int& face, R& u, R& v) {
+  const R ax = std::fabs(d[0]), ay = std::fabs(d[1]), az = std::fabs(d[2]);
+  R sc, tc, ma;
+  if (ax >= ay && ax >= az) {
+    ma = ax;
+    if (d[0] >= 0) { face = 0; sc = -d[2]; tc = -d[1]; } else { face = 1; sc = d[2]; tc = -d[1]; }
+  } else if (ay >= az) {
+    ma = ay;
+    if (d[1] >= 0) { face = 2; sc = d[0]; tc = d[2]; } else { face = 3; sc = d[0]; tc = -d[2]; }
+  } else {
+    ma = az;
+    if (d[2] >= 0) { face = 4; sc = d[0]; tc = -d[1]; } else { face = 5; sc = -d[0]; tc = -d[1]; }
+  }
+  u = R(0.5) * (sc / ma + R(1));
+  v = R(0.5) * (tc / ma + R(1));
+}
+
+// the four texels (face-local flat indices) and weights of the bilinear lookup
+void taps(int Rn, float u, float v, int idx[4], double w[4]) {
+  float x = u * static_cast<float>(Rn) - 0.5f, y = v * static_cast<float>(Rn) - 0.5f;
+  x = std::min(std::max(x, 0.0f), static_cast<float>(Rn - 1));
+  y = std::min(std::max(y, 0.0f), static_cast<float>(Rn - 1));
+  const int x0 = static_cast<int>(std::floor(x)), y0 = static_cast<int>(std::floor(y));
+  const int x1 = std::min(x0 + 1, Rn - 1), y1 = std::min(y0 + 1, Rn - 1);
+  const float fx = x - static_cast<float>(x0), fy = y - static_cast<float>(y0);
+  idx[0] = y0 * Rn + x0; w[0] = (1.0f - fx) * (1.0f - fy);
+  idx[1] = y0 * Rn + x1; w[1] = fx * (1.0f - fy);
+  idx[2] = y1 * Rn + x0; w[2] = (1.0f - fx) * fy;
+  idx[3] = y1 * Rn + x1; w[3] = fx * fy;
+}
+
+void direction(const Camera& cam, int px, int py, const float* jitter, int64_t HW, int64_t o, float d[3]) {
+  const float jx = jitter ? jitter[o] : 0.0f, jy = jitter ? jitter[HW + o] : 0.0f;
+  const float c[3] = {((static_cast<float>(px) + 0.5f) + jx - cam.cx) / cam.fx,
+                      ((static_cast<float>(py) + 0.5f) + jy - cam.cy) / cam.fy, 1.0f};
+  for (int k = 0; k < 3; ++k) d[k] = (cam.R[k] * c[0] + cam.R[3 + k] * c[1]) + cam.R[6 + k] * c[2];
+}
+}  // namespace sky
+
+extern "C" {
+// out[3][H][W] = img + (1 - opac) * f_sky(d) in FP64; inputs [3][H][W], [H][W].
+void orc_sky_f64(const double* img, const double* opac, const double* cube, int R, const float* camv, int W, int H,
+                 const float* jitter, double* out) {
+  const Camera cam = make_cam(camv, W, H);
+  const int64_t HW = static_cast<int64_t>(H) * W, F = static_cast<int64_t>(R) * R;
+  for (int py = 0; py < H; ++py)
+    for (int px = 0; px < W; ++px) {
+      const int64_t o = static_cast<int64_t>(py) * W + px;
+      float d[3], u, v;
+      double w[4];
+      int face, idx[4];
+      sky::direction(cam, px, py, jitter, HW, o, d);
+      sky::face_uv<float>(d, face, u, v);
+      sky::taps(R, u, v, idx, w);
+      for (int c = 0; c < 3; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < 4; ++k) s += w[k] * cube[(face * 3 + c) * F + idx[k]];
+        out[c * HW + o] = img[c * HW + o] + (1.0 - opac[o]) * s;
+      }
+    }
+}
+
+// Adjoint of orc_sky_f64 for dL/dout = g: dL/dopac [H][W] (overwritten) and
+// dL/dcube [6][3][R][R] (overwritten); dL/dimg is g itself.
+void orc_sky_bwd_f64(const double* g, const double* opac, const double* cube, int R, const float* camv, int W, int H,
+                     const float* jitter, double* dopac, double* dcube) {
+  const Camera cam = make_cam(camv, W, H);
+  const int64_t HW = static_cast<int64_t>(H) * W, F = static_cast<int64_t>(R) * R;
+  for (int64_t k = 0; k < 6 * 3 * F; ++k) dcube[k] = 0.0;
+  for (int py = 0; py < H; ++py)
+    for (int px = 0; px < W; ++px) {
+      const int64_t o = static_cast<int64_t>(py) * W + px;
+      float d[3], u, v;
+      double w[4];
+      int face, idx[4];
+      sky::direction(cam, px, py, jitter, HW, o, d);
+      sky::face_uv<float>(d, face, u, v);
+      sky::taps(R, u, v, idx, w);
+      double dO = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < 4; ++k) {
+          s += w[k] * cube[(face * 3 + c) * F + idx[k]];
+          dcube[(face * 3 + c) * F + idx[k]] += w[k] * (1.0 - opac[o]) * g[c * HW + o];
+        }
+        dO -= s * g[c * HW + o];
+      }
+      dopac[o] = dO;
+    }
+}
+
+// The face and face coordinates of a world direction, in FP32 as the
+// composite takes them (for the pins).
+void orc_sky_face_uv(const double* d, int* face, double* uv) {
+  const float df[3] = {static_cast<float>(d[0]), static_cast<float>(d[1]), static_cast<float>(d[2])};
+  float u, v;
+  sky::face_uv<float>(df, *face, u, v);
+  uv[0] = u;
+  uv[1] = v;
+}
+}
