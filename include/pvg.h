@@ -274,6 +274,29 @@ int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const
                                   const float* const* dL_dimg, const pvg_channels* channels,
                                   pvg_gaussians_grad* grad, int32_t accumulate, void* tmp,
                                   size_t tmp_bytes, void* stream);
+/* Sky refinement (Sec. 3.4): out = img + (1 - opacity) * f_sky(d), with f_sky
+ * a learnable cube map `cube` [6][3][cube_res][cube_res] (faces +X, -X, +Y,
+ * -Y, +Z, -Z; channel; row v; column u) looked up bilinearly, inside the face,
+ * in the world-frame direction d = R^T ((px + 1/2 + jx - cx) / fx, (py + 1/2
+ * + jy - cy) / fy, 1) of pixel (px, py).  img [3][H][W] is the render with a
+ * black background; opacity [H][W] is 1 - final_T; jitter (optional, may be
+ * NULL) [2][H][W] moves each direction inside its pixel (the paper perturbs it
+ * within the unit pixel while training).  The face is the axis of the largest
+ * |d_i| (ties to the lower axis) with OpenGL face coordinates; texel (u R -
+ * 1/2, v R - 1/2), clamped to [0, R - 1].  Device memory, caller-owned;
+ * PVG_ERR_INVALID on a bad camera, null arrays or cube_res outside
+ * [1, 16384]; asynchronous on `stream`. */
+int pvg_sky_composite(const pvg_camera* cam, const float* img, const float* opacity, const float* cube,
+                      int32_t cube_res, const float* jitter, float* out, void* stream);
+/* Adjoint of pvg_sky_composite for dL_dout [3][H][W]: writes dL_dopacity
+ * [H][W] (= -sum_c f_sky,c(d) dL_dout_c) and adds (1 - opacity) dL_dout times
+ * the bilinear weights into dL_dcube [6][3][R][R] with float atomics (zero it
+ * first for a fresh gradient; the order of the additions varies from run to
+ * run).  dL/dimg is dL_dout itself. */
+int pvg_sky_composite_bwd(const pvg_camera* cam, const float* dL_dout, const float* opacity, const float* cube,
+                          int32_t cube_res, const float* jitter, float* dL_dopacity, float* dL_dcube,
+                          void* stream);
+
 /* Scratch bytes of pvg_render_bwd_views.  Host only. */
 int pvg_bwd_views_tmp_bytes(int64_t n, int32_t n_views, int32_t max_width, int32_t max_height,
                             int64_t max_capacity, size_t* bytes);

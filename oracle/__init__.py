@@ -272,8 +272,8 @@ def project_f64(mu, s, q, cam):
     J = np.zeros(4, np.float64)
     cov = np.zeros(3, np.float64)
     cv = cam_array(cam)
-    lib().orc_project_f64(_p(_c(mu, np.float64)), _p(_c(s, np.float64)), _p(_c(q, np.float64)), _p(cv),
-                          cam["width"], cam["height"], _p(m), _p(J), _p(cov))
+    mu, s, q = _c(mu, np.float64), _c(s, np.float64), _c(q, np.float64)  # held for the call
+    lib().orc_project_f64(_p(mu), _p(s), _p(q), _p(cv), cam["width"], cam["height"], _p(m), _p(J), _p(cov))
     return m, J, cov
 
 
@@ -285,8 +285,8 @@ def sky_f64(img, opac, cube, cam, jitter=None):
     out = np.zeros((3, H, W), np.float64)
     cv = cam_array(cam)
     jv = None if jitter is None else _c(jitter, np.float32)
-    lib().orc_sky_f64(_p(_c(img, np.float64)), _p(_c(opac, np.float64)), _p(_c(cube, np.float64)), R, _p(cv), W, H,
-                      _p(jv), _p(out))
+    img, opac, cube = _c(img, np.float64), _c(opac, np.float64), _c(cube, np.float64)  # held for the call
+    lib().orc_sky_f64(_p(img), _p(opac), _p(cube), R, _p(cv), W, H, _p(jv), _p(out))
     return out
 
 
@@ -298,13 +298,14 @@ def sky_bwd_f64(g, opac, cube, cam, jitter=None):
     dC = np.zeros((6, 3, R, R), np.float64)
     cv = cam_array(cam)
     jv = None if jitter is None else _c(jitter, np.float32)
-    lib().orc_sky_bwd_f64(_p(_c(g, np.float64)), _p(_c(opac, np.float64)), _p(_c(cube, np.float64)), R, _p(cv), W, H,
-                          _p(jv), _p(dO), _p(dC))
+    g, opac, cube = _c(g, np.float64), _c(opac, np.float64), _c(cube, np.float64)  # held for the call
+    lib().orc_sky_bwd_f64(_p(g), _p(opac), _p(cube), R, _p(cv), W, H, _p(jv), _p(dO), _p(dC))
     return dO, dC
 
 
 def sky_face_uv(d):
     face = np.zeros(1, np.int32)
     uv = np.zeros(2, np.float64)
-    lib().orc_sky_face_uv(_p(_c(d, np.float64)), _p(face), _p(uv))
+    d = _c(d, np.float64)
+    lib().orc_sky_face_uv(_p(d), _p(face), _p(uv))
     return int(face[0]), uv

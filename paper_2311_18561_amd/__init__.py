@@ -13,6 +13,7 @@ from .render import (  # noqa: F401
     FIELDS,
     PVGRender,
     PVGRenderViews,
+    PVGSkyComposite,
     bin_sort,
     bin_sort_nosync,
     camera_struct,
@@ -21,6 +22,7 @@ from .render import (  # noqa: F401
     preprocess_views,
     pvg_render,
     pvg_render_views,
+    pvg_sky_composite,
     render,
     render_bwd,
     render_fwd,

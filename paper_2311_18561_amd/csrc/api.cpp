@@ -327,6 +327,28 @@ int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_fram
                               tmp_bytes, stream);
 }
 
+int pvg_sky_composite(const pvg_camera* cam, const float* img, const float* opacity, const float* cube,
+                      int32_t cube_res, const float* jitter, float* out, void* stream) {
+  if (!check_camera(cam)) return PVG_ERR_INVALID;
+  if (!img || !opacity || !cube || !out) { set_error("a sky composite array is null"); return PVG_ERR_INVALID; }
+  if (cube_res < 1 || cube_res > 16384) { set_error("cube_res = %d out of [1, 16384]", cube_res); return PVG_ERR_INVALID; }
+  PVG_HIP(launch_sky(cam, img, opacity, cube, cube_res, jitter, out, static_cast<hipStream_t>(stream)));
+  return PVG_OK;
+}
+
+int pvg_sky_composite_bwd(const pvg_camera* cam, const float* dL_dout, const float* opacity, const float* cube,
+                          int32_t cube_res, const float* jitter, float* dL_dopacity, float* dL_dcube, void* stream) {
+  if (!check_camera(cam)) return PVG_ERR_INVALID;
+  if (!dL_dout || !opacity || !cube || !dL_dopacity || !dL_dcube) {
+    set_error("a sky composite array is null");
+    return PVG_ERR_INVALID;
+  }
+  if (cube_res < 1 || cube_res > 16384) { set_error("cube_res = %d out of [1, 16384]", cube_res); return PVG_ERR_INVALID; }
+  PVG_HIP(launch_sky_bwd(cam, dL_dout, opacity, cube, cube_res, jitter, dL_dopacity, dL_dcube,
+                         static_cast<hipStream_t>(stream)));
+  return PVG_OK;
+}
+
 int pvg_bwd_views_tmp_bytes(int64_t n, int32_t n_views, int32_t max_width, int32_t max_height, int64_t max_capacity,
                             size_t* bytes) {
   if (!bytes || n < 0 || n_views < 1 || max_width <= 0 || max_height <= 0 || max_capacity < 0 ||

@@ -1,0 +1,127 @@
+// Sky composite of the sky refinement (Sec. 3.4): C_f = C + (1 - O) f_sky(d),
+// where f_sky is a learnable cube map looked up in the pixel's world-frame
+// viewing direction, optionally jittered inside the pixel.  One thread per
+// pixel; the adjoint adds each pixel's bilinear weights times (1 - O) dL/dC_f
+// into the cube map's gradient with float atomics and writes dL/dO.
+//
+// Conventions: d_cam = ((px + 1/2 + jx - cx) / fx, (py + 1/2 + jy - cy) / fy,
+// 1), d = R^T d_cam; faces +X, -X, +Y, -Y, +Z, -Z (0..5) by the largest |d_i|
+// (ties to the lower axis); face coordinates as in OpenGL cube maps; texel
+// (u R - 1/2, v R - 1/2), bilinear inside the face with the coordinates
+// clamped to [0, R - 1]; cube [6][3][R][R].  The geometry is FP32 without
+// contraction, so the face and texel decisions are the oracle's.
+#include "pvg_math.hpp"
+
+namespace pvg {
+
+struct SkyView {
+  float R[9];
+  float fx, fy, cx, cy;
+  int32_t W, H;
+};
+
+__device__ __forceinline__ void sky_taps(const SkyView& c, int px, int py, const float* __restrict__ jitter,
+                                         int64_t HW, int64_t o, int Rn, int& face, int idx[4], float w[4]) {
+  const float jx = jitter ? jitter[o] : 0.0f, jy = jitter ? jitter[HW + o] : 0.0f;
+  const float c0 = ((static_cast<float>(px) + 0.5f) + jx - c.cx) / c.fx;
+  const float c1 = ((static_cast<float>(py) + 0.5f) + jy - c.cy) / c.fy;
+  float d[3];
+  for (int k = 0; k < 3; ++k) d[k] = (c.R[k] * c0 + c.R[3 + k] * c1) + c.R[6 + k] * 1.0f;
+  const float ax = fabsf(d[0]), ay = fabsf(d[1]), az = fabsf(d[2]);
+  float sc, tc, ma;
+  if (ax >= ay && ax >= az) {
+    ma = ax;
+    if (d[0] >= 0.0f) { face = 0; sc = -d[2]; tc = -d[1]; } else { face = 1; sc = d[2]; tc = -d[1]; }
+  } else if (ay >= az) {
+    ma = ay;
+    if (d[1] >= 0.0f) { face = 2; sc = d[0]; tc = d[2]; } else { face = 3; sc = d[0]; tc = -d[2]; }
+  } else {
+    ma = az;
+    if (d[2] >= 0.0f) { face = 4; sc = d[0]; tc = -d[1]; } else { face = 5; sc = -d[0]; tc = -d[1]; }
+  }
+  const float u = 0.5f * (sc / ma + 1.0f), v = 0.5f * (tc / ma + 1.0f);
+  const float rm = static_cast<float>(Rn - 1);
+  // fminf / fmaxf also send a NaN coordinate into the face
+  const float x = fminf(fmaxf(u * static_cast<float>(Rn) - 0.5f, 0.0f), rm);
+  const float y = fminf(fmaxf(v * static_cast<float>(Rn) - 0.5f, 0.0f), rm);
+  const int x0 = min(max(static_cast<int>(floorf(x)), 0), Rn - 1), y0 = min(max(static_cast<int>(floorf(y)), 0), Rn - 1);
+  const int x1 = min(x0 + 1, Rn - 1), y1 = min(y0 + 1, Rn - 1);
+  const float fx = x - static_cast<float>(x0), fy = y - static_cast<float>(y0);
+  idx[0] = y0 * Rn + x0; w[0] = (1.0f - fx) * (1.0f - fy);
+  idx[1] = y0 * Rn + x1; w[1] = fx * (1.0f - fy);
+  idx[2] = y1 * Rn + x0; w[2] = (1.0f - fx) * fy;
+  idx[3] = y1 * Rn + x1; w[3] = fx * fy;
+}
+
+__global__ void __launch_bounds__(256) k_sky_fwd(SkyView c, const float* __restrict__ img,
+                                                 const float* __restrict__ opac, const float* __restrict__ cube,
+                                                 int Rn, const float* __restrict__ jitter, float* out) {
+  const int64_t HW = static_cast<int64_t>(c.W) * c.H;
+  const int64_t o = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (o >= HW) return;
+  const int px = static_cast<int>(o % c.W), py = static_cast<int>(o / c.W);
+  int face, idx[4];
+  float w[4];
+  sky_taps(c, px, py, jitter, HW, o, Rn, face, idx, w);
+  const int64_t F = static_cast<int64_t>(Rn) * Rn;
+  const float t = 1.0f - opac[o];
+  for (int ch = 0; ch < 3; ++ch) {
+    const float* cf = cube + (face * 3 + ch) * F;
+    const float s = ((w[0] * cf[idx[0]] + w[1] * cf[idx[1]]) + w[2] * cf[idx[2]]) + w[3] * cf[idx[3]];
+    out[ch * HW + o] = img[ch * HW + o] + t * s;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sky_bwd(SkyView c, const float* __restrict__ g,
+                                                 const float* __restrict__ opac, const float* __restrict__ cube,
+                                                 int Rn, const float* __restrict__ jitter, float* dopac, float* dcube) {
+  const int64_t HW = static_cast<int64_t>(c.W) * c.H;
+  const int64_t o = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (o >= HW) return;
+  const int px = static_cast<int>(o % c.W), py = static_cast<int>(o / c.W);
+  int face, idx[4];
+  float w[4];
+  sky_taps(c, px, py, jitter, HW, o, Rn, face, idx, w);
+  const int64_t F = static_cast<int64_t>(Rn) * Rn;
+  const float t = 1.0f - opac[o];
+  float dO = 0.0f;
+  for (int ch = 0; ch < 3; ++ch) {
+    const float* cf = cube + (face * 3 + ch) * F;
+    float* df = dcube + (face * 3 + ch) * F;
+    const float gc = g[ch * HW + o];
+    const float s = ((w[0] * cf[idx[0]] + w[1] * cf[idx[1]]) + w[2] * cf[idx[2]]) + w[3] * cf[idx[3]];
+    dO -= s * gc;
+    const float tg = t * gc;
+    for (int k = 0; k < 4; ++k)
+      if (w[k] != 0.0f) atomicAdd(&df[idx[k]], w[k] * tg);
+  }
+  dopac[o] = dO;
+}
+
+static SkyView sky_view(const pvg_camera* cam) {
+  SkyView v;
+  for (int k = 0; k < 9; ++k) v.R[k] = cam->R[k];
+  v.fx = cam->fx; v.fy = cam->fy; v.cx = cam->cx; v.cy = cam->cy;
+  v.W = cam->width; v.H = cam->height;
+  return v;
+}
+
+hipError_t launch_sky(const pvg_camera* cam, const float* img, const float* opac, const float* cube, int Rn,
+                      const float* jitter, float* out, hipStream_t s) {
+  const int64_t HW = static_cast<int64_t>(cam->width) * cam->height;
+  if (HW == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sky_fwd, dim3(static_cast<unsigned>((HW + 255) / 256)), dim3(256), 0, s, sky_view(cam), img,
+                     opac, cube, Rn, jitter, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sky_bwd(const pvg_camera* cam, const float* g, const float* opac, const float* cube, int Rn,
+                          const float* jitter, float* dopac, float* dcube, hipStream_t s) {
+  const int64_t HW = static_cast<int64_t>(cam->width) * cam->height;
+  if (HW == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sky_bwd, dim3(static_cast<unsigned>((HW + 255) / 256)), dim3(256), 0, s, sky_view(cam), g,
+                     opac, cube, Rn, jitter, dopac, dcube);
+  return hipGetLastError();
+}
+
+}  // namespace pvg

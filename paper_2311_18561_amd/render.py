@@ -635,3 +635,49 @@ def pvg_render_views(params, views, recompute="auto", tile_cull=True, stack=Fals
 def pvg_render(params, cam, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), recompute=True, tile_cull=True):
     """Differentiable render of the nine parameter tensors (see module doc)."""
     return PVGRender.apply(*params, cam, t, dt, advect_mode, bg, recompute, tile_cull)
+
+
+class PVGSkyComposite(torch.autograd.Function):
+    """Sky refinement (Sec. 3.4): C_f = C + (1 - O) f_sky(d) over a learnable
+    cube map, one view: img [3,H,W] (rendered on a black background), opacity
+    [H,W], cube [6,3,R,R]; the adjoint reaches img, opacity and the cube map."""
+
+    @staticmethod
+    def forward(ctx, img, opacity, cube, cam, jitter):
+        c = camera_struct(cam)
+        H, W = int(c.height), int(c.width)
+        img, opacity, cube = img.contiguous(), opacity.contiguous(), cube.contiguous()
+        if img.shape != (3, H, W) or opacity.shape != (H, W) or cube.dim() != 4 or cube.shape[:2] != (6, 3) \
+                or cube.shape[2] != cube.shape[3]:
+            raise ValueError("pvg_sky_composite needs img [3,H,W], opacity [H,W] and cube [6,3,R,R]")
+        for t in (img, opacity, cube):
+            if t.dtype != torch.float32 or not t.is_cuda:
+                raise ValueError("pvg_sky_composite takes float32 CUDA tensors")
+        if jitter is not None:
+            jitter = jitter.contiguous()
+            if jitter.shape != (2, H, W) or jitter.dtype != torch.float32:
+                raise ValueError("jitter must be float32 [2,H,W]")
+        out = torch.empty_like(img)
+        L.check(L.load().pvg_sky_composite(C.byref(c), _p(img), _p(opacity), _p(cube), int(cube.shape[-1]),
+                                           _p(jitter), _p(out), _stream_handle()))
+        ctx.c = c
+        ctx.save_for_backward(opacity, cube, jitter if jitter is not None else torch.empty(0, device=img.device))
+        ctx.has_jitter = jitter is not None
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        opacity, cube, jitter = ctx.saved_tensors
+        g = g.contiguous()
+        d_op = torch.empty_like(opacity)
+        d_cube = torch.zeros_like(cube)
+        L.check(L.load().pvg_sky_composite_bwd(C.byref(ctx.c), _p(g), _p(opacity), _p(cube), int(cube.shape[-1]),
+                                               _p(jitter) if ctx.has_jitter else None, _p(d_op), _p(d_cube),
+                                               _stream_handle()))
+        return g, d_op, d_cube, None, None
+
+
+def pvg_sky_composite(img, opacity, cube, cam: dict, jitter=None):
+    """C + (1 - O) f_sky(d) for one view (see PVGSkyComposite); jitter
+    (optional [2,H,W], pixels) moves each ray inside its pixel."""
+    return PVGSkyComposite.apply(img, opacity, cube, cam, jitter)

@@ -1,0 +1,92 @@
+"""Sky refinement (Sec. 3.4) on the GPU against the oracle: the composite
+C + (1 - O) f_sky(d) over a cube map and its adjoint into the opacity and the
+cube map, with and without jittered rays; and the whole chain from the
+Gaussians (image and opacity of pvg_render_views) through the composite."""
+import numpy as np
+import pytest
+
+import gen
+from helpers import FIELDS, grad_tolerance_report, to_device
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("jitter", [False, True])
+@pytest.mark.parametrize("res", [1, 7, 64])
+def test_sky_composite_vs_oracle(orc, jitter, res):
+    import paper_2311_18561_amd as pvg
+    cam = gen.yaw_camera(200, 136, 40.0, (0.0, 0.0, 0.0))
+    H, W = cam["height"], cam["width"]
+    rng = np.random.default_rng(res)
+    img = rng.random((3, H, W)).astype(np.float32)
+    opac = rng.random((H, W)).astype(np.float32)
+    cube = rng.random((6, 3, res, res)).astype(np.float32)
+    jit = (rng.random((2, H, W)) - 0.5).astype(np.float32) if jitter else None
+    g = rng.standard_normal((3, H, W)).astype(np.float32)
+    t_img = torch.from_numpy(img).cuda().requires_grad_(True)
+    t_op = torch.from_numpy(opac).cuda().requires_grad_(True)
+    t_cube = torch.from_numpy(cube).cuda().requires_grad_(True)
+    out = pvg.pvg_sky_composite(t_img, t_op, t_cube, cam, None if jit is None else torch.from_numpy(jit).cuda())
+    (out * torch.from_numpy(g).cuda()).sum().backward()
+    ref = orc.sky_f64(img, opac, cube, cam, jit)
+    err = float(np.abs(out.detach().cpu().numpy() - ref).max())
+    print(f"[sky R={res} jitter={jitter}] max |out - oracle| = {err:.3g}")
+    assert err <= 1e-6
+    dO, dC = orc.sky_bwd_f64(g, opac, cube, cam, jit)
+    assert np.array_equal(t_img.grad.cpu().numpy(), g)
+    np.testing.assert_allclose(t_op.grad.cpu().numpy(), dO, rtol=1e-5, atol=1e-5)
+    # the cube gradient sums many pixels' terms of either sign (float atomics,
+    # any order): the tolerance scales with the sum of the terms' magnitudes,
+    # which is the adjoint taken with |g| since (1 - O) and the bilinear weights
+    # are non-negative
+    _, dC_mag = orc.sky_bwd_f64(np.abs(g), opac, cube, cam, jit)
+    worst, l2 = grad_tolerance_report(t_cube.grad.cpu().numpy(), dC, rel=1e-4, magnitude=dC_mag)
+    print(f"[sky R={res} jitter={jitter}] cube grad worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+    assert worst <= 1.0
+
+
+def test_sky_on_rendered_views_vs_fp64(orc):
+    """L = sum w (C + (1 - O) f_sky(d)) for the image and opacity of a render
+    (black background): gradients of the Gaussians against the FP64 render
+    adjoint with dimg = w and dT = sum_c f_sky,c w_c (the composite's
+    dL/dO = -that), and of the cube map against the sky adjoint."""
+    import paper_2311_18561_amd as pvg
+    cfg = gen.make_config(0)
+    scene, cam, t = cfg["scene"], cfg["cameras"][0], cfg["t"]
+    H, W = cam["height"], cam["width"]
+    rng = np.random.default_rng(9)
+    cube = rng.random((6, 3, 16, 16)).astype(np.float32)
+    w = rng.standard_normal((3, H, W)).astype(np.float32)
+    params = [p.requires_grad_(True) for p in to_device(scene)]
+    t_cube = torch.from_numpy(cube).cuda().requires_grad_(True)
+    img, _, opac, _, _ = pvg.pvg_render_views(params, [(cam, t)], channels=True)
+    out = pvg.pvg_sky_composite(img[0], opac[0], t_cube, cam)
+    (out * torch.from_numpy(w).cuda()).sum().backward()
+    o_op = opac[0].detach().cpu().numpy().astype(np.float64)
+    dO, dC = orc.sky_bwd_f64(w, o_op, cube, cam)
+    pre = orc.preprocess_f32(scene, cam, t)
+    bins = orc.bin_sort(pre, cam)
+    args = (orc.scene64(scene), cam, t, 0.0, 0, (0.0, 0.0, 0.0), pre, bins)
+    ref, _ = orc.backward_f64(*args, w.astype(np.float64), dT=-dO)
+    # the colour and the opacity upstream gradients are two sources whose terms
+    # cancel in each Gaussian's sum: the tolerance scales with the sum of the
+    # magnitudes of their separate gradients
+    ref_c, _ = orc.backward_f64(*args, w.astype(np.float64))
+    ref_o, _ = orc.backward_f64(*args, np.zeros_like(w, np.float64), dT=-dO)
+    for f, p in zip(FIELDS, params):
+        mag = np.abs(ref_c[f]) + np.abs(ref_o[f])
+        worst, l2 = grad_tolerance_report(p.grad.detach().cpu().numpy(), ref[f], rel=1e-3, magnitude=mag)
+        print(f"[cfg0 + sky] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+        assert worst <= 1.0, f
+    _, dC_mag = orc.sky_bwd_f64(np.abs(w), o_op, cube, cam)
+    worst, l2 = grad_tolerance_report(t_cube.grad.cpu().numpy(), dC, rel=1e-4, magnitude=dC_mag)
+    print(f"[cfg0 + sky] cube: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+    assert worst <= 1.0

@@ -84,6 +84,12 @@ def test_invalid_arguments_rejected_on_host(lib):
     size = C.c_size_t()
     assert lib.pvg_bwd_views_tmp_bytes(100, 6, 64, 48, 1000, C.byref(size)) == 0 and size.value > 0
     assert lib.pvg_bwd_views_tmp_bytes(100, 0, 64, 48, 1000, C.byref(size)) == L.PVG_ERR_INVALID
+    # the sky composite: null arrays and the cube resolution
+    cam.znear = 0.2
+    assert lib.pvg_sky_composite(C.byref(cam), None, None, None, 8, None, None, None) == L.PVG_ERR_INVALID
+    assert lib.pvg_sky_composite(C.byref(cam), 1, 1, 1, 0, None, 1, None) == L.PVG_ERR_INVALID
+    assert "cube_res" in L.last_error()
+    assert lib.pvg_sky_composite_bwd(C.byref(cam), 1, 1, 1, 20000, None, 1, 1, None) == L.PVG_ERR_INVALID
     # the multi-view preprocess: view count, null arrays, a bad camera among the views
     g.n, g.sh_degree = 0, 0
     cams2 = (L.Camera * 2)(cam, cam)
