@@ -200,8 +200,11 @@ int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera*
  * Gaussian's camera depth z takes the place of its colour in Eq. (3).  Every
  * pointer is optional (NULL: not rendered / no gradient), device memory of
  * [height][width] floats, owned by the caller:
- *   depth      forward output: sum over contributors of T_i alpha_i z_i (the
- *              normalized depth of the paper is depth / (1 - final_T));
+ *   depth      forward output: sum over contributors of T_i alpha_i z_i, or
+ *              with depth_normalized the normalized depth of Sec. 3.1,
+ *              sum T_i alpha_i z_i / sum T_i alpha_i (0 on pixels that no
+ *              Gaussian reaches); for the adjoint with depth_normalized and
+ *              dL_ddepth, the forward's normalized depth (read only);
  *   dL_ddepth  adjoint input: upstream gradient of `depth`;
  *   dL_dT      adjoint input: upstream gradient of final_T (the rendered
  *              opacity O = sum T_i alpha_i is 1 - final_T, so dL/dO enters as
@@ -210,7 +213,9 @@ int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera*
  *              dynamic element analysis), blending each Gaussian's v~ and
  *              rho from geom->feat, which must then be non-NULL (the preprocess
  *              fills it); dL_dvbar and dL_drho their upstream gradients, which
- *              reach v, beta and l. */
+ *              reach v, beta and l.
+ * depth_normalized (0 or 1) selects the depth above; the adjoint must be
+ * given the forward's choice. */
 typedef struct pvg_channels {
   float* depth;
   const float* dL_ddepth;
@@ -219,6 +224,7 @@ typedef struct pvg_channels {
   float* rho;              /* forward output [height][width]: sum T_i alpha_i rho_i */
   const float* dL_dvbar;   /* adjoint input [3][height][width] */
   const float* dL_drho;    /* adjoint input [height][width] */
+  int32_t depth_normalized;
 } pvg_channels;
 
 /* pvg_render_fwd that also writes the channels requested in `channels`

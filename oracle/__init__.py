@@ -213,6 +213,28 @@ def render_f64(sc64, cam, t, dt, mode, bg, pre, bins, tile_mask=None, w=None, wa
     return (L, img, T, D) if want_depth else (L, img, T)
 
 
+def normalized_depth_f64(depth, final_T):
+    """Normalized depth of Sec. 3.1 per pixel: sum_i T_i alpha_i z_i / sum_i
+    T_i alpha_i, from the blended depth (numerator) and final_T; the
+    denominator is 1 - final_T, since the transmittances telescope (T_i alpha_i
+    = T_i - T_(i+1)); 0 where no Gaussian contributes (the sum is then 0)."""
+    A = 1.0 - np.asarray(final_T, np.float64)
+    ok = A > 0.0
+    return np.where(ok, np.asarray(depth, np.float64) / np.where(ok, A, 1.0), 0.0)
+
+
+def normalized_depth_bwd_f64(g, depth, final_T):
+    """Adjoint of normalized_depth_f64 for the upstream gradient g: returns
+    (dD, dT), the gradients of the blended depth and of final_T.  Quotient
+    rule on D / A with A = 1 - final_T: dD = g / A, dT = g (D / A) / A; both 0
+    where A = 0."""
+    A = 1.0 - np.asarray(final_T, np.float64)
+    ok = A > 0.0
+    ia = np.where(ok, 1.0 / np.where(ok, A, 1.0), 0.0)
+    g = np.asarray(g, np.float64)
+    return g * ia, g * (np.asarray(depth, np.float64) * ia) * ia
+
+
 def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, tile_mask=None, dD=None, dT=None, dF=None
                  ) -> tuple[dict, np.ndarray]:
     """FP64 gradients of sum(dimg * image) + sum(dD * depth) + sum(dT * final_T)

@@ -307,6 +307,7 @@ int pvg_render_fwd_channels(const pvg_geom* geom, const pvg_bins* bins, const pv
   v.n_contrib = n_contrib;
   if (channels) {
     v.depth_img = channels->depth;
+    v.depth_norm = channels->depth_normalized != 0;
     v.vbar_img = channels->vbar;
     v.rho_img = channels->rho;
     if ((v.vbar_img || v.rho_img) && geom->n > 0 && !geom->feat) {
@@ -486,6 +487,14 @@ int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const
       v.dL_dT = channels[k].dL_dT;
       v.dL_dvbar = channels[k].dL_dvbar;
       v.dL_drho = channels[k].dL_drho;
+      if (channels[k].depth_normalized && v.dL_ddepth) {
+        if (!channels[k].depth) {
+          set_error("the normalized depth gradient of view %d needs the forward's normalized depth", k);
+          return PVG_ERR_INVALID;
+        }
+        v.depth_norm = 1;
+        v.depth_img = channels[k].depth;
+      }
       if ((v.dL_dvbar || v.dL_drho) && g->n > 0 && !geoms[k].feat) {
         set_error("the velocity and staticness gradients need geom.feat of view %d", k);
         return PVG_ERR_INVALID;

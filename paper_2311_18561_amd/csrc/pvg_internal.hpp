@@ -55,6 +55,9 @@ struct View {
   float* rho_img;            // [H][W] staticness map
   const float* dL_dvbar;     // [3][H][W]
   const float* dL_drho;      // [H][W]
+  // depth_img holds sum T alpha z / sum T alpha (forward output; the adjoint
+  // reads it back to take the quotient's gradient)
+  int32_t depth_norm;
 };
 
 struct Geom {

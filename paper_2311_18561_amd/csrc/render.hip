@@ -151,12 +151,13 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
   tile_bounds(tx, ty, v.W, v.H, X0, X1, Y0, Y1);
   const uint64_t lt = (1ull << lane) - 1ull;
   float T[kPix], Cr[kPix], Cg[kPix], Cb[kPix], Dz[kPix], V0[kPix], V1[kPix], V2[kPix], Rh[kPix];
+  float Aw[kPix];  // sum T alpha, the normalized depth's denominator
   int last[kPix];
   bool act[kPix];
 #pragma unroll
   for (int k = 0; k < kPix; ++k) {
     T[k] = 1.0f; Cr[k] = 0.0f; Cg[k] = 0.0f; Cb[k] = 0.0f; last[k] = 0;
-    Dz[k] = 0.0f; V0[k] = 0.0f; V1[k] = 0.0f; V2[k] = 0.0f; Rh[k] = 0.0f;
+    Dz[k] = 0.0f; V0[k] = 0.0f; V1[k] = 0.0f; V2[k] = 0.0f; Rh[k] = 0.0f; Aw[k] = 0.0f;
     act[k] = px < v.W && py0 + 4 * k < v.H;
   }
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
@@ -218,6 +219,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
         Cb[k] = fmaf(cc.z, w, Cb[k]);
         if (kCh) {
           Dz[k] = fmaf(gz, w, Dz[k]);
+          Aw[k] += w;
           V0[k] = fmaf(gv.x, w, V0[k]);
           V1[k] = fmaf(gv.y, w, V1[k]);
           V2[k] = fmaf(gv.z, w, V2[k]);
@@ -242,7 +244,8 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
       v.final_T[o] = T[k];
       v.n_contrib[o] = last[k];
       if (kCh) {
-        if (v.depth_img) v.depth_img[o] = Dz[k];
+        // every contributor has alpha >= 1/255, so the sum is 0 exactly when none did
+        if (v.depth_img) v.depth_img[o] = !v.depth_norm ? Dz[k] : (Aw[k] > 0.0f ? Dz[k] / Aw[k] : 0.0f);
         if (v.vbar_img) {
           v.vbar_img[o] = V0[k];
           v.vbar_img[HW + o] = V1[k];
@@ -313,8 +316,18 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       gg[k] = v.dL_dimg[HW + o];
       gb[k] = v.dL_dimg[2 * HW + o];
       if (kCh) {
-        if (v.dL_ddepth) gd[k] = v.dL_ddepth[o];
         if (v.dL_dT) gt = v.dL_dT[o];
+        if (v.dL_ddepth) {
+          gd[k] = v.dL_ddepth[o];
+          if (v.depth_norm) {
+            // D / A with A = sum T alpha = 1 - final_T: d/dD = 1 / A and, the
+            // sum telescoping, d/d final_T = (D / A) / A
+            const float A = 1.0f - T[k];
+            const float ia = A > 0.0f ? 1.0f / A : 0.0f;
+            gt = fmaf(gd[k] * v.depth_img[o], ia, gt);
+            gd[k] *= ia;
+          }
+        }
         if (v.dL_dvbar) {
           gv0[k] = v.dL_dvbar[o];
           gv1[k] = v.dL_dvbar[HW + o];

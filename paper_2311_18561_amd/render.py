@@ -220,11 +220,12 @@ def bin_sort_nosync(geom: Geom, cam: L.Camera, capacity: int, tile_cull: bool = 
 
 
 def render_fwd(geom: Geom, bins: Bins, cam: L.Camera, frame: L.Frame, out=None, depth=None, vbar=None,
-               rho=None):
+               rho=None, depth_norm=False):
     """Composite one view; `out` (optional, contiguous [3,H,W] float32)
     receives the image, `depth` (optional, contiguous [H,W] float32) the
-    blended camera depth sum T alpha z, `vbar` ([3,H,W]) and `rho` ([H,W])
-    the velocity and staticness maps (these need a Geom with feat)."""
+    blended camera depth sum T alpha z (with depth_norm the normalized depth
+    sum T alpha z / sum T alpha), `vbar` ([3,H,W]) and `rho` ([H,W]) the
+    velocity and staticness maps (these need a Geom with feat)."""
     dev = geom.xy.device
     H, W = int(cam.height), int(cam.width)
     img = torch.empty((3, H, W), dtype=torch.float32, device=dev) if out is None else out
@@ -237,7 +238,7 @@ def render_fwd(geom: Geom, bins: Bins, cam: L.Camera, frame: L.Frame, out=None, 
     else:
         for t, shp in ((depth, (H, W)), (vbar, (3, H, W)), (rho, (H, W))):
             assert t is None or (t.is_contiguous() and t.shape == shp and t.dtype == torch.float32)
-        ch = L.Channels(_p(depth), None, None, _p(vbar), _p(rho), None, None)
+        ch = L.Channels(_p(depth), None, None, _p(vbar), _p(rho), None, None, 1 if depth_norm else 0)
         L.check(L.load().pvg_render_fwd_channels(C.byref(gs), C.byref(bs), C.byref(cam), C.byref(frame), _p(img),
                                                  _p(final_T), _p(n_contrib), C.byref(ch), _stream_handle()))
     return img, final_T, n_contrib
@@ -296,10 +297,11 @@ class _BwdViewsArgs:
                                                  max(v[3].capacity for v in views), C.byref(size)))
         self.tmp_bytes = int(size.value)
 
-    def call(self, dev, dimgs, grads, accumulate, ddepths=None, dTs=None, dvbars=None, drhos=None):
+    def call(self, dev, dimgs, grads, accumulate, ddepths=None, dTs=None, dvbars=None, drhos=None, depths=None):
         """ddepths / dTs / dvbars / drhos (optional, per view or None):
         upstream gradients of the depth channel, final_T, the velocity map
-        [3,H,W] and the staticness map."""
+        [3,H,W] and the staticness map.  depths (per view or None): the
+        forward's normalized depth, given when ddepths is that map's gradient."""
         gg = L.GaussiansGrad()
         for name, t in zip(FIELDS, grads):
             setattr(gg, name, t.data_ptr())
@@ -323,8 +325,9 @@ class _BwdViewsArgs:
                                                   _stream_handle()))
             return grads
         cont = [[None if d is None else d.contiguous() for d in x] for x in lists]
-        ch = (L.Channels * self.nv)(*[L.Channels(None, _p(a), _p(b), None, None, _p(c), _p(d))
-                                      for a, b, c, d in zip(*cont)])
+        dn = [None] * self.nv if depths is None else [None if d is None else d.contiguous() for d in depths]
+        ch = (L.Channels * self.nv)(*[L.Channels(_p(z), _p(a), _p(b), None, None, _p(c), _p(d), 0 if z is None else 1)
+                                      for z, a, b, c, d in zip(dn, *cont)])
         L.check(L.load().pvg_render_bwd_views_channels(C.byref(self.g), self.nv, self.cams, self.frames, self.geoms,
                                                        self.bins, self.f_t, self.n_c, d_l, ch, C.byref(gg),
                                                        1 if accumulate else 0, _p(tmp), int(tmp.numel()),
@@ -333,16 +336,18 @@ class _BwdViewsArgs:
 
 
 def render_bwd_views(params, n, degree, views, grads=None, accumulate=False, ddepths=None, dTs=None, dvbars=None,
-                     drhos=None):
+                     drhos=None, depths=None):
     """One adjoint call for several views of the same Gaussians:
     views = [(cam, frame, geom, bins, final_T, n_contrib, dL_dimg or None)];
     the per-Gaussian chain rule of all views is summed in registers and the
     gradient written (or added) once.  ddepths / dTs / dvbars / drhos:
-    optional per-view upstream gradients of the channels and of final_T."""
+    optional per-view upstream gradients of the channels and of final_T;
+    depths: per view, the forward's normalized depth when ddepths is its
+    gradient (None: ddepths is the gradient of sum T alpha z)."""
     if grads is None:
         grads = [torch.empty_like(p) for p in params]
     args = _BwdViewsArgs(params, n, degree, [v[:6] for v in views])
-    return args.call(params[0].device, [v[6] for v in views], grads, accumulate, ddepths, dTs, dvbars, drhos)
+    return args.call(params[0].device, [v[6] for v in views], grads, accumulate, ddepths, dTs, dvbars, drhos, depths)
 
 
 def render(params, cam: dict, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), tile_cull=True):
@@ -427,7 +432,8 @@ def _record(stream):
     return ev
 
 
-def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=None, vbars=None, rhos=None):
+def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=None, vbars=None, rhos=None,
+                   depth_norm=False):
     """Bin and composite view k on lane k mod VIEW_STREAMS, where lane 0 is
     the caller's stream and the others are side streams forked from it and
     joined back into it (the views' latency-bound sort and scan kernels
@@ -443,8 +449,8 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
     outgrew its cached capacity is redone.  With `stacked` ([V,3,H,W],
     allocated on the caller's stream) view k's image is written into
     stacked[k]; with `depths` ([V,H,W], the same) its depth channel into
-    depths[k], and likewise the velocity and staticness maps into vbars
-    ([V,3,H,W]) and rhos ([V,H,W])."""
+    depths[k] (the normalized depth with depth_norm), and likewise the
+    velocity and staticness maps into vbars ([V,3,H,W]) and rhos ([V,H,W])."""
     dev = params[0].device
     main = torch.cuda.current_stream(dev)
     side = _streams(dev)
@@ -480,7 +486,7 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
             fe.record(st)
             out = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k],
                              None if depths is None else depths[k], None if vbars is None else vbars[k],
-                             None if rhos is None else rhos[k])
+                             None if rhos is None else rhos[k], depth_norm)
             ev = None
             if st is not main:
                 ev = torch.cuda.Event()
@@ -505,7 +511,7 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
             plans[k][3] = bins
             outs[k] = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k],
                                  None if depths is None else depths[k], None if vbars is None else vbars[k],
-                                 None if rhos is None else rhos[k])
+                                 None if rhos is None else rhos[k], depth_norm)
     return plans, outs
 
 
@@ -554,7 +560,8 @@ class PVGRenderViews(torch.autograd.Function):
                 depths = torch.empty((V, H, W), dtype=torch.float32, device=dev)
                 vbars = torch.empty((V, 3, H, W), dtype=torch.float32, device=dev)
                 rhos = torch.empty((V, H, W), dtype=torch.float32, device=dev)
-        plans, outs = _forward_views(params, n, degree, views, tile_cull, stacked, depths, vbars, rhos)
+        norm = channels == 2
+        plans, outs = _forward_views(params, n, degree, views, tile_cull, stacked, depths, vbars, rhos, norm)
         if recompute == "auto":
             kept_bytes = sum(_bins_bytes(b) for _, _, _, b in plans)
             recompute = kept_bytes > KEEP_FRACTION * torch.cuda.get_device_properties(dev).total_memory
@@ -565,6 +572,8 @@ class PVGRenderViews(torch.autograd.Function):
         saved = list(params)
         for _, T, nc in outs:
             saved += [T, nc]
+        if norm:  # the quotient's adjoint reads the normalized depth back
+            saved.append(depths)
         ctx.save_for_backward(*saved)
         ctx.stack = stack
         ctx.channels = channels
@@ -587,6 +596,7 @@ class PVGRenderViews(torch.autograd.Function):
         saved = ctx.saved_tensors
         params = list(saved[:9])
         grads = [torch.empty_like(p) for p in params]
+        dn = saved[9 + 2 * len(plan)] if ctx.channels == 2 else None
         if recompute:
             # one view at a time, so only one view's lists exist at once; the
             # same inputs give the forward's lists bit for bit, within its capacity
@@ -595,22 +605,24 @@ class PVGRenderViews(torch.autograd.Function):
                 chk = [None if x is None else x[k] for x in (ddepths, dTs, dvbars, drhos)]
                 if dimgs[k] is None and all(x is None for x in chk):
                     continue
-                geom = preprocess(params, n, degree, c, f, feat=ctx.channels)
+                geom = preprocess(params, n, degree, c, f, feat=bool(ctx.channels))
                 bins = bin_sort_nosync(geom, c, cap, tile_cull)
                 render_bwd_views(params, n, degree, [(c, f, geom, bins, saved[9 + 2 * k], saved[10 + 2 * k],
                                                       dimgs[k])], grads=grads, accumulate=not first,
-                                 ddepths=[chk[0]], dTs=[chk[1]], dvbars=[chk[2]], drhos=[chk[3]])
+                                 ddepths=[chk[0]], dTs=[chk[1]], dvbars=[chk[2]], drhos=[chk[3]],
+                                 depths=None if dn is None else [dn[k]])
                 first = False
             if first:
                 for gr in grads:
                     gr.zero_()
         else:  # the kept lists, final_T and n_contrib, with the arguments built in the forward
             ctx.bwd.call(params[0].device, dimgs, grads, accumulate=False, ddepths=ddepths, dTs=dTs, dvbars=dvbars,
-                         drhos=drhos)
+                         drhos=drhos, depths=None if dn is None else [dn[k] for k in range(len(plan))])
         return (None, None, None, None, None, *grads)
 
 
-def pvg_render_views(params, views, recompute="auto", tile_cull=True, stack=False, channels=False):
+def pvg_render_views(params, views, recompute="auto", tile_cull=True, stack=False, channels=False,
+                     normalized_depth=False):
     """Differentiable renders of the nine parameter tensors for several views:
     views = [(cam, t), (cam, t, dt), ... or (cam, t, dt, advect_mode, bg)];
     returns one image [3,H,W] per view, or with stack=True (views of one
@@ -620,12 +632,17 @@ def pvg_render_views(params, views, recompute="auto", tile_cull=True, stack=Fals
     depth [V,H,W] = sum T alpha z, opacity [V,H,W] = sum T alpha = 1 -
     final_T, velocity map [V,3,H,W] = sum T alpha v~ with v~ = v exp(-beta /
     (2 l)), staticness map [V,H,W] = sum T alpha beta / l), all
-    differentiable; the normalized depth is depth / opacity."""
+    differentiable.  normalized_depth=True (with channels) returns the
+    normalized depth sum T alpha z / sum T alpha of Sec. 3.1 in place of the
+    depth (0 where no Gaussian reaches the pixel)."""
     full = _full_views(views)
     stack = bool(stack or channels)
     if stack and len({(int(v[0]["width"]), int(v[0]["height"])) for v in full}) != 1:
         raise ValueError("stack=True needs views of one resolution")
-    out = PVGRenderViews.apply(full, recompute, tile_cull, stack, bool(channels), *params)
+    if normalized_depth and not channels:
+        raise ValueError("normalized_depth needs channels=True")
+    mode = (2 if normalized_depth else 1) if channels else 0
+    out = PVGRenderViews.apply(full, recompute, tile_cull, stack, mode, *params)
     if channels:
         img, depth, final_T, vbar, rho = out
         return img, depth, 1.0 - final_T, vbar, rho

@@ -154,3 +154,68 @@ def test_velocity_staticness_only(orc):
         worst, l2 = grad_tolerance_report(p.grad.detach().cpu().numpy(), ref[f], rel=1e-3)
         print(f"[cfg0 velocity/staticness only] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
         assert worst <= 1.0, f
+
+
+@pytest.mark.parametrize("name,mk_scene,mk_cam,t,dts", CASES)
+@pytest.mark.parametrize("recompute", [False, True])
+def test_normalized_depth_vs_fp64(orc, name, mk_scene, mk_cam, t, dts, recompute):
+    """Normalized depth sum T alpha z / sum T alpha (Sec. 3.1) over two views.
+    Forward: against the oracle's FP64 blended depth over 1 - final_T, per
+    pixel within 5e-5 relative (FP32 sums of up to a few hundred positive
+    terms in numerator and denominator), 0 exactly where no Gaussian reaches.
+    Adjoint: L = sum w img + sum g Dn + sum wO opacity against the FP64
+    adjoint fed the quotient rule's (dD, dT); each element held to 1e-3 of
+    the sum of the |g*| of every view and every source (image, the quotient's
+    numerator and denominator terms, which cancel for a Gaussian at the
+    pixel's mean depth, and opacity)."""
+    import paper_2311_18561_amd as pvg
+    scene, cam = mk_scene(), mk_cam()
+    H, W = cam["height"], cam["width"]
+    rng = np.random.default_rng(21)
+    V = len(dts)
+    w = rng.standard_normal((V, 3, H, W)).astype(np.float32)
+    g = (0.05 * rng.standard_normal((V, H, W))).astype(np.float32)
+    wO = rng.standard_normal((V, H, W)).astype(np.float32)
+    params = [p.requires_grad_(True) for p in to_device(scene)]
+    views = [(cam, t, d) for d in dts]
+    img, dn, opac, _, _ = pvg.pvg_render_views(params, views, recompute=recompute, channels=True,
+                                               normalized_depth=True)
+    cu = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    ((img * cu(w)).sum() + (dn * cu(g)).sum() + (opac * cu(wO)).sum()).backward()
+    sc64 = orc.scene64(scene)
+    ref = {f: np.zeros_like(sc64[f]) for f in FIELDS}
+    mag = {f: np.zeros_like(sc64[f]) for f in FIELDS}
+    zero_img = np.zeros((3, H, W))
+    for k, d in enumerate(dts):
+        pre = orc.preprocess_f32(scene, cam, t, d)
+        bins = orc.bin_sort(pre, cam)
+        args = (sc64, cam, t, d, 0, (0.0, 0.0, 0.0), pre, bins)
+        _, _, T64, D64 = orc.render_f64(*args, want_depth=True)
+        want = orc.normalized_depth_f64(D64, T64)
+        got = dn[k].detach().cpu().numpy().astype(np.float64)
+        rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-30)
+        empty = T64 == 1.0
+        print(f"[{name} recompute={recompute} view {k}] normalized depth: max rel err = {rel[~empty].max():.3g}, "
+              f"empty pixels {int(empty.sum())}")
+        assert rel[~empty].max() <= 5e-5
+        assert np.all(got[empty] == 0.0)
+        dD, dT = orc.normalized_depth_bwd_f64(g[k], D64, T64)
+        w64, wO64 = w[k].astype(np.float64), wO[k].astype(np.float64)
+        total, _ = orc.backward_f64(*args, w64, dD=dD, dT=dT - wO64)
+        parts = [orc.backward_f64(*args, w64)[0], orc.backward_f64(*args, zero_img, dD=dD)[0],
+                 orc.backward_f64(*args, zero_img, dT=dT)[0], orc.backward_f64(*args, zero_img, dT=-wO64)[0]]
+        for f in FIELDS:
+            ref[f] += total[f]
+            mag[f] += sum(np.abs(p[f]) for p in parts)
+    for f, p in zip(FIELDS, params):
+        worst, l2 = grad_tolerance_report(p.grad.detach().cpu().numpy(), ref[f], rel=1e-3, magnitude=mag[f])
+        print(f"[{name} recompute={recompute} normalized depth] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+        assert worst <= 1.0, f
+
+
+def test_normalized_depth_needs_channels():
+    """The normalized depth is one of the channels: asking for it without
+    channels=True is an error rather than a plain image render."""
+    import paper_2311_18561_amd as pvg
+    with pytest.raises(ValueError):
+        pvg.pvg_render_views([], [], channels=False, normalized_depth=True)

@@ -494,6 +494,85 @@ def test_depth_channel_closed_form(orc):
     np.testing.assert_allclose(D64, z0 * (1.0 - T64), rtol=1e-12, atol=1e-12)
 
 
+def test_normalized_depth_closed_form_and_bounds(orc):
+    """Normalized depth (Sec. 3.1): with every Gaussian at one camera depth z0
+    it is z0 on every pixel a Gaussian reaches and 0 elsewhere; on a random
+    scene it is a convex combination of the contributors' depths, so it lies
+    between the smallest and the largest visible depth."""
+    cfg = gen.make_config(0)
+    cam, t = cfg["cameras"][0], cfg["t"]
+    sc = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in cfg["scene"].items()}
+    z0 = 6.5
+    sc["mu"][2] = z0
+    sc["vel"][2] = 0.0
+    sc = gen.subset_scene(sc, np.arange(40))  # leaves part of the image empty
+    pre = orc.preprocess_f32(sc, cam, t)
+    bins = orc.bin_sort(pre, cam)
+    _, _, T64, D64 = orc.render_f64(orc.scene64(sc), cam, t, 0.0, 0, (0, 0, 0), pre, bins, want_depth=True)
+    Dn = orc.normalized_depth_f64(D64, T64)
+    _, _, nc = orc.render_f32(pre, bins, cam, t)
+    hit = nc > 0
+    assert 0.05 < hit.mean() < 0.95
+    np.testing.assert_allclose(Dn[hit], z0, rtol=1e-12)
+    assert np.all(Dn[~hit] == 0.0)
+    # a random scene: sum T alpha z / sum T alpha within [min z, max z]
+    sc = cfg["scene"]
+    pre = orc.preprocess_f32(sc, cam, t)
+    bins = orc.bin_sort(pre, cam)
+    _, _, T64, D64 = orc.render_f64(orc.scene64(sc), cam, t, 0.0, 0, (0, 0, 0), pre, bins, want_depth=True)
+    Dn = orc.normalized_depth_f64(D64, T64)
+    _, _, nc = orc.render_f32(pre, bins, cam, t)
+    vis = pre["radius"] > 0
+    zmin, zmax = float(pre["depth"][vis].min()), float(pre["depth"][vis].max())
+    hit = nc > 0
+    assert np.all(Dn[hit] >= zmin * (1 - 1e-6)) and np.all(Dn[hit] <= zmax * (1 + 1e-6))
+    assert Dn[hit].std() > 0.1  # not a constant
+
+
+def test_normalized_depth_adjoint_matches_finite_differences(orc):
+    """L = sum w img + sum g D / A (A = sum T alpha): finite differences of the
+    FP64 render against the FP64 adjoint fed with normalized_depth_bwd_f64's
+    (dD, dT), sampled entries of every field of the visible Gaussians."""
+    sc = gen.make_scene(30, 7, sh_degree=1)
+    cam = gen.yaw_camera(64, 48, 10.0, (0.2, 0.1, -0.5))
+    t = 0.45
+    pre = orc.preprocess_f32(sc, cam, t)
+    bins = orc.bin_sort(pre, cam)
+    s64 = orc.scene64(sc)
+    H, W = cam["height"], cam["width"]
+    rng = np.random.default_rng(4)
+    w = rng.standard_normal((3, H, W))
+    g = rng.standard_normal((H, W))
+
+    def loss():
+        _, img, T, D = orc.render_f64(s64, cam, t, 0.0, 0, (0, 0, 0), pre, bins, want_depth=True)
+        return float(np.sum(w * img) + np.sum(g * orc.normalized_depth_f64(D, T)))
+
+    _, _, T0, D0 = orc.render_f64(s64, cam, t, 0.0, 0, (0, 0, 0), pre, bins, want_depth=True)
+    dD, dT = orc.normalized_depth_bwd_f64(g, D0, T0)
+    grads, _ = orc.backward_f64(s64, cam, t, 0.0, 0, (0, 0, 0), pre, bins, w, dD=dD, dT=dT)
+    vis = np.nonzero(pre["radius"] > 0)[0]
+    checked = 0
+    for f in orc.FIELDS:
+        arr = s64[f].reshape(-1, sc["n"])
+        gr = grads[f].reshape(-1, sc["n"])
+        rms = np.sqrt(np.mean(gr[:, vis] ** 2))
+        entries = [(r, i) for r in range(arr.shape[0]) for i in vis]
+        for j in rng.choice(len(entries), min(25, len(entries)), replace=False):
+            r, i = entries[j]
+            old = arr[r, i]
+            h = 1e-4 * max(1.0, abs(old))
+            L = {}
+            for k in (-2, -1, 1, 2):
+                arr[r, i] = old + k * h
+                L[k] = loss()
+            arr[r, i] = old
+            fd = (8 * (L[1] - L[-1]) - (L[2] - L[-2])) / (12 * h)
+            assert abs(fd - gr[r, i]) <= 1e-6 * max(abs(gr[r, i]), 1e-2 * rms), (f, r, i, fd, gr[r, i])
+            checked += 1
+    assert checked >= 150
+
+
 def test_velocity_and_staticness_maps_closed_form(orc):
     """With v = 0 the velocity map is exactly 0; with beta / l = rho0 for
     every Gaussian the staticness map is rho0 * (1 - final_T) (FP64 to
