@@ -299,11 +299,14 @@ def main():
         loss.backward()
         return loss
 
-    # the step with the flexible-rendering channels (Sec. 3.1) in the loss: L1
-    # on the images plus an inverse-depth L1 against a sparse synthetic depth
-    # target (5% of the pixels, standing in for projected LiDAR), the opacity
-    # entropy term with a synthetic sky mask (the top eighth of each view) and
-    # the sparse velocity term on the velocity map, weights 0.1, 0.01, 0.01
+    # the step with the flexible-rendering channels (Sec. 3.1) and the sky
+    # (Sec. 3.4) in the loss: each view composited over a learnable cube map
+    # (faces of 1024 x 1024, rays jittered inside their pixel each step), L1
+    # on the composite plus an L1 on the inverse normalized depth against a
+    # sparse synthetic target (5% of the pixels, standing in for projected
+    # LiDAR), the opacity entropy term with a synthetic sky mask (the top
+    # eighth of each view) and the sparse velocity term on the velocity map,
+    # weights 0.1, 0.01, 0.01
     gch = torch.Generator(device="cuda").manual_seed(7)
     V = len(views)
     sparse = (torch.rand((V, H, W), device="cuda", generator=gch) < 0.05).float()
@@ -311,13 +314,18 @@ def main():
     sky = torch.zeros((V, H, W), device="cuda")
     sky[:, : H // 8] = 1.0
 
+    cube = torch.full((6, 3, 1024, 1024), 0.5, device="cuda").requires_grad_(True)
+
     def train_step_channels():
         for p in params:
             p.grad = None
-        imgs, depth, opac, vbar, _ = pvg.pvg_render_views(params, views, channels=True)
+        cube.grad = None
+        imgs, dn, opac, vbar, _ = pvg.pvg_render_views(params, views, channels=True, normalized_depth=True)
+        jit = torch.rand((V, 2, H, W), device="cuda", generator=gch) - 0.5
+        final = torch.stack([pvg.pvg_sky_composite(imgs[k], opac[k], cube, views[k][0], jit[k]) for k in range(V)])
         o = opac.clamp(1e-6, 1.0 - 1e-6)
-        inv = o / depth.clamp_min(1e-6)  # the inverse of the normalized depth depth / O
-        loss = ((imgs - stacked_targets).abs().mean() * V + 0.1 * (sparse * (inv - inv_depth_target).abs()).mean()
+        inv = 1.0 / dn.clamp_min(1e-3)  # the inverse of the normalized depth
+        loss = ((final - stacked_targets).abs().mean() * V + 0.1 * (sparse * (inv - inv_depth_target).abs()).mean()
                 + 0.01 * (-(o * o.log()).mean() - (sky * (1.0 - o).log()).mean()) + 0.01 * vbar.abs().mean())
         loss.backward()
         return loss
@@ -482,10 +490,12 @@ def main():
         "mpix_per_s_fwd": mpix_fwd,
         "iters_per_s_recompute": args.steps / t_recompute,
         "iters_per_s_channels": args.steps / t_channels,
-        "channels_note": ("the same step with pvg_render_views(channels=True): depth sum T alpha z, opacity "
-                          "1 - final_T, velocity and staticness maps rendered; an inverse-depth L1 on 5% of the "
-                          "pixels, the opacity entropy term with a sky mask and the sparse velocity term added to "
-                          "the loss (synthetic targets)"),
+        "channels_note": ("the same step with pvg_render_views(channels=True, normalized_depth=True): normalized "
+                          "depth sum T alpha z / sum T alpha, opacity 1 - final_T, velocity and staticness maps "
+                          "rendered, each view composited over a learnable 6 x 3 x 1024 x 1024 sky cube map with "
+                          "jittered rays (pvg_sky_composite, its gradient into the cube map included); L1 on the "
+                          "composite, an inverse-depth L1 on 5% of the pixels, the opacity entropy term with a sky "
+                          "mask and the sparse velocity term (synthetic targets)"),
         "lists": "kept from the forward (recompute='auto': they fit in a tenth of HBM)",
         "instances_per_render": {"rectangle": M, "listed": Lst, "adjoint_records": visited},
         "visible_per_render": n_vis,

@@ -1,8 +1,14 @@
 // Sky composite of the sky refinement (Sec. 3.4): C_f = C + (1 - O) f_sky(d),
 // where f_sky is a learnable cube map looked up in the pixel's world-frame
 // viewing direction, optionally jittered inside the pixel.  One thread per
-// pixel; the adjoint adds each pixel's bilinear weights times (1 - O) dL/dC_f
-// into the cube map's gradient with float atomics and writes dL/dO.
+// pixel; the adjoint writes dL/dO and adds each pixel's bilinear weights
+// times (1 - O) dL/dC_f into the cube map's gradient.  Neighbouring pixels
+// share texels (a high-resolution image has several pixels per texel), so the
+// adjoint runs on 16 x 16 pixel tiles: each tile sums its contributions to
+// the texel box it covers on its first pixel's face in LDS and adds the box
+// to global memory once per texel and channel; pixels on another face, or a
+// box beyond kSkyBox texels (a tile across a face edge or a coarse map seen
+// at a grazing angle), add to global memory directly.
 //
 // Conventions: d_cam = ((px + 1/2 + jx - cx) / fx, (py + 1/2 + jy - cy) / fy,
 // 1), d = R^T d_cam; faces +X, -X, +Y, -Y, +Z, -Z (0..5) by the largest |d_i|
@@ -10,6 +16,8 @@
 // (u R - 1/2, v R - 1/2), bilinear inside the face with the coordinates
 // clamped to [0, R - 1]; cube [6][3][R][R].  The geometry is FP32 without
 // contraction, so the face and texel decisions are the oracle's.
+#include <climits>
+
 #include "pvg_math.hpp"
 
 namespace pvg {
@@ -72,30 +80,79 @@ __global__ void __launch_bounds__(256) k_sky_fwd(SkyView c, const float* __restr
   }
 }
 
+constexpr int kSkyBox = 1024;  // texels of a tile's LDS box (3 channels: 12 KiB)
+
+// One workgroup per 16 x 16 pixel tile (GX tiles per image row).
 __global__ void __launch_bounds__(256) k_sky_bwd(SkyView c, const float* __restrict__ g,
                                                  const float* __restrict__ opac, const float* __restrict__ cube,
-                                                 int Rn, const float* __restrict__ jitter, float* dopac, float* dcube) {
+                                                 int Rn, const float* __restrict__ jitter, float* dopac, float* dcube,
+                                                 int GX) {
+  __shared__ float s_acc[3 * kSkyBox];
+  __shared__ int s_box[5];  // the tile's face, then min x, min y, max x, max y of its texels there
   const int64_t HW = static_cast<int64_t>(c.W) * c.H;
-  const int64_t o = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (o >= HW) return;
-  const int px = static_cast<int>(o % c.W), py = static_cast<int>(o / c.W);
-  int face, idx[4];
-  float w[4];
-  sky_taps(c, px, py, jitter, HW, o, Rn, face, idx, w);
   const int64_t F = static_cast<int64_t>(Rn) * Rn;
-  const float t = 1.0f - opac[o];
-  float dO = 0.0f;
-  for (int ch = 0; ch < 3; ++ch) {
-    const float* cf = cube + (face * 3 + ch) * F;
-    float* df = dcube + (face * 3 + ch) * F;
-    const float gc = g[ch * HW + o];
-    const float s = ((w[0] * cf[idx[0]] + w[1] * cf[idx[1]]) + w[2] * cf[idx[2]]) + w[3] * cf[idx[3]];
-    dO -= s * gc;
-    const float tg = t * gc;
-    for (int k = 0; k < 4; ++k)
-      if (w[k] != 0.0f) atomicAdd(&df[idx[k]], w[k] * tg);
+  const int tx = static_cast<int>(blockIdx.x % GX), ty = static_cast<int>(blockIdx.x / GX);
+  const int px = tx * 16 + static_cast<int>(threadIdx.x & 15), py = ty * 16 + static_cast<int>(threadIdx.x >> 4);
+  const bool in = px < c.W && py < c.H;  // always true for thread 0: a tile starts inside the image
+  const int64_t o = static_cast<int64_t>(py) * c.W + px;
+  int face = -1, idx[4] = {0, 0, 0, 0};
+  float w[4] = {0.0f, 0.0f, 0.0f, 0.0f}, tg[3] = {0.0f, 0.0f, 0.0f};
+  if (in) {
+    sky_taps(c, px, py, jitter, HW, o, Rn, face, idx, w);
+    const float t = 1.0f - opac[o];
+    float dO = 0.0f;
+    for (int ch = 0; ch < 3; ++ch) {
+      const float* cf = cube + (face * 3 + ch) * F;
+      const float gc = g[ch * HW + o];
+      const float s = ((w[0] * cf[idx[0]] + w[1] * cf[idx[1]]) + w[2] * cf[idx[2]]) + w[3] * cf[idx[3]];
+      dO -= s * gc;
+      tg[ch] = t * gc;
+    }
+    dopac[o] = dO;
   }
-  dopac[o] = dO;
+  if (threadIdx.x == 0) {
+    s_box[0] = face;
+    s_box[1] = INT_MAX; s_box[2] = INT_MAX; s_box[3] = -1; s_box[4] = -1;
+  }
+  __syncthreads();
+  const int f0 = s_box[0];
+  const bool mine = in && face == f0;
+  if (mine) {  // taps span [x0, x1] x [y0, y1]: idx[0] and idx[3]
+    atomicMin(&s_box[1], idx[0] % Rn);
+    atomicMin(&s_box[2], idx[0] / Rn);
+    atomicMax(&s_box[3], idx[3] % Rn);
+    atomicMax(&s_box[4], idx[3] / Rn);
+  }
+  __syncthreads();
+  const int bx = s_box[1], by = s_box[2];
+  const int bw = s_box[3] - bx + 1, bh = s_box[4] - by + 1;  // >= 1: thread 0 is in the box
+  const int area = bw * bh;
+  const bool lds = area <= kSkyBox;  // uniform over the workgroup
+  if (lds) {
+    for (int i = threadIdx.x; i < 3 * area; i += 256) s_acc[i] = 0.0f;
+    __syncthreads();
+  }
+  if (in) {
+    for (int ch = 0; ch < 3; ++ch)
+      for (int k = 0; k < 4; ++k) {
+        if (w[k] == 0.0f) continue;
+        const float val = w[k] * tg[ch];
+        if (lds && mine)
+          atomicAdd(&s_acc[ch * area + (idx[k] / Rn - by) * bw + (idx[k] % Rn - bx)], val);
+        else
+          atomicAdd(&dcube[(face * 3 + ch) * F + idx[k]], val);
+      }
+  }
+  if (lds) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * area; i += 256) {
+      const float val = s_acc[i];
+      if (val == 0.0f) continue;
+      const int ch = i / area, r = i - ch * area;
+      const int yy = by + r / bw, xx = bx + r % bw;
+      atomicAdd(&dcube[(f0 * 3 + ch) * F + static_cast<int64_t>(yy) * Rn + xx], val);
+    }
+  }
 }
 
 static SkyView sky_view(const pvg_camera* cam) {
@@ -119,8 +176,9 @@ hipError_t launch_sky_bwd(const pvg_camera* cam, const float* g, const float* op
                           const float* jitter, float* dopac, float* dcube, hipStream_t s) {
   const int64_t HW = static_cast<int64_t>(cam->width) * cam->height;
   if (HW == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sky_bwd, dim3(static_cast<unsigned>((HW + 255) / 256)), dim3(256), 0, s, sky_view(cam), g,
-                     opac, cube, Rn, jitter, dopac, dcube);
+  const int GX = (cam->width + 15) / 16, GY = (cam->height + 15) / 16;
+  hipLaunchKernelGGL(k_sky_bwd, dim3(static_cast<unsigned>(GX) * static_cast<unsigned>(GY)), dim3(256), 0, s,
+                     sky_view(cam), g, opac, cube, Rn, jitter, dopac, dcube, GX);
   return hipGetLastError();
 }
 

@@ -20,8 +20,12 @@ def _needs_gpu():
 
 
 @pytest.mark.parametrize("jitter", [False, True])
-@pytest.mark.parametrize("res", [1, 7, 64])
+@pytest.mark.parametrize("res", [1, 7, 64, 1024])
 def test_sky_composite_vs_oracle(orc, jitter, res):
+    """The view crosses the +Z / +X face edge.  The adjoint sums a tile's
+    texels in LDS when they fit its box (cube sizes up to 64 here, several
+    pixels per texel) and adds to global memory directly otherwise (1024:
+    several texels per pixel, and the tiles across the face edge)."""
     import paper_2311_18561_amd as pvg
     cam = gen.yaw_camera(200, 136, 40.0, (0.0, 0.0, 0.0))
     H, W = cam["height"], cam["width"]
