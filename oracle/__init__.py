@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pvg_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 FIELDS = ("mu", "scale", "rot", "sh", "opacity", "vel", "period", "tau", "beta")
+from . import adaptive  # noqa: E402,F401  (adaptive control: numpy, no C)
 TILE = 16
 
 
