@@ -82,10 +82,17 @@ typedef struct pvg_gaussians {
   const float* beta;    /* [n] lifespan beta > 0 */
 } pvg_gaussians;
 
-/* Gradients in the layout of pvg_gaussians (device, written or accumulated). */
+/* Gradients in the layout of pvg_gaussians (device, written or accumulated).
+ * densify_grad and densify_count (optional, both or neither, device [n]):
+ * the statistics of the adaptive control (Sec. 3.3).  For every view of the
+ * call in which Gaussian i is visible, the adjoint adds the norm of the
+ * gradient of the loss with respect to its 2D mean in normalized device
+ * coordinates, |(W/2 dL/dx, H/2 dL/dy)| with (x, y) in pixels, to
+ * densify_grad[i] and 1 to densify_count[i]; they are never cleared. */
 typedef struct pvg_gaussians_grad {
   float* mu; float* scale; float* rot; float* sh; float* opacity;
   float* vel; float* period; float* tau; float* beta;
+  float* densify_grad; float* densify_count;
 } pvg_gaussians_grad;
 
 typedef struct pvg_camera { /* host struct, passed by pointer */
@@ -280,6 +287,53 @@ int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const
                                   const float* const* dL_dimg, const pvg_channels* channels,
                                   pvg_gaussians_grad* grad, int32_t accumulate, void* tmp,
                                   size_t tmp_bytes, void* stream);
+/* Position-aware adaptive control (Sec. 3.3, Eq. (9), and the split rules
+ * of the implementation details in the appendix).  gamma(mu) = 1 if |mu| <
+ * 2 r, else |mu| / r - 1.  A Gaussian whose mean view-space gradient
+ * densify_grad / densify_count (0 when the count is 0; see
+ * pvg_gaussians_grad) is at least grad_threshold is cloned when max(s) <=
+ * clone_scale * gamma(mu) and split otherwise.  Any Gaussian, new ones
+ * included, is pruned when max(s) > prune_scale * gamma(mu) or o <
+ * min_opacity.  A clone copies every parameter.  A split replaces the
+ * Gaussian by two children k = 0, 1: scale split_scale_decay * s, tau + dtau,
+ * beta split_beta_decay * beta, mean mu + R(q) (s * eps_k) + dtau v~, with
+ * dtau = beta eps_k3 and v~ = v exp(-beta / (2 l)).  All decisions are FP32. */
+typedef struct pvg_densify_config {
+  float grad_threshold;     /* view-space gradient threshold (1.7e-4 in the paper) */
+  float scene_radius;       /* r of Eq. (9), > 0 */
+  float clone_scale;        /* g */
+  float prune_scale;        /* b */
+  float min_opacity;        /* also prune o < min_opacity; 0 disables */
+  float split_scale_decay;  /* 0.8 in the paper */
+  float split_beta_decay;   /* 1, or 0.8 in the later part of training */
+} pvg_densify_config;
+
+/* Workspace of a densify pass over n Gaussians (n <= 2^30). */
+int pvg_densify_tmp_bytes(int64_t n, size_t* bytes);
+
+/* Decide every Gaussian's outputs and count them: writes the plan into tmp
+ * and the number of Gaussians after the pass into *n_out (host), then
+ * returns; synchronizes `stream` to read the count.  noise: device [8][n]
+ * standard normal draws (rows 4k .. 4k+2: child k's position offset in
+ * units of s along the Gaussian's axes; row 4k+3: its dtau / beta), read
+ * only for split Gaussians.  grad_accum / grad_count: device [n] statistics.
+ * PVG_ERR_INVALID on null pointers, a non-finite threshold or r <= 0;
+ * PVG_ERR_NOMEM when tmp_bytes is short. */
+int pvg_densify_plan(const pvg_gaussians* g, const float* grad_accum, const float* grad_count, const float* noise,
+                     const pvg_densify_config* cfg, void* tmp, size_t tmp_bytes, int64_t* n_out, void* stream);
+
+/* Write the pass planned in tmp (same g, noise and cfg) into `out`, whose
+ * arrays (device, caller-owned, written) hold out->n = *n_out Gaussians of
+ * the same sh_degree.  Order: by parent index; within a parent the kept
+ * original, its clone, then its split children.  extra_in [n_extra][n] ->
+ * extra_out [n_extra][n_out] carry further per-Gaussian rows (optimizer
+ * state): copied for a kept original, zero for every new Gaussian.
+ * PVG_ERR_INVALID when out->n differs from the plan's count (checked before
+ * any write; synchronizes `stream`). */
+int pvg_densify_apply(const pvg_gaussians* g, const float* noise, const pvg_densify_config* cfg, const void* tmp,
+                      size_t tmp_bytes, const pvg_gaussians* out, int32_t n_extra, const float* extra_in,
+                      float* extra_out, void* stream);
+
 /* Sky refinement (Sec. 3.4): out = img + (1 - opacity) * f_sky(d), with f_sky
  * a learnable cube map `cube` [6][3][cube_res][cube_res] (faces +X, -X, +Y,
  * -Y, +Z, -Z; channel; row v; column u) looked up bilinearly, inside the face,

@@ -34,7 +34,13 @@ class Gaussians(C.Structure):
 
 class GaussiansGrad(C.Structure):
     _fields_ = [("mu", vp), ("scale", vp), ("rot", vp), ("sh", vp), ("opacity", vp), ("vel", vp),
-                ("period", vp), ("tau", vp), ("beta", vp)]
+                ("period", vp), ("tau", vp), ("beta", vp), ("densify_grad", vp), ("densify_count", vp)]
+
+
+class DensifyConfig(C.Structure):
+    _fields_ = [("grad_threshold", C.c_float), ("scene_radius", C.c_float), ("clone_scale", C.c_float),
+                ("prune_scale", C.c_float), ("min_opacity", C.c_float), ("split_scale_decay", C.c_float),
+                ("split_beta_decay", C.c_float)]
 
 
 class Camera(C.Structure):
@@ -127,6 +133,10 @@ def load():
         "pvg_render_bwd_views": ([P(Gaussians), i32, P(Camera), P(Frame), P(Geom), P(Bins), P(vp), P(vp), P(vp),
                                   P(GaussiansGrad), i32, vp, C.c_size_t, vp], i32),
         "pvg_bwd_views_tmp_bytes": ([i64, i32, i32, i32, i64, P(C.c_size_t)], i32),
+        "pvg_densify_tmp_bytes": ([i64, P(C.c_size_t)], i32),
+        "pvg_densify_plan": ([P(Gaussians), vp, vp, vp, P(DensifyConfig), vp, C.c_size_t, P(i64), vp], i32),
+        "pvg_densify_apply": ([P(Gaussians), vp, P(DensifyConfig), vp, C.c_size_t, P(Gaussians), i32, vp, vp, vp],
+                              i32),
         "pvg_profile_enable": ([i32], i32),
         "pvg_profile_collect": ([], i32),
         "pvg_profile_read": ([i32, P(C.c_double), P(i64), P(i64)], i32),

@@ -388,6 +388,10 @@ int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const
     set_error("a gradient array is null");
     return PVG_ERR_INVALID;
   }
+  if ((grad->densify_grad == nullptr) != (grad->densify_count == nullptr)) {
+    set_error("densify_grad and densify_count go together");
+    return PVG_ERR_INVALID;
+  }
   int64_t max_tiles = 1, max_cap = 0;
   for (int32_t k = 0; k < n_views; ++k) {
     if (!check_camera(&cams[k]) || !check_frame(&frames[k]) || !check_geom(&geoms[k], g->n) ||
@@ -536,6 +540,80 @@ int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const
     PVG_HIP(launch_fill_f32(grad->tau, 0.0f, n, s));
     PVG_HIP(launch_fill_f32(grad->beta, 0.0f, n, s));
   }
+  return PVG_OK;
+}
+
+namespace {
+bool check_densify(const pvg_densify_config* c) {
+  if (!c) { set_error("config is null"); return false; }
+  const float v[7] = {c->grad_threshold, c->scene_radius, c->clone_scale, c->prune_scale, c->min_opacity,
+                      c->split_scale_decay, c->split_beta_decay};
+  for (float x : v)
+    if (!std::isfinite(x)) { set_error("a densify threshold is not finite"); return false; }
+  if (!(c->scene_radius > 0.0f)) { set_error("scene_radius must be > 0"); return false; }
+  return true;
+}
+pvg::DensifyCfg densify_cfg(const pvg_densify_config* c) {
+  return pvg::DensifyCfg{c->grad_threshold, c->scene_radius, c->clone_scale, c->prune_scale, c->min_opacity,
+                         c->split_scale_decay, c->split_beta_decay};
+}
+pvg::Scene scene_of(const pvg_gaussians* g) {
+  return pvg::Scene{g->mu, g->scale, g->rot, g->sh, g->opacity, g->vel, g->period, g->tau, g->beta, g->n,
+                    g->sh_degree};
+}
+constexpr int64_t kMaxDensifyN = int64_t(1) << 30;  // outputs (at most 2 n) keep 32-bit offsets
+}  // namespace
+
+int pvg_densify_tmp_bytes(int64_t n, size_t* bytes) {
+  if (!bytes || n < 0 || n > kMaxDensifyN) { set_error("n outside [0, 2^30] or null output"); return PVG_ERR_INVALID; }
+  *bytes = pvg::densify_tmp_bytes(n);
+  return PVG_OK;
+}
+
+int pvg_densify_plan(const pvg_gaussians* g, const float* grad_accum, const float* grad_count, const float* noise,
+                     const pvg_densify_config* cfg, void* tmp, size_t tmp_bytes, int64_t* n_out, void* stream) {
+  if (!check_gaussians(g) || !check_densify(cfg)) return PVG_ERR_INVALID;
+  if (g->n > kMaxDensifyN) { set_error("n exceeds 2^30"); return PVG_ERR_INVALID; }
+  if (!n_out || !tmp || (g->n > 0 && (!grad_accum || !grad_count || !noise))) {
+    set_error("a statistics, noise, workspace or output pointer is null");
+    return PVG_ERR_INVALID;
+  }
+  if (tmp_bytes < pvg::densify_tmp_bytes(g->n)) { set_error("tmp_bytes too small"); return PVG_ERR_NOMEM; }
+  auto s = static_cast<hipStream_t>(stream);
+  PVG_HIP(pvg::launch_densify_plan(scene_of(g), grad_accum, grad_count, noise, densify_cfg(cfg), tmp, s));
+  unsigned long long total = 0;
+  PVG_HIP(hipMemcpyAsync(&total, pvg::densify_total_ptr(tmp, g->n), sizeof(total), hipMemcpyDeviceToHost, s));
+  PVG_HIP(hipStreamSynchronize(s));
+  *n_out = static_cast<int64_t>(total);
+  return PVG_OK;
+}
+
+int pvg_densify_apply(const pvg_gaussians* g, const float* noise, const pvg_densify_config* cfg, const void* tmp,
+                      size_t tmp_bytes, const pvg_gaussians* out, int32_t n_extra, const float* extra_in,
+                      float* extra_out, void* stream) {
+  if (!check_gaussians(g) || !check_gaussians(out) || !check_densify(cfg)) return PVG_ERR_INVALID;
+  if (g->n > kMaxDensifyN) { set_error("n exceeds 2^30"); return PVG_ERR_INVALID; }
+  if (out->sh_degree != g->sh_degree) { set_error("out.sh_degree differs from the input's"); return PVG_ERR_INVALID; }
+  if (!tmp || (g->n > 0 && !noise) || n_extra < 0 ||
+      (n_extra > 0 && ((g->n > 0 && !extra_in) || (out->n > 0 && !extra_out)))) {
+    set_error("noise, workspace or extra rows missing, or n_extra < 0");
+    return PVG_ERR_INVALID;
+  }
+  if (tmp_bytes < pvg::densify_tmp_bytes(g->n)) { set_error("tmp_bytes too small"); return PVG_ERR_NOMEM; }
+  auto s = static_cast<hipStream_t>(stream);
+  unsigned long long total = 0;
+  PVG_HIP(hipMemcpyAsync(&total, pvg::densify_total_ptr(const_cast<void*>(tmp), g->n), sizeof(total),
+                         hipMemcpyDeviceToHost, s));
+  PVG_HIP(hipStreamSynchronize(s));
+  if (static_cast<int64_t>(total) != out->n) {
+    set_error("out.n = %lld but the plan produces %llu Gaussians", static_cast<long long>(out->n), total);
+    return PVG_ERR_INVALID;
+  }
+  const pvg::SceneOut so{const_cast<float*>(out->mu), const_cast<float*>(out->scale), const_cast<float*>(out->rot),
+                         const_cast<float*>(out->sh), const_cast<float*>(out->opacity), const_cast<float*>(out->vel),
+                         const_cast<float*>(out->period), const_cast<float*>(out->tau), const_cast<float*>(out->beta),
+                         out->n, out->sh_degree};
+  PVG_HIP(pvg::launch_densify_apply(scene_of(g), noise, densify_cfg(cfg), tmp, so, extra_in, extra_out, n_extra, s));
   return PVG_OK;
 }
 

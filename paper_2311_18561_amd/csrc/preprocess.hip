@@ -275,12 +275,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     acc.tau = grad.tau[i];
     acc.beta = grad.beta[i];
   }
+  float dnorm = 0.0f, dcount = 0.0f;  // view-space gradient statistics of the adaptive control
   for (int v = 0; v < pk.nv; ++v) {
     if (pk.radius[v][i] <= 0) continue;
+    if (grad.densify_grad) {  // |dL / d(mean in NDC)|, NDC = 2 (pixel / size) - 1
+      const float* g = pk.g2d[v] + kG2DStride * i;
+      const float gx = g[0] * (0.5f * static_cast<float>(pk.views[v].W));
+      const float gy = g[1] * (0.5f * static_cast<float>(pk.views[v].H));
+      dnorm += sqrtf(gx * gx + gy * gy);
+      dcount += 1.0f;
+    }
     Proj P;
     project(pk.views[v], i, P, false);
     view_direction(pk.views[v], P);
     adjoint_geometry(pk.views[v], i, P, pk.rgb[v] + 3 * i, pk.g2d[v] + kG2DStride * i, acc);
+  }
+  if (grad.densify_grad) {
+    grad.densify_grad[i] += dnorm;
+    grad.densify_count[i] += dcount;
   }
   for (int q = 0; q < 3; ++q) {
     grad.mu[q * n + i] = acc.mu[q];

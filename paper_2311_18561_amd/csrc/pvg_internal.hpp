@@ -184,6 +184,24 @@ constexpr int kBwdStreams = 3;
 size_t bwd_scratch_bytes(int64_t n, int32_t views, int32_t regions, int64_t capacity, size_t* off_rec,
                          size_t* off_vis, size_t* vis_bytes, size_t* slot_bytes, size_t* region_bytes);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+// Adaptive control (Sec. 3.3): thresholds of one densify/prune pass.
+struct DensifyCfg {
+  float grad_threshold, radius, clone_scale, prune_scale, min_opacity, scale_decay, beta_decay;
+};
+// Writable parameter arrays of the pass's output (n = its Gaussian count).
+struct SceneOut {
+  float* mu; float* scale; float* rot; float* sh; float* opacity;
+  float* vel; float* period; float* tau; float* beta;
+  int64_t n;
+  int32_t degree;
+};
+size_t densify_tmp_bytes(int64_t n);
+hipError_t launch_densify_plan(const Scene& s, const float* gacc, const float* gcnt, const float* noise,
+                               const DensifyCfg& c, void* tmp, hipStream_t st);
+unsigned long long* densify_total_ptr(void* tmp, int64_t n);
+hipError_t launch_densify_apply(const Scene& s, const float* noise, const DensifyCfg& c, const void* tmp,
+                                const SceneOut& out, const float* extra_in, float* extra_out, int32_t n_extra,
+                                hipStream_t st);
 hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 
 // binning: scratch layout and the sort pipeline

@@ -297,14 +297,19 @@ class _BwdViewsArgs:
                                                  max(v[3].capacity for v in views), C.byref(size)))
         self.tmp_bytes = int(size.value)
 
-    def call(self, dev, dimgs, grads, accumulate, ddepths=None, dTs=None, dvbars=None, drhos=None, depths=None):
+    def call(self, dev, dimgs, grads, accumulate, ddepths=None, dTs=None, dvbars=None, drhos=None, depths=None,
+             stats=None):
         """ddepths / dTs / dvbars / drhos (optional, per view or None):
         upstream gradients of the depth channel, final_T, the velocity map
         [3,H,W] and the staticness map.  depths (per view or None): the
-        forward's normalized depth, given when ddepths is that map's gradient."""
+        forward's normalized depth, given when ddepths is that map's gradient.
+        stats: optional (accum, count) [N] tensors that receive the view-space
+        gradient statistics of the adaptive control."""
         gg = L.GaussiansGrad()
         for name, t in zip(FIELDS, grads):
             setattr(gg, name, t.data_ptr())
+        if stats is not None:
+            gg.densify_grad, gg.densify_count = stats[0].data_ptr(), stats[1].data_ptr()
         lists = [list(x) if x is not None else [None] * self.nv for x in (ddepths, dTs, dvbars, drhos)]
         ddepths, dTs, dvbars, drhos = lists
         has = [any(x[k] is not None for x in lists) for k in range(self.nv)]
@@ -336,7 +341,7 @@ class _BwdViewsArgs:
 
 
 def render_bwd_views(params, n, degree, views, grads=None, accumulate=False, ddepths=None, dTs=None, dvbars=None,
-                     drhos=None, depths=None):
+                     drhos=None, depths=None, stats=None):
     """One adjoint call for several views of the same Gaussians:
     views = [(cam, frame, geom, bins, final_T, n_contrib, dL_dimg or None)];
     the per-Gaussian chain rule of all views is summed in registers and the
@@ -347,7 +352,8 @@ def render_bwd_views(params, n, degree, views, grads=None, accumulate=False, dde
     if grads is None:
         grads = [torch.empty_like(p) for p in params]
     args = _BwdViewsArgs(params, n, degree, [v[:6] for v in views])
-    return args.call(params[0].device, [v[6] for v in views], grads, accumulate, ddepths, dTs, dvbars, drhos, depths)
+    return args.call(params[0].device, [v[6] for v in views], grads, accumulate, ddepths, dTs, dvbars, drhos, depths,
+                     stats)
 
 
 def render(params, cam: dict, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), tile_cull=True):
@@ -549,7 +555,7 @@ class PVGRenderViews(torch.autograd.Function):
     the lists when they fit KEEP_FRACTION of the device memory."""
 
     @staticmethod
-    def forward(ctx, views, recompute, tile_cull, stack, channels, *tensors):
+    def forward(ctx, views, recompute, tile_cull, stack, channels, stats, *tensors):
         params, n, degree = _check_params(list(tensors))
         dev = params[0].device
         stacked = depths = vbars = rhos = None
@@ -577,6 +583,7 @@ class PVGRenderViews(torch.autograd.Function):
         ctx.save_for_backward(*saved)
         ctx.stack = stack
         ctx.channels = channels
+        ctx.stats = stats
         if channels:  # images, depth, final_T, velocity and staticness maps, each stacked over the views
             return stacked, depths, torch.stack([T for _, T, _ in outs]), vbars, rhos
         if stack:
@@ -610,19 +617,20 @@ class PVGRenderViews(torch.autograd.Function):
                 render_bwd_views(params, n, degree, [(c, f, geom, bins, saved[9 + 2 * k], saved[10 + 2 * k],
                                                       dimgs[k])], grads=grads, accumulate=not first,
                                  ddepths=[chk[0]], dTs=[chk[1]], dvbars=[chk[2]], drhos=[chk[3]],
-                                 depths=None if dn is None else [dn[k]])
+                                 depths=None if dn is None else [dn[k]], stats=ctx.stats)
                 first = False
             if first:
                 for gr in grads:
                     gr.zero_()
         else:  # the kept lists, final_T and n_contrib, with the arguments built in the forward
             ctx.bwd.call(params[0].device, dimgs, grads, accumulate=False, ddepths=ddepths, dTs=dTs, dvbars=dvbars,
-                         drhos=drhos, depths=None if dn is None else [dn[k] for k in range(len(plan))])
-        return (None, None, None, None, None, *grads)
+                         drhos=drhos, depths=None if dn is None else [dn[k] for k in range(len(plan))],
+                         stats=ctx.stats)
+        return (None, None, None, None, None, None, *grads)
 
 
 def pvg_render_views(params, views, recompute="auto", tile_cull=True, stack=False, channels=False,
-                     normalized_depth=False):
+                     normalized_depth=False, densify_stats=None):
     """Differentiable renders of the nine parameter tensors for several views:
     views = [(cam, t), (cam, t, dt), ... or (cam, t, dt, advect_mode, bg)];
     returns one image [3,H,W] per view, or with stack=True (views of one
@@ -634,7 +642,11 @@ def pvg_render_views(params, views, recompute="auto", tile_cull=True, stack=Fals
     (2 l)), staticness map [V,H,W] = sum T alpha beta / l), all
     differentiable.  normalized_depth=True (with channels) returns the
     normalized depth sum T alpha z / sum T alpha of Sec. 3.1 in place of the
-    depth (0 where no Gaussian reaches the pixel)."""
+    depth (0 where no Gaussian reaches the pixel).  densify_stats: optional
+    (accum, count), contiguous float32 [N] tensors on the parameters' device,
+    to which the backward adds, per view in which a Gaussian is visible, the
+    norm of its view-space (NDC) mean gradient and 1 (the statistics of the
+    adaptive control, Sec. 3.3)."""
     full = _full_views(views)
     stack = bool(stack or channels)
     if stack and len({(int(v[0]["width"]), int(v[0]["height"])) for v in full}) != 1:
@@ -642,7 +654,13 @@ def pvg_render_views(params, views, recompute="auto", tile_cull=True, stack=Fals
     if normalized_depth and not channels:
         raise ValueError("normalized_depth needs channels=True")
     mode = (2 if normalized_depth else 1) if channels else 0
-    out = PVGRenderViews.apply(full, recompute, tile_cull, stack, mode, *params)
+    if densify_stats is not None:
+        n = params[0].shape[1]
+        for t in densify_stats:
+            if t.shape != (n,) or t.dtype != torch.float32 or not t.is_contiguous() or t.device != params[0].device:
+                raise ValueError("densify_stats must be two contiguous float32 [N] tensors on the parameters' device")
+        densify_stats = tuple(densify_stats)
+    out = PVGRenderViews.apply(full, recompute, tile_cull, stack, mode, densify_stats, *params)
     if channels:
         img, depth, final_T, vbar, rho = out
         return img, depth, 1.0 - final_T, vbar, rho
