@@ -306,8 +306,12 @@ def main():
     # sparse synthetic target (5% of the pixels, standing in for projected
     # LiDAR), the opacity entropy term with a synthetic sky mask (the top
     # eighth of each view) and the sparse velocity term on the velocity map,
-    # weights 0.1, 0.01, 0.01
+    # weights 0.1, 0.05, 0.01 (Sec. 4); the backward also accumulates the
+    # view-space gradient statistics of the adaptive control (Sec. 3.3), as
+    # every training iteration of the densification phase does
     gch = torch.Generator(device="cuda").manual_seed(7)
+    d_acc = torch.zeros(N, device="cuda")
+    d_cnt = torch.zeros(N, device="cuda")
     V = len(views)
     sparse = (torch.rand((V, H, W), device="cuda", generator=gch) < 0.05).float()
     inv_depth_target = sparse / (5.0 + 45.0 * torch.rand((V, H, W), device="cuda", generator=gch))
@@ -320,13 +324,14 @@ def main():
         for p in params:
             p.grad = None
         cube.grad = None
-        imgs, dn, opac, vbar, _ = pvg.pvg_render_views(params, views, channels=True, normalized_depth=True)
+        imgs, dn, opac, vbar, _ = pvg.pvg_render_views(params, views, channels=True, normalized_depth=True,
+                                                       densify_stats=(d_acc, d_cnt))
         jit = torch.rand((V, 2, H, W), device="cuda", generator=gch) - 0.5
         final = torch.stack([pvg.pvg_sky_composite(imgs[k], opac[k], cube, views[k][0], jit[k]) for k in range(V)])
         o = opac.clamp(1e-6, 1.0 - 1e-6)
         inv = 1.0 / dn.clamp_min(1e-3)  # the inverse of the normalized depth
         loss = ((final - stacked_targets).abs().mean() * V + 0.1 * (sparse * (inv - inv_depth_target).abs()).mean()
-                + 0.01 * (-(o * o.log()).mean() - (sky * (1.0 - o).log()).mean()) + 0.01 * vbar.abs().mean())
+                + 0.05 * (-(o * o.log()).mean() - (sky * (1.0 - o).log()).mean()) + 0.01 * vbar.abs().mean())
         loss.backward()
         return loss
 
@@ -419,6 +424,39 @@ def main():
         train_step_channels()
     torch.cuda.synchronize()
     t_channels = time.perf_counter() - t0
+    ch_steps = []  # the same step timed one at a time (a rare slow step, e.g. a new allocation, shows as an outlier)
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        train_step_channels()
+        torch.cuda.synchronize()
+        ch_steps.append(time.perf_counter() - t0)
+    ch_med = sorted(ch_steps)[len(ch_steps) // 2]
+
+    # one adaptive-control pass (Sec. 3.3) on the statistics those steps
+    # accumulated: r = 30 m (the foreground radius of Sec. 4), the densify
+    # threshold 1.7e-4, g = 0.01 r, b = 0.1 r; the Adam moments of every
+    # parameter row (2 x 65 rows) are carried along
+    rows = sum(p.numel() // N for p in params)
+    dcfg = pvg.densify_config(30.0)
+    dnoise = torch.randn((8, N), device="cuda", generator=gch)
+    moments = torch.zeros((2 * rows, N), device="cuda")
+    new_params, _ = pvg.densify(params, d_acc, d_cnt, dnoise, dcfg, moments)  # warm
+    n_after = int(new_params[0].shape[1])
+    del new_params
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        new_params, new_m = pvg.densify(params, d_acc, d_cnt, dnoise, dcfg, moments)
+        del new_params, new_m
+    torch.cuda.synchronize()
+    t_dens = (time.perf_counter() - t0) / reps
+    # algorithmic bytes: the decisions read mean, scale, opacity and the two
+    # statistics (36 B) and write a code byte; each output Gaussian reads its
+    # parent's rows and moments and writes its own (rows and moments: 4 B x
+    # (rows + 2 rows) each way)
+    dens_bytes = N * (36 + 1) + N + n_after * 2 * 4 * 3 * rows
 
     # forward-only rate over the three H(t) renders
     torch.cuda.synchronize()
@@ -490,12 +528,19 @@ def main():
         "mpix_per_s_fwd": mpix_fwd,
         "iters_per_s_recompute": args.steps / t_recompute,
         "iters_per_s_channels": args.steps / t_channels,
+        "iters_per_s_channels_median_step": 1.0 / ch_med,
+        "densify": {"ms_per_pass": t_dens * 1e3, "gaussians_in": N, "gaussians_out": n_after,
+                    "statistics_views": int(d_cnt.max().item()), "GB_per_s": dens_bytes / t_dens / 1e9,
+                    "note": ("pvg_densify_plan + pvg_densify_apply on the channel steps' statistics (r = 30, "
+                             "threshold 1.7e-4, g = 0.01 r, b = 0.1 r), Adam moments carried; wall time per pass "
+                             "including the count read-back and the output allocation")},
         "channels_note": ("the same step with pvg_render_views(channels=True, normalized_depth=True): normalized "
                           "depth sum T alpha z / sum T alpha, opacity 1 - final_T, velocity and staticness maps "
                           "rendered, each view composited over a learnable 6 x 3 x 1024 x 1024 sky cube map with "
                           "jittered rays (pvg_sky_composite, its gradient into the cube map included); L1 on the "
                           "composite, an inverse-depth L1 on 5% of the pixels, the opacity entropy term with a sky "
-                          "mask and the sparse velocity term (synthetic targets)"),
+                          "mask and the sparse velocity term, weights 0.1, 0.05, 0.01 (synthetic targets); the "
+                          "backward also accumulates the adaptive control's view-space gradient statistics"),
         "lists": "kept from the forward (recompute='auto': they fit in a tenth of HBM)",
         "instances_per_render": {"rectangle": M, "listed": Lst, "adjoint_records": visited},
         "visible_per_render": n_vis,

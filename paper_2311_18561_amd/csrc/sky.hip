@@ -28,8 +28,11 @@ struct SkyView {
   int32_t W, H;
 };
 
+// Face, the four taps' texel columns tx[k & 1] and rows ty[k >> 1], their
+// flat indices inside the face, and the bilinear weights.
 __device__ __forceinline__ void sky_taps(const SkyView& c, int px, int py, const float* __restrict__ jitter,
-                                         int64_t HW, int64_t o, int Rn, int& face, int idx[4], float w[4]) {
+                                         int64_t HW, int64_t o, int Rn, int& face, int tx[2], int ty[2], int idx[4],
+                                         float w[4]) {
   const float jx = jitter ? jitter[o] : 0.0f, jy = jitter ? jitter[HW + o] : 0.0f;
   const float c0 = ((static_cast<float>(px) + 0.5f) + jx - c.cx) / c.fx;
   const float c1 = ((static_cast<float>(py) + 0.5f) + jy - c.cy) / c.fy;
@@ -54,6 +57,7 @@ __device__ __forceinline__ void sky_taps(const SkyView& c, int px, int py, const
   const float y = fminf(fmaxf(v * static_cast<float>(Rn) - 0.5f, 0.0f), rm);
   const int x0 = min(max(static_cast<int>(floorf(x)), 0), Rn - 1), y0 = min(max(static_cast<int>(floorf(y)), 0), Rn - 1);
   const int x1 = min(x0 + 1, Rn - 1), y1 = min(y0 + 1, Rn - 1);
+  tx[0] = x0; tx[1] = x1; ty[0] = y0; ty[1] = y1;
   const float fx = x - static_cast<float>(x0), fy = y - static_cast<float>(y0);
   idx[0] = y0 * Rn + x0; w[0] = (1.0f - fx) * (1.0f - fy);
   idx[1] = y0 * Rn + x1; w[1] = fx * (1.0f - fy);
@@ -68,9 +72,9 @@ __global__ void __launch_bounds__(256) k_sky_fwd(SkyView c, const float* __restr
   const int64_t o = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (o >= HW) return;
   const int px = static_cast<int>(o % c.W), py = static_cast<int>(o / c.W);
-  int face, idx[4];
+  int face, tx[2], ty[2], idx[4];
   float w[4];
-  sky_taps(c, px, py, jitter, HW, o, Rn, face, idx, w);
+  sky_taps(c, px, py, jitter, HW, o, Rn, face, tx, ty, idx, w);
   const int64_t F = static_cast<int64_t>(Rn) * Rn;
   const float t = 1.0f - opac[o];
   for (int ch = 0; ch < 3; ++ch) {
@@ -95,10 +99,10 @@ __global__ void __launch_bounds__(256) k_sky_bwd(SkyView c, const float* __restr
   const int px = tx * 16 + static_cast<int>(threadIdx.x & 15), py = ty * 16 + static_cast<int>(threadIdx.x >> 4);
   const bool in = px < c.W && py < c.H;  // always true for thread 0: a tile starts inside the image
   const int64_t o = static_cast<int64_t>(py) * c.W + px;
-  int face = -1, idx[4] = {0, 0, 0, 0};
+  int face = -1, tx[2] = {0, 0}, ty[2] = {0, 0}, idx[4] = {0, 0, 0, 0};
   float w[4] = {0.0f, 0.0f, 0.0f, 0.0f}, tg[3] = {0.0f, 0.0f, 0.0f};
   if (in) {
-    sky_taps(c, px, py, jitter, HW, o, Rn, face, idx, w);
+    sky_taps(c, px, py, jitter, HW, o, Rn, face, tx, ty, idx, w);
     const float t = 1.0f - opac[o];
     float dO = 0.0f;
     for (int ch = 0; ch < 3; ++ch) {
@@ -117,11 +121,11 @@ __global__ void __launch_bounds__(256) k_sky_bwd(SkyView c, const float* __restr
   __syncthreads();
   const int f0 = s_box[0];
   const bool mine = in && face == f0;
-  if (mine) {  // taps span [x0, x1] x [y0, y1]: idx[0] and idx[3]
-    atomicMin(&s_box[1], idx[0] % Rn);
-    atomicMin(&s_box[2], idx[0] / Rn);
-    atomicMax(&s_box[3], idx[3] % Rn);
-    atomicMax(&s_box[4], idx[3] / Rn);
+  if (mine) {  // the taps span [tx[0], tx[1]] x [ty[0], ty[1]]
+    atomicMin(&s_box[1], tx[0]);
+    atomicMin(&s_box[2], ty[0]);
+    atomicMax(&s_box[3], tx[1]);
+    atomicMax(&s_box[4], ty[1]);
   }
   __syncthreads();
   const int bx = s_box[1], by = s_box[2];
@@ -138,7 +142,7 @@ __global__ void __launch_bounds__(256) k_sky_bwd(SkyView c, const float* __restr
         if (w[k] == 0.0f) continue;
         const float val = w[k] * tg[ch];
         if (lds && mine)
-          atomicAdd(&s_acc[ch * area + (idx[k] / Rn - by) * bw + (idx[k] % Rn - bx)], val);
+          atomicAdd(&s_acc[ch * area + (ty[k >> 1] - by) * bw + (tx[k & 1] - bx)], val);
         else
           atomicAdd(&dcube[(face * 3 + ch) * F + idx[k]], val);
       }
