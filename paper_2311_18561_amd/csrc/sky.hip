@@ -95,8 +95,9 @@ __global__ void __launch_bounds__(256) k_sky_bwd(SkyView c, const float* __restr
   __shared__ int s_box[5];  // the tile's face, then min x, min y, max x, max y of its texels there
   const int64_t HW = static_cast<int64_t>(c.W) * c.H;
   const int64_t F = static_cast<int64_t>(Rn) * Rn;
-  const int tx = static_cast<int>(blockIdx.x % GX), ty = static_cast<int>(blockIdx.x / GX);
-  const int px = tx * 16 + static_cast<int>(threadIdx.x & 15), py = ty * 16 + static_cast<int>(threadIdx.x >> 4);
+  const int tile_x = static_cast<int>(blockIdx.x % GX), tile_y = static_cast<int>(blockIdx.x / GX);
+  const int px = tile_x * 16 + static_cast<int>(threadIdx.x & 15);
+  const int py = tile_y * 16 + static_cast<int>(threadIdx.x >> 4);
   const bool in = px < c.W && py < c.H;  // always true for thread 0: a tile starts inside the image
   const int64_t o = static_cast<int64_t>(py) * c.W + px;
   int face = -1, tx[2] = {0, 0}, ty[2] = {0, 0}, idx[4] = {0, 0, 0, 0};
