@@ -22,6 +22,7 @@ _SRC = os.path.join(_HERE, "pvg_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 FIELDS = ("mu", "scale", "rot", "sh", "opacity", "vel", "period", "tau", "beta")
 from . import adaptive  # noqa: E402,F401  (adaptive control: numpy, no C)
+from . import optim  # noqa: E402,F401  (Adam step: numpy, no C)
 TILE = 16
 
 
