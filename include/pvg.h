@@ -334,6 +334,28 @@ int pvg_densify_apply(const pvg_gaussians* g, const float* noise, const pvg_dens
                       size_t tmp_bytes, const pvg_gaussians* out, int32_t n_extra, const float* extra_in,
                       float* extra_out, void* stream);
 
+/* Adam (Sec. 4: Adam with per-parameter learning rates) over every
+ * parameter array of `params` (device, updated in place) with the gradients
+ * `grad` of the activated values.  The step is taken in the unconstrained
+ * space of each array: log s, logit o, log l, log beta, and the values
+ * themselves for mu, q, SH, v and tau (the gradient chained there: s dL/ds,
+ * o (1 - o) dL/do, ...).  m, v: device [17 + 3K][n] moments in the order mu
+ * (3 rows), scale (3), rot (4), sh (3K), opacity, vel (3), period, tau, beta;
+ * zero before the first step.  lr: mu, scale, rot, SH degree 0, SH higher
+ * degrees, opacity, vel, period, tau, beta; a zero rate still updates the
+ * moments.  step t >= 1 sets the bias corrections 1 - beta1^t, 1 - beta2^t. */
+typedef struct pvg_adam_config {
+  float lr[10];
+  float beta1, beta2, eps;
+  int32_t step;
+} pvg_adam_config;
+int pvg_adam_step(const pvg_gaussians* params, const pvg_gaussians_grad* grad, float* m, float* v,
+                  const pvg_adam_config* cfg, void* stream);
+
+/* Opacity reset (Sec. 4): o = min(o, cap) and the opacity row of the Adam
+ * moments cleared. */
+int pvg_opacity_reset(const pvg_gaussians* params, float* m, float* v, float cap, void* stream);
+
 /* Sky refinement (Sec. 3.4): out = img + (1 - opacity) * f_sky(d), with f_sky
  * a learnable cube map `cube` [6][3][cube_res][cube_res] (faces +X, -X, +Y,
  * -Y, +Z, -Z; channel; row v; column u) looked up bilinearly, inside the face,

@@ -10,6 +10,7 @@ device memory and streams.
 """
 from ._lib import PVGError, load  # noqa: F401
 from .densify import densify, densify_config  # noqa: F401
+from .optim import PVGAdam, default_lrs  # noqa: F401
 from .render import (  # noqa: F401
     FIELDS,
     PVGRender,

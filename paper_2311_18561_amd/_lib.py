@@ -37,6 +37,11 @@ class GaussiansGrad(C.Structure):
                 ("period", vp), ("tau", vp), ("beta", vp), ("densify_grad", vp), ("densify_count", vp)]
 
 
+class AdamConfig(C.Structure):
+    _fields_ = [("lr", C.c_float * 10), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("step", C.c_int32)]
+
+
 class DensifyConfig(C.Structure):
     _fields_ = [("grad_threshold", C.c_float), ("scene_radius", C.c_float), ("clone_scale", C.c_float),
                 ("prune_scale", C.c_float), ("min_opacity", C.c_float), ("split_scale_decay", C.c_float),
@@ -134,6 +139,8 @@ def load():
                                   P(GaussiansGrad), i32, vp, C.c_size_t, vp], i32),
         "pvg_bwd_views_tmp_bytes": ([i64, i32, i32, i32, i64, P(C.c_size_t)], i32),
         "pvg_densify_tmp_bytes": ([i64, P(C.c_size_t)], i32),
+        "pvg_adam_step": ([P(Gaussians), P(GaussiansGrad), vp, vp, P(AdamConfig), vp], i32),
+        "pvg_opacity_reset": ([P(Gaussians), vp, vp, C.c_float, vp], i32),
         "pvg_densify_plan": ([P(Gaussians), vp, vp, vp, P(DensifyConfig), vp, C.c_size_t, P(i64), vp], i32),
         "pvg_densify_apply": ([P(Gaussians), vp, P(DensifyConfig), vp, C.c_size_t, P(Gaussians), i32, vp, vp, vp],
                               i32),

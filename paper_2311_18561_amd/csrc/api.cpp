@@ -617,6 +617,46 @@ int pvg_densify_apply(const pvg_gaussians* g, const float* noise, const pvg_dens
   return PVG_OK;
 }
 
+int pvg_adam_step(const pvg_gaussians* params, const pvg_gaussians_grad* grad, float* m, float* v,
+                  const pvg_adam_config* cfg, void* stream) {
+  if (!check_gaussians(params)) return PVG_ERR_INVALID;
+  if (!cfg || cfg->step < 1 || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
+      !(cfg->eps > 0.0f)) {
+    set_error("config: step >= 1, beta1 and beta2 in [0, 1), eps > 0");
+    return PVG_ERR_INVALID;
+  }
+  for (float lr : cfg->lr)
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) { set_error("learning rates must be finite and >= 0"); return PVG_ERR_INVALID; }
+  if (params->n > 0 && (!grad || !m || !v || !grad->mu || !grad->scale || !grad->rot || !grad->sh ||
+                        !grad->opacity || !grad->vel || !grad->period || !grad->tau || !grad->beta)) {
+    set_error("a gradient or moment array is null");
+    return PVG_ERR_INVALID;
+  }
+  pvg::AdamCfg c;
+  for (int k = 0; k < 10; ++k) c.lr[k] = cfg->lr[k];
+  c.beta1 = cfg->beta1; c.beta2 = cfg->beta2; c.eps = cfg->eps;
+  c.bc1 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta1), cfg->step));
+  c.bc2 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta2), cfg->step));
+  const pvg::SceneOut so{const_cast<float*>(params->mu), const_cast<float*>(params->scale),
+                         const_cast<float*>(params->rot), const_cast<float*>(params->sh),
+                         const_cast<float*>(params->opacity), const_cast<float*>(params->vel),
+                         const_cast<float*>(params->period), const_cast<float*>(params->tau),
+                         const_cast<float*>(params->beta), params->n, params->sh_degree};
+  PVG_HIP(pvg::launch_adam(so, params->n > 0 ? *grad : pvg_gaussians_grad{}, m, v, c,
+                           static_cast<hipStream_t>(stream)));
+  return PVG_OK;
+}
+
+int pvg_opacity_reset(const pvg_gaussians* params, float* m, float* v, float cap, void* stream) {
+  if (!check_gaussians(params)) return PVG_ERR_INVALID;
+  if (!std::isfinite(cap) || (params->n > 0 && (!m || !v))) { set_error("cap not finite or moments null"); return PVG_ERR_INVALID; }
+  const int64_t n = params->n, K = (params->sh_degree + 1) * (params->sh_degree + 1);
+  const int64_t row = 3 + 3 + 4 + 3 * K;  // the opacity row of the moments
+  PVG_HIP(pvg::launch_opacity_reset(const_cast<float*>(params->opacity), m + row * n, v + row * n, n, cap,
+                                    static_cast<hipStream_t>(stream)));
+  return PVG_OK;
+}
+
 int pvg_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (on && !g_work_dev) {

@@ -196,6 +196,16 @@ struct SceneOut {
   int32_t degree;
 };
 size_t densify_tmp_bytes(int64_t n);
+// Adam over the parameter rows (learning rates: mu, scale, rot, SH degree 0,
+// SH higher degrees, opacity, vel, period, tau, beta); bc1 = 1 - beta1^t,
+// bc2 = 1 - beta2^t.
+struct AdamCfg {
+  float lr[10];
+  float beta1, beta2, eps, bc1, bc2;
+};
+hipError_t launch_adam(const SceneOut& s, const pvg_gaussians_grad& g, float* m, float* v, const AdamCfg& c,
+                       hipStream_t st);
+hipError_t launch_opacity_reset(float* o, float* m_row, float* v_row, int64_t n, float cap, hipStream_t st);
 hipError_t launch_densify_plan(const Scene& s, const float* gacc, const float* gcnt, const float* noise,
                                const DensifyCfg& c, void* tmp, hipStream_t st);
 unsigned long long* densify_total_ptr(void* tmp, int64_t n);

@@ -1,0 +1,74 @@
+"""Fused Adam over the Gaussians (Sec. 4: Adam with per-parameter learning
+rates; the opacity reset) on the library's kernels.  Argument marshalling
+only: the update runs in ``pvg_adam_step``."""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+from .render import FIELDS, _check_params, _p, _stream_handle, gaussians_struct
+
+# order of the learning rates in pvg_adam_config
+LR_KEYS = ("mu", "scale", "rot", "sh0", "shN", "opacity", "vel", "period", "tau", "beta")
+
+
+def default_lrs(scene_radius: float) -> dict:
+    """The paper's rates for v (1e-3), beta (0.02) and o (0.005); the others
+    as in 3DGS (mean 1.6e-4 times the scene extent, scale 5e-3, rotation
+    1e-3, SH 2.5e-3 and 2.5e-3 / 20 above degree 0); tau 1e-3; the cycle
+    length l fixed (a scene-wide hyper-parameter in the paper)."""
+    return {"mu": 1.6e-4 * float(scene_radius), "scale": 5e-3, "rot": 1e-3, "sh0": 2.5e-3, "shN": 2.5e-3 / 20,
+            "opacity": 0.005, "vel": 1e-3, "period": 0.0, "tau": 1e-3, "beta": 0.02}
+
+
+class PVGAdam:
+    """Adam state for one set of Gaussians: moments [2, 17 + 3K, N] (m then
+    v, rows in the parameter order), the step count and the rates.  step()
+    updates the nine parameter tensors in place from their .grad;
+    reset_opacity() caps o and clears its moments; the moments travel
+    through densify as its carried rows (``moments_rows()``)."""
+
+    def __init__(self, params, lrs: dict, betas=(0.9, 0.999), eps=1e-15):
+        params, n, degree = _check_params(list(params))
+        rows = sum(p.numel() // max(n, 1) for p in params) if n else 17 + 3 * (degree + 1) ** 2
+        self.moments = torch.zeros((2, rows, n), dtype=torch.float32, device=params[0].device)
+        self.lrs = dict(lrs)
+        self.betas, self.eps, self.t = betas, eps, 0
+
+    def _cfg(self):
+        c = L.AdamConfig()
+        for k, key in enumerate(LR_KEYS):
+            c.lr[k] = float(self.lrs[key])
+        c.beta1, c.beta2, c.eps, c.step = float(self.betas[0]), float(self.betas[1]), float(self.eps), self.t
+        return c
+
+    def step(self, params, grads=None):
+        params, n, degree = _check_params(list(params))
+        grads = [p.grad for p in params] if grads is None else list(grads)
+        if any(g is None or g.shape != p.shape or not g.is_contiguous() for g, p in zip(grads, params)):
+            raise ValueError("every parameter needs a contiguous gradient of its shape")
+        if self.moments.shape[2] != n:
+            raise ValueError("the moments were sized for another Gaussian count (carry them through densify)")
+        self.t += 1
+        gs = gaussians_struct(params, n, degree)
+        gg = L.GaussiansGrad()
+        for name, t in zip(FIELDS, grads):
+            setattr(gg, name, t.data_ptr())
+        c = self._cfg()
+        L.check(L.load().pvg_adam_step(C.byref(gs), C.byref(gg), _p(self.moments[0]), _p(self.moments[1]),
+                                       C.byref(c), _stream_handle()))
+
+    def reset_opacity(self, params, cap=0.01):
+        params, n, degree = _check_params(list(params))
+        gs = gaussians_struct(params, n, degree)
+        L.check(L.load().pvg_opacity_reset(C.byref(gs), _p(self.moments[0]), _p(self.moments[1]), float(cap),
+                                           _stream_handle()))
+
+    def moments_rows(self):
+        """The moments as [2 (17 + 3K), N] rows for densify's extra rows."""
+        return self.moments.reshape(-1, self.moments.shape[2])
+
+    def set_moments_rows(self, rows):
+        self.moments = rows.reshape(2, -1, rows.shape[1]).contiguous()
