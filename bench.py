@@ -433,6 +433,36 @@ def main():
         ch_steps.append(time.perf_counter() - t0)
     ch_med = sorted(ch_steps)[len(ch_steps) // 2]
 
+    # a whole training iteration: the channel step followed by the fused Adam
+    # step over all 65 parameter rows (Sec. 4 rates); on copies of the
+    # parameters, so the other measurements see the same scene
+    train_params = [p.detach().clone().requires_grad_(True) for p in params]
+    adam = pvg.PVGAdam(train_params, pvg.default_lrs(30.0))
+
+    def train_iteration():
+        for p in train_params:
+            p.grad = None
+        cube.grad = None
+        imgs, dn, opac, vbar, _ = pvg.pvg_render_views(train_params, views, channels=True, normalized_depth=True,
+                                                       densify_stats=(d_acc, d_cnt))
+        jit = torch.rand((V, 2, H, W), device="cuda", generator=gch) - 0.5
+        final = torch.stack([pvg.pvg_sky_composite(imgs[k], opac[k], cube, views[k][0], jit[k]) for k in range(V)])
+        o = opac.clamp(1e-6, 1.0 - 1e-6)
+        inv = 1.0 / dn.clamp_min(1e-3)
+        loss = ((final - stacked_targets).abs().mean() * V + 0.1 * (sparse * (inv - inv_depth_target).abs()).mean()
+                + 0.05 * (-(o * o.log()).mean() - (sky * (1.0 - o).log()).mean()) + 0.01 * vbar.abs().mean())
+        loss.backward()
+        adam.step(train_params)
+
+    train_iteration()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        train_iteration()
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    del train_params, adam
+
     # one adaptive-control pass (Sec. 3.3) on the statistics those steps
     # accumulated: r = 30 m (the foreground radius of Sec. 4), the densify
     # threshold 1.7e-4, g = 0.01 r, b = 0.1 r; the Adam moments of every
@@ -529,6 +559,10 @@ def main():
         "iters_per_s_recompute": args.steps / t_recompute,
         "iters_per_s_channels": args.steps / t_channels,
         "iters_per_s_channels_median_step": 1.0 / ch_med,
+        "iters_per_s_full_iteration": args.steps / t_full,
+        "full_iteration_note": ("the channel step followed by pvg_adam_step over all parameter rows (Sec. 4 rates; "
+                                "the cube map is not updated); SSIM and the temporal-smoothing sampling are not in "
+                                "it: the six views are rendered every iteration"),
         "densify": {"ms_per_pass": t_dens * 1e3, "gaussians_in": N, "gaussians_out": n_after,
                     "statistics_views": int(d_cnt.max().item()), "GB_per_s": dens_bytes / t_dens / 1e9,
                     "note": ("pvg_densify_plan + pvg_densify_apply on the channel steps' statistics (r = 30, "
