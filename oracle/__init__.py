@@ -23,6 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 FIELDS = ("mu", "scale", "rot", "sh", "opacity", "vel", "period", "tau", "beta")
 from . import adaptive  # noqa: E402,F401  (adaptive control: numpy, no C)
 from . import optim  # noqa: E402,F401  (Adam step: numpy, no C)
+from . import ssim  # noqa: E402,F401  (SSIM loss term: numpy and scipy, no C)
 TILE = 16
 
 
