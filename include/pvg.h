@@ -356,6 +356,24 @@ int pvg_adam_step(const pvg_gaussians* params, const pvg_gaussians_grad* grad, f
  * moments cleared. */
 int pvg_opacity_reset(const pvg_gaussians* params, float* m, float* v, float cap, void* stream);
 
+/* SSIM term of the training loss (Sec. 3.4 objective, weight lambda_r):
+ * the structural similarity of Wang et al. per channel and pixel, with an 11
+ * x 11 Gaussian window (sigma 1.5, normalised), zero padding outside the
+ * image and C1 = 0.01^2, C2 = 0.03^2 (values in [0, 1]):
+ *   S = (2 mx my + C1)(2 sxy + C2) / ((mx^2 + my^2 + C1)(sxx + syy + C2)).
+ * x (the render) and y (the target): device [channels][height][width].
+ * ssim_map (optional, may be NULL): S, same layout.  partials: device
+ * [3][channels][height][width] written for pvg_ssim_bwd (dS/dmx,
+ * dS/d(G*x^2), dS/d(G*xy)).  PVG_ERR_INVALID on sizes outside 1..65535 or
+ * null arrays. */
+int pvg_ssim_fwd(const float* x, const float* y, int32_t channels, int32_t height, int32_t width, float* ssim_map,
+                 float* partials, void* stream);
+
+/* Adjoint of pvg_ssim_fwd with respect to x: dL_dx [C][H][W] (written) from
+ * dL_dssim [C][H][W] and the forward's x, y and partials. */
+int pvg_ssim_bwd(const float* dL_dssim, const float* x, const float* y, const float* partials, int32_t channels,
+                 int32_t height, int32_t width, float* dL_dx, void* stream);
+
 /* Sky refinement (Sec. 3.4): out = img + (1 - opacity) * f_sky(d), with f_sky
  * a learnable cube map `cube` [6][3][cube_res][cube_res] (faces +X, -X, +Y,
  * -Y, +Z, -Z; channel; row v; column u) looked up bilinearly, inside the face,

@@ -25,6 +25,7 @@ from .render import (  # noqa: F401
     pvg_render,
     pvg_render_views,
     pvg_sky_composite,
+    pvg_ssim,
     render,
     render_bwd,
     render_fwd,

@@ -141,6 +141,8 @@ def load():
         "pvg_densify_tmp_bytes": ([i64, P(C.c_size_t)], i32),
         "pvg_adam_step": ([P(Gaussians), P(GaussiansGrad), vp, vp, P(AdamConfig), vp], i32),
         "pvg_opacity_reset": ([P(Gaussians), vp, vp, C.c_float, vp], i32),
+        "pvg_ssim_fwd": ([vp, vp, i32, i32, i32, vp, vp, vp], i32),
+        "pvg_ssim_bwd": ([vp, vp, vp, vp, i32, i32, i32, vp, vp], i32),
         "pvg_densify_plan": ([P(Gaussians), vp, vp, vp, P(DensifyConfig), vp, C.c_size_t, P(i64), vp], i32),
         "pvg_densify_apply": ([P(Gaussians), vp, P(DensifyConfig), vp, C.c_size_t, P(Gaussians), i32, vp, vp, vp],
                               i32),

@@ -657,6 +657,29 @@ int pvg_opacity_reset(const pvg_gaussians* params, float* m, float* v, float cap
   return PVG_OK;
 }
 
+int pvg_ssim_fwd(const float* x, const float* y, int32_t channels, int32_t height, int32_t width, float* ssim_map,
+                 float* partials, void* stream) {
+  if (channels < 1 || channels > 65535 || height < 1 || height > 65535 || width < 1 || width > 65535) {
+    set_error("channels, height and width must be in 1..65535");
+    return PVG_ERR_INVALID;
+  }
+  if (!x || !y || !partials) { set_error("x, y or partials is null"); return PVG_ERR_INVALID; }
+  PVG_HIP(pvg::launch_ssim_fwd(x, y, channels, height, width, ssim_map, partials, static_cast<hipStream_t>(stream)));
+  return PVG_OK;
+}
+
+int pvg_ssim_bwd(const float* dL_dssim, const float* x, const float* y, const float* partials, int32_t channels,
+                 int32_t height, int32_t width, float* dL_dx, void* stream) {
+  if (channels < 1 || channels > 65535 || height < 1 || height > 65535 || width < 1 || width > 65535) {
+    set_error("channels, height and width must be in 1..65535");
+    return PVG_ERR_INVALID;
+  }
+  if (!dL_dssim || !x || !y || !partials || !dL_dx) { set_error("an array is null"); return PVG_ERR_INVALID; }
+  PVG_HIP(pvg::launch_ssim_bwd(dL_dssim, x, y, partials, channels, height, width, dL_dx,
+                               static_cast<hipStream_t>(stream)));
+  return PVG_OK;
+}
+
 int pvg_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (on && !g_work_dev) {

@@ -206,6 +206,11 @@ struct AdamCfg {
 hipError_t launch_adam(const SceneOut& s, const pvg_gaussians_grad& g, float* m, float* v, const AdamCfg& c,
                        hipStream_t st);
 hipError_t launch_opacity_reset(float* o, float* m_row, float* v_row, int64_t n, float cap, hipStream_t st);
+// SSIM (11 x 11 Gaussian window, sigma 1.5): map and saved partials [3][C][H][W]; adjoint into dx
+hipError_t launch_ssim_fwd(const float* x, const float* y, int C, int H, int W, float* smap, float* part,
+                           hipStream_t st);
+hipError_t launch_ssim_bwd(const float* g, const float* x, const float* y, const float* part, int C, int H, int W,
+                           float* dx, hipStream_t st);
 hipError_t launch_densify_plan(const Scene& s, const float* gacc, const float* gcnt, const float* noise,
                                const DensifyCfg& c, void* tmp, hipStream_t st);
 unsigned long long* densify_total_ptr(void* tmp, int64_t n);

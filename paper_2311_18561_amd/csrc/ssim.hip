@@ -1,0 +1,170 @@
+// SSIM term of the training loss (Sec. 3.4 objective, weight lambda_r): the
+// structural similarity of Wang et al. with an 11 x 11 Gaussian window
+// (sigma 1.5), zero padding and C1 = 0.01^2, C2 = 0.03^2, per channel and
+// pixel:
+//   S = (2 mx my + C1)(2 sxy + C2) / ((mx^2 + my^2 + C1)(sxx + syy + C2))
+// with mx = G*x, sxx = G*(x^2) - mx^2, sxy = G*(x y) - mx my (G* the window).
+// y (the target) takes no gradient.
+//
+// One 256-thread workgroup per 16 x 16 pixel tile and channel.  The forward
+// stages the tile's 26 x 26 halo of x and y in LDS, filters the five maps
+// separably (rows into LDS, then columns), and writes S and the three
+// partial derivatives dS/dmx, dS/d(G*x^2), dS/d(G*xy) that the adjoint
+// needs.  The adjoint stages the upstream gradient times those partials on
+// the halo, filters them the same way (the window is symmetric, so the
+// zero-padded filter is its own adjoint) and forms
+//   dL/dx = G*(g dS/dmx) + 2 x G*(g dS/dExx) + y G*(g dS/dExy).
+#include <cmath>
+
+#include "pvg_internal.hpp"
+
+namespace pvg {
+
+namespace {
+
+constexpr int kST = 16;            // tile side
+constexpr int kR = 5;              // window radius
+constexpr int kHalo = kST + 2 * kR;  // 26
+constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
+
+struct Window {
+  float w[2 * kR + 1];
+};
+
+template <int kMaps>
+__device__ __forceinline__ void filter_tile(const float (*src)[kHalo][kHalo], float (*h)[kHalo][kST],
+                                            const Window& win, int tr, int tc, float out[kMaps]) {
+  // rows: kHalo x kST outputs per map, shared by the workgroup
+  for (int e = threadIdx.x; e < kHalo * kST; e += 256) {
+    const int r = e / kST, c = e % kST;
+#pragma unroll
+    for (int m = 0; m < kMaps; ++m) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int k = 0; k <= 2 * kR; ++k) acc += win.w[k] * src[m][r][c + k];
+      h[m][r][c] = acc;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < kMaps; ++m) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k <= 2 * kR; ++k) acc += win.w[k] * h[m][tr + k][tc];
+    out[m] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_ssim_fwd(const float* __restrict__ x, const float* __restrict__ y, int H,
+                                                  int W, int GX, Window win, float* __restrict__ smap,
+                                                  float* __restrict__ part) {
+  __shared__ float s_src[5][kHalo][kHalo];
+  __shared__ float s_h[5][kHalo][kST];
+  const int ch = blockIdx.y;
+  const int64_t HW = static_cast<int64_t>(H) * W;
+  const float* xc = x + ch * HW;
+  const float* yc = y + ch * HW;
+  const int x0 = static_cast<int>(blockIdx.x % GX) * kST - kR, y0 = static_cast<int>(blockIdx.x / GX) * kST - kR;
+  for (int e = threadIdx.x; e < kHalo * kHalo; e += 256) {
+    const int r = e / kHalo, c = e % kHalo;
+    const int py = y0 + r, px = x0 + c;
+    float a = 0.0f, b = 0.0f;
+    if (py >= 0 && py < H && px >= 0 && px < W) {
+      a = xc[static_cast<int64_t>(py) * W + px];
+      b = yc[static_cast<int64_t>(py) * W + px];
+    }
+    s_src[0][r][c] = a;
+    s_src[1][r][c] = b;
+    s_src[2][r][c] = a * a;
+    s_src[3][r][c] = b * b;
+    s_src[4][r][c] = a * b;
+  }
+  __syncthreads();
+  const int tr = threadIdx.x / kST, tc = threadIdx.x % kST;
+  float f[5];
+  filter_tile<5>(s_src, s_h, win, tr, tc, f);
+  const int py = y0 + kR + tr, px = x0 + kR + tc;
+  if (py >= H || px >= W) return;
+  const float mx = f[0], my = f[1];
+  const float sxx = f[2] - mx * mx, syy = f[3] - my * my, sxy = f[4] - mx * my;
+  const float A = 2.0f * mx * my + kC1, B = 2.0f * sxy + kC2;
+  const float Cc = mx * mx + my * my + kC1, D = sxx + syy + kC2;
+  const float Q = 1.0f / (Cc * D);  // C >= C1 and D near sxx + syy + C2 > 0: never 0
+  const float S = (A * B) * Q;
+  const int64_t o = ch * HW + static_cast<int64_t>(py) * W + px;
+  if (smap) smap[o] = S;
+  const int64_t CHW = static_cast<int64_t>(gridDim.y) * HW;
+  // dS/dmx (through A, B, C, D), dS/d(G*x^2) (through D), dS/d(G*xy) (through
+  // B); no division by A or B, which may pass through 0
+  part[o] = 2.0f * my * (B - A) * Q + 2.0f * mx * S * (1.0f / D - 1.0f / Cc);
+  part[CHW + o] = -S / D;
+  part[2 * CHW + o] = 2.0f * A * Q;
+}
+
+__global__ void __launch_bounds__(256) k_ssim_bwd(const float* __restrict__ g, const float* __restrict__ x,
+                                                  const float* __restrict__ y, const float* __restrict__ part, int H,
+                                                  int W, int GX, Window win, float* __restrict__ dx) {
+  __shared__ float s_src[3][kHalo][kHalo];
+  __shared__ float s_h[3][kHalo][kST];
+  const int ch = blockIdx.y;
+  const int64_t HW = static_cast<int64_t>(H) * W;
+  const int64_t CHW = static_cast<int64_t>(gridDim.y) * HW;
+  const int x0 = static_cast<int>(blockIdx.x % GX) * kST - kR, y0 = static_cast<int>(blockIdx.x / GX) * kST - kR;
+  for (int e = threadIdx.x; e < kHalo * kHalo; e += 256) {
+    const int r = e / kHalo, c = e % kHalo;
+    const int py = y0 + r, px = x0 + c;
+    float q0 = 0.0f, q1 = 0.0f, q2 = 0.0f;
+    if (py >= 0 && py < H && px >= 0 && px < W) {
+      const int64_t o = ch * HW + static_cast<int64_t>(py) * W + px;
+      const float gg = g[o];
+      q0 = gg * part[o];
+      q1 = gg * part[CHW + o];
+      q2 = gg * part[2 * CHW + o];
+    }
+    s_src[0][r][c] = q0;
+    s_src[1][r][c] = q1;
+    s_src[2][r][c] = q2;
+  }
+  __syncthreads();
+  const int tr = threadIdx.x / kST, tc = threadIdx.x % kST;
+  float f[3];
+  filter_tile<3>(s_src, s_h, win, tr, tc, f);
+  const int py = y0 + kR + tr, px = x0 + kR + tc;
+  if (py >= H || px >= W) return;
+  const int64_t o = ch * HW + static_cast<int64_t>(py) * W + px;
+  dx[o] = f[0] + 2.0f * x[o] * f[1] + y[o] * f[2];
+}
+
+Window gaussian_window() {
+  Window win;
+  double w[2 * kR + 1], sum = 0.0;
+  for (int k = 0; k <= 2 * kR; ++k) {
+    const double d = k - kR;
+    w[k] = std::exp(-(d * d) / (2.0 * 1.5 * 1.5));
+    sum += w[k];
+  }
+  for (int k = 0; k <= 2 * kR; ++k) win.w[k] = static_cast<float>(w[k] / sum);
+  return win;
+}
+
+}  // namespace
+
+hipError_t launch_ssim_fwd(const float* x, const float* y, int C, int H, int W, float* smap, float* part,
+                           hipStream_t st) {
+  if (static_cast<int64_t>(H) * W * C == 0) return hipSuccess;
+  const int GX = (W + kST - 1) / kST, GY = (H + kST - 1) / kST;
+  hipLaunchKernelGGL(k_ssim_fwd, dim3(static_cast<unsigned>(GX) * GY, C), dim3(256), 0, st, x, y, H, W, GX,
+                     gaussian_window(), smap, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_ssim_bwd(const float* g, const float* x, const float* y, const float* part, int C, int H, int W,
+                           float* dx, hipStream_t st) {
+  if (static_cast<int64_t>(H) * W * C == 0) return hipSuccess;
+  const int GX = (W + kST - 1) / kST, GY = (H + kST - 1) / kST;
+  hipLaunchKernelGGL(k_ssim_bwd, dim3(static_cast<unsigned>(GX) * GY, C), dim3(256), 0, st, g, x, y, part, H, W, GX,
+                     gaussian_window(), dx);
+  return hipGetLastError();
+}
+
+}  // namespace pvg

@@ -716,3 +716,36 @@ def pvg_sky_composite(img, opacity, cube, cam: dict, jitter=None):
     """C + (1 - O) f_sky(d) for one view (see PVGSkyComposite); jitter
     (optional [2,H,W], pixels) moves each ray inside its pixel."""
     return PVGSkyComposite.apply(img, opacity, cube, cam, jitter)
+
+
+class PVGSSIM(torch.autograd.Function):
+    """The SSIM map of a render x against a target y (both [C,H,W] float32
+    on the GPU; 11 x 11 Gaussian window, sigma 1.5): the forward keeps the
+    kernel's partials, the backward returns dL/dx (the target takes none)."""
+
+    @staticmethod
+    def forward(ctx, x, y):
+        x, y = x.contiguous(), y.contiguous()
+        if x.shape != y.shape or x.dim() != 3 or x.dtype != torch.float32 or y.dtype != torch.float32:
+            raise ValueError("x and y must be float32 [C,H,W] of one shape")
+        C_, H, W = (int(v) for v in x.shape)
+        smap = torch.empty_like(x)
+        part = torch.empty((3, C_, H, W), dtype=torch.float32, device=x.device)
+        L.check(L.load().pvg_ssim_fwd(_p(x), _p(y), C_, H, W, _p(smap), _p(part), _stream_handle()))
+        ctx.save_for_backward(x, y, part)
+        return smap
+
+    @staticmethod
+    def backward(ctx, g):
+        x, y, part = ctx.saved_tensors
+        g = g.contiguous()
+        dx = torch.empty_like(x)
+        C_, H, W = (int(v) for v in x.shape)
+        L.check(L.load().pvg_ssim_bwd(_p(g), _p(x), _p(y), _p(part), C_, H, W, _p(dx), _stream_handle()))
+        return dx, None
+
+
+def pvg_ssim(x, y):
+    """Differentiable SSIM map of x against y (see PVGSSIM); the loss term of
+    Sec. 3.4 is lambda_r (1 - mean)."""
+    return PVGSSIM.apply(x, y)
