@@ -129,3 +129,18 @@ def view_space_stats(g2d_views, visible_views, sizes):
         acc += np.where(vis, np.hypot(gx, gy), 0.0)
         cnt += vis
     return acc, cnt
+
+
+def split_by_staticness(sc, threshold):
+    """Static / dynamic partition (Sec. 3.2): rho = beta / l in FP32, static
+    when rho >= threshold; both parts in index order."""
+    rho = np.asarray(sc["beta"], f32) / np.asarray(sc["period"], f32)
+    st = rho >= f32(threshold)
+    parts = []
+    for mask in (st, ~st):
+        idx = np.nonzero(mask)[0]
+        part = {"n": int(idx.size), "sh_degree": sc["sh_degree"]}
+        for f in ("mu", "scale", "rot", "sh", "opacity", "vel", "period", "tau", "beta"):
+            part[f] = np.asarray(sc[f], f32)[..., idx].copy()
+        parts.append(part)
+    return parts[0], parts[1]

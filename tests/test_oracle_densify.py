@@ -179,3 +179,24 @@ def test_plan_counts_match_the_pass(n):
     assert out["n"] == int(sum(k.sum() for k in keeps))
     assert not np.any(keeps[0] & (keeps[2] | keeps[3]))  # a split parent is replaced
     assert not np.any(keeps[1] & ~keeps[0])  # a clone survives with its original
+
+
+def test_staticness_split_partition():
+    """rho = beta / l >= threshold is static (a point exactly at the
+    threshold included); the two parts partition the Gaussians and keep
+    their order."""
+    rng = np.random.default_rng(9)
+    n = 200
+    sc = scene(rng.uniform(-10, 10, (n, 3)), np.exp(rng.normal(-1, 0.5, (n, 3))), beta=rng.uniform(0.05, 2, n),
+               period=rng.uniform(0.5, 3, n))
+    sc["beta"][0], sc["period"][0] = 1.5, 1.5  # rho exactly 1
+    st, dy = ad.split_by_staticness(sc, 1.0)
+    rho = sc["beta"] / sc["period"]
+    assert st["n"] + dy["n"] == n and st["n"] == int((rho >= 1.0).sum())
+    assert st["mu"][0, 0] == sc["mu"][0, 0]  # the threshold point is static, first in order
+    idx_s = np.nonzero(rho >= 1.0)[0]
+    idx_d = np.nonzero(rho < 1.0)[0]
+    np.testing.assert_array_equal(st["tau"], sc["tau"][idx_s])
+    np.testing.assert_array_equal(dy["sh"], sc["sh"][..., idx_d])
+    a, b = ad.split_by_staticness(sc, 1e9)
+    assert a["n"] == 0 and b["n"] == n
