@@ -356,6 +356,20 @@ int pvg_adam_step(const pvg_gaussians* params, const pvg_gaussians_grad* grad, f
  * moments cleared. */
 int pvg_opacity_reset(const pvg_gaussians* params, float* m, float* v, float cap, void* stream);
 
+/* Static / dynamic split (Sec. 3.2: the staticness rho = beta / l with a
+ * threshold separates static from dynamic points).  A Gaussian is static
+ * when rho >= rho_threshold (FP32).  The plan (workspace of
+ * pvg_densify_tmp_bytes(n)) writes the number of static Gaussians into
+ * *n_static (host; synchronizes `stream`); the apply copies each Gaussian
+ * into out_static (n = *n_static) or out_dynamic (n = g->n - *n_static),
+ * both in index order, device arrays owned by the caller.  PVG_ERR_INVALID
+ * when the outputs' sizes or degrees differ from the plan's (checked before
+ * any write). */
+int pvg_staticness_split_plan(const pvg_gaussians* g, float rho_threshold, void* tmp, size_t tmp_bytes,
+                              int64_t* n_static, void* stream);
+int pvg_staticness_split_apply(const pvg_gaussians* g, float rho_threshold, const void* tmp, size_t tmp_bytes,
+                               const pvg_gaussians* out_static, const pvg_gaussians* out_dynamic, void* stream);
+
 /* SSIM term of the training loss (Sec. 3.4 objective, weight lambda_r):
  * the structural similarity of Wang et al. per channel and pixel, with an 11
  * x 11 Gaussian window (sigma 1.5, normalised), zero padding outside the

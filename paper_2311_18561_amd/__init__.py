@@ -9,7 +9,7 @@ All computation runs in ``libpvg.so`` (HIP kernels behind a C ABI declared in
 device memory and streams.
 """
 from ._lib import PVGError, load  # noqa: F401
-from .densify import densify, densify_config  # noqa: F401
+from .densify import densify, densify_config, split_by_staticness  # noqa: F401
 from .optim import PVGAdam, default_lrs  # noqa: F401
 from .render import (  # noqa: F401
     FIELDS,

@@ -142,6 +142,9 @@ def load():
         "pvg_adam_step": ([P(Gaussians), P(GaussiansGrad), vp, vp, P(AdamConfig), vp], i32),
         "pvg_opacity_reset": ([P(Gaussians), vp, vp, C.c_float, vp], i32),
         "pvg_ssim_fwd": ([vp, vp, i32, i32, i32, vp, vp, vp], i32),
+        "pvg_staticness_split_plan": ([P(Gaussians), C.c_float, vp, C.c_size_t, P(i64), vp], i32),
+        "pvg_staticness_split_apply": ([P(Gaussians), C.c_float, vp, C.c_size_t, P(Gaussians), P(Gaussians), vp],
+                                       i32),
         "pvg_ssim_bwd": ([vp, vp, vp, vp, i32, i32, i32, vp, vp], i32),
         "pvg_densify_plan": ([P(Gaussians), vp, vp, vp, P(DensifyConfig), vp, C.c_size_t, P(i64), vp], i32),
         "pvg_densify_apply": ([P(Gaussians), vp, P(DensifyConfig), vp, C.c_size_t, P(Gaussians), i32, vp, vp, vp],

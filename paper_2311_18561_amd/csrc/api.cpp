@@ -657,6 +657,60 @@ int pvg_opacity_reset(const pvg_gaussians* params, float* m, float* v, float cap
   return PVG_OK;
 }
 
+namespace {
+pvg::SceneOut scene_out(const pvg_gaussians* o) {
+  return pvg::SceneOut{const_cast<float*>(o->mu), const_cast<float*>(o->scale), const_cast<float*>(o->rot),
+                       const_cast<float*>(o->sh), const_cast<float*>(o->opacity), const_cast<float*>(o->vel),
+                       const_cast<float*>(o->period), const_cast<float*>(o->tau), const_cast<float*>(o->beta),
+                       o->n, o->sh_degree};
+}
+}  // namespace
+
+int pvg_staticness_split_plan(const pvg_gaussians* g, float rho_threshold, void* tmp, size_t tmp_bytes,
+                              int64_t* n_static, void* stream) {
+  if (!check_gaussians(g)) return PVG_ERR_INVALID;
+  if (g->n > kMaxDensifyN || !n_static || !tmp || !std::isfinite(rho_threshold)) {
+    set_error("n above 2^30, a null pointer or a non-finite threshold");
+    return PVG_ERR_INVALID;
+  }
+  if (tmp_bytes < pvg::densify_tmp_bytes(g->n)) { set_error("tmp_bytes too small"); return PVG_ERR_NOMEM; }
+  auto s = static_cast<hipStream_t>(stream);
+  PVG_HIP(pvg::launch_static_plan(scene_of(g), rho_threshold, tmp, s));
+  unsigned long long total = 0;
+  PVG_HIP(hipMemcpyAsync(&total, pvg::densify_total_ptr(tmp, g->n), sizeof(total), hipMemcpyDeviceToHost, s));
+  PVG_HIP(hipStreamSynchronize(s));
+  *n_static = static_cast<int64_t>(total);
+  return PVG_OK;
+}
+
+int pvg_staticness_split_apply(const pvg_gaussians* g, float rho_threshold, const void* tmp, size_t tmp_bytes,
+                               const pvg_gaussians* out_static, const pvg_gaussians* out_dynamic, void* stream) {
+  if (!check_gaussians(g) || !check_gaussians(out_static) || !check_gaussians(out_dynamic)) return PVG_ERR_INVALID;
+  if (g->n > kMaxDensifyN || !tmp || !std::isfinite(rho_threshold)) {
+    set_error("n above 2^30, a null workspace or a non-finite threshold");
+    return PVG_ERR_INVALID;
+  }
+  if (out_static->sh_degree != g->sh_degree || out_dynamic->sh_degree != g->sh_degree) {
+    set_error("outputs must have the input's sh_degree");
+    return PVG_ERR_INVALID;
+  }
+  if (tmp_bytes < pvg::densify_tmp_bytes(g->n)) { set_error("tmp_bytes too small"); return PVG_ERR_NOMEM; }
+  auto s = static_cast<hipStream_t>(stream);
+  unsigned long long total = 0;
+  PVG_HIP(hipMemcpyAsync(&total, pvg::densify_total_ptr(const_cast<void*>(tmp), g->n), sizeof(total),
+                         hipMemcpyDeviceToHost, s));
+  PVG_HIP(hipStreamSynchronize(s));
+  if (static_cast<int64_t>(total) != out_static->n || g->n - static_cast<int64_t>(total) != out_dynamic->n) {
+    set_error("outputs hold %lld and %lld Gaussians but the plan splits %lld into %llu static",
+              static_cast<long long>(out_static->n), static_cast<long long>(out_dynamic->n),
+              static_cast<long long>(g->n), total);
+    return PVG_ERR_INVALID;
+  }
+  PVG_HIP(pvg::launch_static_apply(scene_of(g), rho_threshold, tmp, scene_out(out_static), scene_out(out_dynamic),
+                                   s));
+  return PVG_OK;
+}
+
 int pvg_ssim_fwd(const float* x, const float* y, int32_t channels, int32_t height, int32_t width, float* ssim_map,
                  float* partials, void* stream) {
   if (channels < 1 || channels > 65535 || height < 1 || height > 65535 || width < 1 || width > 65535) {

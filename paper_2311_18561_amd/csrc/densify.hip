@@ -203,7 +203,72 @@ __global__ void __launch_bounds__(kDB) k_densify_apply(Scene s, const float* __r
   }
 }
 
+// Static / dynamic split (Sec. 3.2: a threshold on the staticness rho =
+// beta / l separates static from dynamic points).  Static when rho >=
+// threshold (FP32, correctly rounded division).  The plan counts static
+// Gaussians per block (scanned by k_densify_scan); the apply kernel writes a
+// static Gaussian at its rank among the static ones and a dynamic one at
+// i minus the number of static Gaussians before it, so both sets keep index
+// order.
+__device__ __forceinline__ bool is_static(const Scene& s, int64_t i, float thr) {
+  return s.beta[i] / s.period[i] >= thr;
+}
+
+__global__ void __launch_bounds__(kDB) k_static_plan(Scene s, float thr, uint32_t* block_count) {
+  __shared__ uint32_t s_wave[kDB / 64];
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kDB + threadIdx.x;
+  const uint32_t st = (i < s.n && is_static(s, i, thr)) ? 1u : 0u;
+  uint32_t total;
+  block_exclusive(st, s_wave, &total);
+  if (threadIdx.x == 0) block_count[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kDB) k_static_apply(Scene s, float thr, const uint32_t* __restrict__ block_off,
+                                                      SceneOut os, SceneOut od) {
+  __shared__ uint32_t s_wave[kDB / 64];
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kDB + threadIdx.x;
+  const bool st = i < s.n && is_static(s, i, thr);
+  uint32_t total;
+  const uint32_t local = block_exclusive(st ? 1u : 0u, s_wave, &total);
+  if (i >= s.n) return;
+  const int64_t before = static_cast<int64_t>(block_off[blockIdx.x]) + local;  // static Gaussians before i
+  const SceneOut& o = st ? os : od;
+  const int64_t j = st ? before : i - before;
+  if (j >= o.n) return;  // the host sizes both outputs from the plan's count
+  const int64_t n = s.n, m = o.n;
+  const int K3 = 3 * (s.degree + 1) * (s.degree + 1);
+  copy_rows(s.mu, o.mu, 3, n, m, i, j);
+  copy_rows(s.scale, o.scale, 3, n, m, i, j);
+  copy_rows(s.rot, o.rot, 4, n, m, i, j);
+  copy_rows(s.sh, o.sh, K3, n, m, i, j);
+  copy_rows(s.vel, o.vel, 3, n, m, i, j);
+  o.opacity[j] = s.opacity[i];
+  o.period[j] = s.period[i];
+  o.tau[j] = s.tau[i];
+  o.beta[j] = s.beta[i];
+}
+
 }  // namespace
+
+hipError_t launch_static_plan(const Scene& s, float thr, void* tmp, hipStream_t st) {
+  const int64_t nb = (s.n + kDB - 1) / kDB;
+  uint32_t* bc = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(tmp) + ((s.n + 255) / 256) * 256);
+  unsigned long long* total = densify_total_ptr(tmp, s.n);
+  if (s.n == 0) return launch_fill_u32(reinterpret_cast<uint32_t*>(total), 0u, 2, st);
+  hipLaunchKernelGGL(k_static_plan, dim3(static_cast<unsigned>(nb)), dim3(kDB), 0, st, s, thr, bc);
+  hipLaunchKernelGGL(k_densify_scan, dim3(1), dim3(1024), 0, st, bc, nb, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_static_apply(const Scene& s, float thr, const void* tmp, const SceneOut& os, const SceneOut& od,
+                               hipStream_t st) {
+  if (s.n == 0) return hipSuccess;
+  const int64_t nb = (s.n + kDB - 1) / kDB;
+  const uint32_t* bo =
+      reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(tmp) + ((s.n + 255) / 256) * 256);
+  hipLaunchKernelGGL(k_static_apply, dim3(static_cast<unsigned>(nb)), dim3(kDB), 0, st, s, thr, bo, os, od);
+  return hipGetLastError();
+}
 
 size_t densify_tmp_bytes(int64_t n) {
   const int64_t nb = (n + kDB - 1) / kDB;

@@ -214,6 +214,10 @@ hipError_t launch_ssim_bwd(const float* g, const float* x, const float* y, const
 hipError_t launch_densify_plan(const Scene& s, const float* gacc, const float* gcnt, const float* noise,
                                const DensifyCfg& c, void* tmp, hipStream_t st);
 unsigned long long* densify_total_ptr(void* tmp, int64_t n);
+// static / dynamic split by staticness (same workspace as densify)
+hipError_t launch_static_plan(const Scene& s, float thr, void* tmp, hipStream_t st);
+hipError_t launch_static_apply(const Scene& s, float thr, const void* tmp, const SceneOut& os, const SceneOut& od,
+                               hipStream_t st);
 hipError_t launch_densify_apply(const Scene& s, const float* noise, const DensifyCfg& c, const void* tmp,
                                 const SceneOut& out, const float* extra_in, float* extra_out, int32_t n_extra,
                                 hipStream_t st);

@@ -53,4 +53,26 @@ def densify(params, grad_accum, grad_count, noise, cfg: L.DensifyConfig, extra=N
     return out, extra_out
 
 
-__all__ = ["densify", "densify_config", "FIELDS"]
+def split_by_staticness(params, rho_threshold):
+    """Static and dynamic Gaussians (rho = beta / l >= rho_threshold is
+    static, Sec. 3.2): returns (static parameter tensors, dynamic ones),
+    each in index order."""
+    params, n, degree = _check_params(list(params))
+    dev = params[0].device
+    lib = L.load()
+    size = C.c_size_t()
+    L.check(lib.pvg_densify_tmp_bytes(n, C.byref(size)))
+    tmp = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device=dev)
+    g = gaussians_struct(params, n, degree)
+    n_static = C.c_int64()
+    L.check(lib.pvg_staticness_split_plan(C.byref(g), float(rho_threshold), _p(tmp), int(tmp.numel()),
+                                          C.byref(n_static), _stream_handle()))
+    ns = int(n_static.value)
+    outs = [[torch.empty((*p.shape[:-1], m), dtype=torch.float32, device=dev) for p in params] for m in (ns, n - ns)]
+    gs, gd = gaussians_struct(outs[0], ns, degree), gaussians_struct(outs[1], n - ns, degree)
+    L.check(lib.pvg_staticness_split_apply(C.byref(g), float(rho_threshold), _p(tmp), int(tmp.numel()), C.byref(gs),
+                                           C.byref(gd), _stream_handle()))
+    return outs[0], outs[1]
+
+
+__all__ = ["densify", "densify_config", "split_by_staticness", "FIELDS"]
