@@ -155,16 +155,30 @@ __global__ void __launch_bounds__(1024) k_densify_scan(uint32_t* block_count, in
   if (threadIdx.x == 1023) *out_total = s_sum[1023];
 }
 
+// Rows are copied eight at a time, all loads before the stores, so a thread
+// keeps eight loads in flight instead of waiting on each row in turn.
 __device__ __forceinline__ void copy_rows(const float* __restrict__ src, float* __restrict__ dst, int rows,
                                           int64_t n, int64_t n_out, int64_t i, int64_t j) {
-  for (int r = 0; r < rows; ++r) dst[r * n_out + j] = src[r * n + i];
+  for (int r0 = 0; r0 < rows; r0 += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = r0 + u < rows ? src[(r0 + u) * n + i] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (r0 + u < rows) dst[(r0 + u) * n_out + j] = v[u];
+  }
 }
 
+constexpr int kExtraRowsPerBlock = 32;  // carried rows per blockIdx.y slice of the apply grid
+
+// blockIdx.y = 0 writes the parameters; blockIdx.y = 1, 2, ... each write
+// kExtraRowsPerBlock of the carried rows.  Every block re-derives its
+// Gaussians' output offsets from the codes.
 __global__ void __launch_bounds__(kDB) k_densify_apply(Scene s, const float* __restrict__ noise, DensifyCfg c,
                                                        const uint8_t* __restrict__ codes,
                                                        const uint32_t* __restrict__ block_off, SceneOut out,
-                                                       const float* __restrict__ extra_in, float* extra_out,
-                                                       int32_t n_extra) {
+                                                       const float* __restrict__ extra_in,
+                                                       float* __restrict__ extra_out, int32_t n_extra) {
   __shared__ uint32_t s_wave[kDB / 64];
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kDB + threadIdx.x;
   const uint32_t code = i < s.n ? codes[i] : 0u;
@@ -172,8 +186,26 @@ __global__ void __launch_bounds__(kDB) k_densify_apply(Scene s, const float* __r
   const uint32_t local = block_exclusive(static_cast<uint32_t>(__popc(code)), s_wave, &total);
   if (code == 0) return;
   const int64_t n = s.n, m = out.n;
+  const int64_t j0 = static_cast<int64_t>(block_off[blockIdx.x]) + local;
+  if (blockIdx.y > 0) {  // a slice of the carried rows: kept for the original, zero for new points
+    const int r0 = (blockIdx.y - 1) * kExtraRowsPerBlock;
+    const int rows = min(kExtraRowsPerBlock, n_extra - r0);
+    int64_t j = j0;
+    for (int slot = 0; slot < 4; ++slot) {
+      if (!(code & (1u << slot))) continue;
+      if (j >= m) return;
+      if (slot == 0) {
+        copy_rows(extra_in + static_cast<int64_t>(r0) * n, extra_out + static_cast<int64_t>(r0) * m, rows, n, m, i,
+                  j);
+      } else {
+        for (int r = 0; r < rows; ++r) extra_out[(r0 + r) * m + j] = 0.0f;
+      }
+      ++j;
+    }
+    return;
+  }
   const int K3 = 3 * (s.degree + 1) * (s.degree + 1);
-  int64_t j = static_cast<int64_t>(block_off[blockIdx.x]) + local;
+  int64_t j = j0;
   for (int slot = 0; slot < 4; ++slot) {
     if (!(code & (1u << slot))) continue;
     if (j >= m) return;  // the host checks out.n against the plan's total; never write past it
@@ -197,8 +229,6 @@ __global__ void __launch_bounds__(kDB) k_densify_apply(Scene s, const float* __r
       out.tau[j] = ch.tau;
       out.beta[j] = ch.beta;
     }
-    // extra per-Gaussian rows (optimizer state): kept for the original, zero for new points
-    for (int r = 0; r < n_extra; ++r) extra_out[r * m + j] = slot == 0 ? extra_in[r * n + i] : 0.0f;
     ++j;
   }
 }
@@ -303,8 +333,9 @@ hipError_t launch_densify_apply(const Scene& s, const float* noise, const Densif
   const int64_t nb = (s.n + kDB - 1) / kDB;
   const uint8_t* codes = static_cast<const uint8_t*>(tmp);
   const uint32_t* bo = reinterpret_cast<const uint32_t*>(codes + ((s.n + 255) / 256) * 256);
-  hipLaunchKernelGGL(k_densify_apply, dim3(static_cast<unsigned>(nb)), dim3(kDB), 0, st, s, noise, c, codes, bo,
-                     out, extra_in, extra_out, n_extra);
+  const unsigned slices = 1u + static_cast<unsigned>((n_extra + kExtraRowsPerBlock - 1) / kExtraRowsPerBlock);
+  hipLaunchKernelGGL(k_densify_apply, dim3(static_cast<unsigned>(nb), slices), dim3(kDB), 0, st, s, noise, c, codes,
+                     bo, out, extra_in, extra_out, n_extra);
   return hipGetLastError();
 }
 
