@@ -110,3 +110,60 @@ def test_workspace_query(lib):
     assert lib.pvg_workspace_query(1000, 100, 70, 0, C.byref(ws)) == 0
     assert ws.num_tiles == 7 * 5
     assert lib.pvg_workspace_query(-1, 128, 96, 0, C.byref(ws)) == L.PVG_ERR_INVALID
+
+
+def test_new_entry_points_reject_bad_arguments_on_host(lib):
+    """The adaptive control, optimizer, SSIM and staticness entry points
+    validate on the host before any launch."""
+    from paper_2311_18561_amd import _lib as L
+    size = C.c_size_t()
+    assert lib.pvg_densify_tmp_bytes(-1, C.byref(size)) == L.PVG_ERR_INVALID
+    assert lib.pvg_densify_tmp_bytes((1 << 30) + 1, C.byref(size)) == L.PVG_ERR_INVALID
+    assert lib.pvg_densify_tmp_bytes(1000, C.byref(size)) == 0 and size.value >= 1000
+    g = L.Gaussians()
+    g.n, g.sh_degree = 0, 0
+    n_out = C.c_int64()
+    bad = L.DensifyConfig(1.7e-4, 0.0, 0.3, 3.0, 0.0, 0.8, 1.0)  # r = 0
+    assert lib.pvg_densify_plan(C.byref(g), None, None, None, C.byref(bad), 1, 1 << 20, C.byref(n_out),
+                                None) == L.PVG_ERR_INVALID
+    assert "scene_radius" in L.last_error()
+    bad.scene_radius, bad.clone_scale = 30.0, float("inf")
+    assert lib.pvg_densify_plan(C.byref(g), None, None, None, C.byref(bad), 1, 1 << 20, C.byref(n_out),
+                                None) == L.PVG_ERR_INVALID
+    g.n = 10
+    ok = L.DensifyConfig(1.7e-4, 30.0, 0.3, 3.0, 0.0, 0.8, 1.0)
+    g.mu = g.scale = g.rot = g.sh = g.opacity = g.vel = g.period = g.tau = g.beta = 1
+    assert lib.pvg_densify_plan(C.byref(g), None, 1, 1, C.byref(ok), 1, 1 << 20, C.byref(n_out),
+                                None) == L.PVG_ERR_INVALID  # statistics missing
+    assert lib.pvg_densify_plan(C.byref(g), 1, 1, 1, C.byref(ok), 1, 4, C.byref(n_out), None) == L.PVG_ERR_NOMEM
+    # Adam: step >= 1, betas in [0, 1), eps > 0, rates finite and >= 0
+    cfg = L.AdamConfig()
+    cfg.beta1, cfg.beta2, cfg.eps, cfg.step = 0.9, 0.999, 1e-15, 0
+    gg = L.GaussiansGrad()
+    assert lib.pvg_adam_step(C.byref(g), C.byref(gg), 1, 1, C.byref(cfg), None) == L.PVG_ERR_INVALID
+    cfg.step, cfg.beta1 = 1, 1.0
+    assert lib.pvg_adam_step(C.byref(g), C.byref(gg), 1, 1, C.byref(cfg), None) == L.PVG_ERR_INVALID
+    cfg.beta1, cfg.lr[3] = 0.9, -1e-3
+    assert lib.pvg_adam_step(C.byref(g), C.byref(gg), 1, 1, C.byref(cfg), None) == L.PVG_ERR_INVALID
+    cfg.lr[3] = 1e-3
+    assert lib.pvg_adam_step(C.byref(g), C.byref(gg), 1, 1, C.byref(cfg), None) == L.PVG_ERR_INVALID  # grads null
+    assert lib.pvg_opacity_reset(C.byref(g), 1, 1, float("nan"), None) == L.PVG_ERR_INVALID
+    # SSIM: sizes and arrays
+    assert lib.pvg_ssim_fwd(1, 1, 3, 0, 16, None, 1, None) == L.PVG_ERR_INVALID
+    assert lib.pvg_ssim_fwd(None, 1, 3, 16, 16, None, 1, None) == L.PVG_ERR_INVALID
+    assert lib.pvg_ssim_bwd(1, 1, 1, None, 3, 16, 16, 1, None) == L.PVG_ERR_INVALID
+    # staticness split: threshold and workspace
+    assert lib.pvg_staticness_split_plan(C.byref(g), float("nan"), 1, 1 << 20, C.byref(n_out),
+                                         None) == L.PVG_ERR_INVALID
+    assert lib.pvg_staticness_split_plan(C.byref(g), 0.5, 1, 4, C.byref(n_out), None) == L.PVG_ERR_NOMEM
+    # the densify statistics go as a pair
+    gg.mu = gg.scale = gg.rot = gg.sh = gg.opacity = gg.vel = gg.period = gg.tau = gg.beta = 1
+    gg.densify_grad = 1
+    cam = L.Camera()
+    cam.width, cam.height, cam.fx, cam.fy, cam.znear = 64, 48, 50.0, 50.0, 0.2
+    fr = L.Frame()
+    geom, bins = L.Geom(), L.Bins()
+    one = (C.c_void_p * 1)(1)
+    assert lib.pvg_render_bwd_views(C.byref(g), 1, C.byref(cam), C.byref(fr), C.byref(geom), C.byref(bins), one,
+                                    one, one, C.byref(gg), 0, 1, 1 << 20, None) == L.PVG_ERR_INVALID
+    assert "densify" in L.last_error()
