@@ -58,10 +58,10 @@ def lib():
         L.orc_render_bruteforce_f32.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
         L.orc_render_bruteforce_f32.restype = None
         L.orc_render_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
-                                     vp, vp, vp, vp, vp]
+                                     vp, vp, vp, vp, vp, vp]
         L.orc_render_f64.restype = C.c_double
         L.orc_backward_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
-                                       vp, vp, vp]
+                                       vp, vp, vp, vp]
         L.orc_backward_f64.restype = None
         L.orc_temporal_f64.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_double, i32, vp, vp]
@@ -193,10 +193,12 @@ def scene64(scene) -> dict:
 
 
 def render_f64(sc64, cam, t, dt, mode, bg, pre, bins, tile_mask=None, w=None, want_img=True, wD=None, wT=None,
-               want_depth=False, wF=None):
+               want_depth=False, wF=None, colour=None):
     """FP64 image on the FP32 stage's discrete structure; returns (sum(w*img)
     + sum(wD*depth) + sum(wT*final_T), img, final_T), and the depth channel
-    as a fourth result with want_depth."""
+    as a fourth result with want_depth.  colour (optional, [N,3]): values
+    composited in place of the SH colour (three channels of a per-Gaussian
+    feature vector, Sec. 4.1)."""
     n = int(sc64["n"])
     W, H = cam["width"], cam["height"]
     arrs, ptrs = _param_ptrs(sc64, np.float64)
@@ -210,9 +212,11 @@ def render_f64(sc64, cam, t, dt, mode, bg, pre, bins, tile_mask=None, w=None, wa
     wFv = None if wF is None else _c(wF, np.float64)
     D = np.zeros((H, W), np.float64) if want_depth else None
     tm = None if tile_mask is None else _c(tile_mask, np.uint8)
+    col = None if colour is None else _c(colour, np.float64)
     L = lib().orc_render_f64(n, int(sc64["sh_degree"]), ptrs, _p(cv), W, H, _p(fv), _p(pre["xy"]),
                              _p(pre["conic_op"]), _p(pre["radius"]), _p(pre["flags"]), _p(bins["ranges"]),
-                             _p(ig), _p(tm), _p(wv), _p(img), _p(T), _p(wDv), _p(wTv), _p(D), _p(wFv), None)
+                             _p(ig), _p(tm), _p(wv), _p(img), _p(T), _p(wDv), _p(wTv), _p(D), _p(wFv), None,
+                             _p(col))
     return (L, img, T, D) if want_depth else (L, img, T)
 
 
@@ -238,8 +242,8 @@ def normalized_depth_bwd_f64(g, depth, final_T):
     return g * ia, g * (np.asarray(depth, np.float64) * ia) * ia
 
 
-def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, tile_mask=None, dD=None, dT=None, dF=None
-                 ) -> tuple[dict, np.ndarray]:
+def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, tile_mask=None, dD=None, dT=None, dF=None,
+                 colour=None) -> tuple[dict, np.ndarray]:
     """FP64 gradients of sum(dimg * image) + sum(dD * depth) + sum(dT * final_T)
     + sum(dF * (velocity map, staticness map)) for every parameter array, and
     g2d [N,14] (entries 9..13: d depth, d v~, d rho).
@@ -263,6 +267,7 @@ def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, tile_mask=None, dD
     dDv = None if dD is None else _c(dD, np.float64)
     dTv = None if dT is None else _c(dT, np.float64)
     dFv = None if dF is None else _c(dF, np.float64)
+    col = None if colour is None else _c(colour, np.float64)  # feature values in place of the colour
     if tm is not None:
         if dFv is not None:
             assert not np.any(dFv[:, ~keep]), "dF must be zero outside the tile mask"
@@ -270,7 +275,7 @@ def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, tile_mask=None, dD
             assert extra is None or not np.any(extra[~keep]), "dD and dT must be zero outside the tile mask"
     lib().orc_backward_f64(n, int(sc64["sh_degree"]), ptrs, _p(cv), W, H, _p(fv), _p(pre["xy"]),
                            _p(pre["conic_op"]), _p(pre["radius"]), _p(pre["flags"]), _p(bins["ranges"]),
-                           _p(ig), _p(d), gptrs, _p(g2d), _p(tm), _p(dDv), _p(dTv), _p(dFv))
+                           _p(ig), _p(d), gptrs, _p(g2d), _p(tm), _p(dDv), _p(dTv), _p(dFv), _p(col))
     return grads, g2d
 
 

@@ -636,7 +636,9 @@ double orc_render_f64(int64_t n, int degree, const void* const* arr, const float
                       const int32_t* radius32, const uint32_t* flags32, const uint32_t* ranges,
                       const uint32_t* inst_gauss, const uint8_t* tile_mask, const double* w,
                       double* img, double* final_T, const double* wD, const double* wT, double* depth_img,
-                      const double* wF, double* feat_img) {
+                      const double* wF, double* feat_img, const double* colour) {
+  // colour (optional, [n][3]): per-Gaussian values composited in place of
+  // the SH colour (a feature vector three channels at a time, Sec. 4.1)
   const Params prm = make_params(n, degree, arr);
   const Camera cam = make_cam(camv, W, H);
   const Frame fr = make_frame(framev);
@@ -646,6 +648,8 @@ double orc_render_f64(int64_t n, int degree, const void* const* arr, const float
     if (radius32[i] <= 0) { val[i].visible = false; continue; }
     Fixed fx{true, flags32[i]};
     preprocess_one<double>(prm, i, cam, fr, &fx, val[i], nullptr);
+    if (colour)
+      for (int c = 0; c < 3; ++c) val[i].rgb[c] = colour[3 * i + c];
   }
   const int GX = (W + kTile - 1) / kTile, GY = (H + kTile - 1) / kTile;
   const int64_t HW = static_cast<int64_t>(H) * W;
@@ -691,7 +695,11 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
                       const float* framev, const float* xy32, const float* conic_op32,
                       const int32_t* radius32, const uint32_t* flags32, const uint32_t* ranges,
                       const uint32_t* inst_gauss, const double* dimg, void* const* garr, double* g2d_out,
-                      const uint8_t* tile_mask, const double* dD, const double* dT, const double* dF) {
+                      const uint8_t* tile_mask, const double* dD, const double* dT, const double* dF,
+                      const double* colour) {
+  // colour (optional, [n][3]): as in orc_render_f64; the colour is then a
+  // plain per-Gaussian value, so nothing flows into the SH or, through the
+  // view direction, into the mean, and g2d[6..8] is its gradient
   const Params prm = make_params(n, degree, arr);
   const Camera cam = make_cam(camv, W, H);
   const Frame fr = make_frame(framev);
@@ -702,6 +710,8 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
     if (radius32[i] <= 0) { val[i].visible = false; continue; }
     Fixed fx{true, flags32[i]};
     preprocess_one<double>(prm, i, cam, fr, &fx, val[i], &inter[i]);
+    if (colour)
+      for (int c = 0; c < 3; ++c) val[i].rgb[c] = colour[3 * i + c];
   }
   const int GX = (W + kTile - 1) / kTile, GY = (H + kTile - 1) / kTile;
   const int64_t HW = static_cast<int64_t>(H) * W;
@@ -792,7 +802,7 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
 
     // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2)
     double ddir[3] = {0, 0, 0};
-    for (int ch = 0; ch < 3; ++ch) {
+    for (int ch = 0; ch < 3 && !colour; ++ch) {
       const bool clamp = (v.flags & (kShClampR << ch)) != 0;
       const double draw = clamp ? 0.0 : gg[6 + ch];
       for (int k = 0; k < K; ++k) {

@@ -694,3 +694,59 @@ def test_tile_masked_adjoint_equals_full(orc):
     for f in full:
         assert np.array_equal(full[f], part[f]), f
     assert np.abs(g_full).max() > 0
+
+
+def test_feature_in_place_of_colour_closed_form(orc):
+    """Semantic rendering (Sec. 4.1) composites per-Gaussian vectors like the
+    colour: a constant vector f gives f (1 - final_T) at every pixel."""
+    cfg = gen.make_config(0)
+    sc, cam, t = cfg["scene"], cfg["cameras"][0], cfg["t"]
+    pre = orc.preprocess_f32(sc, cam, t)
+    bins = orc.bin_sort(pre, cam)
+    f = np.array([0.2, -0.5, 0.9])
+    col = np.tile(f, (sc["n"], 1))
+    _, img, T = orc.render_f64(orc.scene64(sc), cam, t, 0.0, 0, (0, 0, 0), pre, bins, colour=col)
+    np.testing.assert_allclose(img, f[:, None, None] * (1.0 - T)[None], rtol=1e-12, atol=1e-14)
+
+
+def test_feature_in_place_of_colour_adjoint_fd(orc):
+    """With per-Gaussian values in place of the colour (any sign): finite
+    differences of sum w img against the adjoint, with respect to those
+    values (g2d[:, 6:9]) and to the geometry; nothing reaches the SH."""
+    sc = gen.make_scene(30, 7, sh_degree=2)
+    cam = gen.yaw_camera(64, 48, 10.0, (0.2, 0.1, -0.5))
+    t = 0.45
+    pre = orc.preprocess_f32(sc, cam, t)
+    bins = orc.bin_sort(pre, cam)
+    s64 = orc.scene64(sc)
+    rng = np.random.default_rng(8)
+    col = rng.standard_normal((sc["n"], 3))
+    w = rng.standard_normal((3, cam["height"], cam["width"]))
+    grads, g2d = orc.backward_f64(s64, cam, t, 0.0, 0, (0, 0, 0), pre, bins, w, colour=col)
+    assert not np.any(grads["sh"])
+
+    def loss(c=col):
+        return orc.render_f64(s64, cam, t, 0.0, 0, (0, 0, 0), pre, bins, w=w, want_img=False, colour=c)[0]
+
+    vis = np.nonzero(pre["radius"] > 0)[0]
+    for i in vis[:8]:
+        for ch in range(3):
+            cp, cm = col.copy(), col.copy()
+            cp[i, ch] += 1e-6
+            cm[i, ch] -= 1e-6
+            fd = (loss(cp) - loss(cm)) / 2e-6
+            assert abs(fd - g2d[i, 6 + ch]) <= 1e-7 * max(1.0, abs(fd)), (i, ch, fd, g2d[i, 6 + ch])
+    rms = {f: np.sqrt(np.mean(grads[f].reshape(-1, sc["n"])[:, vis] ** 2)) for f in ("mu", "opacity", "scale")}
+    for f in ("mu", "opacity", "scale"):
+        arr = s64[f].reshape(-1, sc["n"])
+        g = grads[f].reshape(-1, sc["n"])
+        for i in vis[:6]:
+            old = arr[0, i]
+            h = 1e-5 * max(1.0, abs(old))
+            arr[0, i] = old + h
+            lp = loss()
+            arr[0, i] = old - h
+            lm = loss()
+            arr[0, i] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[0, i]) <= 1e-5 * max(abs(g[0, i]), 1e-2 * rms[f]), (f, i, fd, g[0, i])
