@@ -222,7 +222,14 @@ int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera*
  *              fills it); dL_dvbar and dL_drho their upstream gradients, which
  *              reach v, beta and l.
  * depth_normalized (0 or 1) selects the depth above; the adjoint must be
- * given the forward's choice. */
+ * given the forward's choice.
+ * feature_grad (adjoint only, optional): the view composited three channels
+ * of a per-Gaussian feature vector in place of the colour (its geom->rgb
+ * points at them, [n][3]; the semantic vectors of Sec. 4.1 go through such
+ * views three channels at a time).  Their gradient is added into
+ * feature_grad ([3][n] device, never cleared), no channel counts as
+ * clamped, and the colour's SH and view-direction chain is skipped, so the
+ * parameters receive only the compositing's gradient. */
 typedef struct pvg_channels {
   float* depth;
   const float* dL_ddepth;
@@ -232,6 +239,7 @@ typedef struct pvg_channels {
   const float* dL_dvbar;   /* adjoint input [3][height][width] */
   const float* dL_drho;    /* adjoint input [height][width] */
   int32_t depth_normalized;
+  float* feature_grad;
 } pvg_channels;
 
 /* pvg_render_fwd that also writes the channels requested in `channels`

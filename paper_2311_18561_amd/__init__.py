@@ -25,6 +25,7 @@ from .render import (  # noqa: F401
     preprocess_views,
     pvg_render,
     pvg_render_views,
+    pvg_render_semantic,
     pvg_sky_composite,
     pvg_ssim,
     render,

@@ -61,7 +61,7 @@ class Frame(C.Structure):
 class Channels(C.Structure):
     _fields_ = [("depth", C.c_void_p), ("dL_ddepth", C.c_void_p), ("dL_dT", C.c_void_p), ("vbar", C.c_void_p),
                 ("rho", C.c_void_p), ("dL_dvbar", C.c_void_p), ("dL_drho", C.c_void_p),
-                ("depth_normalized", C.c_int32)]
+                ("depth_normalized", C.c_int32), ("feature_grad", C.c_void_p)]
 
 
 class Geom(C.Structure):

@@ -519,6 +519,7 @@ int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const
     pk.radius[pk.nv] = geoms[k].radius;
     pk.rgb[pk.nv] = geoms[k].rgb;
     pk.g2d[pk.nv] = g2d;
+    pk.feat_grad[pk.nv] = channels ? channels[k].feature_grad : nullptr;
     ++pk.nv;
     if (pk.nv == group || used_slots == kMaxBwdViews) {
       const int st = flush();

@@ -76,7 +76,7 @@ struct GeoGrad {
 // zeroed and g[9..11] the view direction, which is all dL/dsh needs.  rgb is
 // the forward's colour of the Gaussian, where a clamped channel is -0.
 __device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const Proj& P, const float* rgb, float* g,
-                                                 GeoGrad& acc) {
+                                                 GeoGrad& acc, bool feature) {
   const Scene& s = v.s;
   const int64_t n = s.n;
   const int K = (s.degree + 1) * (s.degree + 1);
@@ -87,8 +87,9 @@ __device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const
   float dmr[3] = {0.0f, 0.0f, 0.0f};
 
   // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2), dir = u / |u|; its
-  // dependence on the direction moves the mean
-  {
+  // dependence on the direction moves the mean.  A feature view's "colour"
+  // is a per-Gaussian value: no clamp, no direction term, g[6..8] kept.
+  if (!feature) {
     float draw[3];
     for (int ch = 0; ch < 3; ++ch) draw[ch] = signbit(rgb[ch]) ? 0.0f : g[6 + ch];
     float wk[16];
@@ -288,7 +289,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     Proj P;
     project(pk.views[v], i, P, false);
     view_direction(pk.views[v], P);
-    adjoint_geometry(pk.views[v], i, P, pk.rgb[v] + 3 * i, pk.g2d[v] + kG2DStride * i, acc);
+    adjoint_geometry(pk.views[v], i, P, pk.rgb[v] + 3 * i, pk.g2d[v] + kG2DStride * i, acc,
+                     pk.feat_grad[v] != nullptr);
   }
   if (grad.densify_grad) {
     grad.densify_grad[i] += dnorm;
@@ -312,6 +314,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   for (int v = 0; v < pk.nv; ++v) {
     if (pk.radius[v][i] <= 0) continue;
     const float* g = pk.g2d[v] + kG2DStride * i;  // d(rgb) unclamped part and direction, from the first loop
+    if (pk.feat_grad[v]) {  // a feature view: its gradient goes to the feature rows, not to the SH
+      for (int c = 0; c < 3; ++c) pk.feat_grad[v][c * n + i] += g[6 + c];
+      continue;
+    }
     const float draw[3] = {g[6], g[7], g[8]};
     float Y[16];
 #pragma unroll

@@ -144,6 +144,10 @@ struct BwdViews {
   const int32_t* radius[kMaxBwdViews];
   const float* rgb[kMaxBwdViews];  // the forward's colours (clamped channels are -0)
   float* g2d[kMaxBwdViews];  // the adjoint also leaves per-view scratch values in slots 6..11
+  // non-null: the view composited three channels of a per-Gaussian feature
+  // in place of the colour; their gradient is added here ([3][n]) and the
+  // colour's SH and view-direction chain is skipped
+  float* feat_grad[kMaxBwdViews];
 };
 hipError_t launch_preprocess_bwd(const BwdViews& pk, const pvg_gaussians_grad& grad, int accumulate,
                                  hipStream_t s);

@@ -749,3 +749,95 @@ def pvg_ssim(x, y):
     """Differentiable SSIM map of x against y (see PVGSSIM); the loss term of
     Sec. 3.4 is lambda_r (1 - mean)."""
     return PVGSSIM.apply(x, y)
+
+
+class PVGRenderSemantic(torch.autograd.Function):
+    """Per-Gaussian vectors (e.g. the 19 semantic class scores of Sec. 4.1)
+    composited like the colour, differentiable in the vectors and, through
+    alpha, in the Gaussians.  The compositing kernels take three channels
+    per pass (a geom whose rgb points at them, the view's own lists); the
+    adjoint sends every pass of every view through one multi-view call, with
+    each pass's colour gradient added into the vectors."""
+
+    @staticmethod
+    def forward(ctx, views, feats, *tensors):
+        params, n, degree = _check_params(list(tensors))
+        dev = params[0].device
+        if feats.dim() != 2 or feats.shape[1] != n or feats.dtype != torch.float32:
+            raise ValueError("feats must be float32 [N_channels, n]")
+        nch = int(feats.shape[0])
+        groups = (nch + 2) // 3
+        padded = torch.zeros((groups * 3, n), dtype=torch.float32, device=dev)
+        padded[:nch] = feats
+        fb = padded.reshape(groups, 3, n).transpose(1, 2).contiguous()  # [G][n][3], the geom.rgb layout
+        plans, outs = _forward_views(params, n, degree, views, tile_cull=True)
+        V = len(views)
+        H, W = int(views[0][0]["height"]), int(views[0][0]["width"])
+        out = torch.empty((V, groups * 3, H, W), dtype=torch.float32, device=dev)
+        T_tmp = torch.empty((H, W), dtype=torch.float32, device=dev)
+        nc_tmp = torch.empty((H, W), dtype=torch.int32, device=dev)
+        lib = L.load()
+        for k, (c, f, geom, bins) in enumerate(plans):
+            bs = bins.struct()
+            for gi in range(groups):
+                gs = geom.struct()
+                gs.rgb = fb[gi].data_ptr()
+                L.check(lib.pvg_render_fwd(C.byref(gs), C.byref(bs), C.byref(c), C.byref(f), _p(out[k, 3 * gi]),
+                                           _p(T_tmp), _p(nc_tmp), _stream_handle()))
+        ctx.plans, ctx.n, ctx.degree, ctx.nch, ctx.groups = plans, n, degree, nch, groups
+        ctx.save_for_backward(*params, fb, *[T for _, T, _ in outs], *[nc for _, _, nc in outs])
+        return out[:, :nch]
+
+    @staticmethod
+    def backward(ctx, dout):
+        saved = ctx.saved_tensors
+        params, fb = list(saved[:9]), saved[9]
+        V = len(ctx.plans)
+        Ts, ncs = saved[10:10 + V], saved[10 + V:10 + 2 * V]
+        n, degree, groups = ctx.n, ctx.degree, ctx.groups
+        dev = params[0].device
+        grads = [torch.empty_like(p) for p in params]
+        dfeat = torch.zeros((groups * 3, n), dtype=torch.float32, device=dev)
+        if dout is None:
+            for gr in grads:
+                gr.zero_()
+            return (None, dfeat[:ctx.nch], *grads)
+        H, W = int(dout.shape[2]), int(dout.shape[3])
+        d = torch.zeros((V, groups * 3, H, W), dtype=torch.float32, device=dev)
+        d[:, :ctx.nch] = dout
+        entries = [(k, gi) for k in range(V) for gi in range(groups)]
+        m = len(entries)
+        cams = (L.Camera * m)(*[ctx.plans[k][0] for k, _ in entries])
+        frames = (L.Frame * m)(*[ctx.plans[k][1] for k, _ in entries])
+        geoms = (L.Geom * m)(*[ctx.plans[k][2].struct() for k, _ in entries])
+        for j, (_, gi) in enumerate(entries):
+            geoms[j].rgb = fb[gi].data_ptr()
+        bins = (L.Bins * m)(*[ctx.plans[k][3].struct() for k, _ in entries])
+        f_t = (C.c_void_p * m)(*[Ts[k].data_ptr() for k, _ in entries])
+        n_c = (C.c_void_p * m)(*[ncs[k].data_ptr() for k, _ in entries])
+        d_l = (C.c_void_p * m)(*[d[k, 3 * gi].data_ptr() for k, gi in entries])
+        ch = (L.Channels * m)(*[L.Channels(None, None, None, None, None, None, None, 0,
+                                           dfeat[3 * gi].data_ptr()) for _, gi in entries])
+        g = gaussians_struct(params, n, degree)
+        gg = L.GaussiansGrad()
+        for name, t in zip(FIELDS, grads):
+            setattr(gg, name, t.data_ptr())
+        size = C.c_size_t()
+        lib = L.load()
+        L.check(lib.pvg_bwd_views_tmp_bytes(n, m, W, H, max(p[3].capacity for p in ctx.plans), C.byref(size)))
+        tmp = _scratch(dev, int(size.value))
+        L.check(lib.pvg_render_bwd_views_channels(C.byref(g), m, cams, frames, geoms, bins, f_t, n_c, d_l, ch,
+                                                  C.byref(gg), 0, _p(tmp), int(tmp.numel()), _stream_handle()))
+        return (None, dfeat[:ctx.nch], *grads)
+
+
+def pvg_render_semantic(params, views, feats):
+    """Composited per-Gaussian vectors [V, N_channels, H, W] for views of one
+    resolution (views as for pvg_render_views); feats: float32 [N_channels,
+    n] on the parameters' device (the semantic class scores of Sec. 4.1;
+    the cross-entropy against 2D labels is the caller's).  Differentiable in
+    feats and the parameters."""
+    full = _full_views(views)
+    if len({(int(v[0]["width"]), int(v[0]["height"])) for v in full}) != 1:
+        raise ValueError("views of one resolution are required")
+    return PVGRenderSemantic.apply(full, feats.contiguous(), *params)
