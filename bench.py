@@ -466,6 +466,27 @@ def main():
     t_full = time.perf_counter() - t0
     del train_params, adam
 
+    # semantic rendering (Sec. 4.1): 19 class scores per Gaussian composited
+    # over the six views and differentiated (vectors and Gaussians)
+    sem = torch.randn((19, N), device="cuda", generator=gch).requires_grad_(True)
+    sem_w = torch.randn((V, 19, H, W), device="cuda", generator=gch)
+
+    def semantic_step():
+        for p in params:
+            p.grad = None
+        sem.grad = None
+        (pvg.pvg_render_semantic(params, views, sem) * sem_w).sum().backward()
+
+    semantic_step()
+    torch.cuda.synchronize()
+    sem_reps = 3
+    t0 = time.perf_counter()
+    for _ in range(sem_reps):
+        semantic_step()
+    torch.cuda.synchronize()
+    t_sem = (time.perf_counter() - t0) / sem_reps
+    del sem, sem_w
+
     # one adaptive-control pass (Sec. 3.3) on the statistics those steps
     # accumulated: r = 30 m (the foreground radius of Sec. 4), the densify
     # threshold 1.7e-4, g = 0.01 r, b = 0.1 r; the Adam moments of every
@@ -563,6 +584,9 @@ def main():
         "iters_per_s_channels": args.steps / t_channels,
         "iters_per_s_channels_median_step": 1.0 / ch_med,
         "iters_per_s_full_iteration": args.steps / t_full,
+        "semantic_ms_per_step": t_sem * 1e3,
+        "semantic_note": ("pvg_render_semantic forward and backward of 19 class scores per Gaussian over the six "
+                          "views (seven three-channel passes per view on the view's lists, one adjoint call)"),
         "full_iteration_note": ("the channel step with the colour term (1 - 0.2) L1 + 0.2 (1 - SSIM) per view "
                                 "(pvg_ssim, 11 x 11 Gaussian window), followed by pvg_adam_step over all parameter "
                                 "rows (Sec. 4 rates; the cube map is not updated); the temporal-smoothing sampling "
