@@ -44,8 +44,17 @@ class PVGAdam:
         c.beta1, c.beta2, c.eps, c.step = float(self.betas[0]), float(self.betas[1]), float(self.eps), self.t
         return c
 
+    @staticmethod
+    def _in_place(params):
+        """The parameters themselves (updated in place): they must be contiguous,
+        or the update would land in a copy."""
+        params = list(params)
+        if any(not p.is_contiguous() for p in params):
+            raise ValueError("parameters updated in place must be contiguous")
+        return _check_params(params)
+
     def step(self, params, grads=None):
-        params, n, degree = _check_params(list(params))
+        params, n, degree = self._in_place(params)
         grads = [p.grad for p in params] if grads is None else list(grads)
         if any(g is None or g.shape != p.shape or not g.is_contiguous() for g, p in zip(grads, params)):
             raise ValueError("every parameter needs a contiguous gradient of its shape")
@@ -61,7 +70,7 @@ class PVGAdam:
                                        C.byref(c), _stream_handle()))
 
     def reset_opacity(self, params, cap=0.01):
-        params, n, degree = _check_params(list(params))
+        params, n, degree = self._in_place(params)
         gs = gaussians_struct(params, n, degree)
         L.check(L.load().pvg_opacity_reset(C.byref(gs), _p(self.moments[0]), _p(self.moments[1]), float(cap),
                                            _stream_handle()))

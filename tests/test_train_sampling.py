@@ -38,3 +38,14 @@ def test_eta_limits_and_errors():
         args.update(kw)
         with pytest.raises(ValueError):
             temporal_smoothing_views(**args)
+
+
+def test_adam_refuses_non_contiguous_parameters():
+    """An in-place update of a copy would leave the caller's tensor as it was:
+    non-contiguous parameters are refused before any GPU work."""
+    import torch
+
+    from paper_2311_18561_amd.optim import PVGAdam
+    mu = torch.zeros((4, 3)).t()  # [3, 4] view, not contiguous
+    with pytest.raises(ValueError):
+        PVGAdam._in_place([mu])
