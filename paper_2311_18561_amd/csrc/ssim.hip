@@ -31,9 +31,23 @@ struct Window {
   float w[2 * kR + 1];
 };
 
+// Workgroup b takes tile (b mod 8) * per + b / 8: workgroups are dealt to the
+// eight XCDs in turn, so each XCD gets a contiguous band of tiles and the
+// halos that neighbouring tiles share stay in its L2.  Tiles past the end
+// (the grid is 8 per) exit at once.
+__device__ __forceinline__ int64_t band_tile(int64_t b, int64_t total) {
+  const int64_t per = (total + 7) / 8;
+  return (b % 8) * per + b / 8;
+}
+
+// The SSIM kernels may fuse multiply-adds and use the hardware reciprocal:
+// no decision depends on their rounding (the bar is a tolerance), and with
+// contraction off they were bound by the separate multiplies and adds of the
+// window sums and the IEEE division sequences.
 template <int kMaps>
 __device__ __forceinline__ void filter_tile(const float (*src)[kHalo][kHalo], float (*h)[kHalo][kST],
                                             const Window& win, int tr, int tc, float out[kMaps]) {
+#pragma clang fp contract(fast)
   // rows: kHalo x kST outputs per map, shared by the workgroup
   for (int e = threadIdx.x; e < kHalo * kST; e += 256) {
     const int r = e / kST, c = e % kST;
@@ -56,15 +70,18 @@ __device__ __forceinline__ void filter_tile(const float (*src)[kHalo][kHalo], fl
 }
 
 __global__ void __launch_bounds__(256) k_ssim_fwd(const float* __restrict__ x, const float* __restrict__ y, int H,
-                                                  int W, int GX, Window win, float* __restrict__ smap,
-                                                  float* __restrict__ part) {
+                                                  int W, int GX, int64_t ntiles, Window win,
+                                                  float* __restrict__ smap, float* __restrict__ part) {
+#pragma clang fp contract(fast)
   __shared__ float s_src[5][kHalo][kHalo];
   __shared__ float s_h[5][kHalo][kST];
   const int ch = blockIdx.y;
   const int64_t HW = static_cast<int64_t>(H) * W;
   const float* xc = x + ch * HW;
   const float* yc = y + ch * HW;
-  const int x0 = static_cast<int>(blockIdx.x % GX) * kST - kR, y0 = static_cast<int>(blockIdx.x / GX) * kST - kR;
+  const int64_t tile = band_tile(blockIdx.x, ntiles);
+  if (tile >= ntiles) return;  // the whole workgroup, before any barrier
+  const int x0 = static_cast<int>(tile % GX) * kST - kR, y0 = static_cast<int>(tile / GX) * kST - kR;
   for (int e = threadIdx.x; e < kHalo * kHalo; e += 256) {
     const int r = e / kHalo, c = e % kHalo;
     const int py = y0 + r, px = x0 + c;
@@ -89,27 +106,32 @@ __global__ void __launch_bounds__(256) k_ssim_fwd(const float* __restrict__ x, c
   const float sxx = f[2] - mx * mx, syy = f[3] - my * my, sxy = f[4] - mx * my;
   const float A = 2.0f * mx * my + kC1, B = 2.0f * sxy + kC2;
   const float Cc = mx * mx + my * my + kC1, D = sxx + syy + kC2;
-  const float Q = 1.0f / (Cc * D);  // C >= C1 and D near sxx + syy + C2 > 0: never 0
+  // C >= C1 and D near sxx + syy + C2 > 0: neither is ever 0
+  const float iC = __builtin_amdgcn_rcpf(Cc), iD = __builtin_amdgcn_rcpf(D);
+  const float Q = iC * iD;
   const float S = (A * B) * Q;
   const int64_t o = ch * HW + static_cast<int64_t>(py) * W + px;
   if (smap) smap[o] = S;
   const int64_t CHW = static_cast<int64_t>(gridDim.y) * HW;
   // dS/dmx (through A, B, C, D), dS/d(G*x^2) (through D), dS/d(G*xy) (through
   // B); no division by A or B, which may pass through 0
-  part[o] = 2.0f * my * (B - A) * Q + 2.0f * mx * S * (1.0f / D - 1.0f / Cc);
-  part[CHW + o] = -S / D;
+  part[o] = 2.0f * my * (B - A) * Q + 2.0f * mx * S * (iD - iC);
+  part[CHW + o] = -S * iD;
   part[2 * CHW + o] = 2.0f * A * Q;
 }
 
 __global__ void __launch_bounds__(256) k_ssim_bwd(const float* __restrict__ g, const float* __restrict__ x,
                                                   const float* __restrict__ y, const float* __restrict__ part, int H,
-                                                  int W, int GX, Window win, float* __restrict__ dx) {
+                                                  int W, int GX, int64_t ntiles, Window win, float* __restrict__ dx) {
+#pragma clang fp contract(fast)
   __shared__ float s_src[3][kHalo][kHalo];
   __shared__ float s_h[3][kHalo][kST];
   const int ch = blockIdx.y;
   const int64_t HW = static_cast<int64_t>(H) * W;
   const int64_t CHW = static_cast<int64_t>(gridDim.y) * HW;
-  const int x0 = static_cast<int>(blockIdx.x % GX) * kST - kR, y0 = static_cast<int>(blockIdx.x / GX) * kST - kR;
+  const int64_t tile = band_tile(blockIdx.x, ntiles);
+  if (tile >= ntiles) return;  // the whole workgroup, before any barrier
+  const int x0 = static_cast<int>(tile % GX) * kST - kR, y0 = static_cast<int>(tile / GX) * kST - kR;
   for (int e = threadIdx.x; e < kHalo * kHalo; e += 256) {
     const int r = e / kHalo, c = e % kHalo;
     const int py = y0 + r, px = x0 + c;
@@ -153,8 +175,9 @@ hipError_t launch_ssim_fwd(const float* x, const float* y, int C, int H, int W, 
                            hipStream_t st) {
   if (static_cast<int64_t>(H) * W * C == 0) return hipSuccess;
   const int GX = (W + kST - 1) / kST, GY = (H + kST - 1) / kST;
-  hipLaunchKernelGGL(k_ssim_fwd, dim3(static_cast<unsigned>(GX) * GY, C), dim3(256), 0, st, x, y, H, W, GX,
-                     gaussian_window(), smap, part);
+  const int64_t ntiles = static_cast<int64_t>(GX) * GY;
+  hipLaunchKernelGGL(k_ssim_fwd, dim3(static_cast<unsigned>(8 * ((ntiles + 7) / 8)), C), dim3(256), 0, st, x, y, H,
+                     W, GX, ntiles, gaussian_window(), smap, part);
   return hipGetLastError();
 }
 
@@ -162,8 +185,9 @@ hipError_t launch_ssim_bwd(const float* g, const float* x, const float* y, const
                            float* dx, hipStream_t st) {
   if (static_cast<int64_t>(H) * W * C == 0) return hipSuccess;
   const int GX = (W + kST - 1) / kST, GY = (H + kST - 1) / kST;
-  hipLaunchKernelGGL(k_ssim_bwd, dim3(static_cast<unsigned>(GX) * GY, C), dim3(256), 0, st, g, x, y, part, H, W, GX,
-                     gaussian_window(), dx);
+  const int64_t ntiles = static_cast<int64_t>(GX) * GY;
+  hipLaunchKernelGGL(k_ssim_bwd, dim3(static_cast<unsigned>(8 * ((ntiles + 7) / 8)), C), dim3(256), 0, st, g, x, y,
+                     part, H, W, GX, ntiles, gaussian_window(), dx);
   return hipGetLastError();
 }
 
