@@ -994,7 +994,7 @@ int orc_project_f64(const double* mu, const double* s, const double* q, const fl
 // learnable cube map looked up in the pixel's viewing direction d, here taken
 // through the pixel centre moved by an optional jitter (the paper perturbs d
 // within the unit pixel while training); the lookup geometry in FP32, the
-// blend in FP64.  Conventions of this build (the
+// blend in FP64.  Conventions taken here (the
 // paper fixes none): d_cam = ((px + 0.5 + jx - cx) / fx, (py + 0.5 + jy - cy)
 // / fy, 1), d = R^T d_cam in the world frame; faces +X, -X, +Y, -Y, +Z, -Z
 // (0..5) chosen by the largest |d_i| (ties to the lower axis); face
