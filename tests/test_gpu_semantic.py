@@ -33,12 +33,16 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("name,mk_scene,mk_cam,t", CASES)
-def test_semantic_vs_fp64(orc, name, mk_scene, mk_cam, t):
+# 19 channels (seven passes, the last padded) on both cases; 3 (one exact
+# pass) and 1 (one padded pass) on the tiny case
+RUNS = [(*CASES[0], 19), (*CASES[1], 19), (*CASES[0], 3), (*CASES[0], 1)]
+
+
+@pytest.mark.parametrize("name,mk_scene,mk_cam,t,N", RUNS)
+def test_semantic_vs_fp64(orc, name, mk_scene, mk_cam, t, N):
     import paper_2311_18561_amd as pvg
     scene, cam = mk_scene(), mk_cam()
     n, H, W = scene["n"], cam["height"], cam["width"]
-    N = 19
     rng = np.random.default_rng(13)
     feats = rng.standard_normal((N, n)).astype(np.float32)
     dts = (0.0, 0.05)
@@ -76,7 +80,7 @@ def test_semantic_vs_fp64(orc, name, mk_scene, mk_cam, t):
                 mag[f] += np.abs(part[f])
             dfeat[3 * gi:3 * gi + 3] += g2d[:, 6:9].T
             dmag[3 * gi:3 * gi + 3] += g2d_abs[:, 6:9].T
-    print(f"[semantic {name}] max |map - oracle| = {worst_map:.3g}")
+    print(f"[semantic {name} N={N}] max |map - oracle| = {worst_map:.3g}")
     assert worst_map <= 2e-5
     worst, l2 = grad_tolerance_report(tf.grad.cpu().numpy(), dfeat[:N], rel=1e-3, magnitude=dmag[:N])
     print(f"[semantic {name}] vectors: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
@@ -89,3 +93,15 @@ def test_semantic_vs_fp64(orc, name, mk_scene, mk_cam, t):
         worst, l2 = grad_tolerance_report(g, ref[f], rel=1e-3, magnitude=mag[f])
         print(f"[semantic {name}] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
         assert worst <= 1.0, f
+
+
+def test_semantic_rejects_bad_shapes():
+    import paper_2311_18561_amd as pvg
+    cfg = gen.make_config(0)
+    params = to_device(cfg["scene"])
+    cam = cfg["cameras"][0]
+    with pytest.raises(ValueError):
+        pvg.pvg_render_semantic(params, [(cam, 0.5)], torch.zeros((4, cfg["scene"]["n"] + 1), device="cuda"))
+    with pytest.raises(ValueError):
+        pvg.pvg_render_semantic(params, [(cam, 0.5), (gen.yaw_camera(64, 48, 0.0, (0, 0, 0)), 0.5)],
+                                torch.zeros((4, cfg["scene"]["n"]), device="cuda"))
