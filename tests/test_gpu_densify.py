@@ -152,3 +152,30 @@ def test_view_space_statistics_vs_fp64(orc, recompute):
     ratio = np.abs(got - 2 * ref_acc) / (1e-3 * np.maximum(2 * ref_acc, floor))
     print(f"[stats recompute={recompute}] worst/tol = {ratio.max():.3g}, visible (view 0) {int(vis[0].sum())}")
     assert ratio.max() <= 1.0
+
+
+def test_densify_bench_shape_bit_exact(orc):
+    """The benchmark's pass: the 1M-Gaussian driving-path scene, r = 30,
+    threshold 1.7e-4, g = 0.01 r, b = 0.1 r, and the Adam moments of all 65
+    parameter rows carried (130 rows: five row slices of the apply grid);
+    bit-exact against the oracle."""
+    import paper_2311_18561_amd as pvg
+    sc = gen.make_config(2)["scene"]
+    n = sc["n"]
+    rng = np.random.default_rng(21)
+    acc = rng.uniform(0, 4e-4, n).astype(np.float32)
+    cnt = rng.integers(0, 7, n).astype(np.float32)
+    noise = rng.standard_normal((8, n)).astype(np.float32)
+    extra = rng.standard_normal((130, n)).astype(np.float32)
+    cfg = dict(grad_threshold=1.7e-4, scene_radius=30.0, clone_scale=0.3, prune_scale=3.0, min_opacity=0.0,
+               split_scale_decay=0.8, split_beta_decay=1.0)
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    out, ex = pvg.densify(to_device(sc), cu(acc), cu(cnt), cu(noise), pvg.densify_config(30.0), cu(extra))
+    ref, ref_ex = orc.adaptive.densify(sc, acc, cnt, noise, cfg, extra)
+    keeps = orc.adaptive.plan(sc, acc, cnt, noise, cfg)
+    print(f"[densify 1M] out {ref['n']}: clones {int(keeps[1].sum())}, children {int(keeps[2].sum() + keeps[3].sum())}, "
+          f"pruned {int(n - keeps[0].sum() - (keeps[2] | keeps[3]).sum())}")
+    assert out[0].shape[-1] == ref["n"]
+    for f, o in zip(FIELDS, out):
+        assert np.array_equal(o.cpu().numpy(), ref[f]), f
+    assert np.array_equal(ex.cpu().numpy(), ref_ex)
