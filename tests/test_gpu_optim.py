@@ -104,3 +104,38 @@ def test_opacity_reset_and_moments_through_densify(orc):
     opt.set_moments_rows(rows)
     assert opt.moments.shape == (2, 17 + 3 * K, new[0].shape[1])
     opt.step(new, [torch.zeros_like(p) for p in new])  # runs on the new count
+
+
+def test_adam_bench_shape(orc):
+    """The benchmark's optimizer step: the 1M-Gaussian degree-3 scene with
+    the default rates (r = 30), two steps, against the oracle with the bars
+    of test_adam_vs_fp64."""
+    import paper_2311_18561_amd as pvg
+    sc = gen.make_config(2)["scene"]
+    n = sc["n"]
+    lrs = pvg.default_lrs(30.0)
+    lrs32 = {k: f32(v) for k, v in lrs.items()}
+    params = to_device(sc)
+    opt = pvg.PVGAdam(params, lrs)
+    ref = {k: (np.asarray(v, np.float64) if isinstance(v, np.ndarray) else v) for k, v in sc.items()}
+    rows = orc.optim.rows_of(ref)
+    m = np.zeros((len(rows), n))
+    v = np.zeros((len(rows), n))
+    rng = np.random.default_rng(8)
+    for t in (1, 2):
+        g = {f: (rng.standard_normal(np.shape(sc[f])) * 1e-3).astype(np.float32) for f in FIELDS}
+        opt.step(params, [torch.from_numpy(g[f]).cuda() for f in FIELDS])
+        ref, m, v = orc.optim.adam_step(ref, {f: g[f].astype(np.float64) for f in FIELDS}, m, v, lrs32, t,
+                                        beta1=f32(0.9), beta2=f32(0.999), eps=f32(1e-15))
+    torch.cuda.synchronize()
+    for f, p in zip(FIELDS, params):
+        got = p.cpu().numpy().astype(np.float64)
+        lr = max(lrs32["sh0"], lrs32["shN"]) if f == "sh" else lrs32[f]
+        err = np.abs(got - ref[f]) - (2e-6 * np.abs(ref[f]) + 2e-6 * lr)
+        assert err.max() <= 0, (f, float(err.max()))
+    mm = opt.moments.cpu().numpy().astype(np.float64)
+    for got, want, name in ((mm[0], m, "m"), (mm[1], v, "v")):
+        row_scale = np.abs(want).max(axis=1, keepdims=True)
+        err = np.abs(got - want) - (1e-5 * np.abs(want) + 1e-6 * row_scale)
+        assert err.max() <= 0, (name, float(err.max()))
+    print(f"[adam 1M] two steps within tolerance over {len(rows)} rows")
