@@ -157,3 +157,74 @@ def test_large_scene_six_cameras_sampled(orc):
         worst, l2 = grad_tolerance_report(got[f][:, touched], ref[f][:, touched])
         print(f"[6M] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
         assert worst <= 1.0, f
+
+
+def test_channels_full_size_sampled(orc):
+    """The channel step's render at the benchmark's shape: the six views of
+    the 1M-Gaussian workload through pvg_render_views(channels=True,
+    normalized_depth=True).  For the middle camera's flow-translated view:
+    one tile row of the normalized depth, velocity and staticness maps
+    against the oracle, and a loss on normalized depth, opacity, velocity
+    and staticness confined to six tiles against the FP64 adjoint on those
+    tiles (the tolerance summed over the loss's sources: the quotient's two
+    terms and the rest)."""
+    import paper_2311_18561_amd as pvg
+    cfg = gen.make_config(2)
+    scene, cams, t, dt = cfg["scene"], cfg["cameras"], cfg["t"], cfg["dt"]
+    W, H = cfg["width"], cfg["height"]
+    GX, GY = (W + 15) // 16, (H + 15) // 16
+    views = [(cam, t, d) for cam in cams for d in (0.0, dt)]
+    k, cam, d = 3, cams[1], dt
+    rng = np.random.default_rng(31)
+    m = np.zeros(GX * GY, np.uint8)
+    m[rng.choice(np.arange(GX * (GY // 4), GX * (3 * GY // 4)), 6, replace=False)] = 1
+    keep = np.repeat(np.repeat(m.reshape(GY, GX), 16, 0), 16, 1)[:H, :W].astype(np.float64)
+    wD = (0.05 * rng.standard_normal((H, W)) * keep).astype(np.float32)
+    wO = (rng.standard_normal((H, W)) * keep).astype(np.float32)
+    wF = (rng.standard_normal((4, H, W)) * keep).astype(np.float32)
+    params = [p.requires_grad_(True) for p in to_device(scene)]
+    img, dn, opac, vbar, rho = pvg.pvg_render_views(params, views, channels=True, normalized_depth=True)
+    cu = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    loss = ((dn[k] * cu(wD)).sum() + (opac[k] * cu(wO)).sum() + (vbar[k] * cu(wF[:3])).sum()
+            + (rho[k] * cu(wF[3])).sum())
+    loss.backward()
+    got = {f: p.grad.detach().cpu().numpy().astype(np.float64) for f, p in zip(FIELDS, params)}
+    sc64 = orc.scene64(scene)
+    pre = orc.preprocess_f32(scene, cam, t, d)
+    bins = orc.bin_sort(pre, cam)
+    args = (sc64, cam, t, d, 0, (0.0, 0.0, 0.0), pre, bins)
+    # forward: one tile row
+    row = GY // 2
+    rmask = np.zeros(GX * GY, np.uint8)
+    rmask[row * GX:(row + 1) * GX] = 1
+    _, _, T64, D64 = orc.render_f64(*args, tile_mask=rmask, want_depth=True)
+    ys = slice(row * 16, row * 16 + 16)
+    want = orc.normalized_depth_f64(D64, T64)[ys]
+    hit = want > 0
+    rel = np.abs(dn[k].detach().cpu().numpy()[ys] - want)[hit] / want[hit]
+    _, _, _, F = orc.render_f32(pre, bins, cam, t, d, want_feat=True, tiles=(row * GX, (row + 1) * GX))
+    got_f = np.concatenate([vbar[k].detach().cpu().numpy(), rho[k].detach().cpu().numpy()[None]])[:, ys]
+    ferr = float(np.abs(got_f - F[:, ys]).max()) / max(1.0, float(np.abs(F[:, ys]).max()))
+    print(f"[channels full size] row {row}: normalized depth max rel err {rel.max():.3g}, "
+          f"velocity / staticness {ferr:.3g}")
+    assert rel.max() <= 5e-5 and ferr <= 1e-5
+    # backward on six tiles
+    _, _, Tm, Dm = orc.render_f64(*args, tile_mask=m, want_depth=True)
+    dD, dTn = orc.normalized_depth_bwd_f64(wD.astype(np.float64), Dm, Tm)
+    zero = np.zeros((3, H, W))
+    pD, _ = orc.backward_f64(*args, zero, tile_mask=m, dD=dD)
+    pT, _ = orc.backward_f64(*args, zero, tile_mask=m, dT=dTn)
+    pR, _ = orc.backward_f64(*args, zero, tile_mask=m, dT=-wO.astype(np.float64), dF=wF.astype(np.float64))
+    touched = np.zeros(scene["n"], bool)
+    for f in FIELDS:
+        touched |= (np.abs(pD[f]) + np.abs(pT[f]) + np.abs(pR[f])).reshape(-1, scene["n"]).max(axis=0) > 0
+    assert touched.sum() > 100
+    n = scene["n"]
+    for f in FIELDS:
+        ref = (pD[f] + pT[f] + pR[f]).reshape(-1, n)
+        mag = (np.abs(pD[f]) + np.abs(pT[f]) + np.abs(pR[f])).reshape(-1, n)
+        g2 = got[f].reshape(-1, n)
+        assert np.abs(g2[:, ~touched]).max() <= 1e-6 * max(np.abs(ref).max(), 1e-30), f
+        worst, l2 = grad_tolerance_report(g2[:, touched], ref[:, touched], rel=1e-3, magnitude=mag[:, touched])
+        print(f"[channels full size] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+        assert worst <= 1.0, f
