@@ -40,44 +40,84 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def _open(path):
+    L = C.CDLL(path)
+    vp = C.c_void_p
+    i64, i32 = C.c_int64, C.c_int
+    L.orc_preprocess_f32.argtypes = [i64, i32, vp, vp, i32, i32, vp] + [vp] * 9
+    L.orc_preprocess_f32.restype = None
+    L.orc_bin_sort.argtypes = [i64, vp, vp, vp, i32, i32, i64, vp, vp, vp]
+    L.orc_bin_sort.restype = i64
+    L.orc_render_f32.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, i64, i64, vp, vp, vp, vp, vp,
+                                 vp, vp]
+    L.orc_render_f32.restype = None
+    L.orc_render_bruteforce_f32.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
+    L.orc_render_bruteforce_f32.restype = None
+    L.orc_render_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                 vp, vp, vp, vp, vp, vp]
+    L.orc_render_f64.restype = C.c_double
+    L.orc_backward_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                   vp, vp, vp, vp]
+    L.orc_backward_f64.restype = None
+    L.orc_temporal_f64.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                   C.c_double, C.c_double, i32, vp, vp]
+    L.orc_temporal_f64.restype = None
+    L.orc_sh_basis_f64.argtypes = [i32, vp, vp, vp]
+    L.orc_sh_basis_f64.restype = None
+    L.orc_project_f64.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
+    L.orc_project_f64.restype = C.c_int
+    L.orc_sky_f64.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp]
+    L.orc_sky_f64.restype = None
+    L.orc_sky_bwd_f64.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp, vp]
+    L.orc_sky_bwd_f64.restype = None
+    L.orc_sky_face_uv.argtypes = [vp, vp, vp]
+    L.orc_sky_face_uv.restype = None
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = C.CDLL(_LIB)
-        vp = C.c_void_p
-        i64, i32 = C.c_int64, C.c_int
-        L.orc_preprocess_f32.argtypes = [i64, i32, vp, vp, i32, i32, vp] + [vp] * 9
-        L.orc_preprocess_f32.restype = None
-        L.orc_bin_sort.argtypes = [i64, vp, vp, vp, i32, i32, i64, vp, vp, vp]
-        L.orc_bin_sort.restype = i64
-        L.orc_render_f32.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, i64, i64, vp, vp, vp, vp, vp,
-                                     vp, vp]
-        L.orc_render_f32.restype = None
-        L.orc_render_bruteforce_f32.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
-        L.orc_render_bruteforce_f32.restype = None
-        L.orc_render_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
-                                     vp, vp, vp, vp, vp, vp]
-        L.orc_render_f64.restype = C.c_double
-        L.orc_backward_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
-                                       vp, vp, vp, vp]
-        L.orc_backward_f64.restype = None
-        L.orc_temporal_f64.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, C.c_double,
-                                       C.c_double, C.c_double, i32, vp, vp]
-        L.orc_temporal_f64.restype = None
-        L.orc_sh_basis_f64.argtypes = [i32, vp, vp, vp]
-        L.orc_sh_basis_f64.restype = None
-        L.orc_project_f64.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, vp]
-        L.orc_project_f64.restype = C.c_int
-        L.orc_sky_f64.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp]
-        L.orc_sky_f64.restype = None
-        L.orc_sky_bwd_f64.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp, vp]
-        L.orc_sky_bwd_f64.restype = None
-        L.orc_sky_face_uv.argtypes = [vp, vp, vp]
-        L.orc_sky_face_uv.restype = None
-        _lib = L
+        _lib = _open(_LIB)
     return _lib
+
+
+def build_variant(src_text: str, out_path: str) -> str:
+    """Compile a variant of the oracle's source (the tests plant mistakes in
+    it to show that a pin catches them) with the oracle's own flags."""
+    src = out_path + ".cpp"
+    with open(src, "w") as fh:
+        fh.write(src_text)
+    cmd = ["g++", "-O2", "-std=c++17", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-o",
+           out_path, src]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
+def source_text() -> str:
+    with open(_SRC) as fh:
+        return fh.read()
+
+
+class use_library:
+    """Context manager: every oracle call inside it goes to the library at
+    `path` (a variant built by build_variant) instead of liboracle.so."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = lib()
+        _lib = _open(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
 
 
 def _p(a):

@@ -9,7 +9,7 @@ import ctypes as C
 import torch
 
 from . import _lib as L
-from .render import FIELDS, _check_params, _p, _stream_handle, gaussians_struct
+from .render import FIELDS, _check_params, _p, _stream_handle, check_tensor, gaussians_struct
 
 
 def densify_config(scene_radius, grad_threshold=1.7e-4, clone_scale=None, prune_scale=None, min_opacity=0.0,
@@ -29,12 +29,13 @@ def densify(params, grad_accum, grad_count, noise, cfg: L.DensifyConfig, extra=N
     (kept for surviving originals, zero for new Gaussians)."""
     params, n, degree = _check_params(list(params))
     dev = params[0].device
-    for t, shp in ((grad_accum, (n,)), (grad_count, (n,)), (noise, (8, n))):
-        if t.shape != shp or t.dtype != torch.float32 or not t.is_contiguous() or t.device != dev:
-            raise ValueError(f"expected a contiguous float32 {shp} tensor on {dev}")
-    if extra is not None and (extra.dim() != 2 or extra.shape[1] != n or extra.dtype != torch.float32
-                              or not extra.is_contiguous()):
-        raise ValueError("extra must be a contiguous float32 [R, N] tensor")
+    for t, shp, what in ((grad_accum, (n,), "grad_accum"), (grad_count, (n,), "grad_count"),
+                         (noise, (8, n), "noise")):
+        check_tensor(t, shp, dev, what)
+    if extra is not None:
+        if not isinstance(extra, torch.Tensor) or extra.dim() != 2:
+            raise ValueError("extra must be a [R, N] tensor")
+        check_tensor(extra, (extra.shape[0], n), dev, "extra")
     lib = L.load()
     size = C.c_size_t()
     L.check(lib.pvg_densify_tmp_bytes(n, C.byref(size)))

@@ -8,7 +8,7 @@ import ctypes as C
 import torch
 
 from . import _lib as L
-from .render import FIELDS, _check_params, _p, _stream_handle, gaussians_struct
+from .render import FIELDS, _check_params, _p, _stream_handle, check_tensor, gaussians_struct
 
 # order of the learning rates in pvg_adam_config
 LR_KEYS = ("mu", "scale", "rot", "sh0", "shN", "opacity", "vel", "period", "tau", "beta")
@@ -56,8 +56,10 @@ class PVGAdam:
     def step(self, params, grads=None):
         params, n, degree = self._in_place(params)
         grads = [p.grad for p in params] if grads is None else list(grads)
-        if any(g is None or g.shape != p.shape or not g.is_contiguous() for g, p in zip(grads, params)):
-            raise ValueError("every parameter needs a contiguous gradient of its shape")
+        if len(grads) != len(params) or any(g is None for g in grads):
+            raise ValueError("every parameter needs a gradient")
+        for name, g, p in zip(FIELDS, grads, params):
+            check_tensor(g, p.shape, p.device, f"the gradient of {name}")
         if self.moments.shape[2] != n:
             raise ValueError("the moments were sized for another Gaussian count (carry them through densify)")
         self.t += 1
@@ -80,4 +82,9 @@ class PVGAdam:
         return self.moments.reshape(-1, self.moments.shape[2])
 
     def set_moments_rows(self, rows):
-        self.moments = rows.reshape(2, -1, rows.shape[1]).contiguous()
+        """Take the moments back from densify's carried rows [2 (17 + 3K), N']."""
+        if not isinstance(rows, torch.Tensor) or rows.dim() != 2:
+            raise ValueError("moment rows must be a 2-D tensor")
+        check_tensor(rows, (self.moments.shape[0] * self.moments.shape[1], rows.shape[1]), self.moments.device,
+                     "the moment rows")
+        self.moments = rows.reshape(2, -1, rows.shape[1])

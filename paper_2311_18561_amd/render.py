@@ -58,6 +58,23 @@ def _check_params(params):
     return out, n, degree
 
 
+def check_tensor(t, shape, device, what):
+    """A buffer handed to a kernel: float32, contiguous, of `shape`, on
+    `device`.  Raises (before any launch) otherwise: a host tensor would pass
+    a host pointer to the kernel and another dtype a buffer of another size."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{what} must be float32, got {t.dtype}")
+    if t.device != torch.device(device):
+        raise ValueError(f"{what} is on {t.device}, expected {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t
+
+
 def gaussians_struct(params, n, degree) -> L.Gaussians:
     g = L.Gaussians()
     g.n = n
