@@ -196,6 +196,22 @@ int pvg_preprocess_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
 int pvg_bin_sort(const pvg_geom* geom, const pvg_camera* cam, pvg_bins* bins, void* tmp,
                  size_t tmp_bytes, int32_t sync_count, void* stream);
 
+/* pvg_bin_sort without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP stream capture, tight serving loops, hosts
+ * that forbid allocation): the scratch is a library-held device array of
+ * PVG_NOALLOC_SCRATCH_BYTES, one per device, held until the process ends.
+ * Same arguments, outputs, sync_count semantics and errors as pvg_bin_sort,
+ * with identical results; PVG_ERR_NOMEM (nothing launched) when the scratch
+ * that n, the camera's tile count and bins->capacity need (the
+ * bin_tmp_bytes of pvg_workspace_query) exceeds PVG_NOALLOC_SCRATCH_BYTES.
+ * Calls no device allocation or free; the stage profiler records no events
+ * for it.  Every call on a device shares that device's array, which keeps
+ * the last call's contents: calls ordered on one stream are safe, calls
+ * that overlap on one device (other streams, other threads) race. */
+#define PVG_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int pvg_bin_sort_noalloc(const pvg_geom* geom, const pvg_camera* cam, pvg_bins* bins, int32_t sync_count,
+                         void* stream);
+
 /* Front-to-back alpha blending of each pixel's tile list (Eq. (3)).
  * img [3][height][width] = C + T_final * bg; final_T [height][width];
  * n_contrib [height][width] = list position of the last contributor + 1. */

@@ -19,6 +19,7 @@ PVG_ERR_BUSY = -4
 PVG_ERR_HIP = -5
 PVG_ERR_NOT_FOUND = -6
 PVG_ERR_TIMEOUT = -7
+NOALLOC_SCRATCH_BYTES = 256 << 20  # PVG_NOALLOC_SCRATCH_BYTES of include/pvg.h
 
 STAGES = ("preprocess", "compact", "depth_sort", "scan_emit", "tile_sort", "ranges", "render_fwd", "render_bwd",
           "preprocess_bwd", "grad_gather")
@@ -127,6 +128,7 @@ def load():
         "pvg_preprocess": ([P(Gaussians), P(Camera), P(Frame), P(Geom), vp], i32),
         "pvg_preprocess_views": ([P(Gaussians), i32, P(Camera), P(Frame), P(Geom), vp], i32),
         "pvg_bin_sort": ([P(Geom), P(Camera), P(Bins), vp, C.c_size_t, i32, vp], i32),
+        "pvg_bin_sort_noalloc": ([P(Geom), P(Camera), P(Bins), i32, vp], i32),
         "pvg_render_fwd": ([P(Geom), P(Bins), P(Camera), P(Frame), vp, vp, vp, vp], i32),
         "pvg_sky_composite": ([P(Camera), vp, vp, vp, i32, vp, vp, vp], i32),
         "pvg_sky_composite_bwd": ([P(Camera), vp, vp, vp, i32, vp, vp, vp, vp], i32),

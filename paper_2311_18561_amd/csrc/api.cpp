@@ -54,7 +54,14 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
-bool profiling() { return g_prof_on; }
+namespace {
+thread_local bool t_no_profile = false;
+}
+
+NoProfile::NoProfile() : prev_(t_no_profile) { t_no_profile = true; }
+NoProfile::~NoProfile() { t_no_profile = prev_; }
+
+bool profiling() { return g_prof_on && !t_no_profile; }
 
 unsigned long long* profile_work_counter(int stage) {
   if (!g_prof_on || !g_count_work || !g_work_dev) return nullptr;
@@ -62,7 +69,7 @@ unsigned long long* profile_work_counter(int stage) {
 }
 
 StageScope::StageScope(int stage, hipStream_t s) : stage_(stage), s_(s), on_(false) {
-  if (!g_prof_on) return;
+  if (!g_prof_on || t_no_profile) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -283,6 +290,28 @@ int pvg_bin_sort(const pvg_geom* geom, const pvg_camera* cam, pvg_bins* bins, vo
     set_error("bin_sort scratch of %zu bytes is smaller than the %zu required", tmp_bytes, plan.total);
     return PVG_ERR_NOMEM;
   }
+  const View v = make_view(nullptr, cam, nullptr);
+  bins->num_instances = -1;
+  bins->num_visible = -1;
+  return run_bin_sort(single(v, geom->n), to_geom(geom), bins, tmp, plan, sync_count,
+                      static_cast<hipStream_t>(stream));
+}
+
+int pvg_bin_sort_noalloc(const pvg_geom* geom, const pvg_camera* cam, pvg_bins* bins, int32_t sync_count,
+                         void* stream) {
+  if (!geom || !check_geom(geom, geom->n) || !check_camera(cam) || !check_bins(bins)) return PVG_ERR_INVALID;
+  if (geom->n > 0xffffffffll) { set_error("n too large"); return PVG_ERR_INVALID; }
+  const BinPlan plan = plan_bins(geom->n, tiles_of(cam), bins->capacity);
+  if (plan.total > PVG_NOALLOC_SCRATCH_BYTES) {
+    set_error("bin_sort of %lld Gaussians on %lld tiles with capacity %lld needs %zu bytes of scratch; the "
+              "library-held scratch holds %zu (use pvg_bin_sort with a workspace)",
+              static_cast<long long>(geom->n), static_cast<long long>(tiles_of(cam)),
+              static_cast<long long>(bins->capacity), plan.total, static_cast<size_t>(PVG_NOALLOC_SCRATCH_BYTES));
+    return PVG_ERR_NOMEM;
+  }
+  void* tmp = nullptr;
+  PVG_HIP(noalloc_scratch(&tmp));
+  const NoProfile quiet;
   const View v = make_view(nullptr, cam, nullptr);
   bins->num_instances = -1;
   bins->num_visible = -1;

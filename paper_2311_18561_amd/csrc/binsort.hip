@@ -29,6 +29,8 @@
 // wave ballots (lanes with equal digits) and per-wave LDS counters, which keeps
 // the sort stable.  Counts live on the device; kernels sized for a capacity
 // exit early past the live count, so no host synchronisation is needed.
+#include <mutex>
+
 #include "pvg_math.hpp"
 
 namespace pvg {
@@ -841,6 +843,33 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
     }
   }
   return PVG_OK;
+}
+
+// ------------------------------------------------- library-held bin_sort scratch
+// The scratch of pvg_bin_sort_noalloc, for callers that cannot allocate device
+// memory.  Each device the library runs on holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in, never a
+// device address: host code uses only the address hipGetSymbolAddress returns,
+// looked up once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[PVG_NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace pvg

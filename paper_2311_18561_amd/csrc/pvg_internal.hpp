@@ -242,6 +242,16 @@ struct BinPlan {
 BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity);
 int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp, const BinPlan& plan,
                  int sync_count, hipStream_t s);
+// device address of the library-held bin_sort scratch (PVG_NOALLOC_SCRATCH_BYTES)
+// on the current device, looked up on the first call per device
+hipError_t noalloc_scratch(void** out);
+// with a NoProfile in scope the calling thread's launches record no stage
+// events (event creation may allocate)
+struct NoProfile {
+  NoProfile();
+  ~NoProfile();
+  bool prev_;
+};
 // batched forward of a device view table (no host synchronisation, capturable)
 int run_batch_forward(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp, const BinPlan& plan,
                       hipStream_t s);

@@ -167,3 +167,27 @@ def test_new_entry_points_reject_bad_arguments_on_host(lib):
     assert lib.pvg_render_bwd_views(C.byref(g), 1, C.byref(cam), C.byref(fr), C.byref(geom), C.byref(bins), one,
                                     one, one, C.byref(gg), 0, 1, 1 << 20, None) == L.PVG_ERR_INVALID
     assert "densify" in L.last_error()
+
+
+def test_noalloc_bin_sort_rejects_an_oversized_plan_on_host(lib):
+    """The library-held scratch has a fixed size: a bin sort whose plan needs
+    more is refused before any device call (the arrays are never touched)."""
+    from paper_2311_18561_amd import _lib as L
+    geom = L.Geom()
+    geom.n = 4_000_000
+    geom.xy = geom.depth = geom.conic_op = geom.rgb = geom.radius = geom.tiles = 16
+    cam = L.Camera()
+    cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.znear = 1920, 1280, 1500.0, 1500.0, 960.0, 640.0, 0.2
+    cam.R[:] = [1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0]
+    bins = L.Bins()
+    bins.capacity = 40_000_000
+    bins.keys = bins.vals = bins.ranges = bins.counters = 16
+    bins.tile_cull = 1
+    assert lib.pvg_bin_sort_noalloc(C.byref(geom), C.byref(cam), C.byref(bins), 1, None) == L.PVG_ERR_NOMEM
+    msg = L.last_error()
+    assert "library-held scratch" in msg and str(L.NOALLOC_SCRATCH_BYTES) in msg
+    ws = L.WsSizes()
+    assert lib.pvg_workspace_query(geom.n, 1920, 1280, bins.capacity, C.byref(ws)) == 0
+    assert ws.bin_tmp_bytes > L.NOALLOC_SCRATCH_BYTES
+    bins.capacity = -1
+    assert lib.pvg_bin_sort_noalloc(C.byref(geom), C.byref(cam), C.byref(bins), 1, None) == L.PVG_ERR_INVALID
