@@ -51,6 +51,8 @@ def _open(path):
     L.orc_render_f32.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, i64, i64, vp, vp, vp, vp, vp,
                                  vp, vp]
     L.orc_render_f32.restype = None
+    L.orc_render_margin_f32.argtypes = [i64, vp, vp, vp, vp, i32, i32, vp, vp, vp, i64, i64, vp, i32]
+    L.orc_render_margin_f32.restype = None
     L.orc_render_bruteforce_f32.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
     L.orc_render_bruteforce_f32.restype = None
     L.orc_render_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
@@ -203,6 +205,24 @@ def render_f32(pre, bins, cam, t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0), tiles=None
     if want_feat:
         out += (F,)
     return out
+
+
+def render_margin_f32(pre, bins, cam, t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0), tiles=None, gradients=False):
+    """Per-pixel decision margin of the FP32 walk over the tiles [lo, hi)
+    (elsewhere +inf): below 1 some skip or stop decision of the pixel sits
+    within the rounding a differently-rounded FP32 renderer may take the
+    other way (see composite_pixel_f32 in the C source); with gradients also
+    the adjoint's branch at the alpha clamp."""
+    n = pre["depth"].shape[0]
+    W, H = cam["width"], cam["height"]
+    GX, GY = grid(cam)
+    lo, hi = (0, GX * GY) if tiles is None else tiles
+    m = np.full((H, W), np.inf, np.float32)
+    fv = frame_array(t, dt, mode, bg)
+    ig = bins["inst_gauss"] if bins["M"] > 0 else np.zeros(1, np.uint32)
+    lib().orc_render_margin_f32(n, _p(pre["xy"]), _p(pre["conic_op"]), _p(pre["rgb"]), _p(pre["radius"]), W, H,
+                                _p(fv), _p(bins["ranges"]), _p(ig), lo, hi, _p(m), 1 if gradients else 0)
+    return m
 
 
 def render_bruteforce_f32(pre, cam, t, dt=0.0, mode=0, bg=(0.0, 0.0, 0.0)):

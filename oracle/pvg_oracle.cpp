@@ -409,22 +409,55 @@ void composite_pixel(int px, int py, const uint32_t* list, int64_t len, const Sp
 }
 
 // FP32 image path specialisation: values and decisions are one array.
+// Decision margin of a pixel's walk (margin != nullptr): the walk of Eq. (3)
+// takes three discrete decisions per pair (skip when the exponent is
+// positive, skip when alpha < 1/255, stop when T would fall below 1e-4).  A
+// renderer whose FP32 exponent or exponential rounds differently by a few
+// ulps may take the other branch where the exact value sits at a threshold.
+// *margin receives the smallest, over the walked pairs, of each decision's
+// distance to its threshold in units of the rounding it can absorb:
+// |power| / (1e-5 S) with S the sum of the exponent's term magnitudes;
+// |255 alpha - 1| / 1e-5 (alpha known to ~1e-6 relative); and
+// |ln(T_new / 1e-4)| / U with U = 1e-5 sum alpha_i / (1 - alpha_i) + 1e-6 over
+// the contributors so far (the relative uncertainty of T that the alphas'
+// carry through the products 1 - alpha).  Below 1 a decision is ambiguous.
+// With clamp_margin the adjoint's branch at the alpha clamp counts as well
+// (the clamped pair passes no gradient): |raw / 0.99 - 1| / 1e-5 over the
+// contributors, raw = o~ exp(power) before the clamp.
 void composite_pixel_f32(int px, int py, const uint32_t* list, int64_t len, const Splat<float>* sp,
-                         const float bg[3], float out[3], float& Tfin, float Fout[5], int& ncontrib) {
+                         const float bg[3], float out[3], float& Tfin, float Fout[5], int& ncontrib,
+                         float* margin = nullptr, bool clamp_margin = false) {
   float T = 1.0f;
   float C[3] = {0.0f, 0.0f, 0.0f};
   float F[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   ncontrib = 0;
   const float fpx = static_cast<float>(px), fpy = static_cast<float>(py);
+  double m = 1e30, u = 1e-6;
   for (int64_t k = 0; k < len; ++k) {
     const Splat<float>& d = sp[list[k]];
     const float dx = d.x - fpx, dy = d.y - fpy;
     const float power = -0.5f * (d.A * (dx * dx) + d.C * (dy * dy)) - d.B * (dx * dy);
+    if (margin) {
+      const double S = 0.5 * (std::fabs(static_cast<double>(d.A)) * dx * dx +
+                              std::fabs(static_cast<double>(d.C)) * dy * dy) +
+                       std::fabs(static_cast<double>(d.B) * dx * dy);
+      if (S > 0.0) m = std::min(m, std::fabs(static_cast<double>(power)) / (1e-5 * S));
+    }
     if (power > 0.0f) continue;
     const float alpha = std::min(0.99f, d.op * std::exp(power));
+    if (margin) m = std::min(m, std::fabs(255.0 * alpha - 1.0) / 1e-5);
     if (alpha < 1.0f / 255.0f) continue;
     const float Tn = T * (1.0f - alpha);
+    if (margin) {
+      u += 1e-5 * alpha / (1.0 - alpha);
+      if (Tn > 0.0f) m = std::min(m, std::fabs(std::log(static_cast<double>(Tn) / 1e-4)) / u);
+      else m = 0.0;
+    }
     if (Tn < 0.0001f) break;
+    if (margin && clamp_margin) {
+      const double raw = static_cast<double>(d.op * std::exp(power));
+      m = std::min(m, std::fabs(raw / 0.99 - 1.0) / 1e-5);
+    }
     for (int c = 0; c < 3; ++c) C[c] = C[c] + d.rgb[c] * (alpha * T);
     F[0] = F[0] + d.depth * (alpha * T);
     for (int f = 0; f < 4; ++f) F[1 + f] = F[1 + f] + d.feat[f] * (alpha * T);
@@ -434,6 +467,7 @@ void composite_pixel_f32(int px, int py, const uint32_t* list, int64_t len, cons
   for (int c = 0; c < 3; ++c) out[c] = C[c] + T * bg[c];
   Tfin = T;
   for (int f = 0; f < 5; ++f) Fout[f] = F[f];
+  if (margin) *margin = static_cast<float>(std::min(m, 1e30));
 }
 
 Camera make_cam(const float* c, int W, int H) {
@@ -582,6 +616,29 @@ void orc_render_f32(int64_t n, const float* xy, const float* conic_op, const flo
         if (depth_img) depth_img[o] = Fo[0];
         if (feat_img)
           for (int f = 0; f < 4; ++f) feat_img[f * HW + o] = Fo[1 + f];
+      }
+  }
+}
+
+// The decision margin (see composite_pixel_f32) of every pixel of the tiles
+// [tile_lo, tile_hi): margin[H][W], untouched outside those tiles.
+void orc_render_margin_f32(int64_t n, const float* xy, const float* conic_op, const float* rgb,
+                           const int32_t* radius, int W, int H, const float* framev, const uint32_t* ranges,
+                           const uint32_t* inst_gauss, int64_t tile_lo, int64_t tile_hi, float* margin,
+                           int clamp_margin) {
+  const Frame fr = make_frame(framev);
+  const std::vector<Splat<float>> sp = load_splats(n, xy, conic_op, rgb, radius, nullptr);
+  const int GX = (W + kTile - 1) / kTile;
+  for (int64_t t = tile_lo; t < tile_hi; ++t) {
+    const int tx = static_cast<int>(t % GX), ty = static_cast<int>(t / GX);
+    const uint32_t* list = inst_gauss + ranges[2 * t];
+    const int64_t len = static_cast<int64_t>(ranges[2 * t + 1]) - ranges[2 * t];
+    for (int py = ty * kTile; py < std::min(H, (ty + 1) * kTile); ++py)
+      for (int px = tx * kTile; px < std::min(W, (tx + 1) * kTile); ++px) {
+        float out[3], Tf, Fo[5];
+        int nc;
+        composite_pixel_f32(px, py, list, len, sp.data(), fr.bg, out, Tf, Fo, nc,
+                            &margin[static_cast<int64_t>(py) * W + px], clamp_margin != 0);
       }
   }
 }

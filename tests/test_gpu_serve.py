@@ -1,11 +1,17 @@
 """The render server on the GPU: each request's image is the same alone and in
 a mixed batch (scenes, resolutions, times), through graph replays, and when a
-batch overflows its instance capacity and is rerun request by request."""
+batch overflows its instance capacity and is rerun request by request; every
+served image also equals the oracle's render of its request (Sec. 3 problem
+statement: one image per scene, camera and time) within 1e-4 at every pixel
+whose skip and stop decisions are unambiguous (helpers.image_parity)."""
 import numpy as np
 import pytest
 
 import gen
-from helpers import to_device
+import oracle
+from helpers import image_parity, oracle_margin, to_device
+
+IMG_TOL = 1e-4
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -37,6 +43,24 @@ def _requests(rng, n_req):
     return reqs
 
 
+def _oracle_images(scenes, reqs):
+    oracle.build(force=False)
+    out = []
+    for sc, cam, t, bg in reqs:
+        r = oracle.render(scenes[sc], cam, t, 0.0, 0, bg)
+        out.append((r["img"], oracle_margin(r["pre"], r["bins"], cam, t, 0.0, 0, bg)))
+    return out
+
+
+def _check_oracle(outs, refs, label):
+    excused = 0
+    for i, (o, (ref, margin)) in enumerate(zip(outs, refs)):
+        worst, ex = image_parity(o.cpu().numpy(), ref, margin, IMG_TOL)
+        excused += ex
+    print(f"{label}: {len(outs)} images within {IMG_TOL} of the oracle; {excused} pixels excused at ambiguous "
+          f"decisions")
+
+
 def _direct(params, cam, t, bg):
     import paper_2311_18561_amd as pvg
     img, _, _, _, _ = pvg.render(params, cam, t, 0.0, 0, bg)
@@ -51,6 +75,7 @@ def test_batched_results_equal_individual_renders(use_graphs):
     rng = np.random.default_rng(7)
     reqs = _requests(rng, 24)
     expect = [_direct(params[sc], cam, t, bg) for sc, cam, t, bg in reqs]
+    refs = _oracle_images(scenes, reqs)
     torch.cuda.synchronize()
     with Server(max_batch=6, max_inflight=2, use_graphs=use_graphs, max_batch_gaussians=400_000,
                 max_batch_pixels=6 * 320 * 240, instance_capacity=1 << 24) as srv:
@@ -65,6 +90,7 @@ def test_batched_results_equal_individual_renders(use_graphs):
             assert max(sizes) > 1
             for i, (o, e) in enumerate(zip(outs, expect)):
                 assert torch.equal(o, e), (rep, i, float((o - e).abs().max()))
+            _check_oracle(outs, refs, f"mixed batches, replay {rep}")
             _ = _direct(params[0], reqs[0][1], 0.3, (0, 0, 0))  # unrelated eager work
             torch.cuda.synchronize()
         st = srv.stats()
@@ -72,6 +98,24 @@ def test_batched_results_equal_individual_renders(use_graphs):
         assert st["completed"] == 72
         if use_graphs:
             assert st["graph_launches"] == st["batches"] and st["graph_builds"] >= 1
+
+
+def test_served_alone_matches_the_oracle():
+    """One request per launch (no batching, no overlap), with and without
+    graph replay: each image against the oracle."""
+    from paper_2311_18561_amd.serve import Server
+    scenes = _scenes()
+    params = [to_device(s) for s in scenes]
+    reqs = _requests(np.random.default_rng(8), 9)
+    refs = _oracle_images(scenes, reqs)
+    for use_graphs in (False, True):
+        with Server(max_batch=1, max_inflight=1, use_graphs=use_graphs, max_batch_gaussians=100_000,
+                    max_batch_pixels=320 * 240, instance_capacity=1 << 22) as srv:
+            sids = [srv.load_scene(p) for p in params]
+            outs = [torch.full((3, cam["height"], cam["width"]), -1.0, device="cuda") for _, cam, _, _ in reqs]
+            res = [srv.wait(srv.submit(sids[sc], cam, t, out, bg)) for (sc, cam, t, bg), out in zip(reqs, outs)]
+            assert all(r.status == 0 and r.batch_size == 1 for r in res)
+            _check_oracle(outs, refs, f"alone, graphs={use_graphs}")
 
 
 def test_overflow_reruns_requests_alone():
@@ -99,6 +143,8 @@ def test_overflow_reruns_requests_alone():
         assert all(r.status == 0 for r in res)
         for o, e in zip(outs, expect):
             assert torch.equal(o, e)
+        _check_oracle(outs, _oracle_images(scenes[:1], [(0, cam, 0.5, (0.0, 0.0, 0.0)) for cam in cams]),
+                      "rerun after overflow")
         st = srv.stats()
         assert st["retries"] >= 2
     # a request that alone exceeds the capacity fails cleanly

@@ -7,12 +7,16 @@ Forward: one full tile row of two views against the FP32 oracle (image,
 transmittance, last contributor).  Backward: an image gradient confined to a
 few random tiles of those two views, so the FP64 oracle adjoint restricted
 to the same tiles gives the exact expected gradient of every parameter.
+Pixels whose skip or stop decisions are ambiguous (the oracle's decision
+margin below 1: either branch is a correct FP32 render) are held to no image
+bar and get no loss weight.
 """
 import numpy as np
 import pytest
 
 import gen
-from helpers import FIELDS, grad_tolerance_report, last_contributor_ids, to_device
+from helpers import (FIELDS, check_culled_lists, gpu_forward, grad_tolerance_report, image_parity,
+                     last_contributor_ids, oracle_margin, oracle_margin_tiles, to_device, unambiguous)
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -33,11 +37,15 @@ def test_training_workload_full_size_sampled(orc):
     views = [(cam, t, d) for cam in cams for d in (0.0, dt)]
     checked = {2: (cams[1], 0.0), 3: (cams[1], dt)}  # the middle camera, both times
     rng = np.random.default_rng(12)
-    masks, weights = {}, {}
-    for k in checked:
+    masks, weights, oracle_lists = {}, {}, {}
+    for k, (cam, d) in checked.items():
+        pre = orc.preprocess_f32(scene, cam, t, d)
+        bins = orc.bin_sort(pre, cam)
+        oracle_lists[k] = (pre, bins)
         m = np.zeros(GX * GY, np.uint8)
         m[rng.choice(np.arange(GX * (GY // 4), GX * (3 * GY // 4)), 6, replace=False)] = 1
         keep = np.repeat(np.repeat(m.reshape(GY, GX), 16, 0), 16, 1)[:H, :W]
+        keep = keep * unambiguous(oracle_margin_tiles(pre, bins, cam, t, d, np.nonzero(m)[0], gradients=True))
         masks[k] = m
         weights[k] = (rng.standard_normal((3, H, W)) * keep).astype(np.float32)
     params = [p.requires_grad_(True) for p in to_device(scene)]
@@ -50,14 +58,13 @@ def test_training_workload_full_size_sampled(orc):
     sc64 = orc.scene64(scene)
     row = GY // 2
     for k, (cam, d) in checked.items():
-        pre = orc.preprocess_f32(scene, cam, t, d)
-        bins = orc.bin_sort(pre, cam)
+        pre, bins = oracle_lists[k]
         img_o, T_o, nc_o = orc.render_f32(pre, bins, cam, t, d, tiles=(row * GX, (row + 1) * GX))
+        margin = oracle_margin(pre, bins, cam, t, d, tiles=(row * GX, (row + 1) * GX))
         ys = slice(row * 16, row * 16 + 16)
         g_img = imgs[k].detach().cpu().numpy()
-        err = np.abs(g_img[:, ys] - img_o[:, ys]).max()
-        print(f"[view {k}] tile row {row}: max |img - oracle| = {err:.3g}")
-        assert err <= 1e-4
+        err, excused = image_parity(g_img, img_o, margin, rows=ys)
+        print(f"[view {k}] tile row {row}: max |img - oracle| = {err:.3g} at unambiguous pixels, {excused} excused")
         # last contributor of each pixel of the row: the GPU's lists are culled, the oracle's are rectangles
         img_g, T_g, nc_g, geom_g, bins_g = pvg.render(params, cam, t, d)
         assert torch.equal(img_g, imgs[k].detach())
@@ -65,10 +72,10 @@ def test_training_workload_full_size_sampled(orc):
         ids_g = last_contributor_ids(nc_g.cpu().numpy(), bins_g.vals[:L_].cpu().numpy().view(np.uint32),
                                      bins_g.ranges.cpu().numpy().view(np.uint32), W)
         ids_o = last_contributor_ids(nc_o, bins["inst_gauss"], bins["ranges"], W)
-        flips = int((ids_g[ys] != ids_o[ys]).sum())
-        print(f"[view {k}] last-contributor differences in the row: {flips} of {16 * W}")
-        assert flips <= 2
-        assert np.abs(T_g.cpu().numpy()[ys] - T_o[ys]).max() <= 1e-4
+        flips = ids_g[ys] != ids_o[ys]
+        print(f"[view {k}] last-contributor differences in the row: {int(flips.sum())} of {16 * W}")
+        assert not np.any(flips & (margin[ys] >= 1.0))
+        image_parity(T_g.cpu().numpy(), T_o, margin, rows=ys)
         part, _ = orc.backward_f64(sc64, cam, t, d, 0, (0, 0, 0), pre, bins, weights[k].astype(np.float64),
                                    tile_mask=masks[k])
         for f in FIELDS:
@@ -94,6 +101,35 @@ def test_training_workload_full_size_sampled(orc):
         assert worst <= 1.0, f
 
 
+def test_training_view_sort_full_size(orc):
+    """The sorted lists of one whole 1920x1280 view of the 1M-Gaussian scene
+    (the middle camera's H(t), about 31M rectangle instances), bit for bit:
+    radii and tile counts, the rectangle lists (tile_cull=False: tile ids and
+    Gaussian indices in (tile, depth, index) order) and the tile ranges
+    against the oracle's sort; the culled lists as order-kept sublists whose
+    dropped entries no pixel of their tile can use."""
+    cfg = gen.make_config(2)
+    scene, cam, t = cfg["scene"], cfg["cameras"][1], cfg["t"]
+    pre = orc.preprocess_f32(scene, cam, t)
+    bins = orc.bin_sort(pre, cam)
+    gr = gpu_forward(scene, cam, t, tile_cull=False)
+    print(f"[sort full size] rectangle instances: GPU {gr['M']}, oracle {bins['M']}; visible {gr['num_visible']}",
+          flush=True)
+    assert bins["M"] > 20_000_000
+    assert np.array_equal(gr["radius"], pre["radius"])
+    assert np.array_equal(gr["tiles"], pre["tiles"].view(np.uint32))
+    assert gr["M"] == gr["L"] == bins["M"]
+    assert np.array_equal(gr["keys"], bins["inst_tile"])
+    assert np.array_equal(gr["vals"], bins["inst_gauss"])
+    assert np.array_equal(gr["ranges"], bins["ranges"])
+    del gr
+    g = gpu_forward(scene, cam, t, tile_cull=True)
+    dropped = check_culled_lists(g["keys"], g["vals"], g["ranges"], bins["inst_tile"], bins["inst_gauss"], pre, cam,
+                                 scene["n"], sample=200_000)
+    print(f"[sort full size] culled lists: {g['L']} listed, {dropped} rectangle entries dropped")
+    assert g["L"] + dropped == bins["M"]
+
+
 def test_large_scene_six_cameras_sampled(orc):
     """The 6M-Gaussian scene (40% far field) seen by six cameras, through the
     same multi-view call.  For two of the views, the oracle renders one tile
@@ -110,11 +146,26 @@ def test_large_scene_six_cameras_sampled(orc):
     checked = (0, 3)
     rng = np.random.default_rng(21)
     row = GY // 2
-    masks, weights = {}, {}
+    masks, weights, subsets = {}, {}, {}
     for k in checked:
+        cam = cams[k]
         m = np.zeros(GX * GY, np.uint8)
         m[rng.choice(np.arange(GX * (GY // 4), GX * (3 * GY // 4)), 6, replace=False)] = 1
+        pre = orc.preprocess_f32(scene, cam, t)
+        r = pre["rect"]
+        tile_ids = np.nonzero(m)[0]
+        reach = (pre["radius"] > 0) & (r[:, 1] <= row) & (row < r[:, 3])
+        for tid in tile_ids:
+            tx, ty = tid % GX, tid // GX
+            reach |= (pre["radius"] > 0) & (r[:, 0] <= tx) & (tx < r[:, 2]) & (r[:, 1] <= ty) & (ty < r[:, 3])
+        idx = np.nonzero(reach)[0]
+        sub = gen.subset_scene(scene, idx)
+        pre_s = orc.preprocess_f32(sub, cam, t)
+        assert np.array_equal(pre_s["radius"], pre["radius"][idx]) and np.array_equal(pre_s["xy"], pre["xy"][idx])
+        bins_s = orc.bin_sort(pre_s, cam)
+        subsets[k] = (idx, sub, pre_s, bins_s)
         keep = np.repeat(np.repeat(m.reshape(GY, GX), 16, 0), 16, 1)[:H, :W]
+        keep = keep * unambiguous(oracle_margin_tiles(pre_s, bins_s, cam, t, 0.0, tile_ids, gradients=True))
         masks[k] = m
         weights[k] = (rng.standard_normal((3, H, W)) * keep).astype(np.float32)
     params = [p.requires_grad_(True) for p in to_device(scene)]
@@ -125,24 +176,13 @@ def test_large_scene_six_cameras_sampled(orc):
     ref = {f: np.zeros_like(got[f]) for f in FIELDS}
     for k in checked:
         cam = cams[k]
-        pre = orc.preprocess_f32(scene, cam, t)
-        r = pre["rect"]
-        tile_ids = np.nonzero(masks[k])[0]
-        reach = (pre["radius"] > 0) & (r[:, 1] <= row) & (row < r[:, 3])
-        for tid in tile_ids:
-            tx, ty = tid % GX, tid // GX
-            reach |= (pre["radius"] > 0) & (r[:, 0] <= tx) & (tx < r[:, 2]) & (r[:, 1] <= ty) & (ty < r[:, 3])
-        idx = np.nonzero(reach)[0]
-        sub = gen.subset_scene(scene, idx)
-        pre_s = orc.preprocess_f32(sub, cam, t)
-        assert np.array_equal(pre_s["radius"], pre["radius"][idx]) and np.array_equal(pre_s["xy"], pre["xy"][idx])
-        bins_s = orc.bin_sort(pre_s, cam)
+        idx, sub, pre_s, bins_s = subsets[k]
         img_o, T_o, nc_o = orc.render_f32(pre_s, bins_s, cam, t, tiles=(row * GX, (row + 1) * GX))
+        margin = oracle_margin(pre_s, bins_s, cam, t, tiles=(row * GX, (row + 1) * GX))
         ys = slice(row * 16, row * 16 + 16)
-        err = np.abs(imgs[k].detach().cpu().numpy()[:, ys] - img_o[:, ys]).max()
+        err, excused = image_parity(imgs[k].detach().cpu().numpy(), img_o, margin, rows=ys)
         print(f"[6M view {k}] {idx.size} Gaussians reach the sampled tiles; tile row {row}: "
-              f"max |img - oracle| = {err:.3g}")
-        assert err <= 1e-4
+              f"max |img - oracle| = {err:.3g} at unambiguous pixels, {excused} excused")
         part, _ = orc.backward_f64(orc.scene64(sub), cam, t, 0.0, 0, (0, 0, 0), pre_s, bins_s,
                                    weights[k].astype(np.float64), tile_mask=masks[k])
         for f in FIELDS:
@@ -164,7 +204,8 @@ def test_channels_full_size_sampled(orc):
     the 1M-Gaussian workload through pvg_render_views(channels=True,
     normalized_depth=True).  For the middle camera's flow-translated view:
     one tile row of the normalized depth, velocity and staticness maps
-    against the oracle, and a loss on normalized depth, opacity, velocity
+    against the oracle (pixels with unambiguous decisions), and a loss on
+    normalized depth, opacity, velocity
     and staticness confined to six tiles against the FP64 adjoint on those
     tiles (the tolerance summed over the loss's sources: the quotient's two
     terms and the rest)."""
@@ -178,7 +219,10 @@ def test_channels_full_size_sampled(orc):
     rng = np.random.default_rng(31)
     m = np.zeros(GX * GY, np.uint8)
     m[rng.choice(np.arange(GX * (GY // 4), GX * (3 * GY // 4)), 6, replace=False)] = 1
+    pre = orc.preprocess_f32(scene, cam, t, d)
+    bins = orc.bin_sort(pre, cam)
     keep = np.repeat(np.repeat(m.reshape(GY, GX), 16, 0), 16, 1)[:H, :W].astype(np.float64)
+    keep = keep * unambiguous(oracle_margin_tiles(pre, bins, cam, t, d, np.nonzero(m)[0], gradients=True))
     wD = (0.05 * rng.standard_normal((H, W)) * keep).astype(np.float32)
     wO = (rng.standard_normal((H, W)) * keep).astype(np.float32)
     wF = (rng.standard_normal((4, H, W)) * keep).astype(np.float32)
@@ -190,8 +234,6 @@ def test_channels_full_size_sampled(orc):
     loss.backward()
     got = {f: p.grad.detach().cpu().numpy().astype(np.float64) for f, p in zip(FIELDS, params)}
     sc64 = orc.scene64(scene)
-    pre = orc.preprocess_f32(scene, cam, t, d)
-    bins = orc.bin_sort(pre, cam)
     args = (sc64, cam, t, d, 0, (0.0, 0.0, 0.0), pre, bins)
     # forward: one tile row
     row = GY // 2
@@ -199,12 +241,13 @@ def test_channels_full_size_sampled(orc):
     rmask[row * GX:(row + 1) * GX] = 1
     _, _, T64, D64 = orc.render_f64(*args, tile_mask=rmask, want_depth=True)
     ys = slice(row * 16, row * 16 + 16)
+    clear = oracle_margin(pre, bins, cam, t, d, tiles=(row * GX, (row + 1) * GX))[ys] >= 1.0
     want = orc.normalized_depth_f64(D64, T64)[ys]
-    hit = want > 0
+    hit = (want > 0) & clear
     rel = np.abs(dn[k].detach().cpu().numpy()[ys] - want)[hit] / want[hit]
     _, _, _, F = orc.render_f32(pre, bins, cam, t, d, want_feat=True, tiles=(row * GX, (row + 1) * GX))
     got_f = np.concatenate([vbar[k].detach().cpu().numpy(), rho[k].detach().cpu().numpy()[None]])[:, ys]
-    ferr = float(np.abs(got_f - F[:, ys]).max()) / max(1.0, float(np.abs(F[:, ys]).max()))
+    ferr = float(np.abs(got_f - F[:, ys])[:, clear].max()) / max(1.0, float(np.abs(F[:, ys]).max()))
     print(f"[channels full size] row {row}: normalized depth max rel err {rel.max():.3g}, "
           f"velocity / staticness {ferr:.3g}")
     assert rel.max() <= 5e-5 and ferr <= 1e-5
@@ -226,5 +269,7 @@ def test_channels_full_size_sampled(orc):
         g2 = got[f].reshape(-1, n)
         assert np.abs(g2[:, ~touched]).max() <= 1e-6 * max(np.abs(ref).max(), 1e-30), f
         worst, l2 = grad_tolerance_report(g2[:, touched], ref[:, touched], rel=1e-3, magnitude=mag[:, touched])
-        print(f"[channels full size] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+        plain, _ = grad_tolerance_report(g2[:, touched], ref[:, touched], rel=1e-3)
+        print(f"[channels full size] {f}: worst/tol = {worst:.3g} (per-element bar on |g*| alone: {plain:.3g}), "
+              f"l2 rel = {l2:.3g}")
         assert worst <= 1.0, f
