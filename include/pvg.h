@@ -229,9 +229,12 @@ int pvg_render_fwd(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera*
  *              Gaussian reaches); for the adjoint with depth_normalized and
  *              dL_ddepth, the forward's normalized depth (read only);
  *   dL_ddepth  adjoint input: upstream gradient of `depth`;
- *   dL_dT      adjoint input: upstream gradient of final_T (the rendered
- *              opacity O = sum T_i alpha_i is 1 - final_T, so dL/dO enters as
- *              dL_dT = -dL/dO);
+ *   dL_dT      adjoint input: upstream gradient of final_T;
+ *   opacity    forward output: the rendered opacity O = sum T_i alpha_i =
+ *              1 - final_T (the opacity of the sky composite and the opacity
+ *              loss of Sec. 3.4);
+ *   dL_dopacity adjoint input: upstream gradient of `opacity` (it adds to
+ *              dL_dT with the opposite sign);
  *   vbar, rho  the velocity map and the staticness map (Sec. 3.4 and the
  *              dynamic element analysis), blending each Gaussian's v~ and
  *              rho from geom->feat, which must then be non-NULL (the preprocess
@@ -256,6 +259,8 @@ typedef struct pvg_channels {
   const float* dL_drho;    /* adjoint input [height][width] */
   int32_t depth_normalized;
   float* feature_grad;
+  float* opacity;            /* forward output [height][width]: 1 - final_T */
+  const float* dL_dopacity;  /* adjoint input [height][width] */
 } pvg_channels;
 
 /* pvg_render_fwd that also writes the channels requested in `channels`
@@ -375,6 +380,16 @@ typedef struct pvg_adam_config {
 } pvg_adam_config;
 int pvg_adam_step(const pvg_gaussians* params, const pvg_gaussians_grad* grad, float* m, float* v,
                   const pvg_adam_config* cfg, void* stream);
+
+/* Adam (Sec. 4) on a dense learnable array of `count` floats: the sky cube
+ * map of Sec. 3.4 ([6][3][R][R], its texels taken as they are).  p (updated in
+ * place), grad, and the moments m, v (zero before the first step) are device
+ * arrays of `count` floats; the update is pvg_adam_step's on the identity
+ * space with the single rate lr (a zero rate still updates the moments, a
+ * zero step leaves p bit for bit).  step t >= 1 sets the bias corrections.
+ * PVG_ERR_INVALID on null arrays, count < 0 or a bad rate or beta. */
+int pvg_adam_dense(float* p, const float* grad, float* m, float* v, int64_t count, float lr, float beta1,
+                   float beta2, float eps, int32_t step, void* stream);
 
 /* Opacity reset (Sec. 4): o = min(o, cap) and the opacity row of the Adam
  * moments cleared. */

@@ -52,3 +52,14 @@ def adam_step(sc, grads, m, v, lrs, t, beta1=0.9, beta2=0.999, eps=1e-15):
         new = np.exp(raw) if kind == "log" else (1.0 / (1.0 + np.exp(-raw)) if kind == "logit" else raw)
         out[f].reshape(-1, n)[j] = new if lr != 0 else p
     return out, m, v
+
+
+def adam_dense(p, g, m, v, lr, t, beta1=0.9, beta2=0.999, eps=1e-15):
+    """One Adam step on a dense array taken as it is (the learnable sky cube
+    map of Sec. 3.4); returns (new p, m, v), FP64."""
+    p, g = np.asarray(p, np.float64), np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1 - beta2) * g * g
+    bc1, bc2 = 1.0 - beta1 ** t, 1.0 - beta2 ** t
+    new = p - lr * (m / bc1) / (np.sqrt(v / bc2) + eps) if lr != 0 else p.copy()
+    return new, m, v

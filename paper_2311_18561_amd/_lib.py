@@ -62,7 +62,8 @@ class Frame(C.Structure):
 class Channels(C.Structure):
     _fields_ = [("depth", C.c_void_p), ("dL_ddepth", C.c_void_p), ("dL_dT", C.c_void_p), ("vbar", C.c_void_p),
                 ("rho", C.c_void_p), ("dL_dvbar", C.c_void_p), ("dL_drho", C.c_void_p),
-                ("depth_normalized", C.c_int32), ("feature_grad", C.c_void_p)]
+                ("depth_normalized", C.c_int32), ("feature_grad", C.c_void_p), ("opacity", C.c_void_p),
+                ("dL_dopacity", C.c_void_p)]
 
 
 class Geom(C.Structure):
@@ -143,6 +144,7 @@ def load():
         "pvg_densify_tmp_bytes": ([i64, P(C.c_size_t)], i32),
         "pvg_adam_step": ([P(Gaussians), P(GaussiansGrad), vp, vp, P(AdamConfig), vp], i32),
         "pvg_opacity_reset": ([P(Gaussians), vp, vp, C.c_float, vp], i32),
+        "pvg_adam_dense": ([vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp], i32),
         "pvg_ssim_fwd": ([vp, vp, i32, i32, i32, vp, vp, vp], i32),
         "pvg_staticness_split_plan": ([P(Gaussians), C.c_float, vp, C.c_size_t, P(i64), vp], i32),
         "pvg_staticness_split_apply": ([P(Gaussians), C.c_float, vp, C.c_size_t, P(Gaussians), P(Gaussians), vp],

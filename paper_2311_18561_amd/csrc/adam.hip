@@ -65,7 +65,44 @@ __global__ void __launch_bounds__(256) k_opacity_reset(float* __restrict__ o, fl
   v[i] = 0.0f;
 }
 
+// Plain Adam on a dense array (the learnable sky cube map of Sec. 3.4, whose
+// texels are taken as they are): four texels per thread, the same update as
+// adam_row's identity case.
+__global__ void __launch_bounds__(256) k_adam_dense(float* __restrict__ p, const float* __restrict__ g,
+                                                    float* __restrict__ m, float* __restrict__ v, int64_t count,
+                                                    float lr, AdamCfg c) {
+  const int64_t i0 = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) * 4;
+  if (i0 >= count) return;
+  if (i0 + 4 <= count && (reinterpret_cast<uintptr_t>(p + i0) & 15) == 0 &&
+      (reinterpret_cast<uintptr_t>(g + i0) & 15) == 0 && (reinterpret_cast<uintptr_t>(m + i0) & 15) == 0 &&
+      (reinterpret_cast<uintptr_t>(v + i0) & 15) == 0) {
+    float4 pp = *reinterpret_cast<const float4*>(p + i0);
+    const float4 gg = *reinterpret_cast<const float4*>(g + i0);
+    float4 mm = *reinterpret_cast<const float4*>(m + i0);
+    float4 vv = *reinterpret_cast<const float4*>(v + i0);
+    float* pe = &pp.x;
+    const float* ge = &gg.x;
+    float* me = &mm.x;
+    float* ve = &vv.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) adam_row(pe + k, ge + k, me + k, ve + k, kIdent, lr, c);
+    *reinterpret_cast<float4*>(p + i0) = pp;
+    *reinterpret_cast<float4*>(m + i0) = mm;
+    *reinterpret_cast<float4*>(v + i0) = vv;
+    return;
+  }
+  for (int64_t i = i0; i < min(i0 + 4, count); ++i) adam_row(p + i, g + i, m + i, v + i, kIdent, lr, c);
+}
+
 }  // namespace
+
+hipError_t launch_adam_dense(float* p, const float* g, float* m, float* v, int64_t count, float lr, const AdamCfg& c,
+                             hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const int64_t blocks = (count + 1023) / 1024;
+  hipLaunchKernelGGL(k_adam_dense, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, p, g, m, v, count, lr, c);
+  return hipGetLastError();
+}
 
 hipError_t launch_adam(const SceneOut& s, const pvg_gaussians_grad& g, float* m, float* v, const AdamCfg& c,
                        hipStream_t st) {

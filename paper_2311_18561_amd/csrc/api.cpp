@@ -339,6 +339,7 @@ int pvg_render_fwd_channels(const pvg_geom* geom, const pvg_bins* bins, const pv
     v.depth_norm = channels->depth_normalized != 0;
     v.vbar_img = channels->vbar;
     v.rho_img = channels->rho;
+    v.opacity_img = channels->opacity;
     if ((v.vbar_img || v.rho_img) && geom->n > 0 && !geom->feat) {
       set_error("the velocity and staticness channels need geom.feat");
       return PVG_ERR_INVALID;
@@ -518,6 +519,7 @@ int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const
     if (channels) {
       v.dL_ddepth = channels[k].dL_ddepth;
       v.dL_dT = channels[k].dL_dT;
+      v.dL_dO = channels[k].dL_dopacity;
       v.dL_dvbar = channels[k].dL_dvbar;
       v.dL_drho = channels[k].dL_drho;
       if (channels[k].depth_normalized && v.dL_ddepth) {
@@ -674,6 +676,24 @@ int pvg_adam_step(const pvg_gaussians* params, const pvg_gaussians_grad* grad, f
                          const_cast<float*>(params->beta), params->n, params->sh_degree};
   PVG_HIP(pvg::launch_adam(so, params->n > 0 ? *grad : pvg_gaussians_grad{}, m, v, c,
                            static_cast<hipStream_t>(stream)));
+  return PVG_OK;
+}
+
+int pvg_adam_dense(float* p, const float* grad, float* m, float* v, int64_t count, float lr, float beta1,
+                   float beta2, float eps, int32_t step, void* stream) {
+  if (count < 0 || count > (int64_t{1} << 40)) { set_error("count outside 0..2^40"); return PVG_ERR_INVALID; }
+  if (step < 1 || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) ||
+      !(lr >= 0.0f) || !std::isfinite(lr)) {
+    set_error("step >= 1, beta1 and beta2 in [0, 1), eps > 0 and a finite lr >= 0 are required");
+    return PVG_ERR_INVALID;
+  }
+  if (count > 0 && (!p || !grad || !m || !v)) { set_error("an array is null"); return PVG_ERR_INVALID; }
+  pvg::AdamCfg c;
+  for (int k = 0; k < 10; ++k) c.lr[k] = lr;
+  c.beta1 = beta1; c.beta2 = beta2; c.eps = eps;
+  c.bc1 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta1), step));
+  c.bc2 = static_cast<float>(1.0 - std::pow(static_cast<double>(beta2), step));
+  PVG_HIP(pvg::launch_adam_dense(p, grad, m, v, count, lr, c, static_cast<hipStream_t>(stream)));
   return PVG_OK;
 }
 

@@ -58,6 +58,10 @@ struct View {
   // depth_img holds sum T alpha z / sum T alpha (forward output; the adjoint
   // reads it back to take the quotient's gradient)
   int32_t depth_norm;
+  // the rendered opacity O = sum T alpha = 1 - final_T (forward output) and
+  // its upstream gradient (adjoint input), each optional
+  float* opacity_img;        // [H][W]
+  const float* dL_dO;        // [H][W]
 };
 
 struct Geom {
@@ -207,6 +211,8 @@ struct AdamCfg {
   float lr[10];
   float beta1, beta2, eps, bc1, bc2;
 };
+hipError_t launch_adam_dense(float* p, const float* g, float* m, float* v, int64_t count, float lr, const AdamCfg& c,
+                             hipStream_t st);
 hipError_t launch_adam(const SceneOut& s, const pvg_gaussians_grad& g, float* m, float* v, const AdamCfg& c,
                        hipStream_t st);
 hipError_t launch_opacity_reset(float* o, float* m_row, float* v_row, int64_t n, float cap, hipStream_t st);

@@ -243,6 +243,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
       v.img[2 * HW + o] = Cb[k] + T[k] * v.bg[2];
       v.final_T[o] = T[k];
       v.n_contrib[o] = last[k];
+      if (v.opacity_img) v.opacity_img[o] = 1.0f - T[k];
       if (kCh) {
         // every contributor has alpha >= 1/255, so the sum is 0 exactly when none did
         if (v.depth_img) v.depth_img[o] = !v.depth_norm ? Dz[k] : (Aw[k] > 0.0f ? Dz[k] / Aw[k] : 0.0f);
@@ -317,6 +318,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       gb[k] = v.dL_dimg[2 * HW + o];
       if (kCh) {
         if (v.dL_dT) gt = v.dL_dT[o];
+        if (v.dL_dO) gt -= v.dL_dO[o];  // O = 1 - final_T
         if (v.dL_ddepth) {
           gd[k] = v.dL_ddepth[o];
           if (v.depth_norm) {
@@ -693,7 +695,8 @@ hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const Lists& l
   if (vs.total_tiles == 0) return hipSuccess;
   const bool culled = lists.culled;
   // channel gradients are single-view only
-  const bool ch = !vs.table && (vs.one.dL_ddepth || vs.one.dL_dT || vs.one.dL_dvbar || vs.one.dL_drho);
+  const bool ch =
+      !vs.table && (vs.one.dL_ddepth || vs.one.dL_dT || vs.one.dL_dO || vs.one.dL_dvbar || vs.one.dL_drho);
   {
     StageScope scope(PVG_STAGE_RENDER_BWD, s);
     // clear the flags (a fill kernel: no memset node in a captured graph)

@@ -23,6 +23,42 @@ def default_lrs(scene_radius: float) -> dict:
             "opacity": 0.005, "vel": 1e-3, "period": 0.0, "tau": 1e-3, "beta": 0.02}
 
 
+# the sky cube map's rate: the paper gives none; a texel is a colour, like a
+# degree-0 SH coefficient, and takes that coefficient's rate
+SKY_LR = 2.5e-3
+
+
+class DenseAdam:
+    """Adam on one dense learnable float32 tensor (the sky cube map
+    [6,3,R,R] of Sec. 3.4), updated in place by ``pvg_adam_dense``; the
+    moments live here."""
+
+    def __init__(self, param, lr: float = SKY_LR, betas=(0.9, 0.999), eps=1e-15):
+        self._check(param)
+        self.m = torch.zeros_like(param)
+        self.v = torch.zeros_like(param)
+        self.lr, self.betas, self.eps, self.t = float(lr), betas, eps, 0
+
+    @staticmethod
+    def _check(param):
+        if not isinstance(param, torch.Tensor) or param.dtype != torch.float32 or not param.is_cuda \
+                or not param.is_contiguous():
+            raise ValueError("a contiguous float32 tensor on a GPU is required")
+
+    def step(self, param, grad=None):
+        self._check(param)
+        grad = param.grad if grad is None else grad
+        if grad is None:
+            raise ValueError("the tensor has no gradient")
+        check_tensor(grad, param.shape, param.device, "the gradient")
+        if self.m.shape != param.shape or self.m.device != param.device:
+            raise ValueError("the moments were made for another tensor")
+        self.t += 1
+        L.check(L.load().pvg_adam_dense(_p(param), _p(grad), _p(self.m), _p(self.v), param.numel(), self.lr,
+                                        float(self.betas[0]), float(self.betas[1]), float(self.eps), self.t,
+                                        _stream_handle()))
+
+
 class PVGAdam:
     """Adam state for one set of Gaussians: moments [2, 17 + 3K, N] (m then
     v, rows in the parameter order), the step count and the rates.  step()

@@ -237,25 +237,27 @@ def bin_sort_nosync(geom: Geom, cam: L.Camera, capacity: int, tile_cull: bool = 
 
 
 def render_fwd(geom: Geom, bins: Bins, cam: L.Camera, frame: L.Frame, out=None, depth=None, vbar=None,
-               rho=None, depth_norm=False):
+               rho=None, depth_norm=False, opacity=None):
     """Composite one view; `out` (optional, contiguous [3,H,W] float32)
     receives the image, `depth` (optional, contiguous [H,W] float32) the
     blended camera depth sum T alpha z (with depth_norm the normalized depth
     sum T alpha z / sum T alpha), `vbar` ([3,H,W]) and `rho` ([H,W]) the
-    velocity and staticness maps (these need a Geom with feat)."""
+    velocity and staticness maps (these need a Geom with feat), `opacity`
+    ([H,W]) the rendered opacity sum T alpha = 1 - final_T."""
     dev = geom.xy.device
     H, W = int(cam.height), int(cam.width)
     img = torch.empty((3, H, W), dtype=torch.float32, device=dev) if out is None else out
     final_T = torch.empty((H, W), dtype=torch.float32, device=dev)
     n_contrib = torch.empty((H, W), dtype=torch.int32, device=dev)
     gs, bs = geom.struct(), bins.struct()
-    if depth is None and vbar is None and rho is None:
+    if depth is None and vbar is None and rho is None and opacity is None:
         L.check(L.load().pvg_render_fwd(C.byref(gs), C.byref(bs), C.byref(cam), C.byref(frame), _p(img),
                                         _p(final_T), _p(n_contrib), _stream_handle()))
     else:
-        for t, shp in ((depth, (H, W)), (vbar, (3, H, W)), (rho, (H, W))):
+        for t, shp in ((depth, (H, W)), (vbar, (3, H, W)), (rho, (H, W)), (opacity, (H, W))):
             assert t is None or (t.is_contiguous() and t.shape == shp and t.dtype == torch.float32)
         ch = L.Channels(_p(depth), None, None, _p(vbar), _p(rho), None, None, 1 if depth_norm else 0)
+        ch.opacity = _p(opacity)
         L.check(L.load().pvg_render_fwd_channels(C.byref(gs), C.byref(bs), C.byref(cam), C.byref(frame), _p(img),
                                                  _p(final_T), _p(n_contrib), C.byref(ch), _stream_handle()))
     return img, final_T, n_contrib
@@ -314,11 +316,11 @@ class _BwdViewsArgs:
                                                  max(v[3].capacity for v in views), C.byref(size)))
         self.tmp_bytes = int(size.value)
 
-    def call(self, dev, dimgs, grads, accumulate, ddepths=None, dTs=None, dvbars=None, drhos=None, depths=None,
+    def call(self, dev, dimgs, grads, accumulate, ddepths=None, dOs=None, dvbars=None, drhos=None, depths=None,
              stats=None):
-        """ddepths / dTs / dvbars / drhos (optional, per view or None):
-        upstream gradients of the depth channel, final_T, the velocity map
-        [3,H,W] and the staticness map.  depths (per view or None): the
+        """ddepths / dOs / dvbars / drhos (optional, per view or None):
+        upstream gradients of the depth channel, the rendered opacity
+        1 - final_T, the velocity map [3,H,W] and the staticness map.  depths (per view or None): the
         forward's normalized depth, given when ddepths is that map's gradient.
         stats: optional (accum, count) [N] tensors that receive the view-space
         gradient statistics of the adaptive control."""
@@ -327,8 +329,7 @@ class _BwdViewsArgs:
             setattr(gg, name, t.data_ptr())
         if stats is not None:
             gg.densify_grad, gg.densify_count = stats[0].data_ptr(), stats[1].data_ptr()
-        lists = [list(x) if x is not None else [None] * self.nv for x in (ddepths, dTs, dvbars, drhos)]
-        ddepths, dTs, dvbars, drhos = lists
+        lists = [list(x) if x is not None else [None] * self.nv for x in (ddepths, dOs, dvbars, drhos)]
         has = [any(x[k] is not None for x in lists) for k in range(self.nv)]
         chan = any(has)
         dimgs = list(dimgs)
@@ -348,8 +349,10 @@ class _BwdViewsArgs:
             return grads
         cont = [[None if d is None else d.contiguous() for d in x] for x in lists]
         dn = [None] * self.nv if depths is None else [None if d is None else d.contiguous() for d in depths]
-        ch = (L.Channels * self.nv)(*[L.Channels(_p(z), _p(a), _p(b), None, None, _p(c), _p(d), 0 if z is None else 1)
-                                      for z, a, b, c, d in zip(dn, *cont)])
+        ch = (L.Channels * self.nv)()
+        for k, (z, a, b, c, d) in enumerate(zip(dn, *cont)):
+            ch[k] = L.Channels(_p(z), _p(a), None, None, None, _p(c), _p(d), 0 if z is None else 1)
+            ch[k].dL_dopacity = _p(b)
         L.check(L.load().pvg_render_bwd_views_channels(C.byref(self.g), self.nv, self.cams, self.frames, self.geoms,
                                                        self.bins, self.f_t, self.n_c, d_l, ch, C.byref(gg),
                                                        1 if accumulate else 0, _p(tmp), int(tmp.numel()),
@@ -357,19 +360,20 @@ class _BwdViewsArgs:
         return grads
 
 
-def render_bwd_views(params, n, degree, views, grads=None, accumulate=False, ddepths=None, dTs=None, dvbars=None,
+def render_bwd_views(params, n, degree, views, grads=None, accumulate=False, ddepths=None, dOs=None, dvbars=None,
                      drhos=None, depths=None, stats=None):
     """One adjoint call for several views of the same Gaussians:
     views = [(cam, frame, geom, bins, final_T, n_contrib, dL_dimg or None)];
     the per-Gaussian chain rule of all views is summed in registers and the
-    gradient written (or added) once.  ddepths / dTs / dvbars / drhos:
-    optional per-view upstream gradients of the channels and of final_T;
+    gradient written (or added) once.  ddepths / dOs / dvbars / drhos:
+    optional per-view upstream gradients of the channels (dOs: of the
+    rendered opacity 1 - final_T);
     depths: per view, the forward's normalized depth when ddepths is its
     gradient (None: ddepths is the gradient of sum T alpha z)."""
     if grads is None:
         grads = [torch.empty_like(p) for p in params]
     args = _BwdViewsArgs(params, n, degree, [v[:6] for v in views])
-    return args.call(params[0].device, [v[6] for v in views], grads, accumulate, ddepths, dTs, dvbars, drhos, depths,
+    return args.call(params[0].device, [v[6] for v in views], grads, accumulate, ddepths, dOs, dvbars, drhos, depths,
                      stats)
 
 
@@ -412,6 +416,8 @@ class PVGRender(torch.autograd.Function):
 
 
 KEEP_FRACTION = 0.1  # recompute="auto" keeps the views' lists while they fit this share of device memory
+# the list policy the last multi-view forward took (True: rebuilt in the backward), for reports
+last_recompute = None
 VIEW_STREAMS = 3     # views of one call run concurrently on this many lanes: the caller's stream and side streams (default priority)
 _side_streams: dict = {}
 
@@ -456,7 +462,7 @@ def _record(stream):
 
 
 def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=None, vbars=None, rhos=None,
-                   depth_norm=False):
+                   depth_norm=False, opacs=None):
     """Bin and composite view k on lane k mod VIEW_STREAMS, where lane 0 is
     the caller's stream and the others are side streams forked from it and
     joined back into it (the views' latency-bound sort and scan kernels
@@ -473,7 +479,8 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
     allocated on the caller's stream) view k's image is written into
     stacked[k]; with `depths` ([V,H,W], the same) its depth channel into
     depths[k] (the normalized depth with depth_norm), and likewise the
-    velocity and staticness maps into vbars ([V,3,H,W]) and rhos ([V,H,W])."""
+    velocity and staticness maps into vbars ([V,3,H,W]) and rhos ([V,H,W]),
+    and the rendered opacity 1 - final_T into opacs ([V,H,W])."""
     dev = params[0].device
     main = torch.cuda.current_stream(dev)
     side = _streams(dev)
@@ -509,7 +516,7 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
             fe.record(st)
             out = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k],
                              None if depths is None else depths[k], None if vbars is None else vbars[k],
-                             None if rhos is None else rhos[k], depth_norm)
+                             None if rhos is None else rhos[k], depth_norm, None if opacs is None else opacs[k])
             ev = None
             if st is not main:
                 ev = torch.cuda.Event()
@@ -534,7 +541,7 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
             plans[k][3] = bins
             outs[k] = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k],
                                  None if depths is None else depths[k], None if vbars is None else vbars[k],
-                                 None if rhos is None else rhos[k], depth_norm)
+                                 None if rhos is None else rhos[k], depth_norm, None if opacs is None else opacs[k])
     return plans, outs
 
 
@@ -575,7 +582,7 @@ class PVGRenderViews(torch.autograd.Function):
     def forward(ctx, views, recompute, tile_cull, stack, channels, stats, *tensors):
         params, n, degree = _check_params(list(tensors))
         dev = params[0].device
-        stacked = depths = vbars = rhos = None
+        stacked = depths = vbars = rhos = opacs = None
         if stack:
             V, H, W = len(views), int(views[0][0]["height"]), int(views[0][0]["width"])
             stacked = torch.empty((V, 3, H, W), dtype=torch.float32, device=dev)
@@ -583,11 +590,14 @@ class PVGRenderViews(torch.autograd.Function):
                 depths = torch.empty((V, H, W), dtype=torch.float32, device=dev)
                 vbars = torch.empty((V, 3, H, W), dtype=torch.float32, device=dev)
                 rhos = torch.empty((V, H, W), dtype=torch.float32, device=dev)
+                opacs = torch.empty((V, H, W), dtype=torch.float32, device=dev)
         norm = channels == 2
-        plans, outs = _forward_views(params, n, degree, views, tile_cull, stacked, depths, vbars, rhos, norm)
+        plans, outs = _forward_views(params, n, degree, views, tile_cull, stacked, depths, vbars, rhos, norm, opacs)
         if recompute == "auto":
             kept_bytes = sum(_bins_bytes(b) for _, _, _, b in plans)
             recompute = kept_bytes > KEEP_FRACTION * torch.cuda.get_device_properties(dev).total_memory
+        global last_recompute
+        last_recompute = bool(recompute)
         ctx.meta = (n, degree, bool(recompute), tile_cull, [(c, f, b.capacity) for c, f, _, b in plans])
         ctx.kept = None if recompute else [(g, b) for _, _, g, b in plans]
         ctx.bwd = None if recompute else _BwdViewsArgs(
@@ -601,8 +611,8 @@ class PVGRenderViews(torch.autograd.Function):
         ctx.stack = stack
         ctx.channels = channels
         ctx.stats = stats
-        if channels:  # images, depth, final_T, velocity and staticness maps, each stacked over the views
-            return stacked, depths, torch.stack([T for _, T, _ in outs]), vbars, rhos
+        if channels:  # images, depth, opacity, velocity and staticness maps, each stacked over the views
+            return stacked, depths, opacs, vbars, rhos
         if stack:
             return stacked
         return tuple(img for img, _, _ in outs)
@@ -610,9 +620,9 @@ class PVGRenderViews(torch.autograd.Function):
     @staticmethod
     def backward(ctx, *dimgs):
         n, degree, recompute, tile_cull, plan = ctx.meta
-        ddepths = dTs = dvbars = drhos = None
+        ddepths = dOs = dvbars = drhos = None
         if ctx.channels:
-            ddepths, dTs, dvbars, drhos = ([None if d is None else d[k] for k in range(len(plan))]
+            ddepths, dOs, dvbars, drhos = ([None if d is None else d[k] for k in range(len(plan))]
                                            for d in dimgs[1:5])
         if ctx.stack:
             d = dimgs[0]
@@ -626,21 +636,21 @@ class PVGRenderViews(torch.autograd.Function):
             # same inputs give the forward's lists bit for bit, within its capacity
             first = True
             for k, (c, f, cap) in enumerate(plan):
-                chk = [None if x is None else x[k] for x in (ddepths, dTs, dvbars, drhos)]
+                chk = [None if x is None else x[k] for x in (ddepths, dOs, dvbars, drhos)]
                 if dimgs[k] is None and all(x is None for x in chk):
                     continue
                 geom = preprocess(params, n, degree, c, f, feat=bool(ctx.channels))
                 bins = bin_sort_nosync(geom, c, cap, tile_cull)
                 render_bwd_views(params, n, degree, [(c, f, geom, bins, saved[9 + 2 * k], saved[10 + 2 * k],
                                                       dimgs[k])], grads=grads, accumulate=not first,
-                                 ddepths=[chk[0]], dTs=[chk[1]], dvbars=[chk[2]], drhos=[chk[3]],
+                                 ddepths=[chk[0]], dOs=[chk[1]], dvbars=[chk[2]], drhos=[chk[3]],
                                  depths=None if dn is None else [dn[k]], stats=ctx.stats)
                 first = False
             if first:
                 for gr in grads:
                     gr.zero_()
         else:  # the kept lists, final_T and n_contrib, with the arguments built in the forward
-            ctx.bwd.call(params[0].device, dimgs, grads, accumulate=False, ddepths=ddepths, dTs=dTs, dvbars=dvbars,
+            ctx.bwd.call(params[0].device, dimgs, grads, accumulate=False, ddepths=ddepths, dOs=dOs, dvbars=dvbars,
                          drhos=drhos, depths=None if dn is None else [dn[k] for k in range(len(plan))],
                          stats=ctx.stats)
         return (None, None, None, None, None, None, *grads)
@@ -678,9 +688,6 @@ def pvg_render_views(params, views, recompute="auto", tile_cull=True, stack=Fals
                 raise ValueError("densify_stats must be two contiguous float32 [N] tensors on the parameters' device")
         densify_stats = tuple(densify_stats)
     out = PVGRenderViews.apply(full, recompute, tile_cull, stack, mode, densify_stats, *params)
-    if channels:
-        img, depth, final_T, vbar, rho = out
-        return img, depth, 1.0 - final_T, vbar, rho
     return out
 
 

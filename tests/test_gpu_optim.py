@@ -139,3 +139,34 @@ def test_adam_bench_shape(orc):
         err = np.abs(got - want) - (1e-5 * np.abs(want) + 1e-6 * row_scale)
         assert err.max() <= 0, (name, float(err.max()))
     print(f"[adam 1M] two steps within tolerance over {len(rows)} rows")
+
+
+@pytest.mark.parametrize("res", [5, 1024])
+def test_sky_cube_adam_vs_fp64(orc, res):
+    """pvg_adam_dense on a [6,3,R,R] cube map (R = 5: a ragged count with
+    the vector and tail paths; R = 1024: the training resolution of Sec. 4)
+    against the FP64 oracle over three steps, with the bars of
+    test_adam_vs_fp64; a face with a zero gradient keeps its texels."""
+    import paper_2311_18561_amd as pvg
+    rng = np.random.default_rng(9)
+    cube0 = rng.uniform(0, 1, (6, 3, res, res)).astype(np.float32)
+    cube = torch.from_numpy(cube0).cuda()
+    opt = pvg.DenseAdam(cube, pvg.SKY_LR)
+    lr = f32(pvg.SKY_LR)
+    p, m, v = cube0.astype(np.float64), np.zeros(cube0.shape), np.zeros(cube0.shape)
+    for t in range(1, 4):
+        g = (rng.standard_normal(cube0.shape) * 1e-2).astype(np.float32)
+        g[2] = 0.0
+        opt.step(cube, torch.from_numpy(g).cuda())
+        p, m, v = orc.optim.adam_dense(p, g.astype(np.float64), m, v, lr, t, beta1=f32(0.9), beta2=f32(0.999),
+                                       eps=f32(1e-15))
+        torch.cuda.synchronize()
+        got = cube.cpu().numpy().astype(np.float64)
+        err = np.abs(got - p) - (2e-6 * np.abs(p) + 2e-6 * lr)
+        assert err.max() <= 0, (t, float(err.max()))
+        for gm, want in ((opt.m, m), (opt.v, v)):
+            e = np.abs(gm.cpu().numpy().astype(np.float64) - want) - (1e-5 * np.abs(want) + 1e-6 * np.abs(want).max())
+            assert e.max() <= 0, (t, float(e.max()))
+    assert np.array_equal(cube.cpu().numpy()[2], cube0[2])
+    with pytest.raises(ValueError):
+        opt.step(cube, torch.zeros((6, 3, res, res + 1), device="cuda"))

@@ -83,3 +83,25 @@ def test_first_step_closed_form_and_zero_rate():
     gl = g["period"] * sc["period"]
     np.testing.assert_allclose(m[r_period], 0.1 * gl, rtol=1e-12)
     np.testing.assert_allclose(v[r_period], 0.001 * gl * gl, rtol=1e-12)
+
+
+def test_dense_adam_matches_torch_adam():
+    """The cube-map step (a dense array as it is) against torch.optim.Adam
+    over four steps, and its zero-rate case."""
+    rng = np.random.default_rng(3)
+    p0 = rng.uniform(0, 1, (6, 3, 5, 5))
+    leaf = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([leaf], lr=2.5e-3, betas=(0.9, 0.999), eps=1e-15)
+    p, m, v = p0, np.zeros_like(p0), np.zeros_like(p0)
+    for t in range(1, 5):
+        g = rng.standard_normal(p0.shape) * 1e-2
+        g[0] = 0.0  # a face with no gradient keeps its texels
+        p, m, v = oo.adam_dense(p, g, m, v, 2.5e-3, t)
+        leaf.grad = torch.tensor(g)
+        opt.step()
+        np.testing.assert_allclose(p, leaf.detach().numpy(), rtol=1e-12, atol=1e-15, err_msg=f"step {t}")
+    assert np.array_equal(p[0], p0[0])
+    q, m2, v2 = oo.adam_dense(p0, g, np.zeros_like(p0), np.zeros_like(p0), 0.0, 1)
+    assert np.array_equal(q, p0)
+    np.testing.assert_allclose(m2, 0.1 * g, rtol=1e-12)
+    np.testing.assert_allclose(v2, 0.001 * g * g, rtol=1e-12)

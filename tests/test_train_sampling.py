@@ -94,3 +94,13 @@ def test_moment_rows_and_densify_extra_are_checked():
                 torch.ones((6, 40)).t()):
         with pytest.raises((TypeError, ValueError)):
             opt.set_moments_rows(bad)
+
+
+def test_dense_adam_checks_before_any_launch():
+    import torch
+
+    import paper_2311_18561_amd as pvg
+    with pytest.raises(ValueError):
+        pvg.DenseAdam(torch.zeros((6, 3, 4, 4)))  # a host tensor
+    with pytest.raises(ValueError):
+        pvg.DenseAdam(torch.zeros((6, 3, 4, 4), dtype=torch.float64))
