@@ -42,8 +42,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count")
+    ap.add_argument("--period", type=int, default=200,
+                    help="iterations of the timed training-loop period (the densify interval)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 2k, 200k and 6M workloads")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
@@ -108,39 +111,149 @@ def measured_traffic(kernel):
             + rec["write_kib_per_dispatch"] * 1024 * rec["write_scale"])
 
 
-def cpu_baseline(cfg, budget_s=20.0):
-    """The oracle (single thread) on one camera's H(t) render of the same
-    scene: FP32 preprocess of all Gaussians, instance sort, and per-pixel
-    compositing of as many tile rows as fit the time budget."""
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, rows_sampled=8):
+    """The oracle (single thread, as it stands) on one camera's H(t) view of
+    the same scene, forward and backward: FP32 per-Gaussian stage and
+    instance sort of all Gaussians, FP32 compositing and the FP64 adjoint
+    (the oracle's gradient path: the per-Gaussian chain of every Gaussian
+    once, the compositing adjoint per tile) of `rows_sampled` tile rows
+    spread evenly over the frame, the per-row parts scaled to the whole
+    frame; the training-shaped step is six such views."""
     import numpy as np
 
     import oracle
     oracle.build(force=False)
     scene, cam, t = cfg["scene"], cfg["cameras"][1], cfg["t"]
+    GX, GY = oracle.grid(cam)
+    W, H = cam["width"], cam["height"]
     t0 = time.perf_counter()
     pre = oracle.preprocess_f32(scene, cam, t)
     bins = oracle.bin_sort(pre, cam)
     t_setup = time.perf_counter() - t0
-    GX, GY = oracle.grid(cam)
-    rows, spent = 0, 0.0
+    rows = [int(r) for r in np.linspace(0, GY - 1, rows_sampled).round()]
+    t_fwd = 0.0
+    for r in rows:
+        t1 = time.perf_counter()
+        oracle.render_f32(pre, bins, cam, t, tiles=(r * GX, (r + 1) * GX))
+        t_fwd += time.perf_counter() - t1
+    sc64 = oracle.scene64(scene)
+    mask = np.zeros(GX * GY, np.uint8)
     t1 = time.perf_counter()
-    while rows < GY and (time.perf_counter() - t0) < budget_s:
-        oracle.render_f32(pre, bins, cam, t, tiles=(rows * GX, (rows + 1) * GX))
-        rows += 1
-    spent = time.perf_counter() - t1
-    px_rows = rows * 16 * cam["width"]
-    full_composite = spent * (GY / max(rows, 1))
-    per_render = t_setup + full_composite
+    oracle.backward_f64(sc64, cam, t, 0.0, 0, (0.0, 0.0, 0.0), pre, bins, np.zeros((3, H, W)), tile_mask=mask)
+    t_bwd_fixed = time.perf_counter() - t1
+    dimg = np.zeros((3, H, W))
+    rng = np.random.default_rng(0)
+    for r in rows:
+        mask[r * GX:(r + 1) * GX] = 1
+        dimg[:, r * 16:(r + 1) * 16] = rng.standard_normal((3, 16, W))
+    t1 = time.perf_counter()
+    oracle.backward_f64(sc64, cam, t, 0.0, 0, (0.0, 0.0, 0.0), pre, bins, dimg, tile_mask=mask)
+    t_bwd_rows = max(time.perf_counter() - t1 - t_bwd_fixed, 0.0)
+    scale = GY / len(rows)
+    t_view_fwd = t_setup + t_fwd * scale
+    t_view = t_view_fwd + t_bwd_fixed + t_bwd_rows * scale
+    views = 2 * len(cfg["cameras"])
     return {
-        "value": (cam["width"] * cam["height"]) / per_render / 1e6,
-        "unit": "Mpix/s fwd",
+        "value": 1.0 / (views * t_view),
+        "unit": "iters/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"one 1920x1280 H(t) render of the 1M-Gaussian scene: preprocess + sort of all "
-                   f"{scene['n']} Gaussians ({t_setup:.1f} s) and compositing of {rows}/{GY} tile rows "
-                   f"({px_rows} px, {spent:.1f} s), scaled to the full frame"),
+        "sample": (f"one 1920x1280 H(t) view of the 1M-Gaussian scene through the single-threaded oracle: FP32 "
+                   f"per-Gaussian stage + instance sort of all {scene['n']} Gaussians ({t_setup:.1f} s), FP32 "
+                   f"compositing of {len(rows)}/{GY} tile rows spread over the frame ({t_fwd:.1f} s), the FP64 "
+                   f"adjoint's per-Gaussian chain ({t_bwd_fixed:.1f} s) and its compositing adjoint on the same rows "
+                   f"({t_bwd_rows:.1f} s); rows scaled to the frame, {views} such views per step"),
+        "mpix_per_s_fwd": W * H / t_view_fwd / 1e6,
+        "seconds_per_view": t_view,
+        "host_cpu": host_cpu_model(),
         "host_cores_available": os.cpu_count(),
     }
+
+
+def config_legs(steps):
+    """The other workloads in the headline's units, each with seeded
+    synthetic inputs resident in HBM before its timed region:
+    - 2k Gaussians, degree 0, 128x96 (forward only): Mpix/s;
+    - 200k Gaussians, degree 3, 960x640 (forward + L1 backward): it/s;
+    - 6M Gaussians (40% far field), degree 3, six 1920x1280 cameras at one t
+      (forward + L1 backward of all six): it/s with the lists kept and with
+      them rebuilt in the backward, and the peak device memory of each."""
+    import torch
+
+    import gen
+    import paper_2311_18561_amd as pvg
+
+    def timed(fn, reps, warm=2):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    out = {}
+    c = gen.make_config(0)
+    p = [torch.from_numpy(c["scene"][f]).cuda() for f in pvg.FIELDS]
+    view = [(c["cameras"][0], c["t"])]
+
+    def fwd0():
+        with torch.no_grad():
+            pvg.render_views(p, view)
+
+    s0 = timed(fwd0, max(50, 10 * steps))
+    out["forward_2k_128x96"] = {"mpix_per_s_fwd": c["width"] * c["height"] / s0 / 1e6, "ms_per_render": s0 * 1e3,
+                                "gaussians": c["scene"]["n"]}
+    del p
+    print("# config legs: 2k forward done", file=sys.stderr, flush=True)
+
+    def fwd_bwd_leg(cfg, views, recompute):
+        params = [torch.from_numpy(cfg["scene"][f]).cuda().requires_grad_(True) for f in pvg.FIELDS]
+        tg = torch.stack([torch.from_numpy(x).cuda() for x in cfg["targets"]])
+
+        def step():
+            for q in params:
+                q.grad = None
+            imgs = pvg.pvg_render_views(params, views, recompute=recompute, stack=True)
+            ((imgs - tg).abs().mean() * len(views)).backward()
+
+        step()
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        sec = timed(step, steps, warm=1)
+        peak = torch.cuda.max_memory_allocated()
+        del params, tg
+        torch.cuda.empty_cache()
+        return sec, peak
+
+    c = gen.make_config(1)
+    s1, peak1 = fwd_bwd_leg(c, [(c["cameras"][0], c["t"])], "auto")
+    out["train_200k_960x640"] = {"iters_per_s": 1.0 / s1, "ms_per_step": s1 * 1e3, "gaussians": c["scene"]["n"],
+                                 "peak_bytes": peak1}
+    print("# config legs: 200k forward+backward done", file=sys.stderr, flush=True)
+    c = gen.make_config(4)
+    views = [(cam, c["t"]) for cam in c["cameras"]]
+    s4k, peak4k = fwd_bwd_leg(c, views, False)
+    s4r, peak4r = fwd_bwd_leg(c, views, True)
+    out["train_6M_6x1920x1280"] = {
+        "iters_per_s_kept_lists": 1.0 / s4k, "iters_per_s_recompute": 1.0 / s4r,
+        "ms_per_step_kept_lists": s4k * 1e3, "ms_per_step_recompute": s4r * 1e3,
+        "peak_bytes_kept_lists": peak4k, "peak_bytes_recompute": peak4r, "gaussians": c["scene"]["n"],
+        "views": len(views), "mpix_per_step": len(views) * c["width"] * c["height"] / 1e6}
+    print("# config legs: 6M forward+backward done", file=sys.stderr, flush=True)
+    return out
 
 
 SERVE_SCENES = ((500_000, 30), (1_000_000, 31), (2_000_000, 32), (3_000_000, 33))
@@ -363,12 +476,26 @@ def main():
             out[name] = {"ms": ms.value, "calls": calls.value, "work": work.value}
         return out
 
+    # each step's span on the launch stream from events recorded between the
+    # steps (no synchronisation inside the timed region), and the host time
+    # each step takes to return
+    import importlib
+    render_mod = importlib.import_module("paper_2311_18561_amd.render")
+    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    host_s = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    step_ev[0].record()
+    for i in range(args.steps):
+        h0 = time.perf_counter()
         train_step()
+        host_s.append(time.perf_counter() - h0)
+        step_ev[i + 1].record()
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    step_ms = sorted(step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps))
+    host_ms = sorted(h * 1e3 for h in host_s)
+    policy_recompute = render_mod.last_recompute
 
     # Per-kernel durations come from a separate pass that runs the same six
     # renders one view at a time (single-view calls on one stream), since the
@@ -433,38 +560,89 @@ def main():
         ch_steps.append(time.perf_counter() - t0)
     ch_med = sorted(ch_steps)[len(ch_steps) // 2]
 
-    # a whole training iteration: the channel step followed by the fused Adam
-    # step over all 65 parameter rows (Sec. 4 rates); on copies of the
-    # parameters, so the other measurements see the same scene
+    # A period of the training loop (Sec. 4 and the appendix): PERIOD
+    # iterations that each sample one view per camera at the next training
+    # frame (frames 0.02 apart on the 100 m path, the camera centre moving
+    # with t) with the temporal smoothing of Sec. 3.4 (dt = 0 with
+    # probability eta = 0.5, else dt from a 1.5-frame span and the state at
+    # t - dt translated by v_bar dt), render them with the channels over the
+    # sky cube map, take the loss (1 - 0.2) L1 + 0.2 (1 - SSIM) + the depth,
+    # opacity and velocity terms, run the backward with the densification
+    # statistics, and step Adam on the Gaussians and on the cube map; the
+    # period's first iteration ends with the densify pass (every 200
+    # iterations), and the opacity reset (every 3000) is added amortized.  On
+    # copies of the parameters, so the other measurements see the same scene.
+    import random
+
     train_params = [p.detach().clone().requires_grad_(True) for p in params]
     adam = pvg.PVGAdam(train_params, pvg.default_lrs(30.0))
+    train_cube = cube.detach().clone().requires_grad_(True)
+    cube_adam = pvg.DenseAdam(train_cube, pvg.SKY_LR)
+    yaws = (-45.0, 0.0, 45.0)
+    sample_rng = random.Random(11)
+    state = {"acc": torch.zeros(N, device="cuda"), "cnt": torch.zeros(N, device="cuda"), "frame": 0,
+             "views": 0, "translated": 0}
+    n_frames, frame_dt = 50, 0.02
+    dcfg = pvg.densify_config(30.0)
 
-    def train_iteration():
+    def train_iteration(densify_after=False):
+        nonlocal train_params
+        f = state["frame"] % n_frames
+        state["frame"] += 1
+        t_f = f * frame_dt
+        cams_f = [gen.yaw_camera(W, H, y, (0.0, 0.0, 100.0 * t_f)) for y in yaws]
+        vs, _ = pvg.temporal_smoothing_views(cams_f, t_f, frame_dt, eta=0.5, rng=sample_rng)
+        state["views"] += len(vs)
+        state["translated"] += sum(1 for v in vs if v[2] != 0.0)
         for p in train_params:
             p.grad = None
-        cube.grad = None
-        imgs, dn, opac, vbar, _ = pvg.pvg_render_views(train_params, views, channels=True, normalized_depth=True,
-                                                       densify_stats=(d_acc, d_cnt))
-        jit = torch.rand((V, 2, H, W), device="cuda", generator=gch) - 0.5
-        final = torch.stack([pvg.pvg_sky_composite(imgs[k], opac[k], cube, views[k][0], jit[k]) for k in range(V)])
+        train_cube.grad = None
+        Vf = len(vs)
+        imgs, dn, opac, vbar, _ = pvg.pvg_render_views(train_params, vs, channels=True, normalized_depth=True,
+                                                       densify_stats=(state["acc"], state["cnt"]))
+        jit = torch.rand((Vf, 2, H, W), device="cuda", generator=gch) - 0.5
+        final = torch.stack([pvg.pvg_sky_composite(imgs[k], opac[k], train_cube, vs[k][0], jit[k])
+                             for k in range(Vf)])
         o = opac.clamp(1e-6, 1.0 - 1e-6)
         inv = 1.0 / dn.clamp_min(1e-3)
-        # (1 - lambda_r) L1 + lambda_r (1 - SSIM) per view, lambda_r = 0.2 (Sec. 4)
-        ssim = torch.stack([pvg.pvg_ssim(final[k], stacked_targets[k]).mean() for k in range(V)])
-        rgb = 0.8 * (final - stacked_targets).abs().mean() * V + 0.2 * (1.0 - ssim).sum()
-        loss = (rgb + 0.1 * (sparse * (inv - inv_depth_target).abs()).mean()
-                + 0.05 * (-(o * o.log()).mean() - (sky * (1.0 - o).log()).mean()) + 0.01 * vbar.abs().mean())
+        tg = stacked_targets[0::2]
+        ssim = torch.stack([pvg.pvg_ssim(final[k], tg[k]).mean() for k in range(Vf)])
+        rgb = 0.8 * (final - tg).abs().mean() * Vf + 0.2 * (1.0 - ssim).sum()
+        loss = (rgb + 0.1 * (sparse[:Vf] * (inv - inv_depth_target[:Vf]).abs()).mean()
+                + 0.05 * (-(o * o.log()).mean() - (sky[:Vf] * (1.0 - o).log()).mean())
+                + 0.01 * vbar.abs().mean())
         loss.backward()
         adam.step(train_params)
+        cube_adam.step(train_cube)
+        if densify_after:
+            n_now = train_params[0].shape[1]
+            dnz = torch.randn((8, n_now), device="cuda", generator=gch)
+            new, rows = pvg.densify(train_params, state["acc"], state["cnt"], dnz, dcfg, adam.moments_rows())
+            adam.set_moments_rows(rows)
+            train_params = [p.requires_grad_(True) for p in new]
+            m = train_params[0].shape[1]
+            state["acc"], state["cnt"] = torch.zeros(m, device="cuda"), torch.zeros(m, device="cuda")
 
-    train_iteration()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(2):
         train_iteration()
     torch.cuda.synchronize()
-    t_full = time.perf_counter() - t0
-    del train_params, adam
+    n_period_start = train_params[0].shape[1]
+    state["views"] = state["translated"] = 0
+    t0 = time.perf_counter()
+    for i in range(args.period):
+        train_iteration(densify_after=(i == 0))
+    torch.cuda.synchronize()
+    t_period = time.perf_counter() - t0
+    n_period_end = train_params[0].shape[1]
+    reset_reps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reset_reps):
+        adam.reset_opacity(train_params, 0.01)
+    torch.cuda.synchronize()
+    t_reset = (time.perf_counter() - t0) / reset_reps
+    t_full = t_period / args.period + t_reset / 3000.0
+    del train_params, adam, train_cube, cube_adam
 
     # semantic rendering (Sec. 4.1): 19 class scores per Gaussian composited
     # over the six views and differentiated (vectors and Gaussians)
@@ -583,14 +761,22 @@ def main():
         "iters_per_s_recompute": args.steps / t_recompute,
         "iters_per_s_channels": args.steps / t_channels,
         "iters_per_s_channels_median_step": 1.0 / ch_med,
-        "iters_per_s_full_iteration": args.steps / t_full,
+        "iters_per_s_full_iteration": 1.0 / t_full,
         "semantic_ms_per_step": t_sem * 1e3,
         "semantic_note": ("pvg_render_semantic forward and backward of 19 class scores per Gaussian over the six "
                           "views (seven three-channel passes per view on the view's lists, one adjoint call)"),
-        "full_iteration_note": ("the channel step with the colour term (1 - 0.2) L1 + 0.2 (1 - SSIM) per view "
-                                "(pvg_ssim, 11 x 11 Gaussian window), followed by pvg_adam_step over all parameter "
-                                "rows (Sec. 4 rates; the cube map is not updated); the temporal-smoothing sampling "
-                                "is not in it: the six views are rendered every iteration"),
+        "full_iteration_note": (f"a {args.period}-iteration period of the training loop (timed whole): each "
+                                "iteration samples one view per camera (3) at the next frame with the temporal "
+                                "smoothing of Sec. 3.4 (eta = 0.5, dt from a 1.5-frame span), renders the channels "
+                                "over the 1024^2 sky cube map, takes (1 - 0.2) L1 + 0.2 (1 - SSIM) with the depth, "
+                                "opacity and velocity terms, runs the backward with the densification statistics and "
+                                "steps Adam on the Gaussians (pvg_adam_step) and on the cube map (pvg_adam_dense); "
+                                "the first iteration ends with the densify pass (every 200 iterations) and the "
+                                "opacity reset (every 3000) is added amortized"),
+        "full_iteration": {"period": args.period, "gaussians_before": n_period_start,
+                           "gaussians_after": n_period_end, "ms_per_period": t_period * 1e3,
+                           "opacity_reset_ms": t_reset * 1e3, "views_rendered": state["views"],
+                           "views_translated": state["translated"]},
         "densify": {"ms_per_pass": t_dens * 1e3, "gaussians_in": N, "gaussians_out": n_after,
                     "statistics_views": int(d_cnt.max().item()), "GB_per_s": dens_bytes / t_dens / 1e9,
                     "note": ("pvg_densify_plan + pvg_densify_apply on the channel steps' statistics (r = 30, "
@@ -603,7 +789,12 @@ def main():
                           "composite, an inverse-depth L1 on 5% of the pixels, the opacity entropy term with a sky "
                           "mask and the sparse velocity term, weights 0.1, 0.05, 0.01 (synthetic targets); the "
                           "backward also accumulates the adaptive control's view-space gradient statistics"),
-        "lists": "kept from the forward (recompute='auto': they fit in a tenth of HBM)",
+        "lists": ("rebuilt in the backward" if policy_recompute else "kept from the forward") +
+                 " (recompute='auto': kept while they fit in a tenth of HBM)",
+        "step_ms": {"mean": sum(step_ms) / len(step_ms), "median": step_ms[len(step_ms) // 2], "min": step_ms[0],
+                    "max": step_ms[-1], "measured": "events on the launch stream between consecutive steps"},
+        "host_ms_per_step": {"median": host_ms[len(host_ms) // 2], "max": host_ms[-1],
+                             "note": "host time until the step's launches return (the forward waits for binning)"},
         "instances_per_render": {"rectangle": M, "listed": Lst, "adjoint_records": visited},
         "visible_per_render": n_vis,
         "roofline": roof,
@@ -612,6 +803,11 @@ def main():
                         "(the timed step runs views concurrently on side streams and adds all views' per-Gaussian "
                         "adjoints in one pass)"),
     }
+    if not args.no_configs:
+        del params, targets
+        torch.cuda.empty_cache()
+        params = targets = None
+        out["other_workloads"] = config_legs(args.steps)
     if not args.no_serve:
         del params, targets
         torch.cuda.empty_cache()
