@@ -59,7 +59,7 @@ def _open(path):
                                  vp, vp, vp, vp, vp, vp]
     L.orc_render_f64.restype = C.c_double
     L.orc_backward_f64.argtypes = [i64, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
-                                   vp, vp, vp, vp]
+                                   vp, vp, vp, vp, vp, vp, vp]
     L.orc_backward_f64.restype = None
     L.orc_temporal_f64.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, C.c_double,
                                    C.c_double, C.c_double, i32, vp, vp]
@@ -303,12 +303,18 @@ def normalized_depth_bwd_f64(g, depth, final_T):
 
 
 def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, tile_mask=None, dD=None, dT=None, dF=None,
-                 colour=None) -> tuple[dict, np.ndarray]:
+                 colour=None, g2d_in=None, want_abs=False, want_terms=False):
     """FP64 gradients of sum(dimg * image) + sum(dD * depth) + sum(dT * final_T)
     + sum(dF * (velocity map, staticness map)) for every parameter array, and
     g2d [N,14] (entries 9..13: d depth, d v~, d rho).
     tile_mask (optional, one byte per tile): only these tiles are visited; dimg,
-    dD and dT must be zero on every other tile."""
+    dD and dT must be zero on every other tile.  g2d_in ([N,14]): skip the
+    compositing adjoint and take these screen-space gradients through the
+    chain rule.  want_abs: also return the per-Gaussian sums over the pixels of
+    the absolute values of the screen-space terms ([N,14], third result).
+    want_terms: instead return, third, per parameter entry the magnitude of
+    its terms: those sums carried through the chain rule in absolute value
+    (the scale an FP32 adjoint's rounding is relative to)."""
     n = int(sc64["n"])
     W, H = cam["width"], cam["height"]
     arrs, ptrs = _param_ptrs(sc64, np.float64)
@@ -333,10 +339,17 @@ def backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, tile_mask=None, dD
             assert not np.any(dFv[:, ~keep]), "dF must be zero outside the tile mask"
         for extra in (dDv, dTv):
             assert extra is None or not np.any(extra[~keep]), "dD and dT must be zero outside the tile mask"
+    gin = None if g2d_in is None else _c(g2d_in, np.float64)
+    g2a = np.zeros((n, 14), np.float64) if (want_abs or want_terms) else None
+    terms = {f: np.zeros_like(sc64[f], dtype=np.float64) for f in FIELDS} if want_terms else None
+    tptrs = (C.c_void_p * 9)(*[terms[f].ctypes.data for f in FIELDS]) if want_terms else None
     lib().orc_backward_f64(n, int(sc64["sh_degree"]), ptrs, _p(cv), W, H, _p(fv), _p(pre["xy"]),
                            _p(pre["conic_op"]), _p(pre["radius"]), _p(pre["flags"]), _p(bins["ranges"]),
-                           _p(ig), _p(d), gptrs, _p(g2d), _p(tm), _p(dDv), _p(dTv), _p(dFv), _p(col))
-    return grads, g2d
+                           _p(ig), _p(d), gptrs, _p(g2d), _p(tm), _p(dDv), _p(dTv), _p(dFv), _p(col), _p(gin),
+                           _p(g2a), tptrs)
+    if want_terms:
+        return grads, g2d, terms
+    return (grads, g2d, g2a) if want_abs else (grads, g2d)
 
 
 def temporal_f64(mu, v, l, tau, beta, o, t, dt=0.0, mode=0):

@@ -753,10 +753,18 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
                       const int32_t* radius32, const uint32_t* flags32, const uint32_t* ranges,
                       const uint32_t* inst_gauss, const double* dimg, void* const* garr, double* g2d_out,
                       const uint8_t* tile_mask, const double* dD, const double* dT, const double* dF,
-                      const double* colour) {
+                      const double* colour, const double* g2d_in, double* g2d_abs_out, void* const* mag_arr) {
   // colour (optional, [n][3]): as in orc_render_f64; the colour is then a
   // plain per-Gaussian value, so nothing flows into the SH or, through the
-  // view direction, into the mean, and g2d[6..8] is its gradient
+  // view direction, into the mean, and g2d[6..8] is its gradient.
+  // g2d_in (optional, [n][14]): skip the compositing adjoint and apply the
+  // chain rule to these screen-space gradients (the chain is linear in them).
+  // g2d_abs_out (optional, [n][14]): the sum over the pixels of the absolute
+  // value of every term added into each screen-space entry (with the
+  // alpha-gradient's own terms taken in absolute value): the scale that the
+  // rounding of a sum of those terms is relative to.  mag_arr (optional, with
+  // g2d_abs_out; nine arrays shaped like garr): per parameter entry, that
+  // scale carried through the chain rule in absolute value.
   const Params prm = make_params(n, degree, arr);
   const Camera cam = make_cam(camv, W, H);
   const Frame fr = make_frame(framev);
@@ -773,11 +781,13 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
   const int GX = (W + kTile - 1) / kTile, GY = (H + kTile - 1) / kTile;
   const int64_t HW = static_cast<int64_t>(H) * W;
   std::vector<double> g2d(static_cast<size_t>(n) * kG2D, 0.0);
+  std::vector<double> g2a(g2d_abs_out ? static_cast<size_t>(n) * kG2D : 0, 0.0);
   std::vector<Contrib<double>> rec;
+  if (g2d_in) std::memcpy(g2d.data(), g2d_in, g2d.size() * sizeof(double));
 
   // O6: per pixel, the derivative of Eq. (3) with respect to each
   // contributor's alpha, colour, and through alpha its opacity, conic and mean.
-  for (int64_t t = 0; t < static_cast<int64_t>(GX) * GY; ++t) {
+  for (int64_t t = 0; !g2d_in && t < static_cast<int64_t>(GX) * GY; ++t) {
     // tile_mask (optional): tiles left out must carry a zero dimg, so they add nothing
     if (tile_mask && !tile_mask[t]) continue;
     const int tx = static_cast<int>(t % GX), ty = static_cast<int>(t / GX);
@@ -802,17 +812,36 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
           const Contrib<double>& c = rec[k];
           const Splat<double>& v = val[c.g];
           double* gg = &g2d[kG2D * static_cast<size_t>(c.g)];
-          double dalpha = 0.0;
+          double dalpha = 0.0, dabs = 0.0;
           for (int ch = 0; ch < 3; ++ch) {
             gg[6 + ch] += c.T * c.alpha * g[ch];
             dalpha += g[ch] * (c.T * v.rgb[ch] - S[ch] / (1.0 - c.alpha));
+            dabs += std::fabs(g[ch]) * (std::fabs(c.T * v.rgb[ch]) + std::fabs(S[ch] / (1.0 - c.alpha)));
           }
           gg[9] += c.T * c.alpha * gD;
           dalpha += gD * (c.T * v.depth - SD / (1.0 - c.alpha));
           dalpha += gT * (-Tf / (1.0 - c.alpha));
+          dabs += std::fabs(gD) * (std::fabs(c.T * v.depth) + std::fabs(SD / (1.0 - c.alpha))) +
+                  std::fabs(gT * Tf / (1.0 - c.alpha));
           for (int f = 0; f < 4; ++f) {
             gg[10 + f] += c.T * c.alpha * gF[f];
             dalpha += gF[f] * (c.T * v.feat[f] - SF[f] / (1.0 - c.alpha));
+            dabs += std::fabs(gF[f]) * (std::fabs(c.T * v.feat[f]) + std::fabs(SF[f] / (1.0 - c.alpha)));
+          }
+          if (g2d_abs_out) {
+            double* ga = &g2a[kG2D * static_cast<size_t>(c.g)];
+            for (int ch = 0; ch < 3; ++ch) ga[6 + ch] += std::fabs(c.T * c.alpha * g[ch]);
+            ga[9] += std::fabs(c.T * c.alpha * gD);
+            for (int f = 0; f < 4; ++f) ga[10 + f] += std::fabs(c.T * c.alpha * gF[f]);
+            if (!c.clamped) {
+              const double ap = c.alpha * dabs;
+              ga[5] += c.G * dabs;
+              ga[2] += 0.5 * c.dx * c.dx * ap;
+              ga[3] += std::fabs(c.dx * c.dy) * ap;
+              ga[4] += 0.5 * c.dy * c.dy * ap;
+              ga[0] += (std::fabs(v.A * c.dx) + std::fabs(v.B * c.dy)) * ap;
+              ga[1] += (std::fabs(v.B * c.dx) + std::fabs(v.C * c.dy)) * ap;
+            }
           }
           for (int ch = 0; ch < 3; ++ch) S[ch] += c.T * c.alpha * v.rgb[ch];
           SD += c.T * c.alpha * v.depth;
@@ -829,6 +858,7 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
       }
   }
   if (g2d_out) std::memcpy(g2d_out, g2d.data(), g2d.size() * sizeof(double));
+  if (g2d_abs_out) std::memcpy(g2d_abs_out, g2a.data(), g2a.size() * sizeof(double));
 
   // O7: chain rule back to the per-point parameters.
   const int K = (degree + 1) * (degree + 1);
@@ -850,11 +880,12 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
   double Wm[9];
   for (int c = 0; c < 9; ++c) Wm[c] = cam.R[c];
   const double fx = cam.fx, fy = cam.fy;
-  for (int64_t i = 0; i < n; ++i) {
-    if (!val[i].visible) continue;
+  // the chain rule of Gaussian i from its screen-space gradient gg; put(field,
+  // row, value) receives each parameter-gradient entry (fields in the order
+  // mu, scale, rot, sh, opacity, vel, period, tau, beta)
+  auto chain = [&](int64_t i, const double* gg, auto&& put) {
     const Inter<double>& it = inter[i];
     const Splat<double>& v = val[i];
-    const double* gg = &g2d[kG2D * static_cast<size_t>(i)];
     double dmur[3] = {0, 0, 0};
 
     // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2)
@@ -863,7 +894,7 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
       const bool clamp = (v.flags & (kShClampR << ch)) != 0;
       const double draw = clamp ? 0.0 : gg[6 + ch];
       for (int k = 0; k < K; ++k) {
-        gsh[(3 * k + ch) * n + i] = it.Y[k] * draw;
+        put(3, 3 * k + ch, it.Y[k] * draw);
         const double shv = static_cast<const double*>(prm.sh)[(3 * k + ch) * n + i];
         for (int c = 0; c < 3; ++c) ddir[c] += shv * draw * it.dY[k][c];
       }
@@ -938,7 +969,7 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
     for (int c = 0; c < 3; ++c) {
       double acc = 0;
       for (int r = 0; r < 3; ++r) acc += dM[3 * r + c] * it.Rq[3 * r + c];
-      gs[c * n + i] = acc;
+      put(1, c, acc);
       for (int r = 0; r < 3; ++r) dR[3 * r + c] = dM[3 * r + c] * it.s[c];
     }
     // R(q^) -> q^
@@ -952,7 +983,7 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
     for (int e = 0; e < 9; ++e)
       for (int c = 0; c < 4; ++c) dqn[c] += dR[e] * dRdq[e][c];
     const double qd = w * dqn[0] + x * dqn[1] + y * dqn[2] + z * dqn[3];
-    for (int c = 0; c < 4; ++c) gq[c * n + i] = (dqn[c] - it.qn[c] * qd) / it.qnorm;
+    for (int c = 0; c < 4; ++c) put(2, c, (dqn[c] - it.qn[c] * qd) / it.qnorm);
 
     // flow translation (Eqs. (10), (12)): mu_r = mu~ + v e dt, e = exp(-beta/(2l))
     double dl = 0, dtau = 0, dbeta = 0;
@@ -975,9 +1006,8 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
     const double k = it.l / (2.0 * kPi) * std::sin(phi);
     const double vg = it.v[0] * dmur[0] + it.v[1] * dmur[1] + it.v[2] * dmur[2];
     for (int c = 0; c < 3; ++c) {
-      gmu[c * n + i] = dmur[c];
+      put(0, c, dmur[c]);
       dv[c] += k * dmur[c];
-      gv[c * n + i] = dv[c];
     }
     dtau += -std::cos(phi) * vg;
     dl += (std::sin(phi) / (2.0 * kPi) - del / it.l * std::cos(phi)) * vg;
@@ -991,17 +1021,42 @@ void orc_backward_f64(int64_t n, int degree, const void* const* arr, const float
       }
       dbeta += vdot * e * (-0.5 / it.l) + gg[13] / it.l;
       dl += vdot * e * (0.5 * it.beta / (it.l * it.l)) - gg[13] * it.beta / (it.l * it.l);
-      for (int c = 0; c < 3; ++c) gv[c * n + i] = dv[c];
+      for (int c = 0; c < 3; ++c) put(5, c, dv[c]);
     }
     // opacity decay (Eq. (7)): o~ = o exp(-(t - tau)^2 / (2 beta^2))
     const double eo = std::exp(-0.5 * (del / it.beta) * (del / it.beta));
     const double dop = gg[5];
-    go[i] = eo * dop;
+    put(4, 0, eo * dop);
     dtau += dop * v.op * del / (it.beta * it.beta);
     dbeta += dop * v.op * del * del / (it.beta * it.beta * it.beta);
-    gl[i] = dl;
-    gtau[i] = dtau;
-    gbeta[i] = dbeta;
+    put(6, 0, dl);
+    put(7, 0, dtau);
+    put(8, 0, dbeta);
+  };
+  for (int64_t i = 0; i < n; ++i) {
+    if (!val[i].visible) continue;
+    chain(i, &g2d[kG2D * static_cast<size_t>(i)],
+          [&](int f, int r, double x) { static_cast<double*>(garr[f])[r * n + i] = x; });
+  }
+  // the magnitude of each entry's terms: the chain's Jacobian column of every
+  // screen-space entry, in absolute value, times that entry's absolute sum
+  if (mag_arr && g2d_abs_out) {
+    for (int f = 0; f < 9; ++f) {
+      const int rows = f == 3 ? 3 * K : (f == 2 ? 4 : (f == 0 || f == 1 || f == 5) ? 3 : 1);
+      std::fill(static_cast<double*>(mag_arr[f]), static_cast<double*>(mag_arr[f]) + rows * n, 0.0);
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      if (!val[i].visible) continue;
+      const double* ga = &g2a[kG2D * static_cast<size_t>(i)];
+      for (int k = 0; k < kG2D; ++k) {
+        if (!(ga[k] > 0.0)) continue;
+        double e[kG2D] = {};
+        e[k] = 1.0;
+        chain(i, e, [&](int f, int r, double x) {
+          static_cast<double*>(mag_arr[f])[r * n + i] += std::fabs(x) * ga[k];
+        });
+      }
+    }
   }
 }
 

@@ -122,15 +122,22 @@ def geom_as_oracle_pre(g, cam):
             "radius": g["radius"], "rect": rect, "tiles": g["tiles"], "flags": np.zeros(n, np.uint32)}
 
 
-def grad_tolerance_report(g_gpu, g_ref, rel=1e-3, floor=1e-2, magnitude=None):
+def grad_tolerance_report(g_gpu, g_ref, rel=1e-3, floor=1e-2, magnitude=None, terms=None):
     """Per element |g - g*| <= rel * max(|g*|, floor * rms(g*)); returns (worst ratio, l2 rel err).
     magnitude (optional, same shape): the scale of the terms summed into g*
     (for a sum over views, the sum of the views' |g*|), used instead of |g*|,
-    since FP32 sums are accurate relative to their terms, not to the total."""
+    since FP32 sums are accurate relative to their terms, not to the total.
+    terms (optional, same shape): the oracle's bound on the magnitude of the
+    per-pixel terms behind each element (oracle.grad_magnitude_f64); the bar
+    is then at least rel * 1e-2 * terms, about 170 FP32 roundings of that
+    scale, which a sum of a few hundred rounded terms can reach but a wrong
+    term cannot hide under where the element does not cancel."""
     g_gpu = np.asarray(g_gpu, np.float64)
     g_ref = np.asarray(g_ref, np.float64)
     rms = np.sqrt(np.mean(g_ref ** 2)) if g_ref.size else 0.0
     mag = np.abs(g_ref) if magnitude is None else np.maximum(np.abs(g_ref), np.asarray(magnitude, np.float64))
+    if terms is not None:
+        mag = np.maximum(mag, 1e-2 * np.asarray(terms, np.float64))
     denom = np.maximum(mag, floor * rms)
     denom = np.where(denom > 0, denom, 1.0)
     ratio = np.abs(g_gpu - g_ref) / (rel * denom)
@@ -227,3 +234,9 @@ def image_parity(img, ref, margin, tol=1e-4, rows=None, max_excused=None):
     assert worst <= tol, f"error {worst:.3g} above {tol} at a pixel whose decisions are unambiguous"
     assert excused <= bound, f"{excused} pixels differ at ambiguous decisions (bound {bound})"
     return worst, excused
+
+
+def oracle_grads(orc, sc64, cam, t, dt, mode, bg, pre, bins, dimg, **kw):
+    """The FP64 adjoint (backward_f64) and, per parameter entry, the
+    magnitude of its terms: (grads, g2d, terms)."""
+    return orc.backward_f64(sc64, cam, t, dt, mode, bg, pre, bins, dimg, want_terms=True, **kw)

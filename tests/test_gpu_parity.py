@@ -3,7 +3,9 @@
 Bars: bit-exact per-Gaussian discrete structure (radius, tile counts, depth
 keys, 2D mean and conic), bit-exact sorted instances and ranges; images within
 1e-4 absolute of the FP32 oracle; gradients within 1e-3 relative of the FP64
-oracle (per element, relative to max(|g*|, 1e-2 rms(g*)) of that tensor).
+oracle (per element, relative to max(|g*|, 1e-2 rms(g*)) of that tensor, and
+at least 1e-2 of the magnitude of the element's terms, since an FP32 sum is
+accurate relative to its terms, not to a total that cancels).
 The compositing walk's skip and stop decisions are discrete: where the
 oracle's exact value sits within rounding of a threshold (its decision
 margin below 1) either branch is a correct FP32 render, so images are held to
@@ -19,7 +21,7 @@ import pytest
 
 import gen
 from helpers import (FIELDS, check_culled_lists, geom_as_oracle_pre, gpu_forward, grad_tolerance_report,
-                     image_parity, last_contributor_ids, oracle_margin, to_device, unambiguous)
+                     image_parity, last_contributor_ids, oracle_grads, oracle_margin, to_device, unambiguous)
 
 pytestmark = pytest.mark.gpu
 
@@ -129,11 +131,17 @@ def _backward_compare(orc, scene, cam, t, dt, mode, bg, seed=0, rel=1e-3, tile_c
     params = [p.requires_grad_(True) for p in to_device(scene)]
     img = pvg.pvg_render(params, cam, t, dt, mode, bg, tile_cull=tile_cull)
     (img * torch.from_numpy(w).cuda()).sum().backward()
-    ref, _ = orc.backward_f64(orc.scene64(scene), cam, t, dt, mode, bg, pre, bins, w.astype(np.float64))
+    ref, _, terms = oracle_grads(orc, orc.scene64(scene), cam, t, dt, mode, bg, pre, bins, w.astype(np.float64))
     report = {}
     for f, p in zip(FIELDS, params):
         got = p.grad.detach().cpu().numpy().astype(np.float64)
-        report[f] = grad_tolerance_report(got, ref[f], rel=rel)
+        report[f] = grad_tolerance_report(got, ref[f], rel=rel, terms=terms[f])
+        if report[f][0] > 0.5:  # describe the worst element
+            r = ref[f].reshape(-1)
+            gg = got.reshape(-1)
+            floor = 1e-2 * np.sqrt(np.mean(r ** 2))
+            j = int(np.argmax(np.abs(gg - r) / (rel * np.maximum(np.abs(r), floor))))
+            print(f"  {f}[{j}]: got {gg[j]:.9g} ref {r[j]:.9g} floor {floor:.3g} (entry {j % scene['n']})")
     return report
 
 
@@ -243,18 +251,35 @@ def test_preprocess_views_equals_single_view_preprocess():
 
 
 @pytest.mark.parametrize("recompute", [True, False])
-def test_multi_view_render_matches_single_views(recompute):
+def test_multi_view_render_matches_single_views(orc, recompute):
     """pvg_render_views: each image equals the single-view render bit for bit;
-    the gradients (added in the kernels) equal the sum of the single-view
-    gradients up to FP32 addition order; a view that outgrows the cached
-    capacity is redone."""
+    the gradients (the views' screen-space gradients taken through one
+    per-Gaussian chain in the kernels) and the sum of the single-view
+    gradients both match the FP64 oracle summed over the views, each element
+    within 1e-3 of the sum over the views of max(|g*|, 1e-2 of its terms);
+    a view that outgrows the cached capacity is redone."""
     import importlib
     import paper_2311_18561_amd as pvg
     R = importlib.import_module("paper_2311_18561_amd.render")
     cfg = gen.make_config(1, n=20_000)
     cams = [gen.yaw_camera(320, 208, yaw, (0.0, 0.0, 0.0)) for yaw in (-20.0, 0.0, 20.0)]
     views = [(cam, 0.4, d) for cam in cams for d in (0.0, 0.05)]
-    w = [torch.linspace(-1, 1, 3 * 208 * 320, device="cuda").reshape(3, 208, 320) * (k + 1) for k in range(6)]
+    sc64 = orc.scene64(cfg["scene"])
+    ramp = np.linspace(-1, 1, 3 * 208 * 320).reshape(3, 208, 320)
+    ref = {f: np.zeros_like(sc64[f]) for f in FIELDS}
+    mag = {f: np.zeros_like(sc64[f]) for f in FIELDS}
+    wn = []
+    for k, (cam, t, d) in enumerate(views):
+        pre = orc.preprocess_f32(cfg["scene"], cam, t, d)
+        bins = orc.bin_sort(pre, cam)
+        keep = unambiguous(oracle_margin(pre, bins, cam, t, d, gradients=True))
+        wk = (ramp * (k + 1) * keep).astype(np.float32)
+        wn.append(wk)
+        part, _, terms = oracle_grads(orc, sc64, cam, t, d, 0, (0, 0, 0), pre, bins, wk.astype(np.float64))
+        for f in FIELDS:
+            ref[f] += part[f]
+            mag[f] += np.maximum(np.abs(part[f]), 1e-2 * terms[f])
+    w = [torch.from_numpy(x).cuda() for x in wn]
     ref_imgs, ref_grads = [], None
     params = [p.requires_grad_(True) for p in to_device(cfg["scene"])]
     for k, (cam, t, d) in enumerate(views):
@@ -272,8 +297,9 @@ def test_multi_view_render_matches_single_views(recompute):
         for a, b in zip(imgs, ref_imgs):
             assert torch.equal(a.detach(), b)
         for f, p, g in zip(FIELDS, params, ref_grads):
-            worst, l2 = grad_tolerance_report(p.grad.cpu().numpy(), g.cpu().numpy(), rel=1e-4)
-            assert worst <= 1.0, (shrink, f, worst)
+            for label, got in (("multi-view", p.grad), ("single views", g)):
+                worst, l2 = grad_tolerance_report(got.cpu().numpy(), ref[f], magnitude=mag[f])
+                assert worst <= 1.0, (label, shrink, f, worst)
         # the same views as one stacked [V,3,H,W] output
         for p in params:
             p.grad = None
@@ -282,8 +308,8 @@ def test_multi_view_render_matches_single_views(recompute):
         (stacked * torch.stack(w)).sum().backward()
         for k, b in enumerate(ref_imgs):
             assert torch.equal(stacked[k].detach(), b)
-        for f, p, g in zip(FIELDS, params, ref_grads):
-            worst, l2 = grad_tolerance_report(p.grad.cpu().numpy(), g.cpu().numpy(), rel=1e-4)
+        for f, p in zip(FIELDS, params):
+            worst, l2 = grad_tolerance_report(p.grad.cpu().numpy(), ref[f], magnitude=mag[f])
             assert worst <= 1.0, ("stacked", shrink, f, worst)
 
 
@@ -414,8 +440,8 @@ def test_config1_full_size(orc):
     img = pvg.pvg_render(params, cam, t)
     (img * torch.from_numpy(dimg).cuda()).sum().backward()
     dimg = dimg.astype(np.float64)
-    ref, _ = orc.backward_f64(orc.scene64(scene), cam, t, 0.0, 0, (0, 0, 0), o["pre"], o["bins"], dimg)
+    ref, _, terms = oracle_grads(orc, orc.scene64(scene), cam, t, 0.0, 0, (0, 0, 0), o["pre"], o["bins"], dimg)
     for f, p in zip(FIELDS, params):
-        worst, l2 = grad_tolerance_report(p.grad.detach().cpu().numpy(), ref[f])
+        worst, l2 = grad_tolerance_report(p.grad.detach().cpu().numpy(), ref[f], terms=terms[f])
         print(f"[cfg1] {f}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
         assert worst <= 1.0, f
