@@ -546,6 +546,10 @@ int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const
     PVG_HIP(launch_render_bwd(single(v, g->n), to_geom(&geoms[k]), lists, rec, vis,
                               static_cast<int64_t>(vis_bytes), g2d, serial ? s : side[r]));
     ++launched;
+    if (pk.nv > 0 && !(v.t == pk.views[0].t)) {  // a pass shares one render time
+      const int st = flush();
+      if (st != PVG_OK) return st;
+    }
     pk.views[pk.nv] = v;
     pk.radius[pk.nv] = geoms[k].radius;
     pk.rgb[pk.nv] = geoms[k].rgb;

@@ -40,6 +40,11 @@ constexpr int kScanItems = 4;                       // items per thread in the s
 constexpr int kScanBlock = kThreads * kScanItems;   // 1024
 constexpr int kRsItems = 16;                        // items per thread in a radix pass
 constexpr int kRsBlock = kThreads * kRsItems;       // 4096
+// Digits of the depth passes.  Three passes of 11 bits measured slower than
+// four of 8 on the benchmark's 0.58M visible Gaussians (2048-digit block
+// scans and 11 ballots per key outweigh the saved pass).
+constexpr int kDepthBits = 8;
+constexpr int kDepthPasses = (32 + kDepthBits - 1) / kDepthBits;
 
 // ------------------------------------------------------------------ helpers
 template <class T>
@@ -170,16 +175,20 @@ __global__ void __launch_bounds__(kThreads) k_vis_compact(const uint32_t* __rest
 }
 
 // ------------------------------------------------------------------ radix passes
+// kMaxBits: the widest digit a kernel instance handles (8 for the tile
+// passes, 11 for the depth passes: 32 bits in three passes); `bits` <= it.
+template <int kMaxBits>
 __global__ void __launch_bounds__(kThreads) k_rs_hist(const uint32_t* __restrict__ keys, const uint32_t* n_dev,
                                                       int64_t n_host, int shift, int bits, uint32_t* hist,
                                                       int64_t cols) {
-  __shared__ uint32_t h[256];
+  constexpr int kR = 1 << kMaxBits;
+  __shared__ uint32_t h[kR];
   const int64_t n = live_count(n_dev, n_host);
   const int64_t nb = (n + kRsBlock - 1) / kRsBlock;
   const int radix = 1 << bits;
   const uint32_t mask = static_cast<uint32_t>(radix - 1);
   for (int64_t lb = blockIdx.x; lb < nb; lb += gridDim.x) {
-    h[threadIdx.x] = 0;
+    for (int d = threadIdx.x; d < radix; d += kThreads) h[d] = 0;
     __syncthreads();
     const int64_t base = lb * kRsBlock + threadIdx.x;
 #pragma unroll 4
@@ -188,7 +197,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_hist(const uint32_t* __restrict
       if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < radix) hist[threadIdx.x * cols + lb] = h[threadIdx.x];
+    for (int d = threadIdx.x; d < radix; d += kThreads) hist[d * cols + lb] = h[d];
     __syncthreads();
   }
 }
@@ -225,17 +234,21 @@ __global__ void __launch_bounds__(kThreads) k_rs_rowscan(uint32_t* hist, int64_t
 // keys (wave ballots find lanes with equal digits; a wave-private LDS counter
 // per digit carries ranks across its 16 sub-tiles), the block combines the
 // four waves per digit, stages the block's 4096 pairs locally sorted in LDS and
-// writes each digit's run contiguously.
+// writes each digit's run contiguously.  A thread owns kPerT consecutive
+// digits in the block-wide digit scans.
+template <int kMaxBits>
 __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint32_t* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin, uint32_t* kout,
                                                          uint32_t* vout, const uint32_t* n_dev, int64_t n_host,
                                                          int shift, int bits, const uint32_t* __restrict__ hist,
                                                          int64_t cols, const uint32_t* __restrict__ rowtot) {
+  constexpr int kR = 1 << kMaxBits;
+  constexpr int kPerT = kR / kThreads > 0 ? kR / kThreads : 1;  // digits per thread in the digit scans
   constexpr int kPer = kRsItems;                 // items per lane
   constexpr int kWaveItems = 64 * kPer;          // contiguous items per wave
-  __shared__ uint32_t s_cnt[kThreads / 64][256];  // per-wave digit counts, then per-wave digit bases
-  __shared__ uint32_t s_off[256];                // block-local first slot of each digit
-  __shared__ uint32_t s_gbase[256];              // global first slot of each digit for this block
+  __shared__ uint32_t s_cnt[kThreads / 64][kR];  // per-wave digit counts, then per-wave digit bases
+  __shared__ uint32_t s_off[kR];                 // block-local first slot of each digit
+  __shared__ uint32_t s_gbase[kR];               // global first slot of each digit for this block
   __shared__ uint32_t s_k[kRsBlock];
   __shared__ uint32_t s_v[kRsBlock];
   __shared__ uint32_t lds[5];
@@ -246,15 +259,32 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint32_t* __restr
   const int radix = 1 << bits;
   const uint32_t mask = static_cast<uint32_t>(radix - 1);
   const uint64_t lt = (1ull << lane) - 1ull;
-  uint32_t digit_base;
+  // digit_base[j]: first global slot of digit tid * kPerT + j
+  uint32_t digit_base[kPerT];
   {
-    const uint32_t t = tid < radix ? rowtot[tid] : 0u;
+    uint32_t t[kPerT], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kPerT; ++j) {
+      const int d = tid * kPerT + j;
+      t[j] = d < radix ? rowtot[d] : 0u;
+      sum += t[j];
+    }
     uint32_t tot;
-    digit_base = block_excl_scan<uint32_t>(t, lds, tot);
+    uint32_t run = block_excl_scan<uint32_t>(sum, lds, tot);
+#pragma unroll
+    for (int j = 0; j < kPerT; ++j) {
+      digit_base[j] = run;
+      run += t[j];
+    }
   }
   for (int64_t lb = blockIdx.x; lb < nb; lb += gridDim.x) {
-    for (int w = 0; w < kThreads / 64; ++w) s_cnt[w][tid] = 0;
-    if (tid < radix) s_gbase[tid] = digit_base + hist[tid * cols + lb];
+    for (int w = 0; w < kThreads / 64; ++w)
+      for (int d = tid; d < radix; d += kThreads) s_cnt[w][d] = 0;
+#pragma unroll
+    for (int j = 0; j < kPerT; ++j) {
+      const int d = tid * kPerT + j;
+      if (d < radix) s_gbase[d] = digit_base[j] + hist[d * cols + lb];
+    }
     __syncthreads();
     // phase 1: wave-local stable ranks
     const int64_t wbase = lb * kRsBlock + static_cast<int64_t>(wid) * kWaveItems;
@@ -283,20 +313,31 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint32_t* __restr
     __syncthreads();
     // phase 2: per digit, combine the waves and scan over digits
     {
-      uint32_t c[kThreads / 64], tot = 0;
-      for (int w = 0; w < kThreads / 64; ++w) {
-        c[w] = tid < radix ? s_cnt[w][tid] : 0u;
-        tot += c[w];
+      uint32_t c[kPerT][kThreads / 64], tot[kPerT], sum = 0;
+#pragma unroll
+      for (int j = 0; j < kPerT; ++j) {
+        const int d = tid * kPerT + j;
+        tot[j] = 0;
+        for (int w = 0; w < kThreads / 64; ++w) {
+          c[j][w] = d < radix ? s_cnt[w][d] : 0u;
+          tot[j] += c[j][w];
+        }
+        sum += tot[j];
       }
       uint32_t all;
-      const uint32_t off = block_excl_scan<uint32_t>(tot, lds, all);
-      if (tid < radix) {
-        s_off[tid] = off;
-        uint32_t run = off;
-        for (int w = 0; w < kThreads / 64; ++w) {
-          s_cnt[w][tid] = run;
-          run += c[w];
+      uint32_t off = block_excl_scan<uint32_t>(sum, lds, all);
+#pragma unroll
+      for (int j = 0; j < kPerT; ++j) {
+        const int d = tid * kPerT + j;
+        if (d < radix) {
+          s_off[d] = off;
+          uint32_t run = off;
+          for (int w = 0; w < kThreads / 64; ++w) {
+            s_cnt[w][d] = run;
+            run += c[j][w];
+          }
         }
+        off += tot[j];
       }
     }
     __syncthreads();
@@ -680,15 +721,18 @@ BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity) {
   while ((int64_t{1} << bits) < tiles) ++bits;
   p.tile_bits = bits;
   p.tile_passes = static_cast<int>(cdiv(bits, 8));
-  p.hist_cols = std::max<int64_t>(1, std::max(cdiv(n, kRsBlock), cdiv(capacity, kRsBlock)));
+  p.hist_cols = std::max<int64_t>(1, cdiv(capacity, kRsBlock));
+  p.hist_cols_depth = std::max<int64_t>(1, cdiv(n, kRsBlock));
   size_t off = 0;
   p.off_vis_keys = off; off = align256(off + sizeof(uint32_t) * 2 * std::max<int64_t>(n, 1));
   p.off_vis_vals = off; off = align256(off + sizeof(uint32_t) * 2 * std::max<int64_t>(n, 1));
   p.off_offsets = off;  off = align256(off + sizeof(uint32_t) * std::max<int64_t>(n, 1));
   const int64_t nparts = std::max<int64_t>(1, cdiv(n, kThreads));  // blocks of the row kernels (the most)
   p.off_partials = off; off = align256(off + sizeof(unsigned long long) * (nparts + 1));
-  p.off_hist = off;     off = align256(off + sizeof(uint32_t) * 256 * p.hist_cols);
-  p.off_rowtot = off;   off = align256(off + sizeof(uint32_t) * 256);
+  p.off_hist = off;
+  off = align256(off + sizeof(uint32_t) * std::max<int64_t>((int64_t{1} << kDepthBits) * p.hist_cols_depth,
+                                                            256 * p.hist_cols));
+  p.off_rowtot = off;   off = align256(off + sizeof(uint32_t) * (1 << kDepthBits));
   p.off_partials2 = off;
   off = align256(off + sizeof(unsigned long long) * (std::max<int64_t>(1, cdiv(capacity, kThreads)) + 1));
   p.off_rows = off;     off = align256(off + sizeof(uint4) * std::max<int64_t>(capacity, 1));
@@ -700,14 +744,17 @@ BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity) {
 // One stable LSD pass of `bits` bits at `shift` from (kin, vin) to (kout, vout).
 constexpr int64_t kMaxGrid = 8192;  // physical blocks of a grid-stride pass
 
+template <int kMaxBits>
 static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, int64_t n_grid, int shift, int bits, uint32_t* hist,
                              int64_t cols, uint32_t* rowtot, hipStream_t s) {
+  if (bits < 1 || bits > kMaxBits) return hipErrorInvalidValue;
   const unsigned nb = static_cast<unsigned>(std::min(kMaxGrid, std::max<int64_t>(1, cdiv(n_grid, kRsBlock))));
-  hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, kin, n_dev, n_grid, shift, bits, hist, cols);
+  hipLaunchKernelGGL(k_rs_hist<kMaxBits>, dim3(nb), dim3(kThreads), 0, s, kin, n_dev, n_grid, shift, bits, hist,
+                     cols);
   hipLaunchKernelGGL(k_rs_rowscan, dim3(1u << bits), dim3(kThreads), 0, s, hist, cols, n_dev, n_grid, rowtot);
-  hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_grid, shift,
-                     bits, hist, cols, rowtot);
+  hipLaunchKernelGGL(k_rs_scatter<kMaxBits>, dim3(nb), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_grid,
+                     shift, bits, hist, cols, rowtot);
   return hipGetLastError();
 }
 
@@ -733,20 +780,24 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, static_cast<const uint32_t*>(nullptr),
                        vs.live, n, kScanBlock, counters + 1, int64_t{-1}, static_cast<uint32_t*>(nullptr),
                        static_cast<uint32_t*>(nullptr), static_cast<const uint32_t*>(nullptr));
+    // into buffer 1 when the depth passes are odd in number, so they end in buffer 0
+    const int64_t start = (kDepthPasses & 1) * nvis_stride;
     hipLaunchKernelGGL(k_vis_compact, dim3(nb), dim3(kThreads), 0, s, geom.tiles, geom.depth, vs.live, n, partials,
-                       vkeys, vvals);
+                       vkeys + start, vvals + start);
     PVG_HIP(hipGetLastError());
   }
-  // depth sort of the visible Gaussians: 4 passes of 8 bits, ends in buffer 0
+  // depth sort of the visible Gaussians: kDepthPasses LSD passes, ending in buffer 0
   if (n > 0) {
     StageScope sc(PVG_STAGE_DEPTH_SORT, s);
-    for (int pass = 0; pass < 4; ++pass) {
-      const int src = pass & 1, dst = src ^ 1;
-      PVG_HIP(radix_pass(vkeys + src * nvis_stride, vvals + src * nvis_stride, vkeys + dst * nvis_stride,
-                         vvals + dst * nvis_stride, counters + 1, n, 8 * pass, 8, hist, plan.hist_cols, rowtot, s));
+    for (int pass = 0; pass < kDepthPasses; ++pass) {
+      const int src = ((kDepthPasses & 1) + pass) & 1, dst = src ^ 1;
+      const int shift = kDepthBits * pass;
+      PVG_HIP(radix_pass<kDepthBits>(vkeys + src * nvis_stride, vvals + src * nvis_stride, vkeys + dst * nvis_stride,
+                                     vvals + dst * nvis_stride, counters + 1, n, shift,
+                                     std::min(kDepthBits, 32 - shift), hist, plan.hist_cols_depth, rowtot, s));
     }
   }
-  const uint32_t* order = vvals;  // buffer 0 after an even number of passes
+  const uint32_t* order = vvals;  // buffer 0 after the depth passes
   const bool cull = bins->tile_cull != 0;
   unsigned long long* partials2 = reinterpret_cast<unsigned long long*>(base + plan.off_partials2);
   uint4* rows = reinterpret_cast<uint4*>(base + plan.off_rows);
@@ -829,8 +880,8 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
       const int src = (start + pass) & 1, dst = src ^ 1;
       const int shift = per * pass;
       const int bits = std::min(per, plan.tile_bits - shift);
-      PVG_HIP(radix_pass(bins->keys + src * cap, bins->vals + src * cap, bins->keys + dst * cap,
-                         bins->vals + dst * cap, counters, m_grid, shift, bits, hist, plan.hist_cols, rowtot, s));
+      PVG_HIP(radix_pass<8>(bins->keys + src * cap, bins->vals + src * cap, bins->keys + dst * cap,
+                            bins->vals + dst * cap, counters, m_grid, shift, bits, hist, plan.hist_cols, rowtot, s));
     }
   }
   {

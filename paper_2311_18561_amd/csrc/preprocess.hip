@@ -1,24 +1,32 @@
 // Per-Gaussian stage (forward and adjoint) of the PVG rasterizer on gfx950.
 //
-// Forward: one thread per (view, Gaussian): temporal state (Sec. 3.2,
-// Eqs. (6)-(7)), flow translation (Sec. 3.4, Eqs. (10), (12)), EWA projection
-// (Sec. 3.1, Eq. (2)), radius, tile rectangle and SH colour.  Parameter reads
-// are structure-of-arrays, so a wave reads 256 contiguous bytes per field; the
-// SH coefficients (up to 192 B per Gaussian) are only read for visible ones.
+// Forward: temporal state (Sec. 3.2, Eqs. (6)-(7)), flow translation
+// (Sec. 3.4, Eqs. (10), (12)), EWA projection (Sec. 3.1, Eq. (2)), radius,
+// tile rectangle and SH colour.  Parameter reads are structure-of-arrays, so
+// a wave reads 256 contiguous bytes per field; the SH coefficients (up to
+// 192 B per Gaussian) are only read for visible ones.  For several views of
+// one set of Gaussians a thread takes one Gaussian through every view: the
+// time state (two double-precision transcendentals) is formed once per
+// distinct render time and the 3D covariance once, then each view's
+// projection.
 //
 // Adjoint: one thread per Gaussian recomputes the forward state of each view
-// (bit-identical, so every branch decision is the forward's), applies the
+// (bit-identical, so every branch decision is the forward's) and applies the
 // chain rule from that view's screen-space gradient (2D mean, conic,
-// opacity, colour) back to {mu, q, s, o, c, tau, beta, v} and l, sums over
-// the views in registers and writes each gradient entry once.
+// opacity, colour) to the view's translated mean, covariance and opacity.
+// Those are summed over the views in registers; the covariance's chain to
+// (s, q) is then taken once, and the temporal chain to {mu, v, tau, beta, l}
+// and o once per distinct render time, since each is linear in the sums.
 #include "pvg_math.hpp"
 
 namespace pvg {
 
-// The projected record of Gaussian i of view v at slot gi of geom.
-__device__ __forceinline__ void preprocess_one(const View& v, int64_t i, const Geom& geom, int64_t gi) {
+// The projected record of Gaussian i of view v at slot gi of geom, from its
+// time state and covariance.
+__device__ __forceinline__ void preprocess_view(const View& v, int64_t i, GaussTime& G, GaussCov& C,
+                                                const Geom& geom, int64_t gi) {
   Proj P;
-  const bool vis = project(v, i, P, true);
+  const bool vis = project_view(v, i, G, C, P, true);
   geom.depth[gi] = P.p[2];
   if (vis) {
     reinterpret_cast<float2*>(geom.xy)[gi] = make_float2(P.x, P.y);
@@ -50,19 +58,31 @@ __global__ void __launch_bounds__(256) k_preprocess(ViewSet vs, Geom geom, unsig
   const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (gi >= live_gauss(vs)) return;
   const View& v = view_at(vs, view_of_gauss(vs, gi));
-  preprocess_one(v, gi - v.geom_off, geom, gi);
+  const int64_t i = gi - v.geom_off;
+  GaussTime G;
+  GaussCov C;
+  C.ready = false;
+  gauss_time(v.s, i, v.t, G);
+  preprocess_view(v, i, G, C, geom, gi);
   (void)dummy;
 }
 
-// Several views of one set of Gaussians: block b projects the 256 Gaussians
-// of chunk b / nv into view b % nv, so the views of a chunk are dispatched
-// back to back and its parameters come from HBM once (the other views' reads
-// hit the caches); each view's record is the single-view one.
+// Several views of one set of Gaussians: thread i takes Gaussian i through
+// every view of the pass, forming its time state once per distinct render
+// time and its covariance once; each view's record is the single-view one
+// (the same operations on the same values).
 __global__ void __launch_bounds__(256) k_preprocess_views(PreViews pk) {
-  const int32_t k = static_cast<int32_t>(blockIdx.x % static_cast<uint32_t>(pk.nv));
-  const int64_t i = static_cast<int64_t>(blockIdx.x / static_cast<uint32_t>(pk.nv)) * 256 + threadIdx.x;
-  if (i >= pk.views[0].s.n) return;
-  preprocess_one(pk.views[k], i, pk.geoms[k], i);
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const Scene& s = pk.views[0].s;
+  if (i >= s.n) return;
+  GaussTime G;
+  GaussCov C;
+  C.ready = false;
+  gauss_time(s, i, pk.views[0].t, G);
+  for (int32_t k = 0; k < pk.nv; ++k) {
+    if (pk.views[k].t != G.t) gauss_time(s, i, pk.views[k].t, G);
+    preprocess_view(pk.views[k], i, G, C, pk.geoms[k], i);
+  }
 }
 
 // Gradient entries of one Gaussian other than its SH coefficients.
@@ -70,20 +90,44 @@ struct GeoGrad {
   float mu[3], scale[3], rot[4], vel[3], op, l, tau, beta;
 };
 
-// One view's chain rule for everything but dL/dsh, added into acc.  g is the
-// view's screen-space gradient of the Gaussian: d(mean x, y), d(conic A, B, C),
-// d(opacity), d(rgb), d(depth); on return g[6..8] holds d(rgb) with clamped channels
-// zeroed and g[9..11] the view direction, which is all dL/dsh needs.  rgb is
-// the forward's colour of the Gaussian, where a clamped channel is -0.
-__device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const Proj& P, const float* rgb, float* g,
-                                                 GeoGrad& acc, bool feature) {
+// Per-Gaussian sums of the views' gradients with respect to the quantities
+// the views share: the covariance Sigma, and per render time the translated
+// means (split by flow mode: plain, translated by v_bar dt, translated by
+// v dt) and the decayed opacity; plus the blended velocity and staticness.
+struct ViewSums {
+  float dSig[6];        // d Sigma, upper triangle (00, 01, 02, 11, 12, 22)
+  float dmr[3];         // sum over the views of dL/d(translated mean)
+  float dmr_dt_bar[3];  // sum of dt dL/d(mean) over the views translated by v_bar dt
+  float dmr_dt_raw[3];  // the same over the views translated by v dt
+  float dop;            // sum of dL/d o~(t)
+  float dvb[3], drho;   // blended v~ = v exp(-beta / (2 l)) and rho = beta / l
+};
+
+__device__ __forceinline__ void clear_time_sums(ViewSums& S) {
+  for (int c = 0; c < 3; ++c) { S.dmr[c] = 0.0f; S.dmr_dt_bar[c] = 0.0f; S.dmr_dt_raw[c] = 0.0f; }
+  S.dop = 0.0f;
+}
+
+// One view's chain rule from its screen-space gradient g of the Gaussian:
+// d(mean x, y), d(conic A, B, C), d(opacity), d(rgb), and the blended
+// channels' d(z, v~, rho), to the view's translated mean, covariance and
+// opacity, added into S.  On return g[6..8] holds d(rgb) with clamped
+// channels zeroed and g[9..11] the view direction, which is all dL/dsh
+// needs.  rgb is the forward's colour of the Gaussian, where a clamped
+// channel is -0.
+__device__ __forceinline__ void adjoint_view(const View& v, int64_t i, const Proj& P, const GaussCov& C,
+                                             const float* rgb, float* g, ViewSums& S, bool feature) {
   const Scene& s = v.s;
   const int64_t n = s.n;
   const int K = (s.degree + 1) * (s.degree + 1);
   const float dmx = g[0], dmy = g[1], dA = g[2], dB = g[3], dC = g[4], dop = g[5];
   // the blended channels' gradients (0 without them), read before slots 9.. are reused:
   // camera depth z, mean velocity v~ and staticness rho
-  const float dz = g[9], dvb0 = g[10], dvb1 = g[11], dvb2 = g[12], drho = g[13];
+  const float dz = g[9];
+  S.dvb[0] += g[10];
+  S.dvb[1] += g[11];
+  S.dvb[2] += g[12];
+  S.drho += g[13];
   float dmr[3] = {0.0f, 0.0f, 0.0f};
 
   // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 1/2), dir = u / |u|; its
@@ -122,18 +166,22 @@ __device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const
   const float hb = 0.5f * db;
   const float* T0 = P.T2;
   const float* T1 = P.T2 + 3;
-  float dSig[9];
-  for (int r = 0; r < 3; ++r)
-    for (int q = 0; q < 3; ++q)
-      dSig[3 * r + q] = da * T0[r] * T0[q] + hb * (T0[r] * T1[q] + T1[r] * T0[q]) + dc * T1[r] * T1[q];
+  {
+    constexpr int kr[6] = {0, 0, 0, 1, 1, 2}, kq[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int r = kr[e], q = kq[e];
+      S.dSig[e] += da * T0[r] * T0[q] + hb * (T0[r] * T1[q] + T1[r] * T0[q]) + dc * T1[r] * T1[q];
+    }
+  }
   float V0[3], V1[3], dT0[3], dT1[3];
   for (int q = 0; q < 3; ++q) {
     V0[q] = da * T0[q] + hb * T1[q];
     V1[q] = hb * T0[q] + dc * T1[q];
   }
   for (int q = 0; q < 3; ++q) {
-    dT0[q] = 2.0f * (V0[0] * P.Sig[q] + V0[1] * P.Sig[3 + q] + V0[2] * P.Sig[6 + q]);
-    dT1[q] = 2.0f * (V1[0] * P.Sig[q] + V1[1] * P.Sig[3 + q] + V1[2] * P.Sig[6 + q]);
+    dT0[q] = 2.0f * (V0[0] * C.Sig[q] + V0[1] * C.Sig[3 + q] + V0[2] * C.Sig[6 + q]);
+    dT1[q] = 2.0f * (V1[0] * C.Sig[q] + V1[1] * C.Sig[3 + q] + V1[2] * C.Sig[6 + q]);
   }
   const float* W = v.R;
   float dJ00 = 0.0f, dJ02 = 0.0f, dJ11 = 0.0f, dJ12 = 0.0f;
@@ -166,85 +214,100 @@ __device__ __forceinline__ void adjoint_geometry(const View& v, int64_t i, const
   dp[2] += -v.fx * px * iz2 * dmx - v.fy * py * iz2 * dmy;
   for (int q = 0; q < 3; ++q) dmr[q] += W[q] * dp[0] + W[3 + q] * dp[1] + W[6 + q] * dp[2];
 
-  // Sigma = M M^T, M = R(q^) diag(s)
+  // the translated mean mr = mu~(t) + v_bar dt (mode 0) or + v dt (mode 1)
+  for (int q = 0; q < 3; ++q) S.dmr[q] += dmr[q];
+  if (v.dt != 0.0f) {
+    float* dst = v.mode == 0 ? S.dmr_dt_bar : S.dmr_dt_raw;
+    for (int q = 0; q < 3; ++q) dst[q] += v.dt * dmr[q];
+  }
+  S.dop += dop;
+}
+
+// Sigma = M M^T, M = R(q^) diag(s): the summed d Sigma to d s and d q.
+__device__ __forceinline__ void adjoint_cov(const GaussCov& C, const float dS[6], GeoGrad& acc) {
+  const float dSig[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
   float dR[9];
   for (int q = 0; q < 3; ++q) {
     float ds = 0.0f;
     for (int r = 0; r < 3; ++r) {
-      const float dM = 2.0f * (dSig[3 * r] * P.M[q] + dSig[3 * r + 1] * P.M[3 + q] + dSig[3 * r + 2] * P.M[6 + q]);
-      ds += dM * P.Rq[3 * r + q];
-      dR[3 * r + q] = dM * P.sc[q];
+      const float dM = 2.0f * (dSig[3 * r] * C.M[q] + dSig[3 * r + 1] * C.M[3 + q] + dSig[3 * r + 2] * C.M[6 + q]);
+      ds += dM * C.Rq[3 * r + q];
+      dR[3 * r + q] = dM * C.sc[q];
     }
     acc.scale[q] += ds;
   }
-  {
-    const float w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
-    float dq[4];
-    dq[0] = 2.0f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-    dq[1] = 2.0f * (y * dR[1] + z * dR[2] + y * dR[3] - w * dR[5] + z * dR[6] + w * dR[7]) -
-            4.0f * x * (dR[4] + dR[8]);
-    dq[2] = 2.0f * (x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7]) -
-            4.0f * y * (dR[0] + dR[8]);
-    dq[3] = 2.0f * (-w * dR[1] + x * dR[2] + w * dR[3] + y * dR[5] + x * dR[6] + y * dR[7]) -
-            4.0f * z * (dR[0] + dR[4]);
-    const float qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-    for (int q = 0; q < 4; ++q) acc.rot[q] += (dq[q] - P.qn[q] * qd) / P.qnorm;
-  }
+  const float w = C.qn[0], x = C.qn[1], y = C.qn[2], z = C.qn[3];
+  float dq[4];
+  dq[0] = 2.0f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  dq[1] = 2.0f * (y * dR[1] + z * dR[2] + y * dR[3] - w * dR[5] + z * dR[6] + w * dR[7]) -
+          4.0f * x * (dR[4] + dR[8]);
+  dq[2] = 2.0f * (x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7]) -
+          4.0f * y * (dR[0] + dR[8]);
+  dq[3] = 2.0f * (-w * dR[1] + x * dR[2] + w * dR[3] + y * dR[5] + x * dR[6] + y * dR[7]) -
+          4.0f * z * (dR[0] + dR[4]);
+  const float qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+  for (int q = 0; q < 4; ++q) acc.rot[q] += (dq[q] - C.qn[q] * qd) / C.qnorm;
+}
 
-  // temporal model
-  const float l = s.period[i], tau = s.tau[i], beta = s.beta[i];
-  float vel[3];
-  for (int q = 0; q < 3; ++q) vel[q] = s.vel[q * n + i];
-  const float vg = vel[0] * dmr[0] + vel[1] * dmr[1] + vel[2] * dmr[2];
-  float dv[3] = {0.0f, 0.0f, 0.0f};
+// The temporal chain of the views at one render time t (Eqs. (6), (7), (10),
+// (12)), from the time sums of S, into acc.
+__device__ __forceinline__ void adjoint_time(const Scene& s, int64_t i, const GaussTime& G, const ViewSums& S,
+                                             GeoGrad& acc) {
+  const float l = G.l, beta = G.beta, tau = s.tau[i];
+  const float* vel = G.vel;
   float dl = 0.0f, dtau = 0.0f, dbeta = 0.0f;
-  if (v.dt != 0.0f) {
-    if (v.mode == 0) {
-      const float e = expf(-0.5f * (beta / l));
-      for (int q = 0; q < 3; ++q) dv[q] += e * v.dt * dmr[q];
-      dbeta += vg * v.dt * e * (-0.5f / l);
-      dl += vg * v.dt * e * (0.5f * beta / (l * l));
-    } else {
-      for (int q = 0; q < 3; ++q) dv[q] += v.dt * dmr[q];
-    }
+  // flow translation: mr = mu~ + v e dt (mode 0, e = exp(-beta / (2 l))) or + v dt
+  {
+    const float e = expf(-0.5f * (beta / l));
+    const float vg = vel[0] * S.dmr_dt_bar[0] + vel[1] * S.dmr_dt_bar[1] + vel[2] * S.dmr_dt_bar[2];
+    for (int q = 0; q < 3; ++q) acc.vel[q] += e * S.dmr_dt_bar[q] + S.dmr_dt_raw[q];
+    dbeta += vg * e * (-0.5f / l);
+    dl += vg * e * (0.5f * beta / (l * l));
   }
-  const float d = v.t - tau;
+  // vibration: mu~ = mu + (l / 2 pi) sin(phi) v, phi = 2 pi (t - tau) / l
+  const float vg = vel[0] * S.dmr[0] + vel[1] * S.dmr[1] + vel[2] * S.dmr[2];
+  const float d = G.t - tau;
   const float phi = (kTwoPi * d) / l;
   float sphi, cphi;
   sincosf(phi, &sphi, &cphi);
   const float k = (l / kTwoPi) * sphi;
   for (int q = 0; q < 3; ++q) {
-    acc.mu[q] += dmr[q];
-    acc.vel[q] += dv[q] + k * dmr[q];
+    acc.mu[q] += S.dmr[q];
+    acc.vel[q] += k * S.dmr[q];
   }
   dtau += -cphi * vg;
   dl += (sphi / kTwoPi - (d / l) * cphi) * vg;
-  {  // v~ = v e with e = exp(-beta / (2 l)), rho = beta / l
-    const float e = expf(-0.5f * (beta / l));
-    const float vdot = vel[0] * dvb0 + vel[1] * dvb1 + vel[2] * dvb2;
-    acc.vel[0] += e * dvb0;
-    acc.vel[1] += e * dvb1;
-    acc.vel[2] += e * dvb2;
-    dbeta += vdot * e * (-0.5f / l) + drho / l;
-    dl += vdot * e * (0.5f * beta / (l * l)) - drho * beta / (l * l);
-  }
+  // opacity decay: o~ = o exp(-(t - tau)^2 / (2 beta^2))
   const float qb = d / beta;
   const float eo = expf(-0.5f * (qb * qb));
-  acc.op += eo * dop;
-  dtau += dop * P.op * d / (beta * beta);
-  dbeta += dop * P.op * d * d / (beta * beta * beta);
+  acc.op += eo * S.dop;
+  dtau += S.dop * G.op * d / (beta * beta);
+  dbeta += S.dop * G.op * d * d / (beta * beta * beta);
   acc.l += dl;
   acc.tau += dtau;
   acc.beta += dbeta;
 }
 
+// The blended velocity and staticness maps' chain (time-independent):
+// v~ = v e, e = exp(-beta / (2 l)); rho = beta / l.
+__device__ __forceinline__ void adjoint_features(const GaussTime& G, const ViewSums& S, GeoGrad& acc) {
+  const float l = G.l, beta = G.beta;
+  const float e = expf(-0.5f * (beta / l));
+  const float vdot = G.vel[0] * S.dvb[0] + G.vel[1] * S.dvb[1] + G.vel[2] * S.dvb[2];
+  for (int q = 0; q < 3; ++q) acc.vel[q] += e * S.dvb[q];
+  acc.beta += vdot * e * (-0.5f / l) + S.drho / l;
+  acc.l += vdot * e * (0.5f * beta / (l * l)) - S.drho * beta / (l * l);
+}
+
 // Adjoint of the per-Gaussian stage for up to kMaxBwdViews views of one set
-// of Gaussians: each Gaussian's gradient is summed over the views in
-// registers (the SH part in a second loop over the views, to bound register
-// use) and written, or added, once.  A Gaussian no view sees gets zeros
-// (accumulate = 0) or is left alone.
-// 3 waves per SIMD: the compiler fits the view loop in 168 registers without spilling
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_preprocess_bwd(BwdViews pk, pvg_gaussians_grad grad, int accumulate) {
+// of Gaussians at one render time (the host splits passes where t changes):
+// each Gaussian's gradient is summed over the views in registers (the SH part
+// in a second loop over the views, to bound register use) and written, or
+// added, once.  A Gaussian no view sees gets zeros (accumulate = 0) or is
+// left alone.
+// 3 waves per SIMD: the view loop fits in 168 registers without spilling
+__global__ void __launch_bounds__(256) k_preprocess_bwd(BwdViews pk, pvg_gaussians_grad grad,
+                                                                                             int accumulate) {
   const Scene& s = pk.views[0].s;
   const int64_t n = s.n;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
@@ -263,6 +326,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     }
     return;
   }
+  GaussTime G;
+  gauss_time(s, i, pk.views[0].t, G);
+  GaussCov C;
+  C.ready = false;
+  ViewSums S;
+  for (int e = 0; e < 6; ++e) S.dSig[e] = 0.0f;
+  for (int c = 0; c < 3; ++c) S.dvb[c] = 0.0f;
+  S.drho = 0.0f;
+  clear_time_sums(S);
+  float dnorm = 0.0f, dcount = 0.0f;  // view-space gradient statistics of the adaptive control
+  for (int v = 0; v < pk.nv; ++v) {
+    if (pk.radius[v][i] <= 0) continue;
+    const View& vw = pk.views[v];
+    float* g = pk.g2d[v] + kG2DStride * i;
+    if (grad.densify_grad) {  // |dL / d(mean in NDC)|, NDC = 2 (pixel / size) - 1
+      const float gx = g[0] * (0.5f * static_cast<float>(vw.W));
+      const float gy = g[1] * (0.5f * static_cast<float>(vw.H));
+      dnorm += sqrtf(gx * gx + gy * gy);
+      dcount += 1.0f;
+    }
+    Proj P;
+    project_view(vw, i, G, C, P, false);
+    view_direction(vw, P);
+    adjoint_view(vw, i, P, C, pk.rgb[v] + 3 * i, g, S, pk.feat_grad[v] != nullptr);
+  }
   GeoGrad acc = {};
   if (accumulate) {  // start from the previous values
     for (int q = 0; q < 3; ++q) {
@@ -276,22 +364,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     acc.tau = grad.tau[i];
     acc.beta = grad.beta[i];
   }
-  float dnorm = 0.0f, dcount = 0.0f;  // view-space gradient statistics of the adaptive control
-  for (int v = 0; v < pk.nv; ++v) {
-    if (pk.radius[v][i] <= 0) continue;
-    if (grad.densify_grad) {  // |dL / d(mean in NDC)|, NDC = 2 (pixel / size) - 1
-      const float* g = pk.g2d[v] + kG2DStride * i;
-      const float gx = g[0] * (0.5f * static_cast<float>(pk.views[v].W));
-      const float gy = g[1] * (0.5f * static_cast<float>(pk.views[v].H));
-      dnorm += sqrtf(gx * gx + gy * gy);
-      dcount += 1.0f;
-    }
-    Proj P;
-    project(pk.views[v], i, P, false);
-    view_direction(pk.views[v], P);
-    adjoint_geometry(pk.views[v], i, P, pk.rgb[v] + 3 * i, pk.g2d[v] + kG2DStride * i, acc,
-                     pk.feat_grad[v] != nullptr);
-  }
+  adjoint_time(s, i, G, S, acc);
+  gauss_cov(s, i, C);  // formed again rather than held through the view loop
+  adjoint_cov(C, S.dSig, acc);
+  adjoint_features(G, S, acc);
   if (grad.densify_grad) {
     grad.densify_grad[i] += dnorm;
     grad.densify_count[i] += dcount;
@@ -353,7 +429,7 @@ hipError_t launch_preprocess_views(const PreViews& pk, hipStream_t s) {
   const int64_t n = pk.views[0].s.n;
   if (n == 0 || pk.nv <= 0) return hipSuccess;
   StageScope scope(PVG_STAGE_PREPROCESS, s);
-  hipLaunchKernelGGL(k_preprocess_views, dim3(grid_for(n, 256) * static_cast<unsigned>(pk.nv)), dim3(256), 0, s, pk);
+  hipLaunchKernelGGL(k_preprocess_views, dim3(grid_for(n, 256)), dim3(256), 0, s, pk);
   return hipGetLastError();
 }
 

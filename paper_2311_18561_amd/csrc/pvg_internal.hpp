@@ -138,9 +138,9 @@ unsigned long long* profile_work_counter(int stage);  // device counter, or null
 
 // kernel launchers (stream-ordered, no host sync)
 hipError_t launch_preprocess(const ViewSet& vs, const Geom& geom, hipStream_t s);
-// Views of one set of Gaussians for the per-Gaussian adjoint (same scene in
-// every view): each view's camera and frame, its radii (visibility) and its
-// screen-space gradient g2d [n][kG2DStride].
+// Views of one set of Gaussians for the per-Gaussian adjoint (same scene and
+// the same render time t in every view): each view's camera and frame, its
+// radii (visibility) and its screen-space gradient g2d [n][kG2DStride].
 constexpr int kMaxBwdViews = 8;
 struct BwdViews {
   int32_t nv;
@@ -243,7 +243,8 @@ struct BinPlan {
   // scratch carve-up (bytes offsets into tmp)
   size_t off_vis_keys, off_vis_vals, off_offsets, off_partials, off_hist, off_rowtot, off_partials2, off_rows,
       off_num_rows, total;
-  int64_t hist_cols;     // blocks per radix row (max over the passes)
+  int64_t hist_cols;       // blocks per radix row of the tile passes
+  int64_t hist_cols_depth; // blocks per radix row of the depth passes
 };
 BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity);
 int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp, const BinPlan& plan,

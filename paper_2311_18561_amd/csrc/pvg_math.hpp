@@ -107,8 +107,6 @@ struct Proj {
   float mr[3];      // translated mean (Eq. (12)) or mu~(t) (Eq. (6))
   float op;         // o~(t) (Eq. (7))
   float p[3];       // camera-space point
-  float qn[4], qnorm, Rq[9], sc[3], M[9];
-  float Sig[9];     // 3D covariance (row-major, symmetric)
   float tx, ty, J00, J02, J11, J12, T2[6];
   float ca, cb, cc, det;  // dilated 2D covariance
   float A, B, C, x, y;
@@ -248,25 +246,86 @@ __device__ __forceinline__ void tile_bounds(int tx, int ty, int W, int H, float&
   Y1 = static_cast<float>(min(H, (ty + 1) * kTile) - 1);
 }
 
-// Temporal state (Eqs. (6), (7)) and flow translation (Eqs. (10), (12)).
-__device__ __forceinline__ void temporal_state(const View& v, int64_t i, float mr[3], float& op) {
-  const Scene& s = v.s;
+// The part of the per-Gaussian stage that depends on the time t but not on
+// the camera: the vibrating mean mu~(t) (Eq. (6)) and the decayed opacity
+// o~(t) (Eq. (7)), with the velocity and the flow factor exp(-beta / (2 l))
+// of Eq. (10) (evaluated on first use).  Views of one training step share t,
+// so a kernel that handles several views of a Gaussian forms this once.
+struct GaussTime {
+  float t;        // the time it was formed for
+  float mt[3];    // mu~(t)
+  float vel[3];
+  float op;       // o~(t)
+  float beta, l;
+  float ev;       // exp(-beta / (2 l)), or a negative value before its first use
+};
+
+__device__ __forceinline__ void gauss_time(const Scene& s, int64_t i, float t, GaussTime& G) {
   const int64_t n = s.n;
   const float l = s.period[i], tau = s.tau[i], beta = s.beta[i], o = s.opacity[i];
-  const float d = v.t - tau;
+  const float d = t - tau;
   const float phi = (kTwoPi * d) / l;
   const float k = (l / kTwoPi) * sin_cr(phi);
   const float q = d / beta;
-  op = o * exp_cr(-0.5f * (q * q));
-  float vel[3];
+  G.t = t;
+  G.op = o * exp_cr(-0.5f * (q * q));
   for (int c = 0; c < 3; ++c) {
-    vel[c] = s.vel[c * n + i];
-    mr[c] = s.mu[c * n + i] + k * vel[c];
+    G.vel[c] = s.vel[c * n + i];
+    G.mt[c] = s.mu[c * n + i] + k * G.vel[c];
   }
+  G.beta = beta;
+  G.l = l;
+  G.ev = -1.0f;
+}
+
+// Temporal state of one view (Eqs. (6), (7)) with its flow translation
+// (Eqs. (10), (12)): mr = mu~(t) + v_bar dt.
+__device__ __forceinline__ void view_mean(const View& v, GaussTime& G, float mr[3]) {
+  for (int c = 0; c < 3; ++c) mr[c] = G.mt[c];
   if (v.dt != 0.0f) {
-    const float ev = v.mode == 0 ? exp_cr(-0.5f * (beta / l)) : 1.0f;
-    for (int c = 0; c < 3; ++c) mr[c] = mr[c] + (vel[c] * ev) * v.dt;
+    float ev = 1.0f;
+    if (v.mode == 0) {
+      if (G.ev < 0.0f) G.ev = exp_cr(-0.5f * (G.beta / G.l));
+      ev = G.ev;
+    }
+    for (int c = 0; c < 3; ++c) mr[c] = mr[c] + (G.vel[c] * ev) * v.dt;
   }
+}
+
+// The camera-independent 3D covariance Sigma = R(q) S S^T R(q)^T of
+// Gaussian i, with the intermediate values the adjoint reuses.
+struct GaussCov {
+  float qn[4], qnorm, Rq[9], sc[3], M[9];
+  float Sig[9];  // row-major, symmetric
+  bool ready;    // formed (a view that culls the Gaussian at the near plane does not need it)
+};
+
+__device__ __forceinline__ void gauss_cov(const Scene& s, int64_t i, GaussCov& G) {
+  const int64_t n = s.n;
+  G.ready = true;
+  float q[4];
+  for (int c = 0; c < 4; ++c) q[c] = s.rot[c * n + i];
+  const float n2 = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
+  G.qnorm = sqrtf(n2);
+  for (int c = 0; c < 4; ++c) G.qn[c] = q[c] / G.qnorm;
+  {
+    const float w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
+    G.Rq[0] = 1.0f - 2.0f * (y * y + z * z);
+    G.Rq[1] = 2.0f * (x * y - w * z);
+    G.Rq[2] = 2.0f * (x * z + w * y);
+    G.Rq[3] = 2.0f * (x * y + w * z);
+    G.Rq[4] = 1.0f - 2.0f * (x * x + z * z);
+    G.Rq[5] = 2.0f * (y * z - w * x);
+    G.Rq[6] = 2.0f * (x * z - w * y);
+    G.Rq[7] = 2.0f * (y * z + w * x);
+    G.Rq[8] = 1.0f - 2.0f * (x * x + y * y);
+  }
+  for (int c = 0; c < 3; ++c) G.sc[c] = s.scale[c * n + i];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) G.M[3 * r + c] = G.Rq[3 * r + c] * G.sc[c];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      G.Sig[3 * r + c] = (G.M[3 * r] * G.M[3 * c] + G.M[3 * r + 1] * G.M[3 * c + 1]) + G.M[3 * r + 2] * G.M[3 * c + 2];
 }
 
 // Unit direction from the camera centre -R^T T to the (translated) mean.
@@ -279,43 +338,25 @@ __device__ __forceinline__ void view_direction(const View& v, Proj& P) {
   for (int c = 0; c < 3; ++c) P.dir[c] = u[c] / P.ulen;
 }
 
-// The per-Gaussian stage up to the tile rectangle; returns false for an
-// invisible Gaussian.  With `color` it also evaluates the clamped SH colour.
-__device__ __forceinline__ bool project(const View& v, int64_t i, Proj& P, bool color) {
+// The camera-dependent rest of the per-Gaussian stage, from the time state
+// and the covariance: view transform and near cull, EWA projection, conic,
+// radius and tile rectangle; returns false for an invisible Gaussian.  With
+// `color` it also evaluates the clamped SH colour.  P's covariance fields are
+// not filled (the caller holds them in C).
+__device__ __forceinline__ bool project_view(const View& v, int64_t i, GaussTime& G, GaussCov& C, Proj& P,
+                                             bool color) {
   const Scene& s = v.s;
   const int64_t n = s.n;
-  temporal_state(v, i, P.mr, P.op);
+  view_mean(v, G, P.mr);
+  P.op = G.op;
   const float* W = v.R;
   for (int r = 0; r < 3; ++r)
     P.p[r] = ((W[3 * r] * P.mr[0] + W[3 * r + 1] * P.mr[1]) + W[3 * r + 2] * P.mr[2]) + v.T[r];
   P.radius = 0;
   P.flags = 0;
   if (!(P.p[2] > v.znear)) return false;
-
-  // Sigma = R(q) S S^T R(q)^T
-  float q[4];
-  for (int c = 0; c < 4; ++c) q[c] = s.rot[c * n + i];
-  const float n2 = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
-  P.qnorm = sqrtf(n2);
-  for (int c = 0; c < 4; ++c) P.qn[c] = q[c] / P.qnorm;
-  {
-    const float w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
-    P.Rq[0] = 1.0f - 2.0f * (y * y + z * z);
-    P.Rq[1] = 2.0f * (x * y - w * z);
-    P.Rq[2] = 2.0f * (x * z + w * y);
-    P.Rq[3] = 2.0f * (x * y + w * z);
-    P.Rq[4] = 1.0f - 2.0f * (x * x + z * z);
-    P.Rq[5] = 2.0f * (y * z - w * x);
-    P.Rq[6] = 2.0f * (x * z - w * y);
-    P.Rq[7] = 2.0f * (y * z + w * x);
-    P.Rq[8] = 1.0f - 2.0f * (x * x + y * y);
-  }
-  for (int c = 0; c < 3; ++c) P.sc[c] = s.scale[c * n + i];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) P.M[3 * r + c] = P.Rq[3 * r + c] * P.sc[c];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c)
-      P.Sig[3 * r + c] = (P.M[3 * r] * P.M[3 * c] + P.M[3 * r + 1] * P.M[3 * c + 1]) + P.M[3 * r + 2] * P.M[3 * c + 2];
+  if (!C.ready) gauss_cov(s, i, C);
+  const float* Sig = C.Sig;
 
   // EWA (Eq. (2)) with the Jacobian at the guarded point
   const float px = P.p[0], py = P.p[1], pz = P.p[2];
@@ -340,7 +381,7 @@ __device__ __forceinline__ bool project(const View& v, int64_t i, Proj& P, bool 
   float U[6];
   for (int r = 0; r < 2; ++r)
     for (int c = 0; c < 3; ++c)
-      U[3 * r + c] = (P.T2[3 * r] * P.Sig[c] + P.T2[3 * r + 1] * P.Sig[3 + c]) + P.T2[3 * r + 2] * P.Sig[6 + c];
+      U[3 * r + c] = (P.T2[3 * r] * Sig[c] + P.T2[3 * r + 1] * Sig[3 + c]) + P.T2[3 * r + 2] * Sig[6 + c];
   const float s00 = (U[0] * P.T2[0] + U[1] * P.T2[1]) + U[2] * P.T2[2];
   const float s01 = (U[0] * P.T2[3] + U[1] * P.T2[4]) + U[2] * P.T2[5];
   const float s11 = (U[3] * P.T2[3] + U[4] * P.T2[4]) + U[5] * P.T2[5];
@@ -380,6 +421,15 @@ __device__ __forceinline__ bool project(const View& v, int64_t i, Proj& P, bool 
     }
   }
   return true;
+}
+
+// The whole per-Gaussian stage of Gaussian i in one view.
+__device__ __forceinline__ bool project(const View& v, int64_t i, Proj& P, bool color) {
+  GaussTime G;
+  GaussCov C;
+  C.ready = false;
+  gauss_time(v.s, i, v.t, G);
+  return project_view(v, i, G, C, P, color);
 }
 
 }  // namespace pvg

@@ -97,30 +97,25 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
-// e^x for the compositing loops: Cody and Waite's reduction x log2(e) = n + f
-// with n = rint(x log2(e)), where the product's rounding error is recovered
-// by an FMA and a second, low-order part of log2(e) (the constant split in
-// two floats), 2^f from the hardware base-2 exponential on |f| <= 1/2 + eps,
-// and the exponent n applied exactly by ldexp.  These are the operations of
-// the device library's expf, which adds range checks for overflow and
-// underflow; here the results are equal bit for bit on (-103, 0] and callers
-// discard every pair with x > 0, while below -103 the value is 0 or a
-// subnormal far under any alpha threshold.  |x| stays below 2^31 / log2(e)
-// for any finite pair exponent of a listed Gaussian (a conic entry is at most
-// 1 / 0.3 after the dilation, and offsets are bounded by the image).
-__device__ __forceinline__ float exp_blend(float x) {
-  constexpr float kL2eHi = 1.44269502162933349609375f;  // log2(e) rounded to float
-  constexpr float kL2eLo = 1.92596285e-08f;             // log2(e) - kL2eHi, rounded toward zero
-  const float ph = x * kL2eHi;
-  const float pl = fmaf(x, kL2eLo, fmaf(x, kL2eHi, -ph));
-  const float n = __builtin_rintf(ph);
-  return __builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f((ph - n) + pl), static_cast<int>(n));
+// The pair exponent in base 2.  With the conic (A, B, C) scaled once per
+// Gaussian into q = -log2(e) (A / 2, B, C / 2), the exponent of Eq. (3)'s
+// 2D Gaussian at offset (dx, dy) is power = ln 2 * p2 with
+//   p2 = q.x dx^2 + q.y dx dy + q.z dy^2 = (q.z dy + q.y dx) dy + q.x dx^2,
+// so alpha = o 2^p2 takes the hardware base-2 exponential directly.  A lane
+// forms c1 = q.y dx and c0 = q.x dx^2 once per Gaussian (its four pixels
+// share dx) and then two FMAs per pixel.  The rounding differs from the
+// natural-base form by a few ulps relative to the terms' magnitudes; a skip
+// or stop decision can then go the other way only where its exact value sits
+// within that of a threshold.  The forward and the adjoint share this
+// function, so they take every decision alike.
+constexpr float kLog2e = 1.44269504088896341f;
+
+__device__ __forceinline__ float4 pair_coefs(float A, float B, float C, float o) {
+  return make_float4(-0.5f * kLog2e * A, -kLog2e * B, -0.5f * kLog2e * C, o);
 }
 
-// G-exponent of a (pixel, Gaussian) pair; the exact arithmetic (and with it
-// every branch decision) is shared by the forward and the adjoint.
-__device__ __forceinline__ float pair_power(float dx, float dy, float A, float B, float C) {
-  return -0.5f * (A * (dx * dx) + C * (dy * dy)) - B * (dx * dy);
+__device__ __forceinline__ float pair_exp2(float qz, float c1, float c0, float dy) {
+  return fmaf(fmaf(qz, dy, c1), dy, c0);
 }
 
 constexpr int kPix = 4;  // pixels per lane
@@ -186,7 +181,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
     if (keep) {
       const int slot = __popcll(km & lt);
       s_xy[slot] = m;
-      s_co[slot] = co;
+      s_co[slot] = pair_coefs(co.x, co.y, co.z, co.w);
       s_rgb[slot] = c;
       if (kCh) {
         s_z[slot] = z;
@@ -203,13 +198,15 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
       const float gz = kCh ? s_z[j] : 0.0f;
       const float4 gv = kCh ? s_fv[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       const int pos = __float_as_int(cc.w);
+      const float dx = gm.x - fpx;
+      const float c1 = gc.y * dx, c0 = (gc.x * dx) * dx;
 #pragma unroll
       for (int k = 0; k < kPix; ++k) {
         if (kCount) evaluated += act[k] ? 1 : 0;
-        const float dx = gm.x - fpx, dy = gm.y - static_cast<float>(py0 + 4 * k);
-        const float power = pair_power(dx, dy, gc.x, gc.y, gc.z);
-        const float alpha = fminf(kAlphaMax, gc.w * exp_blend(power));
-        const bool ok = act[k] && !(power > 0.0f) && !(alpha < kAlphaMin);
+        const float dy = gm.y - static_cast<float>(py0 + 4 * k);
+        const float p2 = pair_exp2(gc.z, c1, c0, dy);
+        const float alpha = fminf(kAlphaMax, gc.w * __builtin_amdgcn_exp2f(p2));
+        const bool ok = act[k] && !(p2 > 0.0f) && !(alpha < kAlphaMin);
         const float Tn = T[k] * (1.0f - alpha);
         const bool stop = ok && Tn < kTMin;
         const bool use = ok && !stop;
@@ -271,14 +268,16 @@ template <bool kCount, bool kCulled, bool kCh>
 __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists lists, float* rec,
                                                    uint8_t* vis, unsigned long long* pair_counter) {
   // The gradient arithmetic may fuse multiply-adds.  Every branch decision
-  // (exponent sign, alpha thresholds) comes from pair_power and single
-  // products, which stay unfused, so the adjoint takes the forward's.
+  // (exponent sign, alpha thresholds) comes from pair_coefs, pair_exp2 (its
+  // FMAs explicit) and single products, which fuse with nothing, so the
+  // adjoint takes the forward's.
 #pragma clang fp contract(fast)
   const uint32_t* __restrict__ vals = lists.vals;
   const uint32_t* __restrict__ ranges = lists.ranges;
   const uint32_t* __restrict__ first = lists.first;
   __shared__ float2 s_xy[64];
   __shared__ float4 s_co[64];
+  __shared__ float4 s_q[64];    // pair_coefs of the conic and the opacity
   __shared__ float4 s_rgb[64];  // rgb and the 0-based list position (as int bits)
   __shared__ uint32_t s_g[64];
   __shared__ float s_acc[64][kRecFloats];
@@ -374,6 +373,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       s_g[slot] = g;
       s_xy[slot] = m;
       s_co[slot] = co;
+      s_q[slot] = pair_coefs(co.x, co.y, co.z, co.w);
       s_rgb[slot] = c;
       if (kCh) {
         s_z[slot] = z;
@@ -385,6 +385,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
     for (int j = cnt - 1; j >= 0; --j) {
       const float2 gm = s_xy[j];
       const float4 gc = s_co[j];
+      const float4 gq = s_q[j];
       const float4 cc = s_rgb[j];
       const float gz = kCh ? s_z[j] : 0.0f;
       const float4 gf = kCh ? s_fv[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -396,6 +397,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       // An unused pair takes alpha = 0, which leaves T (rcp(1) is exact)
       // and the colour behind it unchanged, so no selects are needed.
       const float dx = gm.x - fpx;
+      const float c1 = gq.y * dx, c0 = (gq.x * dx) * dx;
       float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, cr = 0.0f, cgr = 0.0f, cb = 0.0f;
       float cz = 0.0f, cv0 = 0.0f, cv1 = 0.0f, cv2 = 0.0f, ch = 0.0f;
       bool any = false;
@@ -404,10 +406,10 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
         const bool inr = pos < last[k];
         if (kCount) evaluated += inr ? 1 : 0;
         const float dy = gm.y - static_cast<float>(py0 + 4 * k);
-        const float power = pair_power(dx, dy, gc.x, gc.y, gc.z);
-        const float raw = gc.w * exp_blend(power);
+        const float p2 = pair_exp2(gq.z, c1, c0, dy);
+        const float raw = gq.w * __builtin_amdgcn_exp2f(p2);
         const float alpha = fminf(kAlphaMax, raw);
-        const bool ok = inr && !(power > 0.0f) && !(alpha < kAlphaMin);
+        const bool ok = inr && !(p2 > 0.0f) && !(alpha < kAlphaMin);
         any = any || ok;
         const float au = ok ? alpha : 0.0f;
         const float om = 1.0f - au;
