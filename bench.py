@@ -646,7 +646,7 @@ def main():
 
     # semantic rendering (Sec. 4.1): 19 class scores per Gaussian composited
     # over the six views and differentiated (vectors and Gaussians)
-    sem = torch.randn((19, N), device="cuda", generator=gch).requires_grad_(True)
+    sem = torch.randn((N, 19), device="cuda", generator=gch).requires_grad_(True)
     sem_w = torch.randn((V, 19, H, W), device="cuda", generator=gch)
 
     def semantic_step():

@@ -316,6 +316,45 @@ int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const
                                   const float* const* dL_dimg, const pvg_channels* channels,
                                   pvg_gaussians_grad* grad, int32_t accumulate, void* tmp,
                                   size_t tmp_bytes, void* stream);
+/* Feature compositing (Sec. 4.1, Eq. (3)): every Gaussian carries an
+ * N-vector (the semantic class scores), blended in place of the colour with
+ * no background term, out[c] = sum_i T_i alpha_i f_i,c, all N channels in
+ * one walk of each tile list.  feat: device [n][ld] floats, row stride ld >=
+ * n_ch, channels 0 .. n_ch - 1 of each row used, read only; 1 <= n_ch <=
+ * PVG_MAX_FEATURE_CHANNELS (split wider vectors into column groups: the
+ * adjoint is linear in the upstream gradient).  out: device [n_ch][height]
+ * [width]; final_T and n_contrib as in pvg_render_fwd, bit-identical to a
+ * colour render of the same geom and bins, and what the adjoint needs.
+ * PVG_ERR_INVALID on an invalid geom, bins or camera, a null pointer, n_ch
+ * out of range or ld < n_ch; asynchronous on `stream`. */
+#define PVG_MAX_FEATURE_CHANNELS 32
+int pvg_render_features(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera* cam, const float* feat,
+                        int64_t ld, int32_t n_ch, float* out, float* final_T, int32_t* n_contrib, void* stream);
+
+/* Scratch bytes of pvg_render_features_bwd for n Gaussians, n_views views,
+ * n_ch channels and the largest bins capacity among the views.
+ * PVG_ERR_INVALID on negative or out-of-range sizes or a null output. */
+int pvg_features_bwd_tmp_bytes(int64_t n, int32_t n_views, int32_t n_ch, int64_t max_capacity, size_t* bytes);
+
+/* Adjoint of pvg_render_features over several views of one set of Gaussians
+ * (cameras, and H(t) with the flow-translated H(t + dt) of Sec. 3.4), given
+ * dL_dout[k] (device [n_ch][height][width]; NULL skips view k) and the
+ * forward's final_T[k] and n_contrib[k].  geoms and bins as for
+ * pvg_render_bwd_views.  The vectors' gradient is added into feat_grad
+ * (device [n][ld], never cleared); the parameters' gradient, which reaches
+ * them through alpha only, is written (accumulate = 0) or added (1) into
+ * grad: the SH arrays receive zeros, or are left as they are.  The views
+ * run in order on `stream` (each adds into feat_grad).  tmp: at least
+ * pvg_features_bwd_tmp_bytes bytes.  Without atomics: bitwise reproducible.
+ * Errors as for pvg_render_bwd_views, and PVG_ERR_INVALID on n_ch out of
+ * range, ld < n_ch, or a null feat or feat_grad with n > 0. */
+int pvg_render_features_bwd(const pvg_gaussians* g, int32_t n_views, const pvg_camera* cams,
+                            const pvg_frame* frames, const pvg_geom* geoms, const pvg_bins* bins,
+                            const float* const* final_T, const int32_t* const* n_contrib, const float* feat,
+                            int64_t ld, int32_t n_ch, const float* const* dL_dout, float* feat_grad,
+                            pvg_gaussians_grad* grad, int32_t accumulate, void* tmp, size_t tmp_bytes,
+                            void* stream);
+
 /* Position-aware adaptive control (Sec. 3.3, Eq. (9), and the split rules
  * of the implementation details in the appendix).  gamma(mu) = 1 if |mu| <
  * 2 r, else |mu| / r - 1.  A Gaussian whose mean view-space gradient

@@ -30,6 +30,8 @@ from .render import (  # noqa: F401
     pvg_ssim,
     render,
     render_bwd,
+    render_features,
+    render_features_bwd,
     render_fwd,
     render_views,
 )

@@ -20,6 +20,7 @@ PVG_ERR_HIP = -5
 PVG_ERR_NOT_FOUND = -6
 PVG_ERR_TIMEOUT = -7
 NOALLOC_SCRATCH_BYTES = 256 << 20  # PVG_NOALLOC_SCRATCH_BYTES of include/pvg.h
+MAX_FEATURE_CHANNELS = 32  # PVG_MAX_FEATURE_CHANNELS
 
 STAGES = ("preprocess", "compact", "depth_sort", "scan_emit", "tile_sort", "ranges", "render_fwd", "render_bwd",
           "preprocess_bwd", "grad_gather")
@@ -136,6 +137,10 @@ def load():
         "pvg_render_fwd_channels": ([P(Geom), P(Bins), P(Camera), P(Frame), vp, vp, vp, P(Channels), vp], i32),
         "pvg_render_bwd_views_channels": ([P(Gaussians), i32, P(Camera), P(Frame), P(Geom), P(Bins), P(vp), P(vp),
                                            P(vp), P(Channels), P(GaussiansGrad), i32, vp, C.c_size_t, vp], i32),
+        "pvg_render_features": ([P(Geom), P(Bins), P(Camera), vp, i64, i32, vp, vp, vp, vp], i32),
+        "pvg_features_bwd_tmp_bytes": ([i64, i32, i32, i64, P(C.c_size_t)], i32),
+        "pvg_render_features_bwd": ([P(Gaussians), i32, P(Camera), P(Frame), P(Geom), P(Bins), P(vp), P(vp), vp,
+                                     i64, i32, P(vp), vp, P(GaussiansGrad), i32, vp, C.c_size_t, vp], i32),
         "pvg_render_bwd": ([P(Gaussians), P(Camera), P(Frame), P(Geom), P(Bins), vp, vp, vp, P(GaussiansGrad),
                             i32, vp, C.c_size_t, vp], i32),
         "pvg_render_bwd_views": ([P(Gaussians), i32, P(Camera), P(Frame), P(Geom), P(Bins), P(vp), P(vp), P(vp),

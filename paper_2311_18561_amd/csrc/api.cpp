@@ -176,6 +176,23 @@ static ViewSet single(const View& v, int64_t n) {
   return vs;
 }
 
+// scratch of the feature adjoint: g2d [views][n][kG2DStride] | rec [capacity][6 + feature_width(n_ch)] |
+// vis [capacity] bytes (padded for the 16-byte flag reads)
+static size_t feature_scratch_bytes(int64_t n, int32_t views, int32_t n_ch, int64_t capacity, size_t* off_rec,
+                                    size_t* off_vis, size_t* vis_bytes, size_t* slot_bytes) {
+  auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
+  const size_t slot = al(sizeof(float) * kG2DStride * static_cast<size_t>(std::max<int64_t>(n, 1)));
+  const size_t g2d = slot * static_cast<size_t>(std::max(views, 1));
+  const size_t cap = static_cast<size_t>(std::max<int64_t>(capacity, 1));
+  const size_t rec = al(sizeof(float) * static_cast<size_t>(6 + feature_width(n_ch)) * cap);
+  const size_t vis = al((cap + 31) & ~static_cast<size_t>(15));
+  if (off_rec) *off_rec = g2d;
+  if (off_vis) *off_vis = g2d + rec;
+  if (vis_bytes) *vis_bytes = vis;
+  if (slot_bytes) *slot_bytes = slot;
+  return g2d + rec + vis;
+}
+
 size_t bwd_scratch_bytes(int64_t n, int32_t views, int32_t regions, int64_t capacity, size_t* off_rec,
                          size_t* off_vis, size_t* vis_bytes, size_t* slot_bytes, size_t* region_bytes) {
   auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
@@ -350,6 +367,25 @@ int pvg_render_fwd_channels(const pvg_geom* geom, const pvg_bins* bins, const pv
   return PVG_OK;
 }
 
+int pvg_render_features(const pvg_geom* geom, const pvg_bins* bins, const pvg_camera* cam, const float* feat,
+                        int64_t ld, int32_t n_ch, float* out, float* final_T, int32_t* n_contrib, void* stream) {
+  if (!geom || !check_geom(geom, geom->n) || !check_bins(bins) || !check_camera(cam)) return PVG_ERR_INVALID;
+  if (n_ch < 1 || n_ch > kMaxFeatureChannels || ld < n_ch) {
+    set_error("n_ch outside [1, %d] or ld < n_ch", kMaxFeatureChannels);
+    return PVG_ERR_INVALID;
+  }
+  if (!out || !final_T || !n_contrib || (geom->n > 0 && !feat)) {
+    set_error("feat or an output array is null");
+    return PVG_ERR_INVALID;
+  }
+  View v = make_view(nullptr, cam, nullptr);
+  v.final_T = final_T;
+  v.n_contrib = n_contrib;
+  PVG_HIP(launch_feature_fwd(single(v, geom->n), to_geom(geom), bins->vals, bins->ranges, bins->tile_cull != 0, feat,
+                             ld, n_ch, out, static_cast<hipStream_t>(stream)));
+  return PVG_OK;
+}
+
 int pvg_render_bwd(const pvg_gaussians* g, const pvg_camera* cam, const pvg_frame* frame, const pvg_geom* geom,
                    const pvg_bins* bins, const float* final_T, const int32_t* n_contrib, const float* dL_dimg,
                    pvg_gaussians_grad* grad, int32_t accumulate, void* tmp, size_t tmp_bytes, void* stream) {
@@ -400,6 +436,22 @@ int pvg_render_bwd_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
                          int32_t accumulate, void* tmp, size_t tmp_bytes, void* stream) {
   return pvg_render_bwd_views_channels(g, n_views, cams, frames, geoms, bins, final_T, n_contrib, dL_dimg, nullptr,
                                        grad, accumulate, tmp, tmp_bytes, stream);
+}
+
+// Zeros into every parameter gradient array (an overwriting adjoint that no
+// view fed still writes its result).
+static int zero_param_grads(const pvg_gaussians* g, const pvg_gaussians_grad* grad, hipStream_t s) {
+  const int64_t n = g->n, K = (g->sh_degree + 1) * (g->sh_degree + 1);
+  PVG_HIP(launch_fill_f32(grad->mu, 0.0f, 3 * n, s));
+  PVG_HIP(launch_fill_f32(grad->scale, 0.0f, 3 * n, s));
+  PVG_HIP(launch_fill_f32(grad->rot, 0.0f, 4 * n, s));
+  PVG_HIP(launch_fill_f32(grad->sh, 0.0f, 3 * K * n, s));
+  PVG_HIP(launch_fill_f32(grad->opacity, 0.0f, n, s));
+  PVG_HIP(launch_fill_f32(grad->vel, 0.0f, 3 * n, s));
+  PVG_HIP(launch_fill_f32(grad->period, 0.0f, n, s));
+  PVG_HIP(launch_fill_f32(grad->tau, 0.0f, n, s));
+  PVG_HIP(launch_fill_f32(grad->beta, 0.0f, n, s));
+  return PVG_OK;
 }
 
 int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const pvg_camera* cams,
@@ -563,19 +615,118 @@ int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const
   }
   const int st = flush();
   if (st != PVG_OK) return st;
-  if (first_group && !accumulate && g->n > 0) {
-    // no view carries a gradient: overwriting still means writing zeros
-    const int64_t n = g->n, K = (g->sh_degree + 1) * (g->sh_degree + 1);
-    PVG_HIP(launch_fill_f32(grad->mu, 0.0f, 3 * n, s));
-    PVG_HIP(launch_fill_f32(grad->scale, 0.0f, 3 * n, s));
-    PVG_HIP(launch_fill_f32(grad->rot, 0.0f, 4 * n, s));
-    PVG_HIP(launch_fill_f32(grad->sh, 0.0f, 3 * K * n, s));
-    PVG_HIP(launch_fill_f32(grad->opacity, 0.0f, n, s));
-    PVG_HIP(launch_fill_f32(grad->vel, 0.0f, 3 * n, s));
-    PVG_HIP(launch_fill_f32(grad->period, 0.0f, n, s));
-    PVG_HIP(launch_fill_f32(grad->tau, 0.0f, n, s));
-    PVG_HIP(launch_fill_f32(grad->beta, 0.0f, n, s));
+  if (first_group && !accumulate && g->n > 0) return zero_param_grads(g, grad, s);
+  return PVG_OK;
+}
+
+// The adjoint of feature compositing.  The views run in order on the
+// caller's stream with one record region (a view's gather adds into the
+// caller's feature gradient, so views must not overlap); the per-Gaussian
+// pass runs per group of up to kMaxBwdViews views of one render time.
+int pvg_features_bwd_tmp_bytes(int64_t n, int32_t n_views, int32_t n_ch, int64_t max_capacity, size_t* bytes) {
+  if (!bytes || n < 0 || n_views < 1 || n_ch < 1 || n_ch > kMaxFeatureChannels || max_capacity < 0 ||
+      max_capacity > 0xffffffffll) {
+    set_error("n < 0, n_views < 1, n_ch outside [1, %d], capacity outside [0, 2^32) or null output",
+              kMaxFeatureChannels);
+    return PVG_ERR_INVALID;
   }
+  *bytes = feature_scratch_bytes(n, std::min(n_views, kMaxBwdViews), n_ch, max_capacity, nullptr, nullptr, nullptr,
+                                 nullptr);
+  return PVG_OK;
+}
+
+int pvg_render_features_bwd(const pvg_gaussians* g, int32_t n_views, const pvg_camera* cams,
+                            const pvg_frame* frames, const pvg_geom* geoms, const pvg_bins* bins,
+                            const float* const* final_T, const int32_t* const* n_contrib, const float* feat,
+                            int64_t ld, int32_t n_ch, const float* const* dL_dout, float* feat_grad,
+                            pvg_gaussians_grad* grad, int32_t accumulate, void* tmp, size_t tmp_bytes,
+                            void* stream) {
+  if (!check_gaussians(g)) return PVG_ERR_INVALID;
+  if (n_views < 1 || !cams || !frames || !geoms || !bins || !final_T || !n_contrib || !dL_dout) {
+    set_error("n_views < 1 or a per-view array is null");
+    return PVG_ERR_INVALID;
+  }
+  if (n_ch < 1 || n_ch > kMaxFeatureChannels || ld < n_ch) {
+    set_error("n_ch outside [1, %d] or ld < n_ch", kMaxFeatureChannels);
+    return PVG_ERR_INVALID;
+  }
+  if (g->n > 0 && (!feat || !feat_grad)) { set_error("feat or feat_grad is null"); return PVG_ERR_INVALID; }
+  if (!grad || (g->n > 0 && (!grad->mu || !grad->scale || !grad->rot || !grad->sh || !grad->opacity ||
+                             !grad->vel || !grad->period || !grad->tau || !grad->beta))) {
+    set_error("a gradient array is null");
+    return PVG_ERR_INVALID;
+  }
+  if ((grad->densify_grad == nullptr) != (grad->densify_count == nullptr)) {
+    set_error("densify_grad and densify_count go together");
+    return PVG_ERR_INVALID;
+  }
+  int64_t max_cap = 0;
+  for (int32_t k = 0; k < n_views; ++k) {
+    if (!check_camera(&cams[k]) || !check_frame(&frames[k]) || !check_geom(&geoms[k], g->n) ||
+        !check_bins(&bins[k]))
+      return PVG_ERR_INVALID;
+    if (!dL_dout[k]) continue;
+    if (!final_T[k] || !n_contrib[k]) { set_error("view %d: final_T or n_contrib is null", k); return PVG_ERR_INVALID; }
+    if (g->n > 0 && !bins[k].first) {
+      set_error("view %d: bins.first is null: the adjoint needs each Gaussian's first instance index", k);
+      return PVG_ERR_INVALID;
+    }
+    if (g->n > 0 && bins[k].tile_cull && (!bins[k].rows || !bins[k].row_base)) {
+      set_error("view %d: bins.rows / bins.row_base are null: the adjoint of culled lists needs them", k);
+      return PVG_ERR_INVALID;
+    }
+    max_cap = std::max(max_cap, bins[k].capacity);
+  }
+  const int32_t slots = std::min(n_views, kMaxBwdViews);
+  size_t off_rec = 0, off_vis = 0, vis_bytes = 0, slot_bytes = 0;
+  const size_t need = feature_scratch_bytes(g->n, slots, n_ch, max_cap, &off_rec, &off_vis, &vis_bytes, &slot_bytes);
+  if (!tmp || tmp_bytes < need) {
+    set_error("feature adjoint scratch of %zu bytes is smaller than the %zu required", tmp_bytes, need);
+    return PVG_ERR_NOMEM;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(tmp);
+  float* rec = reinterpret_cast<float*>(base + off_rec);
+  uint8_t* vis = reinterpret_cast<uint8_t*>(base + off_vis);
+  BwdViews pk;
+  std::memset(&pk, 0, sizeof(pk));
+  bool first_group = true;
+  auto flush = [&]() -> int {
+    if (pk.nv == 0) return PVG_OK;
+    PVG_HIP(launch_preprocess_bwd(pk, *grad, first_group ? accumulate : 1, s));
+    first_group = false;
+    pk.nv = 0;
+    return PVG_OK;
+  };
+  for (int32_t k = 0; k < n_views; ++k) {
+    if (!dL_dout[k]) continue;
+    View v = make_view(g, &cams[k], &frames[k]);
+    v.final_T = const_cast<float*>(final_T[k]);
+    v.n_contrib = const_cast<int32_t*>(n_contrib[k]);
+    if (pk.nv > 0 && !(v.t == pk.views[0].t)) {  // a pass shares one render time
+      const int st = flush();
+      if (st != PVG_OK) return st;
+    }
+    float* g2d = reinterpret_cast<float*>(base + slot_bytes * static_cast<size_t>(pk.nv));
+    const Lists lists{bins[k].vals, bins[k].ranges, bins[k].first, bins[k].tile_cull != 0,
+                      reinterpret_cast<const uint2*>(bins[k].rows), bins[k].row_base, bins[k].capacity};
+    PVG_HIP(launch_feature_bwd(single(v, g->n), to_geom(&geoms[k]), lists, feat, ld, n_ch, dL_dout[k], rec, vis,
+                               static_cast<int64_t>(vis_bytes), g2d, feat_grad, s));
+    pk.views[pk.nv] = v;
+    pk.radius[pk.nv] = geoms[k].radius;
+    pk.rgb[pk.nv] = geoms[k].rgb;
+    pk.g2d[pk.nv] = g2d;
+    pk.feat_grad[pk.nv] = nullptr;
+    pk.no_colour[pk.nv] = true;
+    ++pk.nv;
+    if (pk.nv == kMaxBwdViews) {
+      const int st = flush();
+      if (st != PVG_OK) return st;
+    }
+  }
+  const int st = flush();
+  if (st != PVG_OK) return st;
+  if (first_group && !accumulate && g->n > 0) return zero_param_grads(g, grad, s);
   return PVG_OK;
 }
 

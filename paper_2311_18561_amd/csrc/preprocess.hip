@@ -349,7 +349,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(BwdViews pk, pvg_gaussia
     Proj P;
     project_view(vw, i, G, C, P, false);
     view_direction(vw, P);
-    adjoint_view(vw, i, P, C, pk.rgb[v] + 3 * i, g, S, pk.feat_grad[v] != nullptr);
+    adjoint_view(vw, i, P, C, pk.rgb[v] + 3 * i, g, S, pk.feat_grad[v] != nullptr || pk.no_colour[v]);
   }
   GeoGrad acc = {};
   if (accumulate) {  // start from the previous values
@@ -389,6 +389,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(BwdViews pk, pvg_gaussia
   for (int j = 0; j < 48; ++j) gsh[j] = (j < 3 * K && accumulate) ? grad.sh[j * n + i] : 0.0f;
   for (int v = 0; v < pk.nv; ++v) {
     if (pk.radius[v][i] <= 0) continue;
+    if (pk.no_colour[v]) continue;
     const float* g = pk.g2d[v] + kG2DStride * i;  // d(rgb) unclamped part and direction, from the first loop
     if (pk.feat_grad[v]) {  // a feature view: its gradient goes to the feature rows, not to the SH
       for (int c = 0; c < 3; ++c) pk.feat_grad[v][c * n + i] += g[6 + c];

@@ -152,6 +152,9 @@ struct BwdViews {
   // in place of the colour; their gradient is added here ([3][n]) and the
   // colour's SH and view-direction chain is skipped
   float* feat_grad[kMaxBwdViews];
+  // true: the view composited a feature vector and no colour at all (g2d
+  // slots 6..11 unused); the colour's SH and view-direction chain is skipped
+  bool no_colour[kMaxBwdViews];
 };
 hipError_t launch_preprocess_bwd(const BwdViews& pk, const pvg_gaussians_grad& grad, int accumulate,
                                  hipStream_t s);
@@ -186,6 +189,19 @@ struct Lists {
 // adjoint of compositing: per-(Gaussian, tile) records, then their per-Gaussian sums into g2d
 hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const Lists& lists, float* rec, uint8_t* vis,
                              int64_t vis_bytes, float* g2d, hipStream_t s);
+// N-channel feature compositing (Sec. 4.1's per-Gaussian vectors through
+// Eq. (3)) of one view: out [nch][H][W] and the view's final_T / n_contrib;
+// feat [n][ld], channels c < nch used (1 <= nch <= kMaxFeatureChannels)
+constexpr int kMaxFeatureChannels = 32;
+int feature_width(int nch);  // channels a record carries: nch rounded up to a kernel width
+hipError_t launch_feature_fwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals, const uint32_t* ranges,
+                              bool culled, const float* feat, int64_t ld, int nch, float* out, hipStream_t s);
+// its adjoint for one view: records [capacity][6 + feature_width(nch)], then per
+// visible Gaussian the screen-space sums into g2d and the feature sums added
+// into feat_grad [n][ld]
+hipError_t launch_feature_bwd(const ViewSet& vs, const Geom& geom, const Lists& lists, const float* feat, int64_t ld,
+                              int nch, const float* dout, float* rec, uint8_t* vis, int64_t vis_bytes, float* g2d,
+                              float* feat_grad, hipStream_t s);
 // scratch of the adjoint: g2d [views][n][12] | regions x (rec [capacity][9] | vis [capacity] bytes, padded);
 // one region per view adjoint that runs concurrently (at most kBwdStreams)
 constexpr int kBwdStreams = 3;

@@ -263,6 +263,60 @@ def render_fwd(geom: Geom, bins: Bins, cam: L.Camera, frame: L.Frame, out=None, 
     return img, final_T, n_contrib
 
 
+def render_features(geom: Geom, bins: Bins, cam: L.Camera, feats, out=None, c0=0, width=None):
+    """Composite channels c0 .. c0 + width - 1 (at most the library's channel
+    limit; default all of them from c0) of feats ([n, N] float32, a
+    Gaussian's vector contiguous) in one walk of the view's lists; returns
+    (out [width, H, W], final_T, n_contrib)."""
+    dev = geom.xy.device
+    H, W = int(cam.height), int(cam.width)
+    nch = int(feats.shape[1])
+    width = nch - c0 if width is None else width
+    if out is None:
+        out = torch.empty((width, H, W), dtype=torch.float32, device=dev)
+    assert feats.is_contiguous() and out.is_contiguous() and out.shape == (width, H, W)
+    final_T = torch.empty((H, W), dtype=torch.float32, device=dev)
+    n_contrib = torch.empty((H, W), dtype=torch.int32, device=dev)
+    gs, bs = geom.struct(), bins.struct()
+    L.check(L.load().pvg_render_features(C.byref(gs), C.byref(bs), C.byref(cam), feats.data_ptr() + 4 * c0, nch,
+                                         width, _p(out), _p(final_T), _p(n_contrib), _stream_handle()))
+    return out, final_T, n_contrib
+
+
+def render_features_bwd(params, n, degree, views, feats, dL_dout, feat_grad, grads=None, accumulate=False, c0=0,
+                        width=None):
+    """Adjoint of render_features over views [(cam, frame, geom, bins, final_T,
+    n_contrib)] with upstream gradients dL_dout[k] ([width, H, W]): adds the
+    vectors' gradient into feat_grad ([n, N], columns c0 ..) and writes (or
+    with accumulate adds) the parameters' gradient into grads."""
+    dev = params[0].device
+    if grads is None:
+        grads = [torch.empty_like(p) for p in params]
+    nch = int(feats.shape[1])
+    width = nch - c0 if width is None else width
+    V = len(views)
+    cams = (L.Camera * V)(*[v[0] for v in views])
+    frames = (L.Frame * V)(*[v[1] for v in views])
+    geoms = (L.Geom * V)(*[v[2].struct() for v in views])
+    bins = (L.Bins * V)(*[v[3].struct() for v in views])
+    f_t = (C.c_void_p * V)(*[v[4].data_ptr() for v in views])
+    n_c = (C.c_void_p * V)(*[v[5].data_ptr() for v in views])
+    dls = [d.contiguous() for d in dL_dout]
+    d_l = (C.c_void_p * V)(*[d.data_ptr() for d in dls])
+    g = gaussians_struct(params, n, degree)
+    gg = L.GaussiansGrad()
+    for name, t in zip(FIELDS, grads):
+        setattr(gg, name, t.data_ptr())
+    lib = L.load()
+    size = C.c_size_t()
+    L.check(lib.pvg_features_bwd_tmp_bytes(n, V, width, max(v[3].capacity for v in views), C.byref(size)))
+    tmp = _scratch(dev, int(size.value))
+    L.check(lib.pvg_render_features_bwd(C.byref(g), V, cams, frames, geoms, bins, f_t, n_c, feats.data_ptr() + 4 * c0,
+                                        nch, width, d_l, feat_grad.data_ptr() + 4 * c0, C.byref(gg),
+                                        1 if accumulate else 0, _p(tmp), int(tmp.numel()), _stream_handle()))
+    return grads
+
+
 def render_bwd(params, n, degree, cam, frame, geom, bins, final_T, n_contrib, dL_dimg, grads=None, accumulate=False):
     dev = params[0].device
     if grads is None:
@@ -462,7 +516,7 @@ def _record(stream):
 
 
 def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=None, vbars=None, rhos=None,
-                   depth_norm=False, opacs=None):
+                   depth_norm=False, opacs=None, composite=None):
     """Bin and composite view k on lane k mod VIEW_STREAMS, where lane 0 is
     the caller's stream and the others are side streams forked from it and
     joined back into it (the views' latency-bound sort and scan kernels
@@ -480,7 +534,10 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
     stacked[k]; with `depths` ([V,H,W], the same) its depth channel into
     depths[k] (the normalized depth with depth_norm), and likewise the
     velocity and staticness maps into vbars ([V,3,H,W]) and rhos ([V,H,W]),
-    and the rendered opacity 1 - final_T into opacs ([V,H,W])."""
+    and the rendered opacity 1 - final_T into opacs ([V,H,W]).  With
+    `composite`, view k is composited by composite(k, geom, bins, cam,
+    frame) (on the view's lane) instead, which returns (None, final_T,
+    n_contrib) and writes its own outputs."""
     dev = params[0].device
     main = torch.cuda.current_stream(dev)
     side = _streams(dev)
@@ -514,9 +571,7 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
             flags[k].copy_(bins.counters[2], non_blocking=True)
             fe = torch.cuda.Event()
             fe.record(st)
-            out = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k],
-                             None if depths is None else depths[k], None if vbars is None else vbars[k],
-                             None if rhos is None else rhos[k], depth_norm, None if opacs is None else opacs[k])
+            out = _composite_view(k, geom, bins, c, f, stacked, depths, vbars, rhos, depth_norm, opacs, composite)
             ev = None
             if st is not main:
                 ev = torch.cuda.Event()
@@ -531,7 +586,8 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
     for (st, _), (_, _, _, bins), out in zip(done, plans, outs):
         if st is not main:  # allocated on the side stream, used later on the caller's
             for tns in (*bins.tensors(), *(out if stacked is None else out[1:])):
-                tns.record_stream(main)
+                if tns is not None:
+                    tns.record_stream(main)
     for fe in flagged:
         fe.synchronize()
     for k, flag in enumerate(flags.tolist()):
@@ -539,10 +595,17 @@ def _forward_views(params, n, degree, views, tile_cull, stacked=None, depths=Non
             c, f, geom, _ = plans[k]
             bins = bin_sort(geom, c, tile_cull=tile_cull)
             plans[k][3] = bins
-            outs[k] = render_fwd(geom, bins, c, f, None if stacked is None else stacked[k],
-                                 None if depths is None else depths[k], None if vbars is None else vbars[k],
-                                 None if rhos is None else rhos[k], depth_norm, None if opacs is None else opacs[k])
+            outs[k] = _composite_view(k, geom, bins, c, f, stacked, depths, vbars, rhos, depth_norm, opacs,
+                                      composite)
     return plans, outs
+
+
+def _composite_view(k, geom, bins, c, f, stacked, depths, vbars, rhos, depth_norm, opacs, composite):
+    if composite is not None:
+        return composite(k, geom, bins, c, f)
+    return render_fwd(geom, bins, c, f, None if stacked is None else stacked[k],
+                      None if depths is None else depths[k], None if vbars is None else vbars[k],
+                      None if rhos is None else rhos[k], depth_norm, None if opacs is None else opacs[k])
 
 
 def render_views(params, views, tile_cull=True):
@@ -777,90 +840,71 @@ def pvg_ssim(x, y):
 
 class PVGRenderSemantic(torch.autograd.Function):
     """Per-Gaussian vectors (e.g. the 19 semantic class scores of Sec. 4.1)
-    composited like the colour, differentiable in the vectors and, through
-    alpha, in the Gaussians.  The compositing kernels take three channels
-    per pass (a geom whose rgb points at them, the view's own lists); the
-    adjoint sends every pass of every view through one multi-view call, with
-    each pass's colour gradient added into the vectors."""
+    composited like the colour (no background), differentiable in the
+    vectors and, through alpha, in the Gaussians.  Each view's lists are
+    walked once for all channels (pvg_render_features); vectors wider than
+    the library's channel limit go in column groups, whose adjoints add up
+    (the adjoint is linear in the upstream gradient)."""
 
     @staticmethod
     def forward(ctx, views, feats, *tensors):
         params, n, degree = _check_params(list(tensors))
         dev = params[0].device
-        if feats.dim() != 2 or feats.shape[1] != n or feats.dtype != torch.float32:
-            raise ValueError("feats must be float32 [N_channels, n]")
-        nch = int(feats.shape[0])
-        groups = (nch + 2) // 3
-        padded = torch.zeros((groups * 3, n), dtype=torch.float32, device=dev)
-        padded[:nch] = feats
-        fb = padded.reshape(groups, 3, n).transpose(1, 2).contiguous()  # [G][n][3], the geom.rgb layout
-        plans, outs = _forward_views(params, n, degree, views, tile_cull=True)
+        if feats.dim() != 2 or feats.shape[0] != n or feats.dtype != torch.float32 or feats.device != dev:
+            raise ValueError("feats must be float32 [n, N_channels] on the parameters' device")
+        nch = int(feats.shape[1])
+        if nch < 1:
+            raise ValueError("feats needs at least one channel")
         V = len(views)
         H, W = int(views[0][0]["height"]), int(views[0][0]["width"])
-        out = torch.empty((V, groups * 3, H, W), dtype=torch.float32, device=dev)
-        T_tmp = torch.empty((H, W), dtype=torch.float32, device=dev)
-        nc_tmp = torch.empty((H, W), dtype=torch.int32, device=dev)
-        lib = L.load()
-        for k, (c, f, geom, bins) in enumerate(plans):
-            bs = bins.struct()
-            for gi in range(groups):
-                gs = geom.struct()
-                gs.rgb = fb[gi].data_ptr()
-                L.check(lib.pvg_render_fwd(C.byref(gs), C.byref(bs), C.byref(c), C.byref(f), _p(out[k, 3 * gi]),
-                                           _p(T_tmp), _p(nc_tmp), _stream_handle()))
-        ctx.plans, ctx.n, ctx.degree, ctx.nch, ctx.groups = plans, n, degree, nch, groups
-        ctx.save_for_backward(*params, fb, *[T for _, T, _ in outs], *[nc for _, _, nc in outs])
-        return out[:, :nch]
+        out = torch.empty((V, nch, H, W), dtype=torch.float32, device=dev)
+        groups = _feature_groups(nch)
+
+        def composite(k, geom, bins, c, f):
+            for c0, w in groups:
+                _, T, nc = render_features(geom, bins, c, feats, out[k, c0:c0 + w], c0, w)
+            return None, T, nc
+
+        plans, outs = _forward_views(params, n, degree, views, tile_cull=True, composite=composite)
+        ctx.plans, ctx.n, ctx.degree, ctx.nch = plans, n, degree, nch
+        ctx.save_for_backward(*params, feats, *[T for _, T, _ in outs], *[nc for _, _, nc in outs])
+        return out
 
     @staticmethod
     def backward(ctx, dout):
         saved = ctx.saved_tensors
-        params, fb = list(saved[:9]), saved[9]
+        params, feats = list(saved[:9]), saved[9]
         V = len(ctx.plans)
         Ts, ncs = saved[10:10 + V], saved[10 + V:10 + 2 * V]
-        n, degree, groups = ctx.n, ctx.degree, ctx.groups
+        n, degree, nch = ctx.n, ctx.degree, ctx.nch
         dev = params[0].device
         grads = [torch.empty_like(p) for p in params]
-        dfeat = torch.zeros((groups * 3, n), dtype=torch.float32, device=dev)
+        dfeat = torch.zeros((n, nch), dtype=torch.float32, device=dev)
         if dout is None:
             for gr in grads:
                 gr.zero_()
-            return (None, dfeat[:ctx.nch], *grads)
-        H, W = int(dout.shape[2]), int(dout.shape[3])
-        d = torch.zeros((V, groups * 3, H, W), dtype=torch.float32, device=dev)
-        d[:, :ctx.nch] = dout
-        entries = [(k, gi) for k in range(V) for gi in range(groups)]
-        m = len(entries)
-        cams = (L.Camera * m)(*[ctx.plans[k][0] for k, _ in entries])
-        frames = (L.Frame * m)(*[ctx.plans[k][1] for k, _ in entries])
-        geoms = (L.Geom * m)(*[ctx.plans[k][2].struct() for k, _ in entries])
-        for j, (_, gi) in enumerate(entries):
-            geoms[j].rgb = fb[gi].data_ptr()
-        bins = (L.Bins * m)(*[ctx.plans[k][3].struct() for k, _ in entries])
-        f_t = (C.c_void_p * m)(*[Ts[k].data_ptr() for k, _ in entries])
-        n_c = (C.c_void_p * m)(*[ncs[k].data_ptr() for k, _ in entries])
-        d_l = (C.c_void_p * m)(*[d[k, 3 * gi].data_ptr() for k, gi in entries])
-        ch = (L.Channels * m)(*[L.Channels(None, None, None, None, None, None, None, 0,
-                                           dfeat[3 * gi].data_ptr()) for _, gi in entries])
-        g = gaussians_struct(params, n, degree)
-        gg = L.GaussiansGrad()
-        for name, t in zip(FIELDS, grads):
-            setattr(gg, name, t.data_ptr())
-        size = C.c_size_t()
-        lib = L.load()
-        L.check(lib.pvg_bwd_views_tmp_bytes(n, m, W, H, max(p[3].capacity for p in ctx.plans), C.byref(size)))
-        tmp = _scratch(dev, int(size.value))
-        L.check(lib.pvg_render_bwd_views_channels(C.byref(g), m, cams, frames, geoms, bins, f_t, n_c, d_l, ch,
-                                                  C.byref(gg), 0, _p(tmp), int(tmp.numel()), _stream_handle()))
-        return (None, dfeat[:ctx.nch], *grads)
+            return (None, dfeat, *grads)
+        dout = dout.contiguous()
+        views = [(c, f, geom, bins, T, nc) for (c, f, geom, bins), T, nc in zip(ctx.plans, Ts, ncs)]
+        for j, (c0, w) in enumerate(_feature_groups(nch)):
+            render_features_bwd(params, n, degree, views, feats, [dout[k, c0:c0 + w] for k in range(V)], dfeat, grads,
+                                accumulate=j > 0, c0=c0, width=w)
+        return (None, dfeat, *grads)
+
+
+def _feature_groups(nch):
+    """Column groups (first channel, width) of at most the library's channel limit."""
+    step = L.MAX_FEATURE_CHANNELS
+    return [(c0, min(step, nch - c0)) for c0 in range(0, nch, step)]
 
 
 def pvg_render_semantic(params, views, feats):
     """Composited per-Gaussian vectors [V, N_channels, H, W] for views of one
-    resolution (views as for pvg_render_views); feats: float32 [N_channels,
-    n] on the parameters' device (the semantic class scores of Sec. 4.1;
-    the cross-entropy against 2D labels is the caller's).  Differentiable in
-    feats and the parameters."""
+    resolution (views as for pvg_render_views); feats: float32 [n,
+    N_channels] on the parameters' device, each Gaussian's vector contiguous
+    (the rows the compositing reads; the semantic class scores of Sec. 4.1;
+    the cross-entropy against 2D labels is the caller's).
+    Differentiable in feats and the parameters."""
     full = _full_views(views)
     if len({(int(v[0]["width"]), int(v[0]["height"])) for v in full}) != 1:
         raise ValueError("views of one resolution are required")

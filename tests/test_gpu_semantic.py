@@ -1,8 +1,9 @@
 """Semantic rendering (Sec. 4.1: a 19-dimensional vector per Gaussian
-composited into class-score maps) on the GPU against the FP64 oracle with
-those vectors in place of the colour, three channels per pass: the maps,
-the vectors' gradient and the Gaussians' gradient (no SH term) for two
-views (H(t) and the flow-translated render).
+composited into class-score maps) on the GPU against the FP64 oracle, which
+takes the vectors three channels at a time in place of the colour: the
+maps, the vectors' gradient and the Gaussians' gradient (no SH term) for
+two views (H(t) and the flow-translated render).  The library walks each
+list once for up to 32 channels; wider vectors go in column groups.
 
 Bars: maps within 2e-5 of the oracle (unit-scale vectors); the vectors'
 gradient within 1e-3 of the sum of its terms' magnitudes (the oracle's
@@ -34,9 +35,9 @@ CASES = [
 ]
 
 
-# 19 channels (seven passes, the last padded) on both cases; 3 (one exact
-# pass) and 1 (one padded pass) on the tiny case
-RUNS = [(*CASES[0], 19), (*CASES[1], 19), (*CASES[0], 3), (*CASES[0], 1)]
+# 19 channels on both cases; on the tiny case every kernel width (1 -> 4,
+# 3 -> 4, 8, 12, 16, 24, 32) and 40 (two column groups, 32 + 8)
+RUNS = [(*CASES[0], 19), (*CASES[1], 19)] + [(*CASES[0], N) for N in (1, 3, 8, 12, 16, 24, 32, 40)]
 
 
 @pytest.mark.parametrize("name,mk_scene,mk_cam,t,N", RUNS)
@@ -45,7 +46,7 @@ def test_semantic_vs_fp64(orc, name, mk_scene, mk_cam, t, N):
     scene, cam = mk_scene(), mk_cam()
     n, H, W = scene["n"], cam["height"], cam["width"]
     rng = np.random.default_rng(13)
-    feats = rng.standard_normal((N, n)).astype(np.float32)
+    feats = rng.standard_normal((n, N)).astype(np.float32)
     dts = (0.0, 0.05)
     lists, keep, clear = [], [], []
     for d in dts:
@@ -64,7 +65,7 @@ def test_semantic_vs_fp64(orc, name, mk_scene, mk_cam, t, N):
     sc64 = orc.scene64(scene)
     groups = (N + 2) // 3
     padded = np.zeros((groups * 3, n))
-    padded[:N] = feats
+    padded[:N] = feats.T
     wpad = np.zeros((len(dts), groups * 3, H, W))
     wpad[:, :N] = w
     ref = {f: np.zeros_like(sc64[f]) for f in FIELDS}
@@ -90,7 +91,7 @@ def test_semantic_vs_fp64(orc, name, mk_scene, mk_cam, t, N):
             dmag[3 * gi:3 * gi + 3] += g2d_abs[:, 6:9].T
     print(f"[semantic {name} N={N}] max |map - oracle| = {worst_map:.3g}")
     assert worst_map <= 2e-5
-    worst, l2 = grad_tolerance_report(tf.grad.cpu().numpy(), dfeat[:N], rel=1e-3, magnitude=dmag[:N])
+    worst, l2 = grad_tolerance_report(tf.grad.cpu().numpy(), dfeat[:N].T, rel=1e-3, magnitude=dmag[:N].T)
     print(f"[semantic {name}] vectors: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
     assert worst <= 1.0
     for f, p in zip(FIELDS, params):
@@ -108,8 +109,83 @@ def test_semantic_rejects_bad_shapes():
     cfg = gen.make_config(0)
     params = to_device(cfg["scene"])
     cam = cfg["cameras"][0]
+    n = cfg["scene"]["n"]
     with pytest.raises(ValueError):
-        pvg.pvg_render_semantic(params, [(cam, 0.5)], torch.zeros((4, cfg["scene"]["n"] + 1), device="cuda"))
+        pvg.pvg_render_semantic(params, [(cam, 0.5)], torch.zeros((n + 1, 4), device="cuda"))
+    with pytest.raises(ValueError):
+        pvg.pvg_render_semantic(params, [(cam, 0.5)], torch.zeros((n, 0), device="cuda"))
     with pytest.raises(ValueError):
         pvg.pvg_render_semantic(params, [(cam, 0.5), (gen.yaw_camera(64, 48, 0.0, (0, 0, 0)), 0.5)],
-                                torch.zeros((4, cfg["scene"]["n"]), device="cuda"))
+                                torch.zeros((n, 4), device="cuda"))
+
+
+@pytest.mark.parametrize("N", [5, 19])
+def test_features_rect_lists_vs_fp64(orc, N):
+    """pvg_render_features and its adjoint on rectangle lists (no tile
+    culling): final_T and n_contrib bit for bit those of the colour render
+    of the same geom and bins, the maps against the oracle, and the two
+    gradients against the oracle's with the bars above.  Channels come from
+    a wider row (ld = N + 3) to check the row stride."""
+    import paper_2311_18561_amd as pvg
+    cfg = gen.make_config(0)
+    scene, cam, t = cfg["scene"], cfg["cameras"][0], cfg["t"]
+    n, H, W = scene["n"], cam["height"], cam["width"]
+    rng = np.random.default_rng(N)
+    wide = rng.standard_normal((n, N + 3)).astype(np.float32)
+    pre = orc.preprocess_f32(scene, cam, t)
+    bins_o = orc.bin_sort(pre, cam)
+    keep = unambiguous(oracle_margin(pre, bins_o, cam, t, gradients=True))
+    clear = oracle_margin(pre, bins_o, cam, t) >= 1.0
+    w = (rng.standard_normal((N, H, W)) * keep).astype(np.float32)
+    params = to_device(scene)
+    c, f = pvg.camera_struct(cam), pvg.frame_struct(t)
+    geom = pvg.preprocess(params, n, scene["sh_degree"], c, f)
+    bins = pvg.bin_sort(geom, c, tile_cull=False)
+    img, T0, nc0 = pvg.render_fwd(geom, bins, c, f)
+    tw = torch.from_numpy(wide).cuda()
+    maps, T, nc = pvg.render_features(geom, bins, c, tw, c0=1, width=N)
+    assert torch.equal(T, T0) and torch.equal(nc, nc0)
+    dfeat = torch.zeros_like(tw)
+    grads = pvg.render_features_bwd(params, n, scene["sh_degree"], [(c, f, geom, bins, T, nc)], tw,
+                                    [torch.from_numpy(w).cuda()], dfeat, c0=1, width=N)
+    torch.cuda.synchronize()
+    sc64 = orc.scene64(scene)
+    feats = wide[:, 1:1 + N].astype(np.float64)
+    groups = (N + 2) // 3
+    ref = {f_: np.zeros_like(sc64[f_]) for f_ in FIELDS}
+    mag = {f_: np.zeros_like(sc64[f_]) for f_ in FIELDS}
+    dref = np.zeros((n, groups * 3))
+    dmag = np.zeros((n, groups * 3))
+    got = maps.cpu().numpy()
+    worst_map = 0.0
+    args = (sc64, cam, t, 0.0, 0, (0.0, 0.0, 0.0), pre, bins_o)
+    for gi in range(groups):
+        col = np.zeros((n, 3))
+        c1 = min(3, N - 3 * gi)
+        col[:, :c1] = feats[:, 3 * gi:3 * gi + c1]
+        wg = np.zeros((3, H, W))
+        wg[:c1] = w[3 * gi:3 * gi + c1]
+        _, im, _ = orc.render_f64(*args, colour=col)
+        worst_map = max(worst_map, float(np.abs(got[3 * gi:3 * gi + c1] - im[:c1])[:, clear].max()))
+        part, g2d, terms = oracle_grads(orc, *args, wg, colour=col)
+        _, g2d_abs = orc.backward_f64(*args, np.abs(wg), colour=col)
+        for f_ in FIELDS:
+            ref[f_] += part[f_]
+            mag[f_] += np.maximum(np.abs(part[f_]), 1e-2 * terms[f_])
+        dref[:, 3 * gi:3 * gi + 3] = g2d[:, 6:9]
+        dmag[:, 3 * gi:3 * gi + 3] = g2d_abs[:, 6:9]
+    print(f"[features rect N={N}] max |map - oracle| = {worst_map:.3g}")
+    assert worst_map <= 2e-5
+    d = dfeat.cpu().numpy()
+    assert not np.any(d[:, 0]) and not np.any(d[:, 1 + N:])  # columns outside the group untouched
+    worst, l2 = grad_tolerance_report(d[:, 1:1 + N], dref[:, :N], rel=1e-3, magnitude=dmag[:, :N])
+    print(f"[features rect N={N}] vectors: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+    assert worst <= 1.0
+    for f_, g in zip(FIELDS, grads):
+        g = g.cpu().numpy()
+        if f_ == "sh":
+            assert not np.any(g)
+            continue
+        worst, l2 = grad_tolerance_report(g, ref[f_], rel=1e-3, magnitude=mag[f_])
+        print(f"[features rect N={N}] {f_}: worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+        assert worst <= 1.0, f_

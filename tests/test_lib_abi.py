@@ -191,3 +191,42 @@ def test_noalloc_bin_sort_rejects_an_oversized_plan_on_host(lib):
     assert ws.bin_tmp_bytes > L.NOALLOC_SCRATCH_BYTES
     bins.capacity = -1
     assert lib.pvg_bin_sort_noalloc(C.byref(geom), C.byref(cam), C.byref(bins), 1, None) == L.PVG_ERR_INVALID
+
+
+def test_feature_entry_points_reject_bad_arguments_on_host(lib):
+    """Feature compositing and its adjoint refuse a channel count outside
+    [1, PVG_MAX_FEATURE_CHANNELS], a row stride below it and missing arrays
+    before any device call; the scratch query grows with the channel count."""
+    from paper_2311_18561_amd import _lib as L
+    geom = L.Geom()
+    geom.n = 10
+    geom.xy = geom.depth = geom.conic_op = geom.rgb = geom.radius = geom.tiles = 16
+    cam = L.Camera()
+    cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.znear = 64, 48, 50.0, 50.0, 32.0, 24.0, 0.2
+    cam.R[:] = [1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0]
+    bins = L.Bins()
+    bins.capacity = 100
+    bins.keys = bins.vals = bins.ranges = bins.counters = 16
+    for nch, ld in ((0, 4), (L.MAX_FEATURE_CHANNELS + 1, 64), (8, 7)):
+        assert lib.pvg_render_features(C.byref(geom), C.byref(bins), C.byref(cam), 16, ld, nch, 16, 16, 16,
+                                       None) == L.PVG_ERR_INVALID
+        assert "n_ch" in L.last_error()
+    assert lib.pvg_render_features(C.byref(geom), C.byref(bins), C.byref(cam), None, 4, 4, 16, 16, 16,
+                                   None) == L.PVG_ERR_INVALID
+    size = C.c_size_t()
+    assert lib.pvg_features_bwd_tmp_bytes(10, 1, 0, 100, C.byref(size)) == L.PVG_ERR_INVALID
+    assert lib.pvg_features_bwd_tmp_bytes(10, 1, L.MAX_FEATURE_CHANNELS + 1, 100, C.byref(size)) == L.PVG_ERR_INVALID
+    sizes = []
+    for nch in (1, 4, 5, 19, 32):
+        assert lib.pvg_features_bwd_tmp_bytes(1000, 2, nch, 100_000, C.byref(size)) == 0
+        sizes.append(size.value)
+    assert sizes[0] == sizes[1] and sizes[1] < sizes[2] < sizes[3] < sizes[4]
+    # records hold 6 + (n_ch rounded up to a kernel width) floats per instance
+    assert sizes[4] - sizes[1] >= 4 * (32 - 4) * 100_000
+    g = L.Gaussians()
+    g.n = 10
+    gg = L.GaussiansGrad()
+    one = (C.c_void_p * 1)(16)
+    args = (C.byref(g), 1, C.byref(cam), C.byref(L.Frame()), C.byref(geom), C.byref(bins), one, one)
+    assert lib.pvg_render_features_bwd(*args, 16, 4, 0, one, 16, C.byref(gg), 0, 16, 1 << 20,
+                                       None) == L.PVG_ERR_INVALID
