@@ -653,7 +653,7 @@ def main():
         for p in params:
             p.grad = None
         sem.grad = None
-        (pvg.pvg_render_semantic(params, views, sem) * sem_w).sum().backward()
+        torch.dot(pvg.pvg_render_semantic(params, views, sem).reshape(-1), sem_w.reshape(-1)).backward()
 
     semantic_step()
     torch.cuda.synchronize()
@@ -764,7 +764,8 @@ def main():
         "iters_per_s_full_iteration": 1.0 / t_full,
         "semantic_ms_per_step": t_sem * 1e3,
         "semantic_note": ("pvg_render_semantic forward and backward of 19 class scores per Gaussian over the six "
-                          "views (seven three-channel passes per view on the view's lists, one adjoint call)"),
+                          "views: one list walk per view for all 19 channels, forward and adjoint, and the loss "
+                          "<maps, w> for a fixed random w"),
         "full_iteration_note": (f"a {args.period}-iteration period of the training loop (timed whole): each "
                                 "iteration samples one view per camera (3) at the next frame with the temporal "
                                 "smoothing of Sec. 3.4 (eta = 0.5, dt from a 1.5-frame span), renders the channels "

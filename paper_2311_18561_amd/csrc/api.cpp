@@ -176,7 +176,7 @@ static ViewSet single(const View& v, int64_t n) {
   return vs;
 }
 
-// scratch of the feature adjoint: g2d [views][n][kG2DStride] | rec [capacity][6 + feature_width(n_ch)] |
+// scratch of the feature adjoint: g2d [views][n][kG2DStride] | rec [capacity][8 + feature_width(n_ch)] |
 // vis [capacity] bytes (padded for the 16-byte flag reads)
 static size_t feature_scratch_bytes(int64_t n, int32_t views, int32_t n_ch, int64_t capacity, size_t* off_rec,
                                     size_t* off_vis, size_t* vis_bytes, size_t* slot_bytes) {
@@ -184,7 +184,7 @@ static size_t feature_scratch_bytes(int64_t n, int32_t views, int32_t n_ch, int6
   const size_t slot = al(sizeof(float) * kG2DStride * static_cast<size_t>(std::max<int64_t>(n, 1)));
   const size_t g2d = slot * static_cast<size_t>(std::max(views, 1));
   const size_t cap = static_cast<size_t>(std::max<int64_t>(capacity, 1));
-  const size_t rec = al(sizeof(float) * static_cast<size_t>(6 + feature_width(n_ch)) * cap);
+  const size_t rec = al(sizeof(float) * static_cast<size_t>(8 + feature_width(n_ch)) * cap);
   const size_t vis = al((cap + 31) & ~static_cast<size_t>(15));
   if (off_rec) *off_rec = g2d;
   if (off_vis) *off_vis = g2d + rec;

@@ -184,6 +184,25 @@ __device__ __forceinline__ uint32_t record_index(const Lists& lists, const Geom&
   return lists.first[g] + static_cast<uint32_t>((ty - rect[1]) * (rect[2] - rect[0]) + (tx - rect[0]));
 }
 
+// acc[q] += r[q], q < kSums; records of a multiple of four floats (the
+// record array 16-byte aligned) are read 16 bytes at a time.
+template <int kSums>
+__device__ __forceinline__ void add_record(const float* __restrict__ r, float* acc) {
+  if constexpr (kSums % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < kSums / 4; ++q) {
+      const float4 x = reinterpret_cast<const float4*>(r)[q];
+      acc[4 * q] += x.x;
+      acc[4 * q + 1] += x.y;
+      acc[4 * q + 2] += x.z;
+      acc[4 * q + 3] += x.w;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kSums; ++q) acc[q] += r[q];
+  }
+}
+
 // Sum of one Gaussian's flagged records in [e0, e0 + cnt) by one thread,
 // reading the flags 16 at a time.  The emission order keeps a Gaussian's
 // pairs contiguous.
@@ -203,8 +222,7 @@ __device__ __forceinline__ void gather_range(uint32_t e0, uint32_t cnt, const fl
       const uint32_t e = b + static_cast<uint32_t>(j);
       if (((words[j >> 2] >> (8 * (j & 3))) & 0xffu) && e >= e0 && e < e1) {
         const float* r = rec + kSums * static_cast<int64_t>(e);  // records are kSums floats apart
-#pragma unroll
-        for (int q = 0; q < kSums; ++q) acc[q] += r[q];
+        add_record<kSums>(r, acc);
       }
     }
   }
@@ -260,8 +278,7 @@ __device__ __forceinline__ void gather_range_wave(uint32_t e0, uint32_t cnt, int
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int k = lane; k < total; k += 64) {
       const float* r = rec + kSums * static_cast<int64_t>(idx[k]);
-#pragma unroll
-      for (int q = 0; q < kSums; ++q) acc[q] += r[q];
+      add_record<kSums>(r, acc);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -19,6 +19,10 @@
 
 namespace pvg {
 
+// Floats of one adjoint record: d(mean 2D) 2, d(conic) 3, d(opacity) 1, two
+// zeros (so that records are 16-byte aligned), d(feature) kNC.
+constexpr int feature_record_floats(int kNC) { return 8 + kNC; }
+
 // Channels c < nch of Gaussian g (row stride ld), padded with zeros to kNC.
 template <int kNC>
 __device__ __forceinline__ void load_feature(const float* __restrict__ feat, int64_t ld, int nch, uint32_t g,
@@ -114,6 +118,8 @@ __global__ void __launch_bounds__(64) k_feat_fwd(ViewSet vs, Geom geom, const ui
         last[k] = use ? pos : last[k];
         act[k] = act[k] && !stop;
       }
+      // a pair no pixel of the tile uses adds nothing
+      if (!__any(w[0] != 0.0f || w[1] != 0.0f || w[2] != 0.0f || w[3] != 0.0f)) continue;
 #pragma unroll
       for (int q = 0; q < kQ; ++q) {
         const float4 f = s_f[j][q];
@@ -152,13 +158,13 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
   // arithmetic may fuse.
 #pragma clang fp contract(fast)
   constexpr int kQ = kNC / 4;
-  constexpr int kRec = 6 + kNC;  // record: d(mean 2D) 2, d(conic) 3, d(opacity) 1, d(feature) kNC
+  constexpr int kRec = feature_record_floats(kNC);
   __shared__ float2 s_xy[64];
   __shared__ float4 s_co[64];
   __shared__ float4 s_q[64];
   __shared__ int s_pos[64];
   __shared__ float4 s_f[64][kQ];
-  __shared__ float s_acc[64][kRec];
+  __shared__ float4 s_acc[64][kRec / 4];
   __shared__ int s_any[64];
   const int64_t ntiles = live_tiles(vs);
   const int64_t tile = xcd_tile(blockIdx.x, ntiles);
@@ -222,6 +228,28 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
       const float4 gc = s_co[j];
       const float4 gq = s_q[j];
       const int pos = s_pos[j];
+      // alpha of the lane's four pixels as in the colour adjoint; a pair no
+      // pixel of the tile uses takes alpha = 0 everywhere, which leaves T
+      // (rcp(1) is exact) and the blend behind it unchanged: it is skipped
+      const float dx = gm.x - fpx;
+      const float c1 = gq.y * dx, c0 = (gq.x * dx) * dx;
+      float au[kPix], gate[kPix];
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < kPix; ++k) {
+        const bool inr = pos < last[k];
+        const float dy = gm.y - static_cast<float>(py0 + 4 * k);
+        const float p2 = pair_exp2(gq.z, c1, c0, dy);
+        const float raw = gq.w * __builtin_amdgcn_exp2f(p2);
+        const float alpha = fminf(kAlphaMax, raw);
+        const bool ok = inr && !(p2 > 0.0f) && !(alpha < kAlphaMin);
+        any = any || ok;
+        au[k] = ok ? alpha : 0.0f;
+        gate[k] = raw > kAlphaMax ? 0.0f : au[k];  // alpha's own gradient is 0 where it is clamped
+      }
+      const bool wany = __any(any);
+      if (lane == 0) s_any[j] = wany ? 1 : 0;
+      if (!wany) continue;
       // blended gradient of each pixel: sum_c f_c dL/dC_c
       float cg[kPix];
 #pragma unroll
@@ -233,28 +261,17 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
         for (int k = 0; k < kPix; ++k)
           cg[k] += f.x * G[k][4 * q] + f.y * G[k][4 * q + 1] + f.z * G[k][4 * q + 2] + f.w * G[k][4 * q + 3];
       }
-      // alpha, transmittance recovery and the moments of the power gradient
-      // as in the colour adjoint; an unused pair takes alpha = 0
-      const float dx = gm.x - fpx;
-      const float c1 = gq.y * dx, c0 = (gq.x * dx) * dx;
+      // transmittance recovery and the moments of the power gradient
       float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, w[kPix];
-      bool any = false;
 #pragma unroll
       for (int k = 0; k < kPix; ++k) {
-        const bool inr = pos < last[k];
         const float dy = gm.y - static_cast<float>(py0 + 4 * k);
-        const float p2 = pair_exp2(gq.z, c1, c0, dy);
-        const float raw = gq.w * __builtin_amdgcn_exp2f(p2);
-        const float alpha = fminf(kAlphaMax, raw);
-        const bool ok = inr && !(p2 > 0.0f) && !(alpha < kAlphaMin);
-        any = any || ok;
-        const float au = ok ? alpha : 0.0f;
-        const float om = 1.0f - au;
+        const float om = 1.0f - au[k];
         T[k] *= __builtin_amdgcn_rcpf(om);
         const float dal = T[k] * (cg[k] - rr[k]);
-        w[k] = au * T[k];
-        rr[k] = fmaf(au, cg[k], om * rr[k]);
-        const float gp = (raw > kAlphaMax ? 0.0f : au) * dal;
+        w[k] = au[k] * T[k];
+        rr[k] = fmaf(au[k], cg[k], om * rr[k]);
+        const float gp = gate[k] * dal;
         s0 += gp;
         s1 = fmaf(dy, gp, s1);
         s2 = fmaf(dy * dy, gp, s2);
@@ -268,21 +285,21 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
         a[3] = -(dx * s1);
         a[4] = -0.5f * s2;
         a[5] = gc.w > 0.0f ? s0 * __builtin_amdgcn_rcpf(gc.w) : 0.0f;
+        a[6] = 0.0f;
+        a[7] = 0.0f;
 #pragma unroll
-        for (int c = 0; c < kNC; ++c) a[6 + c] = w[0] * G[0][c] + w[1] * G[1][c] + w[2] * G[2][c] + w[3] * G[3][c];
+        for (int c = 0; c < kNC; ++c) a[8 + c] = w[0] * G[0][c] + w[1] * G[1][c] + w[2] * G[2][c] + w[3] * G[3][c];
       }
-      const bool wany = __any(any);
-      if (wany) wave_sum_store<kRec>(a, lane, s_acc[j]);
-      if (lane == 0) s_any[j] = wany ? 1 : 0;
+      wave_sum_store<kRec>(a, lane, reinterpret_cast<float*>(s_acc[j]));
     }
     __syncthreads();
     if (keep && s_any[__popcll(km & lt)] != 0) {
       const int slot = __popcll(km & lt);
       const uint32_t e = record_index<kCulled>(lists, geom, v, g, m, tx, ty);
       if (static_cast<int64_t>(e) < lists.capacity) {
-        float* dst = rec + kRec * static_cast<int64_t>(e);
+        float4* dst = reinterpret_cast<float4*>(rec + kRec * static_cast<int64_t>(e));
 #pragma unroll
-        for (int q = 0; q < kRec; ++q) dst[q] = s_acc[slot][q];
+        for (int q = 0; q < kRec / 4; ++q) dst[q] = s_acc[slot][q];
         vis[e] = 1;
       }
     }
@@ -292,12 +309,13 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
 
 // Per visible Gaussian: the sum of its flagged records.  g2d receives the
 // six screen-space sums (slots 6..13 zero: no colour, no channels) and the
-// feature sums are added into feat_grad[g][c], c < nch.
+// feature sums are added into feat_grad[g][c], c < nch.  Records are read
+// 16 bytes at a time.
 template <int kNC, bool kCulled>
 __global__ void __launch_bounds__(256) k_feat_gather(ViewSet vs, Geom geom, Lists lists, const float* __restrict__ rec,
                                                      const uint8_t* __restrict__ vis, float* g2d, float* feat_grad,
                                                      int64_t ld, int nch) {
-  constexpr int kRec = 6 + kNC;
+  constexpr int kRec = feature_record_floats(kNC);
   constexpr int kAcc = (kRec + 15) / 16 * 16;
   __shared__ uint32_t s_queue[256][3];
   __shared__ uint32_t s_idx[4][1024];
@@ -319,7 +337,7 @@ __global__ void __launch_bounds__(256) k_feat_gather(ViewSet vs, Geom geom, List
     float* fg = feat_grad + ld * gi;
 #pragma unroll
     for (int c = 0; c < kNC; ++c)
-      if (c < nch) fg[c] += acc[6 + c];
+      if (c < nch) fg[c] += acc[8 + c];
   } else if (visible) {
     const int q = atomicAdd(&s_qn, 1);
     s_queue[q][0] = static_cast<uint32_t>(gi);
@@ -337,7 +355,7 @@ __global__ void __launch_bounds__(256) k_feat_gather(ViewSet vs, Geom geom, List
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (lane < 14) g2d[kG2DStride * static_cast<int64_t>(g) + lane] = lane < 6 ? s_red[wid][lane] : 0.0f;
-    if (lane < nch && lane < kNC) feat_grad[ld * static_cast<int64_t>(g) + lane] += s_red[wid][6 + lane];
+    if (lane < nch && lane < kNC) feat_grad[ld * static_cast<int64_t>(g) + lane] += s_red[wid][8 + lane];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

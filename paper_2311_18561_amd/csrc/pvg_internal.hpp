@@ -196,7 +196,7 @@ constexpr int kMaxFeatureChannels = 32;
 int feature_width(int nch);  // channels a record carries: nch rounded up to a kernel width
 hipError_t launch_feature_fwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals, const uint32_t* ranges,
                               bool culled, const float* feat, int64_t ld, int nch, float* out, hipStream_t s);
-// its adjoint for one view: records [capacity][6 + feature_width(nch)], then per
+// its adjoint for one view: records [capacity][8 + feature_width(nch)], then per
 // visible Gaussian the screen-space sums into g2d and the feature sums added
 // into feat_grad [n][ld]
 hipError_t launch_feature_bwd(const ViewSet& vs, const Geom& geom, const Lists& lists, const float* feat, int64_t ld,
