@@ -78,7 +78,10 @@ typedef struct pvg_serve_report {
   double span_s;
 } pvg_serve_report;
 
-/* Creates a server and its batch workspaces (counted against the budget). */
+/* Creates a server and its batch workspaces (counted against the budget).
+ * Test hook: with PVG_FAULT_INJECT=k (k >= 1) in the environment when the
+ * server is created, every k-th batch launch fails before any device work;
+ * its tickets finish with PVG_ERR_HIP and the server carries on. */
 int pvg_serve_create(const pvg_serve_config* cfg, pvg_server** out);
 /* Copies a scene (device arrays) into server-owned HBM; fails with
  * PVG_ERR_NOMEM beyond the memory budget. */

@@ -19,7 +19,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pvg_oracle.cpp")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# PVG_ORACLE_LIB: another build of pvg_oracle.cpp (an instrumented one, say)
+_LIB = os.environ.get("PVG_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 FIELDS = ("mu", "scale", "rot", "sh", "opacity", "vel", "period", "tau", "beta")
 from . import adaptive  # noqa: E402,F401  (adaptive control: numpy, no C)
 from . import optim  # noqa: E402,F401  (Adam step: numpy, no C)

@@ -1082,8 +1082,9 @@ void orc_sh_basis_f64(int degree, const double* dir, double* Y, double* dY) {
 // covariance (a, b, c) of the point mu with scale s and rotation q seen by cam.
 int orc_project_f64(const double* mu, const double* s, const double* q, const float* camv, int W, int H,
                     double* m, double* J, double* cov) {
-  double zero3[3] = {0, 0, 0}, one = 1.0, tau = 0.0, beta = 1.0, l = 1.0, o = 1.0, sh = 0.0;
-  const void* arr[9] = {mu, s, q, &sh, &o, zero3, &l, &tau, &beta};
+  // degree 0: the SH array holds one coefficient per colour channel
+  double zero3[3] = {0, 0, 0}, one = 1.0, tau = 0.0, beta = 1.0, l = 1.0, o = 1.0, sh[3] = {0, 0, 0};
+  const void* arr[9] = {mu, s, q, sh, &o, zero3, &l, &tau, &beta};
   const Params prm = make_params(1, 0, arr);
   (void)one;
   const Camera cam = make_cam(camv, W, H);

@@ -11,6 +11,7 @@ device memory and streams.
 from ._lib import PVGError, load  # noqa: F401
 from .densify import densify, densify_config, split_by_staticness  # noqa: F401
 from .optim import SKY_LR, DenseAdam, PVGAdam, default_lrs  # noqa: F401
+from .scene_io import load_scene, save_scene  # noqa: F401
 from .train import temporal_smoothing_views  # noqa: F401
 from .render import (  # noqa: F401
     FIELDS,

@@ -9,7 +9,8 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpvg.so")
+# PVG_LIB: another build of the same sources (an instrumented host build, say)
+LIB_PATH = os.environ.get("PVG_LIB") or os.path.join(_HERE, "libpvg.so")
 
 PVG_OK = 0
 PVG_ERR_INVALID = -1

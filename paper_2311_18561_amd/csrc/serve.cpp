@@ -15,6 +15,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <cstdlib>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -110,6 +111,11 @@ struct pvg_server {
   int64_t completed = 0, failed = 0, batches = 0, batch_reqs = 0, retries = 0, graph_launches = 0, graph_builds = 0;
   double pixels = 0.0;
   int64_t t_first = 0, t_last = 0;
+  // fault injection for tests of failure handling: with PVG_FAULT_INJECT=k
+  // in the environment at creation, every k-th batch launch fails before
+  // touching the device (its tickets get PVG_ERR_HIP); 0: off
+  int64_t fault_every = 0;
+  int64_t launches = 0;  // scheduler thread only
 };
 
 namespace pvg {
@@ -182,6 +188,10 @@ int enqueue_batch(pvg_server* s, Lane& L, const ViewSet& vs, const BinPlan& plan
 // Writes the lane's view table for `batch` and launches it.
 int launch_batch(pvg_server* s, Lane& L) {
   L.t_launch = now_ns();
+  if (s->fault_every > 0 && ++s->launches % s->fault_every == 0) {
+    set_error("injected launch fault (PVG_FAULT_INJECT)");
+    return PVG_ERR_HIP;
+  }
   if (stub(s)) return PVG_OK;
   Header* h = static_cast<Header*>(L.h_stage);
   View* views = reinterpret_cast<View*>(static_cast<char*>(L.h_stage) + sizeof(Header));
@@ -451,6 +461,7 @@ int pvg_serve_create(const pvg_serve_config* cfg, pvg_server** out) {
   }
   auto* s = new pvg_server();
   s->cfg = *cfg;
+  if (const char* fi = std::getenv("PVG_FAULT_INJECT")) s->fault_every = std::max(0ll, std::atoll(fi));
   // tiles of a batch: pixels / 256 plus the partial tiles of up to max_batch views
   s->max_tiles = s->cfg.max_batch_pixels / 256 + static_cast<int64_t>(s->cfg.max_batch) * 512;
   s->hdr_bytes = align256(sizeof(Header) + sizeof(View) * static_cast<size_t>(s->cfg.max_batch));

@@ -150,3 +150,45 @@ def test_invalid_configuration_rejected():
         with pytest.raises(L.PVGError) as e:
             s.submit(sid + 100, CAM, 0.0)
         assert e.value.status == L.PVG_ERR_NOT_FOUND
+
+
+def test_injected_launch_fault_fails_its_tickets_and_the_server_carries_on(monkeypatch):
+    """PVG_FAULT_INJECT=2: every second batch launch fails before any device
+    work.  Requests go one batch at a time, so exactly the even-numbered
+    batches fail with PVG_ERR_HIP and the others complete."""
+    monkeypatch.setenv("PVG_FAULT_INJECT", "2")
+    with Server(max_batch=4, max_inflight=1, stub_launch_us=2_000) as s:
+        sid = s.load_scene(n=1000)
+        status = [s.wait(s.submit(sid, CAM, 0.0)).status for _ in range(6)]
+        assert status == [0, L.PVG_ERR_HIP] * 3
+        # a batch of several requests fails as a whole
+        tks = [s.submit(sid, CAM, 0.0) for _ in range(3)]
+        res = [s.wait(t) for t in tks]
+        assert {r.status for r in res} <= {0, L.PVG_ERR_HIP}
+        st = s.stats()
+        assert st["completed"] + st["failed"] == 9 and st["failed"] >= 3
+    monkeypatch.delenv("PVG_FAULT_INJECT")
+    with Server(max_batch=4, max_inflight=1, stub_launch_us=2_000) as s:  # off again
+        sid = s.load_scene(n=1000)
+        assert [s.wait(s.submit(sid, CAM, 0.0)).status for _ in range(4)] == [0] * 4
+
+
+def test_scene_files_round_trip_into_a_server(tmp_path):
+    """save_scene / load_scene: one float32 .npy per field, bit-exact round
+    trip, shape checks on load, and the loaded scene accepted by a server."""
+    import numpy as np
+    import paper_2311_18561_amd as pvg
+    scene = gen.make_scene(500, 3, sh_degree=2)
+    params = [scene[f] for f in pvg.FIELDS]
+    pvg.save_scene(str(tmp_path / "s"), params)
+    back = pvg.load_scene(str(tmp_path / "s"))
+    assert all(np.array_equal(a, b) and b.dtype == np.float32 for a, b in zip(params, back))
+    assert sorted(p.name for p in (tmp_path / "s").iterdir()) == sorted(f + ".npy" for f in pvg.FIELDS)
+    np.save(tmp_path / "s" / "tau.npy", np.zeros(499, np.float32))
+    with pytest.raises(ValueError):
+        pvg.load_scene(str(tmp_path / "s"))
+    with pytest.raises(ValueError):
+        pvg.save_scene(str(tmp_path / "t"), params[:3] + [params[3][:, :, :10]] + params[4:])
+    with Server(max_batch=2, max_inflight=1, stub_launch_us=1_000) as s:
+        sid = s.load_scene(n=back[0].shape[1], sh_degree=2)
+        assert s.wait(s.submit(sid, CAM, 0.0)).status == 0
