@@ -34,10 +34,10 @@ __device__ __forceinline__ float swap_sum16(float x, float y) {
 }
 __device__ __forceinline__ float dpp_add(float x, int ctrl) {
   switch (ctrl) {  // the control word must be a compile-time constant
-    case 0x128: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, false));
-    case 0x124: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xf, 0xf, false));
-    case 0x4e: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4e, 0xf, 0xf, false));
-    default: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xb1, 0xf, 0xf, false));
+    case 0x128: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, true));
+    case 0x124: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xf, 0xf, true));
+    case 0x4e: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4e, 0xf, 0xf, true));
+    default: return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xb1, 0xf, 0xf, true));
   }
 }
 __device__ __forceinline__ void wave_sum10(const float a[10], float out[3]) {
@@ -137,6 +137,11 @@ __device__ __forceinline__ float pair_exp2(float qz, float c1, float c0, float d
 }
 
 constexpr int kPix = 4;  // pixels per lane
+
+// The forward walks a batch's pairs in groups of kGroup (a batch is padded
+// with pairs no pixel uses up to a whole group).
+constexpr int kGroup = 4;
+__device__ __forceinline__ int pad_to(int cnt) { return (cnt + kGroup - 1) / kGroup * kGroup; }
 
 // The index range [e0, e0 + cnt) of a visible Gaussian's pairs in emission
 // order: first[g] and the listed count (its rectangle's tiles, or, for

@@ -84,6 +84,7 @@ __global__ void __launch_bounds__(64) k_feat_fwd(ViewSet vs, Geom geom, const ui
       keep = kCulled || tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1);
     }
     const uint64_t km = __ballot(keep);
+    const int cnt = __popcll(km);
     if (keep) {
       const int slot = __popcll(km & lt);
       s_xy[slot] = m;
@@ -94,41 +95,51 @@ __global__ void __launch_bounds__(64) k_feat_fwd(ViewSet vs, Geom geom, const ui
 #pragma unroll
       for (int q = 0; q < kQ; ++q) s_f[slot][q] = f[q];
     }
+    if (lane >= cnt && lane < pad_to(cnt)) {  // padding pairs (alpha = 0, finite values); the lane may also have filled a slot below cnt
+      s_xy[lane] = make_float2(0.0f, 0.0f);
+      s_co[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      s_pos[lane] = 0;
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) s_f[lane][q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
     __syncthreads();
-    const int cnt = __popcll(km);
-    for (int j = 0; j < cnt; ++j) {
+    // groups of kGroup pairs, one test for a finished wave per group (as in
+    // the colour forward)
+    for (int j0 = 0; j0 < cnt; j0 += kGroup) {
       if (!__any(act[0] || act[1] || act[2] || act[3])) break;
-      const float2 gm = s_xy[j];
-      const float4 gc = s_co[j];
-      const int pos = s_pos[j];
-      const float dx = gm.x - fpx;
-      const float c1 = gc.y * dx, c0 = (gc.x * dx) * dx;
-      float w[kPix];
 #pragma unroll
-      for (int k = 0; k < kPix; ++k) {
-        const float dy = gm.y - static_cast<float>(py0 + 4 * k);
-        const float p2 = pair_exp2(gc.z, c1, c0, dy);
-        const float alpha = fminf(kAlphaMax, gc.w * __builtin_amdgcn_exp2f(p2));
-        const bool ok = act[k] && !(p2 > 0.0f) && !(alpha < kAlphaMin);
-        const float Tn = T[k] * (1.0f - alpha);
-        const bool stop = ok && Tn < kTMin;
-        const bool use = ok && !stop;
-        w[k] = use ? alpha * T[k] : 0.0f;
-        T[k] = use ? Tn : T[k];
-        last[k] = use ? pos : last[k];
-        act[k] = act[k] && !stop;
-      }
-      // a pair no pixel of the tile uses adds nothing
-      if (!__any(w[0] != 0.0f || w[1] != 0.0f || w[2] != 0.0f || w[3] != 0.0f)) continue;
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) {
-        const float4 f = s_f[j][q];
+      for (int u = 0; u < kGroup; ++u) {
+        const int j = j0 + u;
+        const float2 gm = s_xy[j];
+        const float4 gc = s_co[j];
+        const int pos = s_pos[j];
+        const float dx = gm.x - fpx;
+        const float c1 = gc.y * dx, c0 = (gc.x * dx) * dx;
+        float w[kPix];
 #pragma unroll
         for (int k = 0; k < kPix; ++k) {
-          F[k][4 * q + 0] = fmaf(f.x, w[k], F[k][4 * q + 0]);
-          F[k][4 * q + 1] = fmaf(f.y, w[k], F[k][4 * q + 1]);
-          F[k][4 * q + 2] = fmaf(f.z, w[k], F[k][4 * q + 2]);
-          F[k][4 * q + 3] = fmaf(f.w, w[k], F[k][4 * q + 3]);
+          const float dy = gm.y - static_cast<float>(py0 + 4 * k);
+          const float p2 = pair_exp2(gc.z, c1, c0, dy);
+          const float alpha = fminf(kAlphaMax, gc.w * __builtin_amdgcn_exp2f(p2));
+          const bool ok = act[k] && !(p2 > 0.0f) && !(alpha < kAlphaMin);
+          const float Tn = T[k] * (1.0f - alpha);
+          const bool stop = ok && Tn < kTMin;
+          const bool use = ok && !stop;
+          w[k] = use ? alpha * T[k] : 0.0f;
+          T[k] = use ? Tn : T[k];
+          last[k] = use ? pos : last[k];
+          act[k] = act[k] && !stop;
+        }
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          const float4 f = s_f[j][q];
+#pragma unroll
+          for (int k = 0; k < kPix; ++k) {
+            F[k][4 * q + 0] = fmaf(f.x, w[k], F[k][4 * q + 0]);
+            F[k][4 * q + 1] = fmaf(f.y, w[k], F[k][4 * q + 1]);
+            F[k][4 * q + 2] = fmaf(f.z, w[k], F[k][4 * q + 2]);
+            F[k][4 * q + 3] = fmaf(f.w, w[k], F[k][4 * q + 3]);
+          }
         }
       }
     }
@@ -213,7 +224,7 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
     if (keep) {
       const int slot = __popcll(km & lt);
       s_xy[slot] = m;
-      s_co[slot] = co;
+      s_co[slot] = make_float4(-co.x, -co.y, -co.z, co.w > 0.0f ? __builtin_amdgcn_rcpf(co.w) : 0.0f);
       s_q[slot] = pair_coefs(co.x, co.y, co.z, co.w);
       s_pos[slot] = lo + lane;
       float4 f[kQ];
@@ -268,9 +279,10 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
         const float dy = gm.y - static_cast<float>(py0 + 4 * k);
         const float om = 1.0f - au[k];
         T[k] *= __builtin_amdgcn_rcpf(om);
-        const float dal = T[k] * (cg[k] - rr[k]);
+        const float d = cg[k] - rr[k];
+        const float dal = T[k] * d;
         w[k] = au[k] * T[k];
-        rr[k] = fmaf(au[k], cg[k], om * rr[k]);
+        rr[k] = fmaf(au[k], d, rr[k]);  // alpha c + (1 - alpha) rr
         const float gp = gate[k] * dal;
         s0 += gp;
         s1 = fmaf(dy, gp, s1);
@@ -279,12 +291,12 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
       float a[kRec];
       {
         const float sx = dx * s0;
-        a[0] = -(gc.x * sx + gc.y * s1);
-        a[1] = -(gc.y * sx + gc.z * s1);
+        a[0] = gc.x * sx + gc.y * s1;  // gc holds -A, -B, -C and 1 / o
+        a[1] = gc.y * sx + gc.z * s1;
         a[2] = -0.5f * (dx * sx);
         a[3] = -(dx * s1);
         a[4] = -0.5f * s2;
-        a[5] = gc.w > 0.0f ? s0 * __builtin_amdgcn_rcpf(gc.w) : 0.0f;
+        a[5] = s0 * gc.w;
         a[6] = 0.0f;
         a[7] = 0.0f;
 #pragma unroll

@@ -84,6 +84,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
       keep = kCulled || tile_reachable(m.x, m.y, co.x, co.y, co.z, co.w, X0, X1, Y0, Y1);
     }
     const uint64_t km = __ballot(keep);
+    const int cnt = __popcll(km);
     if (keep) {
       const int slot = __popcll(km & lt);
       s_xy[slot] = m;
@@ -94,43 +95,61 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
         s_fv[slot] = fv;
       }
     }
+    if (lane >= cnt && lane < pad_to(cnt)) {
+      // padding up to a whole group (the lane may also have filled a slot
+      // below cnt): opacity 0 gives alpha = 0, which no pixel uses, and
+      // finite values keep the blends' products at 0
+      s_xy[lane] = make_float2(0.0f, 0.0f);
+      s_co[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      s_rgb[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (kCh) {
+        s_z[lane] = 0.0f;
+        s_fv[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+    }
     __syncthreads();
-    const int cnt = __popcll(km);
-    for (int j = 0; j < cnt; ++j) {
+    // Pairs go in groups of kGroup with one test for a finished wave per
+    // group, so the pixels' active flags stay in scalar lane masks through a
+    // group instead of being carried in vector registers from pair to pair.
+    for (int j0 = 0; j0 < cnt; j0 += kGroup) {
       if (!__any(act[0] || act[1] || act[2] || act[3])) break;
-      const float2 gm = s_xy[j];
-      const float4 gc = s_co[j];
-      const float4 cc = s_rgb[j];
-      const float gz = kCh ? s_z[j] : 0.0f;
-      const float4 gv = kCh ? s_fv[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      const int pos = __float_as_int(cc.w);
-      const float dx = gm.x - fpx;
-      const float c1 = gc.y * dx, c0 = (gc.x * dx) * dx;
 #pragma unroll
-      for (int k = 0; k < kPix; ++k) {
-        if (kCount) evaluated += act[k] ? 1 : 0;
-        const float dy = gm.y - static_cast<float>(py0 + 4 * k);
-        const float p2 = pair_exp2(gc.z, c1, c0, dy);
-        const float alpha = fminf(kAlphaMax, gc.w * __builtin_amdgcn_exp2f(p2));
-        const bool ok = act[k] && !(p2 > 0.0f) && !(alpha < kAlphaMin);
-        const float Tn = T[k] * (1.0f - alpha);
-        const bool stop = ok && Tn < kTMin;
-        const bool use = ok && !stop;
-        const float w = use ? alpha * T[k] : 0.0f;
-        Cr[k] = fmaf(cc.x, w, Cr[k]);
-        Cg[k] = fmaf(cc.y, w, Cg[k]);
-        Cb[k] = fmaf(cc.z, w, Cb[k]);
-        if (kCh) {
-          Dz[k] = fmaf(gz, w, Dz[k]);
-          Aw[k] += w;
-          V0[k] = fmaf(gv.x, w, V0[k]);
-          V1[k] = fmaf(gv.y, w, V1[k]);
-          V2[k] = fmaf(gv.z, w, V2[k]);
-          Rh[k] = fmaf(gv.w, w, Rh[k]);
+      for (int u = 0; u < kGroup; ++u) {
+        const int j = j0 + u;
+        const float2 gm = s_xy[j];
+        const float4 gc = s_co[j];
+        const float4 cc = s_rgb[j];
+        const float gz = kCh ? s_z[j] : 0.0f;
+        const float4 gv = kCh ? s_fv[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const int pos = __float_as_int(cc.w);
+        const float dx = gm.x - fpx;
+        const float c1 = gc.y * dx, c0 = (gc.x * dx) * dx;
+#pragma unroll
+        for (int k = 0; k < kPix; ++k) {
+          if (kCount) evaluated += (act[k] && j < cnt) ? 1 : 0;
+          const float dy = gm.y - static_cast<float>(py0 + 4 * k);
+          const float p2 = pair_exp2(gc.z, c1, c0, dy);
+          const float alpha = fminf(kAlphaMax, gc.w * __builtin_amdgcn_exp2f(p2));
+          const bool ok = act[k] && !(p2 > 0.0f) && !(alpha < kAlphaMin);
+          const float Tn = T[k] * (1.0f - alpha);
+          const bool stop = ok && Tn < kTMin;
+          const bool use = ok && !stop;
+          const float w = use ? alpha * T[k] : 0.0f;
+          Cr[k] = fmaf(cc.x, w, Cr[k]);
+          Cg[k] = fmaf(cc.y, w, Cg[k]);
+          Cb[k] = fmaf(cc.z, w, Cb[k]);
+          if (kCh) {
+            Dz[k] = fmaf(gz, w, Dz[k]);
+            Aw[k] += w;
+            V0[k] = fmaf(gv.x, w, V0[k]);
+            V1[k] = fmaf(gv.y, w, V1[k]);
+            V2[k] = fmaf(gv.z, w, V2[k]);
+            Rh[k] = fmaf(gv.w, w, Rh[k]);
+          }
+          T[k] = use ? Tn : T[k];
+          last[k] = use ? pos : last[k];
+          act[k] = act[k] && !stop;
         }
-        T[k] = use ? Tn : T[k];
-        last[k] = use ? pos : last[k];
-        act[k] = act[k] && !stop;
       }
     }
     __syncthreads();
@@ -181,7 +200,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
   const uint32_t* __restrict__ vals = lists.vals;
   const uint32_t* __restrict__ ranges = lists.ranges;
   __shared__ float2 s_xy[64];
-  __shared__ float4 s_co[64];
+  __shared__ float4 s_co[64];   // -A, -B, -C and 1 / o
   __shared__ float4 s_q[64];    // pair_coefs of the conic and the opacity
   __shared__ float4 s_rgb[64];  // rgb and the 0-based list position (as int bits)
   __shared__ uint32_t s_g[64];
@@ -277,7 +296,9 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       const int slot = __popcll(km & lt);
       s_g[slot] = g;
       s_xy[slot] = m;
-      s_co[slot] = co;
+      // the negated conic and 1 / o for the record sums (one reciprocal per
+      // Gaussian and batch rather than per pair)
+      s_co[slot] = make_float4(-co.x, -co.y, -co.z, co.w > 0.0f ? __builtin_amdgcn_rcpf(co.w) : 0.0f);
       s_q[slot] = pair_coefs(co.x, co.y, co.z, co.w);
       s_rgb[slot] = c;
       if (kCh) {
@@ -327,7 +348,8 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
           cg = fmaf(gf.z, gv2[k], cg);
           cg = fmaf(gf.w, gh[k], cg);
         }
-        const float dal = T[k] * (cg - rr[k]);
+        const float d = cg - rr[k];
+        const float dal = T[k] * d;
         const float w = au * T[k];
         cr = fmaf(w, gr[k], cr);
         cgr = fmaf(w, gg[k], cgr);
@@ -339,7 +361,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
           cv2 = fmaf(w, gv2[k], cv2);
           ch = fmaf(w, gh[k], ch);
         }
-        rr[k] = fmaf(au, cg, om * rr[k]);
+        rr[k] = fmaf(au, d, rr[k]);  // alpha c + (1 - alpha) rr
         const float gp = (raw > kAlphaMax ? 0.0f : au) * dal;
         s0 += gp;
         s1 = fmaf(dy, gp, s1);
@@ -351,12 +373,12 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
       float a[16];
       {
         const float sx = dx * s0;
-        a[0] = -(gc.x * sx + gc.y * s1);
-        a[1] = -(gc.y * sx + gc.z * s1);
+        a[0] = gc.x * sx + gc.y * s1;  // gc holds -A, -B, -C
+        a[1] = gc.y * sx + gc.z * s1;
         a[2] = -0.5f * (dx * sx);
         a[3] = -(dx * s1);
         a[4] = -0.5f * s2;
-        a[5] = gc.w > 0.0f ? s0 * __builtin_amdgcn_rcpf(gc.w) : 0.0f;
+        a[5] = s0 * gc.w;  // gc.w = 1 / o (0 for o = 0)
         a[6] = cr;
         a[7] = cgr;
         a[8] = cb;
