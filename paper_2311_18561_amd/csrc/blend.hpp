@@ -7,9 +7,27 @@
 
 namespace pvg {
 
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
-  const int64_t per = (total + 7) / 8;
-  return (b % 8) * per + b / 8;
+// Tiles are dealt to the eight XCDs (which receive workgroups round-robin)
+// in chunks of xcd_chunk(total) consecutive tiles, about one tile row of a
+// 1920-pixel view: chunk k goes to XCD k mod 8.  Each XCD then sees the
+// image's whole mix of light and heavy tiles (with one band of rows per XCD,
+// the XCDs holding the densest rows kept working long after the others),
+// while a chunk's tiles, which share many Gaussians, stay in one XCD's L2.
+// `total` is the launch's tile capacity (the same on host and device); the
+// grid is render_grid(total) blocks, and blocks whose tile is past the live
+// count return at once.
+__host__ __device__ __forceinline__ int64_t xcd_chunk(int64_t total) {
+  const int64_t c = total / 80;
+  return c < 1 ? 1 : (c > 120 ? 120 : c);
+}
+__host__ __device__ __forceinline__ int64_t render_grid(int64_t total) {
+  const int64_t span = 8 * xcd_chunk(total);
+  return (total + span - 1) / span * span;
+}
+__host__ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t total) {
+  const int64_t c = xcd_chunk(total);
+  const int64_t q = b >> 3, x = b & 7;
+  return ((q / c) * 8 + x) * c + q % c;
 }
 
 __device__ __forceinline__ float wave_sum(float x) {

@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(64) k_feat_fwd(ViewSet vs, Geom geom, const ui
   __shared__ int s_pos[64];
   __shared__ float4 s_f[64][kQ];
   const int64_t ntiles = live_tiles(vs);
-  const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+  const int64_t tile = xcd_tile(blockIdx.x, vs.total_tiles);
   if (tile >= ntiles) return;
   const View& v = vs.one;
   const int tx = static_cast<int>(tile % v.GX), ty = static_cast<int>(tile / v.GX);
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
   __shared__ float4 s_acc[64][kRec / 4];
   __shared__ int s_any[64];
   const int64_t ntiles = live_tiles(vs);
-  const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+  const int64_t tile = xcd_tile(blockIdx.x, vs.total_tiles);
   if (tile >= ntiles) return;
   const View& v = vs.one;
   const int tx = static_cast<int>(tile % v.GX), ty = static_cast<int>(tile / v.GX);
@@ -382,7 +382,7 @@ namespace {
 template <int kNC>
 hipError_t fwd_at(const ViewSet& vs, const Geom& geom, const uint32_t* vals, const uint32_t* ranges, bool culled,
                   const float* feat, int64_t ld, int nch, float* out, hipStream_t s) {
-  const dim3 grid(static_cast<unsigned>(((vs.total_tiles + 7) / 8) * 8));
+  const dim3 grid(static_cast<unsigned>(render_grid(vs.total_tiles)));
   auto k = culled ? k_feat_fwd<kNC, true> : k_feat_fwd<kNC, false>;
   hipLaunchKernelGGL(k, grid, dim3(64), 0, s, vs, geom, vals, ranges, feat, ld, nch, out);
   return hipGetLastError();
@@ -396,7 +396,7 @@ hipError_t bwd_at(const ViewSet& vs, const Geom& geom, const Lists& lists, const
     StageScope scope(PVG_STAGE_RENDER_BWD, s);
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(vis), 0u, vis_bytes / 4, s);
     if (e != hipSuccess) return e;
-    const dim3 grid(static_cast<unsigned>(((vs.total_tiles + 7) / 8) * 8));
+    const dim3 grid(static_cast<unsigned>(render_grid(vs.total_tiles)));
     auto k = lists.culled ? k_feat_bwd<kNC, true> : k_feat_bwd<kNC, false>;
     hipLaunchKernelGGL(k, grid, dim3(64), 0, s, vs, geom, lists, feat, ld, nch, dout, rec, vis);
     e = hipGetLastError();

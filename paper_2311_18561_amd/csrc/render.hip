@@ -18,9 +18,9 @@
 // at the memory side on this chip and cost three times the rest of the
 // kernel, and the atomic-free sums are bitwise reproducible.
 //
-// Tiles are assigned so that each of the eight XCDs (which receive workgroups
-// round-robin) works on one contiguous band of tiles, keeping the Gaussians
-// shared by neighbouring tiles in that XCD's L2.
+// Tiles reach the eight XCDs in row-sized chunks dealt round-robin
+// (xcd_tile), which balances the XCDs' work and keeps a chunk's shared
+// Gaussians in one L2.
 #include "blend.hpp"
 
 namespace pvg {
@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(64) k_render_fwd(ViewSet vs, Geom geom, const 
   __shared__ float s_z[kCh ? 64 : 1];
   __shared__ float4 s_fv[kCh ? 64 : 1];  // v~ and rho
   const int64_t ntiles = live_tiles(vs);
-  const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+  const int64_t tile = xcd_tile(blockIdx.x, vs.total_tiles);
   if (tile >= ntiles) return;
   const View& v = view_at(vs, view_of_tile(vs, tile));
   const int64_t local = tile - v.tile_off;
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(64) k_render_bwd(ViewSet vs, Geom geom, Lists 
   __shared__ int s_any[64];
   constexpr int kSums = kCh ? 14 : 9;  // also the record stride
   const int64_t ntiles = live_tiles(vs);
-  const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+  const int64_t tile = xcd_tile(blockIdx.x, vs.total_tiles);
   if (tile >= ntiles) return;
   const View& v = view_at(vs, view_of_tile(vs, tile));
   const int64_t local = tile - v.tile_off;
@@ -496,7 +496,7 @@ hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t
                              bool culled, hipStream_t s) {
   if (vs.total_tiles == 0) return hipSuccess;
   StageScope scope(PVG_STAGE_RENDER_FWD, s);
-  const dim3 grid(static_cast<unsigned>(((vs.total_tiles + 7) / 8) * 8));
+  const dim3 grid(static_cast<unsigned>(render_grid(vs.total_tiles)));
   unsigned long long* cnt = profile_work_counter(PVG_STAGE_RENDER_FWD);
   // channels are single-view only
   const bool depth = !vs.table && (vs.one.depth_img || vs.one.vbar_img || vs.one.rho_img);
@@ -520,7 +520,7 @@ hipError_t launch_render_bwd(const ViewSet& vs, const Geom& geom, const Lists& l
     // clear the flags (a fill kernel: no memset node in a captured graph)
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(vis), 0u, vis_bytes / 4, s);
     if (e != hipSuccess) return e;
-    const dim3 grid(static_cast<unsigned>(((vs.total_tiles + 7) / 8) * 8));
+    const dim3 grid(static_cast<unsigned>(render_grid(vs.total_tiles)));
     unsigned long long* cnt = profile_work_counter(PVG_STAGE_RENDER_BWD);
     auto k = ch ? (cnt ? (culled ? k_render_bwd<true, true, true> : k_render_bwd<true, false, true>)
                        : (culled ? k_render_bwd<false, true, true> : k_render_bwd<false, false, true>))

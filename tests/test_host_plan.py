@@ -37,3 +37,19 @@ def test_first_view_alone_when_views_exceed_lanes(plan):
     assert plan(6, 3)[0] == [0, 1, 3, 6]
     assert plan(3, 3)[0] == [0, 3]
     assert plan(7, 3)[0] == [0, 1, 3, 6, 7]
+
+
+def test_compositing_tile_map_is_a_balanced_bijection(tmp_path):
+    """The block -> tile map of the compositing launches (blend.hpp), built
+    for the host: each tile exactly once for every capacity up to 40000
+    tiles, and the XCDs' shares within one chunk of each other."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = str(tmp_path / "tile_map_check")
+    subprocess.run(["/opt/rocm/bin/hipcc", "-std=c++17", "-O1", "-I", os.path.join(root, "include"), "-I",
+                    os.path.join(root, "paper_2311_18561_amd", "csrc"), "-o", exe,
+                    os.path.join(root, "tests", "host", "tile_map_check.cpp")], check=True, capture_output=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "tile map ok" in r.stdout
