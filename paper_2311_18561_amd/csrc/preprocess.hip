@@ -137,15 +137,7 @@ __device__ __forceinline__ void adjoint_view(const View& v, int64_t i, const Pro
     float draw[3];
     for (int ch = 0; ch < 3; ++ch) draw[ch] = signbit(rgb[ch]) ? 0.0f : g[6 + ch];
     float wk[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      float w = 0.0f;
-      if (k < K)
-        for (int ch = 0; ch < 3; ++ch) w += s.sh[(3 * k + ch) * n + i] * draw[ch];
-      wk[k] = w;
-      // read the coefficients four at a time rather than all 48 at once
-      if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-    }
+    sh_weights(s, i, draw, wk);
     float dd[3];
     sh_grad_basis(s.degree, P.dir[0], P.dir[1], P.dir[2], wk, dd);
     const float proj = P.dir[0] * dd[0] + P.dir[1] * dd[1] + P.dir[2] * dd[2];

@@ -251,6 +251,67 @@ __device__ __forceinline__ void tile_bounds(int tx, int ty, int W, int H, float&
 // o~(t) (Eq. (7)), with the velocity and the flow factor exp(-beta / (2 l))
 // of Eq. (10) (evaluated on first use).  Views of one training step share t,
 // so a kernel that handles several views of a Gaussian forms this once.
+// SH evaluation with the coefficient loads batched: K is a template
+// parameter, so no run-time bound separates the loads (one made each row of
+// three a separate round trip to memory).  They go kShGroup rows at a time
+// (a smaller group holds fewer registers; all 16 rows at once measured
+// fastest for the adjoint at degree 3).
+constexpr int kShGroup = 16;
+
+// sum_k sh_k,ch Y_k for the three channels, k ascending.
+template <int K>
+__device__ __forceinline__ void sh_colour_k(const Scene& s, int64_t i, const float Y[16], float out[3]) {
+  const float* __restrict__ sh = s.sh;
+  float acc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += kShGroup) {
+    float c[3 * kShGroup];
+#pragma unroll
+    for (int j = 0; j < 3 * kShGroup; ++j)
+      if (k0 * 3 + j < 3 * K) c[j] = sh[(k0 * 3 + j) * s.n + i];
+#pragma unroll
+    for (int k = 0; k < kShGroup; ++k)
+      if (k0 + k < K)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) acc[ch] += c[3 * k + ch] * Y[k0 + k];
+  }
+  for (int ch = 0; ch < 3; ++ch) out[ch] = acc[ch];
+}
+__device__ __forceinline__ void sh_colour(const Scene& s, int64_t i, const float Y[16], float out[3]) {
+  switch (s.degree) {
+    case 0: sh_colour_k<1>(s, i, Y, out); break;
+    case 1: sh_colour_k<4>(s, i, Y, out); break;
+    case 2: sh_colour_k<9>(s, i, Y, out); break;
+    default: sh_colour_k<16>(s, i, Y, out); break;
+  }
+}
+
+// w_k = sum_ch sh_k,ch d_ch (ch ascending) for k < K, 0 above.
+template <int K>
+__device__ __forceinline__ void sh_weights_k(const Scene& s, int64_t i, const float d[3], float w[16]) {
+  const float* __restrict__ sh = s.sh;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) w[k] = 0.0f;
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += kShGroup) {
+    float c[3 * kShGroup];
+#pragma unroll
+    for (int j = 0; j < 3 * kShGroup; ++j)
+      if (k0 * 3 + j < 3 * K) c[j] = sh[(k0 * 3 + j) * s.n + i];
+#pragma unroll
+    for (int k = 0; k < kShGroup; ++k)
+      if (k0 + k < K) w[k0 + k] = (c[3 * k] * d[0] + c[3 * k + 1] * d[1]) + c[3 * k + 2] * d[2];
+  }
+}
+__device__ __forceinline__ void sh_weights(const Scene& s, int64_t i, const float d[3], float w[16]) {
+  switch (s.degree) {
+    case 0: sh_weights_k<1>(s, i, d, w); break;
+    case 1: sh_weights_k<4>(s, i, d, w); break;
+    case 2: sh_weights_k<9>(s, i, d, w); break;
+    default: sh_weights_k<16>(s, i, d, w); break;
+  }
+}
+
 struct GaussTime {
   float t;        // the time it was formed for
   float mt[3];    // mu~(t)
@@ -407,11 +468,10 @@ __device__ __forceinline__ bool project_view(const View& v, int64_t i, GaussTime
     view_direction(v, P);
     float Y[16];
     sh_eval_basis(s.degree, P.dir[0], P.dir[1], P.dir[2], Y);
-    const int K = (s.degree + 1) * (s.degree + 1);
+    float sum[3];
+    sh_colour(s, i, Y, sum);
     for (int ch = 0; ch < 3; ++ch) {
-      float acc = 0.0f;
-      for (int k = 0; k < K; ++k) acc += s.sh[(3 * k + ch) * n + i] * Y[k];
-      const float raw = acc + 0.5f;
+      const float raw = sum[ch] + 0.5f;
       if (raw < 0.0f) {  // clamped: stored as -0, which composites like +0 and marks the clamp
         P.flags |= (kClampR << ch);
         P.rgb[ch] = -0.0f;
