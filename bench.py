@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="after the warm-up run only the serial per-stage pass (the one the roofline's kernel "
+                         "times come from) and print its stage times: the run to put under a kernel profiler")
     return ap.parse_args()
 
 
@@ -84,7 +87,7 @@ def stage_bytes(stage, n, n_vis, M, Lst, visited, K, tiles, tile_passes, views=1
 # stages that are one kernel each (the roofline is reported for the dominant one)
 SINGLE_KERNEL = {"preprocess": "k_preprocess", "render_fwd": "k_render_fwd", "render_bwd": "k_render_bwd",
                  "grad_gather": "k_grad_gather", "preprocess_bwd": "k_preprocess_bwd"}
-KERNEL_SOURCES = ("render.hip", "preprocess.hip", "pvg_math.hpp", "pvg_internal.hpp")
+KERNEL_SOURCES = ("render.hip", "blend.hpp", "preprocess.hip", "pvg_math.hpp", "pvg_internal.hpp")
 
 
 def kernel_source_digest():
@@ -465,7 +468,6 @@ def main():
         print(f"# copy probe: {args.copy_mib} MiB read + {args.copy_mib} MiB written", file=sys.stderr, flush=True)
         del src, dst
 
-    # timed region: K training-shaped steps, stage events on the launch stream
     import ctypes as C
 
     def read_stages():
@@ -476,6 +478,52 @@ def main():
             out[name] = {"ms": ms.value, "calls": calls.value, "work": work.value}
         return out
 
+    # Per-kernel durations come from a separate pass that runs the same six
+    # renders one view at a time (single-view calls on one stream), since the
+    # timed step overlaps views and a shared GPU stretches each launch.
+    def serial_step():
+        for p in params:
+            p.grad = None
+        loss = None
+        for (cam, tt, d), tgt in zip(views, view_targets):
+            l1 = (pvg.pvg_render(params, cam, tt, d, recompute=False) - tgt).abs().mean()
+            loss = l1 if loss is None else loss + l1
+        loss.backward()
+
+    def serial_stage_pass():
+        serial_steps = 2
+        serial_step()
+        torch.cuda.synchronize()
+        lib.pvg_profile_reset()
+        lib.pvg_profile_enable(1)
+        for _ in range(serial_steps):
+            serial_step()
+        torch.cuda.synchronize()
+        lib.pvg_profile_collect()
+        lib.pvg_profile_enable(0)
+        stages = read_stages()
+        lib.pvg_profile_reset()
+        # one more serial step with the render kernels counting evaluated pairs
+        # (the counts are deterministic: same inputs, same pairs)
+        lib.pvg_profile_enable(2)
+        serial_step()
+        torch.cuda.synchronize()
+        lib.pvg_profile_collect()
+        lib.pvg_profile_enable(0)
+        counted = read_stages()
+        lib.pvg_profile_reset()
+        for name in ("render_fwd", "render_bwd"):
+            if counted[name]["calls"]:
+                stages[name]["work"] = counted[name]["work"] / counted[name]["calls"] * stages[name]["calls"]
+        return stages
+
+    if args.profile_pass:
+        stages = serial_stage_pass()
+        print(json.dumps({"profile_pass": {k: {"ms_per_call": v["ms"] / max(v["calls"], 1), "calls": v["calls"],
+                                                "work": v["work"]} for k, v in stages.items()}}), flush=True)
+        return
+
+    # timed region: K training-shaped steps, stage events on the launch stream
     # each step's span on the launch stream from events recorded between the
     # steps (no synchronisation inside the timed region), and the host time
     # each step takes to return
@@ -497,42 +545,7 @@ def main():
     host_ms = sorted(h * 1e3 for h in host_s)
     policy_recompute = render_mod.last_recompute
 
-    # Per-kernel durations come from a separate pass that runs the same six
-    # renders one view at a time (single-view calls on one stream), since the
-    # timed step overlaps views and a shared GPU stretches each launch.
-    def serial_step():
-        for p in params:
-            p.grad = None
-        loss = None
-        for (cam, tt, d), tgt in zip(views, view_targets):
-            l1 = (pvg.pvg_render(params, cam, tt, d, recompute=False) - tgt).abs().mean()
-            loss = l1 if loss is None else loss + l1
-        loss.backward()
-
-    serial_steps = 2
-    serial_step()
-    torch.cuda.synchronize()
-    lib.pvg_profile_reset()
-    lib.pvg_profile_enable(1)
-    for _ in range(serial_steps):
-        serial_step()
-    torch.cuda.synchronize()
-    lib.pvg_profile_collect()
-    lib.pvg_profile_enable(0)
-    stages = read_stages()
-    lib.pvg_profile_reset()
-    # one more serial step with the render kernels counting evaluated pairs
-    # (the counts are deterministic: same inputs, same pairs)
-    lib.pvg_profile_enable(2)
-    serial_step()
-    torch.cuda.synchronize()
-    lib.pvg_profile_collect()
-    lib.pvg_profile_enable(0)
-    counted = read_stages()
-    lib.pvg_profile_reset()
-    for name in ("render_fwd", "render_bwd"):
-        if counted[name]["calls"]:
-            stages[name]["work"] = counted[name]["work"] / counted[name]["calls"] * stages[name]["calls"]
+    stages = serial_stage_pass()
 
     # the same step with the lists rebuilt in the backward (memory O(N + pixels + one view's instances))
     train_step(recompute=True)
