@@ -22,18 +22,26 @@
 namespace pvg {
 
 // The projected record of Gaussian i of view v at slot gi of geom, from its
-// time state and covariance.
-__device__ __forceinline__ void preprocess_view(const View& v, int64_t i, GaussTime& G, GaussCov& C,
-                                                const Geom& geom, int64_t gi) {
+// time state and covariance.  With `dir` the colour is left to the caller:
+// for a visible Gaussian the view direction goes to dir and the function
+// returns true (the rgb slots are written only for an invisible one).
+template <bool kDir = false>
+__device__ __forceinline__ bool preprocess_view(const View& v, int64_t i, GaussTime& G, GaussCov& C,
+                                                const Geom& geom, int64_t gi, float3* dir = nullptr) {
   Proj P;
-  const bool vis = project_view(v, i, G, C, P, true);
+  const bool vis = project_view(v, i, G, C, P, !kDir);
   geom.depth[gi] = P.p[2];
   if (vis) {
     reinterpret_cast<float2*>(geom.xy)[gi] = make_float2(P.x, P.y);
     reinterpret_cast<float4*>(geom.conic_op)[gi] = make_float4(P.A, P.B, P.C, P.op);
-    geom.rgb[3 * gi] = P.rgb[0];
-    geom.rgb[3 * gi + 1] = P.rgb[1];
-    geom.rgb[3 * gi + 2] = P.rgb[2];
+    if (kDir) {
+      view_direction(v, P);
+      *dir = make_float3(P.dir[0], P.dir[1], P.dir[2]);
+    } else {
+      geom.rgb[3 * gi] = P.rgb[0];
+      geom.rgb[3 * gi + 1] = P.rgb[1];
+      geom.rgb[3 * gi + 2] = P.rgb[2];
+    }
     geom.radius[gi] = P.radius;
     geom.tiles[gi] = static_cast<uint32_t>((P.rect[2] - P.rect[0]) * (P.rect[3] - P.rect[1]));
   } else {
@@ -52,6 +60,7 @@ __device__ __forceinline__ void preprocess_view(const View& v, int64_t i, GaussT
     reinterpret_cast<float4*>(geom.feat)[gi] =
         make_float4(sc.vel[i] * e, sc.vel[sc.n + i] * e, sc.vel[2 * sc.n + i] * e, beta / l);
   }
+  return vis;
 }
 
 __global__ void __launch_bounds__(256) k_preprocess(ViewSet vs, Geom geom, unsigned long long* dummy) {
@@ -67,10 +76,39 @@ __global__ void __launch_bounds__(256) k_preprocess(ViewSet vs, Geom geom, unsig
   (void)dummy;
 }
 
+// The clamped SH colours of Gaussian i in the views whose bit is set in
+// `vis` (view directions in dir), its 3K coefficients loaded once for all of
+// them; per view the operations of project_view's colour, in its order.
+template <int K>
+__device__ __forceinline__ void view_colours(const PreViews& pk, int64_t i, const float3 (&dir)[kMaxBwdViews],
+                                             uint32_t vis) {
+  const Scene& s = pk.views[0].s;
+  float c[3 * K];
+#pragma unroll
+  for (int j = 0; j < 3 * K; ++j) c[j] = s.sh[j * s.n + i];
+#pragma unroll
+  for (int k = 0; k < kMaxBwdViews; ++k) {
+    if (!((vis >> k) & 1u)) continue;
+    float Y[16];
+    sh_eval_basis(s.degree, dir[k].x, dir[k].y, dir[k].z, Y);
+    float* rgb = pk.geoms[k].rgb + 3 * i;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int q = 0; q < K; ++q) acc += c[3 * q + ch] * Y[q];
+      const float raw = acc + 0.5f;
+      rgb[ch] = raw < 0.0f ? -0.0f : raw;  // clamped: -0 marks the clamp
+    }
+  }
+}
+
 // Several views of one set of Gaussians: thread i takes Gaussian i through
 // every view of the pass, forming its time state once per distinct render
-// time and its covariance once; each view's record is the single-view one
-// (the same operations on the same values).
+// time and its covariance once; then, if any view sees it, its SH
+// coefficients are read once and its colour formed in each such view.  Each
+// view's record is the single-view one (the same operations on the same
+// values).
 __global__ void __launch_bounds__(256) k_preprocess_views(PreViews pk) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   const Scene& s = pk.views[0].s;
@@ -79,9 +117,22 @@ __global__ void __launch_bounds__(256) k_preprocess_views(PreViews pk) {
   GaussCov C;
   C.ready = false;
   gauss_time(s, i, pk.views[0].t, G);
-  for (int32_t k = 0; k < pk.nv; ++k) {
-    if (pk.views[k].t != G.t) gauss_time(s, i, pk.views[k].t, G);
-    preprocess_view(pk.views[k], i, G, C, pk.geoms[k], i);
+  float3 dir[kMaxBwdViews];
+  uint32_t vis = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxBwdViews; ++k) {
+    dir[k] = make_float3(0.0f, 0.0f, 1.0f);
+    if (k < pk.nv) {
+      if (pk.views[k].t != G.t) gauss_time(s, i, pk.views[k].t, G);
+      if (preprocess_view<true>(pk.views[k], i, G, C, pk.geoms[k], i, &dir[k])) vis |= 1u << k;
+    }
+  }
+  if (vis == 0) return;
+  switch (s.degree) {
+    case 0: view_colours<1>(pk, i, dir, vis); break;
+    case 1: view_colours<4>(pk, i, dir, vis); break;
+    case 2: view_colours<9>(pk, i, dir, vis); break;
+    default: view_colours<16>(pk, i, dir, vis); break;
   }
 }
 
