@@ -6,8 +6,8 @@
 // with mx = G*x, sxx = G*(x^2) - mx^2, sxy = G*(x y) - mx my (G* the window).
 // y (the target) takes no gradient.
 //
-// One 256-thread workgroup per 16 x 16 pixel tile and channel.  The forward
-// stages the tile's 26 x 26 halo of x and y in LDS, filters the five maps
+// One 256-thread workgroup per 32 x 32 pixel tile and channel.  The forward
+// stages the tile's 42 x 42 halo of x and y in LDS, filters the five maps
 // separably (rows into LDS, then columns), and writes S and the three
 // partial derivatives dS/dmx, dS/d(G*x^2), dS/d(G*xy) that the adjoint
 // needs.  The adjoint stages the upstream gradient times those partials on
@@ -22,9 +22,12 @@ namespace pvg {
 
 namespace {
 
-constexpr int kST = 16;            // tile side
 constexpr int kR = 5;              // window radius
-constexpr int kHalo = kST + 2 * kR;  // 26
+// 32 x 32 tiles (four outputs per thread): each kernel's haloed inputs are
+// the bulk of its reads, and a 42 x 42 halo is 1.7 times its tile where a
+// 26 x 26 one (16 x 16 tiles) is 2.6 times.
+constexpr int kT = 32;
+constexpr int kTH = kT + 2 * kR;  // 42
 constexpr float kC1 = 0.0001f, kC2 = 0.0009f;
 
 struct Window {
@@ -44,46 +47,21 @@ __device__ __forceinline__ int64_t band_tile(int64_t b, int64_t total) {
 // no decision depends on their rounding (the bar is a tolerance), and with
 // contraction off they were bound by the separate multiplies and adds of the
 // window sums and the IEEE division sequences.
-template <int kMaps>
-__device__ __forceinline__ void filter_tile(const float (*src)[kHalo][kHalo], float (*h)[kHalo][kST],
-                                            const Window& win, int tr, int tc, float out[kMaps]) {
-#pragma clang fp contract(fast)
-  // rows: kHalo x kST outputs per map, shared by the workgroup
-  for (int e = threadIdx.x; e < kHalo * kST; e += 256) {
-    const int r = e / kST, c = e % kST;
-#pragma unroll
-    for (int m = 0; m < kMaps; ++m) {
-      float acc = 0.0f;
-#pragma unroll
-      for (int k = 0; k <= 2 * kR; ++k) acc += win.w[k] * src[m][r][c + k];
-      h[m][r][c] = acc;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < kMaps; ++m) {
-    float acc = 0.0f;
-#pragma unroll
-    for (int k = 0; k <= 2 * kR; ++k) acc += win.w[k] * h[m][tr + k][tc];
-    out[m] = acc;
-  }
-}
-
 __global__ void __launch_bounds__(256) k_ssim_fwd(const float* __restrict__ x, const float* __restrict__ y, int H,
                                                   int W, int GX, int64_t ntiles, Window win,
                                                   float* __restrict__ smap, float* __restrict__ part) {
 #pragma clang fp contract(fast)
-  __shared__ float s_src[5][kHalo][kHalo];
-  __shared__ float s_h[5][kHalo][kST];
+  __shared__ float s_src[5][kTH][kTH];
+  __shared__ float s_h[5][kTH][kT];
   const int ch = blockIdx.y;
   const int64_t HW = static_cast<int64_t>(H) * W;
   const float* xc = x + ch * HW;
   const float* yc = y + ch * HW;
   const int64_t tile = band_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;  // the whole workgroup, before any barrier
-  const int x0 = static_cast<int>(tile % GX) * kST - kR, y0 = static_cast<int>(tile / GX) * kST - kR;
-  for (int e = threadIdx.x; e < kHalo * kHalo; e += 256) {
-    const int r = e / kHalo, c = e % kHalo;
+  const int x0 = static_cast<int>(tile % GX) * kT - kR, y0 = static_cast<int>(tile / GX) * kT - kR;
+  for (int e = threadIdx.x; e < kTH * kTH; e += 256) {
+    const int r = e / kTH, c = e % kTH;
     const int py = y0 + r, px = x0 + c;
     float a = 0.0f, b = 0.0f;
     if (py >= 0 && py < H && px >= 0 && px < W) {
@@ -97,43 +75,64 @@ __global__ void __launch_bounds__(256) k_ssim_fwd(const float* __restrict__ x, c
     s_src[4][r][c] = a * b;
   }
   __syncthreads();
-  const int tr = threadIdx.x / kST, tc = threadIdx.x % kST;
-  float f[5];
-  filter_tile<5>(s_src, s_h, win, tr, tc, f);
-  const int py = y0 + kR + tr, px = x0 + kR + tc;
-  if (py >= H || px >= W) return;
-  const float mx = f[0], my = f[1];
-  const float sxx = f[2] - mx * mx, syy = f[3] - my * my, sxy = f[4] - mx * my;
-  const float A = 2.0f * mx * my + kC1, B = 2.0f * sxy + kC2;
-  const float Cc = mx * mx + my * my + kC1, D = sxx + syy + kC2;
-  // C >= C1 and D near sxx + syy + C2 > 0: neither is ever 0
-  const float iC = __builtin_amdgcn_rcpf(Cc), iD = __builtin_amdgcn_rcpf(D);
-  const float Q = iC * iD;
-  const float S = (A * B) * Q;
-  const int64_t o = ch * HW + static_cast<int64_t>(py) * W + px;
-  if (smap) smap[o] = S;
+  for (int e = threadIdx.x; e < kTH * kT; e += 256) {
+    const int r = e / kT, c = e % kT;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int k = 0; k <= 2 * kR; ++k) acc += win.w[k] * s_src[m][r][c + k];
+      s_h[m][r][c] = acc;
+    }
+  }
+  __syncthreads();
   const int64_t CHW = static_cast<int64_t>(gridDim.y) * HW;
-  // dS/dmx (through A, B, C, D), dS/d(G*x^2) (through D), dS/d(G*xy) (through
-  // B); no division by A or B, which may pass through 0
-  part[o] = 2.0f * my * (B - A) * Q + 2.0f * mx * S * (iD - iC);
-  part[CHW + o] = -S * iD;
-  part[2 * CHW + o] = 2.0f * A * Q;
+  const int tc = threadIdx.x % kT, tr0 = threadIdx.x / kT;  // rows tr0 + (256 / kT) j
+#pragma unroll
+  for (int j = 0; j < kT * kT / 256; ++j) {
+    const int tr = tr0 + (256 / kT) * j;
+    float f[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int k = 0; k <= 2 * kR; ++k) acc += win.w[k] * s_h[m][tr + k][tc];
+      f[m] = acc;
+    }
+    const int py = y0 + kR + tr, px = x0 + kR + tc;
+    if (py >= H || px >= W) continue;
+    const float mx = f[0], my = f[1];
+    const float sxx = f[2] - mx * mx, syy = f[3] - my * my, sxy = f[4] - mx * my;
+    const float A = 2.0f * mx * my + kC1, B = 2.0f * sxy + kC2;
+    const float Cc = mx * mx + my * my + kC1, D = sxx + syy + kC2;
+    // C >= C1 and D near sxx + syy + C2 > 0: neither is ever 0
+    const float iC = __builtin_amdgcn_rcpf(Cc), iD = __builtin_amdgcn_rcpf(D);
+    const float Q = iC * iD;
+    const float S = (A * B) * Q;
+    const int64_t o = ch * HW + static_cast<int64_t>(py) * W + px;
+    if (smap) smap[o] = S;
+    // dS/dmx (through A, B, C, D), dS/d(G*x^2) (through D), dS/d(G*xy) (through
+    // B); no division by A or B, which may pass through 0
+    part[o] = 2.0f * my * (B - A) * Q + 2.0f * mx * S * (iD - iC);
+    part[CHW + o] = -S * iD;
+    part[2 * CHW + o] = 2.0f * A * Q;
+  }
 }
 
 __global__ void __launch_bounds__(256) k_ssim_bwd(const float* __restrict__ g, const float* __restrict__ x,
                                                   const float* __restrict__ y, const float* __restrict__ part, int H,
                                                   int W, int GX, int64_t ntiles, Window win, float* __restrict__ dx) {
 #pragma clang fp contract(fast)
-  __shared__ float s_src[3][kHalo][kHalo];
-  __shared__ float s_h[3][kHalo][kST];
+  __shared__ float s_src[3][kTH][kTH];
+  __shared__ float s_h[3][kTH][kT];
   const int ch = blockIdx.y;
   const int64_t HW = static_cast<int64_t>(H) * W;
   const int64_t CHW = static_cast<int64_t>(gridDim.y) * HW;
   const int64_t tile = band_tile(blockIdx.x, ntiles);
   if (tile >= ntiles) return;  // the whole workgroup, before any barrier
-  const int x0 = static_cast<int>(tile % GX) * kST - kR, y0 = static_cast<int>(tile / GX) * kST - kR;
-  for (int e = threadIdx.x; e < kHalo * kHalo; e += 256) {
-    const int r = e / kHalo, c = e % kHalo;
+  const int x0 = static_cast<int>(tile % GX) * kT - kR, y0 = static_cast<int>(tile / GX) * kT - kR;
+  for (int e = threadIdx.x; e < kTH * kTH; e += 256) {
+    const int r = e / kTH, c = e % kTH;
     const int py = y0 + r, px = x0 + c;
     float q0 = 0.0f, q1 = 0.0f, q2 = 0.0f;
     if (py >= 0 && py < H && px >= 0 && px < W) {
@@ -148,13 +147,36 @@ __global__ void __launch_bounds__(256) k_ssim_bwd(const float* __restrict__ g, c
     s_src[2][r][c] = q2;
   }
   __syncthreads();
-  const int tr = threadIdx.x / kST, tc = threadIdx.x % kST;
-  float f[3];
-  filter_tile<3>(s_src, s_h, win, tr, tc, f);
-  const int py = y0 + kR + tr, px = x0 + kR + tc;
-  if (py >= H || px >= W) return;
-  const int64_t o = ch * HW + static_cast<int64_t>(py) * W + px;
-  dx[o] = f[0] + 2.0f * x[o] * f[1] + y[o] * f[2];
+  // rows: kTH x kT outputs per map
+  for (int e = threadIdx.x; e < kTH * kT; e += 256) {
+    const int r = e / kT, c = e % kT;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int k = 0; k <= 2 * kR; ++k) acc += win.w[k] * s_src[m][r][c + k];
+      s_h[m][r][c] = acc;
+    }
+  }
+  __syncthreads();
+  const int tc = threadIdx.x % kT, tr0 = threadIdx.x / kT;  // rows tr0 + 8 j
+#pragma unroll
+  for (int j = 0; j < kT / 8; ++j) {
+    const int tr = tr0 + 8 * j;
+    float f[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int k = 0; k <= 2 * kR; ++k) acc += win.w[k] * s_h[m][tr + k][tc];
+      f[m] = acc;
+    }
+    const int py = y0 + kR + tr, px = x0 + kR + tc;
+    if (py < H && px < W) {
+      const int64_t o = ch * HW + static_cast<int64_t>(py) * W + px;
+      dx[o] = f[0] + 2.0f * x[o] * f[1] + y[o] * f[2];
+    }
+  }
 }
 
 Window gaussian_window() {
@@ -174,7 +196,7 @@ Window gaussian_window() {
 hipError_t launch_ssim_fwd(const float* x, const float* y, int C, int H, int W, float* smap, float* part,
                            hipStream_t st) {
   if (static_cast<int64_t>(H) * W * C == 0) return hipSuccess;
-  const int GX = (W + kST - 1) / kST, GY = (H + kST - 1) / kST;
+  const int GX = (W + kT - 1) / kT, GY = (H + kT - 1) / kT;
   const int64_t ntiles = static_cast<int64_t>(GX) * GY;
   hipLaunchKernelGGL(k_ssim_fwd, dim3(static_cast<unsigned>(8 * ((ntiles + 7) / 8)), C), dim3(256), 0, st, x, y, H,
                      W, GX, ntiles, gaussian_window(), smap, part);
@@ -184,7 +206,7 @@ hipError_t launch_ssim_fwd(const float* x, const float* y, int C, int H, int W, 
 hipError_t launch_ssim_bwd(const float* g, const float* x, const float* y, const float* part, int C, int H, int W,
                            float* dx, hipStream_t st) {
   if (static_cast<int64_t>(H) * W * C == 0) return hipSuccess;
-  const int GX = (W + kST - 1) / kST, GY = (H + kST - 1) / kST;
+  const int GX = (W + kT - 1) / kT, GY = (H + kT - 1) / kT;
   const int64_t ntiles = static_cast<int64_t>(GX) * GY;
   hipLaunchKernelGGL(k_ssim_bwd, dim3(static_cast<unsigned>(8 * ((ntiles + 7) / 8)), C), dim3(256), 0, st, g, x, y,
                      part, H, W, GX, ntiles, gaussian_window(), dx);
