@@ -477,7 +477,7 @@ def main():
         imgs, dn, opac, vbar, _ = pvg.pvg_render_views(params, views, channels=True, normalized_depth=True,
                                                        densify_stats=(d_acc, d_cnt))
         jit = torch.rand((V, 2, H, W), device="cuda", generator=gch) - 0.5
-        final = torch.stack([pvg.pvg_sky_composite(imgs[k], opac[k], cube, views[k][0], jit[k]) for k in range(V)])
+        final = pvg.pvg_sky_composite_views(imgs, opac, cube, [v[0] for v in views], jit)
         o = opac.clamp(1e-6, 1.0 - 1e-6)
         inv = 1.0 / dn.clamp_min(1e-3)  # the inverse of the normalized depth
         loss = ((final - stacked_targets).abs().mean() * V + 0.1 * (sparse * (inv - inv_depth_target).abs()).mean()
@@ -649,8 +649,7 @@ def main():
         imgs, dn, opac, vbar, _ = pvg.pvg_render_views(train_params, vs, channels=True, normalized_depth=True,
                                                        densify_stats=(state["acc"], state["cnt"]))
         jit = torch.rand((Vf, 2, H, W), device="cuda", generator=gch) - 0.5
-        final = torch.stack([pvg.pvg_sky_composite(imgs[k], opac[k], train_cube, vs[k][0], jit[k])
-                             for k in range(Vf)])
+        final = pvg.pvg_sky_composite_views(imgs, opac, train_cube, [v[0] for v in vs], jit)
         o = opac.clamp(1e-6, 1.0 - 1e-6)
         inv = 1.0 / dn.clamp_min(1e-3)
         tg = stacked_targets[0::2]

@@ -482,9 +482,15 @@ int pvg_sky_composite(const pvg_camera* cam, const float* img, const float* opac
                       int32_t cube_res, const float* jitter, float* out, void* stream);
 /* Adjoint of pvg_sky_composite for dL_dout [3][H][W]: writes dL_dopacity
  * [H][W] (= -sum_c f_sky,c(d) dL_dout_c) and adds (1 - opacity) dL_dout times
- * the bilinear weights into dL_dcube [6][3][R][R] with float atomics (zero it
- * first for a fresh gradient; the order of the additions varies from run to
- * run).  dL/dimg is dL_dout itself. */
+ * the bilinear weights into dL_dcube [6][3][R][R] (zero it first for a fresh
+ * gradient; calls on one device add into it in stream order).  dL/dimg is
+ * dL_dout itself.  When a texel spans at most six pixels (2 max(fx, fy) / R
+ * <= 6) and R is a rotation to 1e-3, each 16 x 16 texel block is summed by
+ * one workgroup in 64-bit fixed point and written once: the result does not
+ * depend on the order of the additions, except for pixels whose jitter
+ * exceeds half a pixel, which are added with float atomics.  Coarser maps sum
+ * 16 x 16 pixel tiles the same way and add each tile's texels with float
+ * atomics. */
 int pvg_sky_composite_bwd(const pvg_camera* cam, const float* dL_dout, const float* opacity, const float* cube,
                           int32_t cube_res, const float* jitter, float* dL_dopacity, float* dL_dcube,
                           void* stream);

@@ -28,6 +28,7 @@ from .render import (  # noqa: F401
     pvg_render_views,
     pvg_render_semantic,
     pvg_sky_composite,
+    pvg_sky_composite_views,
     pvg_ssim,
     render,
     render_bwd,

@@ -805,6 +805,60 @@ def pvg_sky_composite(img, opacity, cube, cam: dict, jitter=None):
     return PVGSkyComposite.apply(img, opacity, cube, cam, jitter)
 
 
+class PVGSkyCompositeViews(torch.autograd.Function):
+    """The sky composite of V views of one size over one cube map: imgs
+    [V,3,H,W], opacities [V,H,W], jitter [V,2,H,W] or None.  The backward
+    adds every view's cube-map gradient into one array, so a step pays one
+    zero fill of the cube's gradient instead of one per view plus V - 1
+    sums of full-size arrays."""
+
+    @staticmethod
+    def forward(ctx, imgs, opacities, cube, cams, jitter):
+        cs = [camera_struct(c) for c in cams]
+        V = len(cs)
+        imgs, opacities, cube = imgs.contiguous(), opacities.contiguous(), cube.contiguous()
+        if V == 0 or any((c.width, c.height) != (cs[0].width, cs[0].height) for c in cs):
+            raise ValueError("pvg_sky_composite_views needs one or more views of one size")
+        H, W = int(cs[0].height), int(cs[0].width)
+        if imgs.shape != (V, 3, H, W) or opacities.shape != (V, H, W) or cube.dim() != 4 \
+                or cube.shape[:2] != (6, 3) or cube.shape[2] != cube.shape[3]:
+            raise ValueError("pvg_sky_composite_views needs imgs [V,3,H,W], opacities [V,H,W] and cube [6,3,R,R]")
+        for t in (imgs, opacities, cube):
+            if t.dtype != torch.float32 or not t.is_cuda:
+                raise ValueError("pvg_sky_composite_views takes float32 CUDA tensors")
+        if jitter is not None:
+            jitter = jitter.contiguous()
+            if jitter.shape != (V, 2, H, W) or jitter.dtype != torch.float32:
+                raise ValueError("jitter must be float32 [V,2,H,W]")
+        out = torch.empty_like(imgs)
+        lib, st, res = L.load(), _stream_handle(), int(cube.shape[-1])
+        for k in range(V):
+            L.check(lib.pvg_sky_composite(C.byref(cs[k]), _p(imgs[k]), _p(opacities[k]), _p(cube), res,
+                                          None if jitter is None else _p(jitter[k]), _p(out[k]), st))
+        ctx.cs = cs
+        ctx.save_for_backward(opacities, cube, jitter if jitter is not None else torch.empty(0, device=imgs.device))
+        ctx.has_jitter = jitter is not None
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        opacities, cube, jitter = ctx.saved_tensors
+        g = g.contiguous()
+        d_op = torch.empty_like(opacities)
+        d_cube = torch.zeros_like(cube)
+        lib, st, res = L.load(), _stream_handle(), int(cube.shape[-1])
+        for k, c in enumerate(ctx.cs):
+            L.check(lib.pvg_sky_composite_bwd(C.byref(c), _p(g[k]), _p(opacities[k]), _p(cube), res,
+                                              _p(jitter[k]) if ctx.has_jitter else None, _p(d_op[k]), _p(d_cube),
+                                              st))
+        return g, d_op, d_cube, None, None
+
+
+def pvg_sky_composite_views(imgs, opacities, cube, cams, jitter=None):
+    """C + (1 - O) f_sky(d) for V views of one size (see PVGSkyCompositeViews)."""
+    return PVGSkyCompositeViews.apply(imgs, opacities, cube, list(cams), jitter)
+
+
 class PVGSSIM(torch.autograd.Function):
     """The SSIM map of a render x against a target y (both [C,H,W] float32
     on the GPU; 11 x 11 Gaussian window, sigma 1.5): the forward keeps the

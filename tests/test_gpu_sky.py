@@ -22,10 +22,9 @@ def _needs_gpu():
 @pytest.mark.parametrize("jitter", [False, True])
 @pytest.mark.parametrize("res", [1, 7, 64, 1024])
 def test_sky_composite_vs_oracle(orc, jitter, res):
-    """The view crosses the +Z / +X face edge.  The adjoint sums a tile's
-    texels in LDS when they fit its box (cube sizes up to 64 here, several
-    pixels per texel) and adds to global memory directly otherwise (1024:
-    several texels per pixel, and the tiles across the face edge)."""
+    """The view crosses the +Z / +X face edge (fx = 156).  Cube sizes 1 and 7
+    (tens of pixels per texel) take the adjoint's scatter form, 64 and 1024
+    (4.9 and 0.3 pixels per texel) its gather form."""
     import paper_2311_18561_amd as pvg
     cam = gen.yaw_camera(200, 136, 40.0, (0.0, 0.0, 0.0))
     H, W = cam["height"], cam["width"]
@@ -130,3 +129,142 @@ def test_sky_full_frame_bench_cameras(orc, yaw):
           f"faces reached {faces}")
     assert err <= 1e-6
     assert worst <= 1.0
+
+
+def _sky_case(orc, cam, res, jit, seed, views=1):
+    """Composite and adjoint of `views` views (all at camera `cam`, each with
+    its own image, opacity, jitter and upstream gradient) over one cube map,
+    through pvg_sky_composite_views, against the oracle summed over views."""
+    import paper_2311_18561_amd as pvg
+    H, W = cam["height"], cam["width"]
+    rng = np.random.default_rng(seed)
+    img = rng.random((views, 3, H, W)).astype(np.float32)
+    opac = rng.random((views, H, W)).astype(np.float32)
+    cube = rng.random((6, 3, res, res)).astype(np.float32)
+    g = rng.standard_normal((views, 3, H, W)).astype(np.float32)
+    t_op = torch.from_numpy(opac).cuda().requires_grad_(True)
+    t_cube = torch.from_numpy(cube).cuda().requires_grad_(True)
+    t_jit = None if jit is None else torch.from_numpy(jit).cuda()
+    out = pvg.pvg_sky_composite_views(torch.from_numpy(img).cuda(), t_op, t_cube, [cam] * views, t_jit)
+    (out * torch.from_numpy(g).cuda()).sum().backward()
+    dC = np.zeros((6, 3, res, res))
+    dC_mag = np.zeros_like(dC)
+    for k in range(views):
+        jk = None if jit is None else jit[k]
+        ref = orc.sky_f64(img[k], opac[k], cube, cam, jk)
+        assert float(np.abs(out[k].detach().cpu().numpy() - ref).max()) <= 1e-6
+        dO, dCk = orc.sky_bwd_f64(g[k], opac[k], cube, cam, jk)
+        np.testing.assert_allclose(t_op.grad[k].cpu().numpy(), dO, rtol=1e-5, atol=1e-5)
+        dC += dCk
+        dC_mag += orc.sky_bwd_f64(np.abs(g[k]), opac[k], cube, cam, jk)[1]
+    worst, l2 = grad_tolerance_report(t_cube.grad.cpu().numpy(), dC, rel=1e-4, magnitude=dC_mag)
+    return worst, l2
+
+
+@pytest.mark.parametrize("res", [64, 1024])
+def test_sky_jitter_beyond_half_pixel(orc, res):
+    """Jitter up to 1.5 pixels (two thirds of the pixels beyond the half
+    pixel that the gather's pixel rectangles allow for): those pixels take
+    the per-pixel atomic pass, the rest the gather; every pixel's dL/dO and
+    every texel against the oracle."""
+    cam = gen.yaw_camera(200, 136, 40.0, (0.0, 0.0, 0.0))
+    rng = np.random.default_rng(res + 7)
+    jit = ((rng.random((1, 2, 136, 200)) - 0.5) * 3.0).astype(np.float32)
+    worst, l2 = _sky_case(orc, cam, res, jit, res + 8)
+    print(f"[sky wide jitter R={res}] cube grad worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+    assert worst <= 1.0
+
+
+@pytest.mark.parametrize("fx,res", [(None, 512), (150.0, 256), (150.0, 16)])
+def test_sky_pitched_camera(orc, fx, res):
+    """A camera pitched 70 degrees about x (the view centred near the +Y
+    face; at fx = 150 a 130-degree field that reaches several faces and
+    texel blocks partly behind the camera) at 640 x 480, three views over
+    one cube: the gather at 2 and 1.2 pixels per texel, the scatter at 19."""
+    import math
+    a = math.radians(70.0)
+    R = np.array([[1.0, 0.0, 0.0], [0.0, math.cos(a), -math.sin(a)], [0.0, math.sin(a), math.cos(a)]])
+    cam = gen.make_camera(640, 480, R=R, fx=fx)
+    rng = np.random.default_rng(res)
+    jit = (rng.random((3, 2, 480, 640)) - 0.5).astype(np.float32)
+    worst, l2 = _sky_case(orc, cam, res, jit, res + 1, views=3)
+    print(f"[sky pitched fx={fx} R={res}] cube grad worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+    assert worst <= 1.0
+
+
+def test_sky_full_frame_scatter(orc):
+    """The benchmark's frame (1920 x 1280, fx = 1500, yaw 45) over a coarse
+    128 x 128 cube map (23 pixels per texel): the scatter form at full size."""
+    cam = gen.yaw_camera(1920, 1280, 45.0, (0.0, 0.0, 50.0))
+    rng = np.random.default_rng(128)
+    jit = (rng.random((1, 2, 1280, 1920)) - 0.5).astype(np.float32)
+    worst, l2 = _sky_case(orc, cam, 128, jit, 129)
+    print(f"[sky 1920x1280 R=128] cube grad worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+    assert worst <= 1.0
+
+
+@pytest.mark.parametrize("scale", [1e-30, 1e30])
+def test_sky_gradient_extreme_scales(orc, scale):
+    """Upstream gradients of magnitude 1e-30 and 1e30: the fixed-point sums
+    take their scale from each block's bound, so the cube gradient keeps its
+    relative accuracy at both ends (gather at 64, scatter at 7)."""
+    import paper_2311_18561_amd as pvg
+    cam = gen.yaw_camera(200, 136, 40.0, (0.0, 0.0, 0.0))
+    H, W = cam["height"], cam["width"]
+    rng = np.random.default_rng(31)
+    opac = rng.random((H, W)).astype(np.float32)
+    jit = (rng.random((2, H, W)) - 0.5).astype(np.float32)
+    g = (rng.standard_normal((3, H, W)) * scale).astype(np.float32)
+    for res in (64, 7):
+        cube = rng.random((6, 3, res, res)).astype(np.float32)
+        t_op = torch.from_numpy(opac).cuda().requires_grad_(True)
+        t_cube = torch.from_numpy(cube).cuda().requires_grad_(True)
+        out = pvg.pvg_sky_composite(torch.zeros((3, H, W), device="cuda"), t_op, t_cube, cam,
+                                    torch.from_numpy(jit).cuda())
+        out.backward(torch.from_numpy(g).cuda())
+        dO, dC = orc.sky_bwd_f64(g, opac, cube, cam, jit)
+        _, dC_mag = orc.sky_bwd_f64(np.abs(g), opac, cube, cam, jit)
+        np.testing.assert_allclose(t_op.grad.cpu().numpy(), dO, rtol=1e-5, atol=1e-5 * scale)
+        worst, l2 = grad_tolerance_report(t_cube.grad.cpu().numpy(), dC, rel=1e-4, magnitude=dC_mag)
+        print(f"[sky scale {scale:g} R={res}] cube grad worst/tol = {worst:.3g}, l2 rel = {l2:.3g}")
+        assert worst <= 1.0
+
+
+def test_sky_nonfinite_gradient_and_repeatability(orc):
+    """A NaN and an infinity in the upstream gradient: the texels their
+    pixels reach come out non-finite as in the oracle (those blocks sum in
+    float) and every other texel matches it.  With finite inputs two runs
+    give the same cube gradient bit for bit (integer sums in the gather)."""
+    import paper_2311_18561_amd as pvg
+    cam = gen.yaw_camera(200, 136, 40.0, (0.0, 0.0, 0.0))
+    H, W = cam["height"], cam["width"]
+    rng = np.random.default_rng(37)
+    opac = rng.random((H, W)).astype(np.float32)
+    cube = rng.random((6, 3, 64, 64)).astype(np.float32)
+    jit = (rng.random((2, H, W)) - 0.5).astype(np.float32)
+    g = rng.standard_normal((3, H, W)).astype(np.float32)
+
+    def run(gg):
+        t_op = torch.from_numpy(opac).cuda().requires_grad_(True)
+        t_cube = torch.from_numpy(cube).cuda().requires_grad_(True)
+        out = pvg.pvg_sky_composite(torch.zeros((3, H, W), device="cuda"), t_op, t_cube, cam,
+                                    torch.from_numpy(jit).cuda())
+        out.backward(torch.from_numpy(gg).cuda())
+        return t_op.grad.cpu().numpy(), t_cube.grad.cpu().numpy()
+
+    a, b = run(g)[1], run(g)[1]
+    assert np.array_equal(a, b)
+    gb = g.copy()
+    gb[0, 40, 50] = np.nan
+    gb[2, 100, 150] = np.inf
+    dO_gpu, dC_gpu = run(gb)
+    dO, dC = orc.sky_bwd_f64(gb, opac, cube, cam, jit)
+    assert np.array_equal(np.isfinite(dC_gpu), np.isfinite(dC))
+    assert np.count_nonzero(~np.isfinite(dC)) > 0
+    fin = np.isfinite(dC)
+    _, dC_mag = orc.sky_bwd_f64(np.where(np.isfinite(gb), np.abs(gb), 0.0), opac, cube, cam, jit)
+    worst, _ = grad_tolerance_report(np.where(fin, dC_gpu, 0.0), np.where(fin, dC, 0.0), rel=1e-4,
+                                     magnitude=dC_mag)
+    assert worst <= 1.0
+    np.testing.assert_allclose(dO_gpu[np.isfinite(dO)], dO[np.isfinite(dO)], rtol=1e-5, atol=1e-5)
+    assert np.array_equal(np.isfinite(dO_gpu), np.isfinite(dO))
