@@ -19,6 +19,7 @@ single-threaded CPU oracle timed on a bounded sample are extra fields.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -493,6 +494,13 @@ def main():
         train_step()
         fwd_step()
     torch.cuda.synchronize()
+    # Python's cyclic collector: a full collection over the interpreter's
+    # objects (torch's included) stalls the host for 40-80 ms, once every few
+    # dozen steps, and the GPU waits for it.  Collect once now and move every
+    # live object to the permanent generation, so later collections only scan
+    # what the steps allocate.
+    gc.collect()
+    gc.freeze()
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)

@@ -38,8 +38,13 @@ namespace pvg {
 constexpr int kThreads = 256;
 constexpr int kScanItems = 4;                       // items per thread in the scans / compaction
 constexpr int kScanBlock = kThreads * kScanItems;   // 1024
-constexpr int kRsItems = 16;                        // items per thread in a radix pass
+constexpr int kRsItems = 16;                        // items per thread in a tile pass
 constexpr int kRsBlock = kThreads * kRsItems;       // 4096
+// Items per thread in a depth pass: 1024 keys a block, so that the visible
+// Gaussians of one view (0.58M in the benchmark) fill the chip: with 4096 the
+// passes had 142 blocks for 256 CUs, and their scatter ran at 0.5 TB/s.
+constexpr int kDepthItems = 4;
+constexpr int kDepthBlock = kThreads * kDepthItems;  // 1024
 // Digits of the depth passes.  Three passes of 11 bits measured slower than
 // four of 8 on the benchmark's 0.58M visible Gaussians (2048-digit block
 // scans and 11 ballots per key outweigh the saved pass).
@@ -177,22 +182,23 @@ __global__ void __launch_bounds__(kThreads) k_vis_compact(const uint32_t* __rest
 // ------------------------------------------------------------------ radix passes
 // kMaxBits: the widest digit a kernel instance handles (8 for the tile
 // passes, 11 for the depth passes: 32 bits in three passes); `bits` <= it.
-template <int kMaxBits>
+template <int kMaxBits, int kPer>
 __global__ void __launch_bounds__(kThreads) k_rs_hist(const uint32_t* __restrict__ keys, const uint32_t* n_dev,
                                                       int64_t n_host, int shift, int bits, uint32_t* hist,
                                                       int64_t cols) {
   constexpr int kR = 1 << kMaxBits;
+  constexpr int kBlock = kThreads * kPer;
   __shared__ uint32_t h[kR];
   const int64_t n = live_count(n_dev, n_host);
-  const int64_t nb = (n + kRsBlock - 1) / kRsBlock;
+  const int64_t nb = (n + kBlock - 1) / kBlock;
   const int radix = 1 << bits;
   const uint32_t mask = static_cast<uint32_t>(radix - 1);
   for (int64_t lb = blockIdx.x; lb < nb; lb += gridDim.x) {
     for (int d = threadIdx.x; d < radix; d += kThreads) h[d] = 0;
     __syncthreads();
-    const int64_t base = lb * kRsBlock + threadIdx.x;
+    const int64_t base = lb * kBlock + threadIdx.x;
 #pragma unroll 4
-    for (int k = 0; k < kRsItems; ++k) {
+    for (int k = 0; k < kPer; ++k) {
       const int64_t i = base + k * kThreads;
       if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
     }
@@ -202,12 +208,13 @@ __global__ void __launch_bounds__(kThreads) k_rs_hist(const uint32_t* __restrict
   }
 }
 
-// One block per digit: exclusive scan of that digit's block counts.
+// One block per digit: exclusive scan of that digit's block counts (blocks
+// of `block` keys).
 __global__ void __launch_bounds__(kThreads) k_rs_rowscan(uint32_t* hist, int64_t cols, const uint32_t* n_dev,
-                                                         int64_t n_host, uint32_t* rowtot) {
+                                                         int64_t n_host, int64_t block, uint32_t* rowtot) {
   __shared__ uint32_t lds[5];
   const int64_t n = live_count(n_dev, n_host);
-  const int64_t nb = (n + kRsBlock - 1) / kRsBlock;
+  const int64_t nb = (n + block - 1) / block;
   uint32_t* row = hist + blockIdx.x * cols;
   uint32_t carry = 0;
   for (int64_t base = 0; base < nb; base += kThreads * 4) {
@@ -236,7 +243,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_rowscan(uint32_t* hist, int64_t
 // four waves per digit, stages the block's 4096 pairs locally sorted in LDS and
 // writes each digit's run contiguously.  A thread owns kPerT consecutive
 // digits in the block-wide digit scans.
-template <int kMaxBits>
+template <int kMaxBits, int kPer>
 __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint32_t* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin, uint32_t* kout,
                                                          uint32_t* vout, const uint32_t* n_dev, int64_t n_host,
@@ -244,16 +251,16 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint32_t* __restr
                                                          int64_t cols, const uint32_t* __restrict__ rowtot) {
   constexpr int kR = 1 << kMaxBits;
   constexpr int kPerT = kR / kThreads > 0 ? kR / kThreads : 1;  // digits per thread in the digit scans
-  constexpr int kPer = kRsItems;                 // items per lane
+  constexpr int kBlock = kThreads * kPer;        // items per block
   constexpr int kWaveItems = 64 * kPer;          // contiguous items per wave
   __shared__ uint32_t s_cnt[kThreads / 64][kR];  // per-wave digit counts, then per-wave digit bases
   __shared__ uint32_t s_off[kR];                 // block-local first slot of each digit
   __shared__ uint32_t s_gbase[kR];               // global first slot of each digit for this block
-  __shared__ uint32_t s_k[kRsBlock];
-  __shared__ uint32_t s_v[kRsBlock];
+  __shared__ uint32_t s_k[kBlock];
+  __shared__ uint32_t s_v[kBlock];
   __shared__ uint32_t lds[5];
   const int64_t n = live_count(n_dev, n_host);
-  const int64_t nb = (n + kRsBlock - 1) / kRsBlock;
+  const int64_t nb = (n + kBlock - 1) / kBlock;
   if (static_cast<int64_t>(blockIdx.x) >= nb) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int radix = 1 << bits;
@@ -287,7 +294,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint32_t* __restr
     }
     __syncthreads();
     // phase 1: wave-local stable ranks
-    const int64_t wbase = lb * kRsBlock + static_cast<int64_t>(wid) * kWaveItems;
+    const int64_t wbase = lb * kBlock + static_cast<int64_t>(wid) * kWaveItems;
     uint32_t key[kPer], val[kPer], rank[kPer];
 #pragma unroll
     for (int it = 0; it < kPer; ++it) {
@@ -353,7 +360,7 @@ __global__ void __launch_bounds__(kThreads) k_rs_scatter(const uint32_t* __restr
     }
     __syncthreads();
     // phase 4: coalesced runs out
-    const int64_t live = min(static_cast<int64_t>(kRsBlock), n - lb * kRsBlock);
+    const int64_t live = min(static_cast<int64_t>(kBlock), n - lb * kBlock);
     for (int p = tid; p < live; p += kThreads) {
       const uint32_t k = s_k[p];
       const uint32_t dig = (k >> shift) & mask;
@@ -722,7 +729,7 @@ BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity) {
   p.tile_bits = bits;
   p.tile_passes = static_cast<int>(cdiv(bits, 8));
   p.hist_cols = std::max<int64_t>(1, cdiv(capacity, kRsBlock));
-  p.hist_cols_depth = std::max<int64_t>(1, cdiv(n, kRsBlock));
+  p.hist_cols_depth = std::max<int64_t>(1, cdiv(n, kDepthBlock));
   size_t off = 0;
   p.off_vis_keys = off; off = align256(off + sizeof(uint32_t) * 2 * std::max<int64_t>(n, 1));
   p.off_vis_vals = off; off = align256(off + sizeof(uint32_t) * 2 * std::max<int64_t>(n, 1));
@@ -744,16 +751,19 @@ BinPlan plan_bins(int64_t n, int64_t tiles, int64_t capacity) {
 // One stable LSD pass of `bits` bits at `shift` from (kin, vin) to (kout, vout).
 constexpr int64_t kMaxGrid = 8192;  // physical blocks of a grid-stride pass
 
-template <int kMaxBits>
+template <int kMaxBits, int kPer>
 static hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                              const uint32_t* n_dev, int64_t n_grid, int shift, int bits, uint32_t* hist,
                              int64_t cols, uint32_t* rowtot, hipStream_t s) {
   if (bits < 1 || bits > kMaxBits) return hipErrorInvalidValue;
-  const unsigned nb = static_cast<unsigned>(std::min(kMaxGrid, std::max<int64_t>(1, cdiv(n_grid, kRsBlock))));
-  hipLaunchKernelGGL(k_rs_hist<kMaxBits>, dim3(nb), dim3(kThreads), 0, s, kin, n_dev, n_grid, shift, bits, hist,
-                     cols);
-  hipLaunchKernelGGL(k_rs_rowscan, dim3(1u << bits), dim3(kThreads), 0, s, hist, cols, n_dev, n_grid, rowtot);
-  hipLaunchKernelGGL(k_rs_scatter<kMaxBits>, dim3(nb), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_grid,
+  constexpr int64_t kBlock = int64_t{kThreads} * kPer;
+  const unsigned nb = static_cast<unsigned>(std::min(kMaxGrid, std::max<int64_t>(1, cdiv(n_grid, kBlock))));
+  auto hist_kernel = k_rs_hist<kMaxBits, kPer>;
+  auto scatter_kernel = k_rs_scatter<kMaxBits, kPer>;
+  hipLaunchKernelGGL(hist_kernel, dim3(nb), dim3(kThreads), 0, s, kin, n_dev, n_grid, shift, bits, hist, cols);
+  hipLaunchKernelGGL(k_rs_rowscan, dim3(1u << bits), dim3(kThreads), 0, s, hist, cols, n_dev, n_grid, kBlock,
+                     rowtot);
+  hipLaunchKernelGGL(scatter_kernel, dim3(nb), dim3(kThreads), 0, s, kin, vin, kout, vout, n_dev, n_grid,
                      shift, bits, hist, cols, rowtot);
   return hipGetLastError();
 }
@@ -789,10 +799,11 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
   // depth sort of the visible Gaussians: kDepthPasses LSD passes, ending in buffer 0
   if (n > 0) {
     StageScope sc(PVG_STAGE_DEPTH_SORT, s);
+    const auto depth_pass = radix_pass<kDepthBits, kDepthItems>;
     for (int pass = 0; pass < kDepthPasses; ++pass) {
       const int src = ((kDepthPasses & 1) + pass) & 1, dst = src ^ 1;
       const int shift = kDepthBits * pass;
-      PVG_HIP(radix_pass<kDepthBits>(vkeys + src * nvis_stride, vvals + src * nvis_stride, vkeys + dst * nvis_stride,
+      PVG_HIP(depth_pass(vkeys + src * nvis_stride, vvals + src * nvis_stride, vkeys + dst * nvis_stride,
                                      vvals + dst * nvis_stride, counters + 1, n, shift,
                                      std::min(kDepthBits, 32 - shift), hist, plan.hist_cols_depth, rowtot, s));
     }
@@ -875,12 +886,13 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
   }
   if (passes > 0 && m_grid > 0) {
     StageScope sc(PVG_STAGE_TILE_SORT, s);
+    const auto tile_pass = radix_pass<8, kRsItems>;
     const int per = (plan.tile_bits + passes - 1) / passes;
     for (int pass = 0; pass < passes; ++pass) {
       const int src = (start + pass) & 1, dst = src ^ 1;
       const int shift = per * pass;
       const int bits = std::min(per, plan.tile_bits - shift);
-      PVG_HIP(radix_pass<8>(bins->keys + src * cap, bins->vals + src * cap, bins->keys + dst * cap,
+      PVG_HIP(tile_pass(bins->keys + src * cap, bins->vals + src * cap, bins->keys + dst * cap,
                             bins->vals + dst * cap, counters, m_grid, shift, bits, hist, plan.hist_cols, rowtot, s));
     }
   }
