@@ -484,16 +484,23 @@ int pvg_sky_composite(const pvg_camera* cam, const float* img, const float* opac
  * [H][W] (= -sum_c f_sky,c(d) dL_dout_c) and adds (1 - opacity) dL_dout times
  * the bilinear weights into dL_dcube [6][3][R][R] (zero it first for a fresh
  * gradient; calls on one device add into it in stream order).  dL/dimg is
- * dL_dout itself.  When a texel spans at most six pixels (2 max(fx, fy) / R
- * <= 6) and R is a rotation to 1e-3, each 16 x 16 texel block is summed by
- * one workgroup in 64-bit fixed point and written once: the result does not
- * depend on the order of the additions, except for pixels whose jitter
- * exceeds half a pixel, which are added with float atomics.  Coarser maps sum
- * 16 x 16 pixel tiles the same way and add each tile's texels with float
- * atomics. */
+ * dL_dout itself.  Each 16 x 16 pixel tile sums its texels in LDS in 64-bit
+ * fixed point and adds them to dL_dcube with float atomics, so the order of
+ * those additions, and the last bits of the result, vary from run to run.
+ * Same arguments and errors as pvg_sky_composite. */
 int pvg_sky_composite_bwd(const pvg_camera* cam, const float* dL_dout, const float* opacity, const float* cube,
                           int32_t cube_res, const float* jitter, float* dL_dopacity, float* dL_dcube,
                           void* stream);
+/* pvg_sky_composite_bwd with a result that is the same on every run: each
+ * 16 x 16 texel block of the cube map is summed by one workgroup over the
+ * pixels that can reach it, in 64-bit fixed point, and written once, with no
+ * device-memory atomics.  Slower (about 1.5 - 2.5x at 1920 x 1280 with
+ * R = 1024).  Pixels whose jitter exceeds half a pixel, and cameras whose R
+ * is not a rotation to 1e-3, fall back to float atomics and lose the
+ * guarantee. */
+int pvg_sky_composite_bwd_deterministic(const pvg_camera* cam, const float* dL_dout, const float* opacity,
+                                        const float* cube, int32_t cube_res, const float* jitter,
+                                        float* dL_dopacity, float* dL_dcube, void* stream);
 
 /* Scratch bytes of pvg_render_bwd_views.  Host only. */
 int pvg_bwd_views_tmp_bytes(int64_t n, int32_t n_views, int32_t max_width, int32_t max_height,

@@ -135,6 +135,7 @@ def load():
         "pvg_render_fwd": ([P(Geom), P(Bins), P(Camera), P(Frame), vp, vp, vp, vp], i32),
         "pvg_sky_composite": ([P(Camera), vp, vp, vp, i32, vp, vp, vp], i32),
         "pvg_sky_composite_bwd": ([P(Camera), vp, vp, vp, i32, vp, vp, vp, vp], i32),
+        "pvg_sky_composite_bwd_deterministic": ([P(Camera), vp, vp, vp, i32, vp, vp, vp, vp], i32),
         "pvg_render_fwd_channels": ([P(Geom), P(Bins), P(Camera), P(Frame), vp, vp, vp, P(Channels), vp], i32),
         "pvg_render_bwd_views_channels": ([P(Gaussians), i32, P(Camera), P(Frame), P(Geom), P(Bins), P(vp), P(vp),
                                            P(vp), P(Channels), P(GaussiansGrad), i32, vp, C.c_size_t, vp], i32),

@@ -403,17 +403,29 @@ int pvg_sky_composite(const pvg_camera* cam, const float* img, const float* opac
   return PVG_OK;
 }
 
-int pvg_sky_composite_bwd(const pvg_camera* cam, const float* dL_dout, const float* opacity, const float* cube,
-                          int32_t cube_res, const float* jitter, float* dL_dopacity, float* dL_dcube, void* stream) {
+static int sky_bwd(const pvg_camera* cam, const float* dL_dout, const float* opacity, const float* cube,
+                   int32_t cube_res, const float* jitter, float* dL_dopacity, float* dL_dcube, bool deterministic,
+                   void* stream) {
   if (!check_camera(cam)) return PVG_ERR_INVALID;
   if (!dL_dout || !opacity || !cube || !dL_dopacity || !dL_dcube) {
     set_error("a sky composite array is null");
     return PVG_ERR_INVALID;
   }
   if (cube_res < 1 || cube_res > 16384) { set_error("cube_res = %d out of [1, 16384]", cube_res); return PVG_ERR_INVALID; }
-  PVG_HIP(launch_sky_bwd(cam, dL_dout, opacity, cube, cube_res, jitter, dL_dopacity, dL_dcube,
+  PVG_HIP(launch_sky_bwd(cam, dL_dout, opacity, cube, cube_res, jitter, dL_dopacity, dL_dcube, deterministic,
                          static_cast<hipStream_t>(stream)));
   return PVG_OK;
+}
+
+int pvg_sky_composite_bwd(const pvg_camera* cam, const float* dL_dout, const float* opacity, const float* cube,
+                          int32_t cube_res, const float* jitter, float* dL_dopacity, float* dL_dcube, void* stream) {
+  return sky_bwd(cam, dL_dout, opacity, cube, cube_res, jitter, dL_dopacity, dL_dcube, false, stream);
+}
+
+int pvg_sky_composite_bwd_deterministic(const pvg_camera* cam, const float* dL_dout, const float* opacity,
+                                        const float* cube, int32_t cube_res, const float* jitter, float* dL_dopacity,
+                                        float* dL_dcube, void* stream) {
+  return sky_bwd(cam, dL_dout, opacity, cube, cube_res, jitter, dL_dopacity, dL_dcube, true, stream);
 }
 
 int pvg_bwd_views_tmp_bytes(int64_t n, int32_t n_views, int32_t max_width, int32_t max_height, int64_t max_capacity,

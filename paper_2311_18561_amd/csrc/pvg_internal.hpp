@@ -169,8 +169,10 @@ hipError_t launch_preprocess_views(const PreViews& pk, hipStream_t s);
 // sky composite (Sec. 3.4): out = img + (1 - opac) f_sky(d) and its adjoint
 hipError_t launch_sky(const pvg_camera* cam, const float* img, const float* opac, const float* cube, int Rn,
                       const float* jitter, float* out, hipStream_t s);
+// deterministic: the texel-block gather (the same cube gradient on every run)
+// instead of the pixel-tile scatter, whose float atomics add in any order
 hipError_t launch_sky_bwd(const pvg_camera* cam, const float* g, const float* opac, const float* cube, int Rn,
-                          const float* jitter, float* dopac, float* dcube, hipStream_t s);
+                          const float* jitter, float* dopac, float* dcube, bool deterministic, hipStream_t s);
 // culled: the lists hold only tiles that pass tile_reachable (the render skips the test)
 hipError_t launch_render_fwd(const ViewSet& vs, const Geom& geom, const uint32_t* vals,
                              const uint32_t* ranges, bool culled, hipStream_t s);

@@ -157,11 +157,23 @@ __global__ void __launch_bounds__(256) k_sky_bwd(SkyView c, const float* __restr
   __syncthreads();
   const int f0 = s_box[0];
   const bool mine = in && face == f0;
-  if (mine) {  // the taps span [tx[0], tx[1]] x [ty[0], ty[1]]
-    atomicMin(&s_box[1], tx[0]);
-    atomicMin(&s_box[2], ty[0]);
-    atomicMax(&s_box[3], tx[1]);
-    atomicMax(&s_box[4], ty[1]);
+  {  // the taps span [tx[0], tx[1]] x [ty[0], ty[1]]; reduced over the wave
+     // first (LDS atomics of all lanes on one address compile to a loop over
+     // the lanes, which cost this kernel 65 of its 110 us)
+    int x0 = mine ? tx[0] : INT_MAX, y0 = mine ? ty[0] : INT_MAX, x1 = mine ? tx[1] : -1, y1 = mine ? ty[1] : -1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      x0 = min(x0, __shfl_xor(x0, off, 64));
+      y0 = min(y0, __shfl_xor(y0, off, 64));
+      x1 = max(x1, __shfl_xor(x1, off, 64));
+      y1 = max(y1, __shfl_xor(y1, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicMin(&s_box[1], x0);
+      atomicMin(&s_box[2], y0);
+      atomicMax(&s_box[3], x1);
+      atomicMax(&s_box[4], y1);
+    }
   }
   {
     const float a0 = fabsf(tg[0]), a1 = fabsf(tg[1]), a2 = fabsf(tg[2]);
@@ -211,15 +223,15 @@ __global__ void __launch_bounds__(256) k_sky_bwd(SkyView c, const float* __restr
 
 // ---- the gather form ----
 
-constexpr int kSkyTB = 16;               // texel block side
+constexpr int kSkyTB = 16;               // largest texel block side (the LDS sums' size)
 constexpr float kSkyJitter = 0.5f;       // the |jitter| the pixel rectangles allow for
-constexpr float kSkyGatherMaxPx = 6.0f;  // pixels per texel (face centre, image centre) up to which it gathers
 constexpr int kSkyMaxSuper = 6 * 8 * 8;  // superblocks of a cube map
 constexpr int kSkyGatherThreads = 512;   // threads of a texel block's workgroup
 
 struct SkyGather {
   float M[9];    // camera direction from a face point: c = M q, M the inverse of R^T (row-major)
   float delta;   // the face points kept have c.z >= delta (the rest project beyond the image margin)
+  int32_t tb;    // texel block side: 16, or less for coarse maps (1 to 16)
   int32_t nb;    // texel blocks per face side
   int32_t sbs;   // blocks per superblock side (at most 8 superblocks per face side)
   int32_t nsb;   // superblocks per face side
@@ -355,8 +367,9 @@ __global__ void __launch_bounds__(kSkyGatherThreads) k_sky_bwd_gather(SkyView c,
   const int f = sb / (G.nsb * G.nsb), sr = sb % (G.nsb * G.nsb);
   const int bx = (sr % G.nsb) * G.sbs + in_sb % G.sbs, by = (sr / G.nsb) * G.sbs + in_sb / G.sbs;
   if (bx >= G.nb || by >= G.nb) return;
-  const int X0 = bx * kSkyTB, Y0 = by * kSkyTB;
-  const int X1 = min(X0 + kSkyTB - 1, Rn - 1), Y1 = min(Y0 + kSkyTB - 1, Rn - 1);
+  const int tb = G.tb;
+  const int X0 = bx * tb, Y0 = by * tb;
+  const int X1 = min(X0 + tb - 1, Rn - 1), Y1 = min(Y0 + tb - 1, Rn - 1);
   if (threadIdx.x == 0) {
     int r[4];
     s_rect[4] = sky_block_rect(c, G, Rn, f, X0, X1, Y0, Y1, r) ? 1 : 0;
@@ -425,8 +438,8 @@ __global__ void __launch_bounds__(kSkyGatherThreads) k_sky_bwd_gather(SkyView c,
     const bool hit[4] = {own && w[0] != 0.0f, cin1 && rin0 && w[1] != 0.0f, cin0 && rin1 && w[2] != 0.0f,
                          cin1 && rin1 && w[3] != 0.0f};
     if (!(own || hit[1] || hit[2] || hit[3])) continue;
-    const int slot = (ty[0] - Y0) * kSkyTB + (tx[0] - X0);
-    constexpr int kOff[4] = {0, 1, kSkyTB, kSkyTB + 1};
+    const int slot = (ty[0] - Y0) * tb + (tx[0] - X0);
+    const int off[4] = {0, 1, tb, tb + 1};
     const float t = 1.0f - opac[o];
     float dO = 0.0f;
     for (int ch = 0; ch < 3; ++ch) {
@@ -441,9 +454,9 @@ __global__ void __launch_bounds__(kSkyGatherThreads) k_sky_bwd_gather(SkyView c,
       for (int q = 0; q < 4; ++q) {
         if (!hit[q]) continue;
         if (fixed)
-          atomicAdd(&s_acc[ch * kT + slot + kOff[q]], sky_fixed(w[q] * tg, k));
+          atomicAdd(&s_acc[ch * kT + slot + off[q]], sky_fixed(w[q] * tg, k));
         else
-          atomicAdd(&facc[ch * kT + slot + kOff[q]], w[q] * tg);
+          atomicAdd(&facc[ch * kT + slot + off[q]], w[q] * tg);
       }
     }
     if (own) dopac[o] = dO;
@@ -452,7 +465,8 @@ __global__ void __launch_bounds__(kSkyGatherThreads) k_sky_bwd_gather(SkyView c,
   // each texel of the block is this workgroup's alone: plain read-add-write
   for (int i = threadIdx.x; i < 3 * kT; i += kSkyGatherThreads) {
     const int ch = i / kT, rr = i % kT;
-    float* p = dcube + (f * 3 + ch) * F + static_cast<int64_t>(Y0 + rr / kSkyTB) * Rn + (X0 + rr % kSkyTB);
+    if (rr >= tb * tb) continue;
+    float* p = dcube + (f * 3 + ch) * F + static_cast<int64_t>(Y0 + rr / tb) * Rn + (X0 + rr % tb);
     if (fixed) {
       const long long a = static_cast<long long>(s_acc[i]);
       if (a != 0) *p = static_cast<float>(static_cast<double>(*p) + ldexp(static_cast<double>(a), -k));
@@ -463,12 +477,9 @@ __global__ void __launch_bounds__(kSkyGatherThreads) k_sky_bwd_gather(SkyView c,
   }
 }
 
-// The gather's set-up, or false for the scatter: more than kSkyGatherMaxPx
-// pixels per texel, or a rotation that is not orthonormal to 1e-3 (the clip
-// plane's bound assumes |M q| >= about |q|).
+// The gather's set-up, or false for the scatter: a rotation that is not
+// orthonormal to 1e-3 (the clip plane's bound assumes |M q| >= about |q|).
 static bool sky_gather_setup(const pvg_camera* cam, int Rn, SkyGather& G) {
-  const double px_per_texel = 2.0 * std::max(cam->fx, cam->fy) / Rn;
-  if (!(px_per_texel <= kSkyGatherMaxPx)) return false;
   double A[3][3];  // R^T
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) A[i][j] = cam->R[3 * j + i];
@@ -503,7 +514,13 @@ static bool sky_gather_setup(const pvg_camera* cam, int Rn, SkyGather& G) {
   }
   cone += 0.02;  // far above the rounding of the test below
   const double cc = std::cos(cone), sc = std::sin(cone);
-  G.nb = (Rn + kSkyTB - 1) / kSkyTB;
+  // Blocks of about 48 pixels a side: 16 texels up to three pixels per texel,
+  // fewer texels for coarser maps (a 16-texel block of a 128 map seen at
+  // fx = 1500 spans 370 pixels, and its workgroup alone walked 0.14M of them)
+  const double px_per_texel = 2.0 * std::max(cam->fx, cam->fy) / Rn;
+  G.tb = kSkyTB;
+  while (G.tb > 1 && G.tb * px_per_texel > 48.0) G.tb >>= 1;
+  G.nb = (Rn + G.tb - 1) / G.tb;
   G.sbs = std::max(8, (G.nb + 7) / 8);
   G.nsb = (G.nb + G.sbs - 1) / G.sbs;
   G.count = 0;
@@ -512,7 +529,7 @@ static bool sky_gather_setup(const pvg_camera* cam, int Rn, SkyGather& G) {
   // centre, less the footprint's angular radius (largest at a corner: the
   // footprint is a convex quad inside a hemisphere), is within `cone`:
   // cos(angle to axis) >= cos(cone + radius).
-  const double span = static_cast<double>(G.sbs) * kSkyTB;
+  const double span = static_cast<double>(G.sbs) * G.tb;
   for (int f = 0; f < 6; ++f)
     for (int r = 0; r < G.nsb; ++r)
       for (int q = 0; q < G.nsb; ++q) {
@@ -571,11 +588,11 @@ hipError_t launch_sky(const pvg_camera* cam, const float* img, const float* opac
 }
 
 hipError_t launch_sky_bwd(const pvg_camera* cam, const float* g, const float* opac, const float* cube, int Rn,
-                          const float* jitter, float* dopac, float* dcube, hipStream_t s) {
+                          const float* jitter, float* dopac, float* dcube, bool deterministic, hipStream_t s) {
   const int64_t HW = static_cast<int64_t>(cam->width) * cam->height;
   if (HW == 0) return hipSuccess;
   SkyGather G;
-  if (sky_gather_setup(cam, Rn, G)) {
+  if (deterministic && sky_gather_setup(cam, Rn, G)) {
     const SkyView v = sky_view(cam);
     if (jitter)
       hipLaunchKernelGGL(k_sky_bwd_stray, dim3(static_cast<unsigned>((HW + 255) / 256)), dim3(256), 0, s, v, g, opac,

@@ -762,10 +762,11 @@ def pvg_render(params, cam, t, dt=0.0, advect_mode=0, bg=(0.0, 0.0, 0.0), recomp
 class PVGSkyComposite(torch.autograd.Function):
     """Sky refinement (Sec. 3.4): C_f = C + (1 - O) f_sky(d) over a learnable
     cube map, one view: img [3,H,W] (rendered on a black background), opacity
-    [H,W], cube [6,3,R,R]; the adjoint reaches img, opacity and the cube map."""
+    [H,W], cube [6,3,R,R]; the adjoint reaches img, opacity and the cube map
+    (deterministic: the cube gradient's run-to-run identical form)."""
 
     @staticmethod
-    def forward(ctx, img, opacity, cube, cam, jitter):
+    def forward(ctx, img, opacity, cube, cam, jitter, deterministic=False):
         c = camera_struct(cam)
         H, W = int(c.height), int(c.width)
         img, opacity, cube = img.contiguous(), opacity.contiguous(), cube.contiguous()
@@ -785,6 +786,7 @@ class PVGSkyComposite(torch.autograd.Function):
         ctx.c = c
         ctx.save_for_backward(opacity, cube, jitter if jitter is not None else torch.empty(0, device=img.device))
         ctx.has_jitter = jitter is not None
+        ctx.deterministic = bool(deterministic)
         return out
 
     @staticmethod
@@ -793,16 +795,17 @@ class PVGSkyComposite(torch.autograd.Function):
         g = g.contiguous()
         d_op = torch.empty_like(opacity)
         d_cube = torch.zeros_like(cube)
-        L.check(L.load().pvg_sky_composite_bwd(C.byref(ctx.c), _p(g), _p(opacity), _p(cube), int(cube.shape[-1]),
-                                               _p(jitter) if ctx.has_jitter else None, _p(d_op), _p(d_cube),
-                                               _stream_handle()))
-        return g, d_op, d_cube, None, None
+        lib = L.load()
+        fn = lib.pvg_sky_composite_bwd_deterministic if ctx.deterministic else lib.pvg_sky_composite_bwd
+        L.check(fn(C.byref(ctx.c), _p(g), _p(opacity), _p(cube), int(cube.shape[-1]),
+                   _p(jitter) if ctx.has_jitter else None, _p(d_op), _p(d_cube), _stream_handle()))
+        return g, d_op, d_cube, None, None, None
 
 
-def pvg_sky_composite(img, opacity, cube, cam: dict, jitter=None):
+def pvg_sky_composite(img, opacity, cube, cam: dict, jitter=None, deterministic=False):
     """C + (1 - O) f_sky(d) for one view (see PVGSkyComposite); jitter
     (optional [2,H,W], pixels) moves each ray inside its pixel."""
-    return PVGSkyComposite.apply(img, opacity, cube, cam, jitter)
+    return PVGSkyComposite.apply(img, opacity, cube, cam, jitter, deterministic)
 
 
 class PVGSkyCompositeViews(torch.autograd.Function):
@@ -813,7 +816,7 @@ class PVGSkyCompositeViews(torch.autograd.Function):
     sums of full-size arrays."""
 
     @staticmethod
-    def forward(ctx, imgs, opacities, cube, cams, jitter):
+    def forward(ctx, imgs, opacities, cube, cams, jitter, deterministic=False):
         cs = [camera_struct(c) for c in cams]
         V = len(cs)
         imgs, opacities, cube = imgs.contiguous(), opacities.contiguous(), cube.contiguous()
@@ -838,6 +841,7 @@ class PVGSkyCompositeViews(torch.autograd.Function):
         ctx.cs = cs
         ctx.save_for_backward(opacities, cube, jitter if jitter is not None else torch.empty(0, device=imgs.device))
         ctx.has_jitter = jitter is not None
+        ctx.deterministic = bool(deterministic)
         return out
 
     @staticmethod
@@ -847,16 +851,16 @@ class PVGSkyCompositeViews(torch.autograd.Function):
         d_op = torch.empty_like(opacities)
         d_cube = torch.zeros_like(cube)
         lib, st, res = L.load(), _stream_handle(), int(cube.shape[-1])
+        fn = lib.pvg_sky_composite_bwd_deterministic if ctx.deterministic else lib.pvg_sky_composite_bwd
         for k, c in enumerate(ctx.cs):
-            L.check(lib.pvg_sky_composite_bwd(C.byref(c), _p(g[k]), _p(opacities[k]), _p(cube), res,
-                                              _p(jitter[k]) if ctx.has_jitter else None, _p(d_op[k]), _p(d_cube),
-                                              st))
-        return g, d_op, d_cube, None, None
+            L.check(fn(C.byref(c), _p(g[k]), _p(opacities[k]), _p(cube), res,
+                       _p(jitter[k]) if ctx.has_jitter else None, _p(d_op[k]), _p(d_cube), st))
+        return g, d_op, d_cube, None, None, None
 
 
-def pvg_sky_composite_views(imgs, opacities, cube, cams, jitter=None):
+def pvg_sky_composite_views(imgs, opacities, cube, cams, jitter=None, deterministic=False):
     """C + (1 - O) f_sky(d) for V views of one size (see PVGSkyCompositeViews)."""
-    return PVGSkyCompositeViews.apply(imgs, opacities, cube, list(cams), jitter)
+    return PVGSkyCompositeViews.apply(imgs, opacities, cube, list(cams), jitter, deterministic)
 
 
 class PVGSSIM(torch.autograd.Function):
