@@ -52,6 +52,8 @@ def parse():
                     help="length of the 200 req/s serving trace (its first 2 s are excluded from the statistics)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--profile-sky", action="store_true",
+                    help="after the warm-up run only the sky adjoint's timing pass (both entry points) and print it")
     ap.add_argument("--profile-pass", action="store_true",
                     help="after the warm-up run only the serial per-stage pass (the one the roofline's kernel "
                          "times come from) and print its stage times: the run to put under a kernel profiler")
@@ -560,6 +562,45 @@ def main():
                 stages[name]["work"] = counted[name]["work"] / counted[name]["calls"] * stages[name]["calls"]
         return stages
 
+    def sky_adjoint_pass(reps=20):
+        """The sky adjoint alone (pvg_sky_composite_bwd and its deterministic
+        form) on each camera's 1920x1280 view over the 1024^2 cube map, with
+        jittered rays: microseconds per view from HIP events on the launch
+        stream, after three untimed calls."""
+        import ctypes
+        from paper_2311_18561_amd.render import camera_struct
+        gs = torch.Generator(device="cuda").manual_seed(5)
+        g = torch.randn((3, H, W), device="cuda", generator=gs)
+        op = torch.rand((H, W), device="cuda", generator=gs)
+        jt = torch.rand((2, H, W), device="cuda", generator=gs) - 0.5
+        d_op = torch.empty_like(op)
+        d_cube = torch.zeros_like(cube)
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        out = {}
+        for name in ("pvg_sky_composite_bwd", "pvg_sky_composite_bwd_deterministic"):
+            fn = getattr(lib, name)
+            per_view = []
+            for cam in cams:
+                c = camera_struct(cam)
+                args_c = (ctypes.byref(c), ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(op.data_ptr()),
+                          ctypes.c_void_p(cube.data_ptr()), int(cube.shape[-1]), ctypes.c_void_p(jt.data_ptr()),
+                          ctypes.c_void_p(d_op.data_ptr()), ctypes.c_void_p(d_cube.data_ptr()), st)
+                for _ in range(3):
+                    L.check(fn(*args_c))
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    fn(*args_c)
+                e1.record()
+                torch.cuda.synchronize()
+                per_view.append(e0.elapsed_time(e1) / reps * 1e3)
+            out[name] = per_view
+        return out
+
+    if args.profile_sky:
+        print(json.dumps({"profile_sky": sky_adjoint_pass()}), flush=True)
+        return
+
     if args.profile_pass:
         stages = serial_stage_pass()
         print(json.dumps({"profile_pass": {k: {"ms_per_call": v["ms"] / max(v["calls"], 1), "calls": v["calls"],
@@ -615,6 +656,7 @@ def main():
         torch.cuda.synchronize()
         ch_steps.append(time.perf_counter() - t0)
     ch_med = sorted(ch_steps)[len(ch_steps) // 2]
+    sky_us = sky_adjoint_pass()
 
     # A period of the training loop (Sec. 4 and the appendix): PERIOD
     # iterations that each sample one view per camera at the next training
@@ -817,6 +859,10 @@ def main():
         "iters_per_s_channels": args.steps / t_channels,
         "iters_per_s_channels_median_step": 1.0 / ch_med,
         "iters_per_s_full_iteration": 1.0 / t_full,
+        "sky_adjoint": {"us_per_view": sky_us,
+                        "note": ("the sky composite's adjoint alone on each camera's 1920x1280 view over the 1024^2 "
+                                 "cube map with jittered rays (HIP events, 20 calls after 3): the pixel-tile scatter "
+                                 "the training steps use, and the deterministic texel-block gather")},
         "semantic_ms_per_step": t_sem * 1e3,
         "semantic_note": ("pvg_render_semantic forward and backward of 19 class scores per Gaussian over the six "
                           "views: one list walk per view for all 19 channels, forward and adjoint, and the loss "
