@@ -252,6 +252,12 @@ __device__ __forceinline__ void gather_range(uint32_t e0, uint32_t cnt, const fl
 }
 
 constexpr uint32_t kShortRange = 48;  // Gaussians with more listed pairs are gathered by a whole wave
+// Gaussians with more listed pairs than this (near-camera splats reach most
+// of the frame's 9,600 tiles, and a splat in front is flagged in nearly all of
+// them) are gathered by the whole block, each wave taking every fourth
+// round of 1,024 pairs: one wave alone took about 90 us over the largest,
+// while the rest of the gather needed 48 us.
+constexpr uint32_t kHugeRange = 2048;
 
 // Sum of one Gaussian's flagged records in [e0, e0 + cnt) by a whole wave:
 // each round, lane l reads the 16 flags at b + 16 l (1024 pairs per round),

@@ -329,12 +329,12 @@ __global__ void __launch_bounds__(256) k_feat_gather(ViewSet vs, Geom geom, List
                                                      int64_t ld, int nch) {
   constexpr int kRec = feature_record_floats(kNC);
   constexpr int kAcc = (kRec + 15) / 16 * 16;
-  __shared__ uint32_t s_queue[256][3];
+  __shared__ uint32_t s_queue[256][3];  // wave-gathered Gaussians from the front, block-gathered from the back
   __shared__ uint32_t s_idx[4][1024];
   __shared__ float s_red[4][kRec];
-  __shared__ int s_qn;
+  __shared__ int s_qn, s_hn;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  if (tid == 0) s_qn = 0;
+  if (tid == 0) { s_qn = 0; s_hn = 0; }
   __syncthreads();
   const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + tid;
   const bool visible = gi < live_gauss(vs) && geom.radius[gi] > 0;
@@ -351,13 +351,13 @@ __global__ void __launch_bounds__(256) k_feat_gather(ViewSet vs, Geom geom, List
     for (int c = 0; c < kNC; ++c)
       if (c < nch) fg[c] += acc[8 + c];
   } else if (visible) {
-    const int q = atomicAdd(&s_qn, 1);
+    const int q = cnt > kHugeRange ? 255 - atomicAdd(&s_hn, 1) : atomicAdd(&s_qn, 1);
     s_queue[q][0] = static_cast<uint32_t>(gi);
     s_queue[q][1] = e0;
     s_queue[q][2] = cnt;
   }
   __syncthreads();
-  const int qn = s_qn;
+  const int qn = s_qn, hn = s_hn;
   for (int qi = wid; qi < qn; qi += 4) {
     const uint32_t g = s_queue[qi][0];
     float acc[kAcc];
@@ -371,6 +371,31 @@ __global__ void __launch_bounds__(256) k_feat_gather(ViewSet vs, Geom geom, List
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  // block-gathered Gaussians (more than kHugeRange listed pairs), one at a
+  // time: wave w sums rounds w, w + 4, ... of 1,024 pairs and the four shares
+  // are added in wave order
+  __syncthreads();
+  for (int h = 0; h < hn; ++h) {
+    const uint32_t g = s_queue[255 - h][0], he0 = s_queue[255 - h][1], hcnt = s_queue[255 - h][2];
+    float acc[kAcc];
+#pragma unroll
+    for (int c = 0; c < kAcc; ++c) acc[c] = 0.0f;
+    for (uint32_t r0 = 1024u * static_cast<uint32_t>(wid); r0 < hcnt; r0 += 4096u) {
+      float part[kAcc];
+      gather_range_wave<kRec, kAcc>(he0 + r0, min(1024u, hcnt - r0), lane, rec, vis, s_idx[wid], part);
+#pragma unroll
+      for (int c = 0; c < kAcc; ++c) acc[c] += part[c];
+    }
+    wave_sum_store<kRec>(acc, lane, s_red[wid]);
+    __syncthreads();
+    if (tid < kRec) {
+      const float v = ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid];
+      if (tid < 14) g2d[kG2DStride * static_cast<int64_t>(g) + tid] = tid < 6 ? v : 0.0f;
+      if (tid >= 8 && tid - 8 < nch && tid - 8 < kNC) feat_grad[ld * static_cast<int64_t>(g) + (tid - 8)] += v;
+    }
+    if (tid < 14 && tid >= kRec) g2d[kG2DStride * static_cast<int64_t>(g) + tid] = 0.0f;
+    __syncthreads();
   }
 }
 

@@ -451,11 +451,12 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, List
                                                      const float* __restrict__ rec,
                                                      const uint8_t* __restrict__ vis, float* g2d) {
   constexpr int kSums = kCh ? 14 : 9;
-  __shared__ uint32_t s_queue[256][3];
-  __shared__ uint32_t s_idx[4][1024];  // per wave: flagged pair indices of one round
-  __shared__ int s_qn;
+  __shared__ uint32_t s_queue[256][3];  // wave-gathered Gaussians from the front, block-gathered from the back
+  __shared__ uint32_t s_idx[4][1024];   // per wave: flagged pair indices of one round
+  __shared__ float s_part[4][16];       // per wave: its share of a block-gathered Gaussian's sums
+  __shared__ int s_qn, s_hn;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  if (tid == 0) s_qn = 0;
+  if (tid == 0) { s_qn = 0; s_hn = 0; }
   __syncthreads();
   const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + tid;
   const bool visible = gi < live_gauss(vs) && geom.radius[gi] > 0;
@@ -468,13 +469,13 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, List
 #pragma unroll
     for (int c = 0; c < 14; ++c) dst[c] = acc[c];
   } else if (visible) {
-    const int q = atomicAdd(&s_qn, 1);
+    const int q = cnt > kHugeRange ? 255 - atomicAdd(&s_hn, 1) : atomicAdd(&s_qn, 1);
     s_queue[q][0] = static_cast<uint32_t>(gi);
     s_queue[q][1] = e0;
     s_queue[q][2] = cnt;
   }
   __syncthreads();
-  const int qn = s_qn;
+  const int qn = s_qn, hn = s_hn;
   for (int qi = wid; qi < qn; qi += 4) {
     const uint32_t g = s_queue[qi][0];
     float acc[16], red[4];
@@ -489,6 +490,29 @@ __global__ void __launch_bounds__(256) k_grad_gather(ViewSet vs, Geom geom, List
         if (qq < 14) dst[qq] = red[k];
       }
     }
+  }
+  // block-gathered Gaussians, one at a time: wave w sums rounds w, w + 4, ...
+  // and the four shares are added in wave order
+  for (int h = 0; h < hn; ++h) {
+    const uint32_t g = s_queue[255 - h][0], he0 = s_queue[255 - h][1], hcnt = s_queue[255 - h][2];
+    float acc[16], red[4];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = 0.0f;
+    for (uint32_t r0 = 1024u * static_cast<uint32_t>(wid); r0 < hcnt; r0 += 4096u) {
+      float part[16];
+      gather_range_wave<kSums>(he0 + r0, min(1024u, hcnt - r0), lane, rec, vis, s_idx[wid], part);
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc[c] += part[c];
+    }
+    wave_sum16(acc, red);
+    if ((lane & 15) == 0) {
+      const int r = lane >> 4;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s_part[wid][4 * k + 2 * (r & 1) + (r >> 1)] = red[k];
+    }
+    __syncthreads();
+    if (tid < 14) g2d[kG2DStride * static_cast<int64_t>(g) + tid] = ((s_part[0][tid] + s_part[1][tid]) + s_part[2][tid]) + s_part[3][tid];
+    __syncthreads();
   }
 }
 
