@@ -19,6 +19,7 @@ from __future__ import annotations
 import ctypes as C
 import math
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -86,10 +87,11 @@ def gaussians_struct(params, n, degree) -> L.Gaussians:
 
 def camera_struct(cam: dict) -> L.Camera:
     c = L.Camera()
-    R = [float(x) for x in torch.as_tensor(cam["R"], dtype=torch.float32).reshape(-1).tolist()]
-    T = [float(x) for x in torch.as_tensor(cam["T"], dtype=torch.float32).reshape(-1).tolist()]
-    c.R[:] = R
-    c.T[:] = T
+    # numpy rather than torch for the 3x3 and 3-vector: a fifth of the host time
+    R = cam["R"].cpu().numpy() if isinstance(cam["R"], torch.Tensor) else cam["R"]
+    T = cam["T"].cpu().numpy() if isinstance(cam["T"], torch.Tensor) else cam["T"]
+    c.R[:] = np.asarray(R, dtype=np.float32).reshape(-1).tolist()
+    c.T[:] = np.asarray(T, dtype=np.float32).reshape(-1).tolist()
     c.fx, c.fy, c.cx, c.cy = float(cam["fx"]), float(cam["fy"]), float(cam["cx"]), float(cam["cy"])
     c.width, c.height = int(cam["width"]), int(cam["height"])
     c.znear = float(cam.get("znear", 0.2))
