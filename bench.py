@@ -267,7 +267,7 @@ def config_legs(steps):
             for q in params:
                 q.grad = None
             imgs = pvg.pvg_render_views(params, views, recompute=recompute, stack=True)
-            ((imgs - tg).abs().mean() * len(views)).backward()
+            (pvg.l1_loss(imgs, tg) * len(views)).backward()
 
         step()
         torch.cuda.synchronize()
@@ -448,7 +448,7 @@ def main():
         for p in params:
             p.grad = None
         imgs = pvg.pvg_render_views(params, views, recompute=recompute, stack=True)
-        loss = (imgs - stacked_targets).abs().mean() * len(views)  # = the sum of the six per-image means
+        loss = pvg.l1_loss(imgs, stacked_targets) * len(views)  # = the sum of the six per-image means
         loss.backward()
         return loss
 
@@ -483,7 +483,7 @@ def main():
         final = pvg.pvg_sky_composite_views(imgs, opac, cube, [v[0] for v in views], jit)
         o = opac.clamp(1e-6, 1.0 - 1e-6)
         inv = 1.0 / dn.clamp_min(1e-3)  # the inverse of the normalized depth
-        loss = ((final - stacked_targets).abs().mean() * V + 0.1 * (sparse * (inv - inv_depth_target).abs()).mean()
+        loss = (pvg.l1_loss(final, stacked_targets) * V + 0.1 * (sparse * (inv - inv_depth_target).abs()).mean()
                 + 0.05 * (-(o * o.log()).mean() - (sky * (1.0 - o).log()).mean()) + 0.01 * vbar.abs().mean())
         loss.backward()
         return loss
@@ -530,7 +530,7 @@ def main():
             p.grad = None
         loss = None
         for (cam, tt, d), tgt in zip(views, view_targets):
-            l1 = (pvg.pvg_render(params, cam, tt, d, recompute=False) - tgt).abs().mean()
+            l1 = pvg.l1_loss(pvg.pvg_render(params, cam, tt, d, recompute=False), tgt)
             loss = l1 if loss is None else loss + l1
         loss.backward()
 
@@ -680,6 +680,7 @@ def main():
     sample_rng = random.Random(11)
     state = {"acc": torch.zeros(N, device="cuda"), "cnt": torch.zeros(N, device="cuda"), "frame": 0,
              "views": 0, "translated": 0}
+    tg = stacked_targets[0::2].contiguous()  # each camera's target (the H(t) slots)
     n_frames, frame_dt = 50, 0.02
     dcfg = pvg.densify_config(30.0)
 
@@ -702,9 +703,8 @@ def main():
         final = pvg.pvg_sky_composite_views(imgs, opac, train_cube, [v[0] for v in vs], jit)
         o = opac.clamp(1e-6, 1.0 - 1e-6)
         inv = 1.0 / dn.clamp_min(1e-3)
-        tg = stacked_targets[0::2]
         ssim = torch.stack([pvg.pvg_ssim(final[k], tg[k]).mean() for k in range(Vf)])
-        rgb = 0.8 * (final - tg).abs().mean() * Vf + 0.2 * (1.0 - ssim).sum()
+        rgb = 0.8 * pvg.l1_loss(final, tg) * Vf + 0.2 * (1.0 - ssim).sum()
         loss = (rgb + 0.1 * (sparse[:Vf] * (inv - inv_depth_target[:Vf]).abs()).mean()
                 + 0.05 * (-(o * o.log()).mean() - (sky[:Vf] * (1.0 - o).log()).mean())
                 + 0.01 * vbar.abs().mean())

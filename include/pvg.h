@@ -466,6 +466,19 @@ int pvg_ssim_fwd(const float* x, const float* y, int32_t channels, int32_t heigh
 int pvg_ssim_bwd(const float* dL_dssim, const float* x, const float* y, const float* partials, int32_t channels,
                  int32_t height, int32_t width, float* dL_dx, void* stream);
 
+/* L1 term of the training loss (Sec. 3.4 objective; the photometric L1 of
+ * Sec. 4): loss[0] = scale * sum_i |a_i - b_i| over n floats and, when
+ * grad_a is not NULL, grad_a[i] = scale * sign(a_i - b_i) (0 where they are
+ * equal, NaN where the difference is NaN), in one pass over a and b.
+ * partials: device scratch of PVG_L1_PARTIALS floats, caller-owned.  The sum
+ * is formed in a fixed order (per-workgroup partial sums, then their FP64
+ * sum), so the loss is the same on every run.  All arrays are device memory;
+ * PVG_ERR_INVALID on n < 0 or a null a, b, loss or partials; asynchronous on
+ * `stream`. */
+#define PVG_L1_PARTIALS 1024
+int pvg_l1_loss(const float* a, const float* b, int64_t n, float scale, float* loss, float* grad_a, float* partials,
+                void* stream);
+
 /* Sky refinement (Sec. 3.4): out = img + (1 - opacity) * f_sky(d), with f_sky
  * a learnable cube map `cube` [6][3][cube_res][cube_res] (faces +X, -X, +Y,
  * -Y, +Z, -Z; channel; row v; column u) looked up bilinearly, inside the face,

@@ -29,6 +29,7 @@ from .render import (  # noqa: F401
     pvg_render_semantic,
     pvg_sky_composite,
     pvg_sky_composite_views,
+    l1_loss,
     pvg_ssim,
     render,
     render_bwd,

@@ -22,6 +22,7 @@ PVG_ERR_NOT_FOUND = -6
 PVG_ERR_TIMEOUT = -7
 NOALLOC_SCRATCH_BYTES = 256 << 20  # PVG_NOALLOC_SCRATCH_BYTES of include/pvg.h
 MAX_FEATURE_CHANNELS = 32  # PVG_MAX_FEATURE_CHANNELS
+L1_PARTIALS = 1024  # PVG_L1_PARTIALS
 
 STAGES = ("preprocess", "compact", "depth_sort", "scan_emit", "tile_sort", "ranges", "render_fwd", "render_bwd",
           "preprocess_bwd", "grad_gather")
@@ -152,6 +153,7 @@ def load():
         "pvg_adam_step": ([P(Gaussians), P(GaussiansGrad), vp, vp, P(AdamConfig), vp], i32),
         "pvg_opacity_reset": ([P(Gaussians), vp, vp, C.c_float, vp], i32),
         "pvg_adam_dense": ([vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp], i32),
+        "pvg_l1_loss": ([vp, vp, C.c_int64, C.c_float, vp, vp, vp, vp], i32),
         "pvg_ssim_fwd": ([vp, vp, i32, i32, i32, vp, vp, vp], i32),
         "pvg_staticness_split_plan": ([P(Gaussians), C.c_float, vp, C.c_size_t, P(i64), vp], i32),
         "pvg_staticness_split_apply": ([P(Gaussians), C.c_float, vp, C.c_size_t, P(Gaussians), P(Gaussians), vp],

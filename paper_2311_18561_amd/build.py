@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libpvg.so")
 OBJDIR = os.path.join(PKG, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "preprocess.hip", "binsort.hip", "render.hip", "features.hip", "sky.hip", "densify.hip", "adam.hip", "ssim.hip", "serve.cpp"]
+SOURCES = ["api.cpp", "preprocess.hip", "binsort.hip", "render.hip", "features.hip", "sky.hip", "densify.hip", "adam.hip", "ssim.hip", "loss.hip", "serve.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-munsafe-fp-atomics",

@@ -951,6 +951,17 @@ int pvg_ssim_bwd(const float* dL_dssim, const float* x, const float* y, const fl
   return PVG_OK;
 }
 
+int pvg_l1_loss(const float* a, const float* b, int64_t n, float scale, float* loss, float* grad_a, float* partials,
+                void* stream) {
+  if (n < 0 || !a || !b || !loss || !partials) {
+    set_error("n < 0, or a, b, loss or partials is null");
+    return PVG_ERR_INVALID;
+  }
+  static_assert(PVG_L1_PARTIALS == pvg::kL1Blocks, "the header's scratch size is the kernel's block count");
+  PVG_HIP(pvg::launch_l1(a, b, n, scale, loss, grad_a, partials, static_cast<hipStream_t>(stream)));
+  return PVG_OK;
+}
+
 int pvg_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (on && !g_work_dev) {

@@ -235,6 +235,11 @@ hipError_t launch_adam(const SceneOut& s, const pvg_gaussians_grad& g, float* m,
                        hipStream_t st);
 hipError_t launch_opacity_reset(float* o, float* m_row, float* v_row, int64_t n, float cap, hipStream_t st);
 // SSIM (11 x 11 Gaussian window, sigma 1.5): map and saved partials [3][C][H][W]; adjoint into dx
+// L1 loss scale * sum |a - b| over n floats and its gradient scale * sign(a - b)
+// (grad may be null); partials: kL1Blocks floats of scratch
+constexpr int kL1Blocks = 1024;
+hipError_t launch_l1(const float* a, const float* b, int64_t n, float scale, float* loss, float* grad,
+                     float* partials, hipStream_t s);
 hipError_t launch_ssim_fwd(const float* x, const float* y, int C, int H, int W, float* smap, float* part,
                            hipStream_t st);
 hipError_t launch_ssim_bwd(const float* g, const float* x, const float* y, const float* part, int C, int H, int W,

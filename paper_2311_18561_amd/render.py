@@ -865,6 +865,41 @@ def pvg_sky_composite_views(imgs, opacities, cube, cams, jitter=None, determinis
     return PVGSkyCompositeViews.apply(imgs, opacities, cube, list(cams), jitter, deterministic)
 
 
+class PVGL1Loss(torch.autograd.Function):
+    """mean |a - b| over all elements of two float32 CUDA tensors of one
+    shape (the L1 term of the training loss), differentiable in a: one
+    library pass (pvg_l1_loss) forms the sum and the gradient sign(a - b) / n
+    together, and the backward scales that gradient by the upstream value."""
+
+    @staticmethod
+    def forward(ctx, a, b):
+        if a.shape != b.shape:
+            raise ValueError(f"l1_loss needs tensors of one shape, got {tuple(a.shape)} and {tuple(b.shape)}")
+        for t in (a, b):
+            if t.dtype != torch.float32 or not t.is_cuda or t.device != a.device:
+                raise ValueError("l1_loss takes float32 CUDA tensors on one device")
+        a, b = a.contiguous(), b.contiguous()
+        n = a.numel()
+        loss = torch.empty((), dtype=torch.float32, device=a.device)
+        grad = torch.empty_like(a) if ctx.needs_input_grad[0] else None
+        partials = torch.empty(L.L1_PARTIALS, dtype=torch.float32, device=a.device)
+        L.check(L.load().pvg_l1_loss(_p(a), _p(b), n, 1.0 / max(n, 1), _p(loss), _p(grad), _p(partials),
+                                     _stream_handle()))
+        if grad is not None:
+            ctx.save_for_backward(grad)
+        return loss
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return grad * g, None
+
+
+def l1_loss(a, b):
+    """mean |a - b| (see PVGL1Loss)."""
+    return PVGL1Loss.apply(a, b)
+
+
 class PVGSSIM(torch.autograd.Function):
     """The SSIM map of a render x against a target y (both [C,H,W] float32
     on the GPU; 11 x 11 Gaussian window, sigma 1.5): the forward keeps the

@@ -230,3 +230,20 @@ def test_feature_entry_points_reject_bad_arguments_on_host(lib):
     args = (C.byref(g), 1, C.byref(cam), C.byref(L.Frame()), C.byref(geom), C.byref(bins), one, one)
     assert lib.pvg_render_features_bwd(*args, 16, 4, 0, one, 16, C.byref(gg), 0, 16, 1 << 20,
                                        None) == L.PVG_ERR_INVALID
+
+
+def test_l1_loss_arguments_checked_on_host(lib):
+    """pvg_l1_loss: the header's scratch size matches the binding's, and a
+    negative count or a missing array is rejected before any launch."""
+    import re
+
+    from paper_2311_18561_amd import _lib as L
+    hdr = open(os.path.join(ROOT, "include", "pvg.h")).read()
+    assert int(re.search(r"#define PVG_L1_PARTIALS (\d+)", hdr).group(1)) == L.L1_PARTIALS
+    buf = (C.c_float * 8)()
+    p = C.cast(buf, C.c_void_p)
+    assert lib.pvg_l1_loss(p, p, -1, 1.0, p, p, p, None) == L.PVG_ERR_INVALID
+    for k in range(4):  # a, b, loss, partials
+        args = [p, p, 4, 1.0, p, p, p, None]
+        args[[0, 1, 4, 6][k]] = None
+        assert lib.pvg_l1_loss(*args) == L.PVG_ERR_INVALID
