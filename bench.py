@@ -40,8 +40,8 @@ FLOPS_PER_PAIR = {"render_fwd": 25.0, "render_bwd": 70.0}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count")
     ap.add_argument("--period", type=int, default=200,
                     help="iterations of the timed training-loop period (the densify interval)")
