@@ -197,15 +197,36 @@ __global__ void __launch_bounds__(256) k_sky_bwd(SkyView c, const float* __restr
     for (int i = threadIdx.x; i < 3 * area; i += 256) s_acc[i] = 0ull;
     __syncthreads();
   }
+  // A box of at most nine texels (a coarse map: a texel spans more than the
+  // tile) takes the wave's sum per texel and channel, one LDS add per wave:
+  // per-lane adds there put every lane of the wave on the same few addresses.
+  // A wave's 64 terms are at most 64 m, so the four waves stay within the
+  // fixed point's bound.
+  const bool few = lds && area <= 9;  // uniform
+  if (few) {
+    for (int r = 0; r < area; ++r) {
+      const int xr = bx + r % bw, yr = by + r / bw;
+      float v[3] = {0.0f, 0.0f, 0.0f};
+      if (mine)
+        for (int k = 0; k < 4; ++k)
+          if (w[k] != 0.0f && tx[k & 1] == xr && ty[k >> 1] == yr)
+            for (int ch = 0; ch < 3; ++ch) v[ch] += w[k] * tg[ch];
+      for (int ch = 0; ch < 3; ++ch) {
+        const float sum = wave_sum(v[ch]);
+        if ((threadIdx.x & 63) == 0 && sum != 0.0f) atomicAdd(&s_acc[ch * area + r], sky_fixed(sum, ks));
+      }
+    }
+  }
   if (in) {
     for (int ch = 0; ch < 3; ++ch)
       for (int k = 0; k < 4; ++k) {
         if (w[k] == 0.0f) continue;
         const float val = w[k] * tg[ch];
-        if (lds && mine)
-          atomicAdd(&s_acc[ch * area + (ty[k >> 1] - by) * bw + (tx[k & 1] - bx)], sky_fixed(val, ks));
-        else
+        if (lds && mine) {
+          if (!few) atomicAdd(&s_acc[ch * area + (ty[k >> 1] - by) * bw + (tx[k & 1] - bx)], sky_fixed(val, ks));
+        } else {
           atomicAdd(&dcube[(face * 3 + ch) * F + idx[k]], val);
+        }
       }
   }
   if (lds) {
