@@ -880,6 +880,9 @@ class PVGL1Loss(torch.autograd.Function):
                 raise ValueError("l1_loss takes float32 CUDA tensors on one device")
         a, b = a.contiguous(), b.contiguous()
         n = a.numel()
+        if n == 0:  # the mean of nothing, as torch has it
+            ctx.save_for_backward(torch.zeros_like(a))
+            return torch.full((), float("nan"), dtype=torch.float32, device=a.device)
         loss = torch.empty((), dtype=torch.float32, device=a.device)
         grad = torch.empty_like(a) if ctx.needs_input_grad[0] else None
         partials = torch.empty(L.L1_PARTIALS, dtype=torch.float32, device=a.device)
@@ -891,6 +894,8 @@ class PVGL1Loss(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
+        if not ctx.saved_tensors:  # only b asked for a gradient, which this loss does not give
+            return None, None
         (grad,) = ctx.saved_tensors
         return grad * g, None
 

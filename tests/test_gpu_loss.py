@@ -55,3 +55,14 @@ def test_l1_loss_unaligned_and_shaped():
     ref = (x.double() - y.double()).abs().mean().item()
     assert abs(pvg.l1_loss(x, y).item() - ref) <= 1e-6 * ref
     assert torch.equal(xr.grad, torch.sign(x - y) / 1000)
+
+
+def test_l1_loss_empty():
+    """No elements: NaN, as the mean of an empty tensor is in torch, and a
+    gradient of the input's (empty) shape."""
+    import paper_2311_18561_amd as pvg
+    a = torch.empty((0, 3), device="cuda", requires_grad=True)
+    loss = pvg.l1_loss(a, torch.empty((0, 3), device="cuda"))
+    assert torch.isnan(loss).item()
+    loss.backward()
+    assert a.grad.shape == (0, 3)
