@@ -660,18 +660,27 @@ __global__ void __launch_bounds__(kThreads) k_row_intervals(ViewSet vs, const ui
 // the scanned block sums and a block scan, the adjoint's row records
 // brows[i] = (offset, first column | count << 16), first[g], and the block's
 // instances, which are consecutive in the output, written 256 at a time.
+// Each instance's row is found 4096 instances at a time: every non-empty row
+// marks its first instance in the chunk (the row holding the chunk's first
+// instance marks slot 0), and a max-scan carries the marks forward (rows
+// start in increasing order), so an instance finds its row with one LDS read
+// instead of a binary search over the block's 256 row starts.
+constexpr int kEmitRun = 4096;  // instances per chunk of the owner scan
 __global__ void __launch_bounds__(kThreads) k_row_emit(const uint4* __restrict__ rows,
                                                        const uint32_t* __restrict__ num_rows,
                                                        const unsigned long long* __restrict__ tile_partials,
                                                        const uint32_t* __restrict__ counters, uint2* brows,
                                                        uint32_t* first, uint32_t* keys, uint32_t* vals) {
+  constexpr int kPerT = kEmitRun / kThreads;  // 16 owner slots per thread in the scan
   __shared__ uint32_t s_start[kRowBlock];
   __shared__ uint32_t s_tile[kRowBlock];
   __shared__ uint32_t s_g[kRowBlock];
+  __shared__ int s_own[kEmitRun];
+  __shared__ int s_wmax[kThreads / 64];
   __shared__ unsigned long long lds[5];
   if (counters[2]) return;
   const int64_t R = *num_rows;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int64_t nblocks = (R + kRowBlock - 1) / kRowBlock;
   for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
     const int64_t i = blk * kRowBlock + tid;
@@ -685,21 +694,47 @@ __global__ void __launch_bounds__(kThreads) k_row_emit(const uint4* __restrict__
       if (brows) brows[i] = make_uint2(base + pre, rec.y);
       if (first && rec.w == 0u) first[rec.x] = base + pre;
     }
-    s_start[tid] = i < R ? pre : static_cast<uint32_t>(tot);
+    s_start[tid] = pre;
     s_tile[tid] = rec.z;
     s_g[tid] = rec.x;
-    __syncthreads();
     const uint32_t total = static_cast<uint32_t>(tot);
-    for (uint32_t t = tid; t < total; t += kRowBlock) {
-      int lo = 0, hi = kRowBlock - 1;  // last row whose start <= t (empty rows share the next start)
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_start[mid] <= t) lo = mid; else hi = mid - 1;
+    for (uint32_t c0 = 0; c0 < total; c0 += kEmitRun) {
+      const uint32_t n = min(static_cast<uint32_t>(kEmitRun), total - c0);
+      for (int k = tid; k < kEmitRun; k += kThreads) s_own[k] = 0;
+      __syncthreads();
+      if (len > 0 && pre < c0 + n && pre + len > c0)  // this row has instances in the chunk
+        s_own[pre > c0 ? pre - c0 : 0] = tid;
+      __syncthreads();
+      // inclusive max-scan of s_own[0 .. kEmitRun): 16 slots per thread, then
+      // the threads' maxima across the block
+      int run = 0;
+#pragma unroll
+      for (int k = 0; k < kPerT; ++k) run = max(run, s_own[kPerT * tid + k]);
+      int incl = run;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl = max(incl, y);
       }
-      keys[base + t] = s_tile[lo] + (t - s_start[lo]);
-      vals[base + t] = s_g[lo];
+      if (lane == 63) s_wmax[wid] = incl;
+      __syncthreads();
+      int carry = __shfl_up(incl, 1, 64);
+      if (lane == 0) carry = 0;
+      for (int w = 0; w < wid; ++w) carry = max(carry, s_wmax[w]);
+#pragma unroll
+      for (int k = 0; k < kPerT; ++k) {
+        carry = max(carry, s_own[kPerT * tid + k]);
+        s_own[kPerT * tid + k] = carry;
+      }
+      __syncthreads();
+      for (uint32_t u = tid; u < n; u += kThreads) {
+        const int o = s_own[u];
+        const uint32_t t = c0 + u;
+        keys[base + t] = s_tile[o] + (t - s_start[o]);
+        vals[base + t] = s_g[o];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
