@@ -738,15 +738,34 @@ __global__ void __launch_bounds__(kThreads) k_row_emit(const uint4* __restrict__
   }
 }
 
+// Four keys a thread (one 16-byte read, plus the keys either side): the
+// tile of each is a range's first entry where the key before differs, its
+// last where the key after does.
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ counters,
                          uint32_t* ranges, int64_t ntiles) {
   const int64_t n = counters[0];
-  for (int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
-       j += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const uint32_t t = keys[j];
-    if (static_cast<int64_t>(t) >= ntiles) continue;  // only records changed under a running sort get here
-    if (j == 0 || keys[j - 1] != t) ranges[2 * static_cast<int64_t>(t)] = static_cast<uint32_t>(j);
-    if (j == n - 1 || keys[j + 1] != t) ranges[2 * static_cast<int64_t>(t) + 1] = static_cast<uint32_t>(j + 1);
+  const int64_t n4 = (n + 3) / 4;
+  const bool vec = (reinterpret_cast<uintptr_t>(keys) & 15u) == 0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n4;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t j0 = 4 * i;
+    uint32_t k[6];  // keys j0 - 1 .. j0 + 4 (the outer two only where they exist)
+    if (vec && j0 + 4 <= n) {
+      const uint4 q = reinterpret_cast<const uint4*>(keys)[i];
+      k[1] = q.x; k[2] = q.y; k[3] = q.z; k[4] = q.w;
+    } else {
+      for (int c = 0; c < 4; ++c) k[1 + c] = j0 + c < n ? keys[j0 + c] : 0u;
+    }
+    k[0] = j0 > 0 ? keys[j0 - 1] : 0u;
+    k[5] = j0 + 4 < n ? keys[j0 + 4] : 0u;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t j = j0 + c;
+      const uint32_t t = k[1 + c];
+      if (j >= n || static_cast<int64_t>(t) >= ntiles) continue;  // only records changed under a running sort
+      if (j == 0 || k[c] != t) ranges[2 * static_cast<int64_t>(t)] = static_cast<uint32_t>(j);
+      if (j == n - 1 || k[2 + c] != t) ranges[2 * static_cast<int64_t>(t) + 1] = static_cast<uint32_t>(j + 1);
+    }
   }
 }
 
@@ -935,7 +954,7 @@ int run_bin_sort(const ViewSet& vs, const Geom& geom, pvg_bins* bins, void* tmp,
     StageScope sc(PVG_STAGE_RANGES, s);
     PVG_HIP(launch_fill_u32(bins->ranges, 0u, 2 * plan.tiles, s));
     if (m_grid > 0) {
-      hipLaunchKernelGGL(k_ranges, dim3(static_cast<unsigned>(std::min(kMaxGrid * 4, cdiv(m_grid, 256)))),
+      hipLaunchKernelGGL(k_ranges, dim3(static_cast<unsigned>(std::min(kMaxGrid * 4, cdiv(m_grid, 1024)))),
                          dim3(256), 0, s, bins->keys, counters, bins->ranges, static_cast<int64_t>(plan.tiles));
       PVG_HIP(hipGetLastError());
     }
