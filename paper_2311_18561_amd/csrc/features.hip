@@ -322,7 +322,10 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
 // Per visible Gaussian: the sum of its flagged records.  g2d receives the
 // six screen-space sums (slots 6..13 zero: no colour, no channels) and the
 // feature sums are added into feat_grad[g][c], c < nch.  Records are read
-// 16 bytes at a time.
+// 16 bytes at a time.  The block's feature sums are staged in LDS and added
+// into its 256 rows of feat_grad at the end, consecutive threads on
+// consecutive columns: a thread adding its own row's nch floats made each
+// load and store touch a cache line per lane.
 template <int kNC, bool kCulled>
 __global__ void __launch_bounds__(256) k_feat_gather(ViewSet vs, Geom geom, Lists lists, const float* __restrict__ rec,
                                                      const uint8_t* __restrict__ vis, float* g2d, float* feat_grad,
@@ -332,11 +335,15 @@ __global__ void __launch_bounds__(256) k_feat_gather(ViewSet vs, Geom geom, List
   __shared__ uint32_t s_queue[256][3];  // wave-gathered Gaussians from the front, block-gathered from the back
   __shared__ uint32_t s_idx[4][1024];
   __shared__ float s_red[4][kRec];
+  __shared__ float s_fg[256 * kNC];  // row r: the feature sums of Gaussian base + r
+  __shared__ uint8_t s_has[256];     // row r holds a visible Gaussian's sums
   __shared__ int s_qn, s_hn;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (tid == 0) { s_qn = 0; s_hn = 0; }
+  s_has[tid] = 0;
   __syncthreads();
-  const int64_t gi = static_cast<int64_t>(blockIdx.x) * 256 + tid;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * 256;
+  const int64_t gi = base + tid;
   const bool visible = gi < live_gauss(vs) && geom.radius[gi] > 0;
   uint32_t e0 = 0, cnt = 0;
   if (visible) record_range<kCulled>(vs, geom, lists, gi, e0, cnt);
@@ -346,10 +353,10 @@ __global__ void __launch_bounds__(256) k_feat_gather(ViewSet vs, Geom geom, List
     float* dst = g2d + kG2DStride * gi;
 #pragma unroll
     for (int c = 0; c < 14; ++c) dst[c] = c < 6 ? acc[c] : 0.0f;
-    float* fg = feat_grad + ld * gi;
 #pragma unroll
     for (int c = 0; c < kNC; ++c)
-      if (c < nch) fg[c] += acc[8 + c];
+      if (c < nch) s_fg[tid * kNC + c] = acc[8 + c];
+    s_has[tid] = 1;
   } else if (visible) {
     const int q = cnt > kHugeRange ? 255 - atomicAdd(&s_hn, 1) : atomicAdd(&s_qn, 1);
     s_queue[q][0] = static_cast<uint32_t>(gi);
@@ -367,7 +374,9 @@ __global__ void __launch_bounds__(256) k_feat_gather(ViewSet vs, Geom geom, List
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (lane < 14) g2d[kG2DStride * static_cast<int64_t>(g) + lane] = lane < 6 ? s_red[wid][lane] : 0.0f;
-    if (lane < nch && lane < kNC) feat_grad[ld * static_cast<int64_t>(g) + lane] += s_red[wid][8 + lane];
+    const int row = static_cast<int>(static_cast<int64_t>(g) - base);
+    if (lane < nch && lane < kNC) s_fg[row * kNC + lane] = s_red[wid][8 + lane];
+    if (lane == 0) s_has[row] = 1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -392,10 +401,18 @@ __global__ void __launch_bounds__(256) k_feat_gather(ViewSet vs, Geom geom, List
     if (tid < kRec) {
       const float v = ((s_red[0][tid] + s_red[1][tid]) + s_red[2][tid]) + s_red[3][tid];
       if (tid < 14) g2d[kG2DStride * static_cast<int64_t>(g) + tid] = tid < 6 ? v : 0.0f;
-      if (tid >= 8 && tid - 8 < nch && tid - 8 < kNC) feat_grad[ld * static_cast<int64_t>(g) + (tid - 8)] += v;
+      const int row = static_cast<int>(static_cast<int64_t>(g) - base);
+      if (tid >= 8 && tid - 8 < nch && tid - 8 < kNC) s_fg[row * kNC + (tid - 8)] = v;
+      if (tid == 0) s_has[row] = 1;
     }
     if (tid < 14 && tid >= kRec) g2d[kG2DStride * static_cast<int64_t>(g) + tid] = 0.0f;
     __syncthreads();
+  }
+  __syncthreads();
+  const int nw = min(nch, kNC);
+  for (int i = tid; i < 256 * nw; i += 256) {
+    const int row = i / nw, col = i - row * nw;
+    if (s_has[row]) feat_grad[ld * (base + row) + col] += s_fg[row * kNC + col];
   }
 }
 
