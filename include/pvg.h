@@ -20,6 +20,10 @@
  *     "[3][n]" means element (c, i) is at c * n + i.
  *   - The caller owns every input, output and workspace buffer.  The library
  *     never frees caller memory and allocates none in the rendering calls.
+ *     A workspace (`tmp`) starts on a 256-byte boundary (hipMalloc's and
+ *     torch's allocations do): the library cuts it into 256-byte aligned
+ *     parts that its kernels read 16 bytes at a time; a misaligned one is
+ *     PVG_ERR_INVALID.
  *   - Every call is asynchronous on the caller's HIP stream (a hipStream_t
  *     passed as void*, NULL = the null stream) and returns an int status:
  *     0 = PVG_OK, negative = error.  Arguments are validated on the host

@@ -2,6 +2,7 @@
 // profiler.  Kernels live in preprocess.hip, binsort.hip and render.hip.
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -298,6 +299,13 @@ int pvg_preprocess_views(const pvg_gaussians* g, int32_t n_views, const pvg_came
   return PVG_OK;
 }
 
+// A caller's workspace is cut into 256-byte aligned parts read 16 bytes at a time.
+static bool scratch_aligned(const void* tmp, const char* what) {
+  if (reinterpret_cast<uintptr_t>(tmp) % 256 == 0) return true;
+  set_error("%s scratch at %p does not start on a 256-byte boundary", what, tmp);
+  return false;
+}
+
 int pvg_bin_sort(const pvg_geom* geom, const pvg_camera* cam, pvg_bins* bins, void* tmp, size_t tmp_bytes,
                  int32_t sync_count, void* stream) {
   if (!geom || !check_geom(geom, geom->n) || !check_camera(cam) || !check_bins(bins)) return PVG_ERR_INVALID;
@@ -307,6 +315,7 @@ int pvg_bin_sort(const pvg_geom* geom, const pvg_camera* cam, pvg_bins* bins, vo
     set_error("bin_sort scratch of %zu bytes is smaller than the %zu required", tmp_bytes, plan.total);
     return PVG_ERR_NOMEM;
   }
+  if (!scratch_aligned(tmp, "bin_sort")) return PVG_ERR_INVALID;
   const View v = make_view(nullptr, cam, nullptr);
   bins->num_instances = -1;
   bins->num_visible = -1;
@@ -522,6 +531,7 @@ int pvg_render_bwd_views_channels(const pvg_gaussians* g, int32_t n_views, const
     set_error("render_bwd scratch of %zu bytes is smaller than the %zu required", tmp_bytes, need);
     return PVG_ERR_NOMEM;
   }
+  if (!scratch_aligned(tmp, "render_bwd")) return PVG_ERR_INVALID;
   std::vector<hipStream_t> side;
   if (!serial) {
     const int st = side_streams(side);
@@ -696,6 +706,7 @@ int pvg_render_features_bwd(const pvg_gaussians* g, int32_t n_views, const pvg_c
     set_error("feature adjoint scratch of %zu bytes is smaller than the %zu required", tmp_bytes, need);
     return PVG_ERR_NOMEM;
   }
+  if (!scratch_aligned(tmp, "feature adjoint")) return PVG_ERR_INVALID;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(tmp);
   float* rec = reinterpret_cast<float*>(base + off_rec);
@@ -778,6 +789,7 @@ int pvg_densify_plan(const pvg_gaussians* g, const float* grad_accum, const floa
     return PVG_ERR_INVALID;
   }
   if (tmp_bytes < pvg::densify_tmp_bytes(g->n)) { set_error("tmp_bytes too small"); return PVG_ERR_NOMEM; }
+  if (!scratch_aligned(tmp, "densify")) return PVG_ERR_INVALID;
   auto s = static_cast<hipStream_t>(stream);
   PVG_HIP(pvg::launch_densify_plan(scene_of(g), grad_accum, grad_count, noise, densify_cfg(cfg), tmp, s));
   unsigned long long total = 0;
@@ -799,6 +811,7 @@ int pvg_densify_apply(const pvg_gaussians* g, const float* noise, const pvg_dens
     return PVG_ERR_INVALID;
   }
   if (tmp_bytes < pvg::densify_tmp_bytes(g->n)) { set_error("tmp_bytes too small"); return PVG_ERR_NOMEM; }
+  if (!scratch_aligned(tmp, "densify")) return PVG_ERR_INVALID;
   auto s = static_cast<hipStream_t>(stream);
   unsigned long long total = 0;
   PVG_HIP(hipMemcpyAsync(&total, pvg::densify_total_ptr(const_cast<void*>(tmp), g->n), sizeof(total),
@@ -891,6 +904,7 @@ int pvg_staticness_split_plan(const pvg_gaussians* g, float rho_threshold, void*
     return PVG_ERR_INVALID;
   }
   if (tmp_bytes < pvg::densify_tmp_bytes(g->n)) { set_error("tmp_bytes too small"); return PVG_ERR_NOMEM; }
+  if (!scratch_aligned(tmp, "staticness split")) return PVG_ERR_INVALID;
   auto s = static_cast<hipStream_t>(stream);
   PVG_HIP(pvg::launch_static_plan(scene_of(g), rho_threshold, tmp, s));
   unsigned long long total = 0;
@@ -912,6 +926,7 @@ int pvg_staticness_split_apply(const pvg_gaussians* g, float rho_threshold, cons
     return PVG_ERR_INVALID;
   }
   if (tmp_bytes < pvg::densify_tmp_bytes(g->n)) { set_error("tmp_bytes too small"); return PVG_ERR_NOMEM; }
+  if (!scratch_aligned(tmp, "staticness split")) return PVG_ERR_INVALID;
   auto s = static_cast<hipStream_t>(stream);
   unsigned long long total = 0;
   PVG_HIP(hipMemcpyAsync(&total, pvg::densify_total_ptr(const_cast<void*>(tmp), g->n), sizeof(total),

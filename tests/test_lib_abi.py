@@ -193,6 +193,29 @@ def test_noalloc_bin_sort_rejects_an_oversized_plan_on_host(lib):
     assert lib.pvg_bin_sort_noalloc(C.byref(geom), C.byref(cam), C.byref(bins), 1, None) == L.PVG_ERR_INVALID
 
 
+def test_misaligned_workspace_refused_on_host(lib):
+    """A workspace that does not start on a 256-byte boundary is refused
+    before any device call, after the size check (the pointers are never
+    dereferenced on the host; nothing is launched)."""
+    from paper_2311_18561_amd import _lib as L
+    geom = L.Geom()
+    geom.n = 1000
+    geom.xy = geom.depth = geom.conic_op = geom.rgb = geom.radius = geom.tiles = 256
+    cam = L.Camera()
+    cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.znear = 64, 48, 50.0, 50.0, 32.0, 24.0, 0.2
+    cam.R[:] = [1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0]
+    bins = L.Bins()
+    bins.capacity = 10_000
+    bins.keys = bins.vals = bins.ranges = bins.counters = 256
+    ws = L.WsSizes()
+    assert lib.pvg_workspace_query(geom.n, 64, 48, bins.capacity, C.byref(ws)) == 0
+    need = int(ws.bin_tmp_bytes)
+    assert lib.pvg_bin_sort(C.byref(geom), C.byref(cam), C.byref(bins), 4096 + 16, need, 0, None) == L.PVG_ERR_INVALID
+    assert "256-byte boundary" in L.last_error()
+    assert lib.pvg_bin_sort(C.byref(geom), C.byref(cam), C.byref(bins), 4096 + 16, need - 1, 0, None) == \
+        L.PVG_ERR_NOMEM
+
+
 def test_feature_entry_points_reject_bad_arguments_on_host(lib):
     """Feature compositing and its adjoint refuse a channel count outside
     [1, PVG_MAX_FEATURE_CHANNELS], a row stride below it and missing arrays
