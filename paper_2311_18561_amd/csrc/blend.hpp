@@ -94,7 +94,9 @@ __device__ __forceinline__ void wave_sum16(const float a[16], float out[4]) {
 // Wave totals of kN per-lane values (any count), sixteen or ten at a time
 // with wave_sum16 / wave_sum10; lanes with lane % 16 == 0 store value q's
 // total in dst[q] (q < kN), so dst must hold kN floats visible to the wave.
-template <int kN>
+// With kGap > 0 the values from kSplit on go kGap slots further (dst[q +
+// kGap]), leaving a gap the caller fills.
+template <int kN, int kSplit = kN, int kGap = 0>
 __device__ __forceinline__ void wave_sum_store(const float* a, int lane, float* dst) {
 #pragma unroll
   for (int b = 0; b < kN; b += 16) {
@@ -108,7 +110,7 @@ __device__ __forceinline__ void wave_sum_store(const float* a, int lane, float* 
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int q = b + 4 * k + 2 * (r & 1) + (r >> 1);
-          if (q < kN) dst[q] = red[k];
+          if (q < kN) dst[q < kSplit ? q : q + kGap] = red[k];
         }
       }
     } else {
@@ -120,7 +122,7 @@ __device__ __forceinline__ void wave_sum_store(const float* a, int lane, float* 
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const int q = b + 4 * k + 2 * (r & 1) + (r >> 1);
-          if (q < kN) dst[q] = red[k];
+          if (q < kN) dst[q < kSplit ? q : q + kGap] = red[k];
         }
       }
     }

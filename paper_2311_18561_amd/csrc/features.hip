@@ -190,6 +190,8 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
   tile_bounds(tx, ty, v.W, v.H, X0, X1, Y0, Y1);
   const uint64_t lt = (1ull << lane) - 1ull;
   const int64_t HW = static_cast<int64_t>(v.W) * v.H;
+  reinterpret_cast<float*>(s_acc[lane])[6] = 0.0f;  // record slots 6 and 7 stay zero
+  reinterpret_cast<float*>(s_acc[lane])[7] = 0.0f;
   float T[kPix], rr[kPix], G[kPix][kNC];
   int last[kPix];
   int lmax = 0;
@@ -288,7 +290,9 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
         s1 = fmaf(dy, gp, s1);
         s2 = fmaf(dy * dy, gp, s2);
       }
-      float a[kRec];
+      // the six screen-space sums and the kNC feature sums, reduced without
+      // the record's two zero slots (6, 7) between them
+      float a[6 + kNC];
       {
         const float sx = dx * s0;
         a[0] = gc.x * sx + gc.y * s1;  // gc holds -A, -B, -C and 1 / o
@@ -297,12 +301,10 @@ __global__ void __launch_bounds__(64) k_feat_bwd(ViewSet vs, Geom geom, Lists li
         a[3] = -(dx * s1);
         a[4] = -0.5f * s2;
         a[5] = s0 * gc.w;
-        a[6] = 0.0f;
-        a[7] = 0.0f;
 #pragma unroll
-        for (int c = 0; c < kNC; ++c) a[8 + c] = w[0] * G[0][c] + w[1] * G[1][c] + w[2] * G[2][c] + w[3] * G[3][c];
+        for (int c = 0; c < kNC; ++c) a[6 + c] = w[0] * G[0][c] + w[1] * G[1][c] + w[2] * G[2][c] + w[3] * G[3][c];
       }
-      wave_sum_store<kRec>(a, lane, reinterpret_cast<float*>(s_acc[j]));
+      wave_sum_store<6 + kNC, 6, 2>(a, lane, reinterpret_cast<float*>(s_acc[j]));
     }
     __syncthreads();
     if (keep && s_any[__popcll(km & lt)] != 0) {
